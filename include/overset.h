@@ -1,0 +1,220 @@
+/*
+ * overset.h — C ABI of the MI355X (gfx950) overset grid-assembly library.
+ *
+ * The library computes, once per time step, the grid assembly and boundary
+ * interpolation between a stationary curvilinear background grid and rigidly
+ * moving curvilinear overset grids, after Hedayat & Borazjani, "A parallel
+ * dynamic overset grid framework for immersed boundary methods"
+ * (arXiv:1910.09315), Sec. 2.2 and Sec. 2.4. A step is five calls, each
+ * asynchronous on the caller's HIP stream:
+ *
+ *   overset_holecut         blank nodes inside other grids' blank regions    (Sec. 2.2.2)
+ *   overset_fringe_compact  mark query (fringe) points, compact them in order (Sec. 2.2.3, Alg. 1)
+ *   overset_transform       query coordinates into the inertial frame        (Sec. 2.1, Sec. 2.2.3 item 6)
+ *   overset_donor_search    donor cell + natural coordinates per query        (Sec. 2.2.5, Alg. 3; Sec. 2.4 item 1)
+ *   overset_interp          trilinear gather of u, v, w, p                    (Sec. 2.2.6)
+ *
+ * Conventions
+ *  - Pointers are DEVICE pointers unless marked [host]. The caller owns every
+ *    buffer passed to a step call and the grid coordinate arrays given to
+ *    ov_grid_add (which must stay alive and unchanged until ov_ctx_destroy).
+ *    The library owns only what it allocates in ov_ctx_create / ov_grid_add /
+ *    ov_finalize: control cells, FP32 coordinate shadows, warm-start history,
+ *    device tables and scan scratch. Step calls allocate nothing and never
+ *    synchronise the host, so a step can be captured in a HIP graph.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - A grid is (ni, nj, nk) nodes; node (i, j, k) has linear index
+ *    i + ni*(j + nj*k) (the paper's local index, Sec. 2.2.6). Grid g's nodes
+ *    occupy [node_off[g], node_off[g+1]) of every per-node array (flags,
+ *    fields), grids in id order: the paper's packed per-process vector.
+ *    A periodic direction of n nodes has n cells (the last wraps to node 0),
+ *    otherwise n-1. Cell (ci, cj, ck) has linear index ci + nci*(cj + ncj*ck);
+ *    its corner c = c0 + 2 c1 + 4 c2 is node (ci+c0, cj+c1, ck+c2).
+ *  - Grid 0 is the background (identity pose); grids 1.. are overset grids.
+ *  - A pose is 12 doubles: R (3x3 row-major) then c; a body-frame point X is
+ *    at x = R X + c in the inertial frame (R is the transpose of the paper's
+ *    rotation tensor Q, Sec. 2.1). `poses` arrays hold ngrids poses.
+ *  - Flag byte per node: state in bits 0-1 (0 field, 1 hole, 2 fringe), cause
+ *    grid in bits 2-7 (63 = outer boundary of an overset grid).
+ *  - Errors: a negative ov_status is returned BEFORE any launch for bad
+ *    arguments (message in ov_last_error). Conditions only the device can see
+ *    set bits of a device status word read by ov_status_fetch. ORPHAN is a
+ *    per-query result, not an error.
+ *  - Precision is fixed per context: OV_FP64 keeps query coordinates, s,
+ *    fields and outputs in double; OV_MIXED keeps them in float and runs the
+ *    transform, walk, Newton and weights in FP32, followed by an FP64 Newton
+ *    correction for points near a cell face or in ill-conditioned cells.
+ *  - A context is not thread-safe; calls on one context are stream-ordered.
+ */
+#ifndef OVERSET_H
+#define OVERSET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ov_ctx ov_ctx;
+
+enum ov_status {
+    OV_OK = 0,
+    OV_EINVAL = -1,     /* bad pointer, id, option or size */
+    OV_EDIMS = -2,      /* grid dimensions unusable (< 2 nodes along an axis, too many nodes) */
+    OV_ECAPACITY = -3,  /* capacity below what the call needs (host-visible) */
+    OV_EHIP = -4,       /* a HIP runtime call failed */
+    OV_ESTATE = -5      /* call out of order (e.g. step before ov_finalize) */
+};
+
+enum ov_precision { OV_FP64 = 0, OV_MIXED = 1 };
+
+enum ov_blank_kind {
+    OV_BLANK_NONE = 0,
+    OV_BLANK_CYL = 1,       /* prm: r, z0, z1 — x^2 + y^2 < r^2 and z0 <= z <= z1 (body frame) */
+    OV_BLANK_SPHERE = 2,    /* prm: r         — x^2 + y^2 + z^2 < r^2 */
+    OV_BLANK_ELLIPSOID = 3  /* prm: a, b, c   — (x/a)^2 + (y/b)^2 + (z/c)^2 < 1 */
+};
+
+/* Flag byte fields. */
+#define OV_STATE_FIELD 0
+#define OV_STATE_HOLE 1
+#define OV_STATE_FRINGE 2
+#define OV_CAUSE_BOUNDARY 63
+#define OV_MAX_GRIDS 63
+
+/* Per-query status codes written by overset_donor_search. */
+#define OV_Q_ORPHAN 0         /* no valid donor in any candidate grid */
+#define OV_Q_FOUND 1          /* found by the stencil walk */
+#define OV_Q_FALLBACK 2       /* found by the brute-force scan of the control cell */
+#define OV_Q_FP64_FIXED 4     /* bit: the FP64 correction decided the donor (mixed precision) */
+
+/* Device status word bits (ov_status_fetch). */
+#define OV_DEV_CAPACITY 1     /* fringe count exceeded capacity; entries past capacity not written */
+#define OV_DEV_WALK_LIMIT 2   /* at least one walk hit max_walk (the fallback still ran) */
+#define OV_DEV_NONFINITE 4    /* a non-finite query coordinate was met (the query became an orphan) */
+#define OV_DEV_FIX_OVERFLOW 8 /* mixed precision: the FP64 correction queue overflowed */
+
+/* Options (ov_set_option). */
+enum ov_option {
+    OV_OPT_WARM = 1,        /* 1 (default): seed the walk from the previous step's donor; 0: cold */
+    OV_OPT_MAX_WALK = 2,    /* walk steps before the brute-force fallback (default 64, >= 1) */
+    OV_OPT_SEARCH_BLOCK = 3,/* threads per block of the donor search (64..1024, multiple of 64) */
+    OV_OPT_INTERP_BLOCK = 4,/* threads per block of the interpolation (64..1024, multiple of 64) */
+    OV_OPT_HOLECUT_BLOCK = 5,/* threads per block of the hole cut (64..1024, multiple of 64) */
+    OV_OPT_HOLECUT_NPT = 6, /* nodes per thread of the hole cut (1, 2 or 4) */
+    OV_OPT_PERSIST = 7      /* workgroups per CU of persistent launches (1..32; 0 = one item per thread) */
+};
+
+/* Create a context on HIP device `device` with precision `precision`.
+ * *out receives the context [host]. Returns OV_EINVAL / OV_EHIP on failure. */
+int ov_ctx_create(ov_ctx **out, int device, int precision);
+
+/* Free everything the library allocated for `ctx`. Synchronises the device. */
+int ov_ctx_destroy(ov_ctx *ctx);
+
+/* Last error message of `ctx` (static string owned by the context). */
+const char *ov_last_error(const ov_ctx *ctx);
+
+/* Register a structured grid (Sec. 2.2: a block of the overset system).
+ *  ni, nj, nk     nodes per direction, each >= 2; total nodes of all grids < 2^31
+ *  periodic       bit mask: 1 = i, 2 = j, 4 = k wraps (the last node joins node 0)
+ *  X, Y, Z        body-frame node coordinates, FP64, i fastest [device, caller-owned]
+ *  blank_kind     ov_blank_kind of the region this grid cuts from the others
+ *                 (the user-defined blank surface of Sec. 2.2.2), body frame
+ *  blank_prm      8 doubles of shape parameters [host]
+ *  outer          6 ints [host]: query-point layers on faces i-, i+, j-, j+,
+ *                 k-, k+ (the overset boundary faces of Sec. 2.2.3 item 1)
+ *  grid_id        receives the id [host]; the first grid (id 0) is the background.
+ * Must precede ov_finalize. */
+int ov_grid_add(ov_ctx *ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t periodic,
+                const double *X, const double *Y, const double *Z,
+                int32_t blank_kind, const double *blank_prm, const int32_t *outer,
+                int32_t *grid_id);
+
+/* Build the per-grid control cells (Sec. 2.2.5: an axis-aligned auxiliary grid
+ * over each donor grid whose control cells list the donor cells reaching
+ * them), FP32 shadows (mixed precision) and warm-start history. Synchronises
+ * `stream`. After this, no grid can be added. */
+int ov_finalize(ov_ctx *ctx, void *stream);
+
+/* Number of grids / total nodes; node offsets (ngrids+1 int64) [host]. */
+int32_t ov_num_grids(const ov_ctx *ctx);
+int64_t ov_total_nodes(const ov_ctx *ctx);
+int ov_node_offsets(const ov_ctx *ctx, int64_t *out);
+
+/* Set an option (ov_option); returns OV_EINVAL for an unknown key or a value
+ * out of range. Takes effect at the next step call. */
+int ov_set_option(ov_ctx *ctx, int32_t key, int64_t value);
+
+/* Forget the warm-start history (next search is cold). Stream-ordered. */
+int ov_reset_history(ov_ctx *ctx, void *stream);
+
+/* Copy the device status word into *host_status [host] and clear it.
+ * Synchronises `stream`. */
+int ov_status_fetch(ov_ctx *ctx, int32_t *host_status, void *stream);
+
+/* ---------------------------------------------------------------- step */
+
+/* Hole cutting (Sec. 2.2.2, Sec. 2.4 item 2). For every node of every grid A,
+ * in A's pose, and every other grid B with a blank region: the node is a HOLE
+ * iff it lies strictly inside B's blank region placed at B's pose; the cause
+ * is the lowest such B. Writes a hole/field flag byte for every node.
+ *  poses   ngrids poses (12 doubles each)
+ *  flags   total_nodes bytes, fully overwritten */
+int overset_holecut(ov_ctx *ctx, const double *poses, uint8_t *flags, void *stream);
+
+/* Query-point identification and compaction (Sec. 2.2.3 item 1, Alg. 1).
+ * Marks FRINGE: (a) the `outer` face layers of each grid, cause 63; (b) the
+ * buffer layer, every non-hole node within Chebyshev index distance `nf` of a
+ * hole of its own grid (periodic directions wrap), cause = the lowest cause of
+ * those holes. Hole > fringe > field. Then writes the fringe nodes in ascending
+ * (grid, node) order to q_grid / q_node (local node index) and their number to
+ * *d_count (device int64). Entries beyond `capacity` are not written; the
+ * device status bit OV_DEV_CAPACITY is set instead.
+ *  nf         buffer width, 0..3
+ *  flags      hole/field flags from overset_holecut, updated in place */
+int overset_fringe_compact(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
+                           int64_t capacity, int64_t *d_count, void *stream);
+
+/* Inertial-frame coordinates of the compacted queries (the coordinate
+ * packets of Sec. 2.2.3 item 6): x = R_g X_g[node] + c_g for i < *d_count.
+ *  qx   3*capacity values (x block, y block, z block), double (OV_FP64) or
+ *       float (OV_MIXED) */
+int overset_transform(ov_ctx *ctx, const double *poses, const int32_t *q_grid, const int32_t *q_node,
+                      const int64_t *d_count, int64_t capacity, void *qx, void *stream);
+
+/* Donor search (Sec. 2.2.5, Alg. 3) with donor selection (Sec. 2.4 item 1).
+ * For query i < *d_count of grid A whose flag carries cause k, candidate donor
+ * grids are: k (unless 63 or A), then the background 0, then the other grids
+ * in ascending id. In each candidate grid B the query is taken into B's body
+ * frame, a stencil walk seeded from the previous step's donor (or from B's
+ * control cell) moves cell to cell by the signs of the natural coordinates,
+ * and Newton's method solves the trilinear map for s. A cell contains the
+ * point iff s lies in [0,1]^3 (up to 1e-12); it is a valid donor iff none of
+ * its 8 corners is a HOLE. A walk that leaves the grid, repeats or exceeds
+ * max_walk falls back to a brute-force scan of the control cell's candidates,
+ * keeping the lowest valid containing cell index. Outputs per query:
+ *  donor_grid, donor_cell   int32 (-1 for orphans)
+ *  s                        3*capacity natural coordinates (s0 block, s1, s2),
+ *                           double or float by context precision; NaN for orphans
+ *  status                   OV_Q_* code
+ *  flags                    the flags after overset_fringe_compact (read only)
+ *  qx                       output of overset_transform */
+int overset_donor_search(ov_ctx *ctx, const double *poses, const uint8_t *flags, const int32_t *q_grid,
+                         const int32_t *q_node, const void *qx, const int64_t *d_count, int64_t capacity,
+                         int32_t *donor_grid, int32_t *donor_cell, void *s, int32_t *status, void *stream);
+
+/* Trilinear interpolation (Sec. 2.2.6): out[f][i] = sum_{c=0..7} w_c F_f[corner c]
+ * with w_c = prod_d (c_d ? s_d : 1 - s_d), for the 4 fields u, v, w, p and every
+ * query i < *d_count with a donor; orphans are not written.
+ *  fields   4*total_nodes values (u block, v, w, p; grids packed by node offset)
+ *  out      4*capacity values
+ * Both double (OV_FP64) or float (OV_MIXED). */
+int overset_interp(ov_ctx *ctx, const int32_t *donor_grid, const int32_t *donor_cell, const void *s,
+                   const int64_t *d_count, int64_t capacity, const void *fields, void *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OVERSET_H */

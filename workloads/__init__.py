@@ -1,0 +1,375 @@
+"""Seeded synthetic inputs for the overset grid-assembly path.
+
+This module is shared by the tests, the benchmark and the CPU oracle's
+callers. It builds grids, blank-region descriptions, rigid-motion pose
+tables and field values, and nothing else: it holds none of the assembly
+arithmetic (no hole test, no fringe rule, no donor search, no
+interpolation). Every random number is drawn from
+``numpy.random.default_rng(seed)`` in the order documented per builder.
+
+Conventions (shared with the C-ABI library and the oracle):
+
+* A grid is a structured block of ``(ni, nj, nk)`` nodes; node ``(i, j, k)``
+  has linear index ``i + ni*(j + nj*k)`` (i fastest), as in the paper's
+  local index of Sec. 2.2.6.
+* Coordinates are FP64 structure-of-arrays in the grid's own (body) frame.
+* ``periodic`` is a bit mask (1: i, 2: j, 4: k). A periodic direction of
+  n nodes has n cells (the last wraps to node 0); otherwise n-1 cells.
+* Grid 0 is the stationary background (identity pose); grids 1.. are
+  overset grids moving rigidly with a pose ``(R, c)``:
+  ``x_world = R @ X_body + c`` (R row-major). The paper writes the
+  non-inertial frame with a rotation tensor Q (Sec. 2.1, eq. for u_q);
+  here R plays the role of Q transposed.
+* A pose table is an array ``[steps, ngrids, 12]`` = R (9, row-major) then c (3).
+* Fields u, v, w, p are stored as one ``[4, total_nodes]`` array; grid g's
+  nodes start at ``node_offset[g]`` (the paper's packed per-process vector,
+  Sec. 2.2.6).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BLANK_NONE, BLANK_CYL, BLANK_SPHERE, BLANK_ELLIPSOID = 0, 1, 2, 3
+PERIODIC_I, PERIODIC_J, PERIODIC_K = 1, 2, 4
+
+
+@dataclass
+class Grid:
+    """One structured block: dims, periodicity, body-frame coordinates,
+    the blank region it cuts from other grids, and its fringe faces."""
+    name: str
+    dims: tuple
+    periodic: int
+    X: np.ndarray
+    Y: np.ndarray
+    Z: np.ndarray
+    blank_kind: int = BLANK_NONE
+    blank_prm: tuple = ()
+    # fringe layers on the faces (i-, i+, j-, j+, k-, k+)
+    outer: tuple = (0, 0, 0, 0, 0, 0)
+
+    @property
+    def nodes(self) -> int:
+        ni, nj, nk = self.dims
+        return ni * nj * nk
+
+    def blank_prm8(self) -> np.ndarray:
+        out = np.zeros(8, dtype=np.float64)
+        out[: len(self.blank_prm)] = self.blank_prm
+        return out
+
+
+@dataclass
+class Workload:
+    """A complete synthetic input: grids, fringe width, motion, fields."""
+    name: str
+    grids: list
+    nf: int
+    steps: int
+    poses: np.ndarray               # [steps, ngrids, 12]
+    fields: np.ndarray              # [4, total_nodes] float64
+    precision: str = "fp64"         # "fp64" or "mixed"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ngrids(self) -> int:
+        return len(self.grids)
+
+    @property
+    def node_offsets(self) -> np.ndarray:
+        off = np.zeros(self.ngrids + 1, dtype=np.int64)
+        off[1:] = np.cumsum([g.nodes for g in self.grids])
+        return off
+
+    @property
+    def total_nodes(self) -> int:
+        return int(self.node_offsets[-1])
+
+
+# ---------------------------------------------------------------- motion
+def rodrigues(axis, angle: float) -> np.ndarray:
+    """Rotation by `angle` about unit `axis` (Rodrigues' formula)."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return np.eye(3) * math.cos(angle) + math.sin(angle) * K + (1.0 - math.cos(angle)) * np.outer(a, a)
+
+
+def rot_z(angle: float) -> np.ndarray:
+    return rodrigues((0.0, 0.0, 1.0), angle)
+
+
+def pose12(R: np.ndarray, c) -> np.ndarray:
+    out = np.empty(12, dtype=np.float64)
+    out[:9] = np.asarray(R, dtype=np.float64).reshape(9)
+    out[9:] = np.asarray(c, dtype=np.float64)
+    return out
+
+
+IDENTITY_POSE = pose12(np.eye(3), (0.0, 0.0, 0.0))
+
+
+def world_coords(grid: Grid, pose: np.ndarray):
+    """Node positions of `grid` under `pose` (input preparation only: used to
+    evaluate synthetic fields at t=0, never as a step result)."""
+    R = pose[:9].reshape(3, 3)
+    c = pose[9:]
+    P = np.stack([grid.X, grid.Y, grid.Z])
+    W = R @ P + c[:, None]
+    return W[0], W[1], W[2]
+
+
+# ---------------------------------------------------------------- grids
+def _tensor(xs, ys, zs):
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    return X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy()
+
+
+def cartesian_grid(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), name="background") -> Grid:
+    ni, nj, nk = (n, n, n) if np.isscalar(n) else n
+    xs = np.linspace(lo[0], hi[0], ni)
+    ys = np.linspace(lo[1], hi[1], nj)
+    zs = np.linspace(lo[2], hi[2], nk)
+    X, Y, Z = _tensor(xs, ys, zs)
+    return Grid(name, (ni, nj, nk), 0, X, Y, Z)
+
+
+def tanh_stretch(n: int, beta: float) -> np.ndarray:
+    """Node positions on [0,1] clustered toward the centre: the inverse of
+    xi = (1 + tanh(beta (x - 1/2)) / tanh(beta/2)) / 2 at xi = i/(n-1)."""
+    xi = np.linspace(0.0, 1.0, n)
+    x = 0.5 + np.arctanh((2.0 * xi - 1.0) * math.tanh(beta / 2.0)) / beta
+    x[0], x[-1] = 0.0, 1.0
+    return x
+
+
+def _local_spacing(x: np.ndarray) -> np.ndarray:
+    d = np.empty_like(x)
+    d[1:-1] = 0.5 * (x[2:] - x[:-2])
+    d[0] = x[1] - x[0]
+    d[-1] = x[-1] - x[-2]
+    return d
+
+
+def stretched_background(dims, extent=(1.0, 1.0, 1.0), beta=2.0, perturb=0.1,
+                         wavelength=16, name="background") -> Grid:
+    """Curvilinear background: per-axis tanh stretching toward the centre plus a
+    sinusoidal node perturbation of `perturb` local cells with a `wavelength`
+    node period; each coordinate is perturbed by the product of sines of the
+    other two indices, so cell faces are non-planar. No random draws."""
+    ni, nj, nk = dims
+    xs = tanh_stretch(ni, beta) * extent[0]
+    ys = tanh_stretch(nj, beta) * extent[1]
+    zs = tanh_stretch(nk, beta) * extent[2]
+    dx, dy, dz = _local_spacing(xs), _local_spacing(ys), _local_spacing(zs)
+    w = 2.0 * math.pi / wavelength
+    si = np.sin(w * np.arange(ni))
+    sj = np.sin(w * np.arange(nj))
+    sk = np.sin(w * np.arange(nk))
+    # shape [nk, nj, ni]
+    X = xs[None, None, :] + perturb * dx[None, None, :] * (sj[None, :, None] * sk[:, None, None])
+    Y = ys[None, :, None] + perturb * dy[None, :, None] * (sk[:, None, None] * si[None, None, :])
+    Z = zs[:, None, None] + perturb * dz[:, None, None] * (si[None, None, :] * sj[None, :, None])
+    shape = (nk, nj, ni)
+    X = np.broadcast_to(X, shape).ravel().copy()
+    Y = np.broadcast_to(Y, shape).ravel().copy()
+    Z = np.broadcast_to(Z, shape).ravel().copy()
+    return Grid(name, (ni, nj, nk), 0, X, Y, Z)
+
+
+def cylindrical_shell(nr, nth, nz, r0, r1, z0, z1, name="cylinder") -> Grid:
+    """i = radius (uniform r0..r1), j = angle (periodic, 2 pi j / nth),
+    k = axial (uniform z0..z1); body frame centred on the axis."""
+    r = np.linspace(r0, r1, nr)
+    th = 2.0 * math.pi * np.arange(nth) / nth
+    z = np.linspace(z0, z1, nz)
+    R = r[None, None, :]
+    T = th[None, :, None]
+    X = np.broadcast_to(R * np.cos(T), (nz, nth, nr))
+    Y = np.broadcast_to(R * np.sin(T), (nz, nth, nr))
+    Zc = np.broadcast_to(z[:, None, None], (nz, nth, nr))
+    return Grid(name, (nr, nth, nz), PERIODIC_J, X.ravel().copy(), Y.ravel().copy(), Zc.ravel().copy())
+
+
+def ellipsoidal_shell(nr, nphi, nth, inner, outer, name="shell") -> Grid:
+    """Shell between two coaxial ellipsoids with semi-axes `inner` and `outer`
+    (body frame, along x, y, z). i = layer (semi-axes interpolated linearly
+    inner -> outer), j = azimuth phi about x (periodic), k = polar angle
+    theta from +x in [0, pi] with pole nodes (degenerate polar cells).
+    A sphere is inner = (r0,)*3, outer = (r1,)*3."""
+    t = np.linspace(0.0, 1.0, nr)
+    a = inner[0] + t * (outer[0] - inner[0])
+    b = inner[1] + t * (outer[1] - inner[1])
+    c = inner[2] + t * (outer[2] - inner[2])
+    phi = 2.0 * math.pi * np.arange(nphi) / nphi
+    th = math.pi * np.arange(nth) / (nth - 1)
+    ct = np.cos(th)
+    st = np.sin(th)
+    ct[0], ct[-1], st[0], st[-1] = 1.0, -1.0, 0.0, 0.0
+    A = a[None, None, :]
+    B = b[None, None, :]
+    C = c[None, None, :]
+    CT = ct[:, None, None]
+    ST = st[:, None, None]
+    CP = np.cos(phi)[None, :, None]
+    SP = np.sin(phi)[None, :, None]
+    shape = (nth, nphi, nr)
+    X = np.broadcast_to(A * CT, shape)
+    Y = np.broadcast_to(B * ST * CP, shape)
+    Z = np.broadcast_to(C * ST * SP, shape)
+    return Grid(name, (nr, nphi, nth), PERIODIC_J, X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy())
+
+
+def spherical_shell(nr, nphi, nth, r0, r1, name="sphere") -> Grid:
+    return ellipsoidal_shell(nr, nphi, nth, (r0, r0, r0), (r1, r1, r1), name=name)
+
+
+def perturbed_box_grid(rng, dims, h=1.0, amp=0.2, periodic=0, name="random") -> Grid:
+    """Tiny random curvilinear grid: a unit-spacing lattice scaled by h with every
+    node moved by U[-amp, amp] * h per coordinate (draws: X, Y, Z noise, in
+    that order). `periodic` is recorded as given; a ring geometry for periodic
+    directions comes from the shell builders instead."""
+    ni, nj, nk = dims
+    X, Y, Z = _tensor(np.arange(ni) * h, np.arange(nj) * h, np.arange(nk) * h)
+    X = X + rng.uniform(-amp, amp, X.shape) * h
+    Y = Y + rng.uniform(-amp, amp, Y.shape) * h
+    Z = Z + rng.uniform(-amp, amp, Z.shape) * h
+    return Grid(name, (ni, nj, nk), periodic, X, Y, Z)
+
+
+# ---------------------------------------------------------------- fields
+def fourier_modes(rng, nmodes=8, kmax=4):
+    """Draw order per mode: k (3 integers in [-kmax, kmax], redrawn while all
+    zero), amplitude U[-1, 1], phase U[0, 2 pi)."""
+    modes = []
+    for _ in range(nmodes):
+        while True:
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            if np.any(k != 0):
+                break
+        A = rng.uniform(-1.0, 1.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        modes.append((k.astype(np.float64), A, ph))
+    return modes
+
+
+def eval_modes(modes, x, y, z):
+    q = np.zeros_like(x)
+    for k, A, ph in modes:
+        q += A * np.cos(2.0 * math.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+    return q
+
+
+def _fields_from(grids, poses0, fn) -> np.ndarray:
+    total = sum(g.nodes for g in grids)
+    out = np.empty((4, total), dtype=np.float64)
+    o = 0
+    for g, p in zip(grids, poses0):
+        x, y, z = world_coords(g, p)
+        vals = fn(x, y, z)
+        for f in range(4):
+            out[f, o:o + g.nodes] = vals[f]
+        o += g.nodes
+    return out
+
+
+def linear_field(x, y, z):
+    return 1.0 + 2.0 * x - 3.0 * y + 0.5 * z
+
+
+def analytic_fields_c0(x, y, z):
+    return (linear_field(x, y, z),
+            np.sin(2.0 * math.pi * x) * np.cos(2.0 * math.pi * y),
+            np.zeros_like(x),
+            x * y * z)
+
+
+# ---------------------------------------------------------------- configs
+def c0() -> Workload:
+    """Tiny FP64 case: 32^3 uniform background on [0,1]^3; one cylindrical
+    shell 16^3 (r 0.05..0.2, 16 periodic angles, z 0.3..0.7) about the axis
+    (0.5, 0.5), rotated 0.3 rad about z; its body r < 0.05, z in [0.3, 0.7]
+    is cut from the background; its outer 2 radial layers are fringe;
+    buffer width 2. Analytic fields; one step; no random draws."""
+    bg = cartesian_grid(32)
+    cyl = cylindrical_shell(16, 16, 16, 0.05, 0.2, 0.3, 0.7)
+    cyl.blank_kind = BLANK_CYL
+    cyl.blank_prm = (0.05, 0.3, 0.7)
+    cyl.outer = (0, 2, 0, 0, 0, 0)
+    grids = [bg, cyl]
+    poses = np.stack([IDENTITY_POSE, pose12(rot_z(0.3), (0.5, 0.5, 0.0))])[None]
+    fields = _fields_from(grids, poses[0], analytic_fields_c0)
+    return Workload("C0", grids, nf=2, steps=1, poses=poses, fields=fields,
+                    meta={"seed": 0})
+
+
+def sphere_motion(rng, steps, omega, speed, c0):
+    """Pose table of a rigid rotation `omega` rad/step about a random unit axis
+    plus a translation `speed`/step along a random unit direction (draws: axis
+    as 3 normals, then direction as 3 normals)."""
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    poses = np.empty((steps, 12))
+    for t in range(steps):
+        poses[t] = pose12(rodrigues(axis, omega * t), np.asarray(c0) + t * speed * d)
+    return poses, axis, d
+
+
+def sphere_case(name, bg_dims, shell_dims, r0, r1, steps, seed, nf=2,
+                omega=0.01, cells_per_step=0.2, precision="fp64") -> Workload:
+    """Stretched, perturbed background on [0,1]^3 and one spherical shell
+    (radial, azimuth, polar) centred at (0.5, 0.5, 0.5) whose body r < r0 is
+    cut from the background; outer `nf` radial layers are fringe. Motion:
+    `omega` rad/step about a random axis and `cells_per_step` mean background
+    cells per step along a random direction. Fields: per field, a sum of 8
+    random Fourier modes (k <= 4) evaluated at t=0 node positions.
+    Draw order from default_rng(seed): axis, direction, then modes of u, v, w, p."""
+    rng = np.random.default_rng(seed)
+    bg = stretched_background(bg_dims)
+    sph = spherical_shell(*shell_dims, r0, r1)
+    sph.blank_kind = BLANK_SPHERE
+    sph.blank_prm = (r0,)
+    sph.outer = (0, nf, 0, 0, 0, 0)
+    cell = 1.0 / (bg_dims[0] - 1)
+    sp, axis, d = sphere_motion(rng, steps, omega, cells_per_step * cell, (0.5, 0.5, 0.5))
+    poses = np.empty((steps, 2, 12))
+    poses[:, 0] = IDENTITY_POSE
+    poses[:, 1] = sp
+    modes = [fourier_modes(rng) for _ in range(4)]
+    grids = [bg, sph]
+    fields = _fields_from(grids, poses[0], lambda x, y, z: [eval_modes(m, x, y, z) for m in modes])
+    return Workload(name, grids, nf=nf, steps=steps, poses=poses, fields=fields,
+                    precision=precision,
+                    meta={"seed": seed, "axis": axis.tolist(), "direction": d.tolist()})
+
+
+def c1(steps=100) -> Workload:
+    """256^3 stretched curvilinear background + spherical shell 128x128x64,
+    r 0.02..0.12, 0.01 rad/step + 0.2 cell/step, 2 fringe layers, seed 1."""
+    return sphere_case("C1", (256, 256, 256), (128, 128, 64), 0.02, 0.12, steps, seed=1)
+
+
+def c2(steps=100) -> Workload:
+    """C1's grids and motion, run in mixed precision."""
+    w = c1(steps)
+    w.name = "C2"
+    w.precision = "mixed"
+    return w
+
+
+def c1_small(steps=4, seed=11) -> Workload:
+    """A scaled-down C1 for parity tests: 64^3 background, shell 24x32x17."""
+    return sphere_case("C1-small", (64, 64, 64), (24, 32, 17), 0.06, 0.2, steps, seed=seed,
+                       omega=0.05, cells_per_step=0.7)
+
+
+CONFIGS = {"C0": c0, "C1": c1, "C2": c2, "C1-small": c1_small}
+
+
+def build(name: str, **kw) -> Workload:
+    return CONFIGS[name](**kw)
