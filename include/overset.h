@@ -172,12 +172,15 @@ int overset_holecut(ov_ctx *ctx, const double *poses, uint8_t *flags, void *stre
  * *d_count (device int64). Entries beyond `capacity` are not written; the
  * device status bit OV_DEV_CAPACITY is set instead.
  *  nf         buffer width, 0..3
- *  flags      hole/field flags from overset_holecut, updated in place */
+ *  flags      hole/field flags from overset_holecut, updated in place;
+ *             16-byte aligned */
 int overset_fringe_compact(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
                            int64_t capacity, int64_t *d_count, void *stream);
 
-/* Inertial-frame coordinates of the compacted queries (the coordinate
- * packets of Sec. 2.2.3 item 6): x = R_g X_g[node] + c_g for i < *d_count.
+/* Inertial-frame positions of the compacted queries (the coordinate packets
+ * of Sec. 2.2.3 item 6), stored as the offset from the query grid's frame
+ * centre: qx = x - c_g = R_g X_g[node], for i < *d_count. The consumer adds
+ * c_g in FP64, so an FP32 qx (OV_MIXED) only carries the body-scale offset.
  *  qx   3*capacity values (x block, y block, z block), double (OV_FP64) or
  *       float (OV_MIXED) */
 int overset_transform(ov_ctx *ctx, const double *poses, const int32_t *q_grid, const int32_t *q_node,

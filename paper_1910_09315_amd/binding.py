@@ -1,0 +1,179 @@
+"""ctypes binding of liboverset.so (include/overset.h).
+
+Argument marshalling only: every stage runs in the library's HIP kernels.
+Device buffers are torch tensors on a ROCm device; their data pointers and
+the current torch stream (a hipStream_t) are handed to the C ABI. If the
+library has not been built, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboverset.so")
+
+OV_FP64, OV_MIXED = 0, 1
+OV_BLANK_NONE, OV_BLANK_CYL, OV_BLANK_SPHERE, OV_BLANK_ELLIPSOID = 0, 1, 2, 3
+OV_STATE_FIELD, OV_STATE_HOLE, OV_STATE_FRINGE = 0, 1, 2
+OV_CAUSE_BOUNDARY = 63
+OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
+OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE, OV_DEV_FIX_OVERFLOW = 1, 2, 4, 8
+OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
+       "holecut_npt": 6, "persist": 7}
+
+EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
+           "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
+           "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
+           "overset_interp"]
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_lib = None
+
+
+class OversetError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OversetError(f"{path} is missing: build it with paper_1910_09315_amd.build.build()")
+    L = ctypes.CDLL(path)
+    sig = {
+        "ov_ctx_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int]),
+        "ov_ctx_destroy": (ctypes.c_int, [_P]),
+        "ov_last_error": (ctypes.c_char_p, [_P]),
+        "ov_grid_add": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _I32, _P, _P, _P]),
+        "ov_finalize": (ctypes.c_int, [_P, _P]),
+        "ov_num_grids": (_I32, [_P]),
+        "ov_total_nodes": (_I64, [_P]),
+        "ov_node_offsets": (ctypes.c_int, [_P, _P]),
+        "ov_set_option": (ctypes.c_int, [_P, _I32, _I64]),
+        "ov_reset_history": (ctypes.c_int, [_P, _P]),
+        "ov_status_fetch": (ctypes.c_int, [_P, _P, _P]),
+        "overset_holecut": (ctypes.c_int, [_P, _P, _P, _P]),
+        "overset_fringe_compact": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _P, _P]),
+        "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
+        "overset_donor_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P]),
+        "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return _P(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _P(s.cuda_stream)
+
+
+class Context:
+    """Owns an ov_ctx (grids, control cells, warm-start history)."""
+
+    def __init__(self, device: int = 0, precision: str = "fp64"):
+        self.lib = load()
+        self.precision = precision
+        self.device = device
+        h = _P()
+        rc = self.lib.ov_ctx_create(ctypes.byref(h), device, OV_MIXED if precision == "mixed" else OV_FP64)
+        if rc != 0:
+            raise OversetError(f"ov_ctx_create failed ({rc})")
+        self.h = h
+        self._keep = []
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self.lib.ov_last_error(self.h)
+            raise OversetError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ov_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid_add(self, dims, periodic, X, Y, Z, blank_kind=0, blank_prm=(), outer=(0,) * 6) -> int:
+        prm = (ctypes.c_double * 8)(*([float(v) for v in blank_prm] + [0.0] * (8 - len(blank_prm))))
+        out = (ctypes.c_int32 * 6)(*[int(v) for v in outer])
+        gid = ctypes.c_int32()
+        self._keep += [X, Y, Z]
+        self.check(self.lib.ov_grid_add(self.h, int(dims[0]), int(dims[1]), int(dims[2]), int(periodic),
+                                        _ptr(X), _ptr(Y), _ptr(Z), int(blank_kind), prm, out,
+                                        ctypes.byref(gid)), "ov_grid_add")
+        return gid.value
+
+    def finalize(self, stream=None):
+        self.check(self.lib.ov_finalize(self.h, _stream(stream)), "ov_finalize")
+
+    def set_option(self, key: str, value: int):
+        self.check(self.lib.ov_set_option(self.h, OPT[key], int(value)), f"ov_set_option({key})")
+
+    def reset_history(self, stream=None):
+        self.check(self.lib.ov_reset_history(self.h, _stream(stream)), "ov_reset_history")
+
+    def status(self, stream=None) -> int:
+        v = ctypes.c_int32()
+        self.check(self.lib.ov_status_fetch(self.h, ctypes.byref(v), _stream(stream)), "ov_status_fetch")
+        return v.value
+
+    def num_grids(self) -> int:
+        return int(self.lib.ov_num_grids(self.h))
+
+    def total_nodes(self) -> int:
+        return int(self.lib.ov_total_nodes(self.h))
+
+    def node_offsets(self):
+        n = self.num_grids() + 1
+        arr = (ctypes.c_int64 * n)()
+        self.check(self.lib.ov_node_offsets(self.h, arr), "ov_node_offsets")
+        return list(arr)
+
+
+# ---------------------------------------------------------------- step calls (same names as the C ABI)
+def overset_holecut(ctx: Context, poses, flags, stream=None):
+    ctx.check(ctx.lib.overset_holecut(ctx.h, _ptr(poses), _ptr(flags), _stream(stream)), "overset_holecut")
+
+
+def overset_fringe_compact(ctx: Context, nf, flags, q_grid, q_node, capacity, d_count, stream=None):
+    ctx.check(ctx.lib.overset_fringe_compact(ctx.h, int(nf), _ptr(flags), _ptr(q_grid), _ptr(q_node),
+                                             int(capacity), _ptr(d_count), _stream(stream)),
+              "overset_fringe_compact")
+
+
+def overset_transform(ctx: Context, poses, q_grid, q_node, d_count, capacity, qx, stream=None):
+    ctx.check(ctx.lib.overset_transform(ctx.h, _ptr(poses), _ptr(q_grid), _ptr(q_node), _ptr(d_count),
+                                        int(capacity), _ptr(qx), _stream(stream)), "overset_transform")
+
+
+def overset_donor_search(ctx: Context, poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid,
+                         donor_cell, s, status, stream=None):
+    ctx.check(ctx.lib.overset_donor_search(ctx.h, _ptr(poses), _ptr(flags), _ptr(q_grid), _ptr(q_node), _ptr(qx),
+                                           _ptr(d_count), int(capacity), _ptr(donor_grid), _ptr(donor_cell),
+                                           _ptr(s), _ptr(status), _stream(stream)), "overset_donor_search")
+
+
+def overset_interp(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, fields, out, stream=None):
+    ctx.check(ctx.lib.overset_interp(ctx.h, _ptr(donor_grid), _ptr(donor_cell), _ptr(s), _ptr(d_count),
+                                     int(capacity), _ptr(fields), _ptr(out), _stream(stream)), "overset_interp")

@@ -1,0 +1,448 @@
+// Context management, grid registration and control-cell construction.
+//
+// Control cells follow Sec. 2.2.5 of the paper: an axis-aligned auxiliary
+// Cartesian grid is laid over each donor grid (here over the grid's body
+// frame, where it never moves) and each control cell lists the donor cells
+// whose corner box reaches it. A point inside a donor cell is inside that
+// cell's corner box, so the list of the point's control cell is complete:
+// the brute-force fallback of the walk (Alg. 3) scans exactly that list.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "ov_internal.h"
+
+namespace ov {
+
+int fail(ov_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(ov_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, OV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+long long grid_size_for(const ov_ctx* ctx, long long items, int block) {
+  long long need = (items + block - 1) / block;
+  if (need < 1) need = 1;
+  if (ctx->persist > 0) {
+    long long cap = (long long)ctx->num_cus * ctx->persist;
+    if (need > cap) need = cap;
+  }
+  if (need > (1LL << 30)) need = 1LL << 30;
+  return need;
+}
+
+// ---------------------------------------------------------------- setup kernels
+// Per-block min/max of node coordinates (6 partials per block).
+__global__ void k_bounds(const double* __restrict__ X, const double* __restrict__ Y,
+                         const double* __restrict__ Z, long long n, double* __restrict__ part) {
+  __shared__ double red[6][256];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+       m += (long long)gridDim.x * blockDim.x) {
+    double v[3] = {X[m], Y[m], Z[m]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], v[d]);
+      hi[d] = fmax(hi[d], v[d]);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    red[d][threadIdx.x] = lo[d];
+    red[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int d = 0; d < 3; ++d) {
+        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// pass 0: count entries per bin and the lowest cell per bin; pass 1: fill.
+template <int PASS>
+__global__ void k_bins(GridDev g, unsigned long long* __restrict__ cnt, int* __restrict__ rep,
+                       const long long* __restrict__ start, int* __restrict__ cells) {
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncells;
+       c += (long long)gridDim.x * blockDim.x) {
+    double lo[3], hi[3];
+    cell_box(g, c, lo, hi);
+    int a0 = bin_axis(g, 0, lo[0]), a1 = bin_axis(g, 0, hi[0]);
+    int b0 = bin_axis(g, 1, lo[1]), b1 = bin_axis(g, 1, hi[1]);
+    int e0 = bin_axis(g, 2, lo[2]), e1 = bin_axis(g, 2, hi[2]);
+    for (int z = e0; z <= e1; ++z)
+      for (int y = b0; y <= b1; ++y)
+        for (int x = a0; x <= a1; ++x) {
+          long long b = x + (long long)g.nb[0] * (y + (long long)g.nb[1] * z);
+          if (PASS == 0) {
+            atomicAdd(&cnt[b], 1ULL);
+            atomicMin(&rep[b], (int)c);
+          } else {
+            unsigned long long p = atomicAdd(&cnt[b], 1ULL);
+            cells[start[b] + (long long)p] = (int)c;
+          }
+        }
+  }
+}
+
+__global__ void k_fill_int(int* p, long long n, int v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, long long n, uint8_t v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ULL;
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+static long long blocks_for(long long n, int block = 256) {
+  long long b = (n + block - 1) / block;
+  return std::max(1LL, std::min(b, 65536LL));
+}
+
+#define HIPCHK(expr, what)                       \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+int build_control_cells(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
+  GridDev& g = gh.d;
+  // box of the nodes
+  const int nbk = (int)std::min<long long>(1024, blocks_for(g.nnodes));
+  double* d_part = nullptr;
+  HIPCHK(hipMalloc(&d_part, sizeof(double) * 6 * nbk), "hipMalloc bounds");
+  hipLaunchKernelGGL(k_bounds, dim3(nbk), dim3(256), 0, s, g.X, g.Y, g.Z, g.nnodes, d_part);
+  std::vector<double> part(6 * nbk);
+  HIPCHK(hipMemcpyAsync(part.data(), d_part, sizeof(double) * 6 * nbk, hipMemcpyDeviceToHost, s), "bounds copy");
+  HIPCHK(hipStreamSynchronize(s), "bounds sync");
+  (void)hipFree(d_part);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nbk; ++b)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], part[6 * b + d]);
+      hi[d] = std::max(hi[d], part[6 * b + 3 + d]);
+    }
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]))
+      return fail(ctx, OV_EINVAL, "grid has non-finite coordinates");
+  // about two donor cells per control cell along each axis, shaped after the box
+  double ext[3], vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = std::max(hi[d] - lo[d], 1e-300);
+    vol *= ext[d];
+  }
+  double edge = std::cbrt(vol * 8.0 / (double)std::max(1LL, g.ncells));
+  long long nbins = 1;
+  for (int d = 0; d < 3; ++d) {
+    int nb = (int)std::ceil(ext[d] / edge);
+    nb = std::max(1, std::min(nb, 4096));
+    g.nb[d] = nb;
+    g.blo[d] = lo[d];
+    g.bhi[d] = hi[d];
+    g.binv[d] = nb / ext[d];
+    nbins *= nb;
+  }
+  unsigned long long* d_cnt = nullptr;
+  HIPCHK(hipMalloc(&d_cnt, sizeof(unsigned long long) * (nbins + 1)), "hipMalloc bin counts");
+  HIPCHK(hipMalloc(&gh.brep, sizeof(int) * nbins), "hipMalloc bin rep");
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nbins + 1)), dim3(256), 0, s, d_cnt, nbins + 1);
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(nbins)), dim3(256), 0, s, gh.brep, nbins, 0x7fffffff);
+  hipLaunchKernelGGL(k_bins<0>, dim3(blocks_for(g.ncells)), dim3(256), 0, s, g, d_cnt, gh.brep,
+                     (const long long*)nullptr, (int*)nullptr);
+  std::vector<unsigned long long> cnt(nbins);
+  HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(unsigned long long) * nbins, hipMemcpyDeviceToHost, s),
+         "bin count copy");
+  HIPCHK(hipStreamSynchronize(s), "bin count sync");
+  std::vector<long long> start(nbins + 1);
+  start[0] = 0;
+  for (long long b = 0; b < nbins; ++b) start[b + 1] = start[b] + (long long)cnt[b];
+  long long entries = start[nbins];
+  if (entries >= (1LL << 31)) {
+    (void)hipFree(d_cnt);
+    return fail(ctx, OV_EDIMS, "control-cell lists too large (%lld entries)", entries);
+  }
+  HIPCHK(hipMalloc(&gh.bstart, sizeof(long long) * (nbins + 1)), "hipMalloc bin start");
+  HIPCHK(hipMalloc(&gh.bcells, sizeof(int) * std::max(1LL, entries)), "hipMalloc bin cells");
+  HIPCHK(hipMemcpyAsync(gh.bstart, start.data(), sizeof(long long) * (nbins + 1), hipMemcpyHostToDevice, s),
+         "bin start copy");
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nbins + 1)), dim3(256), 0, s, d_cnt, nbins + 1);
+  hipLaunchKernelGGL(k_bins<1>, dim3(blocks_for(g.ncells)), dim3(256), 0, s, g, d_cnt, (int*)nullptr,
+                     (const long long*)gh.bstart, gh.bcells);
+  HIPCHK(hipGetLastError(), "control-cell kernels");
+  HIPCHK(hipStreamSynchronize(s), "control-cell sync");
+  (void)hipFree(d_cnt);
+  // bins that no cell reaches keep rep = INT_MAX: mark them -1
+  std::vector<int> rep(nbins);
+  HIPCHK(hipMemcpy(rep.data(), gh.brep, sizeof(int) * nbins, hipMemcpyDeviceToHost), "bin rep copy");
+  for (auto& r : rep)
+    if (r == 0x7fffffff) r = -1;
+  HIPCHK(hipMemcpy(gh.brep, rep.data(), sizeof(int) * nbins, hipMemcpyHostToDevice), "bin rep copy back");
+  g.bstart = gh.bstart;
+  g.bcells = gh.bcells;
+  g.brep = gh.brep;
+  return OV_OK;
+}
+
+int build_shadows(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
+  GridDev& g = gh.d;
+  HIPCHK(hipMalloc(&gh.xf, sizeof(float) * g.nnodes), "hipMalloc shadow");
+  HIPCHK(hipMalloc(&gh.yf, sizeof(float) * g.nnodes), "hipMalloc shadow");
+  HIPCHK(hipMalloc(&gh.zf, sizeof(float) * g.nnodes), "hipMalloc shadow");
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(g.nnodes)), dim3(256), 0, s, g.X, gh.xf, g.nnodes);
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(g.nnodes)), dim3(256), 0, s, g.Y, gh.yf, g.nnodes);
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(g.nnodes)), dim3(256), 0, s, g.Z, gh.zf, g.nnodes);
+  HIPCHK(hipGetLastError(), "shadow kernels");
+  g.Xf = gh.xf;
+  g.Yf = gh.yf;
+  g.Zf = gh.zf;
+  return OV_OK;
+}
+
+}  // namespace ov
+
+using namespace ov;
+
+// ================================================================ C ABI
+extern "C" {
+
+int ov_ctx_create(ov_ctx** out, int device, int precision) {
+  if (!out) return OV_EINVAL;
+  *out = nullptr;
+  if (precision != OV_FP64 && precision != OV_MIXED) return OV_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return OV_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return OV_EHIP;
+  ov_ctx* ctx = new ov_ctx();
+  ctx->device = device;
+  ctx->precision = precision;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->num_cus = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->d_status, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess) {
+    delete ctx;
+    return OV_EHIP;
+  }
+  *out = ctx;
+  return OV_OK;
+}
+
+int ov_ctx_destroy(ov_ctx* ctx) {
+  if (!ctx) return OV_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& g : ctx->grids) {
+    (void)hipFree(g.xf);
+    (void)hipFree(g.yf);
+    (void)hipFree(g.zf);
+    (void)hipFree(g.bstart);
+    (void)hipFree(g.bcells);
+    (void)hipFree(g.brep);
+  }
+  (void)hipFree(ctx->d_grids);
+  (void)hipFree(ctx->d_status);
+  (void)hipFree(ctx->d_warm_cell);
+  (void)hipFree(ctx->d_warm_grid);
+  (void)hipFree(ctx->d_chunk_counts);
+  (void)hipFree(ctx->d_chunk_offsets);
+  delete ctx;
+  return OV_OK;
+}
+
+const char* ov_last_error(const ov_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ov_grid_add(ov_ctx* ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t periodic, const double* X,
+                const double* Y, const double* Z, int32_t blank_kind, const double* blank_prm,
+                const int32_t* outer, int32_t* grid_id) {
+  if (!ctx) return OV_EINVAL;
+  if (ctx->finalized) return fail(ctx, OV_ESTATE, "ov_grid_add after ov_finalize");
+  if (!X || !Y || !Z || !outer || !grid_id) return fail(ctx, OV_EINVAL, "null argument to ov_grid_add");
+  if ((int)ctx->grids.size() >= kMaxGrids) return fail(ctx, OV_EINVAL, "at most %d grids", kMaxGrids);
+  if (ni < 2 || nj < 2 || nk < 2) return fail(ctx, OV_EDIMS, "grid dims must be >= 2 (got %d %d %d)", ni, nj, nk);
+  if (periodic > 7u) return fail(ctx, OV_EINVAL, "periodic mask must be in 0..7");
+  if (blank_kind < OV_BLANK_NONE || blank_kind > OV_BLANK_ELLIPSOID)
+    return fail(ctx, OV_EINVAL, "unknown blank kind %d", blank_kind);
+  if (blank_kind != OV_BLANK_NONE && !blank_prm) return fail(ctx, OV_EINVAL, "blank parameters missing");
+  long long n = (long long)ni * nj * nk;
+  if (ctx->node_off.back() + n >= (1LL << 31)) return fail(ctx, OV_EDIMS, "total nodes must stay below 2^31");
+  for (int f = 0; f < 6; ++f)
+    if (outer[f] < 0 || outer[f] > 64) return fail(ctx, OV_EINVAL, "outer layers must be in 0..64");
+  GridHost gh;
+  GridDev& g = gh.d;
+  g.ni = ni;
+  g.nj = nj;
+  g.nk = nk;
+  g.per = (int)periodic;
+  g.nci = (periodic & 1) ? ni : ni - 1;
+  g.ncj = (periodic & 2) ? nj : nj - 1;
+  g.nck = (periodic & 4) ? nk : nk - 1;
+  g.nnodes = n;
+  g.ncells = (long long)g.nci * g.ncj * g.nck;
+  if (g.ncells >= (1LL << 31)) return fail(ctx, OV_EDIMS, "too many cells");
+  g.node_off = ctx->node_off.back();
+  g.X = X;
+  g.Y = Y;
+  g.Z = Z;
+  g.blank_kind = blank_kind;
+  double r2 = 0.0;
+  if (blank_kind != OV_BLANK_NONE) {
+    for (int p = 0; p < 8; ++p) g.blank_prm[p] = blank_prm[p];
+    const double* q = blank_prm;
+    if (blank_kind == OV_BLANK_CYL) {
+      if (!(q[0] > 0) || !(q[2] >= q[1])) return fail(ctx, OV_EINVAL, "cylinder blank needs r > 0, z1 >= z0");
+      double zm = std::max(std::fabs(q[1]), std::fabs(q[2]));
+      r2 = q[0] * q[0] + zm * zm;
+    } else if (blank_kind == OV_BLANK_SPHERE) {
+      if (!(q[0] > 0)) return fail(ctx, OV_EINVAL, "sphere blank needs r > 0");
+      r2 = q[0] * q[0];
+    } else {
+      if (!(q[0] > 0 && q[1] > 0 && q[2] > 0)) return fail(ctx, OV_EINVAL, "ellipsoid blank needs a, b, c > 0");
+      double m = std::max(q[0], std::max(q[1], q[2]));
+      r2 = m * m;
+    }
+  }
+  // inflate so the cull never rejects a node the exact test would accept
+  g.cull_r2 = r2 * (1.0 + 1e-9) + 1e-300;
+  for (int f = 0; f < 6; ++f) g.outer[f] = outer[f];
+  g.tiles_i = (ni + kTileI - 1) / kTileI;
+  g.tiles_j = (nj + kTileJ - 1) / kTileJ;
+  g.tiles_k = (nk + kTileK - 1) / kTileK;
+  g.tile_off = ctx->total_tiles;
+  ctx->total_tiles += (long long)g.tiles_i * g.tiles_j * g.tiles_k;
+  *grid_id = (int32_t)ctx->grids.size();
+  ctx->grids.push_back(gh);
+  ctx->node_off.push_back(g.node_off + n);
+  return OV_OK;
+}
+
+int ov_finalize(ov_ctx* ctx, void* stream) {
+  if (!ctx) return OV_EINVAL;
+  if (ctx->finalized) return fail(ctx, OV_ESTATE, "already finalized");
+  if (ctx->grids.empty()) return fail(ctx, OV_ESTATE, "no grids");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  for (auto& g : ctx->grids) {
+    int rc = build_control_cells(ctx, g, s);
+    if (rc != OV_OK) return rc;
+    if (ctx->precision == OV_MIXED) {
+      rc = build_shadows(ctx, g, s);
+      if (rc != OV_OK) return rc;
+    }
+  }
+  long long total = ctx->node_off.back();
+  std::vector<GridDev> table;
+  for (auto& g : ctx->grids) table.push_back(g.d);
+  HIPCHK(hipMalloc(&ctx->d_grids, sizeof(GridDev) * table.size()), "hipMalloc grid table");
+  HIPCHK(hipMemcpy(ctx->d_grids, table.data(), sizeof(GridDev) * table.size(), hipMemcpyHostToDevice),
+         "grid table copy");
+  HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
+  HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
+  ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
+  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk counts");
+  HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * ctx->nchunks), "hipMalloc chunk offsets");
+  HIPCHK(hipGetLastError(), "finalize kernels");
+  HIPCHK(hipStreamSynchronize(s), "finalize sync");
+  ctx->finalized = true;
+  return OV_OK;
+}
+
+int32_t ov_num_grids(const ov_ctx* ctx) { return ctx ? (int32_t)ctx->grids.size() : 0; }
+int64_t ov_total_nodes(const ov_ctx* ctx) { return ctx ? (int64_t)ctx->node_off.back() : 0; }
+
+int ov_node_offsets(const ov_ctx* ctx, int64_t* out) {
+  if (!ctx || !out) return OV_EINVAL;
+  for (size_t g = 0; g < ctx->node_off.size(); ++g) out[g] = ctx->node_off[g];
+  return OV_OK;
+}
+
+int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
+  if (!ctx) return OV_EINVAL;
+  auto block_ok = [](int64_t b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+  switch (key) {
+    case OV_OPT_WARM:
+      if (v != 0 && v != 1) break;
+      ctx->warm = (int)v;
+      return OV_OK;
+    case OV_OPT_MAX_WALK:
+      if (v < 1 || v > 100000) break;
+      ctx->max_walk = (int)v;
+      return OV_OK;
+    case OV_OPT_SEARCH_BLOCK:
+      if (!block_ok(v)) break;
+      ctx->search_block = (int)v;
+      return OV_OK;
+    case OV_OPT_INTERP_BLOCK:
+      if (!block_ok(v)) break;
+      ctx->interp_block = (int)v;
+      return OV_OK;
+    case OV_OPT_HOLECUT_BLOCK:
+      if (!block_ok(v)) break;
+      ctx->holecut_block = (int)v;
+      return OV_OK;
+    case OV_OPT_HOLECUT_NPT:
+      if (v != 1 && v != 2 && v != 4) break;
+      ctx->holecut_npt = (int)v;
+      return OV_OK;
+    case OV_OPT_PERSIST:
+      if (v < 0 || v > 32) break;
+      ctx->persist = (int)v;
+      return OV_OK;
+    default:
+      return fail(ctx, OV_EINVAL, "unknown option %d", key);
+  }
+  return fail(ctx, OV_EINVAL, "option %d: value %lld out of range", key, (long long)v);
+}
+
+int ov_reset_history(ov_ctx* ctx, void* stream) {
+  if (!ctx) return OV_EINVAL;
+  if (!ctx->finalized) return fail(ctx, OV_ESTATE, "ov_reset_history before ov_finalize");
+  long long total = ctx->node_off.back();
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream, ctx->d_warm_grid,
+                     total, (uint8_t)255);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? OV_OK : hip_fail(ctx, e, "reset history");
+}
+
+int ov_status_fetch(ov_ctx* ctx, int32_t* host_status, void* stream) {
+  if (!ctx || !host_status) return OV_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t v = 0;
+  hipError_t e = hipMemcpyAsync(&v, ctx->d_status, sizeof v, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "status fetch");
+  *host_status = v;
+  return OV_OK;
+}
+
+}  // extern "C"

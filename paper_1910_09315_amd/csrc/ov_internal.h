@@ -1,0 +1,182 @@
+// Internal declarations of the gfx950 overset grid-assembly library.
+// Device-side grid table, context layout and the launchers each kernel file
+// provides. Nothing here is part of the C ABI (see include/overset.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "overset.h"
+
+namespace ov {
+
+constexpr int kMaxGrids = OV_MAX_GRIDS;
+constexpr uint8_t kHole = OV_STATE_HOLE;
+constexpr uint8_t kFringe = OV_STATE_FRINGE;
+
+// Containment and Newton constants: a cell contains a point iff its
+// natural coordinates lie in [-kSTol, 1 + kSTol]^3; Newton stops once its
+// last step is at most kNewtonTol (FP64).
+constexpr double kSTol = 1e-12;
+constexpr double kNewtonTol = 1e-12;
+constexpr int kNewtonMaxIt = 50;
+constexpr double kDetMin = 1e-300;
+
+// Fringe-marking tile (nodes along i, j, k) and the widest buffer supported.
+constexpr int kTileI = 64, kTileJ = 8, kTileK = 8;
+constexpr int kMaxNf = 3;
+// Compaction chunk: 256 threads x 16 flag bytes.
+constexpr int kCompactThreads = 256;
+constexpr int kCompactChunk = kCompactThreads * 16;
+
+// One grid as the kernels see it.
+struct GridDev {
+  int ni, nj, nk, per;
+  int nci, ncj, nck, blank_kind;
+  long long node_off, nnodes, ncells;
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const float* Xf;  // FP32 shadows (mixed precision), else null
+  const float* Yf;
+  const float* Zf;
+  double blank_prm[8];
+  double cull_r2;  // body-frame sphere about the origin enclosing the blank region, squared
+  int outer[6];
+  int tiles_i, tiles_j, tiles_k;
+  long long tile_off;  // first fringe tile of this grid
+  // control cells: uniform bins over the body-frame box of the grid's nodes
+  double blo[3], bhi[3], binv[3];
+  int nb[3];
+  int pad_;
+  const long long* bstart;  // [nbins + 1]
+  const int* bcells;        // candidate donor cells, bin after bin
+  const int* brep;          // lowest cell of each bin, -1 if empty
+};
+
+struct GridHost {
+  GridDev d{};
+  // library-owned device buffers of this grid
+  float* xf = nullptr;
+  float* yf = nullptr;
+  float* zf = nullptr;
+  long long* bstart = nullptr;
+  int* bcells = nullptr;
+  int* brep = nullptr;
+};
+
+}  // namespace ov
+
+struct ov_ctx {
+  int device = 0;
+  int precision = OV_FP64;
+  int num_cus = 256;
+  bool finalized = false;
+  std::vector<ov::GridHost> grids;
+  std::vector<long long> node_off{0};
+  long long total_tiles = 0;
+  ov::GridDev* d_grids = nullptr;
+  int32_t* d_status = nullptr;
+  int32_t* d_warm_cell = nullptr;
+  uint8_t* d_warm_grid = nullptr;
+  int32_t* d_chunk_counts = nullptr;
+  long long* d_chunk_offsets = nullptr;
+  long long nchunks = 0;
+  // options
+  int warm = 1;
+  int max_walk = 64;
+  int search_block = 64;
+  int interp_block = 256;
+  int holecut_block = 256;
+  int holecut_npt = 1;
+  int persist = 0;
+  std::string err;
+};
+
+namespace ov {
+
+int fail(ov_ctx* ctx, int code, const char* fmt, ...);
+int hip_fail(ov_ctx* ctx, hipError_t e, const char* what);
+long long grid_size_for(const ov_ctx* ctx, long long items, int block);
+
+// launchers (kernel files)
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s);
+hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s);
+hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
+                          long long capacity, long long* d_count, hipStream_t s);
+hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_grid, const int32_t* q_node,
+                            const long long* d_count, long long capacity, void* qx, hipStream_t s);
+hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                               const int32_t* q_node, const void* qx, const long long* d_count,
+                               long long capacity, int32_t* donor_grid, int32_t* donor_cell, void* s,
+                               int32_t* status, hipStream_t st);
+hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* donor_cell, const void* s,
+                         const long long* d_count, long long capacity, const void* fields, void* out,
+                         hipStream_t st);
+// setup (control cells, shadows)
+int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);
+int build_shadows(ov_ctx* ctx, GridHost& g, hipStream_t s);
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int grid_of_node(const long long* off, int ngrids, long long n) {
+  int lo = 0, hi = ngrids - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= n) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void cell_ijk(const GridDev& g, long long cell, int& ci, int& cj, int& ck) {
+  long long plane = (long long)g.nci * g.ncj;
+  ck = (int)(cell / plane);
+  long long r = cell - (long long)ck * plane;
+  cj = (int)(r / g.nci);
+  ci = (int)(r - (long long)cj * g.nci);
+}
+
+// Node of corner c (c0 + 2 c1 + 4 c2) of cell (ci, cj, ck); periodic wrap.
+__device__ __forceinline__ long long corner_node(const GridDev& g, int ci, int cj, int ck, int c) {
+  int i = ci + (c & 1), j = cj + ((c >> 1) & 1), k = ck + ((c >> 2) & 1);
+  i = (i == g.ni) ? 0 : i;
+  j = (j == g.nj) ? 0 : j;
+  k = (k == g.nk) ? 0 : k;
+  return (long long)i + (long long)g.ni * ((long long)j + (long long)g.nj * k);
+}
+
+// Padded corner box of a cell (FP64), the same test the fallback scan applies.
+__device__ __forceinline__ void cell_box(const GridDev& g, long long cell, double lo[3], double hi[3]) {
+  int ci, cj, ck;
+  cell_ijk(g, cell, ci, cj, ck);
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = INFINITY;
+    hi[d] = -INFINITY;
+  }
+  for (int c = 0; c < 8; ++c) {
+    long long m = corner_node(g, ci, cj, ck, c);
+    double v[3] = {g.X[m], g.Y[m], g.Z[m]};
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], v[d]);
+      hi[d] = fmax(hi[d], v[d]);
+    }
+  }
+  double ext = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+  double pad = 1e-9 * ext + 1e-300;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] -= pad;
+    hi[d] += pad;
+  }
+}
+
+__device__ __forceinline__ int bin_axis(const GridDev& g, int d, double v) {
+  double t = floor((v - g.blo[d]) * g.binv[d]);
+  if (!(t >= 0.0)) return 0;  // also NaN
+  if (t >= (double)g.nb[d]) return g.nb[d] - 1;
+  return (int)t;
+}
+
+}  // namespace ov

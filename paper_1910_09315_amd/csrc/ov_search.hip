@@ -1,0 +1,422 @@
+// Donor search on gfx950 (Sec. 2.2.5 and Alg. 3 of arXiv:1910.09315, donor
+// selection of Sec. 2.4 item 1).
+//
+// One query per lane. For each candidate donor grid the query is taken into
+// that grid's body frame (in FP64), then a stencil walk moves from a seed cell
+// (last step's donor, else the lowest cell of the query's control cell)
+// toward the cell whose trilinear natural coordinates s, found by Newton's
+// method, lie in [0,1]^3. Alg. 3 steps by the signs of face distances; here
+// the signs of s and s-1 play that role (their sign pattern is what the
+// face tests measure, and Newton's s is needed for containment anyway).
+// A walk that leaves the grid, revisits its previous cell, meets a blanked
+// donor or runs out of steps hands over to the brute-force scan of the
+// control cell (Alg. 3, label nxtp), which keeps the lowest valid containing
+// cell index. The walk only accelerates: the scan defines the result.
+//
+// Precision: the natural-coordinate solve runs in T. With T = float (mixed
+// precision) every offset is formed in FP64 from FP64 corners and only then
+// rounded, so the FP32 solve sees cell-local quantities; a result is kept
+// only if its FP32 margin to every face is >= 1e-4 and the cell's Jacobian
+// condition estimate is <= 1e3, otherwise the walk continues in FP64 from
+// that cell (the FP64 correction).
+#include <hip/hip_runtime.h>
+
+#include "ov_internal.h"
+
+namespace ov {
+
+constexpr float kMixedMargin = 1e-4f;
+constexpr float kMixedCond = 1e3f;
+// FP32 steps on only when the point is at least this far outside the cell
+// (in natural coordinates); nearer, FP64 takes over.
+constexpr float kClearlyOutside = 1e-2f;
+constexpr float kNewtonTolF = 2e-6f;
+constexpr int kNewtonMaxItF = 16;
+
+enum WalkResult { kFound = 1, kToScan = 0, kDoubt = 2 };
+
+// Trilinear map of a cell relative to its corner 0:
+//   x(s) - P0 = a1 s0 + a2 s1 + a3 s2 + a4 s0 s1 + a5 s0 s2 + a6 s1 s2 + a7 s0 s1 s2,
+// coefficients formed in FP64 from the corners and rounded to T.
+template <typename T>
+struct CellMap {
+  T a[8][3];  // a[1..7]
+  T e[3];     // query - P0
+};
+
+template <typename T>
+__device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int ck, const double xi[3],
+                                          CellMap<T>& m) {
+  double P[8][3];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    long long n = corner_node(G, ci, cj, ck, c);
+    P[c][0] = G.X[n];
+    P[c][1] = G.Y[n];
+    P[c][2] = G.Z[n];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double p0 = P[0][d];
+    double q1 = P[1][d] - p0, q2 = P[2][d] - p0, q3 = P[3][d] - p0, q4 = P[4][d] - p0;
+    double q5 = P[5][d] - p0, q6 = P[6][d] - p0, q7 = P[7][d] - p0;
+    m.e[d] = (T)(xi[d] - p0);
+    m.a[1][d] = (T)q1;
+    m.a[2][d] = (T)q2;
+    m.a[3][d] = (T)q4;
+    m.a[4][d] = (T)(q3 - q1 - q2);
+    m.a[5][d] = (T)(q5 - q1 - q4);
+    m.a[6][d] = (T)(q6 - q2 - q4);
+    m.a[7][d] = (T)(q7 - q3 - q5 - q6 + q1 + q2 + q4);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void map_and_jacobian(const CellMap<T>& m, const T s[3], T r[3], T J[3][3]) {
+  T st = s[0] * s[1], su = s[0] * s[2], tu = s[1] * s[2], stu = st * s[2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r[d] = m.a[1][d] * s[0] + m.a[2][d] * s[1] + m.a[3][d] * s[2] + m.a[4][d] * st + m.a[5][d] * su +
+           m.a[6][d] * tu + m.a[7][d] * stu - m.e[d];
+    J[d][0] = m.a[1][d] + m.a[4][d] * s[1] + m.a[5][d] * s[2] + m.a[7][d] * tu;
+    J[d][1] = m.a[2][d] + m.a[4][d] * s[0] + m.a[6][d] * s[2] + m.a[7][d] * su;
+    J[d][2] = m.a[3][d] + m.a[5][d] * s[0] + m.a[6][d] * s[1] + m.a[7][d] * st;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T det3(const T J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// Newton's method from s = (1/2, 1/2, 1/2) for x(s) = query. Returns true when
+// the last step is <= tol (and, in FP64, |det J| >= kDetMin at the result).
+// *cond receives ||J||_F ||J^-1||_F at the result (an upper bound of the
+// 2-norm condition number).
+template <typename T>
+__device__ bool newton(const CellMap<T>& m, T s[3], T* cond) {
+  const T tol = sizeof(T) == 8 ? (T)kNewtonTol : (T)kNewtonTolF;
+  const int maxit = sizeof(T) == 8 ? kNewtonMaxIt : kNewtonMaxItF;
+  s[0] = s[1] = s[2] = (T)0.5;
+  for (int it = 0; it < maxit; ++it) {
+    T r[3], J[3][3];
+    map_and_jacobian(m, s, r, J);
+    // Cramer's rule with the columns of J
+    T c12[3] = {J[1][1] * J[2][2] - J[2][1] * J[1][2], J[2][1] * J[0][2] - J[0][1] * J[2][2],
+                J[0][1] * J[1][2] - J[1][1] * J[0][2]};
+    T det = J[0][0] * c12[0] + J[1][0] * c12[1] + J[2][0] * c12[2];
+    if (det == (T)0) return false;
+    T inv = (T)1 / det;
+    T d0 = (r[0] * c12[0] + r[1] * c12[1] + r[2] * c12[2]) * inv;
+    // column 1 replaced by r: det[J0, r, J2] = J0 . (r x J2)
+    T rx2[3] = {r[1] * J[2][2] - r[2] * J[1][2], r[2] * J[0][2] - r[0] * J[2][2], r[0] * J[1][2] - r[1] * J[0][2]};
+    T d1 = (J[0][0] * rx2[0] + J[1][0] * rx2[1] + J[2][0] * rx2[2]) * inv;
+    // column 2 replaced by r: det[J0, J1, r] = J0 . (J1 x r)
+    T j1r[3] = {J[1][1] * r[2] - J[2][1] * r[1], J[2][1] * r[0] - J[0][1] * r[2], J[0][1] * r[1] - J[1][1] * r[0]};
+    T d2 = (J[0][0] * j1r[0] + J[1][0] * j1r[1] + J[2][0] * j1r[2]) * inv;
+    s[0] -= d0;
+    s[1] -= d1;
+    s[2] -= d2;
+    T dm = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
+    if (!(dm == dm) || !(fabs(s[0]) < (T)1e6 && fabs(s[1]) < (T)1e6 && fabs(s[2]) < (T)1e6)) return false;
+    if (dm <= tol) {
+      map_and_jacobian(m, s, r, J);
+      T dt = det3(J);
+      if (sizeof(T) == 8 && !(fabs((double)dt) >= kDetMin)) return false;
+      if (dt == (T)0) return false;
+      if (cond) {
+        T nj = 0, na = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            nj += J[i][j] * J[i][j];
+            // cofactor (i, j)
+            int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            T cf = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+            na += cf * cf;
+          }
+        *cond = sqrt(nj) * sqrt(na) / fabs(dt);
+      }
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename T>
+__device__ __forceinline__ bool inside(const T s[3], T tol) {
+  return s[0] >= -tol && s[0] <= (T)1 + tol && s[1] >= -tol && s[1] <= (T)1 + tol && s[2] >= -tol &&
+         s[2] <= (T)1 + tol;
+}
+
+__device__ __forceinline__ bool cell_valid(const GridDev& G, const uint8_t* fl, int ci, int cj, int ck) {
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ok &= (fl[corner_node(G, ci, cj, ck, c)] & 3) != kHole;
+  return ok;
+}
+
+__device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, bool& clamped) {
+  int w = v + dv;
+  if (periodic) {
+    w %= nc;
+    if (w < 0) w += nc;
+    return w;
+  }
+  if (w < 0) {
+    clamped = true;
+    return 0;
+  }
+  if (w >= nc) {
+    clamped = true;
+    return nc - 1;
+  }
+  return w;
+}
+
+// Stencil walk in precision T from `cell`. On kFound, cell/s hold the donor.
+// On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
+template <typename T>
+__device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3], int max_walk,
+                    bool& limit) {
+  int ci, cj, ck;
+  cell_ijk(G, cell, ci, cj, ck);
+  int pi = -1, pj = -1, pk = -1;
+  for (int stepn = 0; stepn < max_walk; ++stepn) {
+    CellMap<T> m;
+    load_cell<T>(G, ci, cj, ck, xi, m);
+    T cond = 0;
+    bool conv = newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr);
+    const int here = (int)(ci + (long long)G.nci * (cj + (long long)G.ncj * ck));
+    if (sizeof(T) == 4) {
+      // FP32 decides only clear cases: inside with margin >= 1e-4 in a
+      // well-conditioned cell, or clearly outside (then keep walking).
+      // Anything else is handed to FP64 from this cell.
+      T mg = fmin(fmin(s[0], (T)1 - s[0]), fmin(fmin(s[1], (T)1 - s[1]), fmin(s[2], (T)1 - s[2])));
+      if (!(mg == mg)) {
+        cell = here;
+        return kDoubt;
+      }
+      if (conv && cond <= (T)kMixedCond && mg >= (T)kMixedMargin) {
+        cell = here;
+        return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
+      }
+      if (mg > -(T)kClearlyOutside) {
+        cell = here;
+        return kDoubt;
+      }
+    } else {
+      if (conv && inside<T>(s, (T)kSTol)) {
+        cell = here;
+        return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
+      }
+    }
+    if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
+    // step toward the point: the integer part of s, at most 2 cells per axis
+    int di = 0, dj = 0, dk = 0;
+    if (s[0] < (T)0) di = max(-2, (int)floor(s[0]));
+    else if (s[0] > (T)1) di = min(2, (int)floor(s[0]));
+    if (s[1] < (T)0) dj = max(-2, (int)floor(s[1]));
+    else if (s[1] > (T)1) dj = min(2, (int)floor(s[1]));
+    if (s[2] < (T)0) dk = max(-2, (int)floor(s[2]));
+    else if (s[2] > (T)1) dk = min(2, (int)floor(s[2]));
+    bool clamped = false;
+    int ni = step_axis(ci, di, G.nci, G.per & 1, clamped);
+    int nj = step_axis(cj, dj, G.ncj, G.per & 2, clamped);
+    int nk = step_axis(ck, dk, G.nck, G.per & 4, clamped);
+    if ((ni == ci && nj == cj && nk == ck) || (ni == pi && nj == pj && nk == pk)) return kToScan;
+    pi = ci;
+    pj = cj;
+    pk = ck;
+    ci = ni;
+    cj = nj;
+    ck = nk;
+  }
+  limit = true;
+  return kToScan;
+}
+
+// Brute-force scan of the control cell holding xi (FP64): lowest valid
+// containing cell, or -1.
+__device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
+  long long b = bin_axis(G, 0, xi[0]) +
+                (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
+  long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
+  int best = -1;
+  for (long long e = e0; e < e1; ++e) {
+    int cell = G.bcells[e];
+    if (best >= 0 && cell >= best) continue;
+    double lo[3], hi[3];
+    cell_box(G, cell, lo, hi);
+    if (xi[0] < lo[0] || xi[0] > hi[0] || xi[1] < lo[1] || xi[1] > hi[1] || xi[2] < lo[2] || xi[2] > hi[2]) continue;
+    int ci, cj, ck;
+    cell_ijk(G, cell, ci, cj, ck);
+    CellMap<double> m;
+    load_cell<double>(G, ci, cj, ck, xi, m);
+    double s[3];
+    if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
+    if (!cell_valid(G, fl, ci, cj, ck)) continue;
+    best = cell;
+    s_best[0] = s[0];
+    s_best[1] = s[1];
+    s_best[2] = s[2];
+  }
+  return best;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_donor_search(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+                   const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                   const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
+                   long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                   T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
+                   uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status) {
+  __shared__ double sp[kMaxGrids * 12];
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  __syncthreads();
+  const long long n = min(*d_count, cap);
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+    const int A = q_grid[q];
+    const long long m = q_node[q];
+    const GridDev& GA = grids[A];
+    const long long key = GA.node_off + m;
+    const int cause = flags[key] >> 2;
+    const double* pa = sp + 12 * A;
+    // inertial position of the query: frame centre + offset from the transform
+    double x[3];
+    if (sizeof(T) == 4 && A == 0) {
+      // the background's offsets are absolute positions; take them in FP64
+      double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
+      x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
+      x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
+      x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
+    } else {
+      x[0] = pa[9] + (double)qx[q];
+      x[1] = pa[10] + (double)qx[cap + q];
+      x[2] = pa[11] + (double)qx[2 * cap + q];
+    }
+    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    bool limit = false;
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+      atomicOr(dev_status, OV_DEV_NONFINITE);
+    } else {
+      const int first = (cause != OV_CAUSE_BOUNDARY && cause != A && cause < ngrids) ? cause : -1;
+      const int wg = use_warm ? (int)warm_grid[key] : 255;
+      for (int t = -2; t < ngrids; ++t) {
+        int B;
+        if (t == -2) {
+          if (first < 0) continue;
+          B = first;
+        } else if (t == -1) {
+          if (A == 0 || first == 0) continue;
+          B = 0;
+        } else {
+          B = t;
+          if (B == A || B == first || (B == 0 && A != 0)) continue;
+        }
+        const GridDev& G = grids[B];
+        const double* pb = sp + 12 * B;
+        double d0 = x[0] - pb[9], d1 = x[1] - pb[10], d2 = x[2] - pb[11];
+        double xi[3] = {pb[0] * d0 + pb[3] * d1 + pb[6] * d2, pb[1] * d0 + pb[4] * d1 + pb[7] * d2,
+                        pb[2] * d0 + pb[5] * d1 + pb[8] * d2};
+        // outside the box of the grid's nodes: in no cell
+        double ext = fmax(G.bhi[0] - G.blo[0], fmax(G.bhi[1] - G.blo[1], G.bhi[2] - G.blo[2]));
+        double pad = 1e-8 * ext;
+        if (xi[0] < G.blo[0] - pad || xi[0] > G.bhi[0] + pad || xi[1] < G.blo[1] - pad || xi[1] > G.bhi[1] + pad ||
+            xi[2] < G.blo[2] - pad || xi[2] > G.bhi[2] + pad)
+          continue;
+        int seed = -1;
+        if (wg == B) {
+          int wc = warm_cell[key];
+          if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
+        }
+        if (seed < 0) {
+          long long b = bin_axis(G, 0, xi[0]) +
+                        (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
+          seed = G.brep[b];
+          if (seed < 0) continue;  // no cell reaches this control cell
+        }
+        const uint8_t* fl = flags + G.node_off;
+        int cell = seed;
+        int how = OV_Q_FOUND;
+        T s[3];
+        int r = walk<T>(G, fl, xi, cell, s, max_walk, limit);
+        if (sizeof(T) == 4 && r == kDoubt) {
+          double s64[3];
+          r = walk<double>(G, fl, xi, cell, s64, max_walk, limit);
+          s[0] = (T)s64[0];
+          s[1] = (T)s64[1];
+          s[2] = (T)s64[2];
+          how |= OV_Q_FP64_FIXED;
+        }
+        if (r != kFound) {
+          double s64[3];
+          cell = scan_control_cell(G, fl, xi, s64);
+          s[0] = (T)s64[0];
+          s[1] = (T)s64[1];
+          s[2] = (T)s64[2];
+          how = OV_Q_FALLBACK;
+        }
+        if (cell >= 0) {
+          res_grid = B;
+          res_cell = cell;
+          res_status = how;
+          rs[0] = s[0];
+          rs[1] = s[1];
+          rs[2] = s[2];
+          break;
+        }
+      }
+    }
+    if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+    donor_grid[q] = res_grid;
+    donor_cell[q] = res_cell;
+    status[q] = res_status;
+    s_out[q] = rs[0];
+    s_out[cap + q] = rs[1];
+    s_out[2 * cap + q] = rs[2];
+    warm_grid[key] = res_grid < 0 ? (uint8_t)255 : (uint8_t)res_grid;
+    warm_cell[key] = res_cell;
+  }
+}
+
+hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                               const int32_t* q_node, const void* qx, const long long* d_count, long long capacity,
+                               int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, hipStream_t st) {
+  int block = ctx->search_block;
+  long long grid = grid_size_for(ctx, capacity, block);
+  int ng = (int)ctx->grids.size();
+  if (ctx->precision == OV_MIXED)
+    hipLaunchKernelGGL(k_donor_search<float>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses,
+                       flags, q_grid, q_node, (const float*)qx, d_count, capacity, donor_grid, donor_cell, (float*)s,
+                       status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status);
+  else
+    hipLaunchKernelGGL(k_donor_search<double>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses,
+                       flags, q_grid, q_node, (const double*)qx, d_count, capacity, donor_grid, donor_cell,
+                       (double*)s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk,
+                       ctx->d_status);
+  return hipGetLastError();
+}
+
+}  // namespace ov
+
+using namespace ov;
+
+extern "C" int overset_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                                    const int32_t* q_node, const void* qx, const int64_t* d_count, int64_t capacity,
+                                    int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status,
+                                    void* stream) {
+  if (!ctx) return OV_EINVAL;
+  if (!ctx->finalized) return fail(ctx, OV_ESTATE, "step call before ov_finalize");
+  if (capacity < 0) return fail(ctx, OV_EINVAL, "overset_donor_search: negative capacity");
+  if (capacity == 0) return OV_OK;
+  if (!poses || !flags || !q_grid || !q_node || !qx || !d_count || !donor_grid || !donor_cell || !s || !status)
+    return fail(ctx, OV_EINVAL, "overset_donor_search: null pointer");
+  hipError_t e = launch_donor_search(ctx, poses, flags, q_grid, q_node, qx, (const long long*)d_count, capacity,
+                                     donor_grid, donor_cell, s, status, (hipStream_t)stream);
+  return e == hipSuccess ? OV_OK : hip_fail(ctx, e, "overset_donor_search");
+}

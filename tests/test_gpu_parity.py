@@ -1,0 +1,188 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs. Needs an MI355X."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _assembly(w, precision="fp64", capacity=None, options=None):
+    from paper_1910_09315_amd.assembly import Assembly
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=options)
+    if capacity is None:
+        capacity = 2 * a.count_queries(w.poses[0]) + 1024
+    a.allocate(capacity)
+    return a
+
+
+def _run_and_compare(w, steps, precision="fp64", value_rtol=1e-12, s_tol=1e-12, options=None):
+    qx_tol = 1e-14 if precision == "fp64" else 1e-6
+    o = oracle.Oracle(w.grids, w.nf)
+    a = _assembly(w, precision, options=options)
+    poses_dev = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    stats = []
+    for t in range(max(steps) + 1):
+        a.step(poses_dev[t])
+        if t in steps:
+            g = a.results()
+            r = o.step(w.poses[t], w.fields)
+            st = compare(o, w.poses[t], r, g, value_rtol=value_rtol, s_tol=s_tol, qx_tol=qx_tol)
+            st["step"] = t
+            print(w.name, precision, st, flush=True)
+            stats.append(st)
+    assert (a.ctx.status() & ~2) == 0
+    return stats
+
+
+def test_c0_fp64_matches_oracle():
+    w = W.c0()
+    st = _run_and_compare(w, [0])[0]
+    assert st["queries"] == 1040 and st["orphans"] == 144 and st["near"] == 0
+
+
+def test_c1_small_fp64_matches_oracle_every_step():
+    w = W.c1_small(steps=6)
+    _run_and_compare(w, list(range(6)))
+
+
+def test_c1_small_mixed_matches_oracle():
+    w = W.c1_small(steps=6)
+    stats = _run_and_compare(w, list(range(6)), precision="mixed", value_rtol=1e-5, s_tol=1e-4)
+    print("mixed value errors", [s["value_err"] for s in stats])
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return W.c1(steps=100)
+
+
+def test_c1_fp64_matches_oracle_sampled_steps(c1):
+    _run_and_compare(c1, [0, 1, 2, 50, 99])
+
+
+def test_c2_mixed_matches_oracle_sampled_steps(c1):
+    stats = _run_and_compare(c1, [0, 1, 50, 99], precision="mixed", value_rtol=1e-5, s_tol=1e-4)
+    print("C2 value errors", [s["value_err"] for s in stats])
+
+
+def test_warm_equals_cold_and_runs_are_deterministic():
+    w = W.c1_small(steps=4)
+    a = _assembly(w)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    warm = []
+    for t in range(4):
+        a.step(poses[t])
+        warm.append(a.results())
+    # cold: forget the history before the last step
+    a.ctx.reset_history()
+    a.step(poses[3])
+    cold = a.results()
+    o = oracle.Oracle(w.grids, w.nf)
+    ref = o.step(w.poses[3], w.fields)
+    gated = (ref["donor_grid"] >= 0) & (ref["margin"] >= 1e-3)
+    assert np.array_equal(cold["donor_cell"][gated], warm[3]["donor_cell"][gated])
+    assert np.array_equal(cold["donor_grid"] < 0, warm[3]["donor_grid"] < 0)
+    # a second identical system gives bitwise identical results at every step
+    b = _assembly(w, capacity=a.capacity)
+    for t in range(4):
+        b.step(poses[t])
+        r = b.results()
+        for k in ("flags", "q_grid", "q_node", "donor_grid", "donor_cell", "status", "s", "values"):
+            assert np.array_equal(r[k], warm[t][k], equal_nan=True), (t, k)
+
+
+def test_max_walk_one_forces_fallback_same_donors():
+    w = W.c1_small(steps=2)
+    o = oracle.Oracle(w.grids, w.nf)
+    a = _assembly(w, options={"max_walk": 1, "warm": 0})
+    a.step(w.poses[1])
+    g = a.results()
+    r = o.step(w.poses[1], w.fields)
+    compare(o, w.poses[1], r, g, value_rtol=1e-12)
+
+
+def test_capacity_overflow_sets_status_and_writes_nothing_past_capacity():
+    w = W.c0()
+    a = _assembly(w, capacity=100)
+    sentinel = torch.full((200,), -7, dtype=torch.int32, device="cuda")
+    a.q_grid = torch.cat([a.q_grid[:100], sentinel[:100]]).contiguous()
+    a.q_node = torch.cat([a.q_node[:100], sentinel[100:]]).contiguous()
+    a.step(w.poses[0])
+    torch.cuda.synchronize()
+    assert int(a.d_count.item()) == 1040
+    assert a.ctx.status() & 1
+    assert torch.all(a.q_grid[100:] == -7) and torch.all(a.q_node[100:] == -7)
+    # the first 100 entries are the first 100 of the ordered list
+    o = oracle.Oracle(w.grids, w.nf)
+    r = o.step(w.poses[0], w.fields)
+    assert np.array_equal(a.q_node[:100].cpu().numpy(), r["q_node"][:100])
+
+
+def test_no_fringe_gives_zero_queries():
+    bg = W.cartesian_grid(9)
+    g1 = W.cartesian_grid(3, lo=(0.3, 0.3, 0.3), hi=(0.6, 0.6, 0.6))
+    w = W.Workload("empty", [bg, g1], nf=0, steps=1, poses=np.stack([W.IDENTITY_POSE] * 2)[None],
+                   fields=np.zeros((4, bg.nodes + g1.nodes)))
+    a = _assembly(w, capacity=16)
+    a.step(w.poses[0])
+    r = a.results()
+    assert r["count"] == 0 and np.all(r["flags"] == 0)
+
+
+def test_linear_field_reproduced_on_gpu():
+    """u = 1 + 2x - 3y + 0.5z on every grid at t=0 positions is interpolated
+    exactly (1e-12) at every non-orphan query of step 0."""
+    w = W.c1_small(steps=1)
+    off = w.node_offsets
+    F = np.zeros((4, w.total_nodes))
+    for g, grid in enumerate(w.grids):
+        x, y, z = W.world_coords(grid, w.poses[0, g])
+        F[0, off[g]:off[g + 1]] = W.linear_field(x, y, z)
+    w.fields = F
+    a = _assembly(w)
+    a.step(w.poses[0])
+    r = a.results()
+    o = oracle.Oracle(w.grids, w.nf)
+    from parity import query_world
+    xw = query_world(o, w.poses[0], r["q_grid"], r["q_node"])
+    ok = r["donor_grid"] >= 0
+    want = W.linear_field(xw[:, 0], xw[:, 1], xw[:, 2])
+    assert np.abs(r["values"][0][ok] - want[ok]).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_graph_replay_matches_eager():
+    w = W.c1_small(steps=5)
+    a = _assembly(w)
+    b = _assembly(w, capacity=a.capacity)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    b.capture()
+    for t in range(5):
+        a.step(poses[t])
+        ra = a.results()
+        b.replay(poses[t])
+        rb = b.results()
+        for k in ("flags", "q_node", "donor_grid", "donor_cell", "s", "values"):
+            assert np.array_equal(ra[k], rb[k], equal_nan=True), (t, k)
+
+
+def test_bad_arguments_rejected_before_launch():
+    from paper_1910_09315_amd import binding as B
+    w = W.c0()
+    a = _assembly(w, capacity=16)
+    with pytest.raises(B.OversetError):
+        B.overset_fringe_compact(a.ctx, 4, a.flags, a.q_grid, a.q_node, 16, a.d_count)
+    with pytest.raises(B.OversetError):
+        B.overset_holecut(a.ctx, None, a.flags)
+    with pytest.raises(B.OversetError):
+        a.ctx.set_option("search_block", 100)
+    ctx = B.Context(0)
+    x = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.OversetError):
+        ctx.grid_add((1, 2, 4), 0, x, x, x)
+    with pytest.raises(B.OversetError):
+        B.overset_holecut(ctx, x, a.flags)  # before finalize
