@@ -158,22 +158,28 @@ int ov_status_fetch(ov_ctx *ctx, int32_t *host_status, void *stream);
 /* Hole cutting (Sec. 2.2.2, Sec. 2.4 item 2). For every node of every grid A,
  * in A's pose, and every other grid B with a blank region: the node is a HOLE
  * iff it lies strictly inside B's blank region placed at B's pose; the cause
- * is the lowest such B. Writes a hole/field flag byte for every node.
+ * is the lowest such B. Every node's flag byte is overwritten: HOLE (cause B);
+ * else FRINGE with cause 63 if the node lies in one of its grid's `outer`
+ * layers (a fixed set per grid, marked here so that the fringe pass only
+ * visits tiles near holes); else FIELD. The call also records, for the
+ * fringe pass of the same context, which node tiles hold a hole.
  *  poses   ngrids poses (12 doubles each)
  *  flags   total_nodes bytes, fully overwritten */
 int overset_holecut(ov_ctx *ctx, const double *poses, uint8_t *flags, void *stream);
 
 /* Query-point identification and compaction (Sec. 2.2.3 item 1, Alg. 1).
- * Marks FRINGE: (a) the `outer` face layers of each grid, cause 63; (b) the
- * buffer layer, every non-hole node within Chebyshev index distance `nf` of a
- * hole of its own grid (periodic directions wrap), cause = the lowest cause of
- * those holes. Hole > fringe > field. Then writes the fringe nodes in ascending
- * (grid, node) order to q_grid / q_node (local node index) and their number to
- * *d_count (device int64). Entries beyond `capacity` are not written; the
- * device status bit OV_DEV_CAPACITY is set instead.
+ * FRINGE nodes are (a) the `outer` face layers of each grid, cause 63 (marked
+ * by overset_holecut) and (b) the buffer layer: every non-hole node within
+ * Chebyshev index distance `nf` of a hole of its own grid (periodic
+ * directions wrap), cause = the lowest cause of those holes. Hole > fringe >
+ * field. Then writes the fringe nodes in ascending (grid, node) order to
+ * q_grid / q_node (local node index) and their number to *d_count (device
+ * int64). Entries beyond `capacity` are not written; the device status bit
+ * OV_DEV_CAPACITY is set instead.
  *  nf         buffer width, 0..3
- *  flags      hole/field flags from overset_holecut, updated in place;
- *             16-byte aligned */
+ *  flags      the output of overset_holecut on this context, unmodified
+ *             (the call uses the hole-tile record that hole cut left);
+ *             updated in place; 16-byte aligned */
 int overset_fringe_compact(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
                            int64_t capacity, int64_t *d_count, void *stream);
 

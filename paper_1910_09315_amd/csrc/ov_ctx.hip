@@ -271,6 +271,11 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_status);
   (void)hipFree(ctx->d_warm_cell);
   (void)hipFree(ctx->d_warm_grid);
+  (void)hipFree(ctx->d_tile_hole);
+  (void)hipFree(ctx->d_near_list);
+  (void)hipFree(ctx->d_near_count);
+  (void)hipFree(ctx->d_scanq);
+  (void)hipFree(ctx->d_scanq_count);
   (void)hipFree(ctx->d_chunk_counts);
   (void)hipFree(ctx->d_chunk_offsets);
   delete ctx;
@@ -331,7 +336,11 @@ int ov_grid_add(ov_ctx* ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t period
   }
   // inflate so the cull never rejects a node the exact test would accept
   g.cull_r2 = r2 * (1.0 + 1e-9) + 1e-300;
-  for (int f = 0; f < 6; ++f) g.outer[f] = outer[f];
+  g.has_outer = 0;
+  for (int f = 0; f < 6; ++f) {
+    g.outer[f] = outer[f];
+    if (outer[f] > 0) g.has_outer = 1;
+  }
   g.tiles_i = (ni + kTileI - 1) / kTileI;
   g.tiles_j = (nj + kTileJ - 1) / kTileJ;
   g.tiles_k = (nk + kTileK - 1) / kTileK;
@@ -366,6 +375,15 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
   HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
+  HIPCHK(hipMalloc(&ctx->d_tile_hole, std::max(1LL, ctx->total_tiles)), "hipMalloc tile map");
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(ctx->total_tiles)), dim3(256), 0, s, ctx->d_tile_hole,
+                     ctx->total_tiles, (uint8_t)0);
+  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int) * std::max(1LL, ctx->total_tiles)), "hipMalloc near list");
+  HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int)), "hipMalloc near count");
+  HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int), s), "near count init");
+  ctx->scanq_cap = 65536;
+  HIPCHK(hipMalloc(&ctx->d_scanq, sizeof(int2) * ctx->scanq_cap), "hipMalloc scan queue");
+  HIPCHK(hipMalloc(&ctx->d_scanq_count, sizeof(int)), "hipMalloc scan queue count");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
   HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk counts");
   HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * ctx->nchunks), "hipMalloc chunk offsets");

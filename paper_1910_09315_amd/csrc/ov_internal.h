@@ -46,6 +46,7 @@ struct GridDev {
   double blank_prm[8];
   double cull_r2;  // body-frame sphere about the origin enclosing the blank region, squared
   int outer[6];
+  int has_outer;
   int tiles_i, tiles_j, tiles_k;
   long long tile_off;  // first fringe tile of this grid
   // control cells: uniform bins over the body-frame box of the grid's nodes
@@ -82,6 +83,12 @@ struct ov_ctx {
   int32_t* d_status = nullptr;
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
+  uint8_t* d_tile_hole = nullptr;  // per fringe tile: holds a hole (set by the hole cut, cleared by compaction)
+  int* d_near_list = nullptr;      // tiles near a hole (fringe pass)
+  int* d_near_count = nullptr;
+  int2* d_scanq = nullptr;         // queries whose walk fell back to the brute-force scan
+  int* d_scanq_count = nullptr;
+  int scanq_cap = 0;
   int32_t* d_chunk_counts = nullptr;
   long long* d_chunk_offsets = nullptr;
   long long nchunks = 0;
@@ -91,7 +98,7 @@ struct ov_ctx {
   int search_block = 64;
   int interp_block = 256;
   int holecut_block = 256;
-  int holecut_npt = 1;
+  int holecut_npt = 4;
   int persist = 0;
   std::string err;
 };

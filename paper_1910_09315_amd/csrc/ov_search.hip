@@ -45,16 +45,7 @@ struct CellMap {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int ck, const double xi[3],
-                                          CellMap<T>& m) {
-  double P[8][3];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    long long n = corner_node(G, ci, cj, ck, c);
-    P[c][0] = G.X[n];
-    P[c][1] = G.Y[n];
-    P[c][2] = G.Z[n];
-  }
+__device__ __forceinline__ void map_from_corners(const double P[8][3], const double xi[3], CellMap<T>& m) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double p0 = P[0][d];
@@ -69,6 +60,20 @@ __device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int 
     m.a[6][d] = (T)(q6 - q2 - q4);
     m.a[7][d] = (T)(q7 - q3 - q5 - q6 + q1 + q2 + q4);
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int ck, const double xi[3],
+                                          CellMap<T>& m) {
+  double P[8][3];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    long long n = corner_node(G, ci, cj, ck, c);
+    P[c][0] = G.X[n];
+    P[c][1] = G.Y[n];
+    P[c][2] = G.Z[n];
+  }
+  map_from_corners<T>(P, xi, m);
 }
 
 template <typename T>
@@ -192,18 +197,19 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
     const int here = (int)(ci + (long long)G.nci * (cj + (long long)G.ncj * ck));
     if (sizeof(T) == 4) {
       // FP32 decides only clear cases: inside with margin >= 1e-4 in a
-      // well-conditioned cell, or clearly outside (then keep walking).
-      // Anything else is handed to FP64 from this cell.
+      // well-conditioned cell, or outside by more than the FP32 error can
+      // explain (then keep walking). Anything else goes to FP64 from here.
       T mg = fmin(fmin(s[0], (T)1 - s[0]), fmin(fmin(s[1], (T)1 - s[1]), fmin(s[2], (T)1 - s[2])));
       if (!(mg == mg)) {
         cell = here;
         return kDoubt;
       }
-      if (conv && cond <= (T)kMixedCond && mg >= (T)kMixedMargin) {
+      const bool sure = conv && cond <= (T)kMixedCond;
+      if (sure && mg >= (T)kMixedMargin) {
         cell = here;
         return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
       }
-      if (mg > -(T)kClearlyOutside) {
+      if (mg > -(sure ? (T)kMixedMargin : (T)kClearlyOutside)) {
         cell = here;
         return kDoubt;
       }
@@ -238,6 +244,51 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
   return kToScan;
 }
 
+// Sound rejection of a cell before Newton: the trilinear cell lies in the
+// convex hull of its 8 corners, so a point whose projection on some axis
+// falls outside the corners' projections (padded far beyond the containment
+// tolerance) is in no part of the cell. Axes: x, y, z (the corner box) and
+// the normals of the cell's mean i-, j- and k-faces, which separate
+// neighbouring cells, including the thin polar wedges of shell grids.
+__device__ __forceinline__ bool hull_excludes(const double P[8][3], const double xi[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double lo = P[0][d], hi = P[0][d];
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+      lo = fmin(lo, P[c][d]);
+      hi = fmax(hi, P[c][d]);
+    }
+    double pad = 1e-9 * (hi - lo) + 1e-300;
+    if (xi[d] < lo - pad || xi[d] > hi + pad) return true;
+  }
+  double ei[3], ej[3], ek[3], q[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ei[d] = (P[1][d] - P[0][d]) + (P[3][d] - P[2][d]) + (P[5][d] - P[4][d]) + (P[7][d] - P[6][d]);
+    ej[d] = (P[2][d] - P[0][d]) + (P[3][d] - P[1][d]) + (P[6][d] - P[4][d]) + (P[7][d] - P[5][d]);
+    ek[d] = (P[4][d] - P[0][d]) + (P[5][d] - P[1][d]) + (P[6][d] - P[2][d]) + (P[7][d] - P[3][d]);
+    q[d] = xi[d] - P[0][d];
+  }
+  double n[3][3] = {{ej[1] * ek[2] - ej[2] * ek[1], ej[2] * ek[0] - ej[0] * ek[2], ej[0] * ek[1] - ej[1] * ek[0]},
+                    {ek[1] * ei[2] - ek[2] * ei[1], ek[2] * ei[0] - ek[0] * ei[2], ek[0] * ei[1] - ek[1] * ei[0]},
+                    {ei[1] * ej[2] - ei[2] * ej[1], ei[2] * ej[0] - ei[0] * ej[2], ei[0] * ej[1] - ei[1] * ej[0]}};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double lo = 0.0, hi = 0.0;  // corner 0 projects to 0
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+      double v = n[a][0] * (P[c][0] - P[0][0]) + n[a][1] * (P[c][1] - P[0][1]) + n[a][2] * (P[c][2] - P[0][2]);
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+    double pq = n[a][0] * q[0] + n[a][1] * q[1] + n[a][2] * q[2];
+    double pad = 1e-9 * (hi - lo) + 1e-300;
+    if (pq < lo - pad || pq > hi + pad) return true;
+  }
+  return false;
+}
+
 // Brute-force scan of the control cell holding xi (FP64): lowest valid
 // containing cell, or -1.
 __device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
@@ -248,13 +299,19 @@ __device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const doub
   for (long long e = e0; e < e1; ++e) {
     int cell = G.bcells[e];
     if (best >= 0 && cell >= best) continue;
-    double lo[3], hi[3];
-    cell_box(G, cell, lo, hi);
-    if (xi[0] < lo[0] || xi[0] > hi[0] || xi[1] < lo[1] || xi[1] > hi[1] || xi[2] < lo[2] || xi[2] > hi[2]) continue;
     int ci, cj, ck;
     cell_ijk(G, cell, ci, cj, ck);
+    double P[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      long long nd = corner_node(G, ci, cj, ck, c);
+      P[c][0] = G.X[nd];
+      P[c][1] = G.Y[nd];
+      P[c][2] = G.Z[nd];
+    }
+    if (hull_excludes(P, xi)) continue;
     CellMap<double> m;
-    load_cell<double>(G, ci, cj, ck, xi, m);
+    map_from_corners<double>(P, xi, m);
     double s[3];
     if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
     if (!cell_valid(G, fl, ci, cj, ck)) continue;
@@ -266,6 +323,102 @@ __device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const doub
   return best;
 }
 
+// Candidate donor grid at position t of a query of grid A: t = -2 the cause
+// grid, t = -1 the background, t >= 0 grid t; -1 where that position is
+// skipped (Sec. 2.4 item 1).
+__device__ __forceinline__ int candidate_at(int t, int A, int first) {
+  if (t == -2) return first;
+  if (t == -1) return (A == 0 || first == 0) ? -1 : 0;
+  if (t == A || t == first || (t == 0 && A != 0)) return -1;
+  return t;
+}
+
+struct Query {
+  int A, cause, first;
+  long long key;
+  double x[3];
+  bool finite;
+};
+
+template <typename T>
+__device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                                            const int32_t* __restrict__ q_node, const T* __restrict__ qx,
+                                            long long cap, long long q) {
+  Query Q;
+  Q.A = q_grid[q];
+  const long long m = q_node[q];
+  const GridDev& GA = grids[Q.A];
+  Q.key = GA.node_off + m;
+  Q.cause = flags[Q.key] >> 2;
+  Q.first = (Q.cause != OV_CAUSE_BOUNDARY && Q.cause != Q.A && Q.cause < ngrids) ? Q.cause : -1;
+  const double* pa = sp + 12 * Q.A;
+  if (sizeof(T) == 4 && Q.A == 0) {
+    // the background's offsets are absolute positions; take them in FP64
+    double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
+    Q.x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
+    Q.x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
+    Q.x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
+  } else {
+    Q.x[0] = pa[9] + (double)qx[q];
+    Q.x[1] = pa[10] + (double)qx[cap + q];
+    Q.x[2] = pa[11] + (double)qx[2 * cap + q];
+  }
+  Q.finite = isfinite(Q.x[0]) && isfinite(Q.x[1]) && isfinite(Q.x[2]);
+  return Q;
+}
+
+// Query position in grid B's body frame; false if outside the box of B's nodes.
+__device__ __forceinline__ bool to_body(const GridDev& G, const double* pb, const double x[3], double xi[3]) {
+  double d0 = x[0] - pb[9], d1 = x[1] - pb[10], d2 = x[2] - pb[11];
+  xi[0] = pb[0] * d0 + pb[3] * d1 + pb[6] * d2;
+  xi[1] = pb[1] * d0 + pb[4] * d1 + pb[7] * d2;
+  xi[2] = pb[2] * d0 + pb[5] * d1 + pb[8] * d2;
+  double ext = fmax(G.bhi[0] - G.blo[0], fmax(G.bhi[1] - G.blo[1], G.bhi[2] - G.blo[2]));
+  double pad = 1e-8 * ext;
+  return !(xi[0] < G.blo[0] - pad || xi[0] > G.bhi[0] + pad || xi[1] < G.blo[1] - pad || xi[1] > G.bhi[1] + pad ||
+           xi[2] < G.blo[2] - pad || xi[2] > G.bhi[2] + pad);
+}
+
+__device__ __forceinline__ long long bin_of(const GridDev& G, const double xi[3]) {
+  return bin_axis(G, 0, xi[0]) +
+         (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
+}
+
+// Walk in grid B from `seed` (FP32 first in mixed precision, then FP64 from
+// any cell FP32 cannot decide). Returns kFound with cell/s, else kToScan.
+template <typename T>
+__device__ __forceinline__ int walk_grid(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3],
+                                         int max_walk, bool& limit, int& how) {
+  int r = walk<T>(G, fl, xi, cell, s, max_walk, limit);
+  if (sizeof(T) == 4 && r == kDoubt) {
+    double s64[3];
+    r = walk<double>(G, fl, xi, cell, s64, max_walk, limit);
+    s[0] = (T)s64[0];
+    s[1] = (T)s64[1];
+    s[2] = (T)s64[2];
+    how |= OV_Q_FP64_FIXED;
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void write_result(long long q, long long cap, long long key, int grid, int cell, int st,
+                                             const T s[3], int32_t* donor_grid, int32_t* donor_cell, T* s_out,
+                                             int32_t* status, int32_t* warm_cell, uint8_t* warm_grid) {
+  donor_grid[q] = grid;
+  donor_cell[q] = cell;
+  status[q] = st;
+  s_out[q] = s[0];
+  s_out[cap + q] = s[1];
+  s_out[2 * cap + q] = s[2];
+  warm_grid[key] = grid < 0 ? (uint8_t)255 : (uint8_t)grid;
+  warm_cell[key] = cell;
+}
+
+// Phase 1: one query per lane. The walk runs per lane; a query whose walk
+// must fall back to the brute-force scan is queued (query, candidate
+// position) for phase 2, unless the queue is full (then it scans inline).
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_donor_search(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
@@ -273,87 +426,46 @@ __global__ void __launch_bounds__(1024)
                    const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
                    long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
                    T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
-                   uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status) {
+                   uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status,
+                   int2* __restrict__ scanq, int* __restrict__ scanq_count, int scanq_cap) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
   __syncthreads();
   const long long n = min(*d_count, cap);
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-    const int A = q_grid[q];
-    const long long m = q_node[q];
-    const GridDev& GA = grids[A];
-    const long long key = GA.node_off + m;
-    const int cause = flags[key] >> 2;
-    const double* pa = sp + 12 * A;
-    // inertial position of the query: frame centre + offset from the transform
-    double x[3];
-    if (sizeof(T) == 4 && A == 0) {
-      // the background's offsets are absolute positions; take them in FP64
-      double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
-      x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
-      x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
-      x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
-    } else {
-      x[0] = pa[9] + (double)qx[q];
-      x[1] = pa[10] + (double)qx[cap + q];
-      x[2] = pa[11] + (double)qx[2 * cap + q];
-    }
+    const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q);
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
-    bool limit = false;
-    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    bool limit = false, deferred = false;
+    if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
-      const int first = (cause != OV_CAUSE_BOUNDARY && cause != A && cause < ngrids) ? cause : -1;
-      const int wg = use_warm ? (int)warm_grid[key] : 255;
+      const int wg = use_warm ? (int)warm_grid[Q.key] : 255;
       for (int t = -2; t < ngrids; ++t) {
-        int B;
-        if (t == -2) {
-          if (first < 0) continue;
-          B = first;
-        } else if (t == -1) {
-          if (A == 0 || first == 0) continue;
-          B = 0;
-        } else {
-          B = t;
-          if (B == A || B == first || (B == 0 && A != 0)) continue;
-        }
+        const int B = candidate_at(t, Q.A, Q.first);
+        if (B < 0) continue;
         const GridDev& G = grids[B];
-        const double* pb = sp + 12 * B;
-        double d0 = x[0] - pb[9], d1 = x[1] - pb[10], d2 = x[2] - pb[11];
-        double xi[3] = {pb[0] * d0 + pb[3] * d1 + pb[6] * d2, pb[1] * d0 + pb[4] * d1 + pb[7] * d2,
-                        pb[2] * d0 + pb[5] * d1 + pb[8] * d2};
-        // outside the box of the grid's nodes: in no cell
-        double ext = fmax(G.bhi[0] - G.blo[0], fmax(G.bhi[1] - G.blo[1], G.bhi[2] - G.blo[2]));
-        double pad = 1e-8 * ext;
-        if (xi[0] < G.blo[0] - pad || xi[0] > G.bhi[0] + pad || xi[1] < G.blo[1] - pad || xi[1] > G.bhi[1] + pad ||
-            xi[2] < G.blo[2] - pad || xi[2] > G.bhi[2] + pad)
-          continue;
+        double xi[3];
+        if (!to_body(G, sp + 12 * B, Q.x, xi)) continue;
         int seed = -1;
         if (wg == B) {
-          int wc = warm_cell[key];
+          int wc = warm_cell[Q.key];
           if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
         }
         if (seed < 0) {
-          long long b = bin_axis(G, 0, xi[0]) +
-                        (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
-          seed = G.brep[b];
+          seed = G.brep[bin_of(G, xi)];
           if (seed < 0) continue;  // no cell reaches this control cell
         }
         const uint8_t* fl = flags + G.node_off;
-        int cell = seed;
-        int how = OV_Q_FOUND;
+        int cell = seed, how = OV_Q_FOUND;
         T s[3];
-        int r = walk<T>(G, fl, xi, cell, s, max_walk, limit);
-        if (sizeof(T) == 4 && r == kDoubt) {
-          double s64[3];
-          r = walk<double>(G, fl, xi, cell, s64, max_walk, limit);
-          s[0] = (T)s64[0];
-          s[1] = (T)s64[1];
-          s[2] = (T)s64[2];
-          how |= OV_Q_FP64_FIXED;
-        }
-        if (r != kFound) {
+        if (walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how) != kFound) {
+          int slot = atomicAdd(scanq_count, 1);
+          if (slot < scanq_cap) {
+            scanq[slot] = make_int2((int)q, t);
+            deferred = true;
+            break;
+          }
           double s64[3];
           cell = scan_control_cell(G, fl, xi, s64);
           s[0] = (T)s64[0];
@@ -373,32 +485,153 @@ __global__ void __launch_bounds__(1024)
       }
     }
     if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-    donor_grid[q] = res_grid;
-    donor_cell[q] = res_cell;
-    status[q] = res_status;
-    s_out[q] = rs[0];
-    s_out[cap + q] = rs[1];
-    s_out[2 * cap + q] = rs[2];
-    warm_grid[key] = res_grid < 0 ? (uint8_t)255 : (uint8_t)res_grid;
-    warm_cell[key] = res_cell;
+    if (!deferred)
+      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status, rs, donor_grid, donor_cell, s_out, status,
+                      warm_cell, warm_grid);
   }
+}
+
+// Wavefront-cooperative brute-force scan: the 64 lanes split the control
+// cell's candidate list, then the lowest valid containing cell wins.
+__device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
+  const int lane = threadIdx.x & 63;
+  long long b = bin_of(G, xi);
+  long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
+  int best = 0x7fffffff;
+  double sb[3] = {0.0, 0.0, 0.0};
+  for (long long e = e0 + lane; e < e1; e += 64) {
+    int cell = G.bcells[e];
+    if (cell >= best) continue;
+    int ci, cj, ck;
+    cell_ijk(G, cell, ci, cj, ck);
+    double P[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      long long nd = corner_node(G, ci, cj, ck, c);
+      P[c][0] = G.X[nd];
+      P[c][1] = G.Y[nd];
+      P[c][2] = G.Z[nd];
+    }
+    if (hull_excludes(P, xi)) continue;
+    CellMap<double> m;
+    map_from_corners<double>(P, xi, m);
+    double s[3];
+    if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
+    if (!cell_valid(G, fl, ci, cj, ck)) continue;
+    best = cell;
+    sb[0] = s[0];
+    sb[1] = s[1];
+    sb[2] = s[2];
+  }
+  int low = best;
+  for (int o = 32; o > 0; o >>= 1) low = min(low, __shfl_xor(low, o, 64));
+  if (low == 0x7fffffff) return -1;
+  unsigned long long who = __ballot(best == low);
+  int src = __ffsll((long long)who) - 1;
+  s_best[0] = __shfl(sb[0], src, 64);
+  s_best[1] = __shfl(sb[1], src, 64);
+  s_best[2] = __shfl(sb[2], src, 64);
+  return low;
+}
+
+// Phase 2: one wavefront per queued query. All lanes follow the same (uniform)
+// path: the cooperative scan of the grid whose walk failed, then the
+// remaining candidate grids (walk, and cooperative scan if needed).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_donor_scan(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+                 const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                 const int32_t* __restrict__ q_node, const T* __restrict__ qx, long long cap,
+                 int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
+                 int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
+                 int max_walk, int32_t* __restrict__ dev_status, const int2* __restrict__ scanq,
+                 const int* __restrict__ scanq_count, int scanq_cap) {
+  __shared__ double sp[kMaxGrids * 12];
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int nq = min(*scanq_count, scanq_cap);
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nq; w += waves) {
+    const int2 item = scanq[w];
+    const long long q = item.x;
+    const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q);
+    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    bool limit = false;
+    for (int t = item.y; t < ngrids; ++t) {
+      const int B = candidate_at(t, Q.A, Q.first);
+      if (B < 0) continue;
+      const GridDev& G = grids[B];
+      double xi[3];
+      if (!to_body(G, sp + 12 * B, Q.x, xi)) continue;
+      const uint8_t* fl = flags + G.node_off;
+      int cell = -1, how = OV_Q_FALLBACK;
+      T s[3];
+      bool walked = false;
+      if (t != item.y) {
+        int seed = G.brep[bin_of(G, xi)];
+        if (seed < 0) continue;
+        cell = seed;
+        how = OV_Q_FOUND;
+        walked = walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how) == kFound;
+      }
+      if (!walked) {
+        double s64[3];
+        cell = scan_control_cell_wave(G, fl, xi, s64);
+        s[0] = (T)s64[0];
+        s[1] = (T)s64[1];
+        s[2] = (T)s64[2];
+        how = OV_Q_FALLBACK;
+      }
+      if (cell >= 0) {
+        res_grid = B;
+        res_cell = cell;
+        res_status = how;
+        rs[0] = s[0];
+        rs[1] = s[1];
+        rs[2] = s[2];
+        break;
+      }
+    }
+    if (lane == 0) {
+      if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status, rs, donor_grid, donor_cell, s_out, status,
+                      warm_cell, warm_grid);
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+template <typename T>
+static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                            const int32_t* q_node, const T* qx, const long long* d_count, long long capacity,
+                            int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, hipStream_t st) {
+  int block = ctx->search_block;
+  long long grid = grid_size_for(ctx, capacity, block);
+  int ng = (int)ctx->grids.size();
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, ctx->d_scanq_count);
+  hipLaunchKernelGGL(k_donor_search<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
+                     q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell,
+                     ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, ctx->d_scanq, ctx->d_scanq_count,
+                     ctx->scanq_cap);
+  long long g2 = std::max(1LL, std::min<long long>((long long)ctx->num_cus * 2, (capacity + 3) / 4));
+  hipLaunchKernelGGL(k_donor_scan<T>, dim3((unsigned)g2), dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid,
+                     q_node, qx, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell, ctx->d_warm_grid,
+                     ctx->max_walk, ctx->d_status, (const int2*)ctx->d_scanq, (const int*)ctx->d_scanq_count,
+                     ctx->scanq_cap);
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                                const int32_t* q_node, const void* qx, const long long* d_count, long long capacity,
                                int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, hipStream_t st) {
-  int block = ctx->search_block;
-  long long grid = grid_size_for(ctx, capacity, block);
-  int ng = (int)ctx->grids.size();
   if (ctx->precision == OV_MIXED)
-    hipLaunchKernelGGL(k_donor_search<float>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses,
-                       flags, q_grid, q_node, (const float*)qx, d_count, capacity, donor_grid, donor_cell, (float*)s,
-                       status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status);
+    launch_search_t<float>(ctx, poses, flags, q_grid, q_node, (const float*)qx, d_count, capacity, donor_grid,
+                           donor_cell, (float*)s, status, st);
   else
-    hipLaunchKernelGGL(k_donor_search<double>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses,
-                       flags, q_grid, q_node, (const double*)qx, d_count, capacity, donor_grid, donor_cell,
-                       (double*)s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk,
-                       ctx->d_status);
+    launch_search_t<double>(ctx, poses, flags, q_grid, q_node, (const double*)qx, d_count, capacity, donor_grid,
+                            donor_cell, (double*)s, status, st);
   return hipGetLastError();
 }
 

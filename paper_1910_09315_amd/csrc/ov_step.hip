@@ -26,6 +26,7 @@ struct HoleLds {
   const void* Z[kMaxGrids];
   int blank[kMaxGrids];
   int kind[kMaxGrids];
+  int outer[kMaxGrids];
   int nblank;
 };
 
@@ -37,6 +38,7 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
     const GridDev& G = grids[g];
     L.off[g] = G.node_off;
     L.kind[g] = G.blank_kind;
+    L.outer[g] = G.has_outer;
     L.cull[g] = G.cull_r2;
     L.prm[g][0] = G.blank_prm[0];
     L.prm[g][1] = G.blank_prm[1];
@@ -111,88 +113,146 @@ __device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const doubl
 // surface are decided again in FP64 from the FP64 coordinates.
 constexpr float kHoleGuard = 1e-3f;
 
+// Streaming hole cut: each thread loads the coordinates of NPT nodes (strided
+// by the block size, so every load instruction is coalesced) before testing
+// any of them, which keeps 3 * NPT loads per lane in flight.
 template <typename CT>
+__device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __restrict__ grids, int A, long long m,
+                                            CT X, CT Y, CT Z) {
+  const double* pa = L.pose[A];
+  if (sizeof(CT) == 8) {
+    double w[3];
+    w[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
+    w[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
+    w[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
+    return holecut_fp64(L, A, w);
+  }
+  float w0 = (float)pa[0] * (float)X + (float)pa[1] * (float)Y + (float)pa[2] * (float)Z + (float)pa[9];
+  float w1 = (float)pa[3] * (float)X + (float)pa[4] * (float)Y + (float)pa[5] * (float)Z + (float)pa[10];
+  float w2 = (float)pa[6] * (float)X + (float)pa[7] * (float)Y + (float)pa[8] * (float)Z + (float)pa[11];
+  bool unsure = false;
+  int cause = -1;
+  for (int b = 0; b < L.nblank; ++b) {
+    int B = L.blank[b];
+    if (B == A) continue;
+    const double* p = L.pose[B];
+    float d0 = w0 - (float)p[9], d1 = w1 - (float)p[10], d2 = w2 - (float)p[11];
+    if (d0 * d0 + d1 * d1 + d2 * d2 >= (float)L.cull[B] * 1.0001f + 1e-30f) continue;
+    float x = (float)p[0] * d0 + (float)p[3] * d1 + (float)p[6] * d2;
+    float y = (float)p[1] * d0 + (float)p[4] * d1 + (float)p[7] * d2;
+    float z = (float)p[2] * d0 + (float)p[5] * d1 + (float)p[8] * d2;
+    float f = blank_measure<float>(L.kind[B], L.prm[B], x, y, z);
+    if (fabsf(f) < kHoleGuard) {
+      unsure = true;
+      break;
+    }
+    if (f < 0.f) {
+      cause = B;
+      break;
+    }
+  }
+  if (unsure) {
+    const GridDev& G = grids[A];
+    double Xd = G.X[m], Yd = G.Y[m], Zd = G.Z[m];
+    double w[3];
+    w[0] = pa[0] * Xd + pa[1] * Yd + pa[2] * Zd + pa[9];
+    w[1] = pa[3] * Xd + pa[4] * Yd + pa[5] * Zd + pa[10];
+    w[2] = pa[6] * Xd + pa[7] * Yd + pa[8] * Zd + pa[11];
+    cause = holecut_fp64(L, A, w);
+  }
+  return cause;
+}
+
+// Flag byte of a node given its hole cause (-1: none). Holes mark their
+// fringe tile in the tile map; nodes of grids with outer layers compute their
+// (i, j, k) to mark the outer-boundary query layers (a fixed set per grid).
+__device__ __forceinline__ uint8_t node_flag(const GridDev& G, long long m, int cause, uint8_t* tile_hole) {
+  if (cause < 0 && !G.has_outer) return (uint8_t)OV_STATE_FIELD;
+  long long plane = (long long)G.ni * G.nj;
+  int k = (int)(m / plane);
+  long long r = m - (long long)k * plane;
+  int j = (int)(r / G.ni);
+  int i = (int)(r - (long long)j * G.ni);
+  if (cause >= 0) {
+    tile_hole[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] = 1;
+    return (uint8_t)(kHole | (cause << 2));
+  }
+  bool onb = i < G.outer[0] || i >= G.ni - G.outer[1] || j < G.outer[2] || j >= G.nj - G.outer[3] ||
+             k < G.outer[4] || k >= G.nk - G.outer[5];
+  return onb ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint8_t)OV_STATE_FIELD;
+}
+
+template <typename CT, int NPT>
 __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ grids, int ngrids,
                                                  const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                 long long total) {
+                                                 long long total, uint8_t* __restrict__ tile_hole) {
   __shared__ HoleLds L;
   holecut_stage<CT>(L, grids, ngrids, poses);
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < total; n += stride) {
-    int A = grid_of_node(L.off, ngrids, n);
-    long long m = n - L.off[A];
-    const CT* Xa = (const CT*)L.X[A];
-    const CT* Ya = (const CT*)L.Y[A];
-    const CT* Za = (const CT*)L.Z[A];
-    CT X = Xa[m], Y = Ya[m], Z = Za[m];
-    const double* pa = L.pose[A];
-    int cause = -1;
-    if (sizeof(CT) == 8) {
-      double w[3];
-      w[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
-      w[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
-      w[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
-      cause = holecut_fp64(L, A, w);
-    } else {
-      float w0 = (float)pa[0] * (float)X + (float)pa[1] * (float)Y + (float)pa[2] * (float)Z + (float)pa[9];
-      float w1 = (float)pa[3] * (float)X + (float)pa[4] * (float)Y + (float)pa[5] * (float)Z + (float)pa[10];
-      float w2 = (float)pa[6] * (float)X + (float)pa[7] * (float)Y + (float)pa[8] * (float)Z + (float)pa[11];
-      bool unsure = false;
-      for (int b = 0; b < L.nblank; ++b) {
-        int B = L.blank[b];
-        if (B == A) continue;
-        const double* p = L.pose[B];
-        float d0 = w0 - (float)p[9], d1 = w1 - (float)p[10], d2 = w2 - (float)p[11];
-        if (d0 * d0 + d1 * d1 + d2 * d2 >= (float)L.cull[B] * 1.0001f + 1e-30f) continue;
-        float x = (float)p[0] * d0 + (float)p[3] * d1 + (float)p[6] * d2;
-        float y = (float)p[1] * d0 + (float)p[4] * d1 + (float)p[7] * d2;
-        float z = (float)p[2] * d0 + (float)p[5] * d1 + (float)p[8] * d2;
-        float f = blank_measure<float>(L.kind[B], L.prm[B], x, y, z);
-        if (fabsf(f) < kHoleGuard) {
-          unsure = true;
-          break;
-        }
-        if (f < 0.f) {
-          cause = B;
-          break;
-        }
-      }
-      if (unsure) {
-        const GridDev& G = grids[A];
-        double Xd = G.X[m], Yd = G.Y[m], Zd = G.Z[m];
-        double w[3];
-        w[0] = pa[0] * Xd + pa[1] * Yd + pa[2] * Zd + pa[9];
-        w[1] = pa[3] * Xd + pa[4] * Yd + pa[5] * Zd + pa[10];
-        w[2] = pa[6] * Xd + pa[7] * Yd + pa[8] * Zd + pa[11];
-        cause = holecut_fp64(L, A, w);
+  const long long span = (long long)blockDim.x * NPT;
+  for (long long base = (long long)blockIdx.x * span; base < total; base += (long long)gridDim.x * span) {
+    CT X[NPT], Y[NPT], Z[NPT];
+    int A[NPT];
+    long long m[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      long long n = base + (long long)r * blockDim.x + threadIdx.x;
+      A[r] = 0;
+      m[r] = -1;
+      if (n < total) {
+        A[r] = grid_of_node(L.off, ngrids, n);
+        m[r] = n - L.off[A[r]];
+        X[r] = __builtin_nontemporal_load((const CT*)L.X[A[r]] + m[r]);
+        Y[r] = __builtin_nontemporal_load((const CT*)L.Y[A[r]] + m[r]);
+        Z[r] = __builtin_nontemporal_load((const CT*)L.Z[A[r]] + m[r]);
       }
     }
-    flags[n] = cause < 0 ? (uint8_t)OV_STATE_FIELD : (uint8_t)(kHole | (cause << 2));
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      if (m[r] < 0) continue;
+      int cause = holecut_node<CT>(L, grids, A[r], m[r], X[r], Y[r], Z[r]);
+      flags[base + (long long)r * blockDim.x + threadIdx.x] =
+          (cause < 0 && !L.outer[A[r]]) ? (uint8_t)OV_STATE_FIELD : node_flag(grids[A[r]], m[r], cause, tile_hole);
+    }
   }
 }
 
-hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+template <typename CT>
+static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
   long long total = ctx->node_off.back();
   int block = ctx->holecut_block;
-  long long grid = grid_size_for(ctx, total, block);
+  int npt = ctx->holecut_npt;
+  long long chunks = (total + (long long)block * npt - 1) / ((long long)block * npt);
+  int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+  long long grid = std::max(1LL, std::min(chunks, (long long)ctx->num_cus * per_cu));
   int ng = (int)ctx->grids.size();
-  if (ctx->precision == OV_MIXED)
-    hipLaunchKernelGGL(k_holecut<float>, dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       total);
+  if (npt == 4)
+    hipLaunchKernelGGL((k_holecut<CT, 4>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
+                       total, ctx->d_tile_hole);
+  else if (npt == 2)
+    hipLaunchKernelGGL((k_holecut<CT, 2>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
+                       total, ctx->d_tile_hole);
   else
-    hipLaunchKernelGGL(k_holecut<double>, dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       total);
+    hipLaunchKernelGGL((k_holecut<CT, 1>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
+                       total, ctx->d_tile_hole);
+}
+
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+  if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s);
+  else launch_holecut_t<double>(ctx, poses, flags, s);
   return hipGetLastError();
 }
 
 // ================================================================ fringe marking
-// One block per 3D tile of kTileI x kTileJ x kTileK nodes. The tile plus a
-// halo of nf nodes is staged in LDS as "cause if hole, 255 otherwise"; a
-// separable min filter over the (2nf+1)^3 box (i, then j, then k) gives, for
-// every node, the lowest cause of a hole within Chebyshev distance nf.
+// The hole cut already wrote holes, the outer-boundary layers and, per 3D
+// tile of kTileI x kTileJ x kTileK nodes, whether the tile holds a hole.
+// Only tiles with a hole in themselves or a neighbour tile (nf < tile size,
+// so the buffer reaches no further) can gain buffer nodes: one thread per
+// tile lists them, then one block per listed tile stages the tile plus an
+// nf halo in LDS as "cause if hole, 255 otherwise" and takes the lowest cause
+// within Chebyshev distance nf by a separable min filter (i, then j, then k).
 // Holes are never rewritten, so updating flags in place is race-free: a
 // neighbour tile only reads whether a node is a hole.
-constexpr int kEI = kTileI + 2 * kMaxNf, kEJ = kTileJ + 2 * kMaxNf, kEK = kTileK + 2 * kMaxNf;
+static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8, "tile indexing below uses shifts");
 
 __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
   if (v >= 0 && v < n) return v;
@@ -201,34 +261,76 @@ __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
   return v < 0 ? v + n : v;
 }
 
-__global__ void __launch_bounds__(256) k_fringe(const GridDev* __restrict__ grids, int ngrids, int nf,
-                                               uint8_t* __restrict__ flags, long long total_tiles) {
-  __shared__ uint8_t a[kEK][kEJ][kEI];
-  __shared__ uint8_t b[kEK][kEJ][kTileI];
-  __shared__ uint8_t c[kEK][kTileJ][kTileI];
-  __shared__ long long toff[kMaxGrids + 1];
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
-  if (threadIdx.x == 0) {
-    const GridDev& G = grids[ngrids - 1];
-    toff[ngrids] = G.tile_off + (long long)G.tiles_i * G.tiles_j * G.tiles_k;
+__device__ __forceinline__ int tile_grid(const GridDev* __restrict__ grids, int ngrids, long long tile) {
+  int lo = 0, hi = ngrids - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (grids[mid].tile_off <= tile) lo = mid;
+    else hi = mid - 1;
   }
-  __syncthreads();
-  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    int A = grid_of_node(toff, ngrids, tile);
-    const GridDev& G = grids[A];
-    long long t = tile - toff[A];
-    int ti = (int)(t % G.tiles_i);
-    int tj = (int)((t / G.tiles_i) % G.tiles_j);
-    int tk = (int)(t / ((long long)G.tiles_i * G.tiles_j));
-    int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
+  return lo;
+}
+
+__device__ __forceinline__ void tile_coords(const GridDev& G, long long tile, int& ti, int& tj, int& tk) {
+  long long t = tile - G.tile_off;
+  ti = (int)(t % G.tiles_i);
+  tj = (int)((t / G.tiles_i) % G.tiles_j);
+  tk = (int)(t / ((long long)G.tiles_i * G.tiles_j));
+}
+
+__global__ void __launch_bounds__(256) k_fringe_near(const GridDev* __restrict__ grids, int ngrids,
+                                                    const uint8_t* __restrict__ tile_hole, long long total_tiles,
+                                                    int* __restrict__ near_list, int* __restrict__ near_count) {
+  for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
+       tile += (long long)gridDim.x * blockDim.x) {
+    const GridDev& G = grids[tile_grid(grids, ngrids, tile)];
+    int ti, tj, tk;
+    tile_coords(G, tile, ti, tj, tk);
+    bool near = false;
+    for (int dz = -1; dz <= 1 && !near; ++dz) {
+      int z = wrap_or_out(tk + dz, G.tiles_k, G.per & 4);
+      if (z < 0) continue;
+      for (int dy = -1; dy <= 1 && !near; ++dy) {
+        int y = wrap_or_out(tj + dy, G.tiles_j, G.per & 2);
+        if (y < 0) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          int x = wrap_or_out(ti + dx, G.tiles_i, G.per & 1);
+          if (x < 0) continue;
+          if (tile_hole[G.tile_off + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)]) {
+            near = true;
+            break;
+          }
+        }
+      }
+    }
+    if (near) {
+      int slot = atomicAdd(near_count, 1);
+      if ((long long)slot < total_tiles) near_list[slot] = (int)tile;
+    }
+  }
+}
+
+template <int NF>
+__global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict__ grids, int ngrids,
+                                                     uint8_t* __restrict__ flags, const int* __restrict__ near_list,
+                                                     const int* __restrict__ near_count, long long total_tiles) {
+  constexpr int EI = kTileI + 2 * NF, EJ = kTileJ + 2 * NF, EK = kTileK + 2 * NF;
+  __shared__ uint8_t a[EK][EJ][EI];
+  __shared__ uint8_t b[EK][EJ][kTileI];
+  __shared__ uint8_t c[EK][kTileJ][kTileI];
+  const long long nnear = min((long long)*near_count, total_tiles);
+  for (long long it = blockIdx.x; it < nnear; it += gridDim.x) {
+    const long long tile = near_list[it];
+    const GridDev& G = grids[tile_grid(grids, ngrids, tile)];
+    int ti, tj, tk;
+    tile_coords(G, tile, ti, tj, tk);
+    const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
     uint8_t* fl = flags + G.node_off;
-    const int ei = kTileI + 2 * nf, ej = kTileJ + 2 * nf, ek = kTileK + 2 * nf;
-    // stage hole causes with halo
-    for (int e = threadIdx.x; e < ei * ej * ek; e += blockDim.x) {
-      int x = e % ei, y = (e / ei) % ej, z = e / (ei * ej);
-      int i = wrap_or_out(i0 - nf + x, G.ni, G.per & 1);
-      int j = wrap_or_out(j0 - nf + y, G.nj, G.per & 2);
-      int k = wrap_or_out(k0 - nf + z, G.nk, G.per & 4);
+    for (int e = threadIdx.x; e < EI * EJ * EK; e += blockDim.x) {
+      int x = e % EI, y = (e / EI) % EJ, z = e / (EI * EJ);
+      int i = wrap_or_out(i0 - NF + x, G.ni, G.per & 1);
+      int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
+      int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
       uint8_t v = 255;
       if (i >= 0 && j >= 0 && k >= 0) {
         uint8_t f = fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)];
@@ -237,43 +339,59 @@ __global__ void __launch_bounds__(256) k_fringe(const GridDev* __restrict__ grid
       a[z][y][x] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTileI * ej * ek; e += blockDim.x) {
-      int x = e % kTileI, y = (e / kTileI) % ej, z = e / (kTileI * ej);
+    for (int e = threadIdx.x; e < kTileI * EJ * EK; e += blockDim.x) {
+      int x = e & 63, y = (e >> 6) % EJ, z = (e >> 6) / EJ;
       uint8_t m = 255;
-      for (int d = 0; d <= 2 * nf; ++d) m = min(m, a[z][y][x + d]);
+#pragma unroll
+      for (int d = 0; d <= 2 * NF; ++d) m = min(m, a[z][y][x + d]);
       b[z][y][x] = m;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTileI * kTileJ * ek; e += blockDim.x) {
-      int x = e % kTileI, y = (e / kTileI) % kTileJ, z = e / (kTileI * kTileJ);
+    for (int e = threadIdx.x; e < kTileI * kTileJ * EK; e += blockDim.x) {
+      int x = e & 63, y = (e >> 6) & 7, z = e >> 9;
       uint8_t m = 255;
-      for (int d = 0; d <= 2 * nf; ++d) m = min(m, b[z][y + d][x]);
+#pragma unroll
+      for (int d = 0; d <= 2 * NF; ++d) m = min(m, b[z][y + d][x]);
       c[z][y][x] = m;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kTileI * kTileJ * kTileK; e += blockDim.x) {
-      int x = e % kTileI, y = (e / kTileI) % kTileJ, z = e / (kTileI * kTileJ);
+      int x = e & 63, y = (e >> 6) & 7, z = e >> 9;
       int i = i0 + x, j = j0 + y, k = k0 + z;
       if (i >= G.ni || j >= G.nj || k >= G.nk) continue;
-      long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-      uint8_t f = fl[m];
-      if ((f & 3) == kHole) continue;
       uint8_t cause = 255;
-      for (int d = 0; d <= 2 * nf; ++d) cause = min(cause, c[z + d][y][x]);
-      bool onb = i < G.outer[0] || i >= G.ni - G.outer[1] || j < G.outer[2] || j >= G.nj - G.outer[3] ||
-                 k < G.outer[4] || k >= G.nk - G.outer[5];
-      if (onb) cause = min(cause, (uint8_t)OV_CAUSE_BOUNDARY);
-      fl[m] = cause == 255 ? (uint8_t)OV_STATE_FIELD : (uint8_t)(kFringe | (cause << 2));
+#pragma unroll
+      for (int d = 0; d <= 2 * NF; ++d) cause = min(cause, c[z + d][y][x]);
+      if (cause == 255) continue;
+      long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+      // buffer causes are grid ids < 63, so they win over an outer-boundary cause
+      if ((fl[m] & 3) != kHole) fl[m] = (uint8_t)(kFringe | (cause << 2));
     }
     __syncthreads();
   }
 }
 
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
-  long long grid = ctx->total_tiles;
-  if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
-  hipLaunchKernelGGL(k_fringe, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, (int)ctx->grids.size(), nf,
-                     flags, ctx->total_tiles);
+  if (nf == 0) return hipSuccess;  // outer layers were marked by the hole cut
+  const int ng = (int)ctx->grids.size();
+  long long g1 = std::max(1LL, std::min<long long>((ctx->total_tiles + 255) / 256, 65535));
+  hipLaunchKernelGGL(k_fringe_near, dim3((unsigned)g1), dim3(256), 0, s, ctx->d_grids, ng, ctx->d_tile_hole,
+                     ctx->total_tiles, ctx->d_near_list, ctx->d_near_count);
+  long long g2 = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 2));
+  switch (nf) {
+    case 1:
+      hipLaunchKernelGGL(k_fringe_tiles<1>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_fringe_tiles<2>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      break;
+    default:
+      hipLaunchKernelGGL(k_fringe_tiles<3>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -301,8 +419,12 @@ __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, lo
 }
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
-                                                                   int32_t* __restrict__ counts, long long nchunks) {
+                                                                   int32_t* __restrict__ counts, long long nchunks,
+                                                                   uint8_t* __restrict__ tile_hole, long long ntiles) {
   __shared__ int red[kCompactThreads / 64];
+  // the fringe pass has consumed the tile map: clear it for the next hole cut
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (long long)gridDim.x * blockDim.x)
+    tile_hole[t] = 0;
   for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     uint32_t mask;
     int cnt = count_fringe16(flags, ch * kCompactChunk + threadIdx.x * 16, total, mask);
@@ -320,7 +442,8 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
 
 __global__ void __launch_bounds__(1024) k_compact_scan(const int32_t* __restrict__ counts, long long n,
                                                       long long* __restrict__ offsets, long long* __restrict__ d_count,
-                                                      long long capacity, int32_t* __restrict__ status) {
+                                                      long long capacity, int32_t* __restrict__ status,
+                                                      int* __restrict__ near_count) {
   __shared__ long long part[1024];
   long long per = (n + blockDim.x - 1) / blockDim.x;
   long long b0 = threadIdx.x * per, b1 = min(n, b0 + per);
@@ -343,6 +466,7 @@ __global__ void __launch_bounds__(1024) k_compact_scan(const int32_t* __restrict
     long long total = part[threadIdx.x];
     *d_count = total;
     if (total > capacity) atomicOr(status, OV_DEV_CAPACITY);
+    *near_count = 0;  // the fringe pass of this call has consumed its tile list
   }
 }
 
@@ -394,9 +518,9 @@ hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, in
   long long grid = nch;
   if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, nch);
+                     ctx->d_chunk_counts, nch, ctx->d_tile_hole, ctx->total_tiles);
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_chunk_counts, nch, ctx->d_chunk_offsets,
-                     d_count, capacity, ctx->d_status);
+                     d_count, capacity, ctx->d_status, ctx->d_near_count);
   hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
                      (int)ctx->grids.size(), flags, total, ctx->d_chunk_offsets, nch, q_grid, q_node, capacity);
   return hipGetLastError();
