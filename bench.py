@@ -64,10 +64,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C1")
     ap.add_argument("--precision", default=None, help="fp64 or mixed (default: the config's)")
-    ap.add_argument("--graph", action="store_true", help="replay each step from a captured HIP graph")
+    ap.add_argument("--graph", action="store_true", help="single stream, each step replayed from a HIP graph")
+    ap.add_argument("--sequential", action="store_true", help="single stream, eager launches")
+    ap.add_argument("--eager", action="store_true", help="two-stream pipeline with eager launches (no graph)")
+    ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB 5 times (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 5
+        print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": n * 8, "bytes_written": n * 8,
+                          "avg_ms": round(ms, 4), "gbs_read_plus_write": round(2 * n * 8 / ms / 1e6, 1)}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this path has no multi-GPU form.",
               file=sys.stderr)
@@ -77,7 +98,8 @@ def main():
     import torch
 
     import workloads as W
-    from paper_1910_09315_amd.assembly import Assembly
+    from paper_1910_09315_amd import binding as B
+    from paper_1910_09315_amd.assembly import Assembly, Pipeline
 
     t0 = time.perf_counter()
     w = W.build(args.config)
@@ -85,74 +107,102 @@ def main():
     log(f"[bench] workload {w.name} built in {time.perf_counter() - t0:.1f}s: {w.total_nodes} nodes, "
         f"{w.ngrids} grids, {w.steps} poses, precision {precision}")
     dev = torch.device("cuda", 0)
-    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision)
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision,
+                 options={"holecut_cull": 0 if args.no_cull else 1})
     n0 = a.count_queries(w.poses[0])
-    a.allocate(2 * n0 + 4096)
+    cap = 2 * n0 + 4096
+    a.allocate(cap)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).to(dev)
-    log(f"[bench] set-up done, {n0} queries at t=0, capacity {a.capacity}")
-    if args.graph:
+    mode = "graph" if args.graph else ("sequential" if args.sequential else
+                                       ("pipelined" if args.eager else "pipelined-graph"))
+    log(f"[bench] set-up done, {n0} queries at t=0, capacity {cap}, mode {mode}")
+    pipe = None
+    if mode.startswith("pipelined"):
+        pipe = Pipeline(a, cap)
+    elif mode == "graph":
         a.capture()
-        run = lambda t: a.replay(poses[t % w.steps])
-    else:
-        run = lambda t: a.step(poses[t % w.steps])
+    if mode == "pipelined-graph":
+        pipe.capture()
+
+    counts = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
+    hc = [] if mode == "graph" else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                                     for _ in range(args.steps)]
+
+    def run(t, k=None):
+        p = poses[t % w.steps]
+        cnt = counts[t:t + 1]
+        ev = hc[k] if k is not None else None
+        if pipe is not None:
+            pipe.submit(t, p, count_out=cnt, holecut_events=ev)
+        elif mode == "graph":
+            a.replay(p)
+            cnt.copy_(a.d_count, non_blocking=True)
+        else:
+            if ev is not None:
+                ev[0].record()
+            B.overset_holecut(a.ctx, p, a.flags)
+            if ev is not None:
+                ev[1].record()
+            B.overset_fringe_compact(a.ctx, a.nf, a.flags, a.q_grid, a.q_node, cap, a.d_count)
+            a.back(p, a.buf)
+            cnt.copy_(a.d_count, non_blocking=True)
 
     for t in range(args.warmup):
         run(t)
+    if pipe is not None:
+        pipe.join()
     torch.cuda.synchronize(dev)
+    a.ctx.stats()  # zero the work counters: count the timed steps only
     log("[bench] warm-up done")
 
-    # timed region: K steps; per-step query counts accumulate on the device
-    counts = torch.zeros(args.steps, dtype=torch.int64, device=dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    hc = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    from paper_1910_09315_amd import binding as B
-    torch.cuda.synchronize(dev)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     start.record()
+    t_host0 = time.perf_counter()
+    if pipe is not None:
+        pipe.s_front.wait_stream(torch.cuda.current_stream(dev))
+        pipe.s_back.wait_stream(torch.cuda.current_stream(dev))
     for k in range(args.steps):
-        t = args.warmup + k
-        ev[k][0].record()
-        if args.graph:
-            run(t)
-        else:
-            p = poses[t % w.steps]
-            cap = a.capacity
-            hc[k][0].record()
-            B.overset_holecut(a.ctx, p, a.flags)
-            hc[k][1].record()
-            B.overset_fringe_compact(a.ctx, a.nf, a.flags, a.q_grid, a.q_node, cap, a.d_count)
-            B.overset_transform(a.ctx, p, a.q_grid, a.q_node, a.d_count, cap, a.qx)
-            B.overset_donor_search(a.ctx, p, a.flags, a.q_grid, a.q_node, a.qx, a.d_count, cap, a.donor_grid,
-                                   a.donor_cell, a.s, a.status)
-            B.overset_interp(a.ctx, a.donor_grid, a.donor_cell, a.s, a.d_count, cap, a.fields, a.out)
-        ev[k][1].record()
-        counts[k:k + 1].copy_(a.d_count, non_blocking=True)
+        run(args.warmup + k, None if mode == "graph" else k)
+    host_ms = (time.perf_counter() - t_host0) * 1e3
+    if pipe is not None:
+        pipe.join()
     stop.record()
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(stop)
     status = a.ctx.status()
-    queries = int(counts.sum().item())
-    step_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    stat = a.ctx.stats()
+    ntiles = sum(-(-g.dims[0] // 64) * -(-g.dims[1] // 8) * -(-g.dims[2] // 8) for g in w.grids)
+    queries = int(counts[args.warmup:].sum().item())
     value = queries / (total_ms / 1e3)
-    log(f"[bench] {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), {queries} queries, "
-        f"median step {np.median(step_ms):.3f} ms, p90 {np.percentile(step_ms, 90):.3f} ms, status {status}")
+    log(f"[bench] {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms, host submit {host_ms:.1f} ms), "
+        f"{queries} queries, "
+        f"{total_ms / args.steps * 1e3:.1f} us/step, status {status}")
 
     roofline = None
-    if not args.graph:
+    roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
+    if hc:
         hc_ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
         nodes = w.total_nodes
         per_node = 25 if precision == "fp64" else 13   # coordinates (3 x 8 or 3 x 4 B) + 1 flag byte
         bytes_launch = per_node * nodes
+        if not args.no_cull:
+            # culled tiles move only their flag byte: count the coordinates the
+            # kernel actually read, per launch, from the library's counters
+            coord_b = 24 if precision == "fp64" else 12
+            bytes_launch = int(nodes + coord_b * stat[0] / max(1, stat[1]) + 32 * ntiles)
+            per_node = f"1 B flag x {nodes} nodes + {coord_b} B x {stat[0] / max(1, stat[1]):.0f} nodes read " \
+                       f"+ 32 B x {ntiles} tile spheres"
         avg_s = hc_ms.mean() / 1e3
         achieved = bytes_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": "k_holecut", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "avg_us": round(hc_ms.mean() * 1e3, 2),
                     "algorithmic_bytes_per_launch": bytes_launch,
-                    "per_unit": f"{per_node} B per node x {nodes} nodes"}
+                    "per_unit": per_node if isinstance(per_node, str) else f"{per_node} B per node x {nodes} nodes",
+                    "timing": roof_note}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -161,10 +211,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.grids[0].dims[0]}x{w.grids[0].dims[1]}x{w.grids[0].dims[2]} "
                                f"curvilinear background + {w.ngrids - 1} overset shell(s), rigid motion, "
-                               f"{precision}{', hip graph' if args.graph else ''}",
+                               f"{precision}, {mode}",
                    "nodes": w.total_nodes, "queries_per_step_mean": round(queries / args.steps, 1),
-                   "median_step_ms": round(float(np.median(step_ms)), 4),
-                   "p90_step_ms": round(float(np.percentile(step_ms, 90)), 4)},
+                   "mode": mode},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -82,7 +82,9 @@ enum ov_blank_kind {
 #define OV_CAUSE_BOUNDARY 63
 #define OV_MAX_GRIDS 63
 
-/* Per-query status codes written by overset_donor_search. */
+/* Per-query status written by overset_donor_search: a code in bits 0-1, the
+ * FP64-correction flag in bit 2, and in bits 8-15 the number of cells the
+ * walk visited (saturating at 255; a diagnostic). */
 #define OV_Q_ORPHAN 0         /* no valid donor in any candidate grid */
 #define OV_Q_FOUND 1          /* found by the stencil walk */
 #define OV_Q_FALLBACK 2       /* found by the brute-force scan of the control cell */
@@ -101,8 +103,10 @@ enum ov_option {
     OV_OPT_SEARCH_BLOCK = 3,/* threads per block of the donor search (64..1024, multiple of 64) */
     OV_OPT_INTERP_BLOCK = 4,/* threads per block of the interpolation (64..1024, multiple of 64) */
     OV_OPT_HOLECUT_BLOCK = 5,/* threads per block of the hole cut (64..1024, multiple of 64) */
-    OV_OPT_HOLECUT_NPT = 6, /* nodes per thread of the hole cut (1, 2 or 4) */
-    OV_OPT_PERSIST = 7      /* workgroups per CU of persistent launches (1..32; 0 = one item per thread) */
+    OV_OPT_HOLECUT_NPT = 6, /* 16-byte coordinate vectors per lane per chunk of the hole cut (1, 2 or 4) */
+    OV_OPT_PERSIST = 7,     /* workgroups per CU of persistent launches (1..32; 0 = one item per thread) */
+    OV_OPT_HOLECUT_CULL = 8 /* 1 (default): the hole cut skips the coordinates of node tiles whose bounding
+                               sphere cannot reach any blank region (same flags); 0: stream every node */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.
@@ -141,6 +145,15 @@ int ov_finalize(ov_ctx *ctx, void *stream);
 int32_t ov_num_grids(const ov_ctx *ctx);
 int64_t ov_total_nodes(const ov_ctx *ctx);
 int ov_node_offsets(const ov_ctx *ctx, int64_t *out);
+
+/* Work counters accumulated by the step calls since the last fetch. */
+#define OV_STAT_HOLECUT_NODES_READ 0  /* nodes whose coordinates the hole cut read */
+#define OV_STAT_HOLECUT_CALLS 1       /* overset_holecut calls */
+#define OV_STAT_COUNT 8
+
+/* Copy the OV_STAT_COUNT counters into host_out [host] and zero them.
+ * Synchronises `stream`. */
+int ov_stats_fetch(ov_ctx *ctx, int64_t *host_out, void *stream);
 
 /* Set an option (ov_option); returns OV_EINVAL for an unknown key or a value
  * out of range. Takes effect at the next step call. */

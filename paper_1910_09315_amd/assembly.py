@@ -1,6 +1,16 @@
-"""Step driver: device buffers for one overset system and the five C-ABI
+"""Step drivers: device buffers for one overset system and the five C-ABI
 calls of a time step (hole cut, fringe compaction, transform, donor search,
-interpolation), optionally replayed from a captured HIP graph.
+interpolation).
+
+* `Assembly.step` runs a step on one stream (optionally replayed from a
+  captured HIP graph).
+* `Pipeline` runs consecutive steps on two streams with two buffer sets: the
+  front half of step t+1 (hole cut + fringe compaction: bandwidth-bound,
+  every CU busy) overlaps the back half of step t (transform, donor search,
+  interpolation: latency-bound, few wavefronts). The library's scratch is
+  split the same way (front-half scratch, back-half scratch), so each half
+  only has to be ordered against itself; the donor search of step t+1 still
+  follows that of step t on its stream, which keeps the warm start exact.
 
 Grids are any objects with ``dims``, ``periodic``, ``X``, ``Y``, ``Z``
 (FP64 body-frame coordinates, i fastest), ``blank_kind``, ``blank_prm`` and
@@ -12,6 +22,24 @@ import numpy as np
 import torch
 
 from . import binding as B
+
+
+class StepBuffers:
+    """Everything one step writes: flags, the query list, donors, values."""
+
+    def __init__(self, dev, total: int, capacity: int, dtype):
+        n = max(int(capacity), 1)
+        self.capacity = int(capacity)
+        self.flags = torch.empty(total, dtype=torch.uint8, device=dev)
+        self.d_count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.q_grid = torch.empty(n, dtype=torch.int32, device=dev)
+        self.q_node = torch.empty(n, dtype=torch.int32, device=dev)
+        self.qx = torch.empty(3 * n, dtype=dtype, device=dev)
+        self.donor_grid = torch.empty(n, dtype=torch.int32, device=dev)
+        self.donor_cell = torch.empty(n, dtype=torch.int32, device=dev)
+        self.s = torch.empty(3 * n, dtype=dtype, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        self.out = torch.full((4 * n,), float("nan"), dtype=dtype, device=dev)
 
 
 class Assembly:
@@ -35,12 +63,10 @@ class Assembly:
         self.ngrids = len(grids)
         self.total = self.ctx.total_nodes()
         self.node_off = np.array(self.ctx.node_offsets(), dtype=np.int64)
-        self.flags = torch.empty(self.total, dtype=torch.uint8, device=self.dev)
-        self.d_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.fields = None
         if fields is not None:
             self.set_fields(fields)
-        self.capacity = 0
+        self.buf = StepBuffers(self.dev, self.total, 0, self.dtype)
         if capacity is not None:
             self.allocate(capacity)
         self.graph = None
@@ -52,27 +78,28 @@ class Assembly:
         self.fields = torch.as_tensor(f).to(self.dev).to(self.dtype).reshape(-1).contiguous()
 
     def allocate(self, capacity: int):
-        cap = int(capacity)
-        self.capacity = cap
-        n = max(cap, 1)
-        z = dict(device=self.dev)
-        self.q_grid = torch.empty(n, dtype=torch.int32, **z)
-        self.q_node = torch.empty(n, dtype=torch.int32, **z)
-        self.qx = torch.empty(3 * n, dtype=self.dtype, **z)
-        self.donor_grid = torch.empty(n, dtype=torch.int32, **z)
-        self.donor_cell = torch.empty(n, dtype=torch.int32, **z)
-        self.s = torch.empty(3 * n, dtype=self.dtype, **z)
-        self.status = torch.empty(n, dtype=torch.int32, **z)
-        self.out = torch.full((4 * n,), float("nan"), dtype=self.dtype, **z)
+        self.buf = StepBuffers(self.dev, self.total, capacity, self.dtype)
+
+    def __getattr__(self, name):
+        # flags, q_grid, ... of the single buffer set
+        buf = self.__dict__.get("buf")
+        if buf is not None and hasattr(buf, name):
+            return getattr(buf, name)
+        raise AttributeError(name)
+
+    @property
+    def capacity(self) -> int:
+        return self.buf.capacity
 
     def count_queries(self, poses) -> int:
         """Hole cut + fringe compaction with capacity 0: returns the count."""
         p = self.as_poses(poses)
-        B.overset_holecut(self.ctx, p, self.flags)
-        B.overset_fringe_compact(self.ctx, self.nf, self.flags, None, None, 0, self.d_count)
+        b = self.buf
+        B.overset_holecut(self.ctx, p, b.flags)
+        B.overset_fringe_compact(self.ctx, self.nf, b.flags, None, None, 0, b.d_count)
         torch.cuda.synchronize(self.dev)
         self.ctx.status()  # clears the capacity bit this probe sets
-        return int(self.d_count.item())
+        return int(b.d_count.item())
 
     def as_poses(self, poses):
         if isinstance(poses, torch.Tensor) and poses.is_cuda:
@@ -80,18 +107,23 @@ class Assembly:
         return torch.as_tensor(np.ascontiguousarray(poses, dtype=np.float64).reshape(-1)).to(self.dev)
 
     # ------------------------------------------------------------ the step
-    def step(self, poses, stream=None):
-        """One time step on the current stream; nothing synchronises."""
-        p = self.as_poses(poses)
-        cap = self.capacity
-        B.overset_holecut(self.ctx, p, self.flags, stream)
-        B.overset_fringe_compact(self.ctx, self.nf, self.flags, self.q_grid, self.q_node, cap, self.d_count, stream)
-        B.overset_transform(self.ctx, p, self.q_grid, self.q_node, self.d_count, cap, self.qx, stream)
-        B.overset_donor_search(self.ctx, p, self.flags, self.q_grid, self.q_node, self.qx, self.d_count, cap,
-                               self.donor_grid, self.donor_cell, self.s, self.status, stream)
+    def front(self, p, b: StepBuffers, stream=None):
+        B.overset_holecut(self.ctx, p, b.flags, stream)
+        B.overset_fringe_compact(self.ctx, self.nf, b.flags, b.q_grid, b.q_node, b.capacity, b.d_count, stream)
+
+    def back(self, p, b: StepBuffers, stream=None):
+        cap = b.capacity
+        B.overset_transform(self.ctx, p, b.q_grid, b.q_node, b.d_count, cap, b.qx, stream)
+        B.overset_donor_search(self.ctx, p, b.flags, b.q_grid, b.q_node, b.qx, b.d_count, cap, b.donor_grid,
+                               b.donor_cell, b.s, b.status, stream)
         if self.fields is not None:
-            B.overset_interp(self.ctx, self.donor_grid, self.donor_cell, self.s, self.d_count, cap, self.fields,
-                             self.out, stream)
+            B.overset_interp(self.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count, cap, self.fields, b.out, stream)
+
+    def step(self, poses, stream=None):
+        """One time step on one stream; nothing synchronises."""
+        p = self.as_poses(poses)
+        self.front(p, self.buf, stream)
+        self.back(p, self.buf, stream)
 
     def capture(self):
         """Capture one step as a HIP graph reading its poses from a fixed slot."""
@@ -112,17 +144,119 @@ class Assembly:
         self.graph.replay()
 
     # ------------------------------------------------------------ results
-    def results(self) -> dict:
+    def results(self, b: StepBuffers | None = None) -> dict:
+        b = self.buf if b is None else b
         torch.cuda.synchronize(self.dev)
-        n = int(self.d_count.item())
-        m = min(n, self.capacity)
-        cap = max(self.capacity, 1)
-        r = {"count": n, "flags": self.flags.cpu().numpy(),
-             "q_grid": self.q_grid[:m].cpu().numpy(), "q_node": self.q_node[:m].cpu().numpy(),
-             "donor_grid": self.donor_grid[:m].cpu().numpy(), "donor_cell": self.donor_cell[:m].cpu().numpy(),
-             "status": self.status[:m].cpu().numpy(),
-             "s": self.s.reshape(3, cap)[:, :m].T.double().cpu().numpy(),
-             "qx": self.qx.reshape(3, cap)[:, :m].T.double().cpu().numpy()}
+        n = int(b.d_count.item())
+        m = min(n, b.capacity)
+        cap = max(b.capacity, 1)
+        r = {"count": n, "flags": b.flags.cpu().numpy(),
+             "q_grid": b.q_grid[:m].cpu().numpy(), "q_node": b.q_node[:m].cpu().numpy(),
+             "donor_grid": b.donor_grid[:m].cpu().numpy(), "donor_cell": b.donor_cell[:m].cpu().numpy(),
+             "status": b.status[:m].cpu().numpy(),
+             "s": b.s.reshape(3, cap)[:, :m].T.double().cpu().numpy(),
+             "qx": b.qx.reshape(3, cap)[:, :m].T.double().cpu().numpy()}
         if self.fields is not None:
-            r["values"] = self.out.reshape(4, cap)[:, :m].double().cpu().numpy()
+            r["values"] = b.out.reshape(4, cap)[:, :m].double().cpu().numpy()
         return r
+
+
+class Pipeline:
+    """Two-stream, two-buffer execution of consecutive steps of an Assembly."""
+
+    def __init__(self, asm: Assembly, capacity: int):
+        self.a = asm
+        dev = asm.dev
+        self.bufs = [StepBuffers(dev, asm.total, capacity, asm.dtype) for _ in range(2)]
+        self.s_front = torch.cuda.Stream(dev)
+        self.s_back = torch.cuda.Stream(dev)
+        self.front_done = [torch.cuda.Event() for _ in range(2)]
+        self.back_done = [torch.cuda.Event() for _ in range(2)]
+        self.started = [False, False]
+        self.graphs = None
+        cur = torch.cuda.current_stream(dev)
+        self.s_front.wait_stream(cur)
+        self.s_back.wait_stream(cur)
+
+    def submit(self, t: int, poses_dev, count_out=None, holecut_events=None):
+        """Queue step t (poses on the device). Returns its buffer set.
+        count_out: a 1-element device tensor that receives the step's query
+        count; holecut_events: a pair of timing events around the hole cut."""
+        k = t % 2
+        b = self.bufs[k]
+        p = poses_dev.reshape(-1)
+        with torch.cuda.stream(self.s_front):
+            if self.started[k]:
+                self.s_front.wait_event(self.back_done[k])  # step t-2 no longer reads these buffers
+            self._front(k, p, b, holecut_events)
+            self.front_done[k].record(self.s_front)
+        with torch.cuda.stream(self.s_back):
+            self.s_back.wait_event(self.front_done[k])
+            self._back(k, p, b)
+            if count_out is not None:
+                count_out.copy_(b.d_count, non_blocking=True)
+            self.back_done[k].record(self.s_back)
+        self.started[k] = True
+        return b
+
+    def capture(self):
+        """Capture, for each buffer set k, three single-stream HIP graphs: the
+        hole cut, the fringe pass and the back half, all reading their poses
+        from slot k. Afterwards submit() replays graphs instead of launching
+        kernels one by one (the overlap between the two streams is kept:
+        the graphs of different halves are launched on different streams)."""
+        dev = self.a.dev
+        self.slot = torch.zeros(2, self.a.ngrids * 12, dtype=torch.float64, device=dev)
+        cap = torch.cuda.Stream(dev)
+        cap.wait_stream(torch.cuda.current_stream(dev))
+        self.graphs = []
+        for k in range(2):
+            b = self.bufs[k]
+            p = self.slot[k]
+            gs = []
+            for part in ("holecut", "fringe", "back"):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=cap):
+                    if part == "holecut":
+                        B.overset_holecut(self.a.ctx, p, b.flags, cap)
+                    elif part == "fringe":
+                        B.overset_fringe_compact(self.a.ctx, self.a.nf, b.flags, b.q_grid, b.q_node, b.capacity,
+                                                 b.d_count, cap)
+                    else:
+                        self.a.back(p, b, cap)
+                gs.append(g)
+            self.graphs.append(gs)
+        torch.cuda.synchronize(dev)
+
+    def _front(self, k, p, b, holecut_events):
+        if self.graphs is not None:
+            self.slot[k].copy_(p, non_blocking=True)
+        if holecut_events is not None:
+            holecut_events[0].record(self.s_front)
+        if self.graphs is not None:
+            self.graphs[k][0].replay()
+        else:
+            B.overset_holecut(self.a.ctx, p, b.flags, self.s_front)
+        if holecut_events is not None:
+            holecut_events[1].record(self.s_front)
+        if self.graphs is not None:
+            self.graphs[k][1].replay()
+        else:
+            B.overset_fringe_compact(self.a.ctx, self.a.nf, b.flags, b.q_grid, b.q_node, b.capacity, b.d_count,
+                                     self.s_front)
+
+    def _back(self, k, p, b):
+        if self.graphs is not None:
+            self.graphs[k][2].replay()
+        else:
+            self.a.back(p, b, self.s_back)
+
+    def join(self, stream=None):
+        """Make `stream` (default: current) wait for everything submitted."""
+        s = torch.cuda.current_stream(self.a.dev) if stream is None else stream
+        s.wait_stream(self.s_front)
+        s.wait_stream(self.s_back)
+
+    def results(self, t: int) -> dict:
+        self.join()
+        return self.a.results(self.bufs[t % 2])

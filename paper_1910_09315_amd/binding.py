@@ -22,10 +22,11 @@ OV_CAUSE_BOUNDARY = 63
 OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE, OV_DEV_FIX_OVERFLOW = 1, 2, 4, 8
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
-       "holecut_npt": 6, "persist": 7}
+       "holecut_npt": 6, "persist": 7, "holecut_cull": 8}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
+           "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
            "overset_interp"]
 
@@ -59,6 +60,7 @@ def load(path: str = LIB_PATH):
         "ov_set_option": (ctypes.c_int, [_P, _I32, _I64]),
         "ov_reset_history": (ctypes.c_int, [_P, _P]),
         "ov_status_fetch": (ctypes.c_int, [_P, _P, _P]),
+        "ov_stats_fetch": (ctypes.c_int, [_P, _P, _P]),
         "overset_holecut": (ctypes.c_int, [_P, _P, _P, _P]),
         "overset_fringe_compact": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _P, _P]),
         "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
@@ -137,6 +139,12 @@ class Context:
         v = ctypes.c_int32()
         self.check(self.lib.ov_status_fetch(self.h, ctypes.byref(v), _stream(stream)), "ov_status_fetch")
         return v.value
+
+    def stats(self, stream=None) -> list:
+        """Work counters since the last fetch (OV_STAT_*), then zeroed."""
+        arr = (ctypes.c_int64 * 8)()
+        self.check(self.lib.ov_stats_fetch(self.h, arr, _stream(stream)), "ov_stats_fetch")
+        return list(arr)
 
     def num_grids(self) -> int:
         return int(self.lib.ov_num_grids(self.h))

@@ -95,12 +95,87 @@ __global__ void k_bins(GridDev g, unsigned long long* __restrict__ cnt, int* __r
           long long b = x + (long long)g.nb[0] * (y + (long long)g.nb[1] * z);
           if (PASS == 0) {
             atomicAdd(&cnt[b], 1ULL);
-            atomicMin(&rep[b], (int)c);
           } else {
             unsigned long long p = atomicAdd(&cnt[b], 1ULL);
             cells[start[b] + (long long)p] = (int)c;
           }
         }
+  }
+}
+
+// Walk seed of each control cell: the listed donor cell whose corner mean is
+// nearest the control cell's centre (ties: lowest index); -1 if none.
+__global__ void k_bin_rep(GridDev g, const long long* __restrict__ start, const int* __restrict__ cells,
+                          int* __restrict__ rep, long long nbins) {
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nbins; b += (long long)gridDim.x * blockDim.x) {
+    long long bx = b % g.nb[0], by = (b / g.nb[0]) % g.nb[1], bz = b / ((long long)g.nb[0] * g.nb[1]);
+    double ctr[3] = {g.blo[0] + (bx + 0.5) / g.binv[0], g.blo[1] + (by + 0.5) / g.binv[1],
+                     g.blo[2] + (bz + 0.5) / g.binv[2]};
+    int best = -1;
+    double bestd = INFINITY;
+    for (long long e = start[b]; e < start[b + 1]; ++e) {
+      int cell = cells[e];
+      int ci, cj, ck;
+      cell_ijk(g, cell, ci, cj, ck);
+      double m[3] = {0.0, 0.0, 0.0};
+      for (int c = 0; c < 8; ++c) {
+        long long nd = corner_node(g, ci, cj, ck, c);
+        m[0] += g.X[nd];
+        m[1] += g.Y[nd];
+        m[2] += g.Z[nd];
+      }
+      double d0 = m[0] * 0.125 - ctr[0], d1 = m[1] * 0.125 - ctr[1], d2 = m[2] * 0.125 - ctr[2];
+      double d = d0 * d0 + d1 * d1 + d2 * d2;
+      if (d < bestd || (d == bestd && cell < best)) {
+        bestd = d;
+        best = cell;
+      }
+    }
+    rep[b] = best;
+  }
+}
+
+// Bounding sphere (body frame) of each node tile of kTileI x kTileJ x kTileK:
+// centre of the tile's coordinate box, radius = half its diagonal.
+__global__ void __launch_bounds__(256) k_tile_spheres(GridDev g, double4* __restrict__ out) {
+  __shared__ double red[6][256];
+  const long long ntiles = (long long)g.tiles_i * g.tiles_j * g.tiles_k;
+  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int ti = (int)(t % g.tiles_i), tj = (int)((t / g.tiles_i) % g.tiles_j), tk = (int)(t / ((long long)g.tiles_i * g.tiles_j));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int e = threadIdx.x; e < kTileI * kTileJ * kTileK; e += blockDim.x) {
+      int i = ti * kTileI + (e % kTileI), j = tj * kTileJ + (e / kTileI) % kTileJ, k = tk * kTileK + e / (kTileI * kTileJ);
+      if (i >= g.ni || j >= g.nj || k >= g.nk) continue;
+      long long m = (long long)i + (long long)g.ni * ((long long)j + (long long)g.nj * k);
+      double v[3] = {g.X[m], g.Y[m], g.Z[m]};
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(lo[d], v[d]);
+        hi[d] = fmax(hi[d], v[d]);
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      red[d][threadIdx.x] = lo[d];
+      red[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w)
+        for (int d = 0; d < 3; ++d) {
+          red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+          red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + w]);
+        }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double c[3], r2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        c[d] = 0.5 * (red[d][0] + red[3 + d][0]);
+        double h = 0.5 * (red[3 + d][0] - red[d][0]);
+        r2 += h * h;
+      }
+      out[t] = make_double4(c[0], c[1], c[2], sqrt(r2));
+    }
+    __syncthreads();
   }
 }
 
@@ -174,7 +249,6 @@ int build_control_cells(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   HIPCHK(hipMalloc(&d_cnt, sizeof(unsigned long long) * (nbins + 1)), "hipMalloc bin counts");
   HIPCHK(hipMalloc(&gh.brep, sizeof(int) * nbins), "hipMalloc bin rep");
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nbins + 1)), dim3(256), 0, s, d_cnt, nbins + 1);
-  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(nbins)), dim3(256), 0, s, gh.brep, nbins, 0x7fffffff);
   hipLaunchKernelGGL(k_bins<0>, dim3(blocks_for(g.ncells)), dim3(256), 0, s, g, d_cnt, gh.brep,
                      (const long long*)nullptr, (int*)nullptr);
   std::vector<unsigned long long> cnt(nbins);
@@ -197,14 +271,11 @@ int build_control_cells(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   hipLaunchKernelGGL(k_bins<1>, dim3(blocks_for(g.ncells)), dim3(256), 0, s, g, d_cnt, (int*)nullptr,
                      (const long long*)gh.bstart, gh.bcells);
   HIPCHK(hipGetLastError(), "control-cell kernels");
+  hipLaunchKernelGGL(k_bin_rep, dim3(blocks_for(nbins)), dim3(256), 0, s, g, (const long long*)gh.bstart,
+                     (const int*)gh.bcells, gh.brep, nbins);
+  HIPCHK(hipGetLastError(), "control-cell seeds");
   HIPCHK(hipStreamSynchronize(s), "control-cell sync");
   (void)hipFree(d_cnt);
-  // bins that no cell reaches keep rep = INT_MAX: mark them -1
-  std::vector<int> rep(nbins);
-  HIPCHK(hipMemcpy(rep.data(), gh.brep, sizeof(int) * nbins, hipMemcpyDeviceToHost), "bin rep copy");
-  for (auto& r : rep)
-    if (r == 0x7fffffff) r = -1;
-  HIPCHK(hipMemcpy(gh.brep, rep.data(), sizeof(int) * nbins, hipMemcpyHostToDevice), "bin rep copy back");
   g.bstart = gh.bstart;
   g.bcells = gh.bcells;
   g.brep = gh.brep;
@@ -247,7 +318,9 @@ int ov_ctx_create(ov_ctx** out, int device, int precision) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cus = prop.multiProcessorCount;
   if (hipMalloc(&ctx->d_status, sizeof(int32_t)) != hipSuccess ||
-      hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess) {
+      hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&ctx->d_stats, sizeof(unsigned long long) * OV_STAT_COUNT) != hipSuccess ||
+      hipMemset(ctx->d_stats, 0, sizeof(unsigned long long) * OV_STAT_COUNT) != hipSuccess) {
     delete ctx;
     return OV_EHIP;
   }
@@ -269,13 +342,16 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   }
   (void)hipFree(ctx->d_grids);
   (void)hipFree(ctx->d_status);
+  (void)hipFree(ctx->d_stats);
   (void)hipFree(ctx->d_warm_cell);
   (void)hipFree(ctx->d_warm_grid);
+  (void)hipFree(ctx->d_tile_sphere);
   (void)hipFree(ctx->d_tile_hole);
   (void)hipFree(ctx->d_near_list);
   (void)hipFree(ctx->d_near_count);
   (void)hipFree(ctx->d_scanq);
   (void)hipFree(ctx->d_scanq_count);
+  (void)hipFree(ctx->d_scanq_ticket);
   (void)hipFree(ctx->d_chunk_counts);
   (void)hipFree(ctx->d_chunk_offsets);
   delete ctx;
@@ -375,6 +451,12 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
   HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
+  HIPCHK(hipMalloc(&ctx->d_tile_sphere, sizeof(double4) * std::max(1LL, ctx->total_tiles)), "hipMalloc tile spheres");
+  for (auto& g : ctx->grids) {
+    long long nt = (long long)g.d.tiles_i * g.d.tiles_j * g.d.tiles_k;
+    hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)std::min(nt, 65536LL)), dim3(256), 0, s, g.d,
+                       ctx->d_tile_sphere + g.d.tile_off);
+  }
   HIPCHK(hipMalloc(&ctx->d_tile_hole, std::max(1LL, ctx->total_tiles)), "hipMalloc tile map");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(ctx->total_tiles)), dim3(256), 0, s, ctx->d_tile_hole,
                      ctx->total_tiles, (uint8_t)0);
@@ -384,6 +466,9 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   ctx->scanq_cap = 65536;
   HIPCHK(hipMalloc(&ctx->d_scanq, sizeof(int2) * ctx->scanq_cap), "hipMalloc scan queue");
   HIPCHK(hipMalloc(&ctx->d_scanq_count, sizeof(int)), "hipMalloc scan queue count");
+  HIPCHK(hipMalloc(&ctx->d_scanq_ticket, sizeof(unsigned int)), "hipMalloc scan ticket");
+  HIPCHK(hipMemsetAsync(ctx->d_scanq_count, 0, sizeof(int), s), "scan queue init");
+  HIPCHK(hipMemsetAsync(ctx->d_scanq_ticket, 0, sizeof(unsigned int), s), "scan ticket init");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
   HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk counts");
   HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * ctx->nchunks), "hipMalloc chunk offsets");
@@ -430,6 +515,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       if (v != 1 && v != 2 && v != 4) break;
       ctx->holecut_npt = (int)v;
       return OV_OK;
+    case OV_OPT_HOLECUT_CULL:
+      if (v != 0 && v != 1) break;
+      ctx->cull = (int)v;
+      return OV_OK;
     case OV_OPT_PERSIST:
       if (v < 0 || v > 32) break;
       ctx->persist = (int)v;
@@ -460,6 +549,19 @@ int ov_status_fetch(ov_ctx* ctx, int32_t* host_status, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "status fetch");
   *host_status = v;
+  return OV_OK;
+}
+
+int ov_stats_fetch(ov_ctx* ctx, int64_t* host_out, void* stream) {
+  if (!ctx || !host_out) return OV_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long v[OV_STAT_COUNT];
+  hipError_t e = hipMemcpyAsync(v, ctx->d_stats, sizeof v, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_stats, 0, sizeof v, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stats fetch");
+  for (int i = 0; i < OV_STAT_COUNT; ++i) host_out[i] = (int64_t)v[i];
   return OV_OK;
 }
 

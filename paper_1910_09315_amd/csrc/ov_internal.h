@@ -81,13 +81,16 @@ struct ov_ctx {
   long long total_tiles = 0;
   ov::GridDev* d_grids = nullptr;
   int32_t* d_status = nullptr;
+  unsigned long long* d_stats = nullptr;  // OV_STAT_* counters (accumulate until ov_stats_fetch)
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
+  double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
   uint8_t* d_tile_hole = nullptr;  // per fringe tile: holds a hole (set by the hole cut, cleared by compaction)
   int* d_near_list = nullptr;      // tiles near a hole (fringe pass)
   int* d_near_count = nullptr;
   int2* d_scanq = nullptr;         // queries whose walk fell back to the brute-force scan
-  int* d_scanq_count = nullptr;
+  int* d_scanq_count = nullptr;    // emptied by the last block of the scan phase
+  unsigned int* d_scanq_ticket = nullptr;
   int scanq_cap = 0;
   int32_t* d_chunk_counts = nullptr;
   long long* d_chunk_offsets = nullptr;
@@ -97,9 +100,10 @@ struct ov_ctx {
   int max_walk = 64;
   int search_block = 64;
   int interp_block = 256;
-  int holecut_block = 256;
-  int holecut_npt = 4;
+  int holecut_block = 512;
+  int holecut_npt = 2;  // 16-byte coordinate vectors per lane per chunk
   int persist = 0;
+  int cull = 1;  // hole cut: skip coordinate reads of tiles no blank region can reach
   std::string err;
 };
 

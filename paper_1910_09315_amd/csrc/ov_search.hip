@@ -185,11 +185,12 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
 // On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
 template <typename T>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3], int max_walk,
-                    bool& limit) {
+                    bool& limit, int& visited) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   int pi = -1, pj = -1, pk = -1;
   for (int stepn = 0; stepn < max_walk; ++stepn) {
+    ++visited;
     CellMap<T> m;
     load_cell<T>(G, ci, cj, ck, xi, m);
     T cond = 0;
@@ -389,11 +390,11 @@ __device__ __forceinline__ long long bin_of(const GridDev& G, const double xi[3]
 // any cell FP32 cannot decide). Returns kFound with cell/s, else kToScan.
 template <typename T>
 __device__ __forceinline__ int walk_grid(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3],
-                                         int max_walk, bool& limit, int& how) {
-  int r = walk<T>(G, fl, xi, cell, s, max_walk, limit);
+                                         int max_walk, bool& limit, int& how, int& visited) {
+  int r = walk<T>(G, fl, xi, cell, s, max_walk, limit, visited);
   if (sizeof(T) == 4 && r == kDoubt) {
     double s64[3];
-    r = walk<double>(G, fl, xi, cell, s64, max_walk, limit);
+    r = walk<double>(G, fl, xi, cell, s64, max_walk, limit, visited);
     s[0] = (T)s64[0];
     s[1] = (T)s64[1];
     s[2] = (T)s64[2];
@@ -408,7 +409,7 @@ __device__ __forceinline__ void write_result(long long q, long long cap, long lo
                                              int32_t* status, int32_t* warm_cell, uint8_t* warm_grid) {
   donor_grid[q] = grid;
   donor_cell[q] = cell;
-  status[q] = st;
+  status[q] = st;  // bits 8-15: cells the walk visited (diagnostic)
   s_out[q] = s[0];
   s_out[cap + q] = s[1];
   s_out[2 * cap + q] = s[2];
@@ -437,6 +438,7 @@ __global__ void __launch_bounds__(1024)
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
     bool limit = false, deferred = false;
+    int visited = 0;
     if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
@@ -459,7 +461,7 @@ __global__ void __launch_bounds__(1024)
         const uint8_t* fl = flags + G.node_off;
         int cell = seed, how = OV_Q_FOUND;
         T s[3];
-        if (walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how) != kFound) {
+        if (walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how, visited) != kFound) {
           int slot = atomicAdd(scanq_count, 1);
           if (slot < scanq_cap) {
             scanq[slot] = make_int2((int)q, t);
@@ -486,8 +488,8 @@ __global__ void __launch_bounds__(1024)
     }
     if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
     if (!deferred)
-      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status, rs, donor_grid, donor_cell, s_out, status,
-                      warm_cell, warm_grid);
+      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
+                      donor_cell, s_out, status, warm_cell, warm_grid);
   }
 }
 
@@ -545,7 +547,7 @@ __global__ void __launch_bounds__(256)
                  int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
                  int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
                  int max_walk, int32_t* __restrict__ dev_status, const int2* __restrict__ scanq,
-                 const int* __restrict__ scanq_count, int scanq_cap) {
+                 int* __restrict__ scanq_count, int scanq_cap, unsigned int* __restrict__ ticket) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
   __syncthreads();
@@ -559,6 +561,7 @@ __global__ void __launch_bounds__(256)
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
     bool limit = false;
+    int visited = 0;
     for (int t = item.y; t < ngrids; ++t) {
       const int B = candidate_at(t, Q.A, Q.first);
       if (B < 0) continue;
@@ -574,7 +577,7 @@ __global__ void __launch_bounds__(256)
         if (seed < 0) continue;
         cell = seed;
         how = OV_Q_FOUND;
-        walked = walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how) == kFound;
+        walked = walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how, visited) == kFound;
       }
       if (!walked) {
         double s64[3];
@@ -596,13 +599,20 @@ __global__ void __launch_bounds__(256)
     }
     if (lane == 0) {
       if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status, rs, donor_grid, donor_cell, s_out, status,
-                      warm_cell, warm_grid);
+      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
+                      donor_cell, s_out, status, warm_cell, warm_grid);
+    }
+  }
+  // the last block to finish empties the queue for the next call
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(ticket, 1u) == gridDim.x - 1) {
+      *scanq_count = 0;
+      *ticket = 0u;
     }
   }
 }
-
-__global__ void k_zero_int(int* p) { *p = 0; }
 
 template <typename T>
 static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
@@ -611,7 +621,6 @@ static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* fla
   int block = ctx->search_block;
   long long grid = grid_size_for(ctx, capacity, block);
   int ng = (int)ctx->grids.size();
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, ctx->d_scanq_count);
   hipLaunchKernelGGL(k_donor_search<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
                      q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell,
                      ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, ctx->d_scanq, ctx->d_scanq_count,
@@ -619,8 +628,8 @@ static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* fla
   long long g2 = std::max(1LL, std::min<long long>((long long)ctx->num_cus * 2, (capacity + 3) / 4));
   hipLaunchKernelGGL(k_donor_scan<T>, dim3((unsigned)g2), dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid,
                      q_node, qx, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell, ctx->d_warm_grid,
-                     ctx->max_walk, ctx->d_status, (const int2*)ctx->d_scanq, (const int*)ctx->d_scanq_count,
-                     ctx->scanq_cap);
+                     ctx->max_walk, ctx->d_status, (const int2*)ctx->d_scanq, ctx->d_scanq_count, ctx->scanq_cap,
+                     ctx->d_scanq_ticket);
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

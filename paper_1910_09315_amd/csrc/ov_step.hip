@@ -18,8 +18,11 @@ namespace ov {
 // coordinate pointers, and the list of grids that carry a blank region.
 struct HoleLds {
   double pose[kMaxGrids][12];
+  float posef[kMaxGrids][12];
+  float prmf[kMaxGrids][6];  // FP32 shape constants: see holecut_stage
   double prm[kMaxGrids][3];
   double cull[kMaxGrids];
+  float cullf[kMaxGrids];  // FP32 cull radius^2, widened for FP32 rounding
   long long off[kMaxGrids + 1];
   const void* X[kMaxGrids];
   const void* Y[kMaxGrids];
@@ -33,16 +36,32 @@ struct HoleLds {
 template <typename CT>
 __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restrict__ grids, int ngrids,
                                               const double* __restrict__ poses) {
-  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) L.pose[i / 12][i % 12] = poses[i];
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) {
+    L.pose[i / 12][i % 12] = poses[i];
+    L.posef[i / 12][i % 12] = (float)poses[i];
+  }
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
     const GridDev& G = grids[g];
     L.off[g] = G.node_off;
     L.kind[g] = G.blank_kind;
     L.outer[g] = G.has_outer;
     L.cull[g] = G.cull_r2;
+    L.cullf[g] = (float)G.cull_r2 * 1.0001f + 1e-30f;
     L.prm[g][0] = G.blank_prm[0];
     L.prm[g][1] = G.blank_prm[1];
     L.prm[g][2] = G.blank_prm[2];
+    // sphere / cylinder: 1/r^2, -, -, 1/r, z0, z1 ; ellipsoid: 1/a, 1/b, 1/c
+    const double* q = G.blank_prm;
+    if (G.blank_kind == OV_BLANK_ELLIPSOID) {
+      L.prmf[g][0] = (float)(1.0 / q[0]);
+      L.prmf[g][1] = (float)(1.0 / q[1]);
+      L.prmf[g][2] = (float)(1.0 / q[2]);
+    } else if (G.blank_kind != OV_BLANK_NONE) {
+      L.prmf[g][0] = (float)(1.0 / (q[0] * q[0]));
+      L.prmf[g][3] = (float)(1.0 / q[0]);
+      L.prmf[g][4] = (float)q[1];
+      L.prmf[g][5] = (float)q[2];
+    }
     if (sizeof(CT) == 4) {
       L.X[g] = G.Xf;
       L.Y[g] = G.Yf;
@@ -64,23 +83,18 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
   __syncthreads();
 }
 
-// Signed, scale-free inside measure of a body-frame point: < 0 strictly inside.
-// For the cylinder the radial and axial conditions are combined as a max.
-template <typename T>
-__device__ __forceinline__ T blank_measure(int kind, const double* prm, T x, T y, T z) {
-  if (kind == OV_BLANK_SPHERE) {
-    T r = (T)prm[0];
-    return (x * x + y * y + z * z) / (r * r) - (T)1;
-  }
+// Signed, scale-free inside measure of a body-frame point in FP32: < 0
+// strictly inside. For the cylinder the radial and axial conditions are
+// combined as a max. c: the FP32 shape constants of holecut_stage.
+__device__ __forceinline__ float blank_measure_f32(int kind, const float* c, float x, float y, float z) {
+  if (kind == OV_BLANK_SPHERE) return (x * x + y * y + z * z) * c[0] - 1.f;
   if (kind == OV_BLANK_ELLIPSOID) {
-    T u = x / (T)prm[0], v = y / (T)prm[1], w = z / (T)prm[2];
-    return u * u + v * v + w * w - (T)1;
+    float u = x * c[0], v = y * c[1], w = z * c[2];
+    return u * u + v * v + w * w - 1.f;
   }
-  // cylinder: inside iff rho^2 < r^2 and z0 <= z <= z1
-  T r = (T)prm[0];
-  T fr = (x * x + y * y) / (r * r) - (T)1;
-  T fz = fmax(((T)prm[1] - z) / r, (z - (T)prm[2]) / r);
-  return fmax(fr, fz);
+  float fr = (x * x + y * y) * c[0] - 1.f;
+  float fz = fmaxf((c[4] - z) * c[3], (z - c[5]) * c[3]);
+  return fmaxf(fr, fz);
 }
 
 __device__ __forceinline__ bool blank_inside_fp64(int kind, const double* prm, double x, double y, double z) {
@@ -127,21 +141,23 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     w[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
     return holecut_fp64(L, A, w);
   }
-  float w0 = (float)pa[0] * (float)X + (float)pa[1] * (float)Y + (float)pa[2] * (float)Z + (float)pa[9];
-  float w1 = (float)pa[3] * (float)X + (float)pa[4] * (float)Y + (float)pa[5] * (float)Z + (float)pa[10];
-  float w2 = (float)pa[6] * (float)X + (float)pa[7] * (float)Y + (float)pa[8] * (float)Z + (float)pa[11];
+  const float* pf = L.posef[A];
+  const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
+  float w0 = pf[0] * Xf + pf[1] * Yf + pf[2] * Zf + pf[9];
+  float w1 = pf[3] * Xf + pf[4] * Yf + pf[5] * Zf + pf[10];
+  float w2 = pf[6] * Xf + pf[7] * Yf + pf[8] * Zf + pf[11];
   bool unsure = false;
   int cause = -1;
   for (int b = 0; b < L.nblank; ++b) {
     int B = L.blank[b];
     if (B == A) continue;
-    const double* p = L.pose[B];
-    float d0 = w0 - (float)p[9], d1 = w1 - (float)p[10], d2 = w2 - (float)p[11];
-    if (d0 * d0 + d1 * d1 + d2 * d2 >= (float)L.cull[B] * 1.0001f + 1e-30f) continue;
-    float x = (float)p[0] * d0 + (float)p[3] * d1 + (float)p[6] * d2;
-    float y = (float)p[1] * d0 + (float)p[4] * d1 + (float)p[7] * d2;
-    float z = (float)p[2] * d0 + (float)p[5] * d1 + (float)p[8] * d2;
-    float f = blank_measure<float>(L.kind[B], L.prm[B], x, y, z);
+    const float* p = L.posef[B];
+    float d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
+    if (d0 * d0 + d1 * d1 + d2 * d2 >= L.cullf[B]) continue;
+    float x = p[0] * d0 + p[3] * d1 + p[6] * d2;
+    float y = p[1] * d0 + p[4] * d1 + p[7] * d2;
+    float z = p[2] * d0 + p[5] * d1 + p[8] * d2;
+    float f = blank_measure_f32(L.kind[B], L.prmf[B], x, y, z);
     if (fabsf(f) < kHoleGuard) {
       unsure = true;
       break;
@@ -166,8 +182,22 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
 // Flag byte of a node given its hole cause (-1: none). Holes mark their
 // fringe tile in the tile map; nodes of grids with outer layers compute their
 // (i, j, k) to mark the outer-boundary query layers (a fixed set per grid).
-__device__ __forceinline__ uint8_t node_flag(const GridDev& G, long long m, int cause, uint8_t* tile_hole) {
-  if (cause < 0 && !G.has_outer) return (uint8_t)OV_STATE_FIELD;
+// Grid geometry kept in registers by loops that store flag bytes (a byte
+// store may alias anything, so fields read through a GridDev reference would
+// be re-loaded after every store).
+struct GeomR {
+  int ni, nj, nk, tiles_i, tiles_j;
+  int o0, o1, o2, o3, o4, o5;
+  long long tile_off;
+  __device__ __forceinline__ explicit GeomR(const GridDev& G)
+      : ni(G.ni), nj(G.nj), nk(G.nk), tiles_i(G.tiles_i), tiles_j(G.tiles_j), o0(G.outer[0]), o1(G.outer[1]),
+        o2(G.outer[2]), o3(G.outer[3]), o4(G.outer[4]), o5(G.outer[5]), tile_off(G.tile_off) {}
+  __device__ __forceinline__ bool on_outer(int i, int j, int k) const {
+    return i < o0 || i >= ni - o1 || j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5;
+  }
+};
+
+__device__ __forceinline__ uint8_t node_flag(const GeomR& G, long long m, int cause, uint8_t* tile_hole) {
   long long plane = (long long)G.ni * G.nj;
   int k = (int)(m / plane);
   long long r = m - (long long)k * plane;
@@ -177,66 +207,225 @@ __device__ __forceinline__ uint8_t node_flag(const GridDev& G, long long m, int 
     tile_hole[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] = 1;
     return (uint8_t)(kHole | (cause << 2));
   }
-  bool onb = i < G.outer[0] || i >= G.ni - G.outer[1] || j < G.outer[2] || j >= G.nj - G.outer[3] ||
-             k < G.outer[4] || k >= G.nk - G.outer[5];
-  return onb ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint8_t)OV_STATE_FIELD;
+  return G.on_outer(i, j, k) ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint8_t)OV_STATE_FIELD;
 }
 
-template <typename CT, int NPT>
+// Work is split into chunks of blockDim * W * R consecutive nodes that never
+// straddle two grids, so the grid of a chunk is uniform across the block.
+// Each lane loads R vectors of W consecutive nodes (16 bytes) per coordinate
+// array before testing any node, keeping 3 R 16-byte loads in flight.
+template <typename CT>
+struct Vec16;
+typedef double ov_d2 __attribute__((ext_vector_type(2)));
+typedef float ov_f4 __attribute__((ext_vector_type(4)));
+template <>
+struct Vec16<double> {
+  typedef ov_d2 type;
+  static constexpr int W = 2;
+};
+template <>
+struct Vec16<float> {
+  typedef ov_f4 type;
+  static constexpr int W = 4;
+};
+
+template <typename CT, int R>
 __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ grids, int ngrids,
                                                  const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                 long long total, uint8_t* __restrict__ tile_hole) {
+                                                 long long total_chunks, uint8_t* __restrict__ tile_hole,
+                                                 unsigned long long* __restrict__ stats) {
+  typedef typename Vec16<CT>::type V;
+  constexpr int W = Vec16<CT>::W;
   __shared__ HoleLds L;
+  __shared__ long long coff[kMaxGrids + 1];  // first chunk of each grid
   holecut_stage<CT>(L, grids, ngrids, poses);
-  const long long span = (long long)blockDim.x * NPT;
-  for (long long base = (long long)blockIdx.x * span; base < total; base += (long long)gridDim.x * span) {
-    CT X[NPT], Y[NPT], Z[NPT];
-    int A[NPT];
-    long long m[NPT];
+  const long long span = (long long)blockDim.x * W * R;
+  if (threadIdx.x == 0) {
+    long long c = 0;
+    for (int g = 0; g < ngrids; ++g) {
+      coff[g] = c;
+      c += (L.off[g + 1] - L.off[g] + span - 1) / span;
+    }
+    coff[ngrids] = c;
+    if (blockIdx.x == 0) {
+      atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)L.off[ngrids]);
+      atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+    }
+  }
+  __syncthreads();
+  for (long long ch = blockIdx.x; ch < total_chunks; ch += gridDim.x) {
+    const int A = grid_of_node(coff, ngrids, ch);
+    const long long nn = L.off[A + 1] - L.off[A];
+    const long long m0 = (ch - coff[A]) * span + (long long)threadIdx.x * W;
+    const CT* Xa = (const CT*)L.X[A];
+    const CT* Ya = (const CT*)L.Y[A];
+    const CT* Za = (const CT*)L.Z[A];
+    uint8_t* fa = flags + L.off[A];
+    const GeomR GR(grids[A]);
+    const bool outerA = L.outer[A] != 0;
+    CT X[R][W], Y[R][W], Z[R][W];
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-      long long n = base + (long long)r * blockDim.x + threadIdx.x;
-      A[r] = 0;
-      m[r] = -1;
-      if (n < total) {
-        A[r] = grid_of_node(L.off, ngrids, n);
-        m[r] = n - L.off[A[r]];
-        X[r] = __builtin_nontemporal_load((const CT*)L.X[A[r]] + m[r]);
-        Y[r] = __builtin_nontemporal_load((const CT*)L.Y[A[r]] + m[r]);
-        Z[r] = __builtin_nontemporal_load((const CT*)L.Z[A[r]] + m[r]);
+    for (int r = 0; r < R; ++r) {
+      const long long m = m0 + (long long)r * blockDim.x * W;
+      if (m + W <= nn) {
+        V x = __builtin_nontemporal_load(reinterpret_cast<const V*>(Xa + m));
+        V y = __builtin_nontemporal_load(reinterpret_cast<const V*>(Ya + m));
+        V z = __builtin_nontemporal_load(reinterpret_cast<const V*>(Za + m));
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          X[r][w] = x[w];
+          Y[r][w] = y[w];
+          Z[r][w] = z[w];
+        }
+      } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if (m + w < nn) {
+            X[r][w] = Xa[m + w];
+            Y[r][w] = Ya[m + w];
+            Z[r][w] = Za[m + w];
+          }
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-      if (m[r] < 0) continue;
-      int cause = holecut_node<CT>(L, grids, A[r], m[r], X[r], Y[r], Z[r]);
-      flags[base + (long long)r * blockDim.x + threadIdx.x] =
-          (cause < 0 && !L.outer[A[r]]) ? (uint8_t)OV_STATE_FIELD : node_flag(grids[A[r]], m[r], cause, tile_hole);
+    for (int r = 0; r < R; ++r) {
+      const long long m = m0 + (long long)r * blockDim.x * W;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        if (m + w >= nn) continue;
+        int cause = holecut_node<CT>(L, grids, A, m + w, X[r][w], Y[r][w], Z[r][w]);
+        fa[m + w] = (cause < 0 && !outerA) ? (uint8_t)OV_STATE_FIELD : node_flag(GR, m + w, cause, tile_hole);
+      }
     }
+  }
+}
+
+// Hole cut over node tiles (kTileI x kTileJ x kTileK, one block per tile)
+// with culling: a tile whose bounding sphere, placed at its grid's pose,
+// cannot reach the bounding sphere of any other grid's blank region holds no
+// hole, so its coordinates are not read; its flags are still written (field,
+// or fringe on outer-boundary layers). Tiles that may be cut test every node
+// exactly as the streaming kernel does. The kernel also records, for every
+// tile, whether it holds a hole (the fringe pass reads that map).
+template <typename CT>
+__global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict__ grids, int ngrids,
+                                                      const double* __restrict__ poses, uint8_t* __restrict__ flags,
+                                                      const double4* __restrict__ spheres, long long total_tiles,
+                                                      uint8_t* __restrict__ tile_hole,
+                                                      unsigned long long* __restrict__ stats) {
+  __shared__ HoleLds L;
+  __shared__ long long toff[kMaxGrids + 1];
+  holecut_stage<CT>(L, grids, ngrids, poses);
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
+  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
+  __syncthreads();
+  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    const int A = grid_of_node(toff, ngrids, tile);
+    const GeomR G(grids[A]);
+    const int t = (int)(tile - toff[A]);
+    const int i0 = (t % G.tiles_i) * kTileI;
+    const int j0 = ((t / G.tiles_i) % G.tiles_j) * kTileJ;
+    const int k0 = (t / (G.tiles_i * G.tiles_j)) * kTileK;
+    // may any blank region reach this tile? (the same answer in every thread)
+    const double4 sp = spheres[tile];
+    const double* pa = L.pose[A];
+    const double wc0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
+    const double wc1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
+    const double wc2 = pa[6] * sp.x + pa[7] * sp.y + pa[8] * sp.z + pa[11];
+    bool cand = false;
+    for (int b = 0; b < L.nblank; ++b) {
+      const int B = L.blank[b];
+      if (B == A) continue;
+      const double* p = L.pose[B];
+      const double d0 = wc0 - p[9], d1 = wc1 - p[10], d2 = wc2 - p[11];
+      const double rr = (sqrt(L.cull[B]) + sp.w) * (1.0 + 1e-9) + 1e-12;
+      cand |= d0 * d0 + d1 * d1 + d2 * d2 <= rr * rr;
+    }
+    if (tile == blockIdx.x && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+    if (cand && threadIdx.x == 0) {
+      unsigned long long n = (unsigned long long)min(kTileI, G.ni - i0) * min(kTileJ, G.nj - j0) * min(kTileK, G.nk - k0);
+      atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], n);
+    }
+    uint8_t* fa = flags + L.off[A];
+    const CT* Xa = (const CT*)L.X[A];
+    const CT* Ya = (const CT*)L.Y[A];
+    const CT* Za = (const CT*)L.Z[A];
+    const bool outer = L.outer[A] != 0;
+    bool hole = false;
+    // 4 nodes per batch: their coordinates are loaded before any flag store
+    for (int e0 = threadIdx.x; e0 < kTileI * kTileJ * kTileK; e0 += 4 * blockDim.x) {
+      long long m[4];
+      bool ok[4], onb[4];
+      CT X[4], Y[4], Z[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = e0 + r * blockDim.x;
+        const int i = i0 + (e & 63), j = j0 + ((e >> 6) & 7), k = k0 + (e >> 9);
+        ok[r] = e < kTileI * kTileJ * kTileK && i < G.ni && j < G.nj && k < G.nk;
+        m[r] = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+        onb[r] = outer && G.on_outer(i, j, k);
+        if (cand && ok[r]) {
+          X[r] = Xa[m[r]];
+          Y[r] = Ya[m[r]];
+          Z[r] = Za[m[r]];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!ok[r]) continue;
+        const int cause = cand ? holecut_node<CT>(L, grids, A, m[r], X[r], Y[r], Z[r]) : -1;
+        uint8_t f = (uint8_t)OV_STATE_FIELD;
+        if (cause >= 0) {
+          f = (uint8_t)(kHole | (cause << 2));
+          hole = true;
+        } else if (onb[r]) {
+          f = (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2));
+        }
+        fa[m[r]] = f;
+      }
+    }
+    hole = __syncthreads_or(hole);
+    if (threadIdx.x == 0) tile_hole[tile] = hole ? 1 : 0;
   }
 }
 
 template <typename CT>
 static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
-  long long total = ctx->node_off.back();
   int block = ctx->holecut_block;
-  int npt = ctx->holecut_npt;
-  long long chunks = (total + (long long)block * npt - 1) / ((long long)block * npt);
-  int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+  int R = ctx->holecut_npt;  // 16-byte vectors per lane per chunk
+  long long span = (long long)block * Vec16<CT>::W * R;
+  long long chunks = 0;
+  for (auto& g : ctx->grids) chunks += (g.d.nnodes + span - 1) / span;
+  int per_cu = ctx->persist > 0 ? ctx->persist : 16;
   long long grid = std::max(1LL, std::min(chunks, (long long)ctx->num_cus * per_cu));
   int ng = (int)ctx->grids.size();
-  if (npt == 4)
+  if (R == 4)
     hipLaunchKernelGGL((k_holecut<CT, 4>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       total, ctx->d_tile_hole);
-  else if (npt == 2)
+                       chunks, ctx->d_tile_hole, ctx->d_stats);
+  else if (R == 2)
     hipLaunchKernelGGL((k_holecut<CT, 2>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       total, ctx->d_tile_hole);
+                       chunks, ctx->d_tile_hole, ctx->d_stats);
   else
     hipLaunchKernelGGL((k_holecut<CT, 1>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       total, ctx->d_tile_hole);
+                       chunks, ctx->d_tile_hole, ctx->d_stats);
 }
 
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+  if (ctx->cull) {
+    int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+    long long grid = std::max(1LL, std::min(ctx->total_tiles, (long long)ctx->num_cus * per_cu));
+    int ng = (int)ctx->grids.size();
+    if (ctx->precision == OV_MIXED)
+      hipLaunchKernelGGL(k_holecut_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                         flags, (const double4*)ctx->d_tile_sphere, ctx->total_tiles, ctx->d_tile_hole,
+                         ctx->d_stats);
+    else
+      hipLaunchKernelGGL(k_holecut_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                         flags, (const double4*)ctx->d_tile_sphere, ctx->total_tiles, ctx->d_tile_hole,
+                         ctx->d_stats);
+    return hipGetLastError();
+  }
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s);
   else launch_holecut_t<double>(ctx, poses, flags, s);
   return hipGetLastError();
@@ -287,21 +476,13 @@ __global__ void __launch_bounds__(256) k_fringe_near(const GridDev* __restrict__
     int ti, tj, tk;
     tile_coords(G, tile, ti, tj, tk);
     bool near = false;
-    for (int dz = -1; dz <= 1 && !near; ++dz) {
-      int z = wrap_or_out(tk + dz, G.tiles_k, G.per & 4);
-      if (z < 0) continue;
-      for (int dy = -1; dy <= 1 && !near; ++dy) {
-        int y = wrap_or_out(tj + dy, G.tiles_j, G.per & 2);
-        if (y < 0) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-          int x = wrap_or_out(ti + dx, G.tiles_i, G.per & 1);
-          if (x < 0) continue;
-          if (tile_hole[G.tile_off + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)]) {
-            near = true;
-            break;
-          }
-        }
-      }
+#pragma unroll
+    for (int d = 0; d < 27; ++d) {
+      int x = wrap_or_out(ti + d % 3 - 1, G.tiles_i, G.per & 1);
+      int y = wrap_or_out(tj + (d / 3) % 3 - 1, G.tiles_j, G.per & 2);
+      int z = wrap_or_out(tk + d / 9 - 1, G.tiles_k, G.per & 4);
+      if (x >= 0 && y >= 0 && z >= 0)
+        near |= tile_hole[G.tile_off + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)] != 0;
     }
     if (near) {
       int slot = atomicAdd(near_count, 1);
@@ -321,16 +502,53 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
   const long long nnear = min((long long)*near_count, total_tiles);
   for (long long it = blockIdx.x; it < nnear; it += gridDim.x) {
     const long long tile = near_list[it];
-    const GridDev& G = grids[tile_grid(grids, ngrids, tile)];
+    const GridDev& GD = grids[tile_grid(grids, ngrids, tile)];
     int ti, tj, tk;
-    tile_coords(G, tile, ti, tj, tk);
+    tile_coords(GD, tile, ti, tj, tk);
     const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
-    uint8_t* fl = flags + G.node_off;
-    for (int e = threadIdx.x; e < EI * EJ * EK; e += blockDim.x) {
-      int x = e % EI, y = (e / EI) % EJ, z = e / (EI * EJ);
-      int i = wrap_or_out(i0 - NF + x, G.ni, G.per & 1);
-      int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
-      int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
+    uint8_t* fl = flags + GD.node_off;
+    struct {
+      int ni, nj, nk, per;
+    } const G = {GD.ni, GD.nj, GD.nk, GD.per};
+    // stage hole causes with halo: 16 threads per row load the 64 interior
+    // bytes as words where the row is aligned and in range, the halo bytewise
+    for (int e = threadIdx.x; e < EJ * EK * 16; e += blockDim.x) {
+      const int row = e >> 4, part = e & 15;
+      const int y = row % EJ, z = row / EJ;
+      const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
+      const int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
+      uint8_t v[4] = {255, 255, 255, 255};
+      if (j >= 0 && k >= 0) {
+        const uint8_t* rowp = fl + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+        const int i = i0 + part * 4;
+        if (i + 4 <= G.ni && (((uintptr_t)(rowp + i)) & 3) == 0) {
+          uint32_t w4 = *reinterpret_cast<const uint32_t*>(rowp + i);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            uint8_t f = (uint8_t)(w4 >> (8 * q));
+            v[q] = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int ii = wrap_or_out(i + q, G.ni, G.per & 1);
+            if (ii >= 0) {
+              uint8_t f = rowp[ii];
+              if ((f & 3) == kHole) v[q] = f >> 2;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[z][y][NF + part * 4 + q] = v[q];
+    }
+    for (int e = threadIdx.x; e < EJ * EK * 2 * NF; e += blockDim.x) {
+      const int h = e % (2 * NF), row = e / (2 * NF);
+      const int y = row % EJ, z = row / EJ;
+      const int x = h < NF ? h : kTileI + h;  // NF halo bytes on each side
+      const int i = wrap_or_out(i0 - NF + x, G.ni, G.per & 1);
+      const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
+      const int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
       uint8_t v = 255;
       if (i >= 0 && j >= 0 && k >= 0) {
         uint8_t f = fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)];
@@ -359,13 +577,13 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
       int x = e & 63, y = (e >> 6) & 7, z = e >> 9;
       int i = i0 + x, j = j0 + y, k = k0 + z;
       if (i >= G.ni || j >= G.nj || k >= G.nk) continue;
+      if (a[z + NF][y + NF][x + NF] != 255) continue;  // a hole (staged above)
       uint8_t cause = 255;
 #pragma unroll
       for (int d = 0; d <= 2 * NF; ++d) cause = min(cause, c[z + d][y][x]);
       if (cause == 255) continue;
-      long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
       // buffer causes are grid ids < 63, so they win over an outer-boundary cause
-      if ((fl[m] & 3) != kHole) fl[m] = (uint8_t)(kFringe | (cause << 2));
+      fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)] = (uint8_t)(kFringe | (cause << 2));
     }
     __syncthreads();
   }

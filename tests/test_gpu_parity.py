@@ -50,6 +50,13 @@ def test_c1_small_fp64_matches_oracle_every_step():
     _run_and_compare(w, list(range(6)))
 
 
+def test_c1_small_streaming_holecut_matches_oracle():
+    """The same step with the culling hole cut switched off (every node streamed)."""
+    w = W.c1_small(steps=3)
+    _run_and_compare(w, [0, 1, 2], options={"holecut_cull": 0})
+    _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_cull": 0})
+
+
 def test_c1_small_mixed_matches_oracle():
     w = W.c1_small(steps=6)
     stats = _run_and_compare(w, list(range(6)), precision="mixed", value_rtol=1e-5, s_tol=1e-4)
@@ -110,8 +117,8 @@ def test_capacity_overflow_sets_status_and_writes_nothing_past_capacity():
     w = W.c0()
     a = _assembly(w, capacity=100)
     sentinel = torch.full((200,), -7, dtype=torch.int32, device="cuda")
-    a.q_grid = torch.cat([a.q_grid[:100], sentinel[:100]]).contiguous()
-    a.q_node = torch.cat([a.q_node[:100], sentinel[100:]]).contiguous()
+    a.buf.q_grid = torch.cat([a.q_grid[:100], sentinel[:100]]).contiguous()
+    a.buf.q_node = torch.cat([a.q_node[:100], sentinel[100:]]).contiguous()
     a.step(w.poses[0])
     torch.cuda.synchronize()
     assert int(a.d_count.item()) == 1040
@@ -186,3 +193,50 @@ def test_bad_arguments_rejected_before_launch():
         ctx.grid_add((1, 2, 4), 0, x, x, x)
     with pytest.raises(B.OversetError):
         B.overset_holecut(ctx, x, a.flags)  # before finalize
+
+
+def test_two_stream_pipeline_matches_sequential():
+    """Steps run by the two-stream pipeline (front half of step t+1 beside
+    the back half of step t) equal the single-stream steps bitwise."""
+    from paper_1910_09315_amd.assembly import Pipeline
+    w = W.c1_small(steps=7)
+    a = _assembly(w)
+    b = _assembly(w, capacity=a.capacity)
+    pipe = Pipeline(b, a.capacity)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    seq = []
+    for t in range(7):
+        a.step(poses[t])
+        seq.append(a.results())
+    for t in range(7):
+        pipe.submit(t, poses[t])
+        if t >= 1:
+            r = pipe.results(t - 1)
+            for k in ("flags", "q_node", "donor_grid", "donor_cell", "status", "s", "values"):
+                assert np.array_equal(r[k], seq[t - 1][k], equal_nan=True), (t - 1, k)
+
+
+def test_graph_pipeline_matches_sequential():
+    """The two-stream pipeline replaying per-half HIP graphs gives the same
+    results as single-stream steps, step by step."""
+    from paper_1910_09315_amd.assembly import Pipeline
+    w = W.c1_small(steps=7)
+    a = _assembly(w)
+    b = _assembly(w, capacity=a.capacity)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    seq = []
+    for t in range(7):
+        a.step(poses[t])
+        seq.append(a.results())
+    pipe = Pipeline(b, a.capacity)
+    pipe.capture()
+    b.ctx.reset_history()
+    counts = torch.zeros(7, dtype=torch.int64, device="cuda")
+    for t in range(7):
+        pipe.submit(t, poses[t], count_out=counts[t:t + 1])
+        if t >= 1:
+            r = pipe.results(t - 1)
+            for key in ("flags", "q_node", "donor_grid", "donor_cell", "status", "s", "values"):
+                assert np.array_equal(r[key], seq[t - 1][key], equal_nan=True), (t - 1, key)
+    pipe.join()
+    assert [int(x) for x in counts.cpu()] == [seq[t]["count"] for t in range(7)]
