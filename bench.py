@@ -66,7 +66,8 @@ def main():
     ap.add_argument("--precision", default=None, help="fp64 or mixed (default: the config's)")
     ap.add_argument("--graph", action="store_true", help="single stream, each step replayed from a HIP graph")
     ap.add_argument("--sequential", action="store_true", help="single stream, eager launches")
-    ap.add_argument("--eager", action="store_true", help="two-stream pipeline with eager launches (no graph)")
+    ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
+    ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,12 +114,12 @@ def main():
     cap = 2 * n0 + 4096
     a.allocate(cap)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).to(dev)
-    mode = "graph" if args.graph else ("sequential" if args.sequential else
-                                       ("pipelined" if args.eager else "pipelined-graph"))
+    mode = ("graph" if args.graph else "sequential" if args.sequential else "pipelined-py" if args.eager else
+            "pipelined-graph" if args.graphs else "pipelined")
     log(f"[bench] set-up done, {n0} queries at t=0, capacity {cap}, mode {mode}")
     pipe = None
     if mode.startswith("pipelined"):
-        pipe = Pipeline(a, cap)
+        pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=args.steps)
     elif mode == "graph":
         a.capture()
     if mode == "pipelined-graph":
@@ -131,7 +132,7 @@ def main():
     def run(t, k=None):
         p = poses[t % w.steps]
         cnt = counts[t:t + 1]
-        ev = hc[k] if k is not None else None
+        ev = hc[k] if (k is not None and hc) else None
         if pipe is not None:
             pipe.submit(t, p, count_out=cnt, holecut_events=ev)
         elif mode == "graph":
@@ -160,6 +161,9 @@ def main():
     t_wall = time.perf_counter()
     start.record()
     t_host0 = time.perf_counter()
+    if pipe is not None and pipe.native is not None:
+        pipe.native.holecut_times(0)  # restart the timing record
+        pipe.native.set_timing(True)
     if pipe is not None:
         pipe.s_front.wait_stream(torch.cuda.current_stream(dev))
         pipe.s_back.wait_stream(torch.cuda.current_stream(dev))
@@ -183,8 +187,15 @@ def main():
 
     roofline = None
     roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
-    if hc:
+    if pipe is not None and pipe.native is not None:
+        pipe.native.set_timing(False)
+        hc_ms = np.array(pipe.native.holecut_times(args.steps))
+        roof_note = "hip events around every hole cut of the timed steps, recorded by the native executor on its front stream"
+    elif hc:
         hc_ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
+    else:
+        hc_ms = None
+    if hc_ms is not None and len(hc_ms):
         nodes = w.total_nodes
         per_node = 25 if precision == "fp64" else 13   # coordinates (3 x 8 or 3 x 4 B) + 1 flag byte
         bytes_launch = per_node * nodes

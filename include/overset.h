@@ -235,6 +235,59 @@ int overset_donor_search(ov_ctx *ctx, const double *poses, const uint8_t *flags,
 int overset_interp(ov_ctx *ctx, const int32_t *donor_grid, const int32_t *donor_cell, const void *s,
                    const int64_t *d_count, int64_t capacity, const void *fields, void *out, void *stream);
 
+/* ---------------------------------------------------------------- pipelined steps */
+
+/* Every device buffer one step writes (the arguments of the five calls). */
+typedef struct ov_step_buffers {
+    uint8_t *flags;        /* total_nodes bytes, 16-byte aligned */
+    int32_t *q_grid;       /* capacity */
+    int32_t *q_node;       /* capacity */
+    int64_t *d_count;      /* 1 */
+    void *qx;              /* 3*capacity, context precision */
+    int32_t *donor_grid;   /* capacity */
+    int32_t *donor_cell;   /* capacity */
+    void *s;               /* 3*capacity, context precision */
+    int32_t *status;       /* capacity */
+    void *out;             /* 4*capacity, context precision (unused without fields) */
+    int64_t capacity;
+} ov_step_buffers;
+
+typedef struct ov_pipe ov_pipe;
+
+/* A two-stream executor of consecutive steps (a scheduling layer over the
+ * five calls; not a step of the paper's method). Step t uses buffer set
+ * sets[t % 2]; its front half (overset_holecut, overset_fringe_compact) runs
+ * on stream_front and overlaps the back half (overset_transform,
+ * overset_donor_search, overset_interp) of step t-1 on stream_back. Events
+ * order front(t) after back(t-2) and back(t) after front(t); back halves
+ * follow one another on their stream, which keeps the warm start exact.
+ *  sets        2 buffer sets [host array; the device buffers stay caller-owned]
+ *  fields      4*total_nodes field values, or NULL for no interpolation
+ *  max_timed   number of steps whose hole cut may be timed (events, see below)
+ * The context must not be used by other calls while the pipeline has work
+ * in flight. Streams must differ and stay alive until ov_pipe_destroy. */
+int ov_pipe_create(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const void *fields,
+                   void *stream_front, void *stream_back, int32_t max_timed, ov_pipe **out);
+
+/* Queue the next step with poses (device, ngrids*12 doubles, must stay
+ * unchanged until the step completes). If count_out (device int64) is not
+ * NULL it receives the step's query count. Nothing synchronises. */
+int ov_pipe_submit(ov_pipe *pipe, const double *poses, int64_t *count_out);
+
+/* Make `stream` wait for all work submitted so far. */
+int ov_pipe_join(ov_pipe *pipe, void *stream);
+
+/* Time (or stop timing) the hole cut of the following submitted steps with
+ * events on the front stream, up to max_timed steps. */
+int ov_pipe_set_timing(ov_pipe *pipe, int32_t on);
+
+/* Elapsed milliseconds of the timed hole cuts so far (waits for them) into
+ * ms_out[0..*n_out) [host], then restarts the record. */
+int ov_pipe_holecut_times(ov_pipe *pipe, float *ms_out, int32_t max, int32_t *n_out);
+
+/* Wait for the pipeline's streams and free its events. */
+int ov_pipe_destroy(ov_pipe *pipe);
+
 #ifdef __cplusplus
 }
 #endif

@@ -162,14 +162,20 @@ class Assembly:
 
 
 class Pipeline:
-    """Two-stream, two-buffer execution of consecutive steps of an Assembly."""
+    """Two-stream, two-buffer execution of consecutive steps of an Assembly.
+    native=True drives the library's C++ executor (ov_pipe_*: one host call
+    per step); native=False issues the five calls from Python (optionally
+    replaying per-half HIP graphs, see capture())."""
 
-    def __init__(self, asm: Assembly, capacity: int):
+    def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024):
         self.a = asm
         dev = asm.dev
         self.bufs = [StepBuffers(dev, asm.total, capacity, asm.dtype) for _ in range(2)]
         self.s_front = torch.cuda.Stream(dev)
         self.s_back = torch.cuda.Stream(dev)
+        self.native = None
+        if native:
+            self.native = B.NativePipe(asm.ctx, asm.nf, self.bufs, asm.fields, self.s_front, self.s_back, max_timed)
         self.front_done = [torch.cuda.Event() for _ in range(2)]
         self.back_done = [torch.cuda.Event() for _ in range(2)]
         self.started = [False, False]
@@ -185,6 +191,10 @@ class Pipeline:
         k = t % 2
         b = self.bufs[k]
         p = poses_dev.reshape(-1)
+        if self.native is not None:
+            self.native.submit(p, count_out)
+            self.started[k] = True
+            return b
         with torch.cuda.stream(self.s_front):
             if self.started[k]:
                 self.s_front.wait_event(self.back_done[k])  # step t-2 no longer reads these buffers
@@ -254,6 +264,9 @@ class Pipeline:
     def join(self, stream=None):
         """Make `stream` (default: current) wait for everything submitted."""
         s = torch.cuda.current_stream(self.a.dev) if stream is None else stream
+        if self.native is not None:
+            self.native.join(s)
+            return
         s.wait_stream(self.s_front)
         s.wait_stream(self.s_back)
 

@@ -28,7 +28,8 @@ EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "o
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
-           "overset_interp"]
+           "overset_interp", "ov_pipe_create", "ov_pipe_submit", "ov_pipe_join", "ov_pipe_set_timing",
+           "ov_pipe_holecut_times", "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -38,6 +39,13 @@ _lib = None
 
 class OversetError(RuntimeError):
     pass
+
+
+class StepBuffersC(ctypes.Structure):
+    """ov_step_buffers (include/overset.h)."""
+    _fields_ = [("flags", _P), ("q_grid", _P), ("q_node", _P), ("d_count", _P), ("qx", _P),
+                ("donor_grid", _P), ("donor_cell", _P), ("s", _P), ("status", _P), ("out", _P),
+                ("capacity", _I64)]
 
 
 def load(path: str = LIB_PATH):
@@ -66,6 +74,12 @@ def load(path: str = LIB_PATH):
         "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
         "overset_donor_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P]),
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
+        "ov_pipe_create": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+        "ov_pipe_submit": (ctypes.c_int, [_P, _P, _P]),
+        "ov_pipe_join": (ctypes.c_int, [_P, _P]),
+        "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32]),
+        "ov_pipe_holecut_times": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
+        "ov_pipe_destroy": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -185,3 +199,48 @@ def overset_donor_search(ctx: Context, poses, flags, q_grid, q_node, qx, d_count
 def overset_interp(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, fields, out, stream=None):
     ctx.check(ctx.lib.overset_interp(ctx.h, _ptr(donor_grid), _ptr(donor_cell), _ptr(s), _ptr(d_count),
                                      int(capacity), _ptr(fields), _ptr(out), _stream(stream)), "overset_interp")
+
+
+class NativePipe:
+    """ov_pipe: the library's two-stream step executor."""
+
+    def __init__(self, ctx: Context, nf: int, sets, fields, stream_front, stream_back, max_timed: int = 0):
+        self.ctx = ctx
+        arr = (StepBuffersC * 2)()
+        for k, b in enumerate(sets):
+            arr[k] = StepBuffersC(b.flags.data_ptr(), b.q_grid.data_ptr(), b.q_node.data_ptr(), b.d_count.data_ptr(),
+                                  b.qx.data_ptr(), b.donor_grid.data_ptr(), b.donor_cell.data_ptr(),
+                                  b.s.data_ptr(), b.status.data_ptr(), b.out.data_ptr(), b.capacity)
+        self._keep = (sets, fields, stream_front, stream_back)
+        h = _P()
+        ctx.check(ctx.lib.ov_pipe_create(ctx.h, int(nf), arr, _ptr(fields), _P(stream_front.cuda_stream),
+                                         _P(stream_back.cuda_stream), int(max_timed), ctypes.byref(h)),
+                  "ov_pipe_create")
+        self.h = h
+
+    def submit(self, poses, count_out=None):
+        self.ctx.check(self.ctx.lib.ov_pipe_submit(self.h, _ptr(poses), _ptr(count_out)), "ov_pipe_submit")
+
+    def join(self, stream=None):
+        self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")
+
+    def set_timing(self, on: bool):
+        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(bool(on))), "ov_pipe_set_timing")
+
+    def holecut_times(self, max_n: int):
+        out = (ctypes.c_float * max(1, max_n))()
+        n = _I32()
+        self.ctx.check(self.ctx.lib.ov_pipe_holecut_times(self.h, out, int(max_n), ctypes.byref(n)),
+                       "ov_pipe_holecut_times")
+        return [out[i] for i in range(n.value)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ov_pipe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

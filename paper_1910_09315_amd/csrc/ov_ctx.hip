@@ -103,6 +103,27 @@ __global__ void k_bins(GridDev g, unsigned long long* __restrict__ cnt, int* __r
   }
 }
 
+// Sort each control cell's list by cell index (shell sort, one thread per
+// control cell), so a scan in list order meets the lowest index first.
+__global__ void k_bin_sort(const long long* __restrict__ start, int* __restrict__ cells, long long nbins) {
+  const int gaps[8] = {701, 301, 132, 57, 23, 10, 4, 1};
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nbins; b += (long long)gridDim.x * blockDim.x) {
+    int* a = cells + start[b];
+    const int n = (int)(start[b + 1] - start[b]);
+    for (int gi = 0; gi < 8; ++gi) {
+      const int gap = gaps[gi];
+      for (int i = gap; i < n; ++i) {
+        int v = a[i], j = i;
+        while (j >= gap && a[j - gap] > v) {
+          a[j] = a[j - gap];
+          j -= gap;
+        }
+        a[j] = v;
+      }
+    }
+  }
+}
+
 // Walk seed of each control cell: the listed donor cell whose corner mean is
 // nearest the control cell's centre (ties: lowest index); -1 if none.
 __global__ void k_bin_rep(GridDev g, const long long* __restrict__ start, const int* __restrict__ cells,
@@ -271,6 +292,8 @@ int build_control_cells(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   hipLaunchKernelGGL(k_bins<1>, dim3(blocks_for(g.ncells)), dim3(256), 0, s, g, d_cnt, (int*)nullptr,
                      (const long long*)gh.bstart, gh.bcells);
   HIPCHK(hipGetLastError(), "control-cell kernels");
+  hipLaunchKernelGGL(k_bin_sort, dim3(blocks_for(nbins)), dim3(256), 0, s, (const long long*)gh.bstart, gh.bcells,
+                     nbins);
   hipLaunchKernelGGL(k_bin_rep, dim3(blocks_for(nbins)), dim3(256), 0, s, g, (const long long*)gh.bstart,
                      (const int*)gh.bcells, gh.brep, nbins);
   HIPCHK(hipGetLastError(), "control-cell seeds");
@@ -347,8 +370,6 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_warm_grid);
   (void)hipFree(ctx->d_tile_sphere);
   (void)hipFree(ctx->d_tile_hole);
-  (void)hipFree(ctx->d_near_list);
-  (void)hipFree(ctx->d_near_count);
   (void)hipFree(ctx->d_scanq);
   (void)hipFree(ctx->d_scanq_count);
   (void)hipFree(ctx->d_scanq_ticket);
@@ -460,9 +481,6 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_tile_hole, std::max(1LL, ctx->total_tiles)), "hipMalloc tile map");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(ctx->total_tiles)), dim3(256), 0, s, ctx->d_tile_hole,
                      ctx->total_tiles, (uint8_t)0);
-  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int) * std::max(1LL, ctx->total_tiles)), "hipMalloc near list");
-  HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int)), "hipMalloc near count");
-  HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int), s), "near count init");
   ctx->scanq_cap = 65536;
   HIPCHK(hipMalloc(&ctx->d_scanq, sizeof(int2) * ctx->scanq_cap), "hipMalloc scan queue");
   HIPCHK(hipMalloc(&ctx->d_scanq_count, sizeof(int)), "hipMalloc scan queue count");

@@ -86,8 +86,6 @@ struct ov_ctx {
   uint8_t* d_warm_grid = nullptr;
   double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
   uint8_t* d_tile_hole = nullptr;  // per fringe tile: holds a hole (set by the hole cut, cleared by compaction)
-  int* d_near_list = nullptr;      // tiles near a hole (fringe pass)
-  int* d_near_count = nullptr;
   int2* d_scanq = nullptr;         // queries whose walk fell back to the brute-force scan
   int* d_scanq_count = nullptr;    // emptied by the last block of the scan phase
   unsigned int* d_scanq_ticket = nullptr;

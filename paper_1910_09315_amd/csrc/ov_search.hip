@@ -188,7 +188,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
                     bool& limit, int& visited) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
-  int pi = -1, pj = -1, pk = -1;
+  int hist[4] = {-1, -1, -1, -1};  // the last cells visited: a revisit ends the walk
   for (int stepn = 0; stepn < max_walk; ++stepn) {
     ++visited;
     CellMap<T> m;
@@ -221,22 +221,26 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
       }
     }
     if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
-    // step toward the point: the integer part of s, at most 2 cells per axis
+    // step toward the point by the integer part of s: up to a quarter turn
+    // in a periodic direction (where s is an angle-like cell count, e.g. the
+    // azimuth of a shell near its polar axis), up to 8 cells otherwise
+    const int lim_i = (G.per & 1) ? max(2, G.nci / 4) : 8;
+    const int lim_j = (G.per & 2) ? max(2, G.ncj / 4) : 8;
+    const int lim_k = (G.per & 4) ? max(2, G.nck / 4) : 8;
     int di = 0, dj = 0, dk = 0;
-    if (s[0] < (T)0) di = max(-2, (int)floor(s[0]));
-    else if (s[0] > (T)1) di = min(2, (int)floor(s[0]));
-    if (s[1] < (T)0) dj = max(-2, (int)floor(s[1]));
-    else if (s[1] > (T)1) dj = min(2, (int)floor(s[1]));
-    if (s[2] < (T)0) dk = max(-2, (int)floor(s[2]));
-    else if (s[2] > (T)1) dk = min(2, (int)floor(s[2]));
+    if (s[0] < (T)0) di = (int)fmax(-(T)lim_i, floor(s[0]));
+    else if (s[0] > (T)1) di = (int)fmin((T)lim_i, floor(s[0]));
+    if (s[1] < (T)0) dj = (int)fmax(-(T)lim_j, floor(s[1]));
+    else if (s[1] > (T)1) dj = (int)fmin((T)lim_j, floor(s[1]));
+    if (s[2] < (T)0) dk = (int)fmax(-(T)lim_k, floor(s[2]));
+    else if (s[2] > (T)1) dk = (int)fmin((T)lim_k, floor(s[2]));
     bool clamped = false;
     int ni = step_axis(ci, di, G.nci, G.per & 1, clamped);
     int nj = step_axis(cj, dj, G.ncj, G.per & 2, clamped);
     int nk = step_axis(ck, dk, G.nck, G.per & 4, clamped);
-    if ((ni == ci && nj == cj && nk == ck) || (ni == pi && nj == pj && nk == pk)) return kToScan;
-    pi = ci;
-    pj = cj;
-    pk = ck;
+    const int next = (int)(ni + (long long)G.nci * (nj + (long long)G.ncj * nk));
+    hist[stepn & 3] = here;
+    if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
     ci = ni;
     cj = nj;
     ck = nk;
@@ -291,15 +295,14 @@ __device__ __forceinline__ bool hull_excludes(const double P[8][3], const double
 }
 
 // Brute-force scan of the control cell holding xi (FP64): lowest valid
-// containing cell, or -1.
+// containing cell, or -1. Control-cell lists are sorted by cell index, so
+// the first valid containing cell met is the lowest.
 __device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
   long long b = bin_axis(G, 0, xi[0]) +
                 (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
   long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
-  int best = -1;
   for (long long e = e0; e < e1; ++e) {
     int cell = G.bcells[e];
-    if (best >= 0 && cell >= best) continue;
     int ci, cj, ck;
     cell_ijk(G, cell, ci, cj, ck);
     double P[8][3];
@@ -316,12 +319,12 @@ __device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const doub
     double s[3];
     if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
     if (!cell_valid(G, fl, ci, cj, ck)) continue;
-    best = cell;
     s_best[0] = s[0];
     s_best[1] = s[1];
     s_best[2] = s[2];
+    return cell;
   }
-  return best;
+  return -1;
 }
 
 // Candidate donor grid at position t of a query of grid A: t = -2 the cause
@@ -493,47 +496,47 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-// Wavefront-cooperative brute-force scan: the 64 lanes split the control
-// cell's candidate list, then the lowest valid containing cell wins.
+// Wavefront-cooperative brute-force scan: the control cell's sorted list is
+// taken 64 candidates per round, one per lane; the first round holding a
+// valid containing cell ends the scan with its lowest such cell.
 __device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
   const int lane = threadIdx.x & 63;
   long long b = bin_of(G, xi);
   long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
-  int best = 0x7fffffff;
-  double sb[3] = {0.0, 0.0, 0.0};
-  for (long long e = e0 + lane; e < e1; e += 64) {
-    int cell = G.bcells[e];
-    if (cell >= best) continue;
-    int ci, cj, ck;
-    cell_ijk(G, cell, ci, cj, ck);
-    double P[8][3];
+  for (long long base = e0; base < e1; base += 64) {
+    const long long e = base + lane;
+    bool hit = false;
+    double s[3] = {0.0, 0.0, 0.0};
+    int cell = 0x7fffffff;
+    if (e < e1) {
+      cell = G.bcells[e];
+      int ci, cj, ck;
+      cell_ijk(G, cell, ci, cj, ck);
+      double P[8][3];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      long long nd = corner_node(G, ci, cj, ck, c);
-      P[c][0] = G.X[nd];
-      P[c][1] = G.Y[nd];
-      P[c][2] = G.Z[nd];
+      for (int c = 0; c < 8; ++c) {
+        long long nd = corner_node(G, ci, cj, ck, c);
+        P[c][0] = G.X[nd];
+        P[c][1] = G.Y[nd];
+        P[c][2] = G.Z[nd];
+      }
+      if (!hull_excludes(P, xi)) {
+        CellMap<double> m;
+        map_from_corners<double>(P, xi, m);
+        hit = newton<double>(m, s, nullptr) && inside<double>(s, kSTol) && cell_valid(G, fl, ci, cj, ck);
+      }
     }
-    if (hull_excludes(P, xi)) continue;
-    CellMap<double> m;
-    map_from_corners<double>(P, xi, m);
-    double s[3];
-    if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
-    if (!cell_valid(G, fl, ci, cj, ck)) continue;
-    best = cell;
-    sb[0] = s[0];
-    sb[1] = s[1];
-    sb[2] = s[2];
+    const unsigned long long hits = __ballot(hit);
+    if (hits) {
+      // lists are ascending: the lowest lane that hit holds the lowest cell
+      const int src = __ffsll((long long)hits) - 1;
+      s_best[0] = __shfl(s[0], src, 64);
+      s_best[1] = __shfl(s[1], src, 64);
+      s_best[2] = __shfl(s[2], src, 64);
+      return __shfl(cell, src, 64);
+    }
   }
-  int low = best;
-  for (int o = 32; o > 0; o >>= 1) low = min(low, __shfl_xor(low, o, 64));
-  if (low == 0x7fffffff) return -1;
-  unsigned long long who = __ballot(best == low);
-  int src = __ffsll((long long)who) - 1;
-  s_best[0] = __shfl(sb[0], src, 64);
-  s_best[1] = __shfl(sb[1], src, 64);
-  s_best[2] = __shfl(sb[2], src, 64);
-  return low;
+  return -1;
 }
 
 // Phase 2: one wavefront per queued query. All lanes follow the same (uniform)

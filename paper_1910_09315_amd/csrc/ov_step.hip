@@ -301,6 +301,9 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
   }
 }
 
+static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI * kTileJ * kTileK,
+              "a 256-thread block covers a tile with 16 bytes per thread");
+
 // Hole cut over node tiles (kTileI x kTileJ x kTileK, one block per tile)
 // with culling: a tile whose bounding sphere, placed at its grid's pose,
 // cannot reach the bounding sphere of any other grid's blank region holds no
@@ -353,6 +356,28 @@ __global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict
     const CT* Za = (const CT*)L.Z[A];
     const bool outer = L.outer[A] != 0;
     bool hole = false;
+    if (!cand) {
+      // no hole possible: each thread writes 16 flag bytes of one tile row
+      const int row = threadIdx.x >> 2, part = threadIdx.x & 3;
+      const int i = i0 + part * 16, j = j0 + (row & 7), k = k0 + (row >> 3);
+      if (threadIdx.x < 256 && i < G.ni && j < G.nj && k < G.nk) {
+        const long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+        uint8_t* dst = fa + m;
+        const int n = min(16, G.ni - i);
+        const bool row_outer = outer && (j < G.o2 || j >= G.nj - G.o3 || k < G.o4 || k >= G.nk - G.o5);
+        if (!outer || (!row_outer && i >= G.o0 && i + 16 <= G.ni - G.o1)) {
+          if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
+            *reinterpret_cast<uint4*>(dst) = make_uint4(0u, 0u, 0u, 0u);
+          } else {
+            for (int q = 0; q < n; ++q) dst[q] = (uint8_t)OV_STATE_FIELD;
+          }
+        } else {
+          for (int q = 0; q < n; ++q)
+            dst[q] = (row_outer || i + q < G.o0 || i + q >= G.ni - G.o1) ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2))
+                                                                           : (uint8_t)OV_STATE_FIELD;
+        }
+      }
+    } else {
     // 4 nodes per batch: their coordinates are loaded before any flag store
     for (int e0 = threadIdx.x; e0 < kTileI * kTileJ * kTileK; e0 += 4 * blockDim.x) {
       long long m[4];
@@ -384,6 +409,7 @@ __global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict
         }
         fa[m[r]] = f;
       }
+    }
     }
     hole = __syncthreads_or(hole);
     if (threadIdx.x == 0) tile_hole[tile] = hole ? 1 : 0;
@@ -435,10 +461,11 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
 // The hole cut already wrote holes, the outer-boundary layers and, per 3D
 // tile of kTileI x kTileJ x kTileK nodes, whether the tile holds a hole.
 // Only tiles with a hole in themselves or a neighbour tile (nf < tile size,
-// so the buffer reaches no further) can gain buffer nodes: one thread per
-// tile lists them, then one block per listed tile stages the tile plus an
-// nf halo in LDS as "cause if hole, 255 otherwise" and takes the lowest cause
-// within Chebyshev distance nf by a separable min filter (i, then j, then k).
+// so the buffer reaches no further) can gain buffer nodes: a block checks
+// the 27 map entries of its tile and leaves at once otherwise; near a hole it
+// stages the tile plus an nf halo in LDS as "cause if hole, 255 otherwise"
+// and takes the lowest cause within Chebyshev distance nf by a separable min
+// filter (i, then j, then k).
 // Holes are never rewritten, so updating flags in place is race-free: a
 // neighbour tile only reads whether a node is a hole.
 static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8, "tile indexing below uses shifts");
@@ -467,52 +494,41 @@ __device__ __forceinline__ void tile_coords(const GridDev& G, long long tile, in
   tk = (int)(t / ((long long)G.tiles_i * G.tiles_j));
 }
 
-__global__ void __launch_bounds__(256) k_fringe_near(const GridDev* __restrict__ grids, int ngrids,
-                                                    const uint8_t* __restrict__ tile_hole, long long total_tiles,
-                                                    int* __restrict__ near_list, int* __restrict__ near_count) {
-  for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
-       tile += (long long)gridDim.x * blockDim.x) {
-    const GridDev& G = grids[tile_grid(grids, ngrids, tile)];
-    int ti, tj, tk;
-    tile_coords(G, tile, ti, tj, tk);
-    bool near = false;
-#pragma unroll
-    for (int d = 0; d < 27; ++d) {
-      int x = wrap_or_out(ti + d % 3 - 1, G.tiles_i, G.per & 1);
-      int y = wrap_or_out(tj + (d / 3) % 3 - 1, G.tiles_j, G.per & 2);
-      int z = wrap_or_out(tk + d / 9 - 1, G.tiles_k, G.per & 4);
-      if (x >= 0 && y >= 0 && z >= 0)
-        near |= tile_hole[G.tile_off + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)] != 0;
-    }
-    if (near) {
-      int slot = atomicAdd(near_count, 1);
-      if ((long long)slot < total_tiles) near_list[slot] = (int)tile;
-    }
-  }
-}
-
 template <int NF>
 __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict__ grids, int ngrids,
-                                                     uint8_t* __restrict__ flags, const int* __restrict__ near_list,
-                                                     const int* __restrict__ near_count, long long total_tiles) {
+                                                     uint8_t* __restrict__ flags, const uint8_t* __restrict__ tile_hole,
+                                                     long long total_tiles) {
   constexpr int EI = kTileI + 2 * NF, EJ = kTileJ + 2 * NF, EK = kTileK + 2 * NF;
+  constexpr int NROW = EJ * EK * 16, NHALO = EJ * EK * 2 * NF;
   __shared__ uint8_t a[EK][EJ][EI];
   __shared__ uint8_t b[EK][EJ][kTileI];
   __shared__ uint8_t c[EK][kTileJ][kTileI];
-  const long long nnear = min((long long)*near_count, total_tiles);
-  for (long long it = blockIdx.x; it < nnear; it += gridDim.x) {
-    const long long tile = near_list[it];
+  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     const GridDev& GD = grids[tile_grid(grids, ngrids, tile)];
     int ti, tj, tk;
     tile_coords(GD, tile, ti, tj, tk);
+    struct {
+      int ni, nj, nk, per, tiles_i, tiles_j, tiles_k;
+    } const G = {GD.ni, GD.nj, GD.nk, GD.per, GD.tiles_i, GD.tiles_j, GD.tiles_k};
+    const long long toff = GD.tile_off;
+    // a hole in this tile or a neighbour tile? (nf < tile size: nothing further matters)
+    bool near = false;
+    if (threadIdx.x < 27) {
+      int x = wrap_or_out(ti + (int)threadIdx.x % 3 - 1, G.tiles_i, G.per & 1);
+      int y = wrap_or_out(tj + ((int)threadIdx.x / 3) % 3 - 1, G.tiles_j, G.per & 2);
+      int z = wrap_or_out(tk + (int)threadIdx.x / 9 - 1, G.tiles_k, G.per & 4);
+      if (x >= 0 && y >= 0 && z >= 0) near = tile_hole[toff + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)];
+    }
+    if (!__syncthreads_or(near)) continue;
     const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
     uint8_t* fl = flags + GD.node_off;
-    struct {
-      int ni, nj, nk, per;
-    } const G = {GD.ni, GD.nj, GD.nk, GD.per};
     // stage hole causes with halo: 16 threads per row load the 64 interior
-    // bytes as words where the row is aligned and in range, the halo bytewise
-    for (int e = threadIdx.x; e < EJ * EK * 16; e += blockDim.x) {
+    // bytes as words where the row is aligned and in range, the halo bytewise;
+    // fixed trip counts so that all loads are issued before the LDS stores
+#pragma unroll
+    for (int it = 0; it < (NROW + 255) / 256; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= NROW) break;
       const int row = e >> 4, part = e & 15;
       const int y = row % EJ, z = row / EJ;
       const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
@@ -542,7 +558,10 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[z][y][NF + part * 4 + q] = v[q];
     }
-    for (int e = threadIdx.x; e < EJ * EK * 2 * NF; e += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < (NHALO + 255) / 256; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= NHALO) break;
       const int h = e % (2 * NF), row = e / (2 * NF);
       const int y = row % EJ, z = row / EJ;
       const int x = h < NF ? h : kTileI + h;  // NF halo bytes on each side
@@ -592,22 +611,19 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
   if (nf == 0) return hipSuccess;  // outer layers were marked by the hole cut
   const int ng = (int)ctx->grids.size();
-  long long g1 = std::max(1LL, std::min<long long>((ctx->total_tiles + 255) / 256, 65535));
-  hipLaunchKernelGGL(k_fringe_near, dim3((unsigned)g1), dim3(256), 0, s, ctx->d_grids, ng, ctx->d_tile_hole,
-                     ctx->total_tiles, ctx->d_near_list, ctx->d_near_count);
-  long long g2 = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 2));
+  long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 8));
   switch (nf) {
     case 1:
-      hipLaunchKernelGGL(k_fringe_tiles<1>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<1>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_tile_hole, ctx->total_tiles);
       break;
     case 2:
-      hipLaunchKernelGGL(k_fringe_tiles<2>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<2>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_tile_hole, ctx->total_tiles);
       break;
     default:
-      hipLaunchKernelGGL(k_fringe_tiles<3>, dim3((unsigned)g2), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_near_list, ctx->d_near_count, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<3>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
+                         ctx->d_tile_hole, ctx->total_tiles);
       break;
   }
   return hipGetLastError();
@@ -660,8 +676,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
 
 __global__ void __launch_bounds__(1024) k_compact_scan(const int32_t* __restrict__ counts, long long n,
                                                       long long* __restrict__ offsets, long long* __restrict__ d_count,
-                                                      long long capacity, int32_t* __restrict__ status,
-                                                      int* __restrict__ near_count) {
+                                                      long long capacity, int32_t* __restrict__ status) {
   __shared__ long long part[1024];
   long long per = (n + blockDim.x - 1) / blockDim.x;
   long long b0 = threadIdx.x * per, b1 = min(n, b0 + per);
@@ -684,7 +699,6 @@ __global__ void __launch_bounds__(1024) k_compact_scan(const int32_t* __restrict
     long long total = part[threadIdx.x];
     *d_count = total;
     if (total > capacity) atomicOr(status, OV_DEV_CAPACITY);
-    *near_count = 0;  // the fringe pass of this call has consumed its tile list
   }
 }
 
@@ -738,7 +752,7 @@ hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, in
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
                      ctx->d_chunk_counts, nch, ctx->d_tile_hole, ctx->total_tiles);
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_chunk_counts, nch, ctx->d_chunk_offsets,
-                     d_count, capacity, ctx->d_status, ctx->d_near_count);
+                     d_count, capacity, ctx->d_status);
   hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
                      (int)ctx->grids.size(), flags, total, ctx->d_chunk_offsets, nch, q_grid, q_node, capacity);
   return hipGetLastError();

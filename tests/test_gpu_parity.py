@@ -195,14 +195,16 @@ def test_bad_arguments_rejected_before_launch():
         B.overset_holecut(ctx, x, a.flags)  # before finalize
 
 
-def test_two_stream_pipeline_matches_sequential():
+@pytest.mark.parametrize("native", [True, False])
+def test_two_stream_pipeline_matches_sequential(native):
     """Steps run by the two-stream pipeline (front half of step t+1 beside
-    the back half of step t) equal the single-stream steps bitwise."""
+    the back half of step t), driven by the library's executor or from
+    Python, equal the single-stream steps bitwise."""
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
     a = _assembly(w)
     b = _assembly(w, capacity=a.capacity)
-    pipe = Pipeline(b, a.capacity)
+    pipe = Pipeline(b, a.capacity, native=native)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     seq = []
     for t in range(7):
@@ -228,7 +230,7 @@ def test_graph_pipeline_matches_sequential():
     for t in range(7):
         a.step(poses[t])
         seq.append(a.results())
-    pipe = Pipeline(b, a.capacity)
+    pipe = Pipeline(b, a.capacity, native=False)
     pipe.capture()
     b.ctx.reset_history()
     counts = torch.zeros(7, dtype=torch.int64, device="cuda")
