@@ -280,7 +280,7 @@ typedef struct {
     double lo[3], inv[3];
     int nb[3];
     int64_t *start;   /* [nbins + 1] */
-    int64_t *cells;   /* candidate donor cells of each control cell */
+    int32_t *cells;   /* candidate donor cells of each control cell (any order) */
 } orc_bins;
 
 static void cell_aabb(const gdim *g, const double *X, const double *Y, const double *Z,
@@ -351,14 +351,15 @@ orc_bins *orc_bins_build(const int32_t *dims, const double *X, const double *Y, 
     }
     int64_t nbins = (int64_t)b->nb[0] * b->nb[1] * b->nb[2];
     b->start = (int64_t *)calloc((size_t)nbins + 1, sizeof(int64_t));
+    int64_t *cursor = NULL;
     for (int pass = 0; pass < 2; ++pass) {
-        int64_t *cursor = NULL;
         if (pass == 1) {
             for (int64_t q = 0; q < nbins; ++q) b->start[q + 1] += b->start[q];
-            b->cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)(b->start[nbins] > 0 ? b->start[nbins] : 1));
-            cursor = (int64_t *)malloc(sizeof(int64_t) * (size_t)nbins);
+            b->cells = (int32_t *)malloc(sizeof(int32_t) * (size_t)(b->start[nbins] > 0 ? b->start[nbins] : 1));
+            cursor = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nbins > 0 ? nbins : 1));
             memcpy(cursor, b->start, sizeof(int64_t) * (size_t)nbins);
         }
+#pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < ncell; ++c) {
             double clo[3], chi[3];
             cell_aabb(&g, X, Y, Z, c, clo, chi);
@@ -369,12 +370,19 @@ orc_bins *orc_bins_build(const int32_t *dims, const double *X, const double *Y, 
                 for (int y = b0; y <= b1; ++y)
                     for (int x = a0; x <= a1; ++x) {
                         int64_t q = x + (int64_t)b->nb[0] * (y + (int64_t)b->nb[1] * z);
-                        if (pass == 0) b->start[q + 1]++;
-                        else b->cells[cursor[q]++] = c;
+                        if (pass == 0) {
+#pragma omp atomic
+                            b->start[q + 1]++;
+                        } else {
+                            int64_t slot;
+#pragma omp atomic capture
+                            slot = cursor[q]++;
+                            b->cells[slot] = (int32_t)c;
+                        }
                     }
         }
-        free(cursor);
     }
+    free(cursor);
     return b;
 }
 
@@ -547,7 +555,7 @@ void orc_donor_search(int ngrids, const int32_t *dims, const double *const *X, c
             double sb[3] = {0, 0, 0};
             int64_t ncell = (int64_t)g.nci * g.ncj * g.nck;
             int64_t c0 = 0, c1 = ncell;
-            const int64_t *list = NULL;
+            const int32_t *list = NULL;
             if (!exhaustive) {
                 const orc_bins *b = bins[B];
                 double lo[3] = {b->lo[0], b->lo[1], b->lo[2]};

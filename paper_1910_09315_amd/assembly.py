@@ -74,8 +74,9 @@ class Assembly:
 
     # ------------------------------------------------------------ buffers
     def set_fields(self, fields):
-        f = np.ascontiguousarray(fields, dtype=np.float64).reshape(4, self.total)
-        self.fields = torch.as_tensor(f).to(self.dev).to(self.dtype).reshape(-1).contiguous()
+        npdt = np.float32 if self.dtype == torch.float32 else np.float64
+        f = np.ascontiguousarray(np.asarray(fields).reshape(4, self.total), dtype=npdt)
+        self.fields = torch.as_tensor(f).to(self.dev).reshape(-1).contiguous()
 
     def allocate(self, capacity: int):
         self.buf = StepBuffers(self.dev, self.total, capacity, self.dtype)

@@ -368,7 +368,150 @@ def c1_small(steps=4, seed=11) -> Workload:
                        omega=0.05, cells_per_step=0.7)
 
 
-CONFIGS = {"C0": c0, "C1": c1, "C2": c2, "C1-small": c1_small}
+# ---------------------------------------------------------------- school of fish
+# Body-frame semi-axes (axial x, lateral y, vertical z) in fish lengths L:
+# the body (inner shell surface), the blank region cut from every other grid,
+# and the outer shell surface.
+FISH_BODY = (0.5, 0.07, 0.12)
+FISH_BLANK = (0.65, 0.22, 0.18)
+FISH_OUTER = (0.95, 0.45, 0.38)
+# Diamond: front fish, two side fish (lateral +-0.45 L, 1.2 L behind) and
+# the last fish 2.4 L behind (the paper's side offset; a shorter axial
+# spacing than its 1.45 L so that neighbouring shells overlap and exchange
+# fringe points).
+DIAMOND = ((0.0, 0.0), (-1.2, 0.45), (-1.2, -0.45), (-2.4, 0.0))
+
+
+def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixed",
+                extent=(1.5, 1.0, 1.0), diamonds=((0.95, 0.5, 0.3), (0.95, 0.5, 0.7)), dt=1.0 / 240.0) -> Workload:
+    """Stretched background on [0,1.5]x[0,1]^2 and two diamonds of four
+    fish-like ellipsoidal shells (polar axis along the swimming direction x).
+    shell_dims: (N_r, N_phi, N_theta) of the four positions of a diamond.
+    Motion of fish g at time t = step * dt (frequency 1): heave
+    0.1 L sin(2 pi t + a_g) along y, yaw 0.2 sin(2 pi t + b_g) about z,
+    translation U_g t along x with U_g in [0.1, 0.3] L per unit time.
+    Draw order from default_rng(seed): for each fish a_g, b_g, U_g; then the
+    Fourier modes of u, v, w, p."""
+    rng = np.random.default_rng(seed)
+    bg = stretched_background(bg_dims, extent=extent)
+    grids = [bg]
+    centres = []
+    for dc in diamonds:
+        for (dx, dy), dims in zip(DIAMOND, shell_dims):
+            g = ellipsoidal_shell(*dims, tuple(L * a for a in FISH_BODY), tuple(L * a for a in FISH_OUTER),
+                                  name=f"fish{len(grids)}")
+            g.blank_kind = BLANK_ELLIPSOID
+            g.blank_prm = tuple(L * a for a in FISH_BLANK)
+            g.outer = (0, nf, 0, 0, 0, 0)
+            grids.append(g)
+            centres.append((dc[0] + dx * L, dc[1] + dy * L, dc[2]))
+    motion = [(rng.uniform(0, 2 * math.pi), rng.uniform(0, 2 * math.pi), rng.uniform(0.1, 0.3)) for _ in centres]
+    poses = np.empty((steps, len(grids), 12))
+    for t in range(steps):
+        tt = t * dt
+        poses[t, 0] = IDENTITY_POSE
+        for g, (c, (a, b, U)) in enumerate(zip(centres, motion)):
+            yaw = 0.2 * math.sin(2 * math.pi * tt + b)
+            heave = 0.1 * L * math.sin(2 * math.pi * tt + a)
+            poses[t, g + 1] = pose12(rot_z(yaw), (c[0] + U * L * tt, c[1] + heave, c[2]))
+    modes = [fourier_modes(rng) for _ in range(4)]
+    fields = _fields_from(grids, poses[0], lambda x, y, z: [eval_modes(m, x, y, z) for m in modes])
+    return Workload(name, grids, nf=nf, steps=steps, poses=poses, fields=fields, precision=precision,
+                    meta={"seed": seed, "L": L, "body": FISH_BODY, "blank": FISH_BLANK, "outer": FISH_OUTER,
+                          "diamond": DIAMOND, "motion": motion})
+
+
+def c3(steps=200) -> Workload:
+    """384x256x256 stretched background, 8 fish shells of uneven sizes (two
+    each of 64^3, 96x64x64, 128x96x64, 160x96x96), L = 0.25, 200 steps,
+    mixed precision, seed 3."""
+    return school_case("C3", (384, 256, 256), ((160, 96, 96), (128, 96, 64), (96, 64, 64), (64, 64, 64)),
+                       0.25, steps, seed=3)
+
+
+def c3_small(steps=4, precision="fp64") -> Workload:
+    """A scaled-down school for parity tests: 128x96x96 background, shells
+    of 12-24 layers, faster motion (dt = 1/24)."""
+    return school_case("C3-small", (128, 96, 96), ((24, 24, 20), (20, 20, 16), (16, 20, 16), (12, 16, 12)),
+                       0.25, steps, seed=33, precision=precision, dt=1.0 / 24.0)
+
+
+# ---------------------------------------------------------------- many random shells
+def shells_case(name, bg_n, nshells, steps, seed, nf=3, dims_lo=(48, 48, 48), dims_hi=(192, 128, 128),
+                precision="mixed", period=100.0, field_dtype=np.float32, r1_range=(0.04, 0.07)) -> Workload:
+    """Stretched, perturbed bg_n^3 background on [0,1]^3 and `nshells`
+    spherical shells. Per shell, drawn from default_rng(seed) in this order:
+    N_r, N_phi, N_theta (uniform integers in dims_lo..dims_hi); outer radius
+    r1 ~ U[r1_range] (default 0.04..0.07); inner radius r0 = r1 * U[0.3, 0.45]; the centre,
+    uniform in [0.12, 0.88]^3 and redrawn while it is closer than
+    0.8 (r1 + r1') to an earlier centre; a rotation axis (3 normals); a
+    tangential speed at r1 ~ U[0.2, 0.5] cells/step; a translation direction
+    (3 normals); a peak translation speed ~ U[0.2, 0.5] cells/step. The body
+    r < r0 is cut from the other grids. Motion: steady rotation, translation
+    oscillating with `period` steps. Fields (closed form, FP32 by default):
+    u = 1 + 2x - 3y + z/2, v = sin(2 pi x) cos(2 pi y), w = cos(2 pi z),
+    p = x y z at t=0 node positions."""
+    rng = np.random.default_rng(seed)
+    cell = 1.0 / (bg_n - 1)
+    grids = [stretched_background((bg_n, bg_n, bg_n))]
+    spec = []
+    for g in range(nshells):
+        dims = tuple(int(rng.integers(lo, hi + 1)) for lo, hi in zip(dims_lo, dims_hi))
+        r1 = rng.uniform(*r1_range)
+        r0 = r1 * rng.uniform(0.3, 0.45)
+        while True:
+            c = rng.uniform(0.12, 0.88, 3)
+            if all(np.linalg.norm(c - c2) >= 0.8 * (r1 + r12) for (_, _, r12, c2, *_rest) in spec):
+                break
+        axis = rng.normal(size=3)
+        omega = rng.uniform(0.2, 0.5) * cell / r1
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        amp = rng.uniform(0.2, 0.5) * cell * period / (2 * math.pi)
+        spec.append((dims, r0, r1, c, axis, omega, d, amp))
+        sh = spherical_shell(*dims, r0, r1, name=f"shell{g + 1}")
+        sh.blank_kind = BLANK_SPHERE
+        sh.blank_prm = (r0,)
+        sh.outer = (0, nf, 0, 0, 0, 0)
+        grids.append(sh)
+    poses = np.empty((steps, len(grids), 12))
+    for t in range(steps):
+        poses[t, 0] = IDENTITY_POSE
+        for g, (dims, r0, r1, c, axis, omega, d, amp) in enumerate(spec):
+            poses[t, g + 1] = pose12(rodrigues(axis, omega * t), c + amp * math.sin(2 * math.pi * t / period) * d)
+    total = sum(gr.nodes for gr in grids)
+    fields = np.empty((4, total), dtype=field_dtype)
+    o = 0
+    for gr, p in zip(grids, poses[0]):
+        n = gr.nodes
+        for a in range(0, n, 1 << 24):
+            b = min(n, a + (1 << 24))
+            sub = Grid(gr.name, (b - a, 1, 1), 0, gr.X[a:b], gr.Y[a:b], gr.Z[a:b])
+            x, y, z = world_coords(sub, p)
+            fields[0, o + a:o + b] = 1.0 + 2.0 * x - 3.0 * y + 0.5 * z
+            fields[1, o + a:o + b] = np.sin(2 * math.pi * x) * np.cos(2 * math.pi * y)
+            fields[2, o + a:o + b] = np.cos(2 * math.pi * z)
+            fields[3, o + a:o + b] = x * y * z
+        o += n
+    return Workload(name, grids, nf=nf, steps=steps, poses=poses, fields=fields, precision=precision,
+                    meta={"seed": seed, "shells": [(s_[0], s_[1], s_[2], s_[3].tolist()) for s_ in spec]})
+
+
+def c4(steps=500) -> Workload:
+    """512^3 background, 16 spherical shells from 48^3 to 192x128x128 (seed 4),
+    up to 0.5 cell/step of motion, 3 fringe layers, FP32 fields, 500 steps."""
+    return shells_case("C4", 512, 16, steps, seed=4)
+
+
+def c4_small(steps=4, precision="fp64") -> Workload:
+    """A scaled-down C4 for parity tests: 96^3 background, 5 shells of 12-24
+    nodes per direction and outer radius 0.1..0.16."""
+    return shells_case("C4-small", 96, 5, steps, seed=44, dims_lo=(12, 12, 9), dims_hi=(24, 24, 17),
+                       precision=precision, field_dtype=np.float64, r1_range=(0.1, 0.16))
+
+
+CONFIGS = {"C0": c0, "C1": c1, "C2": c2, "C1-small": c1_small, "C3": c3, "C3-small": c3_small,
+           "C4": c4, "C4-small": c4_small}
 
 
 def build(name: str, **kw) -> Workload:
