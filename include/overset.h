@@ -100,7 +100,7 @@ enum ov_blank_kind {
 enum ov_option {
     OV_OPT_WARM = 1,        /* 1 (default): seed the walk from the previous step's donor; 0: cold */
     OV_OPT_MAX_WALK = 2,    /* walk steps before the brute-force fallback (default 64, >= 1) */
-    OV_OPT_SEARCH_BLOCK = 3,/* threads per block of the donor search (64..1024, multiple of 64) */
+    OV_OPT_SEARCH_BLOCK = 3,/* threads per block of the donor search walk (64..256, multiple of 64) */
     OV_OPT_INTERP_BLOCK = 4,/* threads per block of the interpolation (64..1024, multiple of 64) */
     OV_OPT_HOLECUT_BLOCK = 5,/* threads per block of the hole cut (64..1024, multiple of 64) */
     OV_OPT_HOLECUT_NPT = 6, /* 16-byte coordinate vectors per lane per chunk of the hole cut (1, 2 or 4) */

@@ -369,10 +369,16 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_warm_cell);
   (void)hipFree(ctx->d_warm_grid);
   (void)hipFree(ctx->d_tile_sphere);
+  (void)hipFree(ctx->d_stamp);
+  (void)hipFree(ctx->d_tile_mask);
   (void)hipFree(ctx->d_tile_hole);
-  (void)hipFree(ctx->d_scanq);
-  (void)hipFree(ctx->d_scanq_count);
-  (void)hipFree(ctx->d_scanq_ticket);
+  (void)hipFree(ctx->d_tile_near);
+  (void)hipFree(ctx->d_near_list);
+  (void)hipFree(ctx->d_near_count);
+  (void)hipFree(ctx->d_chunk_static);
+  (void)hipFree(ctx->d_chunk_stamp);
+  (void)hipFree(ctx->d_chunk_list);
+  (void)hipFree(ctx->d_chunk_list_count);
   (void)hipFree(ctx->d_chunk_counts);
   (void)hipFree(ctx->d_chunk_offsets);
   delete ctx;
@@ -478,19 +484,34 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)std::min(nt, 65536LL)), dim3(256), 0, s, g.d,
                        ctx->d_tile_sphere + g.d.tile_off);
   }
-  HIPCHK(hipMalloc(&ctx->d_tile_hole, std::max(1LL, ctx->total_tiles)), "hipMalloc tile map");
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(ctx->total_tiles)), dim3(256), 0, s, ctx->d_tile_hole,
-                     ctx->total_tiles, (uint8_t)0);
-  ctx->scanq_cap = 65536;
-  HIPCHK(hipMalloc(&ctx->d_scanq, sizeof(int2) * ctx->scanq_cap), "hipMalloc scan queue");
-  HIPCHK(hipMalloc(&ctx->d_scanq_count, sizeof(int)), "hipMalloc scan queue count");
-  HIPCHK(hipMalloc(&ctx->d_scanq_ticket, sizeof(unsigned int)), "hipMalloc scan ticket");
-  HIPCHK(hipMemsetAsync(ctx->d_scanq_count, 0, sizeof(int), s), "scan queue init");
-  HIPCHK(hipMemsetAsync(ctx->d_scanq_ticket, 0, sizeof(unsigned int), s), "scan ticket init");
+  // front-half scratch (stamps start at 0: "never listed")
+  const long long nt = std::max(1LL, ctx->total_tiles);
+  HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int)), "hipMalloc stamp");
+  HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * nt), "hipMalloc tile masks");
+  HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * nt), "hipMalloc tile holes");
+  HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
+  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * nt), "hipMalloc near list");
+  HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t)), "hipMalloc near count");
+  HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int), s), "stamp init");
+  HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * nt, s), "tile hole init");
+  HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
+  HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t), s), "near count init");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
-  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk counts");
-  HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * ctx->nchunks), "hipMalloc chunk offsets");
+  const long long nch4 = 4 * ((ctx->nchunks + 3) / 4);
+  HIPCHK(hipMalloc(&ctx->d_chunk_static, ctx->nchunks), "hipMalloc static chunk marks");
+  HIPCHK(hipMalloc(&ctx->d_chunk_stamp, sizeof(unsigned int) * ctx->nchunks), "hipMalloc chunk stamps");
+  HIPCHK(hipMalloc(&ctx->d_chunk_list, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk list");
+  HIPCHK(hipMalloc(&ctx->d_chunk_list_count, sizeof(int32_t)), "hipMalloc chunk list count");
+  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * nch4), "hipMalloc chunk counts");
+  HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * (nch4 + 1)), "hipMalloc chunk offsets");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_stamp, 0, sizeof(unsigned int) * ctx->nchunks, s), "chunk stamp init");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_list_count, 0, sizeof(int32_t), s), "chunk list count init");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(int32_t) * nch4, s), "chunk count init");
   HIPCHK(hipGetLastError(), "finalize kernels");
+  {
+    int rc = build_static_chunks(ctx, s);
+    if (rc != OV_OK) return rc;
+  }
   HIPCHK(hipStreamSynchronize(s), "finalize sync");
   ctx->finalized = true;
   return OV_OK;
@@ -518,7 +539,7 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       ctx->max_walk = (int)v;
       return OV_OK;
     case OV_OPT_SEARCH_BLOCK:
-      if (!block_ok(v)) break;
+      if (!block_ok(v) || v > 256) break;
       ctx->search_block = (int)v;
       return OV_OK;
     case OV_OPT_INTERP_BLOCK:

@@ -85,13 +85,23 @@ struct ov_ctx {
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
   double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
-  uint8_t* d_tile_hole = nullptr;  // per fringe tile: holds a hole (set by the hole cut, cleared by compaction)
-  int2* d_scanq = nullptr;         // queries whose walk fell back to the brute-force scan
-  int* d_scanq_count = nullptr;    // emptied by the last block of the scan phase
-  unsigned int* d_scanq_ticket = nullptr;
-  int scanq_cap = 0;
-  int32_t* d_chunk_counts = nullptr;
-  long long* d_chunk_offsets = nullptr;
+  // Front-half scratch, written and read in stream order by the hole cut,
+  // the fringe pass and the compaction. Each hole cut starts a new stamp; a
+  // tile or chunk is on this step's list when its entry equals the stamp, so
+  // nothing needs clearing between steps.
+  unsigned int* d_stamp = nullptr;            // current stamp (device)
+  unsigned long long* d_tile_mask = nullptr;  // per tile: blank regions (bit = grid) that may reach it
+  unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
+  unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
+  int32_t* d_near_list = nullptr;             // tiles that may hold buffer nodes (a hole within kMaxNf)
+  int32_t* d_near_count = nullptr;
+  uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
+  unsigned int* d_chunk_stamp = nullptr;      // per chunk: stamp if on this step's chunk list
+  int32_t* d_chunk_list = nullptr;            // chunks that may hold query nodes: the static ones, then this step's
+  int32_t* d_chunk_list_count = nullptr;      // length of this step's part
+  long long n_static_chunks = 0;
+  int32_t* d_chunk_counts = nullptr;          // padded to a multiple of 4; zero outside the listed chunks
+  long long* d_chunk_offsets = nullptr;       // padded length + 1
   long long nchunks = 0;
   // options
   int warm = 1;
@@ -114,6 +124,7 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 // launchers (kernel files)
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s);
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s);
+int build_static_chunks(ov_ctx* ctx, hipStream_t s);
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
                           long long capacity, long long* d_count, hipStream_t s);
 hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_grid, const int32_t* q_node,

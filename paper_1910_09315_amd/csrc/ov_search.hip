@@ -15,10 +15,14 @@
 //
 // Precision: the natural-coordinate solve runs in T. With T = float (mixed
 // precision) every offset is formed in FP64 from FP64 corners and only then
-// rounded, so the FP32 solve sees cell-local quantities; a result is kept
-// only if its FP32 margin to every face is >= 1e-4 and the cell's Jacobian
-// condition estimate is <= 1e3, otherwise the walk continues in FP64 from
-// that cell (the FP64 correction).
+// rounded, so the FP32 solve sees cell-local quantities. The query position
+// of an overset node comes from the FP32 transform and carries its rounding
+// error e (bounded per component from |qx|); a result is kept only if its
+// FP32 margin to every face is >= 1e-4 plus that error carried into natural
+// coordinates (2 sqrt(3) e ||J^-1||_F) and the cell's Jacobian condition
+// estimate is <= 1e3. Otherwise the walk continues in FP64 from that cell
+// (the FP64 correction), on the position recomputed in FP64 from the FP64
+// node coordinates; the brute-force scans also use that exact position.
 #include <hip/hip_runtime.h>
 
 #include "ov_internal.h"
@@ -99,8 +103,9 @@ __device__ __forceinline__ T det3(const T J[3][3]) {
 // the last step is <= tol (and, in FP64, |det J| >= kDetMin at the result).
 // *cond receives ||J||_F ||J^-1||_F at the result (an upper bound of the
 // 2-norm condition number).
+// *inv_norm receives ||J^-1||_F at the result.
 template <typename T>
-__device__ bool newton(const CellMap<T>& m, T s[3], T* cond) {
+__device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullptr) {
   const T tol = sizeof(T) == 8 ? (T)kNewtonTol : (T)kNewtonTolF;
   const int maxit = sizeof(T) == 8 ? kNewtonMaxIt : kNewtonMaxItF;
   s[0] = s[1] = s[2] = (T)0.5;
@@ -143,6 +148,7 @@ __device__ bool newton(const CellMap<T>& m, T s[3], T* cond) {
             na += cf * cf;
           }
         *cond = sqrt(nj) * sqrt(na) / fabs(dt);
+        if (inv_norm) *inv_norm = sqrt(na) / fabs(dt);
       }
       return true;
     }
@@ -183,9 +189,10 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
 
 // Stencil walk in precision T from `cell`. On kFound, cell/s hold the donor.
 // On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
+// perr bounds the error of each component of xi (FP32 only; 0 when exact).
 template <typename T>
-__device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3], int max_walk,
-                    bool& limit, int& visited) {
+__device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
+                    int max_walk, bool& limit, int& visited) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   int hist[4] = {-1, -1, -1, -1};  // the last cells visited: a revisit ends the walk
@@ -193,8 +200,8 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
     ++visited;
     CellMap<T> m;
     load_cell<T>(G, ci, cj, ck, xi, m);
-    T cond = 0;
-    bool conv = newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr);
+    T cond = 0, inv_norm = 0;
+    bool conv = newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr, sizeof(T) == 4 ? &inv_norm : (T*)nullptr);
     const int here = (int)(ci + (long long)G.nci * (cj + (long long)G.ncj * ck));
     if (sizeof(T) == 4) {
       // FP32 decides only clear cases: inside with margin >= 1e-4 in a
@@ -206,11 +213,13 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], int
         return kDoubt;
       }
       const bool sure = conv && cond <= (T)kMixedCond;
-      if (sure && mg >= (T)kMixedMargin) {
+      // the position error in natural coordinates: |ds|_inf <= ||J^-1||_2 |e|_2
+      const T es = (T)(2.0 * 1.7320508075688772 * perr) * inv_norm;
+      if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
         return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
       }
-      if (mg > -(sure ? (T)kMixedMargin : (T)kClearlyOutside)) {
+      if (mg > -((sure ? (T)kMixedMargin : (T)kClearlyOutside) + es)) {
         cell = here;
         return kDoubt;
       }
@@ -294,39 +303,6 @@ __device__ __forceinline__ bool hull_excludes(const double P[8][3], const double
   return false;
 }
 
-// Brute-force scan of the control cell holding xi (FP64): lowest valid
-// containing cell, or -1. Control-cell lists are sorted by cell index, so
-// the first valid containing cell met is the lowest.
-__device__ int scan_control_cell(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
-  long long b = bin_axis(G, 0, xi[0]) +
-                (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
-  long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
-  for (long long e = e0; e < e1; ++e) {
-    int cell = G.bcells[e];
-    int ci, cj, ck;
-    cell_ijk(G, cell, ci, cj, ck);
-    double P[8][3];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      long long nd = corner_node(G, ci, cj, ck, c);
-      P[c][0] = G.X[nd];
-      P[c][1] = G.Y[nd];
-      P[c][2] = G.Z[nd];
-    }
-    if (hull_excludes(P, xi)) continue;
-    CellMap<double> m;
-    map_from_corners<double>(P, xi, m);
-    double s[3];
-    if (!newton<double>(m, s, nullptr) || !inside<double>(s, kSTol)) continue;
-    if (!cell_valid(G, fl, ci, cj, ck)) continue;
-    s_best[0] = s[0];
-    s_best[1] = s[1];
-    s_best[2] = s[2];
-    return cell;
-  }
-  return -1;
-}
-
 // Candidate donor grid at position t of a query of grid A: t = -2 the cause
 // grid, t = -1 the background, t >= 0 grid t; -1 where that position is
 // skipped (Sec. 2.4 item 1).
@@ -339,49 +315,82 @@ __device__ __forceinline__ int candidate_at(int t, int A, int first) {
 
 struct Query {
   int A, cause, first;
-  long long key;
+  long long key, m;
   double x[3];
+  double err;  // bound on the error of each component of x (0: x is exact)
   bool finite;
 };
 
+// Inertial position of node m of grid A, in FP64 from its FP64 coordinates.
+__device__ __forceinline__ void exact_world(const GridDev& GA, const double* pa, long long m, double x[3]) {
+  double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
+  x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
+  x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
+  x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
+}
+
+// exact = true takes the position from the FP64 node coordinates even where
+// the transform's output is FP32.
 template <typename T>
 __device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
                                             const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
                                             const int32_t* __restrict__ q_node, const T* __restrict__ qx,
-                                            long long cap, long long q) {
+                                            long long cap, long long q, bool exact = false) {
   Query Q;
   Q.A = q_grid[q];
-  const long long m = q_node[q];
+  Q.m = q_node[q];
   const GridDev& GA = grids[Q.A];
-  Q.key = GA.node_off + m;
+  Q.key = GA.node_off + Q.m;
   Q.cause = flags[Q.key] >> 2;
   Q.first = (Q.cause != OV_CAUSE_BOUNDARY && Q.cause != Q.A && Q.cause < ngrids) ? Q.cause : -1;
   const double* pa = sp + 12 * Q.A;
-  if (sizeof(T) == 4 && Q.A == 0) {
-    // the background's offsets are absolute positions; take them in FP64
-    double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
-    Q.x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
-    Q.x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
-    Q.x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
+  Q.err = 0.0;
+  if (sizeof(T) == 4 && (exact || Q.A == 0)) {
+    // the background's offsets are absolute positions (large, so FP32 would
+    // lose most of a cell); take them in FP64
+    exact_world(GA, pa, Q.m, Q.x);
   } else {
-    Q.x[0] = pa[9] + (double)qx[q];
-    Q.x[1] = pa[10] + (double)qx[cap + q];
-    Q.x[2] = pa[11] + (double)qx[2 * cap + q];
+    const double o0 = (double)qx[q], o1 = (double)qx[cap + q], o2 = (double)qx[2 * cap + q];
+    Q.x[0] = pa[9] + o0;
+    Q.x[1] = pa[10] + o1;
+    Q.x[2] = pa[11] + o2;
+    // FP32 transform from FP32 coordinates and pose: a few roundings of
+    // terms no larger than |X|_1 <= sqrt(3) |qx|_2 <= sqrt(3) |qx|_1 each
+    if (sizeof(T) == 4) Q.err = ldexp(fabs(o0) + fabs(o1) + fabs(o2), -20);
   }
   Q.finite = isfinite(Q.x[0]) && isfinite(Q.x[1]) && isfinite(Q.x[2]);
   return Q;
 }
 
-// Query position in grid B's body frame; false if outside the box of B's nodes.
-__device__ __forceinline__ bool to_body(const GridDev& G, const double* pb, const double x[3], double xi[3]) {
+__device__ __forceinline__ void body_frame(const double* pb, const double x[3], double xi[3]) {
   double d0 = x[0] - pb[9], d1 = x[1] - pb[10], d2 = x[2] - pb[11];
   xi[0] = pb[0] * d0 + pb[3] * d1 + pb[6] * d2;
   xi[1] = pb[1] * d0 + pb[4] * d1 + pb[7] * d2;
   xi[2] = pb[2] * d0 + pb[5] * d1 + pb[8] * d2;
+}
+
+// Query position in grid B's body frame; false if outside the box of B's
+// nodes (padded by the position's error bound).
+__device__ __forceinline__ bool to_body(const GridDev& G, const double* pb, const Query& Q, double xi[3]) {
+  body_frame(pb, Q.x, xi);
   double ext = fmax(G.bhi[0] - G.blo[0], fmax(G.bhi[1] - G.blo[1], G.bhi[2] - G.blo[2]));
-  double pad = 1e-8 * ext;
+  double pad = 1e-8 * ext + 2.0 * Q.err;
   return !(xi[0] < G.blo[0] - pad || xi[0] > G.bhi[0] + pad || xi[1] < G.blo[1] - pad || xi[1] > G.bhi[1] + pad ||
            xi[2] < G.blo[2] - pad || xi[2] > G.bhi[2] + pad);
+}
+
+// The exact FP64 position in B's frame (xi itself when it is already exact).
+__device__ __forceinline__ void exact_body(const GridDev* grids, const double* sp, const Query& Q, int B,
+                                           const double xi[3], double xe[3]) {
+  if (Q.err == 0.0) {
+    xe[0] = xi[0];
+    xe[1] = xi[1];
+    xe[2] = xi[2];
+    return;
+  }
+  double x[3];
+  exact_world(grids[Q.A], sp + 12 * Q.A, Q.m, x);
+  body_frame(sp + 12 * B, x, xe);
 }
 
 __device__ __forceinline__ long long bin_of(const GridDev& G, const double xi[3]) {
@@ -389,15 +398,19 @@ __device__ __forceinline__ long long bin_of(const GridDev& G, const double xi[3]
          (long long)G.nb[0] * (bin_axis(G, 1, xi[1]) + (long long)G.nb[1] * bin_axis(G, 2, xi[2]));
 }
 
-// Walk in grid B from `seed` (FP32 first in mixed precision, then FP64 from
-// any cell FP32 cannot decide). Returns kFound with cell/s, else kToScan.
+// Walk in grid B from `seed` (FP32 first in mixed precision, then FP64 on the
+// exact position from any cell FP32 cannot decide). Returns kFound with
+// cell/s, else kToScan.
 template <typename T>
-__device__ __forceinline__ int walk_grid(const GridDev& G, const uint8_t* fl, const double xi[3], int& cell, T s[3],
-                                         int max_walk, bool& limit, int& how, int& visited) {
-  int r = walk<T>(G, fl, xi, cell, s, max_walk, limit, visited);
+__device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp, const Query& Q, int B,
+                                         const uint8_t* fl, const double xi[3], int& cell, T s[3], int max_walk,
+                                         bool& limit, int& how, int& visited) {
+  const GridDev& G = grids[B];
+  int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
   if (sizeof(T) == 4 && r == kDoubt) {
-    double s64[3];
-    r = walk<double>(G, fl, xi, cell, s64, max_walk, limit, visited);
+    double s64[3], xe[3];
+    exact_body(grids, sp, Q, B, xi, xe);
+    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited);
     s[0] = (T)s64[0];
     s[1] = (T)s64[1];
     s[2] = (T)s64[2];
@@ -420,18 +433,26 @@ __device__ __forceinline__ void write_result(long long q, long long cap, long lo
   warm_cell[key] = cell;
 }
 
-// Phase 1: one query per lane. The walk runs per lane; a query whose walk
-// must fall back to the brute-force scan is queued (query, candidate
-// position) for phase 2, unless the queue is full (then it scans inline).
+// Markers left in donor_grid between the passes of one search call; status
+// then holds the candidate position t + 2 (bits 0-7) and the cells visited
+// so far (bits 8-15), donor_cell the cell to continue from.
+constexpr int kDeferFix = -2;   // FP32 could not decide: the FP64 correction continues
+constexpr int kDeferScan = -3;  // the walk failed: brute-force scan from candidate t
+
+__device__ __forceinline__ int defer_status(int t, int visited) { return (t + 2) | (min(visited, 255) << 8); }
+
+// Pass 1: one query per lane, the walk in T over the candidate grids. The
+// first grid whose walk finds a valid containing cell is the donor; a walk
+// FP32 cannot decide or that fails is deferred to the passes below, which
+// keep its place in the candidate order.
 template <typename T>
-__global__ void __launch_bounds__(1024)
-    k_donor_search(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
-                   const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
-                   const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
-                   long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
-                   T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
-                   uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status,
-                   int2* __restrict__ scanq, int* __restrict__ scanq_count, int scanq_cap) {
+__global__ void __launch_bounds__(256)
+    k_donor_walk(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+                 const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                 const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
+                 long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                 T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
+                 uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
   __syncthreads();
@@ -440,8 +461,8 @@ __global__ void __launch_bounds__(1024)
     const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q);
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
-    bool limit = false, deferred = false;
-    int visited = 0;
+    bool limit = false;
+    int visited = 0, defer = 0, defer_t = 0;
     if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
@@ -451,7 +472,7 @@ __global__ void __launch_bounds__(1024)
         if (B < 0) continue;
         const GridDev& G = grids[B];
         double xi[3];
-        if (!to_body(G, sp + 12 * B, Q.x, xi)) continue;
+        if (!to_body(G, sp + 12 * B, Q, xi)) continue;
         int seed = -1;
         if (wg == B) {
           int wc = warm_cell[Q.key];
@@ -461,38 +482,72 @@ __global__ void __launch_bounds__(1024)
           seed = G.brep[bin_of(G, xi)];
           if (seed < 0) continue;  // no cell reaches this control cell
         }
-        const uint8_t* fl = flags + G.node_off;
-        int cell = seed, how = OV_Q_FOUND;
+        int cell = seed;
         T s[3];
-        if (walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how, visited) != kFound) {
-          int slot = atomicAdd(scanq_count, 1);
-          if (slot < scanq_cap) {
-            scanq[slot] = make_int2((int)q, t);
-            deferred = true;
-            break;
-          }
-          double s64[3];
-          cell = scan_control_cell(G, fl, xi, s64);
-          s[0] = (T)s64[0];
-          s[1] = (T)s64[1];
-          s[2] = (T)s64[2];
-          how = OV_Q_FALLBACK;
-        }
-        if (cell >= 0) {
+        const int r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
+        if (r == kFound) {
           res_grid = B;
           res_cell = cell;
-          res_status = how;
+          res_status = OV_Q_FOUND;
           rs[0] = s[0];
           rs[1] = s[1];
           rs[2] = s[2];
-          break;
+        } else {
+          defer = r == kDoubt ? kDeferFix : kDeferScan;
+          defer_t = t;
+          res_cell = cell;
         }
+        break;
       }
     }
     if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-    if (!deferred)
+    if (defer) {
+      donor_grid[q] = defer;
+      donor_cell[q] = res_cell;
+      status[q] = defer_status(defer_t, visited);
+    } else {
       write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
                       donor_cell, s_out, status, warm_cell, warm_grid);
+    }
+  }
+}
+
+// Pass 2 (mixed precision): the FP64 correction. One query per lane; for each
+// query FP32 could not decide, the walk continues in FP64 from that cell on
+// the query's exact position (recomputed from the FP64 node coordinates).
+__global__ void __launch_bounds__(256)
+    k_donor_fix(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+                const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                const int32_t* __restrict__ q_node, const float* __restrict__ qx, const long long* __restrict__ d_count,
+                long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                float* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
+                uint8_t* __restrict__ warm_grid, int max_walk, int32_t* __restrict__ dev_status) {
+  __shared__ double sp[kMaxGrids * 12];
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  __syncthreads();
+  const long long n = min(*d_count, cap);
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+    if (donor_grid[q] != kDeferFix) continue;
+    const int st = status[q];
+    const int t = (st & 255) - 2;
+    int visited = (st >> 8) & 255;
+    const Query Q = load_query<float>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q, true);
+    const int B = candidate_at(t, Q.A, Q.first);
+    const GridDev& G = grids[B];
+    double xi[3], s64[3];
+    body_frame(sp + 12 * B, Q.x, xi);
+    int cell = donor_cell[q];
+    bool limit = false;
+    const int r = walk<double>(G, flags + G.node_off, xi, 0.0, cell, s64, max_walk, limit, visited);
+    if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+    if (r == kFound) {
+      const float sf[3] = {(float)s64[0], (float)s64[1], (float)s64[2]};
+      write_result<float>(q, cap, Q.key, B, cell, OV_Q_FOUND | OV_Q_FP64_FIXED | (min(visited, 255) << 8), sf,
+                          donor_grid, donor_cell, s_out, status, warm_cell, warm_grid);
+    } else {
+      donor_grid[q] = kDeferScan;
+      status[q] = defer_status(t, visited);
+    }
   }
 }
 
@@ -539,80 +594,83 @@ __device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const
   return -1;
 }
 
-// Phase 2: one wavefront per queued query. All lanes follow the same (uniform)
-// path: the cooperative scan of the grid whose walk failed, then the
-// remaining candidate grids (walk, and cooperative scan if needed).
+// Pass 3: the brute-force scan (Alg. 3's fallback). Each wavefront sweeps 64
+// queries and takes the deferred ones one at a time, all lanes together: the
+// cooperative scan of the grid whose walk failed, then the remaining
+// candidate grids (walk, and cooperative scan if needed), all on the exact
+// query position.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_donor_scan(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
                  const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
-                 const int32_t* __restrict__ q_node, const T* __restrict__ qx, long long cap,
-                 int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
-                 int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
-                 int max_walk, int32_t* __restrict__ dev_status, const int2* __restrict__ scanq,
-                 int* __restrict__ scanq_count, int scanq_cap, unsigned int* __restrict__ ticket) {
+                 const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
+                 long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                 T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
+                 uint8_t* __restrict__ warm_grid, int max_walk, int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int nq = min(*scanq_count, scanq_cap);
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nq; w += waves) {
-    const int2 item = scanq[w];
-    const long long q = item.x;
-    const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q);
-    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
-    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
-    bool limit = false;
-    int visited = 0;
-    for (int t = item.y; t < ngrids; ++t) {
-      const int B = candidate_at(t, Q.A, Q.first);
-      if (B < 0) continue;
-      const GridDev& G = grids[B];
-      double xi[3];
-      if (!to_body(G, sp + 12 * B, Q.x, xi)) continue;
-      const uint8_t* fl = flags + G.node_off;
-      int cell = -1, how = OV_Q_FALLBACK;
-      T s[3];
-      bool walked = false;
-      if (t != item.y) {
-        int seed = G.brep[bin_of(G, xi)];
-        if (seed < 0) continue;
-        cell = seed;
-        how = OV_Q_FOUND;
-        walked = walk_grid<T>(G, fl, xi, cell, s, max_walk, limit, how, visited) == kFound;
+  const long long n = min(*d_count, cap);
+  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long base = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < n;
+       base += waves * 64) {
+    const long long ql = base + lane;
+    const bool mine = ql < n && donor_grid[ql] == kDeferScan;
+    unsigned long long pend = __ballot(mine);
+    const int st_l = mine ? status[ql] : 0;
+    while (pend) {
+      const int src = __ffsll((long long)pend) - 1;
+      pend &= pend - 1;
+      const long long q = base + src;
+      const int st = __shfl(st_l, src, 64);
+      const int t0 = (st & 255) - 2;
+      int visited = (st >> 8) & 255;
+      const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q, true);
+      int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+      T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+      bool limit = false;
+      for (int t = t0; t < ngrids; ++t) {
+        const int B = candidate_at(t, Q.A, Q.first);
+        if (B < 0) continue;
+        const GridDev& G = grids[B];
+        double xi[3];
+        if (t == t0) body_frame(sp + 12 * B, Q.x, xi);  // the deferred grid passed the box test
+        else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+        const uint8_t* fl = flags + G.node_off;
+        int cell = -1, how = OV_Q_FALLBACK;
+        T s[3];
+        bool walked = false;
+        if (t != t0) {
+          int seed = G.brep[bin_of(G, xi)];
+          if (seed < 0) continue;
+          cell = seed;
+          how = OV_Q_FOUND;
+          walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, limit, how, visited) == kFound;
+        }
+        if (!walked) {
+          double s64[3];
+          cell = scan_control_cell_wave(G, fl, xi, s64);
+          s[0] = (T)s64[0];
+          s[1] = (T)s64[1];
+          s[2] = (T)s64[2];
+          how = OV_Q_FALLBACK;
+        }
+        if (cell >= 0) {
+          res_grid = B;
+          res_cell = cell;
+          res_status = how;
+          rs[0] = s[0];
+          rs[1] = s[1];
+          rs[2] = s[2];
+          break;
+        }
       }
-      if (!walked) {
-        double s64[3];
-        cell = scan_control_cell_wave(G, fl, xi, s64);
-        s[0] = (T)s64[0];
-        s[1] = (T)s64[1];
-        s[2] = (T)s64[2];
-        how = OV_Q_FALLBACK;
+      if (lane == 0) {
+        if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+        write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
+                        donor_cell, s_out, status, warm_cell, warm_grid);
       }
-      if (cell >= 0) {
-        res_grid = B;
-        res_cell = cell;
-        res_status = how;
-        rs[0] = s[0];
-        rs[1] = s[1];
-        rs[2] = s[2];
-        break;
-      }
-    }
-    if (lane == 0) {
-      if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-      write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
-                      donor_cell, s_out, status, warm_cell, warm_grid);
-    }
-  }
-  // the last block to finish empties the queue for the next call
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(ticket, 1u) == gridDim.x - 1) {
-      *scanq_count = 0;
-      *ticket = 0u;
     }
   }
 }
@@ -621,18 +679,23 @@ template <typename T>
 static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                             const int32_t* q_node, const T* qx, const long long* d_count, long long capacity,
                             int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, hipStream_t st) {
-  int block = ctx->search_block;
+  const int ng = (int)ctx->grids.size();
+  const int block = ctx->search_block;
   long long grid = grid_size_for(ctx, capacity, block);
-  int ng = (int)ctx->grids.size();
-  hipLaunchKernelGGL(k_donor_search<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
+  hipLaunchKernelGGL(k_donor_walk<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
                      q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell,
-                     ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, ctx->d_scanq, ctx->d_scanq_count,
-                     ctx->scanq_cap);
-  long long g2 = std::max(1LL, std::min<long long>((long long)ctx->num_cus * 2, (capacity + 3) / 4));
-  hipLaunchKernelGGL(k_donor_scan<T>, dim3((unsigned)g2), dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid,
-                     q_node, qx, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell, ctx->d_warm_grid,
-                     ctx->max_walk, ctx->d_status, (const int2*)ctx->d_scanq, ctx->d_scanq_count, ctx->scanq_cap,
-                     ctx->d_scanq_ticket);
+                     ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status);
+  // the sweeps: one lane (FP64 correction) or one wavefront per 64 queries (scan)
+  const long long sweep_cap = (long long)ctx->num_cus * 8;
+  if (sizeof(T) == 4)
+    hipLaunchKernelGGL(k_donor_fix, dim3((unsigned)std::max(1LL, std::min(sweep_cap, (capacity + 255) / 256))),
+                       dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid, q_node, (const float*)qx, d_count,
+                       capacity, donor_grid, donor_cell, (float*)s, status, ctx->d_warm_cell, ctx->d_warm_grid,
+                       ctx->max_walk, ctx->d_status);
+  hipLaunchKernelGGL(k_donor_scan<T>, dim3((unsigned)std::max(1LL, std::min(sweep_cap, (capacity + 255) / 256))),
+                     dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid, q_node, qx, d_count, capacity,
+                     donor_grid, donor_cell, s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->max_walk,
+                     ctx->d_status);
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

@@ -27,10 +27,9 @@ struct HoleLds {
   const void* X[kMaxGrids];
   const void* Y[kMaxGrids];
   const void* Z[kMaxGrids];
-  int blank[kMaxGrids];
   int kind[kMaxGrids];
   int outer[kMaxGrids];
-  int nblank;
+  unsigned long long allmask;  // every grid with a blank region
 };
 
 template <typename CT>
@@ -75,10 +74,10 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int nb = 0;
+    unsigned long long m = 0;
     for (int g = 0; g < ngrids; ++g)
-      if (L.kind[g] != OV_BLANK_NONE) L.blank[nb++] = g;
-    L.nblank = nb;
+      if (L.kind[g] != OV_BLANK_NONE) m |= 1ull << g;
+    L.allmask = m;
   }
   __syncthreads();
 }
@@ -107,11 +106,13 @@ __device__ __forceinline__ bool blank_inside_fp64(int kind, const double* prm, d
   return (u * u + v * v + w * w) < 1.0;
 }
 
-// FP64 decision for one node of grid A at world position w: first blanking grid or -1.
-__device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const double w[3]) {
-  for (int b = 0; b < L.nblank; ++b) {
-    int B = L.blank[b];
-    if (B == A) continue;
+// FP64 decision for one node of grid A at world position w: first blanking
+// grid (ascending grid id, among the bits of mask) or -1.
+__device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const double w[3], unsigned long long mask) {
+  mask &= ~(1ull << A);
+  while (mask) {
+    const int B = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
     const double* p = L.pose[B];
     double d0 = w[0] - p[9], d1 = w[1] - p[10], d2 = w[2] - p[11];
     if (d0 * d0 + d1 * d1 + d2 * d2 >= L.cull[B]) continue;
@@ -127,19 +128,20 @@ __device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const doubl
 // surface are decided again in FP64 from the FP64 coordinates.
 constexpr float kHoleGuard = 1e-3f;
 
-// Streaming hole cut: each thread loads the coordinates of NPT nodes (strided
-// by the block size, so every load instruction is coalesced) before testing
-// any of them, which keeps 3 * NPT loads per lane in flight.
+// Hole decision of one node of grid A: the blank regions of the grids in
+// mask (a superset of those that can contain it) are tested in ascending
+// grid id; the first that contains the node is its cause. In FP32, a node
+// within the guard band of a surface is decided again in FP64.
 template <typename CT>
 __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __restrict__ grids, int A, long long m,
-                                            CT X, CT Y, CT Z) {
+                                            CT X, CT Y, CT Z, unsigned long long mask) {
   const double* pa = L.pose[A];
   if (sizeof(CT) == 8) {
     double w[3];
     w[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
     w[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
     w[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
-    return holecut_fp64(L, A, w);
+    return holecut_fp64(L, A, w, mask);
   }
   const float* pf = L.posef[A];
   const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
@@ -148,9 +150,8 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
   float w2 = pf[6] * Xf + pf[7] * Yf + pf[8] * Zf + pf[11];
   bool unsure = false;
   int cause = -1;
-  for (int b = 0; b < L.nblank; ++b) {
-    int B = L.blank[b];
-    if (B == A) continue;
+  for (unsigned long long mm = mask & ~(1ull << A); mm; mm &= mm - 1) {
+    const int B = __ffsll((long long)mm) - 1;
     const float* p = L.posef[B];
     float d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
     if (d0 * d0 + d1 * d1 + d2 * d2 >= L.cullf[B]) continue;
@@ -174,7 +175,7 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     w[0] = pa[0] * Xd + pa[1] * Yd + pa[2] * Zd + pa[9];
     w[1] = pa[3] * Xd + pa[4] * Yd + pa[5] * Zd + pa[10];
     w[2] = pa[6] * Xd + pa[7] * Yd + pa[8] * Zd + pa[11];
-    cause = holecut_fp64(L, A, w);
+    cause = holecut_fp64(L, A, w, mask);
   }
   return cause;
 }
@@ -186,25 +187,26 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
 // store may alias anything, so fields read through a GridDev reference would
 // be re-loaded after every store).
 struct GeomR {
-  int ni, nj, nk, tiles_i, tiles_j;
+  int ni, nj, nk, per, tiles_i, tiles_j;
   int o0, o1, o2, o3, o4, o5;
   long long tile_off;
   __device__ __forceinline__ explicit GeomR(const GridDev& G)
-      : ni(G.ni), nj(G.nj), nk(G.nk), tiles_i(G.tiles_i), tiles_j(G.tiles_j), o0(G.outer[0]), o1(G.outer[1]),
-        o2(G.outer[2]), o3(G.outer[3]), o4(G.outer[4]), o5(G.outer[5]), tile_off(G.tile_off) {}
+      : ni(G.ni), nj(G.nj), nk(G.nk), per(G.per), tiles_i(G.tiles_i), tiles_j(G.tiles_j), o0(G.outer[0]),
+        o1(G.outer[1]), o2(G.outer[2]), o3(G.outer[3]), o4(G.outer[4]), o5(G.outer[5]), tile_off(G.tile_off) {}
   __device__ __forceinline__ bool on_outer(int i, int j, int k) const {
     return i < o0 || i >= ni - o1 || j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5;
   }
 };
 
-__device__ __forceinline__ uint8_t node_flag(const GeomR& G, long long m, int cause, uint8_t* tile_hole) {
+__device__ __forceinline__ uint8_t node_flag(const GeomR& G, long long m, int cause, unsigned int* tile_hole,
+                                             unsigned int stamp) {
   long long plane = (long long)G.ni * G.nj;
   int k = (int)(m / plane);
   long long r = m - (long long)k * plane;
   int j = (int)(r / G.ni);
   int i = (int)(r - (long long)j * G.ni);
   if (cause >= 0) {
-    tile_hole[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] = 1;
+    tile_hole[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] = stamp;
     return (uint8_t)(kHole | (cause << 2));
   }
   return G.on_outer(i, j, k) ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint8_t)OV_STATE_FIELD;
@@ -232,12 +234,14 @@ struct Vec16<float> {
 template <typename CT, int R>
 __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ grids, int ngrids,
                                                  const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                 long long total_chunks, uint8_t* __restrict__ tile_hole,
+                                                 long long total_chunks, unsigned int* __restrict__ tile_hole,
+                                                 const unsigned int* __restrict__ d_stamp,
                                                  unsigned long long* __restrict__ stats) {
   typedef typename Vec16<CT>::type V;
   constexpr int W = Vec16<CT>::W;
   __shared__ HoleLds L;
   __shared__ long long coff[kMaxGrids + 1];  // first chunk of each grid
+  const unsigned int stamp = *d_stamp;
   holecut_stage<CT>(L, grids, ngrids, poses);
   const long long span = (long long)blockDim.x * W * R;
   if (threadIdx.x == 0) {
@@ -294,8 +298,8 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         if (m + w >= nn) continue;
-        int cause = holecut_node<CT>(L, grids, A, m + w, X[r][w], Y[r][w], Z[r][w]);
-        fa[m + w] = (cause < 0 && !outerA) ? (uint8_t)OV_STATE_FIELD : node_flag(GR, m + w, cause, tile_hole);
+        int cause = holecut_node<CT>(L, grids, A, m + w, X[r][w], Y[r][w], Z[r][w], L.allmask);
+        fa[m + w] = (cause < 0 && !outerA) ? (uint8_t)OV_STATE_FIELD : node_flag(GR, m + w, cause, tile_hole, stamp);
       }
     }
   }
@@ -304,18 +308,148 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
 static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI * kTileJ * kTileK,
               "a 256-thread block covers a tile with 16 bytes per thread");
 
-// Hole cut over node tiles (kTileI x kTileJ x kTileK, one block per tile)
-// with culling: a tile whose bounding sphere, placed at its grid's pose,
-// cannot reach the bounding sphere of any other grid's blank region holds no
-// hole, so its coordinates are not read; its flags are still written (field,
-// or fringe on outer-boundary layers). Tiles that may be cut test every node
-// exactly as the streaming kernel does. The kernel also records, for every
-// tile, whether it holds a hole (the fringe pass reads that map).
+// Starts a step of the front half: a new stamp, empty near and chunk lists.
+// Later kernels of the hole cut read the stamp (stream order).
+__device__ __forceinline__ void k_begin_step_body(unsigned int* d_stamp, int32_t* near_count,
+                                                  int32_t* chunk_list_count) {
+  unsigned int v = *d_stamp + 1u;
+  *d_stamp = v == 0u ? 1u : v;  // 0 marks "never listed"
+  *near_count = 0;
+  *chunk_list_count = 0;
+}
+
+__global__ void k_begin_step(unsigned int* __restrict__ d_stamp, int32_t* __restrict__ near_count,
+                             int32_t* __restrict__ chunk_list_count) {
+  k_begin_step_body(d_stamp, near_count, chunk_list_count);
+}
+
+// Tile index along one axis holding the node `which` positions from tile t:
+// 0 = kMaxNf before its first node, 1 = one before, 2 = the tile itself,
+// 3 = one after its last node, 4 = kMaxNf after (wrapped on a periodic axis,
+// clipped otherwise). Buffer nodes lie within kMaxNf nodes of their hole,
+// so these tiles hold every buffer node of a hole in tile t, also where the
+// last tile of a periodic axis is thinner than kMaxNf.
+__device__ __forceinline__ int reach_tile(int t, int which, int n, int size, bool per) {
+  const int i0 = t * size, i1 = min(n, i0 + size) - 1;
+  int v = which == 0 ? i0 - kMaxNf : which == 1 ? i0 - 1 : which == 2 ? i0 : which == 3 ? i1 + 1 : i1 + kMaxNf;
+  if (per) {
+    v %= n;
+    if (v < 0) v += n;
+  } else {
+    v = min(max(v, 0), n - 1);
+  }
+  return v / size;
+}
+
+// Puts combination e (< 125) of the reach tiles of tile (ti, tj, tk) on the
+// near list, once per stamp.
+__device__ __forceinline__ void mark_near(int e, int ti, int tj, int tk, int ni, int nj, int nk, int per, int tiles_i,
+                                          int tiles_j, long long tile_off, unsigned int stamp,
+                                          unsigned int* __restrict__ tile_near, int32_t* __restrict__ near_list,
+                                          int32_t* __restrict__ near_count) {
+  const int x = reach_tile(ti, e % 5, ni, kTileI, per & 1);
+  const int y = reach_tile(tj, (e / 5) % 5, nj, kTileJ, per & 2);
+  const int z = reach_tile(tk, e / 25, nk, kTileK, per & 4);
+  const long long n = tile_off + x + (long long)tiles_i * (y + (long long)tiles_j * z);
+  if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = (int32_t)n;
+}
+
+// Which blank regions may reach each node tile (bit B set: grid B's region
+// may contain a node of the tile). The tile's bounding sphere, placed at its
+// grid's pose, is tested against the sphere about grid B's origin that
+// encloses B's region, then against the region's box in B's body frame
+// (distance from the sphere's centre to the box at most the radius). The
+// radius is padded far beyond FP64 rounding, so no node the exact test
+// would blank is ever culled. One thread per tile.
+__global__ void __launch_bounds__(256) k_tile_masks(const GridDev* __restrict__ grids, int ngrids,
+                                                   const double* __restrict__ poses,
+                                                   const double4* __restrict__ spheres, long long total_tiles,
+                                                   unsigned long long* __restrict__ tile_mask,
+                                                   unsigned int* __restrict__ d_stamp,
+                                                   int32_t* __restrict__ near_count,
+                                                   int32_t* __restrict__ chunk_list_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(d_stamp, near_count, chunk_list_count);
+  __shared__ double P[kMaxGrids][12];
+  __shared__ double box[kMaxGrids][6];
+  __shared__ double rad[kMaxGrids];
+  __shared__ long long toff[kMaxGrids + 1];
+  __shared__ unsigned long long blanks;
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) P[i / 12][i % 12] = poses[i];
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
+    const GridDev& G = grids[g];
+    toff[g] = G.tile_off;
+    rad[g] = sqrt(G.cull_r2);
+    const double* q = G.blank_prm;
+    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    if (G.blank_kind == OV_BLANK_CYL) {
+      lo[0] = lo[1] = -q[0];
+      hi[0] = hi[1] = q[0];
+      lo[2] = q[1];
+      hi[2] = q[2];
+    } else if (G.blank_kind == OV_BLANK_SPHERE) {
+      lo[0] = lo[1] = lo[2] = -q[0];
+      hi[0] = hi[1] = hi[2] = q[0];
+    } else if (G.blank_kind == OV_BLANK_ELLIPSOID) {
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = -q[d];
+        hi[d] = q[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      box[g][d] = lo[d];
+      box[g][3 + d] = hi[d];
+    }
+  }
+  if (threadIdx.x == 0) {
+    toff[ngrids] = total_tiles;
+    unsigned long long m = 0;
+    for (int g = 0; g < ngrids; ++g)
+      if (grids[g].blank_kind != OV_BLANK_NONE) m |= 1ull << g;
+    blanks = m;
+  }
+  __syncthreads();
+  for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
+       tile += (long long)gridDim.x * blockDim.x) {
+    const int A = grid_of_node(toff, ngrids, tile);
+    const double4 sp = spheres[tile];
+    const double* pa = P[A];
+    const double w0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
+    const double w1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
+    const double w2 = pa[6] * sp.x + pa[7] * sp.y + pa[8] * sp.z + pa[11];
+    unsigned long long mask = 0;
+    for (unsigned long long mm = blanks & ~(1ull << A); mm; mm &= mm - 1) {
+      const int B = __ffsll((long long)mm) - 1;
+      const double* p = P[B];
+      const double d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
+      const double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double r = sp.w + 1e-9 * (sp.w + dd + rad[B]) + 1e-12;
+      if (dd > rad[B] + r) continue;
+      const double x = p[0] * d0 + p[3] * d1 + p[6] * d2;
+      const double y = p[1] * d0 + p[4] * d1 + p[7] * d2;
+      const double z = p[2] * d0 + p[5] * d1 + p[8] * d2;
+      const double ex = fmax(fmax(box[B][0] - x, x - box[B][3]), 0.0);
+      const double ey = fmax(fmax(box[B][1] - y, y - box[B][4]), 0.0);
+      const double ez = fmax(fmax(box[B][2] - z, z - box[B][5]), 0.0);
+      if (ex * ex + ey * ey + ez * ez <= r * r) mask |= 1ull << B;
+    }
+    tile_mask[tile] = mask;
+  }
+}
+
+// Hole cut over node tiles (kTileI x kTileJ x kTileK, one block per tile at a
+// time). A tile that no blank region can reach (empty mask) holds no hole:
+// its coordinates are not read and its flags are written directly (field,
+// or fringe on outer-boundary layers). Other tiles test every node against
+// the regions in the tile's mask only. A tile that holds a hole puts the
+// tiles within buffer reach of it on the near list for the fringe pass.
 template <typename CT>
 __global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict__ grids, int ngrids,
                                                       const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                      const double4* __restrict__ spheres, long long total_tiles,
-                                                      uint8_t* __restrict__ tile_hole,
+                                                      const unsigned long long* __restrict__ tile_mask,
+                                                      long long total_tiles, const unsigned int* __restrict__ d_stamp,
+                                                      unsigned int* __restrict__ tile_near,
+                                                      int32_t* __restrict__ near_list,
+                                                      int32_t* __restrict__ near_count,
                                                       unsigned long long* __restrict__ stats) {
   __shared__ HoleLds L;
   __shared__ long long toff[kMaxGrids + 1];
@@ -323,44 +457,23 @@ __global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
   if (threadIdx.x == 0) toff[ngrids] = total_tiles;
   __syncthreads();
+  const unsigned int stamp = *d_stamp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
   for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    const unsigned long long mask = tile_mask[tile];
     const int A = grid_of_node(toff, ngrids, tile);
     const GeomR G(grids[A]);
     const int t = (int)(tile - toff[A]);
-    const int i0 = (t % G.tiles_i) * kTileI;
-    const int j0 = ((t / G.tiles_i) % G.tiles_j) * kTileJ;
-    const int k0 = (t / (G.tiles_i * G.tiles_j)) * kTileK;
-    // may any blank region reach this tile? (the same answer in every thread)
-    const double4 sp = spheres[tile];
-    const double* pa = L.pose[A];
-    const double wc0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
-    const double wc1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
-    const double wc2 = pa[6] * sp.x + pa[7] * sp.y + pa[8] * sp.z + pa[11];
-    bool cand = false;
-    for (int b = 0; b < L.nblank; ++b) {
-      const int B = L.blank[b];
-      if (B == A) continue;
-      const double* p = L.pose[B];
-      const double d0 = wc0 - p[9], d1 = wc1 - p[10], d2 = wc2 - p[11];
-      const double rr = (sqrt(L.cull[B]) + sp.w) * (1.0 + 1e-9) + 1e-12;
-      cand |= d0 * d0 + d1 * d1 + d2 * d2 <= rr * rr;
-    }
-    if (tile == blockIdx.x && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
-    if (cand && threadIdx.x == 0) {
-      unsigned long long n = (unsigned long long)min(kTileI, G.ni - i0) * min(kTileJ, G.nj - j0) * min(kTileK, G.nk - k0);
-      atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], n);
-    }
+    const int ti = t % G.tiles_i, tj = (t / G.tiles_i) % G.tiles_j, tk = t / (G.tiles_i * G.tiles_j);
+    const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
     uint8_t* fa = flags + L.off[A];
-    const CT* Xa = (const CT*)L.X[A];
-    const CT* Ya = (const CT*)L.Y[A];
-    const CT* Za = (const CT*)L.Z[A];
     const bool outer = L.outer[A] != 0;
     bool hole = false;
-    if (!cand) {
+    if (mask == 0) {
       // no hole possible: each thread writes 16 flag bytes of one tile row
       const int row = threadIdx.x >> 2, part = threadIdx.x & 3;
       const int i = i0 + part * 16, j = j0 + (row & 7), k = k0 + (row >> 3);
-      if (threadIdx.x < 256 && i < G.ni && j < G.nj && k < G.nk) {
+      if (i < G.ni && j < G.nj && k < G.nk) {
         const long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
         uint8_t* dst = fa + m;
         const int n = min(16, G.ni - i);
@@ -378,41 +491,77 @@ __global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict
         }
       }
     } else {
-    // 4 nodes per batch: their coordinates are loaded before any flag store
-    for (int e0 = threadIdx.x; e0 < kTileI * kTileJ * kTileK; e0 += 4 * blockDim.x) {
-      long long m[4];
-      bool ok[4], onb[4];
-      CT X[4], Y[4], Z[4];
+      if (threadIdx.x == 0) {
+        unsigned long long n =
+            (unsigned long long)min(kTileI, G.ni - i0) * min(kTileJ, G.nj - j0) * min(kTileK, G.nk - k0);
+        atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], n);
+      }
+      const CT* Xa = (const CT*)L.X[A];
+      const CT* Ya = (const CT*)L.Y[A];
+      const CT* Za = (const CT*)L.Z[A];
+      // 4 nodes per batch: their coordinates are loaded before any flag store
+      for (int e0 = threadIdx.x; e0 < kTileI * kTileJ * kTileK; e0 += 4 * blockDim.x) {
+        long long m[4];
+        bool ok[4], onb[4];
+        CT X[4], Y[4], Z[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = e0 + r * blockDim.x;
-        const int i = i0 + (e & 63), j = j0 + ((e >> 6) & 7), k = k0 + (e >> 9);
-        ok[r] = e < kTileI * kTileJ * kTileK && i < G.ni && j < G.nj && k < G.nk;
-        m[r] = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-        onb[r] = outer && G.on_outer(i, j, k);
-        if (cand && ok[r]) {
-          X[r] = Xa[m[r]];
-          Y[r] = Ya[m[r]];
-          Z[r] = Za[m[r]];
+        for (int r = 0; r < 4; ++r) {
+          const int e = e0 + r * blockDim.x;
+          const int i = i0 + (e & 63), j = j0 + ((e >> 6) & 7), k = k0 + (e >> 9);
+          ok[r] = e < kTileI * kTileJ * kTileK && i < G.ni && j < G.nj && k < G.nk;
+          m[r] = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+          onb[r] = outer && G.on_outer(i, j, k);
+          if (ok[r]) {
+            X[r] = Xa[m[r]];
+            Y[r] = Ya[m[r]];
+            Z[r] = Za[m[r]];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!ok[r]) continue;
+          const int cause = holecut_node<CT>(L, grids, A, m[r], X[r], Y[r], Z[r], mask);
+          uint8_t f = (uint8_t)OV_STATE_FIELD;
+          if (cause >= 0) {
+            f = (uint8_t)(kHole | (cause << 2));
+            hole = true;
+          } else if (onb[r]) {
+            f = (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2));
+          }
+          fa[m[r]] = f;
         }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (!ok[r]) continue;
-        const int cause = cand ? holecut_node<CT>(L, grids, A, m[r], X[r], Y[r], Z[r]) : -1;
-        uint8_t f = (uint8_t)OV_STATE_FIELD;
-        if (cause >= 0) {
-          f = (uint8_t)(kHole | (cause << 2));
-          hole = true;
-        } else if (onb[r]) {
-          f = (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2));
-        }
-        fa[m[r]] = f;
-      }
-    }
     }
     hole = __syncthreads_or(hole);
-    if (threadIdx.x == 0) tile_hole[tile] = hole ? 1 : 0;
+    if (hole && threadIdx.x < 125)
+      mark_near(threadIdx.x, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                near_list, near_count);
+  }
+}
+
+// Near list from the streaming hole cut's per-tile hole stamps: one thread per
+// tile; a tile holding a hole lists its 125 reach combinations.
+__global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restrict__ grids, int ngrids,
+                                                        const unsigned int* __restrict__ tile_hole,
+                                                        long long total_tiles, const unsigned int* __restrict__ d_stamp,
+                                                        unsigned int* __restrict__ tile_near,
+                                                        int32_t* __restrict__ near_list,
+                                                        int32_t* __restrict__ near_count) {
+  __shared__ long long toff[kMaxGrids + 1];
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
+  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
+  __syncthreads();
+  const unsigned int stamp = *d_stamp;
+  for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
+       tile += (long long)gridDim.x * blockDim.x) {
+    if (tile_hole[tile] != stamp) continue;
+    const int A = grid_of_node(toff, ngrids, tile);
+    const GeomR G(grids[A]);
+    const int t = (int)(tile - toff[A]);
+    const int ti = t % G.tiles_i, tj = (t / G.tiles_i) % G.tiles_j, tk = t / (G.tiles_i * G.tiles_j);
+    for (int e = 0; e < 125; ++e)
+      mark_near(e, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near, near_list,
+                near_count);
   }
 }
 
@@ -428,48 +577,55 @@ static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, h
   int ng = (int)ctx->grids.size();
   if (R == 4)
     hipLaunchKernelGGL((k_holecut<CT, 4>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
   else if (R == 2)
     hipLaunchKernelGGL((k_holecut<CT, 2>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
   else
     hipLaunchKernelGGL((k_holecut<CT, 1>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
 }
 
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+  const int ng = (int)ctx->grids.size();
+  const long long nt = ctx->total_tiles;
   if (ctx->cull) {
+    long long mb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
+    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)mb), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                       (const double4*)ctx->d_tile_sphere, nt, ctx->d_tile_mask, ctx->d_stamp, ctx->d_near_count,
+                       ctx->d_chunk_list_count);
     int per_cu = ctx->persist > 0 ? ctx->persist : 8;
-    long long grid = std::max(1LL, std::min(ctx->total_tiles, (long long)ctx->num_cus * per_cu));
-    int ng = (int)ctx->grids.size();
+    long long grid = std::max(1LL, std::min(nt, (long long)ctx->num_cus * per_cu));
     if (ctx->precision == OV_MIXED)
       hipLaunchKernelGGL(k_holecut_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                         flags, (const double4*)ctx->d_tile_sphere, ctx->total_tiles, ctx->d_tile_hole,
-                         ctx->d_stats);
+                         flags, ctx->d_tile_mask, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list,
+                         ctx->d_near_count, ctx->d_stats);
     else
       hipLaunchKernelGGL(k_holecut_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                         flags, (const double4*)ctx->d_tile_sphere, ctx->total_tiles, ctx->d_tile_hole,
-                         ctx->d_stats);
+                         flags, ctx->d_tile_mask, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list,
+                         ctx->d_near_count, ctx->d_stats);
     return hipGetLastError();
   }
+  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s);
   else launch_holecut_t<double>(ctx, poses, flags, s);
+  long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
+  hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, ng, ctx->d_tile_hole, nt,
+                     ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count);
   return hipGetLastError();
 }
 
 // ================================================================ fringe marking
-// The hole cut already wrote holes, the outer-boundary layers and, per 3D
-// tile of kTileI x kTileJ x kTileK nodes, whether the tile holds a hole.
-// Only tiles with a hole in themselves or a neighbour tile (nf < tile size,
-// so the buffer reaches no further) can gain buffer nodes: a block checks
-// the 27 map entries of its tile and leaves at once otherwise; near a hole it
-// stages the tile plus an nf halo in LDS as "cause if hole, 255 otherwise"
-// and takes the lowest cause within Chebyshev distance nf by a separable min
-// filter (i, then j, then k).
-// Holes are never rewritten, so updating flags in place is race-free: a
-// neighbour tile only reads whether a node is a hole.
-static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8, "tile indexing below uses shifts");
-
+// The hole cut wrote holes and the outer-boundary layers, and listed every
+// tile within buffer reach of a hole (the near list). Only those tiles can
+// gain buffer nodes: one block per listed tile stages the tile plus an nf
+// halo in LDS as "cause if hole, 255 otherwise" and takes the lowest cause
+// within Chebyshev distance nf by a separable min filter (i, then j, then
+// k). Holes are never rewritten, so updating flags in place is race-free: a
+// neighbour tile only reads whether a node is a hole. Each listed tile also
+// puts the compaction chunks holding its nodes on this step's chunk list
+// (chunks already on the static list, which hold outer-boundary nodes, are
+// always counted).
 __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
   if (v >= 0 && v < n) return v;
   if (!periodic) return -1;
@@ -477,51 +633,51 @@ __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
   return v < 0 ? v + n : v;
 }
 
-__device__ __forceinline__ int tile_grid(const GridDev* __restrict__ grids, int ngrids, long long tile) {
-  int lo = 0, hi = ngrids - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (grids[mid].tile_off <= tile) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ void tile_coords(const GridDev& G, long long tile, int& ti, int& tj, int& tk) {
-  long long t = tile - G.tile_off;
-  ti = (int)(t % G.tiles_i);
-  tj = (int)((t / G.tiles_i) % G.tiles_j);
-  tk = (int)(t / ((long long)G.tiles_i * G.tiles_j));
-}
-
 template <int NF>
 __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict__ grids, int ngrids,
-                                                     uint8_t* __restrict__ flags, const uint8_t* __restrict__ tile_hole,
-                                                     long long total_tiles) {
-  constexpr int EI = kTileI + 2 * NF, EJ = kTileJ + 2 * NF, EK = kTileK + 2 * NF;
-  constexpr int NROW = EJ * EK * 16, NHALO = EJ * EK * 2 * NF;
+                                                     uint8_t* __restrict__ flags, long long total_tiles,
+                                                     const int32_t* __restrict__ near_list,
+                                                     const int32_t* __restrict__ near_count,
+                                                     const unsigned int* __restrict__ d_stamp,
+                                                     const uint8_t* __restrict__ chunk_static,
+                                                     unsigned int* __restrict__ chunk_stamp,
+                                                     int32_t* __restrict__ chunk_list,
+                                                     int32_t* __restrict__ chunk_list_count, long long n_static) {
+  constexpr int H = NF > 0 ? NF : 1;  // LDS sizes (unused when NF = 0)
+  constexpr int EI = kTileI + 2 * H, EJ = kTileJ + 2 * H, EK = kTileK + 2 * H;
+  constexpr int NROW = EJ * EK * 16, NHALO = EJ * EK * 2 * H;
   __shared__ uint8_t a[EK][EJ][EI];
   __shared__ uint8_t b[EK][EJ][kTileI];
   __shared__ uint8_t c[EK][kTileJ][kTileI];
-  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    const GridDev& GD = grids[tile_grid(grids, ngrids, tile)];
-    int ti, tj, tk;
-    tile_coords(GD, tile, ti, tj, tk);
+  __shared__ long long toff[kMaxGrids + 1];
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
+  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
+  __syncthreads();
+  const int ntl = *near_count;
+  const unsigned int stamp = *d_stamp;
+  for (int idx = blockIdx.x; idx < ntl; idx += gridDim.x) {
+    const long long tile = near_list[idx];
+    const GridDev& GD = grids[grid_of_node(toff, ngrids, tile)];
     struct {
-      int ni, nj, nk, per, tiles_i, tiles_j, tiles_k;
-    } const G = {GD.ni, GD.nj, GD.nk, GD.per, GD.tiles_i, GD.tiles_j, GD.tiles_k};
-    const long long toff = GD.tile_off;
-    // a hole in this tile or a neighbour tile? (nf < tile size: nothing further matters)
-    bool near = false;
-    if (threadIdx.x < 27) {
-      int x = wrap_or_out(ti + (int)threadIdx.x % 3 - 1, G.tiles_i, G.per & 1);
-      int y = wrap_or_out(tj + ((int)threadIdx.x / 3) % 3 - 1, G.tiles_j, G.per & 2);
-      int z = wrap_or_out(tk + (int)threadIdx.x / 9 - 1, G.tiles_k, G.per & 4);
-      if (x >= 0 && y >= 0 && z >= 0) near = tile_hole[toff + x + (long long)G.tiles_i * (y + (long long)G.tiles_j * z)];
+      int ni, nj, nk, per, tiles_i, tiles_j;
+    } const G = {GD.ni, GD.nj, GD.nk, GD.per, GD.tiles_i, GD.tiles_j};
+    const long long noff = GD.node_off;
+    const int t = (int)(tile - GD.tile_off);
+    const int i0 = (t % G.tiles_i) * kTileI, j0 = ((t / G.tiles_i) % G.tiles_j) * kTileJ,
+              k0 = (t / (G.tiles_i * G.tiles_j)) * kTileK;
+    // chunks holding this tile's nodes: one tile row (j, k) per thread
+    if (threadIdx.x < kTileJ * kTileK) {
+      const int j = j0 + (threadIdx.x & 7), k = k0 + (threadIdx.x >> 3);
+      if (j < G.nj && k < G.nk) {
+        const long long r = noff + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+        const long long c0 = (r + i0) / kCompactChunk, c1 = (r + min(G.ni, i0 + kTileI) - 1) / kCompactChunk;
+        for (long long ch = c0; ch <= c1; ++ch)
+          if (!chunk_static[ch] && atomicExch(&chunk_stamp[ch], stamp) != stamp)
+            chunk_list[n_static + atomicAdd(chunk_list_count, 1)] = (int32_t)ch;
+      }
     }
-    if (!__syncthreads_or(near)) continue;
-    const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
-    uint8_t* fl = flags + GD.node_off;
+    if (NF == 0) continue;
+    uint8_t* fl = flags + noff;
     // stage hole causes with halo: 16 threads per row load the 64 interior
     // bytes as words where the row is aligned and in range, the halo bytewise;
     // fixed trip counts so that all loads are issued before the LDS stores
@@ -609,32 +765,40 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 }
 
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
-  if (nf == 0) return hipSuccess;  // outer layers were marked by the hole cut
   const int ng = (int)ctx->grids.size();
-  long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 8));
+  // persistent blocks over the near list (its length is on the device)
+  long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 4));
+#define OV_FRINGE_ARGS                                                                                            \
+  ctx->d_grids, ng, flags, ctx->total_tiles, ctx->d_near_list, ctx->d_near_count, ctx->d_stamp, ctx->d_chunk_static, \
+      ctx->d_chunk_stamp, ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks
   switch (nf) {
+    case 0:
+      hipLaunchKernelGGL(k_fringe_tiles<0>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
+      break;
     case 1:
-      hipLaunchKernelGGL(k_fringe_tiles<1>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_tile_hole, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<1>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
       break;
     case 2:
-      hipLaunchKernelGGL(k_fringe_tiles<2>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_tile_hole, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<2>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
       break;
     default:
-      hipLaunchKernelGGL(k_fringe_tiles<3>, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, ng, flags,
-                         ctx->d_tile_hole, ctx->total_tiles);
+      hipLaunchKernelGGL(k_fringe_tiles<3>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
       break;
   }
+#undef OV_FRINGE_ARGS
   return hipGetLastError();
 }
 
 // ================================================================ compaction
-// Ordered stream compaction of fringe nodes in three passes over 4096-node
-// chunks: count per chunk, exclusive scan of the counts (one block), then
-// each chunk writes its fringe nodes at its offset in node order. Inside a
-// chunk a thread owns 16 consecutive flag bytes; the wave prefix of the
-// per-thread counts is a shuffle scan and the wave totals are scanned in LDS.
+// Ordered stream compaction of query nodes over 4096-node chunks (in the
+// global node numbering), in three passes: count per listed chunk (the
+// static list of chunks with outer-boundary nodes, then this step's list of
+// chunks touching near tiles; no other chunk can hold a query node), an
+// exclusive scan of all chunk counts (one block; it also zeroes the counts
+// for the next step), then each listed chunk with queries writes them at its
+// offset in node order. Inside a chunk a thread owns 16 consecutive flag
+// bytes; the wave prefix of the per-thread counts is a shuffle scan and the
+// wave totals are scanned in LDS.
 __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, long long total, uint32_t& mask) {
   uint8_t v[16];
   if (n0 + 16 <= total) {
@@ -653,13 +817,14 @@ __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, lo
 }
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
-                                                                   int32_t* __restrict__ counts, long long nchunks,
-                                                                   uint8_t* __restrict__ tile_hole, long long ntiles) {
+                                                                   int32_t* __restrict__ counts,
+                                                                   const int32_t* __restrict__ chunk_list,
+                                                                   const int32_t* __restrict__ chunk_list_count,
+                                                                   long long n_static) {
   __shared__ int red[kCompactThreads / 64];
-  // the fringe pass has consumed the tile map: clear it for the next hole cut
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (long long)gridDim.x * blockDim.x)
-    tile_hole[t] = 0;
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  const long long nl = n_static + *chunk_list_count;
+  for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
+    const long long ch = chunk_list[e];
     uint32_t mask;
     int cnt = count_fringe16(flags, ch * kCompactChunk + threadIdx.x * 16, total, mask);
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
@@ -674,38 +839,52 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
   }
 }
 
-__global__ void __launch_bounds__(1024) k_compact_scan(const int32_t* __restrict__ counts, long long n,
+// n4: number of int4 groups of counts (counts padded with zeros); offsets
+// has 4 n4 + 1 entries, the last one the total.
+__global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ counts, long long n4,
                                                       long long* __restrict__ offsets, long long* __restrict__ d_count,
                                                       long long capacity, int32_t* __restrict__ status) {
-  __shared__ long long part[1024];
-  long long per = (n + blockDim.x - 1) / blockDim.x;
-  long long b0 = threadIdx.x * per, b1 = min(n, b0 + per);
+  __shared__ long long wtot[1024 / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long per = (n4 + blockDim.x - 1) / blockDim.x;
+  const long long b0 = min(n4, (long long)threadIdx.x * per), b1 = min(n4, b0 + per);
+  int4* c4 = reinterpret_cast<int4*>(counts);
   long long sum = 0;
-  for (long long i = b0; i < b1; ++i) sum += counts[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    long long v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  long long run = part[threadIdx.x] - sum;
   for (long long i = b0; i < b1; ++i) {
-    offsets[i] = run;
-    run += counts[i];
+    const int4 v = c4[i];
+    sum += (long long)v.x + v.y + v.z + v.w;
+  }
+  long long inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    long long v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wtot[wave] = inc;
+  __syncthreads();
+  long long run = inc - sum;
+  for (int w = 0; w < wave; ++w) run += wtot[w];
+  for (long long i = b0; i < b1; ++i) {
+    const int4 v = c4[i];
+    offsets[4 * i] = run;
+    offsets[4 * i + 1] = run + v.x;
+    offsets[4 * i + 2] = run + v.x + v.y;
+    offsets[4 * i + 3] = run + v.x + v.y + v.z;
+    run += (long long)v.x + v.y + v.z + v.w;
+    c4[i] = make_int4(0, 0, 0, 0);  // ready for the next step's count
   }
   if (threadIdx.x == blockDim.x - 1) {
-    long long total = part[threadIdx.x];
-    *d_count = total;
-    if (total > capacity) atomicOr(status, OV_DEV_CAPACITY);
+    offsets[4 * n4] = run;
+    *d_count = run;
+    if (run > capacity) atomicOr(status, OV_DEV_CAPACITY);
   }
 }
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev* __restrict__ grids, int ngrids,
                                                                    const uint8_t* __restrict__ flags, long long total,
                                                                    const long long* __restrict__ offsets,
-                                                                   long long nchunks, int32_t* __restrict__ q_grid,
+                                                                   const int32_t* __restrict__ chunk_list,
+                                                                   const int32_t* __restrict__ chunk_list_count,
+                                                                   long long n_static, int32_t* __restrict__ q_grid,
                                                                    int32_t* __restrict__ q_node, long long capacity) {
   __shared__ int wsum[kCompactThreads / 64];
   __shared__ long long off[kMaxGrids + 1];
@@ -713,7 +892,11 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
   if (threadIdx.x == 0) off[ngrids] = total;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  const long long nl = n_static + *chunk_list_count;
+  for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
+    const long long ch = chunk_list[e];
+    const long long base = offsets[ch];
+    if (offsets[ch + 1] == base || base >= capacity) continue;  // nothing to write (same in every thread)
     long long n0 = ch * kCompactChunk + threadIdx.x * 16;
     uint32_t mask;
     int cnt = count_fringe16(flags, n0, total, mask);
@@ -727,12 +910,12 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
     __syncthreads();
     int before = 0;
     for (int w = 0; w < wave; ++w) before += wsum[w];
-    long long pos = offsets[ch] + before + (inc - cnt);
+    long long pos = base + before + (inc - cnt);
     while (mask) {
-      int e = __ffs(mask) - 1;
+      int q = __ffs(mask) - 1;
       mask &= mask - 1;
       if (pos < capacity) {
-        long long n = n0 + e;
+        long long n = n0 + q;
         int A = grid_of_node(off, ngrids, n);
         q_grid[pos] = A;
         q_node[pos] = (int32_t)(n - off[A]);
@@ -745,17 +928,68 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
 
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node, long long capacity,
                           long long* d_count, hipStream_t s) {
-  long long total = ctx->node_off.back();
-  long long nch = ctx->nchunks;
-  long long grid = nch;
+  const long long total = ctx->node_off.back();
+  // persistent blocks over the chunk list (its length is on the device)
+  long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, nch, ctx->d_tile_hole, ctx->total_tiles);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_chunk_counts, nch, ctx->d_chunk_offsets,
-                     d_count, capacity, ctx->d_status);
+                     ctx->d_chunk_counts, ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_chunk_counts, (ctx->nchunks + 3) / 4,
+                     ctx->d_chunk_offsets, d_count, capacity, ctx->d_status);
   hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
-                     (int)ctx->grids.size(), flags, total, ctx->d_chunk_offsets, nch, q_grid, q_node, capacity);
+                     (int)ctx->grids.size(), flags, total, ctx->d_chunk_offsets, ctx->d_chunk_list,
+                     ctx->d_chunk_list_count, ctx->n_static_chunks, q_grid, q_node, capacity);
   return hipGetLastError();
+}
+
+// Chunks holding outer-boundary query nodes (fixed per grid): one block per
+// chunk marks them; the host turns the marks into the static chunk list.
+__global__ void __launch_bounds__(256) k_chunk_outer(const GridDev* __restrict__ grids, int ngrids, long long total,
+                                                    long long nchunks, uint8_t* __restrict__ chunk_static) {
+  __shared__ long long off[kMaxGrids + 1];
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) off[g] = grids[g].node_off;
+  if (threadIdx.x == 0) off[ngrids] = total;
+  __syncthreads();
+  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    bool any = false;
+    for (int e = threadIdx.x; e < kCompactChunk; e += blockDim.x) {
+      const long long n = ch * kCompactChunk + e;
+      if (n >= total) break;
+      const int A = grid_of_node(off, ngrids, n);
+      const GeomR G(grids[A]);
+      if (!grids[A].has_outer) continue;
+      const long long m = n - off[A];
+      const long long plane = (long long)G.ni * G.nj;
+      const int k = (int)(m / plane);
+      const long long r = m - (long long)k * plane;
+      const int j = (int)(r / G.ni), i = (int)(r - (long long)j * G.ni);
+      any |= G.on_outer(i, j, k);
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) chunk_static[ch] = any ? 1 : 0;
+  }
+}
+
+int build_static_chunks(ov_ctx* ctx, hipStream_t s) {
+  const long long total = ctx->node_off.back();
+  const long long nch = ctx->nchunks;
+  long long g = std::max(1LL, std::min(nch, 65536LL));
+  hipLaunchKernelGGL(k_chunk_outer, dim3((unsigned)g), dim3(256), 0, s, ctx->d_grids, (int)ctx->grids.size(), total,
+                     nch, ctx->d_chunk_static);
+  std::vector<uint8_t> marks((size_t)nch);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(marks.data(), ctx->d_chunk_static, (size_t)nch, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "static chunk list");
+  std::vector<int32_t> list;
+  for (long long c = 0; c < nch; ++c)
+    if (marks[(size_t)c]) list.push_back((int32_t)c);
+  ctx->n_static_chunks = (long long)list.size();
+  if (!list.empty()) {
+    e = hipMemcpy(ctx->d_chunk_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "static chunk list upload");
+  }
+  return OV_OK;
 }
 
 // ================================================================ transform

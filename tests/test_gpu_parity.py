@@ -242,3 +242,37 @@ def test_graph_pipeline_matches_sequential():
                 assert np.array_equal(r[key], seq[t - 1][key], equal_nan=True), (t - 1, key)
     pipe.join()
     assert [int(x) for x in counts.cpu()] == [seq[t]["count"] for t in range(7)]
+
+
+def seam_case():
+    """Buffer reach across a periodic seam whose last tile is thin: a
+    cylindrical shell with 121 azimuthal nodes (tiles of 8 leave one node in
+    the last) and a blank sphere small enough to cut only its node
+    (i=2, j=1, k=4). With nf = 3 the buffer wraps to j = 119, two tiles back."""
+    bg = W.cartesian_grid(20)
+    cyl = W.cylindrical_shell(6, 121, 9, 0.15, 0.35, 0.3, 0.7)
+    cyl.outer = (0, 2, 0, 0, 0, 0)
+    ball = W.spherical_shell(6, 8, 7, 0.006, 0.03)
+    ball.blank_kind = W.BLANK_SPHERE
+    ball.blank_prm = (0.006,)
+    ball.outer = (0, 1, 0, 0, 0, 0)
+    p_cyl = W.pose12(np.eye(3), (0.5, 0.5, 0.0))
+    m = 2 + 6 * (1 + 121 * 4)
+    centre = np.array([cyl.X[m], cyl.Y[m], cyl.Z[m]]) + p_cyl[9:]
+    poses = np.stack([W.IDENTITY_POSE, p_cyl, W.pose12(np.eye(3), centre)])[None]
+    fields = np.random.default_rng(5).standard_normal((4, bg.nodes + cyl.nodes + ball.nodes))
+    return W.Workload("seam", [bg, cyl, ball], nf=3, steps=1, poses=poses, fields=fields)
+
+
+def test_buffer_wraps_two_tiles_across_a_thin_periodic_seam():
+    w = seam_case()
+    o = oracle.Oracle(w.grids, w.nf)
+    r = o.step(w.poses[0], w.fields)
+    # the case reaches j = 119 of the shell through the seam
+    f = r["flags"][o.node_off[1]:o.node_off[2]].reshape(9, 121, 6)
+    assert (f[4, 1, 2] & 3) == oracle.ST_HOLE
+    # buffer nodes (radial layers 0-3; 4 and 5 are outer-boundary fringe) at j = 119
+    assert ((f[:, 119, :4] & 3) == oracle.ST_FRINGE).sum() > 0
+    assert ((f[:, 118, :4] & 3) == oracle.ST_FRINGE).sum() == 0
+    _run_and_compare(w, [0])
+    _run_and_compare(w, [0], options={"holecut_cull": 0})

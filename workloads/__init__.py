@@ -28,6 +28,7 @@ Conventions (shared with the C-ABI library and the oracle):
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -256,10 +257,28 @@ def fourier_modes(rng, nmodes=8, kmax=4):
     return modes
 
 
-def eval_modes(modes, x, y, z):
-    q = np.zeros_like(x)
+_CHUNK = 1 << 20
+
+
+def _eval_modes_chunk(modes, x, y, z, q):
+    q[:] = 0.0
     for k, A, ph in modes:
         q += A * np.cos(2.0 * math.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+
+
+def eval_modes(modes, x, y, z):
+    """Sum of the modes at every point, evaluated in fixed 2^20-point chunks on
+    a thread pool (numpy releases the GIL inside its loops)."""
+    q = np.empty_like(x)
+    n = x.size
+    spans = [(a, min(a + _CHUNK, n)) for a in range(0, n, _CHUNK)]
+    if len(spans) <= 1:
+        _eval_modes_chunk(modes, x, y, z, q)
+        return q
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda ab: _eval_modes_chunk(modes, x[ab[0]:ab[1]], y[ab[0]:ab[1]], z[ab[0]:ab[1]],
+                                                 q[ab[0]:ab[1]]), spans))
     return q
 
 
