@@ -156,16 +156,23 @@ __global__ void k_bin_rep(GridDev g, const long long* __restrict__ start, const 
   }
 }
 
-// Bounding sphere (body frame) of each node tile of kTileI x kTileJ x kTileK:
-// centre of the tile's coordinate box, radius = half its diagonal.
+// Bounding sphere (body frame) of each sub-tile (kSubI x kTileJ x kTileK
+// nodes, kTileI / kSubI of them per tile along i, sub-tile sb of tile t at
+// index t * kSubPerTile + sb): centre of its coordinate box, radius = half
+// the box diagonal. A sub-tile past the grid's last node gets radius -inf
+// (nothing reaches it).
 __global__ void __launch_bounds__(256) k_tile_spheres(GridDev g, double4* __restrict__ out) {
   __shared__ double red[6][256];
-  const long long ntiles = (long long)g.tiles_i * g.tiles_j * g.tiles_k;
-  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const long long nsub = (long long)g.tiles_i * g.tiles_j * g.tiles_k * kSubPerTile;
+  constexpr int kSubNodes = kSubI * kTileJ * kTileK;
+  for (long long u = blockIdx.x; u < nsub; u += gridDim.x) {
+    const long long t = u / kSubPerTile;
+    const int sb = (int)(u % kSubPerTile);
     int ti = (int)(t % g.tiles_i), tj = (int)((t / g.tiles_i) % g.tiles_j), tk = (int)(t / ((long long)g.tiles_i * g.tiles_j));
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int e = threadIdx.x; e < kTileI * kTileJ * kTileK; e += blockDim.x) {
-      int i = ti * kTileI + (e % kTileI), j = tj * kTileJ + (e / kTileI) % kTileJ, k = tk * kTileK + e / (kTileI * kTileJ);
+    for (int e = threadIdx.x; e < kSubNodes; e += blockDim.x) {
+      int i = ti * kTileI + sb * kSubI + (e % kSubI), j = tj * kTileJ + (e / kSubI) % kTileJ,
+          k = tk * kTileK + e / (kSubI * kTileJ);
       if (i >= g.ni || j >= g.nj || k >= g.nk) continue;
       long long m = (long long)i + (long long)g.ni * ((long long)j + (long long)g.nj * k);
       double v[3] = {g.X[m], g.Y[m], g.Z[m]};
@@ -188,13 +195,17 @@ __global__ void __launch_bounds__(256) k_tile_spheres(GridDev g, double4* __rest
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      double c[3], r2 = 0.0;
-      for (int d = 0; d < 3; ++d) {
-        c[d] = 0.5 * (red[d][0] + red[3 + d][0]);
-        double h = 0.5 * (red[3 + d][0] - red[d][0]);
-        r2 += h * h;
+      if (!(red[0][0] <= red[3][0])) {
+        out[u] = make_double4(0.0, 0.0, 0.0, -INFINITY);  // no node
+      } else {
+        double c[3], r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          c[d] = 0.5 * (red[d][0] + red[3 + d][0]);
+          double h = 0.5 * (red[3 + d][0] - red[d][0]);
+          r2 += h * h;
+        }
+        out[u] = make_double4(c[0], c[1], c[2], sqrt(r2));
       }
-      out[t] = make_double4(c[0], c[1], c[2], sqrt(r2));
     }
     __syncthreads();
   }
@@ -320,6 +331,24 @@ int build_shadows(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   return OV_OK;
 }
 
+__global__ void k_pack_xyz(const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
+                           long long n, double4* __restrict__ P) {
+  for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (long long)gridDim.x * blockDim.x)
+    P[m] = make_double4(X[m], Y[m], Z[m], 0.0);
+}
+
+// (x, y, z, 0) per node, 32 bytes: a cell's corners i and i+1 share a
+// 64-byte span, so one cell is 4 row pairs instead of 12 separate lines of
+// the three coordinate arrays. Built once: body-frame coordinates are fixed.
+int build_gather_layout(ov_ctx* ctx, GridHost& g, hipStream_t s) {
+  HIPCHK(hipMalloc(&g.p, sizeof(double4) * g.d.nnodes), "hipMalloc gather layout");
+  hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.d.nnodes)), dim3(256), 0, s, g.d.X, g.d.Y, g.d.Z, g.d.nnodes,
+                     g.p);
+  HIPCHK(hipGetLastError(), "gather layout");
+  g.d.P = g.p;
+  return OV_OK;
+}
+
 }  // namespace ov
 
 using namespace ov;
@@ -359,6 +388,7 @@ int ov_ctx_destroy(ov_ctx* ctx) {
     (void)hipFree(g.xf);
     (void)hipFree(g.yf);
     (void)hipFree(g.zf);
+    (void)hipFree(g.p);
     (void)hipFree(g.bstart);
     (void)hipFree(g.bcells);
     (void)hipFree(g.brep);
@@ -369,18 +399,24 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_warm_cell);
   (void)hipFree(ctx->d_warm_grid);
   (void)hipFree(ctx->d_tile_sphere);
+  (void)hipFree(ctx->d_tile_info);
+  (void)hipFree(ctx->d_unit_info);
+  (void)hipFree(ctx->d_unit_where);
   (void)hipFree(ctx->d_stamp);
   (void)hipFree(ctx->d_tile_mask);
   (void)hipFree(ctx->d_tile_hole);
   (void)hipFree(ctx->d_tile_near);
   (void)hipFree(ctx->d_near_list);
   (void)hipFree(ctx->d_near_count);
+  (void)hipFree(ctx->d_cand_list);
+  (void)hipFree(ctx->d_cand_count);
   (void)hipFree(ctx->d_chunk_static);
   (void)hipFree(ctx->d_chunk_stamp);
   (void)hipFree(ctx->d_chunk_list);
   (void)hipFree(ctx->d_chunk_list_count);
   (void)hipFree(ctx->d_chunk_counts);
-  (void)hipFree(ctx->d_chunk_offsets);
+  (void)hipFree(ctx->d_super_counts);
+  (void)hipFree(ctx->d_super_offsets);
   delete ctx;
   return OV_OK;
 }
@@ -468,6 +504,8 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
       rc = build_shadows(ctx, g, s);
       if (rc != OV_OK) return rc;
     }
+    rc = build_gather_layout(ctx, g, s);
+    if (rc != OV_OK) return rc;
   }
   long long total = ctx->node_off.back();
   std::vector<GridDev> table;
@@ -478,35 +516,80 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
   HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
-  HIPCHK(hipMalloc(&ctx->d_tile_sphere, sizeof(double4) * std::max(1LL, ctx->total_tiles)), "hipMalloc tile spheres");
+  HIPCHK(hipMalloc(&ctx->d_tile_sphere, sizeof(double4) * kSubPerTile * std::max(1LL, ctx->total_tiles)),
+         "hipMalloc sub-tile spheres");
   for (auto& g : ctx->grids) {
-    long long nt = (long long)g.d.tiles_i * g.d.tiles_j * g.d.tiles_k;
-    hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)std::min(nt, 65536LL)), dim3(256), 0, s, g.d,
-                       ctx->d_tile_sphere + g.d.tile_off);
+    long long nsub = (long long)g.d.tiles_i * g.d.tiles_j * g.d.tiles_k * kSubPerTile;
+    hipLaunchKernelGGL(k_tile_spheres, dim3((unsigned)std::min(nsub, 65536LL)), dim3(256), 0, s, g.d,
+                       ctx->d_tile_sphere + g.d.tile_off * kSubPerTile);
   }
   // front-half scratch (stamps start at 0: "never listed")
   const long long nt = std::max(1LL, ctx->total_tiles);
+  {
+    std::vector<int4> info((size_t)nt, make_int4(0, 0, 0, 0));
+    for (size_t gi = 0; gi < ctx->grids.size(); ++gi) {
+      const GridDev& g = ctx->grids[gi].d;
+      for (int tk = 0; tk < g.tiles_k; ++tk)
+        for (int tj = 0; tj < g.tiles_j; ++tj)
+          for (int ti = 0; ti < g.tiles_i; ++ti)
+            info[(size_t)(g.tile_off + ti + (long long)g.tiles_i * (tj + (long long)g.tiles_j * tk))] =
+                make_int4((int)gi, ti, tj, tk);
+    }
+    HIPCHK(hipMalloc(&ctx->d_tile_info, sizeof(int4) * nt), "hipMalloc tile info");
+    HIPCHK(hipMemcpy(ctx->d_tile_info, info.data(), sizeof(int4) * nt, hipMemcpyHostToDevice), "tile info copy");
+    // hole-cut units: kUnitI x kTileJ x 1 nodes, i fastest, then j, then k;
+    // per unit (flag offset of its first node, its first tile, grid,
+    // columns << 8 | rows present) and (i0, j0, k, 0)
+    std::vector<int4> units, where;
+    for (size_t gi = 0; gi < ctx->grids.size(); ++gi) {
+      const GridDev& g = ctx->grids[gi].d;
+      const int ui_n = (g.ni + kUnitI - 1) / kUnitI;
+      for (int k = 0; k < g.nk; ++k)
+        for (int uj = 0; uj < g.tiles_j; ++uj)
+          for (int ui = 0; ui < ui_n; ++ui) {
+            const int i0 = ui * kUnitI, j0 = uj * kTileJ;
+            const long long base = g.node_off + i0 + (long long)g.ni * (j0 + (long long)g.nj * k);
+            const long long tile = g.tile_off + (i0 >> 6) + (long long)g.tiles_i * (uj + (long long)g.tiles_j * (k >> 3));
+            const int cols = std::min(kUnitI, g.ni - i0), rows = std::min(kTileJ, g.nj - j0);
+            units.push_back(make_int4((int)base, (int)tile, (int)gi, (cols << 8) | rows));
+            where.push_back(make_int4(i0, j0, k, 0));
+          }
+    }
+    ctx->total_units = (long long)units.size();
+    HIPCHK(hipMalloc(&ctx->d_unit_info, sizeof(int4) * units.size()), "hipMalloc unit info");
+    HIPCHK(hipMemcpy(ctx->d_unit_info, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice),
+           "unit info copy");
+    HIPCHK(hipMalloc(&ctx->d_unit_where, sizeof(int4) * where.size()), "hipMalloc unit coordinates");
+    HIPCHK(hipMemcpy(ctx->d_unit_where, where.data(), sizeof(int4) * where.size(), hipMemcpyHostToDevice),
+           "unit coordinates copy");
+  }
   HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int)), "hipMalloc stamp");
-  HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * nt), "hipMalloc tile masks");
+  HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * kSubPerTile * nt), "hipMalloc sub-tile masks");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * nt), "hipMalloc tile holes");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
   HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * nt), "hipMalloc near list");
   HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t)), "hipMalloc near count");
+  HIPCHK(hipMalloc(&ctx->d_cand_list, sizeof(int32_t) * kSubPerTile * nt), "hipMalloc candidate list");
+  HIPCHK(hipMalloc(&ctx->d_cand_count, sizeof(int32_t)), "hipMalloc candidate count");
+  HIPCHK(hipMemsetAsync(ctx->d_cand_count, 0, sizeof(int32_t), s), "candidate count init");
   HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * nt, s), "tile hole init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
   HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t), s), "near count init");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
-  const long long nch4 = 4 * ((ctx->nchunks + 3) / 4);
+  ctx->nsuper = (ctx->nchunks + kSuperChunk - 1) / kSuperChunk;
   HIPCHK(hipMalloc(&ctx->d_chunk_static, ctx->nchunks), "hipMalloc static chunk marks");
   HIPCHK(hipMalloc(&ctx->d_chunk_stamp, sizeof(unsigned int) * ctx->nchunks), "hipMalloc chunk stamps");
   HIPCHK(hipMalloc(&ctx->d_chunk_list, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk list");
   HIPCHK(hipMalloc(&ctx->d_chunk_list_count, sizeof(int32_t)), "hipMalloc chunk list count");
-  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(int32_t) * nch4), "hipMalloc chunk counts");
-  HIPCHK(hipMalloc(&ctx->d_chunk_offsets, sizeof(long long) * (nch4 + 1)), "hipMalloc chunk offsets");
+  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(unsigned long long) * ctx->nchunks), "hipMalloc chunk counts");
+  HIPCHK(hipMalloc(&ctx->d_super_counts, sizeof(int32_t) * kSuperSlots * ctx->nsuper), "hipMalloc superchunk counts");
+  HIPCHK(hipMalloc(&ctx->d_super_offsets, sizeof(long long) * (ctx->nsuper + 1)), "hipMalloc superchunk offsets");
   HIPCHK(hipMemsetAsync(ctx->d_chunk_stamp, 0, sizeof(unsigned int) * ctx->nchunks, s), "chunk stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_chunk_list_count, 0, sizeof(int32_t), s), "chunk list count init");
-  HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(int32_t) * nch4, s), "chunk count init");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(unsigned long long) * ctx->nchunks, s), "chunk count init");
+  HIPCHK(hipMemsetAsync(ctx->d_super_counts, 0, sizeof(int32_t) * kSuperSlots * ctx->nsuper, s),
+         "superchunk count init");
   HIPCHK(hipGetLastError(), "finalize kernels");
   {
     int rc = build_static_chunks(ctx, s);

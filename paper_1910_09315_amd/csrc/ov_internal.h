@@ -26,11 +26,17 @@ constexpr int kNewtonMaxIt = 50;
 constexpr double kDetMin = 1e-300;
 
 // Fringe-marking tile (nodes along i, j, k) and the widest buffer supported.
+// The hole cut culls per sub-tile (kSubI nodes along i) and works in units of
+// kUnitI x kTileJ x 1 nodes (16 consecutive nodes per lane).
 constexpr int kTileI = 64, kTileJ = 8, kTileK = 8;
+constexpr int kSubI = 16, kSubPerTile = kTileI / kSubI;
+constexpr int kUnitI = 128;
 constexpr int kMaxNf = 3;
-// Compaction chunk: 256 threads x 16 flag bytes.
+// Compaction chunk: 256 threads x 16 flag bytes; 64 chunks form a superchunk.
 constexpr int kCompactThreads = 256;
 constexpr int kCompactChunk = kCompactThreads * 16;
+constexpr int kSuperChunk = 64;
+constexpr int kSuperSlots = 8;  // count slots per superchunk (spreads the atomics)
 
 // One grid as the kernels see it.
 struct GridDev {
@@ -43,6 +49,7 @@ struct GridDev {
   const float* Xf;  // FP32 shadows (mixed precision), else null
   const float* Yf;
   const float* Zf;
+  const double4* P;  // (x, y, z, 0) per node: the donor search's gather layout
   double blank_prm[8];
   double cull_r2;  // body-frame sphere about the origin enclosing the blank region, squared
   int outer[6];
@@ -64,6 +71,7 @@ struct GridHost {
   float* xf = nullptr;
   float* yf = nullptr;
   float* zf = nullptr;
+  double4* p = nullptr;
   long long* bstart = nullptr;
   int* bcells = nullptr;
   int* brep = nullptr;
@@ -85,24 +93,31 @@ struct ov_ctx {
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
   double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
+  int4* d_tile_info = nullptr;       // per node tile: (grid, ti, tj, tk)
+  int4* d_unit_info = nullptr;       // per hole-cut unit: (flag offset, first tile, grid, cols << 8 | rows)
+  int4* d_unit_where = nullptr;      // per hole-cut unit: (i0, j0, k, 0)
+  long long total_units = 0;
   // Front-half scratch, written and read in stream order by the hole cut,
   // the fringe pass and the compaction. Each hole cut starts a new stamp; a
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
   unsigned int* d_stamp = nullptr;            // current stamp (device)
-  unsigned long long* d_tile_mask = nullptr;  // per tile: blank regions (bit = grid) that may reach it
+  unsigned long long* d_tile_mask = nullptr;  // per sub-tile: blank regions (bit = grid) that may reach it
   unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
   int32_t* d_near_list = nullptr;             // tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;
+  int32_t* d_cand_list = nullptr;             // sub-tiles some blank region may reach (this step)
+  int32_t* d_cand_count = nullptr;
   uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
   unsigned int* d_chunk_stamp = nullptr;      // per chunk: stamp if on this step's chunk list
   int32_t* d_chunk_list = nullptr;            // chunks that may hold query nodes: the static ones, then this step's
   int32_t* d_chunk_list_count = nullptr;      // length of this step's part
   long long n_static_chunks = 0;
-  int32_t* d_chunk_counts = nullptr;          // padded to a multiple of 4; zero outside the listed chunks
-  long long* d_chunk_offsets = nullptr;       // padded length + 1
-  long long nchunks = 0;
+  unsigned long long* d_chunk_counts = nullptr;  // per chunk: stamp << 32 | query count (listed chunks)
+  int32_t* d_super_counts = nullptr;             // per 64 chunks, kSuperSlots partial counts (zeroed by the scan)
+  long long* d_super_offsets = nullptr;          // per 64 chunks: first query position; last entry the total
+  long long nchunks = 0, nsuper = 0;
   // options
   int warm = 1;
   int max_walk = 64;
@@ -139,8 +154,30 @@ hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* 
 // setup (control cells, shadows)
 int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);
 int build_shadows(ov_ctx* ctx, GridHost& g, hipStream_t s);
+int build_gather_layout(ov_ctx* ctx, GridHost& g, hipStream_t s);
 
 // ---------------------------------------------------------------- device helpers
+// Pointers read from the grid table or from LDS carry no address space, so
+// loads through them would be flat instructions (which also wait on LDS
+// traffic); the library's arrays are all in device memory, and gp() says so.
+template <typename T>
+using gmem = const __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* gp(const T* p) {
+  return (gmem<T>*)p;
+}
+
+typedef double ov_dv2 __attribute__((ext_vector_type(2)));
+
+// (x, y, z) of node n from a grid's gather layout: two 16-byte loads.
+__device__ __forceinline__ void load_xyz(const GridDev& G, long long n, double& x, double& y, double& z) {
+  gmem<ov_dv2>* p = (gmem<ov_dv2>*)gp(G.P) + 2 * n;
+  const ov_dv2 a = p[0], b = p[1];
+  x = a.x;
+  y = a.y;
+  z = b.x;
+}
+
 __device__ __forceinline__ int grid_of_node(const long long* off, int ngrids, long long n) {
   int lo = 0, hi = ngrids - 1;
   while (lo < hi) {

@@ -72,10 +72,7 @@ __device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int 
   double P[8][3];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    long long n = corner_node(G, ci, cj, ck, c);
-    P[c][0] = G.X[n];
-    P[c][1] = G.Y[n];
-    P[c][2] = G.Z[n];
+    load_xyz(G, corner_node(G, ci, cj, ck, c), P[c][0], P[c][1], P[c][2]);
   }
   map_from_corners<T>(P, xi, m);
 }
@@ -323,7 +320,8 @@ struct Query {
 
 // Inertial position of node m of grid A, in FP64 from its FP64 coordinates.
 __device__ __forceinline__ void exact_world(const GridDev& GA, const double* pa, long long m, double x[3]) {
-  double X = GA.X[m], Y = GA.Y[m], Z = GA.Z[m];
+  double X, Y, Z;
+  load_xyz(GA, m, X, Y, Z);
   x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
   x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
   x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
@@ -473,18 +471,21 @@ __global__ void __launch_bounds__(256)
         const GridDev& G = grids[B];
         double xi[3];
         if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+        // seeds: last step's donor cell, then the control cell's lowest cell
+        const int rep = gp(G.brep)[bin_of(G, xi)];
         int seed = -1;
         if (wg == B) {
           int wc = warm_cell[Q.key];
           if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
         }
-        if (seed < 0) {
-          seed = G.brep[bin_of(G, xi)];
-          if (seed < 0) continue;  // no cell reaches this control cell
-        }
-        int cell = seed;
+        if (seed < 0 && rep < 0) continue;  // no cell reaches this control cell
+        int cell = seed >= 0 ? seed : rep;
         T s[3];
-        const int r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
+        int r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
+        if (r == kToScan && seed >= 0 && rep >= 0 && rep != seed) {
+          cell = rep;  // a second start before the brute-force scan
+          r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
+        }
         if (r == kFound) {
           res_grid = B;
           res_cell = cell;
@@ -551,29 +552,37 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Wavefront-cooperative brute-force scan: the control cell's sorted list is
-// taken 64 candidates per round, one per lane; the first round holding a
-// valid containing cell ends the scan with its lowest such cell.
-__device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3]) {
-  const int lane = threadIdx.x & 63;
-  long long b = bin_of(G, xi);
-  long long e0 = G.bstart[b], e1 = G.bstart[b + 1];
-  for (long long base = e0; base < e1; base += 64) {
-    const long long e = base + lane;
+// Block-cooperative brute-force scan of the control cell holding xi: its
+// sorted list is taken blockDim.x candidates per round, one per thread; the
+// first round holding a valid containing cell ends the scan with its lowest
+// such cell (lists ascend, so that is the lowest list position that hits).
+// The next round's cell ids are loaded while the current round is tested.
+// Every thread of the block calls it with the same G and xi.
+struct ScanLds {
+  int pos[4];
+  int cell[4];
+  double s[4][3];
+};
+
+__device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3],
+                                       ScanLds& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long b = bin_of(G, xi);
+  const long long e0 = gp(G.bstart)[b], e1 = gp(G.bstart)[b + 1];
+  int next = e0 + tid < e1 ? gp(G.bcells)[e0 + tid] : -1;
+  for (long long base = e0; base < e1; base += blockDim.x) {
+    const long long e = base + tid;
+    const int cell = next;
+    next = e + blockDim.x < e1 ? gp(G.bcells)[e + blockDim.x] : -1;
     bool hit = false;
     double s[3] = {0.0, 0.0, 0.0};
-    int cell = 0x7fffffff;
     if (e < e1) {
-      cell = G.bcells[e];
       int ci, cj, ck;
       cell_ijk(G, cell, ci, cj, ck);
       double P[8][3];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        long long nd = corner_node(G, ci, cj, ck, c);
-        P[c][0] = G.X[nd];
-        P[c][1] = G.Y[nd];
-        P[c][2] = G.Z[nd];
+        load_xyz(G, corner_node(G, ci, cj, ck, c), P[c][0], P[c][1], P[c][2]);
       }
       if (!hull_excludes(P, xi)) {
         CellMap<double> m;
@@ -582,23 +591,40 @@ __device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const
       }
     }
     const unsigned long long hits = __ballot(hit);
-    if (hits) {
-      // lists are ascending: the lowest lane that hit holds the lowest cell
-      const int src = __ffsll((long long)hits) - 1;
-      s_best[0] = __shfl(s[0], src, 64);
-      s_best[1] = __shfl(s[1], src, 64);
-      s_best[2] = __shfl(s[2], src, 64);
-      return __shfl(cell, src, 64);
+    const int first = hits ? __ffsll((long long)hits) - 1 : 64;
+    if (lane == first) {
+      S.pos[wave] = tid;
+      S.cell[wave] = cell;
+      S.s[wave][0] = s[0];
+      S.s[wave][1] = s[1];
+      S.s[wave][2] = s[2];
     }
+    if (lane == 0 && !hits) S.pos[wave] = 0x7fffffff;
+    __syncthreads();
+    int bw = -1, bp = 0x7fffffff;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+      if (S.pos[w] < bp) {
+        bp = S.pos[w];
+        bw = w;
+      }
+    int found = -1;
+    if (bw >= 0) {
+      found = S.cell[bw];
+      s_best[0] = S.s[bw][0];
+      s_best[1] = S.s[bw][1];
+      s_best[2] = S.s[bw][2];
+    }
+    __syncthreads();  // S is reused by the next round or call
+    if (found >= 0) return found;
   }
   return -1;
 }
 
-// Pass 3: the brute-force scan (Alg. 3's fallback). Each wavefront sweeps 64
-// queries and takes the deferred ones one at a time, all lanes together: the
-// cooperative scan of the grid whose walk failed, then the remaining
-// candidate grids (walk, and cooperative scan if needed), all on the exact
-// query position.
+// Pass 3: the brute-force scan (Alg. 3's fallback). Each block sweeps 256
+// queries, lists the deferred ones (with their status) in LDS, and takes
+// them one at a time with all its threads: the cooperative scan of the grid
+// whose walk failed, then the remaining candidate grids (walk, and
+// cooperative scan if needed), all on the exact query position.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_donor_scan(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
@@ -608,22 +634,25 @@ __global__ void __launch_bounds__(256)
                  T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
                  uint8_t* __restrict__ warm_grid, int max_walk, int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
+  __shared__ int list_q[256], list_st[256];
+  __shared__ int nlist;
+  __shared__ ScanLds S;
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
   const long long n = min(*d_count, cap);
-  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
-  for (long long base = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < n;
-       base += waves * 64) {
-    const long long ql = base + lane;
-    const bool mine = ql < n && donor_grid[ql] == kDeferScan;
-    unsigned long long pend = __ballot(mine);
-    const int st_l = mine ? status[ql] : 0;
-    while (pend) {
-      const int src = __ffsll((long long)pend) - 1;
-      pend &= pend - 1;
-      const long long q = base + src;
-      const int st = __shfl(st_l, src, 64);
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    const long long ql = base + threadIdx.x;
+    if (ql < n && donor_grid[ql] == kDeferScan) {
+      const int slot = atomicAdd(&nlist, 1);
+      list_q[slot] = (int)threadIdx.x;
+      list_st[slot] = status[ql];
+    }
+    __syncthreads();
+    const int nd = nlist;
+    for (int d = 0; d < nd; ++d) {
+      const long long q = base + list_q[d];
+      const int st = list_st[d];
       const int t0 = (st & 255) - 2;
       int visited = (st >> 8) & 255;
       const Query Q = load_query<T>(grids, ngrids, sp, flags, q_grid, q_node, qx, cap, q, true);
@@ -642,7 +671,7 @@ __global__ void __launch_bounds__(256)
         T s[3];
         bool walked = false;
         if (t != t0) {
-          int seed = G.brep[bin_of(G, xi)];
+          int seed = gp(G.brep)[bin_of(G, xi)];
           if (seed < 0) continue;
           cell = seed;
           how = OV_Q_FOUND;
@@ -650,7 +679,7 @@ __global__ void __launch_bounds__(256)
         }
         if (!walked) {
           double s64[3];
-          cell = scan_control_cell_wave(G, fl, xi, s64);
+          cell = scan_control_cell_block(G, fl, xi, s64, S);
           s[0] = (T)s64[0];
           s[1] = (T)s64[1];
           s[2] = (T)s64[2];
@@ -666,12 +695,13 @@ __global__ void __launch_bounds__(256)
           break;
         }
       }
-      if (lane == 0) {
+      if (threadIdx.x == 0) {
         if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
         write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
                         donor_cell, s_out, status, warm_cell, warm_grid);
       }
     }
+    __syncthreads();  // the list is rebuilt for the next range
   }
 }
 
@@ -685,7 +715,7 @@ static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* fla
   hipLaunchKernelGGL(k_donor_walk<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
                      q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell,
                      ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status);
-  // the sweeps: one lane (FP64 correction) or one wavefront per 64 queries (scan)
+  // the sweeps: one lane (FP64 correction) or one block per 256 queries (scan)
   const long long sweep_cap = (long long)ctx->num_cus * 8;
   if (sizeof(T) == 4)
     hipLaunchKernelGGL(k_donor_fix, dim3((unsigned)std::max(1LL, std::min(sweep_cap, (capacity + 255) / 256))),

@@ -170,7 +170,7 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
   }
   if (unsure) {
     const GridDev& G = grids[A];
-    double Xd = G.X[m], Yd = G.Y[m], Zd = G.Z[m];
+    double Xd = gp(G.X)[m], Yd = gp(G.Y)[m], Zd = gp(G.Z)[m];
     double w[3];
     w[0] = pa[0] * Xd + pa[1] * Yd + pa[2] * Zd + pa[9];
     w[1] = pa[3] * Xd + pa[4] * Yd + pa[5] * Zd + pa[10];
@@ -261,9 +261,9 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
     const int A = grid_of_node(coff, ngrids, ch);
     const long long nn = L.off[A + 1] - L.off[A];
     const long long m0 = (ch - coff[A]) * span + (long long)threadIdx.x * W;
-    const CT* Xa = (const CT*)L.X[A];
-    const CT* Ya = (const CT*)L.Y[A];
-    const CT* Za = (const CT*)L.Z[A];
+    gmem<CT>* Xa = gp((const CT*)L.X[A]);
+    gmem<CT>* Ya = gp((const CT*)L.Y[A]);
+    gmem<CT>* Za = gp((const CT*)L.Z[A]);
     uint8_t* fa = flags + L.off[A];
     const GeomR GR(grids[A]);
     const bool outerA = L.outer[A] != 0;
@@ -272,9 +272,9 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
     for (int r = 0; r < R; ++r) {
       const long long m = m0 + (long long)r * blockDim.x * W;
       if (m + W <= nn) {
-        V x = __builtin_nontemporal_load(reinterpret_cast<const V*>(Xa + m));
-        V y = __builtin_nontemporal_load(reinterpret_cast<const V*>(Ya + m));
-        V z = __builtin_nontemporal_load(reinterpret_cast<const V*>(Za + m));
+        V x = __builtin_nontemporal_load((gmem<V>*)(Xa + m));
+        V y = __builtin_nontemporal_load((gmem<V>*)(Ya + m));
+        V z = __builtin_nontemporal_load((gmem<V>*)(Za + m));
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           X[r][w] = x[w];
@@ -311,16 +311,17 @@ static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI *
 // Starts a step of the front half: a new stamp, empty near and chunk lists.
 // Later kernels of the hole cut read the stamp (stream order).
 __device__ __forceinline__ void k_begin_step_body(unsigned int* d_stamp, int32_t* near_count,
-                                                  int32_t* chunk_list_count) {
+                                                  int32_t* chunk_list_count, int32_t* cand_count) {
   unsigned int v = *d_stamp + 1u;
   *d_stamp = v == 0u ? 1u : v;  // 0 marks "never listed"
   *near_count = 0;
   *chunk_list_count = 0;
+  *cand_count = 0;
 }
 
 __global__ void k_begin_step(unsigned int* __restrict__ d_stamp, int32_t* __restrict__ near_count,
-                             int32_t* __restrict__ chunk_list_count) {
-  k_begin_step_body(d_stamp, near_count, chunk_list_count);
+                             int32_t* __restrict__ chunk_list_count, int32_t* __restrict__ cand_count) {
+  k_begin_step_body(d_stamp, near_count, chunk_list_count, cand_count);
 }
 
 // Tile index along one axis holding the node `which` positions from tile t:
@@ -354,30 +355,28 @@ __device__ __forceinline__ void mark_near(int e, int ti, int tj, int tk, int ni,
   if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = (int32_t)n;
 }
 
-// Which blank regions may reach each node tile (bit B set: grid B's region
-// may contain a node of the tile). The tile's bounding sphere, placed at its
+// Which blank regions may reach each sub-tile (bit B set: grid B's region
+// may contain a node of it). The sub-tile's bounding sphere, placed at its
 // grid's pose, is tested against the sphere about grid B's origin that
 // encloses B's region, then against the region's box in B's body frame
 // (distance from the sphere's centre to the box at most the radius). The
 // radius is padded far beyond FP64 rounding, so no node the exact test
-// would blank is ever culled. One thread per tile.
+// would blank is ever culled. One thread per sub-tile; sub-tiles with a
+// non-empty mask are appended to the candidate list.
 __global__ void __launch_bounds__(256) k_tile_masks(const GridDev* __restrict__ grids, int ngrids,
                                                    const double* __restrict__ poses,
-                                                   const double4* __restrict__ spheres, long long total_tiles,
+                                                   const double4* __restrict__ spheres,
+                                                   const int4* __restrict__ tile_info, long long total_tiles,
                                                    unsigned long long* __restrict__ tile_mask,
-                                                   unsigned int* __restrict__ d_stamp,
-                                                   int32_t* __restrict__ near_count,
-                                                   int32_t* __restrict__ chunk_list_count) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(d_stamp, near_count, chunk_list_count);
+                                                   int32_t* __restrict__ cand_list,
+                                                   int32_t* __restrict__ cand_count) {
   __shared__ double P[kMaxGrids][12];
   __shared__ double box[kMaxGrids][6];
   __shared__ double rad[kMaxGrids];
-  __shared__ long long toff[kMaxGrids + 1];
   __shared__ unsigned long long blanks;
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) P[i / 12][i % 12] = poses[i];
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
     const GridDev& G = grids[g];
-    toff[g] = G.tile_off;
     rad[g] = sqrt(G.cull_r2);
     const double* q = G.blank_prm;
     double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
@@ -401,17 +400,16 @@ __global__ void __launch_bounds__(256) k_tile_masks(const GridDev* __restrict__ 
     }
   }
   if (threadIdx.x == 0) {
-    toff[ngrids] = total_tiles;
     unsigned long long m = 0;
     for (int g = 0; g < ngrids; ++g)
       if (grids[g].blank_kind != OV_BLANK_NONE) m |= 1ull << g;
     blanks = m;
   }
   __syncthreads();
-  for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
-       tile += (long long)gridDim.x * blockDim.x) {
-    const int A = grid_of_node(toff, ngrids, tile);
-    const double4 sp = spheres[tile];
+  for (long long sub = (long long)blockIdx.x * blockDim.x + threadIdx.x; sub < total_tiles * kSubPerTile;
+       sub += (long long)gridDim.x * blockDim.x) {
+    const int A = tile_info[sub / kSubPerTile].x;
+    const double4 sp = spheres[sub];
     const double* pa = P[A];
     const double w0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
     const double w1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
@@ -432,133 +430,237 @@ __global__ void __launch_bounds__(256) k_tile_masks(const GridDev* __restrict__ 
       const double ez = fmax(fmax(box[B][2] - z, z - box[B][5]), 0.0);
       if (ex * ex + ey * ey + ez * ez <= r * r) mask |= 1ull << B;
     }
-    tile_mask[tile] = mask;
+    tile_mask[sub] = mask;
+    if (mask) cand_list[atomicAdd(cand_count, 1)] = (int32_t)sub;
   }
 }
 
-// Hole cut over node tiles (kTileI x kTileJ x kTileK, one block per tile at a
-// time). A tile that no blank region can reach (empty mask) holds no hole:
-// its coordinates are not read and its flags are written directly (field,
-// or fringe on outer-boundary layers). Other tiles test every node against
-// the regions in the tile's mask only. A tile that holds a hole puts the
-// tiles within buffer reach of it on the near list for the fringe pass.
-template <typename CT>
-__global__ void __launch_bounds__(256) k_holecut_tiles(const GridDev* __restrict__ grids, int ngrids,
-                                                      const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                      const unsigned long long* __restrict__ tile_mask,
-                                                      long long total_tiles, const unsigned int* __restrict__ d_stamp,
-                                                      unsigned int* __restrict__ tile_near,
-                                                      int32_t* __restrict__ near_list,
-                                                      int32_t* __restrict__ near_count,
-                                                      unsigned long long* __restrict__ stats) {
-  __shared__ HoleLds L;
-  __shared__ long long toff[kMaxGrids + 1];
-  holecut_stage<CT>(L, grids, ngrids, poses);
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
-  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
+// Geometry of every grid for the tile kernels, staged in LDS.
+struct TileGeo {
+  int ni, nj, nk, per, tiles_i, tiles_j;
+  int o[6];
+  long long tile_off;
+};
+
+__device__ __forceinline__ void stage_tile_geo(TileGeo* tg, const GridDev* __restrict__ grids, int ngrids) {
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
+    const GridDev& G = grids[g];
+    TileGeo t;
+    t.ni = G.ni;
+    t.nj = G.nj;
+    t.nk = G.nk;
+    t.per = G.per;
+    t.tiles_i = G.tiles_i;
+    t.tiles_j = G.tiles_j;
+    for (int f = 0; f < 6; ++f) t.o[f] = G.outer[f];
+    t.tile_off = G.tile_off;
+    tg[g] = t;
+  }
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// The culled hole cut runs in three kernels, in stream order:
+//  k_flag_fill       every node's flag as if no blank region reached it
+//                    (field, or fringe on outer-boundary layers);
+//  k_tile_masks      which blank regions may reach each sub-tile, listing the
+//                    sub-tiles with any (the candidates);
+//  k_holecut_cand    the candidate sub-tiles' nodes tested, their flags
+//                    rewritten, and the tiles within buffer reach of a hole
+//                    put on the near list for the fringe pass.
+// The fill is a pure store stream over work units of kUnitI x kTileJ x 1
+// nodes (rows j0..j0+7 of plane k): lane l writes the 16 bytes of nodes
+// i0 + 16 (l % 8) .. + 15 of row j0 + l / 8, so 8 lanes write a 128-byte row
+// span; each wavefront takes 4 consecutive units per iteration, their table
+// entries loaded together, keeping 4 KB of stores in flight.
+static_assert(kUnitI == 8 * 16 && kTileJ == 8 && kTileI == 4 * kSubI, "unit and sub-tile layout");
+
+typedef unsigned int ov_u4 __attribute__((ext_vector_type(4)));
+constexpr int kFillGroup = 4;
+
+__global__ void __launch_bounds__(256) k_flag_fill(const GridDev* __restrict__ grids, int ngrids,
+                                                  uint8_t* __restrict__ flags, const int4* __restrict__ unit_info,
+                                                  const int4* __restrict__ unit_where, long long total_units,
+                                                  unsigned int* __restrict__ d_stamp, int32_t* __restrict__ near_count,
+                                                  int32_t* __restrict__ chunk_list_count,
+                                                  int32_t* __restrict__ cand_count) {
+  __shared__ TileGeo TG[kMaxGrids];
+  __shared__ int has_outer[kMaxGrids];
+  stage_tile_geo(TG, grids, ngrids);
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) has_outer[g] = grids[g].has_outer;
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(d_stamp, near_count, chunk_list_count, cand_count);
   __syncthreads();
-  const unsigned int stamp = *d_stamp;
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
-  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    const unsigned long long mask = tile_mask[tile];
-    const int A = grid_of_node(toff, ngrids, tile);
-    const GeomR G(grids[A]);
-    const int t = (int)(tile - toff[A]);
-    const int ti = t % G.tiles_i, tj = (t / G.tiles_i) % G.tiles_j, tk = t / (G.tiles_i * G.tiles_j);
-    const int i0 = ti * kTileI, j0 = tj * kTileJ, k0 = tk * kTileK;
-    uint8_t* fa = flags + L.off[A];
-    const bool outer = L.outer[A] != 0;
-    bool hole = false;
-    if (mask == 0) {
-      // no hole possible: each thread writes 16 flag bytes of one tile row
-      const int row = threadIdx.x >> 2, part = threadIdx.x & 3;
-      const int i = i0 + part * 16, j = j0 + (row & 7), k = k0 + (row >> 3);
-      if (i < G.ni && j < G.nj && k < G.nk) {
-        const long long m = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-        uint8_t* dst = fa + m;
-        const int n = min(16, G.ni - i);
-        const bool row_outer = outer && (j < G.o2 || j >= G.nj - G.o3 || k < G.o4 || k >= G.nk - G.o5);
-        if (!outer || (!row_outer && i >= G.o0 && i + 16 <= G.ni - G.o1)) {
-          if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
-            *reinterpret_cast<uint4*>(dst) = make_uint4(0u, 0u, 0u, 0u);
-          } else {
-            for (int q = 0; q < n; ++q) dst[q] = (uint8_t)OV_STATE_FIELD;
+  const int lane = threadIdx.x & 63, part = lane & 7, row = lane >> 3;
+  const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+  const long long last = total_units - 1;
+  for (long long u0 = wave * kFillGroup; u0 < total_units; u0 += nwaves * kFillGroup) {
+    int4 info[kFillGroup];
+#pragma unroll
+    for (int q = 0; q < kFillGroup; ++q) info[q] = unit_info[min(u0 + q, last)];
+#pragma unroll
+    for (int q = 0; q < kFillGroup; ++q) {
+      if (u0 + q > last) break;
+      const int A = uniform_i32(info[q].z);
+      const int cols = info[q].w >> 8, rows = info[q].w & 255;
+      const TileGeo& G = TG[A];
+      const int ni = G.ni;
+      if (part * 16 >= cols || row >= rows) continue;
+      const int n = min(16, cols - part * 16);
+      uint8_t* dst = flags + info[q].x + row * ni + part * 16;
+      if (!has_outer[A]) {
+        if (n == 16 && (((uintptr_t)dst) & 15) == 0)
+          __builtin_nontemporal_store((ov_u4){0u, 0u, 0u, 0u}, (ov_u4*)dst);
+        else
+          for (int e = 0; e < n; ++e) dst[e] = (uint8_t)OV_STATE_FIELD;
+      } else {
+        const int4 wh = unit_where[u0 + q];
+        const int i = wh.x + part * 16, j = wh.y + row, k = wh.z;
+        const bool row_outer = j < G.o[2] || j >= G.nj - G.o[3] || k < G.o[4] || k >= G.nk - G.o[5];
+        uint32_t w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          uint32_t word = 0u;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ii = i + 4 * c + r;
+            const bool ob = row_outer || ii < G.o[0] || ii >= ni - G.o[1];
+            word |= (ob ? (uint32_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint32_t)OV_STATE_FIELD) << (8 * r);
           }
+          w[c] = word;
+        }
+        if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
+          *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
         } else {
-          for (int q = 0; q < n; ++q)
-            dst[q] = (row_outer || i + q < G.o0 || i + q >= G.ni - G.o1) ? (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2))
-                                                                           : (uint8_t)OV_STATE_FIELD;
-        }
-      }
-    } else {
-      if (threadIdx.x == 0) {
-        unsigned long long n =
-            (unsigned long long)min(kTileI, G.ni - i0) * min(kTileJ, G.nj - j0) * min(kTileK, G.nk - k0);
-        atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], n);
-      }
-      const CT* Xa = (const CT*)L.X[A];
-      const CT* Ya = (const CT*)L.Y[A];
-      const CT* Za = (const CT*)L.Z[A];
-      // 4 nodes per batch: their coordinates are loaded before any flag store
-      for (int e0 = threadIdx.x; e0 < kTileI * kTileJ * kTileK; e0 += 4 * blockDim.x) {
-        long long m[4];
-        bool ok[4], onb[4];
-        CT X[4], Y[4], Z[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = e0 + r * blockDim.x;
-          const int i = i0 + (e & 63), j = j0 + ((e >> 6) & 7), k = k0 + (e >> 9);
-          ok[r] = e < kTileI * kTileJ * kTileK && i < G.ni && j < G.nj && k < G.nk;
-          m[r] = (long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-          onb[r] = outer && G.on_outer(i, j, k);
-          if (ok[r]) {
-            X[r] = Xa[m[r]];
-            Y[r] = Ya[m[r]];
-            Z[r] = Za[m[r]];
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (!ok[r]) continue;
-          const int cause = holecut_node<CT>(L, grids, A, m[r], X[r], Y[r], Z[r], mask);
-          uint8_t f = (uint8_t)OV_STATE_FIELD;
-          if (cause >= 0) {
-            f = (uint8_t)(kHole | (cause << 2));
-            hole = true;
-          } else if (onb[r]) {
-            f = (uint8_t)(kFringe | (OV_CAUSE_BOUNDARY << 2));
-          }
-          fa[m[r]] = f;
+          for (int e = 0; e < 16; ++e)
+            if (e < n) dst[e] = (uint8_t)(w[e >> 2] >> (8 * (e & 3)));
         }
       }
     }
-    hole = __syncthreads_or(hole);
-    if (hole && threadIdx.x < 125)
-      mark_near(threadIdx.x, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-                near_list, near_count);
+  }
+}
+
+// Candidate sub-tiles (kSubI x kTileJ x kTileK nodes), one wavefront each at
+// a time: lane l takes the 16 nodes i0 .. i0 + 15 of row (j0 + l % 8, k0 +
+// l / 8), loads their coordinates in batches of 4, tests them against the
+// blank regions of the sub-tile's mask only and writes their 16 flags.
+template <typename CT>
+__global__ void __launch_bounds__(256) k_holecut_cand(const GridDev* __restrict__ grids, int ngrids,
+                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
+                                                     const unsigned long long* __restrict__ sub_mask,
+                                                     const int32_t* __restrict__ cand_list,
+                                                     const int32_t* __restrict__ cand_count,
+                                                     const int4* __restrict__ tile_info,
+                                                     const unsigned int* __restrict__ d_stamp,
+                                                     unsigned int* __restrict__ tile_near,
+                                                     int32_t* __restrict__ near_list,
+                                                     int32_t* __restrict__ near_count,
+                                                     unsigned long long* __restrict__ stats) {
+  __shared__ HoleLds L;
+  __shared__ TileGeo TG[kMaxGrids];
+  stage_tile_geo(TG, grids, ngrids);
+  holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
+  const unsigned int stamp = *d_stamp;
+  const int lane = threadIdx.x & 63;
+  const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+  const long long ncand = *cand_count;
+  for (long long c = wave; c < ncand; c += nwaves) {
+    const int sub = cand_list[c];
+    const unsigned long long mask = uniform_u64(sub_mask[sub]);
+    const int4 ti = tile_info[sub / kSubPerTile];
+    const int A = uniform_i32(ti.x);
+    const TileGeo& G = TG[A];
+    const int ni = G.ni, nj = G.nj, nk = G.nk;
+    const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
+    const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI, j = ti.z * kTileJ + (lane & 7),
+              k = ti.w * kTileK + (lane >> 3);
+    const bool ok = i < ni && j < nj && k < nk;
+    const int n = ok ? min(kSubI, ni - i) : 0;
+    const bool outer = L.outer[A] != 0;
+    const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
+    bool hole = false;
+    if (ok) {
+      const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+      uint8_t* dst = flags + L.off[A] + m0;
+      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+      uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;  // the 16 flag bytes
+      // 16 nodes in batches of 4: a batch's coordinates are loaded before
+      // any of its nodes is tested
+#pragma unroll 1
+      for (int b0 = 0; b0 < kSubI; b0 += 4) {
+        uint32_t word = 0u;
+        CT X[4], Y[4], Z[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (b0 + r < n) {
+            X[r] = Xa[b0 + r];
+            Y[r] = Ya[b0 + r];
+            Z[r] = Za[b0 + r];
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = b0 + r;
+          if (e >= n) continue;
+          const int cause = holecut_node<CT>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
+          uint32_t f = OV_STATE_FIELD;
+          if (cause >= 0) {
+            f = kHole | (cause << 2);
+            hole = true;
+          } else if (outer && (row_outer || i + e < o0 || i + e >= ni - o1)) {
+            f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+          }
+          word |= f << (8 * r);
+        }
+        w0 = b0 == 0 ? word : w0;
+        w1 = b0 == 4 ? word : w1;
+        w2 = b0 == 8 ? word : w2;
+        w3 = b0 == 12 ? word : w3;
+      }
+      if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
+        *reinterpret_cast<uint4*>(dst) = make_uint4(w0, w1, w2, w3);
+      } else {
+        for (int e = 0; e < n; ++e) {
+          const uint32_t wd = e < 4 ? w0 : e < 8 ? w1 : e < 12 ? w2 : w3;
+          dst[e] = (uint8_t)(wd >> (8 * (e & 3)));
+        }
+      }
+    }
+    int nr = n;
+    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
+    if (lane == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+    if (__any(hole))
+      for (int e = lane; e < 125; e += 64)
+        mark_near(e, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                  near_list, near_count);
   }
 }
 
 // Near list from the streaming hole cut's per-tile hole stamps: one thread per
 // tile; a tile holding a hole lists its 125 reach combinations.
-__global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restrict__ grids, int ngrids,
+__global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restrict__ grids,
                                                         const unsigned int* __restrict__ tile_hole,
-                                                        long long total_tiles, const unsigned int* __restrict__ d_stamp,
+                                                        const int4* __restrict__ tile_info, long long total_tiles,
+                                                        const unsigned int* __restrict__ d_stamp,
                                                         unsigned int* __restrict__ tile_near,
                                                         int32_t* __restrict__ near_list,
                                                         int32_t* __restrict__ near_count) {
-  __shared__ long long toff[kMaxGrids + 1];
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
-  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
-  __syncthreads();
   const unsigned int stamp = *d_stamp;
   for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
        tile += (long long)gridDim.x * blockDim.x) {
     if (tile_hole[tile] != stamp) continue;
-    const int A = grid_of_node(toff, ngrids, tile);
-    const GeomR G(grids[A]);
-    const int t = (int)(tile - toff[A]);
-    const int ti = t % G.tiles_i, tj = (t / G.tiles_i) % G.tiles_j, tk = t / (G.tiles_i * G.tiles_j);
+    const int4 info = tile_info[tile];
+    const GeomR G(grids[info.x]);
+    const int ti = info.y, tj = info.z, tk = info.w;
     for (int e = 0; e < 125; ++e)
       mark_near(e, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near, near_list,
                 near_count);
@@ -590,28 +692,34 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   const int ng = (int)ctx->grids.size();
   const long long nt = ctx->total_tiles;
   if (ctx->cull) {
-    long long mb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
+    const long long nu = ctx->total_units;
+    long long fb = std::max(1LL, std::min((nu + 4 * kFillGroup - 1) / (4 * kFillGroup), (long long)ctx->num_cus * 8));
+    hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, ctx->d_grids, ng, flags, ctx->d_unit_info,
+                       ctx->d_unit_where, nu, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count,
+                       ctx->d_cand_count);
+    long long mb = std::max(1LL, std::min((nt * kSubPerTile + 255) / 256, (long long)ctx->num_cus * 4));
     hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)mb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                       (const double4*)ctx->d_tile_sphere, nt, ctx->d_tile_mask, ctx->d_stamp, ctx->d_near_count,
-                       ctx->d_chunk_list_count);
-    int per_cu = ctx->persist > 0 ? ctx->persist : 8;
-    long long grid = std::max(1LL, std::min(nt, (long long)ctx->num_cus * per_cu));
+                       (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nt, ctx->d_tile_mask, ctx->d_cand_list,
+                       ctx->d_cand_count);
+    int per_cu = ctx->persist > 0 ? ctx->persist : 4;
+    long long cb = std::max(1LL, std::min((nt * kSubPerTile + 3) / 4, (long long)ctx->num_cus * per_cu));
     if (ctx->precision == OV_MIXED)
-      hipLaunchKernelGGL(k_holecut_tiles<float>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                         flags, ctx->d_tile_mask, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list,
-                         ctx->d_near_count, ctx->d_stats);
+      hipLaunchKernelGGL(k_holecut_cand<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses, flags,
+                         ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info, ctx->d_stamp,
+                         ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
     else
-      hipLaunchKernelGGL(k_holecut_tiles<double>, dim3((unsigned)grid), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                         flags, ctx->d_tile_mask, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list,
-                         ctx->d_near_count, ctx->d_stats);
+      hipLaunchKernelGGL(k_holecut_cand<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses, flags,
+                         ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info, ctx->d_stamp,
+                         ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count);
+  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count,
+                     ctx->d_cand_count);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s);
   else launch_holecut_t<double>(ctx, poses, flags, s);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
-  hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, ng, ctx->d_tile_hole, nt,
-                     ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count);
+  hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, ctx->d_tile_hole,
+                     ctx->d_tile_info, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count);
   return hipGetLastError();
 }
 
@@ -635,7 +743,7 @@ __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
 
 template <int NF>
 __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict__ grids, int ngrids,
-                                                     uint8_t* __restrict__ flags, long long total_tiles,
+                                                     uint8_t* __restrict__ flags, const int4* __restrict__ tile_info,
                                                      const int32_t* __restrict__ near_list,
                                                      const int32_t* __restrict__ near_count,
                                                      const unsigned int* __restrict__ d_stamp,
@@ -649,22 +757,18 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
   __shared__ uint8_t a[EK][EJ][EI];
   __shared__ uint8_t b[EK][EJ][kTileI];
   __shared__ uint8_t c[EK][kTileJ][kTileI];
-  __shared__ long long toff[kMaxGrids + 1];
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) toff[g] = grids[g].tile_off;
-  if (threadIdx.x == 0) toff[ngrids] = total_tiles;
+  __shared__ TileGeo TG[kMaxGrids];
+  __shared__ long long noffs[kMaxGrids];
+  stage_tile_geo(TG, grids, ngrids);
+  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) noffs[g] = grids[g].node_off;
   __syncthreads();
   const int ntl = *near_count;
   const unsigned int stamp = *d_stamp;
   for (int idx = blockIdx.x; idx < ntl; idx += gridDim.x) {
-    const long long tile = near_list[idx];
-    const GridDev& GD = grids[grid_of_node(toff, ngrids, tile)];
-    struct {
-      int ni, nj, nk, per, tiles_i, tiles_j;
-    } const G = {GD.ni, GD.nj, GD.nk, GD.per, GD.tiles_i, GD.tiles_j};
-    const long long noff = GD.node_off;
-    const int t = (int)(tile - GD.tile_off);
-    const int i0 = (t % G.tiles_i) * kTileI, j0 = ((t / G.tiles_i) % G.tiles_j) * kTileJ,
-              k0 = (t / (G.tiles_i * G.tiles_j)) * kTileK;
+    const int4 info = tile_info[near_list[idx]];
+    const TileGeo G = TG[info.x];
+    const long long noff = noffs[info.x];
+    const int i0 = info.y * kTileI, j0 = info.z * kTileJ, k0 = info.w * kTileK;
     // chunks holding this tile's nodes: one tile row (j, k) per thread
     if (threadIdx.x < kTileJ * kTileK) {
       const int j = j0 + (threadIdx.x & 7), k = k0 + (threadIdx.x >> 3);
@@ -769,7 +873,7 @@ hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
   // persistent blocks over the near list (its length is on the device)
   long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 4));
 #define OV_FRINGE_ARGS                                                                                            \
-  ctx->d_grids, ng, flags, ctx->total_tiles, ctx->d_near_list, ctx->d_near_count, ctx->d_stamp, ctx->d_chunk_static, \
+  ctx->d_grids, ng, flags, ctx->d_tile_info, ctx->d_near_list, ctx->d_near_count, ctx->d_stamp, ctx->d_chunk_static, \
       ctx->d_chunk_stamp, ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks
   switch (nf) {
     case 0:
@@ -791,14 +895,16 @@ hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
 
 // ================================================================ compaction
 // Ordered stream compaction of query nodes over 4096-node chunks (in the
-// global node numbering), in three passes: count per listed chunk (the
+// global node numbering), in three passes. (1) Count each listed chunk (the
 // static list of chunks with outer-boundary nodes, then this step's list of
-// chunks touching near tiles; no other chunk can hold a query node), an
-// exclusive scan of all chunk counts (one block; it also zeroes the counts
-// for the next step), then each listed chunk with queries writes them at its
-// offset in node order. Inside a chunk a thread owns 16 consecutive flag
-// bytes; the wave prefix of the per-thread counts is a shuffle scan and the
-// wave totals are scanned in LDS.
+// chunks touching near tiles; no other chunk can hold a query node): the
+// count is stored with this step's stamp and added to its superchunk of 64
+// chunks. (2) One block scans the superchunk counts (and zeroes them). (3)
+// Each listed chunk with queries takes its superchunk's offset plus the
+// stamped counts of the lower chunks of its superchunk (one 64-lane load
+// and a wavefront sum) and writes its query nodes in node order. Inside a
+// chunk a thread owns 16 consecutive flag bytes; the wave prefix of the
+// per-thread counts is a shuffle scan and the wave totals are scanned in LDS.
 __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, long long total, uint32_t& mask) {
   uint8_t v[16];
   if (n0 + 16 <= total) {
@@ -817,12 +923,15 @@ __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, lo
 }
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
-                                                                   int32_t* __restrict__ counts,
+                                                                   unsigned long long* __restrict__ counts,
+                                                                   int32_t* __restrict__ super_counts,
                                                                    const int32_t* __restrict__ chunk_list,
                                                                    const int32_t* __restrict__ chunk_list_count,
-                                                                   long long n_static) {
+                                                                   long long n_static,
+                                                                   const unsigned int* __restrict__ d_stamp) {
   __shared__ int red[kCompactThreads / 64];
   const long long nl = n_static + *chunk_list_count;
+  const unsigned int stamp = *d_stamp;
   for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
     const long long ch = chunk_list[e];
     uint32_t mask;
@@ -833,47 +942,43 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
     if (threadIdx.x == 0) {
       int sum = 0;
       for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[w];
-      counts[ch] = sum;
+      counts[ch] = ((unsigned long long)stamp << 32) | (unsigned int)sum;
+      if (sum) atomicAdd(&super_counts[(ch / kSuperChunk) * kSuperSlots + ch % kSuperSlots], sum);
     }
     __syncthreads();
   }
 }
 
-// n4: number of int4 groups of counts (counts padded with zeros); offsets
-// has 4 n4 + 1 entries, the last one the total.
-__global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ counts, long long n4,
+// Exclusive scan of the superchunk counts in one block (each thread a
+// contiguous run); offsets gets nsuper + 1 entries, the last the total.
+__global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ super_counts, long long nsuper,
                                                       long long* __restrict__ offsets, long long* __restrict__ d_count,
                                                       long long capacity, int32_t* __restrict__ status) {
   __shared__ long long wtot[1024 / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long per = (n4 + blockDim.x - 1) / blockDim.x;
-  const long long b0 = min(n4, (long long)threadIdx.x * per), b1 = min(n4, b0 + per);
-  int4* c4 = reinterpret_cast<int4*>(counts);
+  const long long per = (nsuper + blockDim.x - 1) / blockDim.x;
+  const long long b0 = min(nsuper, (long long)threadIdx.x * per), b1 = min(nsuper, b0 + per);
   long long sum = 0;
-  for (long long i = b0; i < b1; ++i) {
-    const int4 v = c4[i];
-    sum += (long long)v.x + v.y + v.z + v.w;
-  }
+  for (long long i = b0; i < b1; ++i)
+    for (int q = 0; q < kSuperSlots; ++q) sum += super_counts[i * kSuperSlots + q];
   long long inc = sum;
   for (int o = 1; o < 64; o <<= 1) {
-    long long v = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += v;
+    long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
   }
   if (lane == 63) wtot[wave] = inc;
   __syncthreads();
   long long run = inc - sum;
   for (int w = 0; w < wave; ++w) run += wtot[w];
   for (long long i = b0; i < b1; ++i) {
-    const int4 v = c4[i];
-    offsets[4 * i] = run;
-    offsets[4 * i + 1] = run + v.x;
-    offsets[4 * i + 2] = run + v.x + v.y;
-    offsets[4 * i + 3] = run + v.x + v.y + v.z;
-    run += (long long)v.x + v.y + v.z + v.w;
-    c4[i] = make_int4(0, 0, 0, 0);  // ready for the next step's count
+    offsets[i] = run;
+    for (int q = 0; q < kSuperSlots; ++q) {
+      run += super_counts[i * kSuperSlots + q];
+      super_counts[i * kSuperSlots + q] = 0;  // ready for the next step's count
+    }
   }
   if (threadIdx.x == blockDim.x - 1) {
-    offsets[4 * n4] = run;
+    offsets[nsuper] = run;
     *d_count = run;
     if (run > capacity) atomicOr(status, OV_DEV_CAPACITY);
   }
@@ -881,10 +986,14 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ cou
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev* __restrict__ grids, int ngrids,
                                                                    const uint8_t* __restrict__ flags, long long total,
-                                                                   const long long* __restrict__ offsets,
+                                                                   const unsigned long long* __restrict__ counts,
+                                                                   long long nchunks,
+                                                                   const long long* __restrict__ super_offsets,
                                                                    const int32_t* __restrict__ chunk_list,
                                                                    const int32_t* __restrict__ chunk_list_count,
-                                                                   long long n_static, int32_t* __restrict__ q_grid,
+                                                                   long long n_static,
+                                                                   const unsigned int* __restrict__ d_stamp,
+                                                                   int32_t* __restrict__ q_grid,
                                                                    int32_t* __restrict__ q_node, long long capacity) {
   __shared__ int wsum[kCompactThreads / 64];
   __shared__ long long off[kMaxGrids + 1];
@@ -893,18 +1002,26 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long nl = n_static + *chunk_list_count;
+  const unsigned int stamp = *d_stamp;
   for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
     const long long ch = chunk_list[e];
-    const long long base = offsets[ch];
-    if (offsets[ch + 1] == base || base >= capacity) continue;  // nothing to write (same in every thread)
+    // this step's counts of the chunks of ch's superchunk below ch (every
+    // wavefront forms the same sum)
+    const long long c = ch - ch % kSuperChunk + lane;
+    const unsigned long long v = (c < ch && c < nchunks) ? counts[c] : 0ull;
+    long long below = (unsigned int)(v >> 32) == stamp ? (long long)(unsigned int)v : 0;
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
+    const long long base = super_offsets[ch / kSuperChunk] + below;
+    const unsigned long long own = counts[ch];
+    if ((unsigned int)own == 0u || base >= capacity) continue;  // nothing to write (same in every thread)
     long long n0 = ch * kCompactChunk + threadIdx.x * 16;
     uint32_t mask;
     int cnt = count_fringe16(flags, n0, total, mask);
     // inclusive wave scan
     int inc = cnt;
     for (int o = 1; o < 64; o <<= 1) {
-      int v = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += v;
+      int t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
     }
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
@@ -933,12 +1050,14 @@ hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, in
   long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_chunk_counts, (ctx->nchunks + 3) / 4,
-                     ctx->d_chunk_offsets, d_count, capacity, ctx->d_status);
+                     ctx->d_chunk_counts, ctx->d_super_counts, ctx->d_chunk_list, ctx->d_chunk_list_count,
+                     ctx->n_static_chunks, ctx->d_stamp);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_super_counts, ctx->nsuper,
+                     ctx->d_super_offsets, d_count, capacity, ctx->d_status);
   hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
-                     (int)ctx->grids.size(), flags, total, ctx->d_chunk_offsets, ctx->d_chunk_list,
-                     ctx->d_chunk_list_count, ctx->n_static_chunks, q_grid, q_node, capacity);
+                     (int)ctx->grids.size(), flags, total, ctx->d_chunk_counts, ctx->nchunks, ctx->d_super_offsets,
+                     ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks, ctx->d_stamp, q_grid, q_node,
+                     capacity);
   return hipGetLastError();
 }
 
@@ -1007,12 +1126,12 @@ __global__ void k_transform(const GridDev* __restrict__ grids, const double* __r
     const GridDev& G = grids[g];
     const double* p = poses + 12 * g;
     if (sizeof(T) == 8) {
-      double X = G.X[m], Y = G.Y[m], Z = G.Z[m];
+      double X = gp(G.X)[m], Y = gp(G.Y)[m], Z = gp(G.Z)[m];
       qx[q] = (T)(p[0] * X + p[1] * Y + p[2] * Z);
       qx[capacity + q] = (T)(p[3] * X + p[4] * Y + p[5] * Z);
       qx[2 * capacity + q] = (T)(p[6] * X + p[7] * Y + p[8] * Z);
     } else {
-      float X = G.Xf[m], Y = G.Yf[m], Z = G.Zf[m];
+      float X = gp(G.Xf)[m], Y = gp(G.Yf)[m], Z = gp(G.Zf)[m];
       qx[q] = (T)((float)p[0] * X + (float)p[1] * Y + (float)p[2] * Z);
       qx[capacity + q] = (T)((float)p[3] * X + (float)p[4] * Y + (float)p[5] * Z);
       qx[2 * capacity + q] = (T)((float)p[6] * X + (float)p[7] * Y + (float)p[8] * Z);

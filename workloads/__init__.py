@@ -392,7 +392,7 @@ def c1_small(steps=4, seed=11) -> Workload:
 # the body (inner shell surface), the blank region cut from every other grid,
 # and the outer shell surface.
 FISH_BODY = (0.5, 0.07, 0.12)
-FISH_BLANK = (0.65, 0.22, 0.18)
+FISH_BLANK = (0.58, 0.12, 0.16)
 FISH_OUTER = (0.95, 0.45, 0.38)
 # Diamond: front fish, two side fish (lateral +-0.45 L, 1.2 L behind) and
 # the last fish 2.4 L behind (the paper's side offset; a shorter axial
