@@ -94,7 +94,6 @@ enum ov_blank_kind {
 #define OV_DEV_CAPACITY 1     /* fringe count exceeded capacity; entries past capacity not written */
 #define OV_DEV_WALK_LIMIT 2   /* at least one walk hit max_walk (the fallback still ran) */
 #define OV_DEV_NONFINITE 4    /* a non-finite query coordinate was met (the query became an orphan) */
-#define OV_DEV_FIX_OVERFLOW 8 /* mixed precision: the FP64 correction queue overflowed */
 
 /* Options (ov_set_option). */
 enum ov_option {
@@ -105,8 +104,11 @@ enum ov_option {
     OV_OPT_HOLECUT_BLOCK = 5,/* threads per block of the hole cut (64..1024, multiple of 64) */
     OV_OPT_HOLECUT_NPT = 6, /* 16-byte coordinate vectors per lane per chunk of the hole cut (1, 2 or 4) */
     OV_OPT_PERSIST = 7,     /* workgroups per CU of persistent launches (1..32; 0 = one item per thread) */
-    OV_OPT_HOLECUT_CULL = 8 /* 1 (default): the hole cut skips the coordinates of node tiles whose bounding
-                               sphere cannot reach any blank region (same flags); 0: stream every node */
+    OV_OPT_HOLECUT_CULL = 8,/* 1 (default): the hole cut reads the coordinates only of 16x8x8 sub-tiles that
+                               some blank region may reach (bounding sphere vs. the region's enclosing sphere and
+                               body-frame box; same flags); 0: stream every node */
+    OV_OPT_HOLECUT_NPL = 9  /* culled hole cut, candidate nodes per lane: 16 (default, one wavefront per
+                               sub-tile) or 4 (one block per sub-tile: shorter latency when candidates are few) */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.

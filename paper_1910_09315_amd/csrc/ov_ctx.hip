@@ -331,6 +331,21 @@ int build_shadows(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   return OV_OK;
 }
 
+// Flags of a grid with outer-boundary layers before any hole cut: fringe
+// (cause 63) on its outer layers, field elsewhere.
+__global__ void k_base_flags(GridDev g, uint8_t* __restrict__ out) {
+  for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < g.nnodes;
+       m += (long long)gridDim.x * blockDim.x) {
+    const long long plane = (long long)g.ni * g.nj;
+    const int k = (int)(m / plane);
+    const long long r = m - (long long)k * plane;
+    const int j = (int)(r / g.ni), i = (int)(r - (long long)j * g.ni);
+    const bool on = i < g.outer[0] || i >= g.ni - g.outer[1] || j < g.outer[2] || j >= g.nj - g.outer[3] ||
+                    k < g.outer[4] || k >= g.nk - g.outer[5];
+    out[m] = on ? (uint8_t)(OV_STATE_FRINGE | (OV_CAUSE_BOUNDARY << 2)) : (uint8_t)OV_STATE_FIELD;
+  }
+}
+
 __global__ void k_pack_xyz(const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
                            long long n, double4* __restrict__ P) {
   for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (long long)gridDim.x * blockDim.x)
@@ -400,8 +415,8 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_warm_grid);
   (void)hipFree(ctx->d_tile_sphere);
   (void)hipFree(ctx->d_tile_info);
-  (void)hipFree(ctx->d_unit_info);
-  (void)hipFree(ctx->d_unit_where);
+  (void)hipFree(ctx->d_base_flags);
+  (void)hipFree(ctx->d_fill_ranges);
   (void)hipFree(ctx->d_stamp);
   (void)hipFree(ctx->d_tile_mask);
   (void)hipFree(ctx->d_tile_hole);
@@ -537,31 +552,39 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     }
     HIPCHK(hipMalloc(&ctx->d_tile_info, sizeof(int4) * nt), "hipMalloc tile info");
     HIPCHK(hipMemcpy(ctx->d_tile_info, info.data(), sizeof(int4) * nt, hipMemcpyHostToDevice), "tile info copy");
-    // hole-cut units: kUnitI x kTileJ x 1 nodes, i fastest, then j, then k;
-    // per unit (flag offset of its first node, its first tile, grid,
-    // columns << 8 | rows present) and (i0, j0, k, 0)
-    std::vector<int4> units, where;
+    // fill ranges: consecutive grids with (kind 1) or without (kind 0) outer layers
+    std::vector<long long> ranges;
+    long long words = 0;
     for (size_t gi = 0; gi < ctx->grids.size(); ++gi) {
       const GridDev& g = ctx->grids[gi].d;
-      const int ui_n = (g.ni + kUnitI - 1) / kUnitI;
-      for (int k = 0; k < g.nk; ++k)
-        for (int uj = 0; uj < g.tiles_j; ++uj)
-          for (int ui = 0; ui < ui_n; ++ui) {
-            const int i0 = ui * kUnitI, j0 = uj * kTileJ;
-            const long long base = g.node_off + i0 + (long long)g.ni * (j0 + (long long)g.nj * k);
-            const long long tile = g.tile_off + (i0 >> 6) + (long long)g.tiles_i * (uj + (long long)g.tiles_j * (k >> 3));
-            const int cols = std::min(kUnitI, g.ni - i0), rows = std::min(kTileJ, g.nj - j0);
-            units.push_back(make_int4((int)base, (int)tile, (int)gi, (cols << 8) | rows));
-            where.push_back(make_int4(i0, j0, k, 0));
-          }
+      const long long kind = g.has_outer ? 1 : 0;
+      const long long a = g.node_off, b = g.node_off + g.nnodes;
+      if (!ranges.empty() && ranges[ranges.size() - 1] == kind && ranges[ranges.size() - 3] == a) {
+        ranges[ranges.size() - 3] = b;  // extend the previous range
+      } else {
+        ranges.push_back(a);
+        ranges.push_back(b);
+        ranges.push_back(0);
+        ranges.push_back(kind);
+      }
     }
-    ctx->total_units = (long long)units.size();
-    HIPCHK(hipMalloc(&ctx->d_unit_info, sizeof(int4) * units.size()), "hipMalloc unit info");
-    HIPCHK(hipMemcpy(ctx->d_unit_info, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice),
-           "unit info copy");
-    HIPCHK(hipMalloc(&ctx->d_unit_where, sizeof(int4) * where.size()), "hipMalloc unit coordinates");
-    HIPCHK(hipMemcpy(ctx->d_unit_where, where.data(), sizeof(int4) * where.size(), hipMemcpyHostToDevice),
-           "unit coordinates copy");
+    ctx->n_fill_ranges = (int)(ranges.size() / 4);
+    for (int r = 0; r < ctx->n_fill_ranges; ++r) {
+      const long long a = ranges[4 * r], b = ranges[4 * r + 1];
+      ranges[4 * r + 2] = words;
+      const long long wa = (a + 15) / 16, wb = b / 16;
+      words += wb > wa ? wb - wa : 0;
+    }
+    ctx->fill_words = words;
+    HIPCHK(hipMalloc(&ctx->d_base_flags, std::max(1LL, total)), "hipMalloc base flags");
+    for (auto& g : ctx->grids)
+      if (g.d.has_outer)
+        hipLaunchKernelGGL(k_base_flags, dim3(blocks_for(g.d.nnodes)), dim3(256), 0, s, g.d,
+                           ctx->d_base_flags + g.d.node_off);
+    HIPCHK(hipGetLastError(), "base flags");
+    HIPCHK(hipMalloc(&ctx->d_fill_ranges, sizeof(long long) * ranges.size()), "hipMalloc fill ranges");
+    HIPCHK(hipMemcpy(ctx->d_fill_ranges, ranges.data(), sizeof(long long) * ranges.size(), hipMemcpyHostToDevice),
+           "fill ranges copy");
   }
   HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int)), "hipMalloc stamp");
   HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * kSubPerTile * nt), "hipMalloc sub-tile masks");
@@ -640,6 +663,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
     case OV_OPT_HOLECUT_CULL:
       if (v != 0 && v != 1) break;
       ctx->cull = (int)v;
+      return OV_OK;
+    case OV_OPT_HOLECUT_NPL:
+      if (v != 4 && v != 16) break;
+      ctx->holecut_npl = (int)v;
       return OV_OK;
     case OV_OPT_PERSIST:
       if (v < 0 || v > 32) break;

@@ -26,11 +26,9 @@ constexpr int kNewtonMaxIt = 50;
 constexpr double kDetMin = 1e-300;
 
 // Fringe-marking tile (nodes along i, j, k) and the widest buffer supported.
-// The hole cut culls per sub-tile (kSubI nodes along i) and works in units of
-// kUnitI x kTileJ x 1 nodes (16 consecutive nodes per lane).
+// The hole cut culls per sub-tile (kSubI nodes along i).
 constexpr int kTileI = 64, kTileJ = 8, kTileK = 8;
 constexpr int kSubI = 16, kSubPerTile = kTileI / kSubI;
-constexpr int kUnitI = 128;
 constexpr int kMaxNf = 3;
 // Compaction chunk: 256 threads x 16 flag bytes; 64 chunks form a superchunk.
 constexpr int kCompactThreads = 256;
@@ -94,9 +92,15 @@ struct ov_ctx {
   uint8_t* d_warm_grid = nullptr;
   double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
   int4* d_tile_info = nullptr;       // per node tile: (grid, ti, tj, tk)
-  int4* d_unit_info = nullptr;       // per hole-cut unit: (flag offset, first tile, grid, cols << 8 | rows)
-  int4* d_unit_where = nullptr;      // per hole-cut unit: (i0, j0, k, 0)
-  long long total_units = 0;
+  // The flags every step starts from (field everywhere, fringe on the fixed
+  // outer-boundary layers), laid out like the flag array; only the ranges
+  // of grids with outer layers are kept (others are all zero). Consecutive
+  // grids of one kind form a fill range: 4 values per range (start, end,
+  // whole 16-byte words before it, kind 0 = zeros / 1 = copy of the base).
+  uint8_t* d_base_flags = nullptr;
+  long long* d_fill_ranges = nullptr;
+  int n_fill_ranges = 0;
+  long long fill_words = 0;
   // Front-half scratch, written and read in stream order by the hole cut,
   // the fringe pass and the compaction. Each hole cut starts a new stamp; a
   // tile or chunk is on this step's list when its entry equals the stamp, so
@@ -127,6 +131,7 @@ struct ov_ctx {
   int holecut_npt = 2;  // 16-byte coordinate vectors per lane per chunk
   int persist = 0;
   int cull = 1;  // hole cut: skip coordinate reads of tiles no blank region can reach
+  int holecut_npl = 16;  // candidate nodes per lane in the culled hole cut: 16 (wavefront per sub-tile) or 4 (block)
   std::string err;
 };
 

@@ -467,91 +467,147 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
 
 // The culled hole cut runs in three kernels, in stream order:
 //  k_flag_fill       every node's flag as if no blank region reached it
-//                    (field, or fringe on outer-boundary layers);
+//                    (field, or fringe on the fixed outer-boundary layers);
 //  k_tile_masks      which blank regions may reach each sub-tile, listing the
 //                    sub-tiles with any (the candidates);
-//  k_holecut_cand    the candidate sub-tiles' nodes tested, their flags
+//  k_holecut_cand_*  the candidate sub-tiles' nodes tested, their flags
 //                    rewritten, and the tiles within buffer reach of a hole
 //                    put on the near list for the fringe pass.
-// The fill is a pure store stream over work units of kUnitI x kTileJ x 1
-// nodes (rows j0..j0+7 of plane k): lane l writes the 16 bytes of nodes
-// i0 + 16 (l % 8) .. + 15 of row j0 + l / 8, so 8 lanes write a 128-byte row
-// span; each wavefront takes 4 consecutive units per iteration, their table
-// entries loaded together, keeping 4 KB of stores in flight.
-static_assert(kUnitI == 8 * 16 && kTileJ == 8 && kTileI == 4 * kSubI, "unit and sub-tile layout");
+// The fill is a pure stream over the flag array in whole 16-byte words, 4
+// per thread per iteration, a block's words contiguous: zeros over grids
+// without outer layers, a copy of the base flags (computed once) over grids
+// with them. The partial words at a range's ends are written bytewise by
+// one thread each.
+constexpr int kFillUnroll = 4;
 
-typedef unsigned int ov_u4 __attribute__((ext_vector_type(4)));
-constexpr int kFillGroup = 4;
-
-__global__ void __launch_bounds__(256) k_flag_fill(const GridDev* __restrict__ grids, int ngrids,
-                                                  uint8_t* __restrict__ flags, const int4* __restrict__ unit_info,
-                                                  const int4* __restrict__ unit_where, long long total_units,
-                                                  unsigned int* __restrict__ d_stamp, int32_t* __restrict__ near_count,
+__global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
+                                                  const uint8_t* __restrict__ base,
+                                                  const long long* __restrict__ fill_ranges, int nranges,
+                                                  long long fill_words, unsigned int* __restrict__ d_stamp,
+                                                  int32_t* __restrict__ near_count,
                                                   int32_t* __restrict__ chunk_list_count,
                                                   int32_t* __restrict__ cand_count) {
-  __shared__ TileGeo TG[kMaxGrids];
-  __shared__ int has_outer[kMaxGrids];
-  stage_tile_geo(TG, grids, ngrids);
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) has_outer[g] = grids[g].has_outer;
   if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(d_stamp, near_count, chunk_list_count, cand_count);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, part = lane & 7, row = lane >> 3;
-  const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
-  const long long last = total_units - 1;
-  for (long long u0 = wave * kFillGroup; u0 < total_units; u0 += nwaves * kFillGroup) {
-    int4 info[kFillGroup];
+  gmem<long long>* R = gp(fill_ranges);
+  const long long nthreads = (long long)gridDim.x * blockDim.x;
+  for (long long w0 = (long long)blockIdx.x * blockDim.x * kFillUnroll + threadIdx.x; w0 < fill_words;
+       w0 += nthreads * kFillUnroll) {
 #pragma unroll
-    for (int q = 0; q < kFillGroup; ++q) info[q] = unit_info[min(u0 + q, last)];
-#pragma unroll
-    for (int q = 0; q < kFillGroup; ++q) {
-      if (u0 + q > last) break;
-      const int A = uniform_i32(info[q].z);
-      const int cols = info[q].w >> 8, rows = info[q].w & 255;
-      const TileGeo& G = TG[A];
-      const int ni = G.ni;
-      if (part * 16 >= cols || row >= rows) continue;
-      const int n = min(16, cols - part * 16);
-      uint8_t* dst = flags + info[q].x + row * ni + part * 16;
-      if (!has_outer[A]) {
-        if (n == 16 && (((uintptr_t)dst) & 15) == 0)
-          __builtin_nontemporal_store((ov_u4){0u, 0u, 0u, 0u}, (ov_u4*)dst);
-        else
-          for (int e = 0; e < n; ++e) dst[e] = (uint8_t)OV_STATE_FIELD;
-      } else {
-        const int4 wh = unit_where[u0 + q];
-        const int i = wh.x + part * 16, j = wh.y + row, k = wh.z;
-        const bool row_outer = j < G.o[2] || j >= G.nj - G.o[3] || k < G.o[4] || k >= G.nk - G.o[5];
-        uint32_t w[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          uint32_t word = 0u;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ii = i + 4 * c + r;
-            const bool ob = row_outer || ii < G.o[0] || ii >= ni - G.o[1];
-            word |= (ob ? (uint32_t)(kFringe | (OV_CAUSE_BOUNDARY << 2)) : (uint32_t)OV_STATE_FIELD) << (8 * r);
-          }
-          w[c] = word;
-        }
-        if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
-          *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 16; ++e)
-            if (e < n) dst[e] = (uint8_t)(w[e >> 2] >> (8 * (e & 3)));
-        }
-      }
+    for (int q = 0; q < kFillUnroll; ++q) {
+      const long long w = w0 + (long long)q * blockDim.x;
+      if (w >= fill_words) break;
+      int r = 0;
+      while (r + 1 < nranges && R[4 * (r + 1) + 2] <= w) ++r;
+      const long long x = 16 * ((R[4 * r] + 15) / 16 + w - R[4 * r + 2]);  // byte offset of the word
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (R[4 * r + 3]) v = *reinterpret_cast<const uint4*>(base + x);
+      *reinterpret_cast<uint4*>(flags + x) = v;
     }
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < nranges) {
+    // bytes before the first and after the last whole word of range r
+    const long long a = R[4 * threadIdx.x], b = R[4 * threadIdx.x + 1];
+    const bool copy = R[4 * threadIdx.x + 3] != 0;
+    const long long wa = 16 * ((a + 15) / 16), wb = 16 * (b / 16);
+    const long long head_end = min(wa, b), tail_begin = max(wb, head_end);  // at most 15 bytes each
+    for (long long x = a; x < head_end; ++x) flags[x] = copy ? base[x] : (uint8_t)OV_STATE_FIELD;
+    for (long long x = tail_begin; x < b; ++x) flags[x] = copy ? base[x] : (uint8_t)OV_STATE_FIELD;
   }
 }
 
-// Candidate sub-tiles (kSubI x kTileJ x kTileK nodes), one wavefront each at
-// a time: lane l takes the 16 nodes i0 .. i0 + 15 of row (j0 + l % 8, k0 +
-// l / 8), loads their coordinates in batches of 4, tests them against the
-// blank regions of the sub-tile's mask only and writes their 16 flags.
+// Candidate sub-tiles (kSubI x kTileJ x kTileK nodes), one block each at a
+// time (the variant for few candidates: shortest latency per sub-tile):
+// thread t takes the 4 nodes i0 + 4 (t % 4) .. + 3 of row
+// (j0 + (t / 4) % 8, k0 + t / 32), loads their coordinates at once, tests
+// them against the blank regions of the sub-tile's mask only and writes
+// their 4 flags.
+static_assert(kSubI == 16 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a sub-tile with 4 nodes each");
+
 template <typename CT>
-__global__ void __launch_bounds__(256) k_holecut_cand(const GridDev* __restrict__ grids, int ngrids,
+__global__ void __launch_bounds__(256) k_holecut_cand_b(const GridDev* __restrict__ grids, int ngrids,
+                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
+                                                     const unsigned long long* __restrict__ sub_mask,
+                                                     const int32_t* __restrict__ cand_list,
+                                                     const int32_t* __restrict__ cand_count,
+                                                     const int4* __restrict__ tile_info,
+                                                     const unsigned int* __restrict__ d_stamp,
+                                                     unsigned int* __restrict__ tile_near,
+                                                     int32_t* __restrict__ near_list,
+                                                     int32_t* __restrict__ near_count,
+                                                     unsigned long long* __restrict__ stats) {
+  __shared__ HoleLds L;
+  __shared__ TileGeo TG[kMaxGrids];
+  stage_tile_geo(TG, grids, ngrids);
+  holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
+  const unsigned int stamp = *d_stamp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+  const long long ncand = *cand_count;
+  for (long long c = blockIdx.x; c < ncand; c += gridDim.x) {
+    const int sub = cand_list[c];
+    const unsigned long long mask = uniform_u64(sub_mask[sub]);
+    const int4 ti = tile_info[sub / kSubPerTile];
+    const int A = uniform_i32(ti.x);
+    const TileGeo& G = TG[A];
+    const int ni = G.ni, nj = G.nj, nk = G.nk;
+    const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
+    const int t = threadIdx.x;
+    const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI + 4 * (t & 3), j = ti.z * kTileJ + ((t >> 2) & 7),
+              k = ti.w * kTileK + (t >> 5);
+    const bool ok = i < ni && j < nj && k < nk;
+    const int n = ok ? min(4, ni - i) : 0;
+    const bool outer = L.outer[A] != 0;
+    const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
+    bool hole = false;
+    if (ok) {
+      const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+      uint8_t* dst = flags + L.off[A] + m0;
+      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+      CT X[4], Y[4], Z[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < n) {
+          X[r] = Xa[r];
+          Y[r] = Ya[r];
+          Z[r] = Za[r];
+        }
+      uint32_t word = 0u;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r >= n) continue;
+        const int cause = holecut_node<CT>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
+        uint32_t f = OV_STATE_FIELD;
+        if (cause >= 0) {
+          f = kHole | (cause << 2);
+          hole = true;
+        } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
+          f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+        }
+        word |= f << (8 * r);
+      }
+      if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(dst) = word;
+      } else {
+        for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
+      }
+    }
+    int nr = n;
+    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
+    if ((t & 63) == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+    if (__syncthreads_or(hole) && t < 125)
+      mark_near(t, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                near_list, near_count);
+  }
+}
+
+// Candidate sub-tiles, one wavefront each at a time (the variant for many
+// candidates: no block barrier per sub-tile): lane l takes the 16 nodes
+// i0 .. i0 + 15 of row (j0 + l % 8, k0 + l / 8), loads their coordinates in
+// batches of 4, tests them against the blank regions of the sub-tile's mask
+// only and writes their 16 flags.
+template <typename CT>
+__global__ void __launch_bounds__(256) k_holecut_cand_w(const GridDev* __restrict__ grids, int ngrids,
                                                      const double* __restrict__ poses, uint8_t* __restrict__ flags,
                                                      const unsigned long long* __restrict__ sub_mask,
                                                      const int32_t* __restrict__ cand_list,
@@ -692,25 +748,37 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   const int ng = (int)ctx->grids.size();
   const long long nt = ctx->total_tiles;
   if (ctx->cull) {
-    const long long nu = ctx->total_units;
-    long long fb = std::max(1LL, std::min((nu + 4 * kFillGroup - 1) / (4 * kFillGroup), (long long)ctx->num_cus * 8));
-    hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, ctx->d_grids, ng, flags, ctx->d_unit_info,
-                       ctx->d_unit_where, nu, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count,
-                       ctx->d_cand_count);
+    const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
+                                                (long long)ctx->num_cus * 32));
+    hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
+                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, ctx->d_stamp, ctx->d_near_count,
+                       ctx->d_chunk_list_count, ctx->d_cand_count);
     long long mb = std::max(1LL, std::min((nt * kSubPerTile + 255) / 256, (long long)ctx->num_cus * 4));
     hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)mb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                        (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nt, ctx->d_tile_mask, ctx->d_cand_list,
                        ctx->d_cand_count);
-    int per_cu = ctx->persist > 0 ? ctx->persist : 4;
-    long long cb = std::max(1LL, std::min((nt * kSubPerTile + 3) / 4, (long long)ctx->num_cus * per_cu));
-    if (ctx->precision == OV_MIXED)
-      hipLaunchKernelGGL(k_holecut_cand<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses, flags,
-                         ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info, ctx->d_stamp,
-                         ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
-    else
-      hipLaunchKernelGGL(k_holecut_cand<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses, flags,
-                         ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info, ctx->d_stamp,
-                         ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+    int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+    if (ctx->holecut_npl == 4) {
+      long long cb = std::max(1LL, std::min(nt * kSubPerTile, (long long)ctx->num_cus * per_cu));
+      if (ctx->precision == OV_MIXED)
+        hipLaunchKernelGGL(k_holecut_cand_b<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
+                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+      else
+        hipLaunchKernelGGL(k_holecut_cand_b<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
+                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+    } else {
+      long long cb = std::max(1LL, std::min((nt * kSubPerTile + 3) / 4, (long long)ctx->num_cus * per_cu));
+      if (ctx->precision == OV_MIXED)
+        hipLaunchKernelGGL(k_holecut_cand_w<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
+                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+      else
+        hipLaunchKernelGGL(k_holecut_cand_w<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
+                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
+                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+    }
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count,
@@ -782,13 +850,14 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
     }
     if (NF == 0) continue;
     uint8_t* fl = flags + noff;
+    bool any_hole = false;
     // stage hole causes with halo: 16 threads per row load the 64 interior
     // bytes as words where the row is aligned and in range, the halo bytewise;
     // fixed trip counts so that all loads are issued before the LDS stores
 #pragma unroll
     for (int it = 0; it < (NROW + 255) / 256; ++it) {
       const int e = threadIdx.x + it * 256;
-      if (e >= NROW) break;
+      if (e >= NROW) continue;  // only the last round is partial
       const int row = e >> 4, part = e & 15;
       const int y = row % EJ, z = row / EJ;
       const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
@@ -817,12 +886,13 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[z][y][NF + part * 4 + q] = v[q];
+      any_hole |= (v[0] & v[1] & v[2] & v[3]) != 255;
     }
 #pragma unroll
     for (int it = 0; it < (NHALO + 255) / 256; ++it) {
       const int e = threadIdx.x + it * 256;
-      if (e >= NHALO) break;
-      const int h = e % (2 * NF), row = e / (2 * NF);
+      if (e >= NHALO) continue;  // only the last round is partial
+      const int h = e % (2 * H), row = e / (2 * H);  // (H = NF here: NF = 0 never gets this far)
       const int y = row % EJ, z = row / EJ;
       const int x = h < NF ? h : kTileI + h;  // NF halo bytes on each side
       const int i = wrap_or_out(i0 - NF + x, G.ni, G.per & 1);
@@ -834,8 +904,10 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
         if ((f & 3) == kHole) v = f >> 2;
       }
       a[z][y][x] = v;
+      any_hole |= v != 255;
     }
-    __syncthreads();
+    // no hole within nf of the tile: nothing to mark (same in every thread)
+    if (!__syncthreads_or(any_hole)) continue;
     for (int e = threadIdx.x; e < kTileI * EJ * EK; e += blockDim.x) {
       int x = e & 63, y = (e >> 6) % EJ, z = (e >> 6) / EJ;
       uint8_t m = 255;

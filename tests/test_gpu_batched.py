@@ -81,6 +81,11 @@ def test_shells_small_streaming_holecut():
     _run_steps(w, [0, 1], "mixed", options={"holecut_cull": 0})
 
 
+def test_school_small_block_candidate_holecut():
+    w = W.c3_small(steps=3)
+    _run_steps(w, [0, 1, 2], "mixed", options={"holecut_npl": 4})
+
+
 @pytest.mark.timeout(300)
 def test_school_full_size_pipelined_sampled_steps():
     w = W.c3(steps=200)

@@ -57,6 +57,13 @@ def test_c1_small_streaming_holecut_matches_oracle():
     _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_cull": 0})
 
 
+def test_c1_small_block_candidate_holecut_matches_oracle():
+    """The culled hole cut with one block per candidate sub-tile (4 nodes per lane)."""
+    w = W.c1_small(steps=3)
+    _run_and_compare(w, [0, 1, 2], options={"holecut_npl": 4})
+    _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_npl": 4})
+
+
 def test_c1_small_mixed_matches_oracle():
     w = W.c1_small(steps=6)
     stats = _run_and_compare(w, list(range(6)), precision="mixed", value_rtol=1e-5, s_tol=1e-4)
