@@ -69,6 +69,13 @@ def main():
     ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
     ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
+    ap.add_argument("--stages", type=int, default=3, choices=(2, 3), help="native pipeline stages (streams)")
+    ap.add_argument("--per-step-submit", action="store_true",
+                    help="native pipeline: one host call per step instead of one call for all timed steps")
+    ap.add_argument("--no-native-graphs", action="store_true",
+                    help="the native pipeline launches kernels directly instead of replaying per-stage graphs")
+    ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
+                    help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -108,8 +115,10 @@ def main():
     log(f"[bench] workload {w.name} built in {time.perf_counter() - t0:.1f}s: {w.total_nodes} nodes, "
         f"{w.ngrids} grids, {w.steps} poses, precision {precision}")
     dev = torch.device("cuda", 0)
-    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision,
-                 options={"holecut_cull": 0 if args.no_cull else 1})
+    opts = {"holecut_cull": 0 if args.no_cull else 1}
+    if args.npl:
+        opts["holecut_npl"] = args.npl
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=opts)
     n0 = a.count_queries(w.poses[0])
     cap = 2 * n0 + 4096
     a.allocate(cap)
@@ -119,7 +128,9 @@ def main():
     log(f"[bench] set-up done, {n0} queries at t=0, capacity {cap}, mode {mode}")
     pipe = None
     if mode.startswith("pipelined"):
-        pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=args.steps)
+        pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=args.steps,
+                        stages=args.stages if mode == "pipelined" else 2,
+                        graphs=(mode == "pipelined" and not args.no_native_graphs))
     elif mode == "graph":
         a.capture()
     if mode == "pipelined-graph":
@@ -148,6 +159,12 @@ def main():
             a.back(p, a.buf)
             cnt.copy_(a.d_count, non_blocking=True)
 
+    # the native executor takes the timed steps in one call: their poses as one
+    # contiguous device table, prepared before the timed region
+    many = pipe is not None and pipe.native is not None and not args.per_step_submit
+    if many:
+        idx = torch.arange(args.warmup, args.warmup + args.steps, device=dev) % w.steps
+        timed_poses = poses[idx].contiguous()
     for t in range(args.warmup):
         run(t)
     if pipe is not None:
@@ -165,10 +182,12 @@ def main():
         pipe.native.holecut_times(0)  # restart the timing record
         pipe.native.set_timing(True)
     if pipe is not None:
-        pipe.s_front.wait_stream(torch.cuda.current_stream(dev))
-        pipe.s_back.wait_stream(torch.cuda.current_stream(dev))
-    for k in range(args.steps):
-        run(args.warmup + k, None if mode == "graph" else k)
+        pipe.wait_current()
+    if many:
+        pipe.submit_many(args.warmup, timed_poses, counts[args.warmup:args.warmup + args.steps])
+    else:
+        for k in range(args.steps):
+            run(args.warmup + k, None if mode == "graph" else k)
     host_ms = (time.perf_counter() - t_host0) * 1e3
     if pipe is not None:
         pipe.join()
@@ -224,7 +243,9 @@ def main():
                                f"curvilinear background + {w.ngrids - 1} overset shell(s), rigid motion, "
                                f"{precision}, {mode}",
                    "nodes": w.total_nodes, "queries_per_step_mean": round(queries / args.steps, 1),
-                   "mode": mode},
+                   "mode": mode + (f", {args.stages} stages" + ("" if args.no_native_graphs else ", stage graphs")
+                                   + ("" if args.per_step_submit else ", one submit call for all timed steps")
+                                   if mode == "pipelined" else "")},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -271,16 +271,42 @@ typedef struct ov_pipe ov_pipe;
 int ov_pipe_create(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const void *fields,
                    void *stream_front, void *stream_back, int32_t max_timed, ov_pipe **out);
 
+/* The three-stage variant: the hole cut (stage A, on stream_a), fringe
+ * marking + compaction (stage B, stream_b) and the back half (stage C,
+ * stream_c) of consecutive steps, with three buffer sets (step t uses
+ * sets[t % 3]): A(t+1), B(t) and C(t-1) run at the same time. A and B of a
+ * step share one of the context's two front-half scratch slots, alternating
+ * by step. Events order B(t) after A(t), C(t) after B(t), A(t) after C(t-3)
+ * and B(t-2). Same rules as ov_pipe_create otherwise; the three streams must
+ * differ. */
+int ov_pipe_create3(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const void *fields,
+                    void *stream_a, void *stream_b, void *stream_c, int32_t max_timed, ov_pipe **out);
+
+/* Capture every stage of every buffer set once as a single-stream HIP graph
+ * (on a private stream) and replay the graphs from then on: a submitted step
+ * becomes one pose copy into a per-set device slot, one graph launch per
+ * stage and the ordering events. Must be called before the first submit;
+ * options set on the context afterwards do not reach the captured graphs.
+ * on = 0 returns to direct launches. Returns OV_EHIP (graphs off) if the
+ * runtime refuses the capture. */
+int ov_pipe_use_graphs(ov_pipe *pipe, int32_t on);
+
 /* Queue the next step with poses (device, ngrids*12 doubles, must stay
  * unchanged until the step completes). If count_out (device int64) is not
  * NULL it receives the step's query count. Nothing synchronises. */
 int ov_pipe_submit(ov_pipe *pipe, const double *poses, int64_t *count_out);
 
+/* Queue n consecutive steps: step i reads its poses at poses + i*pose_stride
+ * (device; pose_stride >= ngrids*12 doubles) and, if counts_out (device
+ * int64[n]) is not NULL, writes its query count to counts_out[i]. The same
+ * as n calls of ov_pipe_submit, without a host round trip per step. */
+int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride, int64_t n, int64_t *counts_out);
+
 /* Make `stream` wait for all work submitted so far. */
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 
 /* Time (or stop timing) the hole cut of the following submitted steps with
- * events on the front stream, up to max_timed steps. */
+ * events on the stream it runs on (front / stage A), up to max_timed steps. */
 int ov_pipe_set_timing(ov_pipe *pipe, int32_t on);
 
 /* Elapsed milliseconds of the timed hole cuts so far (waits for them) into

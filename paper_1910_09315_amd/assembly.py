@@ -163,33 +163,49 @@ class Assembly:
 
 
 class Pipeline:
-    """Two-stream, two-buffer execution of consecutive steps of an Assembly.
-    native=True drives the library's C++ executor (ov_pipe_*: one host call
-    per step); native=False issues the five calls from Python (optionally
-    replaying per-half HIP graphs, see capture())."""
+    """Pipelined execution of consecutive steps of an Assembly.
+    stages=2: two streams (front = hole cut + fringe + compaction, back =
+    transform + search + interpolation) and two buffer sets; stages=3: three
+    streams (hole cut | fringe + compaction | back half) and three buffer
+    sets (native only). native=True drives the library's C++ executor
+    (ov_pipe_*: one host call per step); native=False issues the five calls
+    from Python (optionally replaying per-half HIP graphs, see capture())."""
 
-    def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024):
+    def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024, stages: int = 2,
+                 graphs: bool = False):
+        if stages not in (2, 3) or (stages == 3 and not native):
+            raise ValueError("stages must be 2, or 3 with the native executor")
         self.a = asm
         dev = asm.dev
-        self.bufs = [StepBuffers(dev, asm.total, capacity, asm.dtype) for _ in range(2)]
-        self.s_front = torch.cuda.Stream(dev)
-        self.s_back = torch.cuda.Stream(dev)
+        self.nsets = stages
+        self.bufs = [StepBuffers(dev, asm.total, capacity, asm.dtype) for _ in range(stages)]
+        self.streams = [torch.cuda.Stream(dev) for _ in range(stages)]
+        self.s_front = self.streams[0]
+        self.s_back = self.streams[-1]
         self.native = None
         if native:
-            self.native = B.NativePipe(asm.ctx, asm.nf, self.bufs, asm.fields, self.s_front, self.s_back, max_timed)
+            self.native = B.NativePipe(asm.ctx, asm.nf, self.bufs, asm.fields, self.streams, max_timed)
+            if graphs:
+                self.native.use_graphs(True)
         self.front_done = [torch.cuda.Event() for _ in range(2)]
         self.back_done = [torch.cuda.Event() for _ in range(2)]
-        self.started = [False, False]
+        self.started = [False] * stages
         self.graphs = None
         cur = torch.cuda.current_stream(dev)
-        self.s_front.wait_stream(cur)
-        self.s_back.wait_stream(cur)
+        for st in self.streams:
+            st.wait_stream(cur)
+
+    def wait_current(self):
+        """Make every pipeline stream wait for the current stream."""
+        cur = torch.cuda.current_stream(self.a.dev)
+        for st in self.streams:
+            st.wait_stream(cur)
 
     def submit(self, t: int, poses_dev, count_out=None, holecut_events=None):
         """Queue step t (poses on the device). Returns its buffer set.
         count_out: a 1-element device tensor that receives the step's query
         count; holecut_events: a pair of timing events around the hole cut."""
-        k = t % 2
+        k = t % self.nsets
         b = self.bufs[k]
         p = poses_dev.reshape(-1)
         if self.native is not None:
@@ -209,6 +225,15 @@ class Pipeline:
             self.back_done[k].record(self.s_back)
         self.started[k] = True
         return b
+
+    def submit_many(self, t0: int, poses_dev, counts_out=None):
+        """Queue steps t0 .. t0 + n - 1 in one call of the native executor.
+        poses_dev: [n, ngrids*12] device tensor; counts_out: int64[n] device tensor."""
+        if self.native is None:
+            raise RuntimeError("submit_many needs the native executor")
+        self.native.submit_many(poses_dev, counts_out)
+        for t in range(t0, t0 + int(poses_dev.shape[0])):
+            self.started[t % self.nsets] = True
 
     def capture(self):
         """Capture, for each buffer set k, three single-stream HIP graphs: the
@@ -273,4 +298,4 @@ class Pipeline:
 
     def results(self, t: int) -> dict:
         self.join()
-        return self.a.results(self.bufs[t % 2])
+        return self.a.results(self.bufs[t % self.nsets])

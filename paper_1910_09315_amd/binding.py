@@ -28,8 +28,8 @@ EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "o
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
-           "overset_interp", "ov_pipe_create", "ov_pipe_submit", "ov_pipe_join", "ov_pipe_set_timing",
-           "ov_pipe_holecut_times", "ov_pipe_destroy"]
+           "overset_interp", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs", "ov_pipe_submit",
+           "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_holecut_times", "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -75,7 +75,10 @@ def load(path: str = LIB_PATH):
         "overset_donor_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P]),
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "ov_pipe_create": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+        "ov_pipe_create3": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+        "ov_pipe_use_graphs": (ctypes.c_int, [_P, _I32]),
         "ov_pipe_submit": (ctypes.c_int, [_P, _P, _P]),
+        "ov_pipe_submit_many": (ctypes.c_int, [_P, _P, _I64, _I64, _P]),
         "ov_pipe_join": (ctypes.c_int, [_P, _P]),
         "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32]),
         "ov_pipe_holecut_times": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
@@ -202,24 +205,42 @@ def overset_interp(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, f
 
 
 class NativePipe:
-    """ov_pipe: the library's two-stream step executor."""
+    """ov_pipe: the library's step executor. Two streams (ov_pipe_create:
+    front, back) and two buffer sets, or three streams (ov_pipe_create3:
+    hole cut, fringe + compaction, back half) and three buffer sets."""
 
-    def __init__(self, ctx: Context, nf: int, sets, fields, stream_front, stream_back, max_timed: int = 0):
+    def __init__(self, ctx: Context, nf: int, sets, fields, streams, max_timed: int = 0):
         self.ctx = ctx
-        arr = (StepBuffersC * 2)()
+        n = len(sets)
+        if n not in (2, 3) or len(streams) != n:
+            raise OversetError("NativePipe: 2 or 3 buffer sets, one stream per stage")
+        arr = (StepBuffersC * n)()
         for k, b in enumerate(sets):
             arr[k] = StepBuffersC(b.flags.data_ptr(), b.q_grid.data_ptr(), b.q_node.data_ptr(), b.d_count.data_ptr(),
                                   b.qx.data_ptr(), b.donor_grid.data_ptr(), b.donor_cell.data_ptr(),
                                   b.s.data_ptr(), b.status.data_ptr(), b.out.data_ptr(), b.capacity)
-        self._keep = (sets, fields, stream_front, stream_back)
+        self._keep = (sets, fields, streams)
         h = _P()
-        ctx.check(ctx.lib.ov_pipe_create(ctx.h, int(nf), arr, _ptr(fields), _P(stream_front.cuda_stream),
-                                         _P(stream_back.cuda_stream), int(max_timed), ctypes.byref(h)),
-                  "ov_pipe_create")
+        st = [_P(x.cuda_stream) for x in streams]
+        if n == 2:
+            ctx.check(ctx.lib.ov_pipe_create(ctx.h, int(nf), arr, _ptr(fields), st[0], st[1], int(max_timed),
+                                             ctypes.byref(h)), "ov_pipe_create")
+        else:
+            ctx.check(ctx.lib.ov_pipe_create3(ctx.h, int(nf), arr, _ptr(fields), st[0], st[1], st[2],
+                                              int(max_timed), ctypes.byref(h)), "ov_pipe_create3")
         self.h = h
+
+    def use_graphs(self, on: bool = True):
+        self.ctx.check(self.ctx.lib.ov_pipe_use_graphs(self.h, int(bool(on))), "ov_pipe_use_graphs")
 
     def submit(self, poses, count_out=None):
         self.ctx.check(self.ctx.lib.ov_pipe_submit(self.h, _ptr(poses), _ptr(count_out)), "ov_pipe_submit")
+
+    def submit_many(self, poses, counts_out=None):
+        """poses: device tensor [n, ngrids*12] (contiguous rows); counts_out: device int64[n] or None."""
+        n, stride = int(poses.shape[0]), int(poses.stride(0))
+        self.ctx.check(self.ctx.lib.ov_pipe_submit_many(self.h, _ptr(poses), stride, n, _ptr(counts_out)),
+                       "ov_pipe_submit_many")
 
     def join(self, stream=None):
         self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")

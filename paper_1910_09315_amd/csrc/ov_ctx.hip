@@ -586,30 +586,30 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     HIPCHK(hipMemcpy(ctx->d_fill_ranges, ranges.data(), sizeof(long long) * ranges.size(), hipMemcpyHostToDevice),
            "fill ranges copy");
   }
-  HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int)), "hipMalloc stamp");
+  HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (1 + kSlots)), "hipMalloc stamps");
   HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * kSubPerTile * nt), "hipMalloc sub-tile masks");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * nt), "hipMalloc tile holes");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
-  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * nt), "hipMalloc near list");
-  HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t)), "hipMalloc near count");
+  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * kSlots * nt), "hipMalloc near lists");
+  HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t) * kSlots), "hipMalloc near counts");
   HIPCHK(hipMalloc(&ctx->d_cand_list, sizeof(int32_t) * kSubPerTile * nt), "hipMalloc candidate list");
   HIPCHK(hipMalloc(&ctx->d_cand_count, sizeof(int32_t)), "hipMalloc candidate count");
   HIPCHK(hipMemsetAsync(ctx->d_cand_count, 0, sizeof(int32_t), s), "candidate count init");
-  HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int), s), "stamp init");
+  HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (1 + kSlots), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * nt, s), "tile hole init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
-  HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t), s), "near count init");
+  HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t) * kSlots, s), "near count init");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
   ctx->nsuper = (ctx->nchunks + kSuperChunk - 1) / kSuperChunk;
   HIPCHK(hipMalloc(&ctx->d_chunk_static, ctx->nchunks), "hipMalloc static chunk marks");
   HIPCHK(hipMalloc(&ctx->d_chunk_stamp, sizeof(unsigned int) * ctx->nchunks), "hipMalloc chunk stamps");
   HIPCHK(hipMalloc(&ctx->d_chunk_list, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk list");
-  HIPCHK(hipMalloc(&ctx->d_chunk_list_count, sizeof(int32_t)), "hipMalloc chunk list count");
+  HIPCHK(hipMalloc(&ctx->d_chunk_list_count, sizeof(int32_t) * kSlots), "hipMalloc chunk list counts");
   HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(unsigned long long) * ctx->nchunks), "hipMalloc chunk counts");
   HIPCHK(hipMalloc(&ctx->d_super_counts, sizeof(int32_t) * kSuperSlots * ctx->nsuper), "hipMalloc superchunk counts");
   HIPCHK(hipMalloc(&ctx->d_super_offsets, sizeof(long long) * (ctx->nsuper + 1)), "hipMalloc superchunk offsets");
   HIPCHK(hipMemsetAsync(ctx->d_chunk_stamp, 0, sizeof(unsigned int) * ctx->nchunks, s), "chunk stamp init");
-  HIPCHK(hipMemsetAsync(ctx->d_chunk_list_count, 0, sizeof(int32_t), s), "chunk list count init");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_list_count, 0, sizeof(int32_t) * kSlots, s), "chunk list count init");
   HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(unsigned long long) * ctx->nchunks, s), "chunk count init");
   HIPCHK(hipMemsetAsync(ctx->d_super_counts, 0, sizeof(int32_t) * kSuperSlots * ctx->nsuper, s),
          "superchunk count init");

@@ -34,6 +34,9 @@ constexpr int kMaxNf = 3;
 constexpr int kCompactThreads = 256;
 constexpr int kCompactChunk = kCompactThreads * 16;
 constexpr int kSuperChunk = 64;
+// Front-half scratch slots: the hole cut and the fringe pass of one step use
+// one slot; up to kSlots steps can be between the two at once.
+constexpr int kSlots = 3;
 constexpr int kSuperSlots = 8;  // count slots per superchunk (spreads the atomics)
 
 // One grid as the kernels see it.
@@ -105,18 +108,18 @@ struct ov_ctx {
   // the fringe pass and the compaction. Each hole cut starts a new stamp; a
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
-  unsigned int* d_stamp = nullptr;            // current stamp (device)
+  unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`
   unsigned long long* d_tile_mask = nullptr;  // per sub-tile: blank regions (bit = grid) that may reach it
   unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
-  int32_t* d_near_list = nullptr;             // tiles that may hold buffer nodes (a hole within kMaxNf)
-  int32_t* d_near_count = nullptr;
+  int32_t* d_near_list = nullptr;             // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
+  int32_t* d_near_count = nullptr;            // per slot
   int32_t* d_cand_list = nullptr;             // sub-tiles some blank region may reach (this step)
   int32_t* d_cand_count = nullptr;
   uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
   unsigned int* d_chunk_stamp = nullptr;      // per chunk: stamp if on this step's chunk list
   int32_t* d_chunk_list = nullptr;            // chunks that may hold query nodes: the static ones, then this step's
-  int32_t* d_chunk_list_count = nullptr;      // length of this step's part
+  int32_t* d_chunk_list_count = nullptr;      // per slot: length of this step's part
   long long n_static_chunks = 0;
   unsigned long long* d_chunk_counts = nullptr;  // per chunk: stamp << 32 | query count (listed chunks)
   int32_t* d_super_counts = nullptr;             // per 64 chunks, kSuperSlots partial counts (zeroed by the scan)
@@ -142,11 +145,13 @@ int hip_fail(ov_ctx* ctx, hipError_t e, const char* what);
 long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 
 // launchers (kernel files)
-hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s);
-hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s);
+// slot: which front-half scratch slot (0..kSlots-1) the step uses (the hole
+// cut and the fringe/compaction of one step must use the same slot)
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0);
+hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0);
 int build_static_chunks(ov_ctx* ctx, hipStream_t s);
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
-                          long long capacity, long long* d_count, hipStream_t s);
+                          long long capacity, long long* d_count, hipStream_t s, int slot = 0);
 hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_grid, const int32_t* q_node,
                             const long long* d_count, long long capacity, void* qx, hipStream_t s);
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

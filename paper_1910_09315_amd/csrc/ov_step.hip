@@ -310,18 +310,24 @@ static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI *
 
 // Starts a step of the front half: a new stamp, empty near and chunk lists.
 // Later kernels of the hole cut read the stamp (stream order).
-__device__ __forceinline__ void k_begin_step_body(unsigned int* d_stamp, int32_t* near_count,
+// `counter` numbers the steps of the context; `d_stamp` is the stamp of the
+// scratch slot this step uses (separate slots let the hole cut of one step
+// overlap the fringe pass of the previous one).
+__device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigned int* d_stamp, int32_t* near_count,
                                                   int32_t* chunk_list_count, int32_t* cand_count) {
-  unsigned int v = *d_stamp + 1u;
-  *d_stamp = v == 0u ? 1u : v;  // 0 marks "never listed"
+  unsigned int v = *counter + 1u;
+  v = v == 0u ? 1u : v;  // 0 marks "never listed"
+  *counter = v;
+  *d_stamp = v;
   *near_count = 0;
   *chunk_list_count = 0;
   *cand_count = 0;
 }
 
-__global__ void k_begin_step(unsigned int* __restrict__ d_stamp, int32_t* __restrict__ near_count,
-                             int32_t* __restrict__ chunk_list_count, int32_t* __restrict__ cand_count) {
-  k_begin_step_body(d_stamp, near_count, chunk_list_count, cand_count);
+__global__ void k_begin_step(unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
+                             int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count,
+                             int32_t* __restrict__ cand_count) {
+  k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, cand_count);
 }
 
 // Tile index along one axis holding the node `which` positions from tile t:
@@ -483,11 +489,13 @@ constexpr int kFillUnroll = 4;
 __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
                                                   const uint8_t* __restrict__ base,
                                                   const long long* __restrict__ fill_ranges, int nranges,
-                                                  long long fill_words, unsigned int* __restrict__ d_stamp,
+                                                  long long fill_words, unsigned int* __restrict__ counter,
+                                                  unsigned int* __restrict__ d_stamp,
                                                   int32_t* __restrict__ near_count,
                                                   int32_t* __restrict__ chunk_list_count,
                                                   int32_t* __restrict__ cand_count) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(d_stamp, near_count, chunk_list_count, cand_count);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, cand_count);
   gmem<long long>* R = gp(fill_ranges);
   const long long nthreads = (long long)gridDim.x * blockDim.x;
   for (long long w0 = (long long)blockIdx.x * blockDim.x * kFillUnroll + threadIdx.x; w0 < fill_words;
@@ -724,7 +732,7 @@ __global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restri
 }
 
 template <typename CT>
-static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, unsigned int* st) {
   int block = ctx->holecut_block;
   int R = ctx->holecut_npt;  // 16-byte vectors per lane per chunk
   long long span = (long long)block * Vec16<CT>::W * R;
@@ -735,24 +743,29 @@ static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, h
   int ng = (int)ctx->grids.size();
   if (R == 4)
     hipLaunchKernelGGL((k_holecut<CT, 4>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
   else if (R == 2)
     hipLaunchKernelGGL((k_holecut<CT, 2>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
   else
     hipLaunchKernelGGL((k_holecut<CT, 1>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, ctx->d_stamp, ctx->d_stats);
+                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
 }
 
-hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s) {
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot) {
   const int ng = (int)ctx->grids.size();
   const long long nt = ctx->total_tiles;
+  unsigned int* counter = ctx->d_stamp;
+  unsigned int* st = ctx->d_stamp + 1 + slot;
+  int32_t* nl = ctx->d_near_list + slot * std::max(1LL, nt);
+  int32_t* nc = ctx->d_near_count + slot;
+  int32_t* clc = ctx->d_chunk_list_count + slot;
   if (ctx->cull) {
     const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
                                                 (long long)ctx->num_cus * 32));
     hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
-                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, ctx->d_stamp, ctx->d_near_count,
-                       ctx->d_chunk_list_count, ctx->d_cand_count);
+                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc,
+                       ctx->d_cand_count);
     long long mb = std::max(1LL, std::min((nt * kSubPerTile + 255) / 256, (long long)ctx->num_cus * 4));
     hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)mb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                        (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nt, ctx->d_tile_mask, ctx->d_cand_list,
@@ -763,31 +776,30 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
       if (ctx->precision == OV_MIXED)
         hipLaunchKernelGGL(k_holecut_cand_b<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                            flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
       else
         hipLaunchKernelGGL(k_holecut_cand_b<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                            flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
     } else {
       long long cb = std::max(1LL, std::min((nt * kSubPerTile + 3) / 4, (long long)ctx->num_cus * per_cu));
       if (ctx->precision == OV_MIXED)
         hipLaunchKernelGGL(k_holecut_cand_w<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                            flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
       else
         hipLaunchKernelGGL(k_holecut_cand_w<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
                            flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count, ctx->d_stats);
+                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, ctx->d_stamp, ctx->d_near_count, ctx->d_chunk_list_count,
-                     ctx->d_cand_count);
-  if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s);
-  else launch_holecut_t<double>(ctx, poses, flags, s);
+  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, counter, st, nc, clc, ctx->d_cand_count);
+  if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st);
+  else launch_holecut_t<double>(ctx, poses, flags, s, st);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
   hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, ctx->d_tile_hole,
-                     ctx->d_tile_info, nt, ctx->d_stamp, ctx->d_tile_near, ctx->d_near_list, ctx->d_near_count);
+                     ctx->d_tile_info, nt, st, ctx->d_tile_near, nl, nc);
   return hipGetLastError();
 }
 
@@ -940,13 +952,17 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
   }
 }
 
-hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s) {
+hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot) {
   const int ng = (int)ctx->grids.size();
+  const int32_t* nl = ctx->d_near_list + slot * std::max(1LL, ctx->total_tiles);
+  const int32_t* nc = ctx->d_near_count + slot;
+  const unsigned int* st = ctx->d_stamp + 1 + slot;
+  int32_t* clc = ctx->d_chunk_list_count + slot;
   // persistent blocks over the near list (its length is on the device)
   long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 4));
 #define OV_FRINGE_ARGS                                                                                            \
-  ctx->d_grids, ng, flags, ctx->d_tile_info, ctx->d_near_list, ctx->d_near_count, ctx->d_stamp, ctx->d_chunk_static, \
-      ctx->d_chunk_stamp, ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks
+  ctx->d_grids, ng, flags, ctx->d_tile_info, nl, nc, st, ctx->d_chunk_static, ctx->d_chunk_stamp, ctx->d_chunk_list, \
+      clc, ctx->n_static_chunks
   switch (nf) {
     case 0:
       hipLaunchKernelGGL(k_fringe_tiles<0>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
@@ -1116,20 +1132,20 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
 }
 
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node, long long capacity,
-                          long long* d_count, hipStream_t s) {
+                          long long* d_count, hipStream_t s, int slot) {
   const long long total = ctx->node_off.back();
+  const unsigned int* st = ctx->d_stamp + 1 + slot;
+  const int32_t* clc = ctx->d_chunk_list_count + slot;
   // persistent blocks over the chunk list (its length is on the device)
   long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, ctx->d_super_counts, ctx->d_chunk_list, ctx->d_chunk_list_count,
-                     ctx->n_static_chunks, ctx->d_stamp);
+                     ctx->d_chunk_counts, ctx->d_super_counts, ctx->d_chunk_list, clc, ctx->n_static_chunks, st);
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_super_counts, ctx->nsuper,
                      ctx->d_super_offsets, d_count, capacity, ctx->d_status);
   hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
                      (int)ctx->grids.size(), flags, total, ctx->d_chunk_counts, ctx->nchunks, ctx->d_super_offsets,
-                     ctx->d_chunk_list, ctx->d_chunk_list_count, ctx->n_static_chunks, ctx->d_stamp, q_grid, q_node,
-                     capacity);
+                     ctx->d_chunk_list, clc, ctx->n_static_chunks, st, q_grid, q_node, capacity);
   return hipGetLastError();
 }
 

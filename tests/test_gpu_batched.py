@@ -44,13 +44,13 @@ def _run_steps(w, steps, precision, options=None):
     return out
 
 
-def _run_pipeline(w, steps, precision):
+def _run_pipeline(w, steps, precision, stages=3):
     from paper_1910_09315_amd.assembly import Assembly, Pipeline
     o = oracle.Oracle(w.grids, w.nf)
     a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision)
     cap = 2 * a.count_queries(w.poses[0]) + 4096
     a.allocate(cap)
-    pipe = Pipeline(a, cap, native=True)
+    pipe = Pipeline(a, cap, native=True, stages=stages)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     out = []
     for t in range(max(steps) + 1):

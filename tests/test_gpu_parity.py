@@ -202,16 +202,18 @@ def test_bad_arguments_rejected_before_launch():
         B.overset_holecut(ctx, x, a.flags)  # before finalize
 
 
-@pytest.mark.parametrize("native", [True, False])
-def test_two_stream_pipeline_matches_sequential(native):
-    """Steps run by the two-stream pipeline (front half of step t+1 beside
-    the back half of step t), driven by the library's executor or from
+@pytest.mark.parametrize("native,stages,graphs", [(True, 2, False), (False, 2, False), (True, 3, False),
+                                                   (True, 2, True), (True, 3, True)])
+def test_pipeline_matches_sequential(native, stages, graphs):
+    """Steps run by the pipelines (two stages: front half of step t+1 beside
+    the back half of step t; three stages: hole cut of t+1, fringe of t and
+    back half of t-1 together), driven by the library's executor or from
     Python, equal the single-stream steps bitwise."""
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
     a = _assembly(w)
     b = _assembly(w, capacity=a.capacity)
-    pipe = Pipeline(b, a.capacity, native=native)
+    pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     seq = []
     for t in range(7):
