@@ -69,11 +69,13 @@ def main():
     ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
     ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
-    ap.add_argument("--stages", type=int, default=3, choices=(2, 3), help="native pipeline stages (streams)")
+    ap.add_argument("--stages", type=int, default=1, choices=(1, 2, 3), help="native executor streams")
     ap.add_argument("--per-step-submit", action="store_true",
                     help="native pipeline: one host call per step instead of one call for all timed steps")
-    ap.add_argument("--no-native-graphs", action="store_true",
-                    help="the native pipeline launches kernels directly instead of replaying per-stage graphs")
+    ap.add_argument("--native-graphs", action="store_true",
+                    help="the native executor replays per-stream HIP graphs instead of launching kernels directly")
+    ap.add_argument("--unfused-back", action="store_true",
+                    help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
@@ -118,6 +120,8 @@ def main():
     opts = {"holecut_cull": 0 if args.no_cull else 1}
     if args.npl:
         opts["holecut_npl"] = args.npl
+    if args.unfused_back:
+        opts["back_fused"] = 0
     a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=opts)
     n0 = a.count_queries(w.poses[0])
     cap = 2 * n0 + 4096
@@ -130,7 +134,7 @@ def main():
     if mode.startswith("pipelined"):
         pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=args.steps,
                         stages=args.stages if mode == "pipelined" else 2,
-                        graphs=(mode == "pipelined" and not args.no_native_graphs))
+                        graphs=(mode == "pipelined" and args.native_graphs))
     elif mode == "graph":
         a.capture()
     if mode == "pipelined-graph":
@@ -219,15 +223,20 @@ def main():
         per_node = 25 if precision == "fp64" else 13   # coordinates (3 x 8 or 3 x 4 B) + 1 flag byte
         bytes_launch = per_node * nodes
         if not args.no_cull:
-            # culled tiles move only their flag byte: count the coordinates the
-            # kernel actually read, per launch, from the library's counters
+            # culled sub-tiles move only their flag byte (grids with outer
+            # fringe layers also read it from the precomputed base flags):
+            # count the coordinates the kernel actually read, per launch, from
+            # the library's counters, and the sub-tile spheres
             coord_b = 24 if precision == "fp64" else 12
-            bytes_launch = int(nodes + coord_b * stat[0] / max(1, stat[1]) + 32 * ntiles)
-            per_node = f"1 B flag x {nodes} nodes + {coord_b} B x {stat[0] / max(1, stat[1]):.0f} nodes read " \
-                       f"+ 32 B x {ntiles} tile spheres"
+            nsub = 4 * ntiles
+            base_nodes = sum(g.nodes for g in w.grids if any(g.outer))
+            bytes_launch = int(nodes + base_nodes + coord_b * stat[0] / max(1, stat[1]) + 32 * nsub)
+            per_node = f"1 B flag written x {nodes} nodes + 1 B base flag read x {base_nodes} nodes + {coord_b} B " \
+                       f"coordinates x {stat[0] / max(1, stat[1]):.0f} nodes read + 32 B x {nsub} sub-tile spheres"
         avg_s = hc_ms.mean() / 1e3
         achieved = bytes_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_holecut", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        roofline = {"bound": "hbm", "kernel": "hole cut (k_fill_masks + k_holecut_cand)" if not args.no_cull
+                    else "k_holecut", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "avg_us": round(hc_ms.mean() * 1e3, 2),
                     "algorithmic_bytes_per_launch": bytes_launch,
@@ -243,7 +252,9 @@ def main():
                                f"curvilinear background + {w.ngrids - 1} overset shell(s), rigid motion, "
                                f"{precision}, {mode}",
                    "nodes": w.total_nodes, "queries_per_step_mean": round(queries / args.steps, 1),
-                   "mode": mode + (f", {args.stages} stages" + ("" if args.no_native_graphs else ", stage graphs")
+                   "mode": mode + (f", native executor on {args.stages} stream(s)"
+                                   + (", per-stream graphs" if args.native_graphs else "")
+                                   + (", unfused back half" if args.unfused_back else ", fused back half")
                                    + ("" if args.per_step_submit else ", one submit call for all timed steps")
                                    if mode == "pipelined" else "")},
         "roofline": roofline,

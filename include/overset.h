@@ -107,8 +107,12 @@ enum ov_option {
     OV_OPT_HOLECUT_CULL = 8,/* 1 (default): the hole cut reads the coordinates only of 16x8x8 sub-tiles that
                                some blank region may reach (bounding sphere vs. the region's enclosing sphere and
                                body-frame box; same flags); 0: stream every node */
-    OV_OPT_HOLECUT_NPL = 9  /* culled hole cut, candidate nodes per lane: 16 (default, one wavefront per
+    OV_OPT_HOLECUT_NPL = 9, /* culled hole cut, candidate nodes per lane: 16 (default, one wavefront per
                                sub-tile) or 4 (one block per sub-tile: shorter latency when candidates are few) */
+    OV_OPT_BACK_FUSED = 10, /* step executors (ov_pipe_*): 1 (default) runs transform, donor search and
+                               interpolation of a step as one kernel; 0 as the separate kernels of the three
+                               calls. Same results. */
+    OV_OPT_BACK_BLOCKS = 11 /* 256-thread workgroups per CU of that one kernel (1..32, default 8) */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.
@@ -255,6 +259,15 @@ typedef struct ov_step_buffers {
 } ov_step_buffers;
 
 typedef struct ov_pipe ov_pipe;
+
+/* A one-stream executor of consecutive steps (a scheduling layer over the
+ * five calls; not a step of the paper's method): each submitted step's
+ * stages run in stream order on `stream`, all steps in the one buffer set
+ * *set. No events: the cheapest form for the host. The results of a step
+ * are in the set until the next step overwrites them. Other rules as
+ * ov_pipe_create. */
+int ov_pipe_create1(ov_ctx *ctx, int32_t nf, const ov_step_buffers *set, const void *fields, void *stream,
+                    int32_t max_timed, ov_pipe **out);
 
 /* A two-stream executor of consecutive steps (a scheduling layer over the
  * five calls; not a step of the paper's method). Step t uses buffer set

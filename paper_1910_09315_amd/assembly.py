@@ -164,17 +164,18 @@ class Assembly:
 
 class Pipeline:
     """Pipelined execution of consecutive steps of an Assembly.
-    stages=2: two streams (front = hole cut + fringe + compaction, back =
-    transform + search + interpolation) and two buffer sets; stages=3: three
-    streams (hole cut | fringe + compaction | back half) and three buffer
-    sets (native only). native=True drives the library's C++ executor
-    (ov_pipe_*: one host call per step); native=False issues the five calls
-    from Python (optionally replaying per-half HIP graphs, see capture())."""
+    stages=1: one stream and one buffer set (native only); stages=2: two
+    streams (front = hole cut + fringe + compaction, back = transform +
+    search + interpolation) and two buffer sets; stages=3: three streams
+    (hole cut | fringe + compaction | back half) and three buffer sets
+    (native only). native=True drives the library's C++ executor (ov_pipe_*:
+    one host call per step); native=False issues the five calls from Python
+    (optionally replaying per-half HIP graphs, see capture())."""
 
     def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024, stages: int = 2,
                  graphs: bool = False):
-        if stages not in (2, 3) or (stages == 3 and not native):
-            raise ValueError("stages must be 2, or 3 with the native executor")
+        if stages not in (1, 2, 3) or (stages != 2 and not native):
+            raise ValueError("stages must be 2, or 1 or 3 with the native executor")
         self.a = asm
         dev = asm.dev
         self.nsets = stages

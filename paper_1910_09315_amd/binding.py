@@ -22,13 +22,15 @@ OV_CAUSE_BOUNDARY = 63
 OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE = 1, 2, 4
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
-       "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9}
+       "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
+       "back_fused": 10, "back_blocks": 11}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
-           "overset_interp", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs", "ov_pipe_submit",
+           "overset_interp", "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
+           "ov_pipe_submit",
            "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_holecut_times", "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
@@ -76,6 +78,7 @@ def load(path: str = LIB_PATH):
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "ov_pipe_create": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_create3": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+        "ov_pipe_create1": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_use_graphs": (ctypes.c_int, [_P, _I32]),
         "ov_pipe_submit": (ctypes.c_int, [_P, _P, _P]),
         "ov_pipe_submit_many": (ctypes.c_int, [_P, _P, _I64, _I64, _P]),
@@ -205,15 +208,16 @@ def overset_interp(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, f
 
 
 class NativePipe:
-    """ov_pipe: the library's step executor. Two streams (ov_pipe_create:
-    front, back) and two buffer sets, or three streams (ov_pipe_create3:
-    hole cut, fringe + compaction, back half) and three buffer sets."""
+    """ov_pipe: the library's step executor. One stream and one buffer set
+    (ov_pipe_create1), two streams (ov_pipe_create: front, back) and two
+    buffer sets, or three streams (ov_pipe_create3: hole cut, fringe +
+    compaction, back half) and three buffer sets."""
 
     def __init__(self, ctx: Context, nf: int, sets, fields, streams, max_timed: int = 0):
         self.ctx = ctx
         n = len(sets)
-        if n not in (2, 3) or len(streams) != n:
-            raise OversetError("NativePipe: 2 or 3 buffer sets, one stream per stage")
+        if n not in (1, 2, 3) or len(streams) != n:
+            raise OversetError("NativePipe: 1, 2 or 3 buffer sets, one stream per set")
         arr = (StepBuffersC * n)()
         for k, b in enumerate(sets):
             arr[k] = StepBuffersC(b.flags.data_ptr(), b.q_grid.data_ptr(), b.q_node.data_ptr(), b.d_count.data_ptr(),
@@ -222,7 +226,10 @@ class NativePipe:
         self._keep = (sets, fields, streams)
         h = _P()
         st = [_P(x.cuda_stream) for x in streams]
-        if n == 2:
+        if n == 1:
+            ctx.check(ctx.lib.ov_pipe_create1(ctx.h, int(nf), arr, _ptr(fields), st[0], int(max_timed),
+                                              ctypes.byref(h)), "ov_pipe_create1")
+        elif n == 2:
             ctx.check(ctx.lib.ov_pipe_create(ctx.h, int(nf), arr, _ptr(fields), st[0], st[1], int(max_timed),
                                              ctypes.byref(h)), "ov_pipe_create")
         else:

@@ -418,13 +418,10 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_base_flags);
   (void)hipFree(ctx->d_fill_ranges);
   (void)hipFree(ctx->d_stamp);
-  (void)hipFree(ctx->d_tile_mask);
   (void)hipFree(ctx->d_tile_hole);
   (void)hipFree(ctx->d_tile_near);
   (void)hipFree(ctx->d_near_list);
   (void)hipFree(ctx->d_near_count);
-  (void)hipFree(ctx->d_cand_list);
-  (void)hipFree(ctx->d_cand_count);
   (void)hipFree(ctx->d_chunk_static);
   (void)hipFree(ctx->d_chunk_stamp);
   (void)hipFree(ctx->d_chunk_list);
@@ -587,14 +584,10 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
            "fill ranges copy");
   }
   HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (1 + kSlots)), "hipMalloc stamps");
-  HIPCHK(hipMalloc(&ctx->d_tile_mask, sizeof(unsigned long long) * kSubPerTile * nt), "hipMalloc sub-tile masks");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * nt), "hipMalloc tile holes");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
   HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * kSlots * nt), "hipMalloc near lists");
   HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t) * kSlots), "hipMalloc near counts");
-  HIPCHK(hipMalloc(&ctx->d_cand_list, sizeof(int32_t) * kSubPerTile * nt), "hipMalloc candidate list");
-  HIPCHK(hipMalloc(&ctx->d_cand_count, sizeof(int32_t)), "hipMalloc candidate count");
-  HIPCHK(hipMemsetAsync(ctx->d_cand_count, 0, sizeof(int32_t), s), "candidate count init");
   HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (1 + kSlots), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * nt, s), "tile hole init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
@@ -667,6 +660,14 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
     case OV_OPT_HOLECUT_NPL:
       if (v != 4 && v != 16) break;
       ctx->holecut_npl = (int)v;
+      return OV_OK;
+    case OV_OPT_BACK_FUSED:
+      if (v != 0 && v != 1) break;
+      ctx->back_fused = (int)v;
+      return OV_OK;
+    case OV_OPT_BACK_BLOCKS:
+      if (v < 1 || v > 32) break;
+      ctx->back_blocks_per_cu = (int)v;
       return OV_OK;
     case OV_OPT_PERSIST:
       if (v < 0 || v > 32) break;

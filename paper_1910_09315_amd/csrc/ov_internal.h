@@ -93,7 +93,7 @@ struct ov_ctx {
   unsigned long long* d_stats = nullptr;  // OV_STAT_* counters (accumulate until ov_stats_fetch)
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
-  double4* d_tile_sphere = nullptr;  // per node tile: body-frame bounding sphere (centre, radius)
+  double4* d_tile_sphere = nullptr;  // per sub-tile: body-frame bounding sphere (centre, radius; -inf if empty)
   int4* d_tile_info = nullptr;       // per node tile: (grid, ti, tj, tk)
   // The flags every step starts from (field everywhere, fringe on the fixed
   // outer-boundary layers), laid out like the flag array; only the ranges
@@ -109,13 +109,10 @@ struct ov_ctx {
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
   unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`
-  unsigned long long* d_tile_mask = nullptr;  // per sub-tile: blank regions (bit = grid) that may reach it
   unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
   int32_t* d_near_list = nullptr;             // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;            // per slot
-  int32_t* d_cand_list = nullptr;             // sub-tiles some blank region may reach (this step)
-  int32_t* d_cand_count = nullptr;
   uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
   unsigned int* d_chunk_stamp = nullptr;      // per chunk: stamp if on this step's chunk list
   int32_t* d_chunk_list = nullptr;            // chunks that may hold query nodes: the static ones, then this step's
@@ -135,6 +132,8 @@ struct ov_ctx {
   int persist = 0;
   int cull = 1;  // hole cut: skip coordinate reads of tiles no blank region can reach
   int holecut_npl = 16;  // candidate nodes per lane in the culled hole cut: 16 (wavefront per sub-tile) or 4 (block)
+  int back_fused = 1;    // step executors: transform, search and interpolation in one kernel
+  int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   std::string err;
 };
 
@@ -161,6 +160,15 @@ hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* 
 hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* donor_cell, const void* s,
                          const long long* d_count, long long capacity, const void* fields, void* out,
                          hipStream_t st);
+// The back half of a step (transform, donor search, interpolation when
+// fields is non-null) for the step executors: one kernel when back_fused is
+// set, else the three launchers above. count_out (nullable) receives the
+// step's query count.
+hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                       const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
+                       int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
+                       void* out, long long* count_out, hipStream_t st);
+hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st);
 // setup (control cells, shadows)
 int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);
 int build_shadows(ov_ctx* ctx, GridHost& g, hipStream_t s);
@@ -236,6 +244,52 @@ __device__ __forceinline__ void cell_box(const GridDev& g, long long cell, doubl
   for (int d = 0; d < 3; ++d) {
     lo[d] -= pad;
     hi[d] += pad;
+  }
+}
+
+// Offset of node m of grid G from the grid's frame centre in inertial axes,
+// o = R X (pose p: R row-major, then the centre): FP64 from the FP64
+// coordinates, or FP32 from the FP32 shadows and the rounded pose.
+template <typename T>
+__device__ __forceinline__ void transform_node(const GridDev& G, const double* p, long long m, T o[3]) {
+  if (sizeof(T) == 8) {
+    const double X = gp(G.X)[m], Y = gp(G.Y)[m], Z = gp(G.Z)[m];
+    o[0] = (T)(p[0] * X + p[1] * Y + p[2] * Z);
+    o[1] = (T)(p[3] * X + p[4] * Y + p[5] * Z);
+    o[2] = (T)(p[6] * X + p[7] * Y + p[8] * Z);
+  } else {
+    const float X = gp(G.Xf)[m], Y = gp(G.Yf)[m], Z = gp(G.Zf)[m];
+    o[0] = (T)((float)p[0] * X + (float)p[1] * Y + (float)p[2] * Z);
+    o[1] = (T)((float)p[3] * X + (float)p[4] * Y + (float)p[5] * Z);
+    o[2] = (T)((float)p[6] * X + (float)p[7] * Y + (float)p[8] * Z);
+  }
+}
+
+// Trilinear interpolation of the 4 fields (field f at fields + f * total) in
+// cell `cell` of grid B at natural coordinates s: weights
+// w_c = prod_d (c_d ? s_d : 1 - s_d) over the 8 corners (periodic wrap).
+template <typename T>
+__device__ __forceinline__ void interp_point(const GridDev& G, int cell, T s0, T s1, T s2,
+                                             const T* __restrict__ fields, long long total, T v[4]) {
+  int ci, cj, ck;
+  cell_ijk(G, cell, ci, cj, ck);
+  T w[8];
+  long long nd[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    T a = (c & 1) ? s0 : (T)1 - s0;
+    T b = (c & 2) ? s1 : (T)1 - s1;
+    T d = (c & 4) ? s2 : (T)1 - s2;
+    w[c] = a * b * d;
+    nd[c] = G.node_off + corner_node(G, ci, cj, ck, c);
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    gmem<T>* F = gp(fields) + (long long)f * total;
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += w[c] * F[nd[c]];
+    v[f] = acc;
   }
 }
 

@@ -327,16 +327,17 @@ __device__ __forceinline__ void exact_world(const GridDev& GA, const double* pa,
   x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
 }
 
-// exact = true takes the position from the FP64 node coordinates even where
-// the transform's output is FP32.
+// The query of grid A's node m with its offset (o0, o1, o2) from the
+// transform (x - c_A). exact = true (or the background in FP32) takes the
+// position from the FP64 node coordinates instead, where the transform's
+// output is FP32.
 template <typename T>
-__device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
-                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
-                                            const int32_t* __restrict__ q_node, const T* __restrict__ qx,
-                                            long long cap, long long q, bool exact = false) {
+__device__ __forceinline__ Query make_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                            const uint8_t* __restrict__ flags, int A, long long m, double o0,
+                                            double o1, double o2, bool exact) {
   Query Q;
-  Q.A = q_grid[q];
-  Q.m = q_node[q];
+  Q.A = A;
+  Q.m = m;
   const GridDev& GA = grids[Q.A];
   Q.key = GA.node_off + Q.m;
   Q.cause = flags[Q.key] >> 2;
@@ -348,7 +349,6 @@ __device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, i
     // lose most of a cell); take them in FP64
     exact_world(GA, pa, Q.m, Q.x);
   } else {
-    const double o0 = (double)qx[q], o1 = (double)qx[cap + q], o2 = (double)qx[2 * cap + q];
     Q.x[0] = pa[9] + o0;
     Q.x[1] = pa[10] + o1;
     Q.x[2] = pa[11] + o2;
@@ -358,6 +358,19 @@ __device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, i
   }
   Q.finite = isfinite(Q.x[0]) && isfinite(Q.x[1]) && isfinite(Q.x[2]);
   return Q;
+}
+
+// Query q of the list, its offset read from the transform's output qx.
+template <typename T>
+__device__ __forceinline__ Query load_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                                            const int32_t* __restrict__ q_node, const T* __restrict__ qx,
+                                            long long cap, long long q, bool exact = false) {
+  const int A = q_grid[q];
+  const bool need = !(sizeof(T) == 4 && (exact || A == 0));
+  const double o0 = need ? (double)qx[q] : 0.0, o1 = need ? (double)qx[cap + q] : 0.0,
+               o2 = need ? (double)qx[2 * cap + q] : 0.0;
+  return make_query<T>(grids, ngrids, sp, flags, A, q_node[q], o0, o1, o2, exact);
 }
 
 __device__ __forceinline__ void body_frame(const double* pb, const double x[3], double xi[3]) {
@@ -705,6 +718,189 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The whole back half of a step in one kernel (the step executors' form of
+// the transform, the three search passes and the interpolation). Each block
+// takes 256 queries at a time, one per thread: the transform; the walk over
+// the candidate grids, with the FP64 correction of an undecided FP32 walk
+// done at once by its lane; then the block's deferred queries one at a time
+// with all its threads, as in the scan pass; then each thread writes its
+// result and interpolates its fields. Every rule that orders candidates,
+// seeds and deferrals is the one of the separate passes, so the results are
+// the same bit for bit.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_back(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+           const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid, const int32_t* __restrict__ q_node,
+           T* __restrict__ qx, const long long* __restrict__ d_count, long long cap,
+           int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
+           int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
+           int use_warm, int max_walk, int32_t* __restrict__ dev_status, const T* __restrict__ fields,
+           long long total_nodes, T* __restrict__ out, long long* __restrict__ count_out) {
+  __shared__ double sp[kMaxGrids * 12];
+  __shared__ int list_q[256], list_st[256];
+  __shared__ int nlist;
+  __shared__ ScanLds S;
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const long long n = min(*d_count, cap);
+  if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = *d_count;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();  // (also orders the pose staging before the first use)
+    const long long q = base + threadIdx.x;
+    const bool mine = q < n;
+    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    int visited = 0;
+    bool limit = false;
+    long long key = 0;
+    if (mine) {
+      const int A = q_grid[q];
+      T o[3];
+      transform_node<T>(grids[A], sp + 12 * A, q_node[q], o);
+      qx[q] = o[0];
+      qx[cap + q] = o[1];
+      qx[2 * cap + q] = o[2];
+      const Query Q =
+          make_query<T>(grids, ngrids, sp, flags, A, q_node[q], (double)o[0], (double)o[1], (double)o[2], false);
+      key = Q.key;
+      int defer = 0, defer_t = 0;
+      if (!Q.finite) {
+        atomicOr(dev_status, OV_DEV_NONFINITE);
+      } else {
+        const int wg = use_warm ? (int)warm_grid[Q.key] : 255;
+        for (int t = -2; t < ngrids; ++t) {
+          const int B = candidate_at(t, Q.A, Q.first);
+          if (B < 0) continue;
+          const GridDev& G = grids[B];
+          double xi[3];
+          if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+          const int rep = gp(G.brep)[bin_of(G, xi)];
+          int seed = -1;
+          if (wg == B) {
+            int wc = warm_cell[Q.key];
+            if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
+          }
+          if (seed < 0 && rep < 0) continue;
+          int cell = seed >= 0 ? seed : rep;
+          T s[3];
+          const uint8_t* fl = flags + G.node_off;
+          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
+          if (r == kToScan && seed >= 0 && rep >= 0 && rep != seed) {
+            cell = rep;
+            r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
+          }
+          int how = OV_Q_FOUND;
+          if (sizeof(T) == 4 && r == kDoubt) {
+            // the FP64 correction: the walk goes on from this cell in FP64
+            // on the exact position
+            const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
+            double xe[3], s64[3];
+            body_frame(sp + 12 * B, QE.x, xe);
+            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited);
+            s[0] = (T)s64[0];
+            s[1] = (T)s64[1];
+            s[2] = (T)s64[2];
+            how = OV_Q_FOUND | OV_Q_FP64_FIXED;
+          }
+          if (r == kFound) {
+            res_grid = B;
+            res_cell = cell;
+            res_status = how;
+            rs[0] = s[0];
+            rs[1] = s[1];
+            rs[2] = s[2];
+          } else {
+            defer = 1;
+            defer_t = t;
+          }
+          break;
+        }
+      }
+      if (defer) {
+        const int slot = atomicAdd(&nlist, 1);
+        list_q[slot] = (int)threadIdx.x;
+        list_st[slot] = defer_status(defer_t, visited);
+      }
+    }
+    __syncthreads();
+    const int nd = nlist;
+    for (int d = 0; d < nd; ++d) {
+      // every thread takes the deferred query (same values in all lanes)
+      const int owner = list_q[d];
+      const long long qd = base + owner;
+      const int st = list_st[d];
+      const int t0 = (st & 255) - 2;
+      int dvisited = (st >> 8) & 255;
+      const int A = q_grid[qd];
+      T o[3] = {0, 0, 0};
+      if (sizeof(T) == 8) transform_node<T>(grids[A], sp + 12 * A, q_node[qd], o);  // (FP32: the exact position)
+      const Query Q =
+          make_query<T>(grids, ngrids, sp, flags, A, q_node[qd], (double)o[0], (double)o[1], (double)o[2], true);
+      int g_grid = -1, g_cell = -1, g_status = OV_Q_ORPHAN;
+      T gs[3] = {(T)NAN, (T)NAN, (T)NAN};
+      bool dlimit = false;
+      for (int t = t0; t < ngrids; ++t) {
+        const int B = candidate_at(t, Q.A, Q.first);
+        if (B < 0) continue;
+        const GridDev& G = grids[B];
+        double xi[3];
+        if (t == t0) body_frame(sp + 12 * B, Q.x, xi);
+        else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+        const uint8_t* fl = flags + G.node_off;
+        int cell = -1, how = OV_Q_FALLBACK;
+        T s[3];
+        bool walked = false;
+        if (t != t0) {
+          int seed = gp(G.brep)[bin_of(G, xi)];
+          if (seed < 0) continue;
+          cell = seed;
+          how = OV_Q_FOUND;
+          walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited) == kFound;
+        }
+        if (!walked) {
+          double s64[3];
+          cell = scan_control_cell_block(G, fl, xi, s64, S);
+          s[0] = (T)s64[0];
+          s[1] = (T)s64[1];
+          s[2] = (T)s64[2];
+          how = OV_Q_FALLBACK;
+        }
+        if (cell >= 0) {
+          g_grid = B;
+          g_cell = cell;
+          g_status = how;
+          gs[0] = s[0];
+          gs[1] = s[1];
+          gs[2] = s[2];
+          break;
+        }
+      }
+      if ((int)threadIdx.x == owner) {
+        res_grid = g_grid;
+        res_cell = g_cell;
+        res_status = g_status;
+        rs[0] = gs[0];
+        rs[1] = gs[1];
+        rs[2] = gs[2];
+        visited = dvisited;
+        limit |= dlimit;
+      }
+    }
+    if (mine) {
+      if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+      write_result<T>(q, cap, key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
+                      donor_cell, s_out, status, warm_cell, warm_grid);
+      if (fields && res_grid >= 0) {
+        T v[4];
+        interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, v);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) out[(long long)f * cap + q] = v[f];
+      }
+    }
+    __syncthreads();  // nlist and the list are rebuilt for the next range
+  }
+}
+
 template <typename T>
 static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                             const int32_t* q_node, const T* qx, const long long* d_count, long long capacity,
@@ -728,6 +924,19 @@ static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* fla
                      ctx->d_status);
 }
 
+template <typename T>
+static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                          const int32_t* q_node, T* qx, const long long* d_count, long long capacity,
+                          int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, const T* fields,
+                          T* out, long long* count_out, hipStream_t st) {
+  const long long grid =
+      std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + 255) / 256));
+  hipLaunchKernelGGL(k_back<T>, dim3((unsigned)grid), dim3(256), 0, st, ctx->d_grids, (int)ctx->grids.size(), poses,
+                     flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status,
+                     ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, fields,
+                     ctx->node_off.back(), out, count_out);
+}
+
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                                const int32_t* q_node, const void* qx, const long long* d_count, long long capacity,
                                int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, hipStream_t st) {
@@ -738,6 +947,39 @@ hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* 
     launch_search_t<double>(ctx, poses, flags, q_grid, q_node, (const double*)qx, d_count, capacity, donor_grid,
                             donor_cell, (double*)s, status, st);
   return hipGetLastError();
+}
+
+__global__ void k_copy_count(long long* __restrict__ dst, const long long* __restrict__ src) { *dst = *src; }
+
+hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, dst, (const long long*)src);
+  return hipGetLastError();
+}
+
+hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
+                       const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
+                       int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
+                       void* out, long long* count_out, hipStream_t st) {
+  if (capacity > 0 && ctx->back_fused) {
+    if (ctx->precision == OV_MIXED)
+      launch_back_t<float>(ctx, poses, flags, q_grid, q_node, (float*)qx, d_count, capacity, donor_grid, donor_cell,
+                           (float*)s, status, (const float*)fields, (float*)out, count_out, st);
+    else
+      launch_back_t<double>(ctx, poses, flags, q_grid, q_node, (double*)qx, d_count, capacity, donor_grid,
+                            donor_cell, (double*)s, status, (const double*)fields, (double*)out, count_out, st);
+    return hipGetLastError();
+  }
+  hipError_t e = hipSuccess;
+  if (capacity > 0) {
+    e = launch_transform(ctx, poses, q_grid, q_node, d_count, capacity, qx, st);
+    if (e == hipSuccess)
+      e = launch_donor_search(ctx, poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s,
+                              status, st);
+    if (e == hipSuccess && fields)
+      e = launch_interp(ctx, donor_grid, donor_cell, s, d_count, capacity, fields, out, st);
+  }
+  if (e == hipSuccess && count_out) e = launch_copy_count(count_out, (const int64_t*)d_count, st);
+  return e;
 }
 
 }  // namespace ov

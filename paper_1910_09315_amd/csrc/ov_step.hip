@@ -30,6 +30,8 @@ struct HoleLds {
   int kind[kMaxGrids];
   int outer[kMaxGrids];
   unsigned long long allmask;  // every grid with a blank region
+  double box[kMaxGrids][6];    // blank region's body-frame box (lo xyz, hi xyz)
+  double rad[kMaxGrids];       // radius of the sphere about the origin enclosing it
 };
 
 template <typename CT>
@@ -71,6 +73,26 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
       L.Z[g] = G.Z;
     }
     if (g == ngrids - 1) L.off[ngrids] = G.node_off + G.nnodes;
+    L.rad[g] = sqrt(G.cull_r2);
+    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    if (G.blank_kind == OV_BLANK_CYL) {
+      lo[0] = lo[1] = -q[0];
+      hi[0] = hi[1] = q[0];
+      lo[2] = q[1];
+      hi[2] = q[2];
+    } else if (G.blank_kind == OV_BLANK_SPHERE) {
+      lo[0] = lo[1] = lo[2] = -q[0];
+      hi[0] = hi[1] = hi[2] = q[0];
+    } else if (G.blank_kind == OV_BLANK_ELLIPSOID) {
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = -q[d];
+        hi[d] = q[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      L.box[g][d] = lo[d];
+      L.box[g][3 + d] = hi[d];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -314,20 +336,18 @@ static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI *
 // scratch slot this step uses (separate slots let the hole cut of one step
 // overlap the fringe pass of the previous one).
 __device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigned int* d_stamp, int32_t* near_count,
-                                                  int32_t* chunk_list_count, int32_t* cand_count) {
+                                                  int32_t* chunk_list_count) {
   unsigned int v = *counter + 1u;
   v = v == 0u ? 1u : v;  // 0 marks "never listed"
   *counter = v;
   *d_stamp = v;
   *near_count = 0;
   *chunk_list_count = 0;
-  *cand_count = 0;
 }
 
 __global__ void k_begin_step(unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
-                             int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count,
-                             int32_t* __restrict__ cand_count) {
-  k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, cand_count);
+                             int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count) {
+  k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
 }
 
 // Tile index along one axis holding the node `which` positions from tile t:
@@ -361,84 +381,35 @@ __device__ __forceinline__ void mark_near(int e, int ti, int tj, int tk, int ni,
   if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = (int32_t)n;
 }
 
-// Which blank regions may reach each sub-tile (bit B set: grid B's region
+// Which blank regions may reach sub-tile `sub` (bit B set: grid B's region
 // may contain a node of it). The sub-tile's bounding sphere, placed at its
 // grid's pose, is tested against the sphere about grid B's origin that
 // encloses B's region, then against the region's box in B's body frame
 // (distance from the sphere's centre to the box at most the radius). The
 // radius is padded far beyond FP64 rounding, so no node the exact test
-// would blank is ever culled. One thread per sub-tile; sub-tiles with a
-// non-empty mask are appended to the candidate list.
-__global__ void __launch_bounds__(256) k_tile_masks(const GridDev* __restrict__ grids, int ngrids,
-                                                   const double* __restrict__ poses,
-                                                   const double4* __restrict__ spheres,
-                                                   const int4* __restrict__ tile_info, long long total_tiles,
-                                                   unsigned long long* __restrict__ tile_mask,
-                                                   int32_t* __restrict__ cand_list,
-                                                   int32_t* __restrict__ cand_count) {
-  __shared__ double P[kMaxGrids][12];
-  __shared__ double box[kMaxGrids][6];
-  __shared__ double rad[kMaxGrids];
-  __shared__ unsigned long long blanks;
-  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) P[i / 12][i % 12] = poses[i];
-  for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
-    const GridDev& G = grids[g];
-    rad[g] = sqrt(G.cull_r2);
-    const double* q = G.blank_prm;
-    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
-    if (G.blank_kind == OV_BLANK_CYL) {
-      lo[0] = lo[1] = -q[0];
-      hi[0] = hi[1] = q[0];
-      lo[2] = q[1];
-      hi[2] = q[2];
-    } else if (G.blank_kind == OV_BLANK_SPHERE) {
-      lo[0] = lo[1] = lo[2] = -q[0];
-      hi[0] = hi[1] = hi[2] = q[0];
-    } else if (G.blank_kind == OV_BLANK_ELLIPSOID) {
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = -q[d];
-        hi[d] = q[d];
-      }
-    }
-    for (int d = 0; d < 3; ++d) {
-      box[g][d] = lo[d];
-      box[g][3 + d] = hi[d];
-    }
+// would blank is ever culled.
+__device__ __forceinline__ unsigned long long sub_mask(const HoleLds& L, int A, double4 sp) {
+  const double* pa = L.pose[A];
+  const double w0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
+  const double w1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
+  const double w2 = pa[6] * sp.x + pa[7] * sp.y + pa[8] * sp.z + pa[11];
+  unsigned long long mask = 0;
+  for (unsigned long long mm = L.allmask & ~(1ull << A); mm; mm &= mm - 1) {
+    const int B = __ffsll((long long)mm) - 1;
+    const double* p = L.pose[B];
+    const double d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
+    const double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double r = sp.w + 1e-9 * (sp.w + dd + L.rad[B]) + 1e-12;
+    if (dd > L.rad[B] + r) continue;
+    const double x = p[0] * d0 + p[3] * d1 + p[6] * d2;
+    const double y = p[1] * d0 + p[4] * d1 + p[7] * d2;
+    const double z = p[2] * d0 + p[5] * d1 + p[8] * d2;
+    const double ex = fmax(fmax(L.box[B][0] - x, x - L.box[B][3]), 0.0);
+    const double ey = fmax(fmax(L.box[B][1] - y, y - L.box[B][4]), 0.0);
+    const double ez = fmax(fmax(L.box[B][2] - z, z - L.box[B][5]), 0.0);
+    if (ex * ex + ey * ey + ez * ez <= r * r) mask |= 1ull << B;
   }
-  if (threadIdx.x == 0) {
-    unsigned long long m = 0;
-    for (int g = 0; g < ngrids; ++g)
-      if (grids[g].blank_kind != OV_BLANK_NONE) m |= 1ull << g;
-    blanks = m;
-  }
-  __syncthreads();
-  for (long long sub = (long long)blockIdx.x * blockDim.x + threadIdx.x; sub < total_tiles * kSubPerTile;
-       sub += (long long)gridDim.x * blockDim.x) {
-    const int A = tile_info[sub / kSubPerTile].x;
-    const double4 sp = spheres[sub];
-    const double* pa = P[A];
-    const double w0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
-    const double w1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
-    const double w2 = pa[6] * sp.x + pa[7] * sp.y + pa[8] * sp.z + pa[11];
-    unsigned long long mask = 0;
-    for (unsigned long long mm = blanks & ~(1ull << A); mm; mm &= mm - 1) {
-      const int B = __ffsll((long long)mm) - 1;
-      const double* p = P[B];
-      const double d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
-      const double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      const double r = sp.w + 1e-9 * (sp.w + dd + rad[B]) + 1e-12;
-      if (dd > rad[B] + r) continue;
-      const double x = p[0] * d0 + p[3] * d1 + p[6] * d2;
-      const double y = p[1] * d0 + p[4] * d1 + p[7] * d2;
-      const double z = p[2] * d0 + p[5] * d1 + p[8] * d2;
-      const double ex = fmax(fmax(box[B][0] - x, x - box[B][3]), 0.0);
-      const double ey = fmax(fmax(box[B][1] - y, y - box[B][4]), 0.0);
-      const double ez = fmax(fmax(box[B][2] - z, z - box[B][5]), 0.0);
-      if (ex * ex + ey * ey + ez * ez <= r * r) mask |= 1ull << B;
-    }
-    tile_mask[sub] = mask;
-    if (mask) cand_list[atomicAdd(cand_count, 1)] = (int32_t)sub;
-  }
+  return mask;
 }
 
 // Geometry of every grid for the tile kernels, staged in LDS.
@@ -471,11 +442,12 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// The culled hole cut runs in three kernels, in stream order:
-//  k_flag_fill       every node's flag as if no blank region reached it
-//                    (field, or fringe on the fixed outer-boundary layers);
-//  k_tile_masks      which blank regions may reach each sub-tile, listing the
-//                    sub-tiles with any (the candidates);
+// The culled hole cut runs in two kernels, in stream order:
+//  k_fill_masks      every node's flag as if no blank region reached it
+//                    (field, or fringe on the fixed outer-boundary layers),
+//                    and in other blocks of the same launch which blank
+//                    regions may reach each sub-tile, listing the sub-tiles
+//                    with any (the candidates);
 //  k_holecut_cand_*  the candidate sub-tiles' nodes tested, their flags
 //                    rewritten, and the tiles within buffer reach of a hole
 //                    put on the near list for the fringe pass.
@@ -486,19 +458,12 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
 // one thread each.
 constexpr int kFillUnroll = 4;
 
-__global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
-                                                  const uint8_t* __restrict__ base,
-                                                  const long long* __restrict__ fill_ranges, int nranges,
-                                                  long long fill_words, unsigned int* __restrict__ counter,
-                                                  unsigned int* __restrict__ d_stamp,
-                                                  int32_t* __restrict__ near_count,
-                                                  int32_t* __restrict__ chunk_list_count,
-                                                  int32_t* __restrict__ cand_count) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, cand_count);
+__device__ __forceinline__ void flag_fill_body(uint8_t* __restrict__ flags, const uint8_t* __restrict__ base,
+                                               const long long* __restrict__ fill_ranges, int nranges,
+                                               long long fill_words, long long bid, long long nblocks) {
   gmem<long long>* R = gp(fill_ranges);
-  const long long nthreads = (long long)gridDim.x * blockDim.x;
-  for (long long w0 = (long long)blockIdx.x * blockDim.x * kFillUnroll + threadIdx.x; w0 < fill_words;
+  const long long nthreads = nblocks * blockDim.x;
+  for (long long w0 = bid * blockDim.x * kFillUnroll + threadIdx.x; w0 < fill_words;
        w0 += nthreads * kFillUnroll) {
 #pragma unroll
     for (int q = 0; q < kFillUnroll; ++q) {
@@ -512,7 +477,7 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
       *reinterpret_cast<uint4*>(flags + x) = v;
     }
   }
-  if (blockIdx.x == 0 && (int)threadIdx.x < nranges) {
+  if (bid == 0 && (int)threadIdx.x < nranges) {
     // bytes before the first and after the last whole word of range r
     const long long a = R[4 * threadIdx.x], b = R[4 * threadIdx.x + 1];
     const bool copy = R[4 * threadIdx.x + 3] != 0;
@@ -521,6 +486,17 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
     for (long long x = a; x < head_end; ++x) flags[x] = copy ? base[x] : (uint8_t)OV_STATE_FIELD;
     for (long long x = tail_begin; x < b; ++x) flags[x] = copy ? base[x] : (uint8_t)OV_STATE_FIELD;
   }
+}
+
+// Block 0 also starts the step (new stamp, empty lists).
+__global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, const uint8_t* __restrict__ base,
+                                                  const long long* __restrict__ fill_ranges, int nranges,
+                                                  long long fill_words, unsigned int* __restrict__ counter,
+                                                  unsigned int* __restrict__ d_stamp,
+                                                  int32_t* __restrict__ near_count,
+                                                  int32_t* __restrict__ chunk_list_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+  flag_fill_body(flags, base, fill_ranges, nranges, fill_words, blockIdx.x, gridDim.x);
 }
 
 // Candidate sub-tiles (kSubI x kTileJ x kTileK nodes), one block each at a
@@ -532,81 +508,64 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags,
 static_assert(kSubI == 16 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a sub-tile with 4 nodes each");
 
 template <typename CT>
-__global__ void __launch_bounds__(256) k_holecut_cand_b(const GridDev* __restrict__ grids, int ngrids,
-                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                     const unsigned long long* __restrict__ sub_mask,
-                                                     const int32_t* __restrict__ cand_list,
-                                                     const int32_t* __restrict__ cand_count,
-                                                     const int4* __restrict__ tile_info,
-                                                     const unsigned int* __restrict__ d_stamp,
-                                                     unsigned int* __restrict__ tile_near,
-                                                     int32_t* __restrict__ near_list,
-                                                     int32_t* __restrict__ near_count,
-                                                     unsigned long long* __restrict__ stats) {
-  __shared__ HoleLds L;
-  __shared__ TileGeo TG[kMaxGrids];
-  stage_tile_geo(TG, grids, ngrids);
-  holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
-  const unsigned int stamp = *d_stamp;
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
-  const long long ncand = *cand_count;
-  for (long long c = blockIdx.x; c < ncand; c += gridDim.x) {
-    const int sub = cand_list[c];
-    const unsigned long long mask = uniform_u64(sub_mask[sub]);
-    const int4 ti = tile_info[sub / kSubPerTile];
-    const int A = uniform_i32(ti.x);
-    const TileGeo& G = TG[A];
-    const int ni = G.ni, nj = G.nj, nk = G.nk;
-    const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
-    const int t = threadIdx.x;
-    const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI + 4 * (t & 3), j = ti.z * kTileJ + ((t >> 2) & 7),
-              k = ti.w * kTileK + (t >> 5);
-    const bool ok = i < ni && j < nj && k < nk;
-    const int n = ok ? min(4, ni - i) : 0;
-    const bool outer = L.outer[A] != 0;
-    const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
-    bool hole = false;
-    if (ok) {
-      const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
-      uint8_t* dst = flags + L.off[A] + m0;
-      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
-      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
-      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
-      CT X[4], Y[4], Z[4];
+__device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
+                                           uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
+                                           unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
+                                           int32_t* __restrict__ near_list, int32_t* __restrict__ near_count,
+                                           unsigned long long* __restrict__ stats) {
+  const int4 ti = tile_info[sub / kSubPerTile];
+  const int A = uniform_i32(ti.x);
+  const TileGeo& G = TG[A];
+  const int ni = G.ni, nj = G.nj, nk = G.nk;
+  const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
+  const int t = threadIdx.x;
+  const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI + 4 * (t & 3), j = ti.z * kTileJ + ((t >> 2) & 7),
+            k = ti.w * kTileK + (t >> 5);
+  const bool ok = i < ni && j < nj && k < nk;
+  const int n = ok ? min(4, ni - i) : 0;
+  const bool outer = L.outer[A] != 0;
+  const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
+  bool hole = false;
+  if (ok) {
+    const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+    uint8_t* dst = flags + L.off[A] + m0;
+    gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+    gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+    gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+    CT X[4], Y[4], Z[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < n) {
-          X[r] = Xa[r];
-          Y[r] = Ya[r];
-          Z[r] = Za[r];
-        }
-      uint32_t word = 0u;
+    for (int r = 0; r < 4; ++r)
+      if (r < n) {
+        X[r] = Xa[r];
+        Y[r] = Ya[r];
+        Z[r] = Za[r];
+      }
+    uint32_t word = 0u;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (r >= n) continue;
-        const int cause = holecut_node<CT>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
-        uint32_t f = OV_STATE_FIELD;
-        if (cause >= 0) {
-          f = kHole | (cause << 2);
-          hole = true;
-        } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
-          f = kFringe | (OV_CAUSE_BOUNDARY << 2);
-        }
-        word |= f << (8 * r);
+    for (int r = 0; r < 4; ++r) {
+      if (r >= n) continue;
+      const int cause = holecut_node<CT>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
+      uint32_t f = OV_STATE_FIELD;
+      if (cause >= 0) {
+        f = kHole | (cause << 2);
+        hole = true;
+      } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
+        f = kFringe | (OV_CAUSE_BOUNDARY << 2);
       }
-      if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
-        *reinterpret_cast<uint32_t*>(dst) = word;
-      } else {
-        for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
-      }
+      word |= f << (8 * r);
     }
-    int nr = n;
-    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
-    if ((t & 63) == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
-    if (__syncthreads_or(hole) && t < 125)
-      mark_near(t, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-                near_list, near_count);
+    if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
+      *reinterpret_cast<uint32_t*>(dst) = word;
+    } else {
+      for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
+    }
   }
+  int nr = n;
+  for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
+  if ((t & 63) == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+  if (__syncthreads_or(hole) && t < 125)
+    mark_near(t, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+              near_list, near_count);
 }
 
 // Candidate sub-tiles, one wavefront each at a time (the variant for many
@@ -615,97 +574,133 @@ __global__ void __launch_bounds__(256) k_holecut_cand_b(const GridDev* __restric
 // batches of 4, tests them against the blank regions of the sub-tile's mask
 // only and writes their 16 flags.
 template <typename CT>
-__global__ void __launch_bounds__(256) k_holecut_cand_w(const GridDev* __restrict__ grids, int ngrids,
-                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
-                                                     const unsigned long long* __restrict__ sub_mask,
-                                                     const int32_t* __restrict__ cand_list,
-                                                     const int32_t* __restrict__ cand_count,
-                                                     const int4* __restrict__ tile_info,
-                                                     const unsigned int* __restrict__ d_stamp,
-                                                     unsigned int* __restrict__ tile_near,
-                                                     int32_t* __restrict__ near_list,
-                                                     int32_t* __restrict__ near_count,
-                                                     unsigned long long* __restrict__ stats) {
+__device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
+                                          uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
+                                          unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
+                                          int32_t* __restrict__ near_list, int32_t* __restrict__ near_count,
+                                          unsigned long long* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int4 ti = tile_info[sub / kSubPerTile];
+  const int A = uniform_i32(ti.x);
+  const TileGeo& G = TG[A];
+  const int ni = G.ni, nj = G.nj, nk = G.nk;
+  const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
+  const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI, j = ti.z * kTileJ + (lane & 7),
+            k = ti.w * kTileK + (lane >> 3);
+  const bool ok = i < ni && j < nj && k < nk;
+  const int n = ok ? min(kSubI, ni - i) : 0;
+  const bool outer = L.outer[A] != 0;
+  const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
+  bool hole = false;
+  if (ok) {
+    const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+    uint8_t* dst = flags + L.off[A] + m0;
+    gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+    gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+    gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+    uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;  // the 16 flag bytes
+    // 16 nodes in batches of 4: a batch's coordinates are loaded before
+    // any of its nodes is tested
+#pragma unroll 1
+    for (int b0 = 0; b0 < kSubI; b0 += 4) {
+      uint32_t word = 0u;
+      CT X[4], Y[4], Z[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (b0 + r < n) {
+          X[r] = Xa[b0 + r];
+          Y[r] = Ya[b0 + r];
+          Z[r] = Za[b0 + r];
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = b0 + r;
+        if (e >= n) continue;
+        const int cause = holecut_node<CT>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
+        uint32_t f = OV_STATE_FIELD;
+        if (cause >= 0) {
+          f = kHole | (cause << 2);
+          hole = true;
+        } else if (outer && (row_outer || i + e < o0 || i + e >= ni - o1)) {
+          f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+        }
+        word |= f << (8 * r);
+      }
+      w0 = b0 == 0 ? word : w0;
+      w1 = b0 == 4 ? word : w1;
+      w2 = b0 == 8 ? word : w2;
+      w3 = b0 == 12 ? word : w3;
+    }
+    if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w0, w1, w2, w3);
+    } else {
+      for (int e = 0; e < n; ++e) {
+        const uint32_t wd = e < 4 ? w0 : e < 8 ? w1 : e < 12 ? w2 : w3;
+        dst[e] = (uint8_t)(wd >> (8 * (e & 3)));
+      }
+    }
+  }
+  int nr = n;
+  for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
+  if (lane == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+  if (__any(hole))
+    for (int e = lane; e < 125; e += 64)
+      mark_near(e, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                near_list, near_count);
+}
+
+// The culled hole cut after the fill: each block takes an interleaved share
+// of the sub-tiles (sub-tile s goes to block s mod gridDim, so neighbouring
+// sub-tiles, which are the ones near a body, spread over the blocks), 256
+// per round. One thread per sub-tile computes its mask; the sub-tiles with
+// any (the candidates) are listed in LDS, and the block then tests their
+// nodes, one candidate per block (cand_block) or per wavefront (cand_wave)
+// at a time. No list leaves the block, so nothing needs resetting between
+// steps.
+template <typename CT, bool WAVE>
+__global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__ grids, int ngrids,
+                                                    const double* __restrict__ poses, uint8_t* __restrict__ flags,
+                                                    const double4* __restrict__ spheres,
+                                                    const int4* __restrict__ tile_info, long long nsub,
+                                                    const unsigned int* __restrict__ d_stamp,
+                                                    unsigned int* __restrict__ tile_near,
+                                                    int32_t* __restrict__ near_list,
+                                                    int32_t* __restrict__ near_count,
+                                                    unsigned long long* __restrict__ stats) {
   __shared__ HoleLds L;
   __shared__ TileGeo TG[kMaxGrids];
+  __shared__ int c_sub[256];
+  __shared__ unsigned long long c_mask[256];
+  __shared__ int c_n;
   stage_tile_geo(TG, grids, ngrids);
   holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
   const unsigned int stamp = *d_stamp;
-  const int lane = threadIdx.x & 63;
-  const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
-  const long long ncand = *cand_count;
-  for (long long c = wave; c < ncand; c += nwaves) {
-    const int sub = cand_list[c];
-    const unsigned long long mask = uniform_u64(sub_mask[sub]);
-    const int4 ti = tile_info[sub / kSubPerTile];
-    const int A = uniform_i32(ti.x);
-    const TileGeo& G = TG[A];
-    const int ni = G.ni, nj = G.nj, nk = G.nk;
-    const int o0 = G.o[0], o1 = G.o[1], o2 = G.o[2], o3 = G.o[3], o4 = G.o[4], o5 = G.o[5];
-    const int i = ti.y * kTileI + (sub % kSubPerTile) * kSubI, j = ti.z * kTileJ + (lane & 7),
-              k = ti.w * kTileK + (lane >> 3);
-    const bool ok = i < ni && j < nj && k < nk;
-    const int n = ok ? min(kSubI, ni - i) : 0;
-    const bool outer = L.outer[A] != 0;
-    const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
-    bool hole = false;
-    if (ok) {
-      const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
-      uint8_t* dst = flags + L.off[A] + m0;
-      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
-      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
-      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
-      uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;  // the 16 flag bytes
-      // 16 nodes in batches of 4: a batch's coordinates are loaded before
-      // any of its nodes is tested
-#pragma unroll 1
-      for (int b0 = 0; b0 < kSubI; b0 += 4) {
-        uint32_t word = 0u;
-        CT X[4], Y[4], Z[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (b0 + r < n) {
-            X[r] = Xa[b0 + r];
-            Y[r] = Ya[b0 + r];
-            Z[r] = Za[b0 + r];
-          }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = b0 + r;
-          if (e >= n) continue;
-          const int cause = holecut_node<CT>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
-          uint32_t f = OV_STATE_FIELD;
-          if (cause >= 0) {
-            f = kHole | (cause << 2);
-            hole = true;
-          } else if (outer && (row_outer || i + e < o0 || i + e >= ni - o1)) {
-            f = kFringe | (OV_CAUSE_BOUNDARY << 2);
-          }
-          word |= f << (8 * r);
-        }
-        w0 = b0 == 0 ? word : w0;
-        w1 = b0 == 4 ? word : w1;
-        w2 = b0 == 8 ? word : w2;
-        w3 = b0 == 12 ? word : w3;
-      }
-      if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
-        *reinterpret_cast<uint4*>(dst) = make_uint4(w0, w1, w2, w3);
-      } else {
-        for (int e = 0; e < n; ++e) {
-          const uint32_t wd = e < 4 ? w0 : e < 8 ? w1 : e < 12 ? w2 : w3;
-          dst[e] = (uint8_t)(wd >> (8 * (e & 3)));
-        }
+  const long long nb = gridDim.x;
+  for (long long r0 = 0; r0 < nsub; r0 += 256 * nb) {
+    if (threadIdx.x == 0) c_n = 0;
+    __syncthreads();
+    const long long sub = r0 + (long long)threadIdx.x * nb + blockIdx.x;
+    if (sub < nsub) {
+      const unsigned long long m = sub_mask(L, tile_info[sub / kSubPerTile].x, spheres[sub]);
+      if (m) {
+        const int slot = atomicAdd(&c_n, 1);
+        c_sub[slot] = (int)sub;
+        c_mask[slot] = m;
       }
     }
-    int nr = n;
-    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
-    if (lane == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
-    if (__any(hole))
-      for (int e = lane; e < 125; e += 64)
-        mark_near(e, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-                  near_list, near_count);
+    __syncthreads();
+    const int n = c_n;
+    if (WAVE) {
+      for (int c = threadIdx.x >> 6; c < n; c += 4)
+        cand_wave<CT>(L, TG, grids, flags, tile_info, uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
+                      tile_near, near_list, near_count, stats);
+    } else {
+      for (int c = 0; c < n; ++c)
+        cand_block<CT>(L, TG, grids, flags, tile_info, c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
+                       near_list, near_count, stats);
+    }
+    __syncthreads();  // the list is rebuilt by the next round
   }
 }
 
@@ -764,37 +759,25 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
                                                 (long long)ctx->num_cus * 32));
     hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
-                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc,
-                       ctx->d_cand_count);
-    long long mb = std::max(1LL, std::min((nt * kSubPerTile + 255) / 256, (long long)ctx->num_cus * 4));
-    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)mb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                       (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nt, ctx->d_tile_mask, ctx->d_cand_list,
-                       ctx->d_cand_count);
-    int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc);
+    const long long nsub = nt * kSubPerTile;
+    const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+    const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
+#define OV_SUB_ARGS                                                                                             \
+  ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, st, ctx->d_tile_near, \
+      nl, nc, ctx->d_stats
+    const bool mixed = ctx->precision == OV_MIXED;
     if (ctx->holecut_npl == 4) {
-      long long cb = std::max(1LL, std::min(nt * kSubPerTile, (long long)ctx->num_cus * per_cu));
-      if (ctx->precision == OV_MIXED)
-        hipLaunchKernelGGL(k_holecut_cand_b<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
-      else
-        hipLaunchKernelGGL(k_holecut_cand_b<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
+      if (mixed) hipLaunchKernelGGL((k_holecut_sub<float, false>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
+      else hipLaunchKernelGGL((k_holecut_sub<double, false>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
     } else {
-      long long cb = std::max(1LL, std::min((nt * kSubPerTile + 3) / 4, (long long)ctx->num_cus * per_cu));
-      if (ctx->precision == OV_MIXED)
-        hipLaunchKernelGGL(k_holecut_cand_w<float>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
-      else
-        hipLaunchKernelGGL(k_holecut_cand_w<double>, dim3((unsigned)cb), dim3(256), 0, s, ctx->d_grids, ng, poses,
-                           flags, ctx->d_tile_mask, ctx->d_cand_list, ctx->d_cand_count, ctx->d_tile_info,
-                           st, ctx->d_tile_near, nl, nc, ctx->d_stats);
+      if (mixed) hipLaunchKernelGGL((k_holecut_sub<float, true>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
+      else hipLaunchKernelGGL((k_holecut_sub<double, true>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
     }
+#undef OV_SUB_ARGS
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, counter, st, nc, clc, ctx->d_cand_count);
+  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, counter, st, nc, clc);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st);
   else launch_holecut_t<double>(ctx, poses, flags, s, st);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
@@ -983,11 +966,12 @@ hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int
 
 // ================================================================ compaction
 // Ordered stream compaction of query nodes over 4096-node chunks (in the
-// global node numbering), in three passes. (1) Count each listed chunk (the
-// static list of chunks with outer-boundary nodes, then this step's list of
-// chunks touching near tiles; no other chunk can hold a query node): the
-// count is stored with this step's stamp and added to its superchunk of 64
-// chunks. (2) One block scans the superchunk counts (and zeroes them). (3)
+// global node numbering), in three passes. (1) Count each
+// listed chunk (the static list of chunks with outer-boundary nodes, then
+// this step's list of chunks touching near tiles; no other chunk can hold a
+// query node): the count is stored with this step's stamp and added to its
+// superchunk of 64 chunks. (2) One block scans the superchunk counts (and
+// zeroes them). (3)
 // Each listed chunk with queries takes its superchunk's offset plus the
 // stamped counts of the lower chunks of its superchunk (one 64-lane load
 // and a wavefront sum) and writes its query nodes in node order. Inside a
@@ -1010,6 +994,45 @@ __device__ __forceinline__ int count_fringe16(const uint8_t* p, long long n0, lo
   return __popc(mask);
 }
 
+// Exclusive scan of the superchunk counts by one block of up to 1024
+// threads (each a contiguous run of superchunks); offsets gets nsuper + 1
+// entries, the last the total, which is also the step's query count. The
+// counts are zeroed for the next step.
+__device__ __forceinline__ void super_scan(int32_t* __restrict__ super_counts, long long nsuper,
+                                           long long* __restrict__ offsets, long long* __restrict__ d_count,
+                                           long long capacity, int32_t* __restrict__ status) {
+  __shared__ long long wtot[1024 / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long per = (nsuper + blockDim.x - 1) / blockDim.x;
+  const long long b0 = min(nsuper, (long long)threadIdx.x * per), b1 = min(nsuper, b0 + per);
+  auto count_at = [&](long long e) { return (long long)super_counts[e]; };
+  long long sum = 0;
+  for (long long i = b0; i < b1; ++i)
+    for (int q = 0; q < kSuperSlots; ++q) sum += count_at(i * kSuperSlots + q);
+  long long inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wtot[wave] = inc;
+  __syncthreads();
+  long long run = inc - sum;
+  for (int w = 0; w < wave; ++w) run += wtot[w];
+  for (long long i = b0; i < b1; ++i) {
+    offsets[i] = run;
+    for (int q = 0; q < kSuperSlots; ++q) {
+      run += count_at(i * kSuperSlots + q);
+      super_counts[i * kSuperSlots + q] = 0;  // ready for the next step's count
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) {
+    offsets[nsuper] = run;
+    *d_count = run;
+    if (run > capacity) atomicOr(status, OV_DEV_CAPACITY);
+  }
+}
+
+// Pass (1): the counts.
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
                                                                    unsigned long long* __restrict__ counts,
                                                                    int32_t* __restrict__ super_counts,
@@ -1037,39 +1060,11 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
   }
 }
 
-// Exclusive scan of the superchunk counts in one block (each thread a
-// contiguous run); offsets gets nsuper + 1 entries, the last the total.
+// Pass (2): the scan, one block.
 __global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ super_counts, long long nsuper,
                                                       long long* __restrict__ offsets, long long* __restrict__ d_count,
                                                       long long capacity, int32_t* __restrict__ status) {
-  __shared__ long long wtot[1024 / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long per = (nsuper + blockDim.x - 1) / blockDim.x;
-  const long long b0 = min(nsuper, (long long)threadIdx.x * per), b1 = min(nsuper, b0 + per);
-  long long sum = 0;
-  for (long long i = b0; i < b1; ++i)
-    for (int q = 0; q < kSuperSlots; ++q) sum += super_counts[i * kSuperSlots + q];
-  long long inc = sum;
-  for (int o = 1; o < 64; o <<= 1) {
-    long long t = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += t;
-  }
-  if (lane == 63) wtot[wave] = inc;
-  __syncthreads();
-  long long run = inc - sum;
-  for (int w = 0; w < wave; ++w) run += wtot[w];
-  for (long long i = b0; i < b1; ++i) {
-    offsets[i] = run;
-    for (int q = 0; q < kSuperSlots; ++q) {
-      run += super_counts[i * kSuperSlots + q];
-      super_counts[i * kSuperSlots + q] = 0;  // ready for the next step's count
-    }
-  }
-  if (threadIdx.x == blockDim.x - 1) {
-    offsets[nsuper] = run;
-    *d_count = run;
-    if (run > capacity) atomicOr(status, OV_DEV_CAPACITY);
-  }
+  super_scan(super_counts, nsuper, offsets, d_count, capacity, status);
 }
 
 __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev* __restrict__ grids, int ngrids,
@@ -1209,21 +1204,12 @@ __global__ void k_transform(const GridDev* __restrict__ grids, const double* __r
                             const long long* __restrict__ d_count, long long capacity, T* __restrict__ qx) {
   long long n = min(*d_count, capacity);
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-    int g = q_grid[q];
-    long long m = q_node[q];
-    const GridDev& G = grids[g];
-    const double* p = poses + 12 * g;
-    if (sizeof(T) == 8) {
-      double X = gp(G.X)[m], Y = gp(G.Y)[m], Z = gp(G.Z)[m];
-      qx[q] = (T)(p[0] * X + p[1] * Y + p[2] * Z);
-      qx[capacity + q] = (T)(p[3] * X + p[4] * Y + p[5] * Z);
-      qx[2 * capacity + q] = (T)(p[6] * X + p[7] * Y + p[8] * Z);
-    } else {
-      float X = gp(G.Xf)[m], Y = gp(G.Yf)[m], Z = gp(G.Zf)[m];
-      qx[q] = (T)((float)p[0] * X + (float)p[1] * Y + (float)p[2] * Z);
-      qx[capacity + q] = (T)((float)p[3] * X + (float)p[4] * Y + (float)p[5] * Z);
-      qx[2 * capacity + q] = (T)((float)p[6] * X + (float)p[7] * Y + (float)p[8] * Z);
-    }
+    const int g = q_grid[q];
+    T o[3];
+    transform_node<T>(grids[g], poses + 12 * g, q_node[q], o);
+    qx[q] = o[0];
+    qx[capacity + q] = o[1];
+    qx[2 * capacity + q] = o[2];
   }
 }
 
@@ -1253,28 +1239,10 @@ __global__ void k_interp(const GridDev* __restrict__ grids, const int32_t* __res
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
     int B = donor_grid[q];
     if (B < 0) continue;
-    const GridDev& G = grids[B];
-    int ci, cj, ck;
-    cell_ijk(G, donor_cell[q], ci, cj, ck);
-    T s0 = s[q], s1 = s[capacity + q], s2 = s[2 * capacity + q];
-    T w[8];
-    long long nd[8];
+    T v[4];
+    interp_point<T>(grids[B], donor_cell[q], s[q], s[capacity + q], s[2 * capacity + q], fields, total_nodes, v);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      T a = (c & 1) ? s0 : (T)1 - s0;
-      T b = (c & 2) ? s1 : (T)1 - s1;
-      T d = (c & 4) ? s2 : (T)1 - s2;
-      w[c] = a * b * d;
-      nd[c] = G.node_off + corner_node(G, ci, cj, ck, c);
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const T* F = fields + (long long)f * total_nodes;
-      T acc = 0;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc += w[c] * F[nd[c]];
-      out[(long long)f * capacity + q] = acc;
-    }
+    for (int f = 0; f < 4; ++f) out[(long long)f * capacity + q] = v[f];
   }
 }
 

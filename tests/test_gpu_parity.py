@@ -202,29 +202,39 @@ def test_bad_arguments_rejected_before_launch():
         B.overset_holecut(ctx, x, a.flags)  # before finalize
 
 
-@pytest.mark.parametrize("native,stages,graphs", [(True, 2, False), (False, 2, False), (True, 3, False),
-                                                   (True, 2, True), (True, 3, True)])
-def test_pipeline_matches_sequential(native, stages, graphs):
-    """Steps run by the pipelines (two stages: front half of step t+1 beside
-    the back half of step t; three stages: hole cut of t+1, fringe of t and
-    back half of t-1 together), driven by the library's executor or from
-    Python, equal the single-stream steps bitwise."""
+@pytest.mark.parametrize("native,stages,graphs,fused,precision", [
+    (True, 1, False, True, "fp64"), (True, 1, False, True, "mixed"), (True, 1, True, True, "fp64"),
+    (True, 2, False, True, "fp64"), (True, 2, False, False, "fp64"), (False, 2, False, True, "fp64"),
+    (True, 3, False, True, "mixed"), (True, 3, False, False, "mixed"), (True, 2, True, True, "mixed"),
+    (True, 3, True, True, "fp64")])
+def test_pipeline_matches_sequential(native, stages, graphs, fused, precision):
+    """Steps run by the executors (one stream; two streams: front half of
+    step t+1 beside the back half of step t; three streams: hole cut of t+1,
+    fringe of t and back half of t-1 together), driven by the library's
+    executor or from Python, with the back half as one kernel or as the
+    separate kernels, equal the single-stream five-call steps bitwise,
+    including each step's query count."""
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
-    a = _assembly(w)
-    b = _assembly(w, capacity=a.capacity)
+    a = _assembly(w, precision)
+    b = _assembly(w, precision, capacity=a.capacity, options={"back_fused": int(fused)})
     pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    counts = torch.full((7,), -1, dtype=torch.int64, device="cuda")
     seq = []
     for t in range(7):
         a.step(poses[t])
         seq.append(a.results())
+    lag = 0 if stages == 1 else 1  # one buffer set: a step's results last until the next step
     for t in range(7):
-        pipe.submit(t, poses[t])
-        if t >= 1:
-            r = pipe.results(t - 1)
-            for k in ("flags", "q_node", "donor_grid", "donor_cell", "status", "s", "values"):
-                assert np.array_equal(r[k], seq[t - 1][k], equal_nan=True), (t - 1, k)
+        pipe.submit(t, poses[t], count_out=counts[t:t + 1])
+        if t >= lag:
+            r = pipe.results(t - lag)
+            for k in ("flags", "q_node", "qx", "donor_grid", "donor_cell", "status", "s", "values"):
+                assert np.array_equal(r[k], seq[t - lag][k], equal_nan=True), (t - lag, k)
+    pipe.join()
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [r["count"] for r in seq]
 
 
 def test_graph_pipeline_matches_sequential():
