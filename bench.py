@@ -78,6 +78,9 @@ def main():
                     help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
+    ap.add_argument("--time-every", type=int, default=10,
+                    help="native executor: time the hole cut of every N-th timed step with events (each costs "
+                         "device time)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -184,7 +187,7 @@ def main():
     t_host0 = time.perf_counter()
     if pipe is not None and pipe.native is not None:
         pipe.native.holecut_times(0)  # restart the timing record
-        pipe.native.set_timing(True)
+        pipe.native.set_timing(args.time_every)
     if pipe is not None:
         pipe.wait_current()
     if many:
@@ -211,9 +214,10 @@ def main():
     roofline = None
     roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
     if pipe is not None and pipe.native is not None:
-        pipe.native.set_timing(False)
+        pipe.native.set_timing(0)
         hc_ms = np.array(pipe.native.holecut_times(args.steps))
-        roof_note = "hip events around every hole cut of the timed steps, recorded by the native executor on its front stream"
+        roof_note = (f"hip events around the hole cut of every {args.time_every}-th timed step, recorded by the "
+                     f"native executor on the stream it runs on")
     elif hc:
         hc_ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
     else:

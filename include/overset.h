@@ -273,9 +273,14 @@ int ov_pipe_create1(ov_ctx *ctx, int32_t nf, const ov_step_buffers *set, const v
  * five calls; not a step of the paper's method). Step t uses buffer set
  * sets[t % 2]; its front half (overset_holecut, overset_fringe_compact) runs
  * on stream_front and overlaps the back half (overset_transform,
- * overset_donor_search, overset_interp) of step t-1 on stream_back. Events
- * order front(t) after back(t-2) and back(t) after front(t); back halves
- * follow one another on their stream, which keeps the warm start exact.
+ * overset_donor_search, overset_interp) of step t-1 on stream_back.
+ * front(t) runs after back(t-2) and back(t) after front(t), ordered with
+ * stream memory operations (hipStreamWriteValue64 / hipStreamWaitValue64)
+ * on sequence counters the executor allocates (16-24 bytes of device
+ * memory); back halves follow one another on their stream, which keeps the
+ * warm start exact. The back half runs as one kernel unless
+ * OV_OPT_BACK_FUSED is 0 (same results). Returns OV_EHIP if the device
+ * cannot wait on memory values.
  *  sets        2 buffer sets [host array; the device buffers stay caller-owned]
  *  fields      4*total_nodes field values, or NULL for no interpolation
  *  max_timed   number of steps whose hole cut may be timed (events, see below)
@@ -288,17 +293,17 @@ int ov_pipe_create(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const v
  * marking + compaction (stage B, stream_b) and the back half (stage C,
  * stream_c) of consecutive steps, with three buffer sets (step t uses
  * sets[t % 3]): A(t+1), B(t) and C(t-1) run at the same time. A and B of a
- * step share one of the context's two front-half scratch slots, alternating
- * by step. Events order B(t) after A(t), C(t) after B(t), A(t) after C(t-3)
- * and B(t-2). Same rules as ov_pipe_create otherwise; the three streams must
- * differ. */
+ * step share front-half scratch slot t % 3 of the context. B(t) runs after
+ * A(t), C(t) after B(t) and A(t) after C(t-3). Same rules as ov_pipe_create
+ * otherwise; the three streams must differ. */
 int ov_pipe_create3(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const void *fields,
                     void *stream_a, void *stream_b, void *stream_c, int32_t max_timed, ov_pipe **out);
 
-/* Capture every stage of every buffer set once as a single-stream HIP graph
- * (on a private stream) and replay the graphs from then on: a submitted step
- * becomes one pose copy into a per-set device slot, one graph launch per
- * stage and the ordering events. Must be called before the first submit;
+/* Capture, for every buffer set, the stages each stream runs once as a
+ * single-stream HIP graph (on a private stream) and replay the graphs from
+ * then on: a submitted step becomes one pose copy into a per-set device
+ * slot, one graph launch per stream and the ordering counter operations.
+ * Must be called before the first submit;
  * options set on the context afterwards do not reach the captured graphs.
  * on = 0 returns to direct launches. Returns OV_EHIP (graphs off) if the
  * runtime refuses the capture. */
@@ -318,8 +323,10 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
 /* Make `stream` wait for all work submitted so far. */
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 
-/* Time (or stop timing) the hole cut of the following submitted steps with
- * events on the stream it runs on (front / stage A), up to max_timed steps. */
+/* Time the hole cut of every on-th following submitted step (on = 1: every
+ * step; 0: stop timing) with events on the stream it runs on (front / stage
+ * A), up to max_timed steps. Each timed step adds two event records to the
+ * stream, which cost device time of their own. */
 int ov_pipe_set_timing(ov_pipe *pipe, int32_t on);
 
 /* Elapsed milliseconds of the timed hole cuts so far (waits for them) into

@@ -252,8 +252,9 @@ class NativePipe:
     def join(self, stream=None):
         self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")
 
-    def set_timing(self, on: bool):
-        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(bool(on))), "ov_pipe_set_timing")
+    def set_timing(self, every: int):
+        """Time the hole cut of every `every`-th following step (0: stop)."""
+        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(every)), "ov_pipe_set_timing")
 
     def holecut_times(self, max_n: int):
         out = (ctypes.c_float * max(1, max_n))()

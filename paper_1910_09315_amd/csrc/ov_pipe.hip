@@ -12,18 +12,22 @@
 //    sets. A(t+1), B(t) and C(t-1) run at the same time.
 // Set k uses front-half scratch slot k of the context (near-tile list,
 // chunk-list length, stamp), so A and B of one step share a slot and no two
-// steps in flight do. Events keep the order every buffer needs: a stage
-// after the previous stage of its step, and the first stage of step t after
+// steps in flight do. The order every buffer needs: a stage runs after the
+// previous stage of its step, and the first stage of step t after
 // the last stage of step t - nsets, the last reader of its buffer set and
 // slot. Stages of one kind follow one another on their stream, which keeps
-// the warm start of the walk exact. Cross-stream waits cost the host far
-// more than launches do, so the stream count is a trade between host time
-// and overlap on the device.
+// the warm start of the walk exact. The order between streams is kept with
+// stream memory operations on 64-bit sequence counters in device memory:
+// after group g of step t its stream writes t + 1 to counter g, and a
+// stream that must follow it waits until the counter is >= t + 1 (the
+// counters only grow). These cost the host far less than event records and
+// event waits; still, the stream count is a trade between host time and
+// overlap on the device.
 //
 // With graphs on (ov_pipe_use_graphs), the stages each stream runs for each
 // buffer set are captured once as a single-stream HIP graph reading its
 // poses from a per-set device slot; a step is then one pose copy, one graph
-// launch per stream and the events.
+// launch per stream and the counter operations.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -36,8 +40,8 @@ struct ov_pipe {
   int nsets = 2;  // = number of streams
   ov_step_buffers sets[3];
   const void* fields = nullptr;
-  hipStream_t st[3] = {};      // stream of each group of stages
-  hipEvent_t done[3][3] = {};  // [group][set]: the group's stages of the set's latest step are done
+  hipStream_t st[3] = {};          // stream of each group of stages
+  unsigned long long* seq = nullptr;  // device: [group] = 1 + the last step whose group is done
   hipEvent_t join[3] = {};
   long long t = 0;
   // graphs
@@ -48,7 +52,7 @@ struct ov_pipe {
   // hole-cut timing (optional)
   std::vector<hipEvent_t> tb, te;
   int ntimed = 0;
-  bool timing = false;
+  int timing = 0;  // time the hole cut of every timing-th submitted step (0: none)
 };
 
 using namespace ov;
@@ -122,10 +126,13 @@ static int pipe_create(ov_ctx* ctx, int32_t nf, int nsets, const ov_step_buffers
   }
   p->fields = fields;
   bool ok = true;
-  for (int g = 0; g < nsets && ok; ++g) {
+  for (int g = 0; g < nsets && ok; ++g)
     ok &= hipEventCreateWithFlags(&p->join[g], hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; k < nsets && ok && nsets > 1; ++k)
-      ok &= hipEventCreateWithFlags(&p->done[g][k], hipEventDisableTiming) == hipSuccess;
+  if (ok && nsets > 1) {
+    int can = 0;
+    ok = hipDeviceGetAttribute(&can, hipDeviceAttributeCanUseStreamWaitValue, ctx->device) == hipSuccess && can;
+    ok = ok && hipMalloc(&p->seq, sizeof(unsigned long long) * 3) == hipSuccess;
+    ok = ok && hipMemset(p->seq, 0, sizeof(unsigned long long) * 3) == hipSuccess;
   }
   p->tb.assign(max_timed, nullptr);
   p->te.assign(max_timed, nullptr);
@@ -135,7 +142,7 @@ static int pipe_create(ov_ctx* ctx, int32_t nf, int nsets, const ov_step_buffers
   }
   if (!ok) {
     ov_pipe_destroy(p);
-    return fail(ctx, OV_EHIP, "ov_pipe_create: event creation failed");
+    return fail(ctx, OV_EHIP, "ov_pipe_create: events or sequence counters could not be created");
   }
   *out = p;
   return OV_OK;
@@ -197,7 +204,8 @@ int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
 
 int ov_pipe_set_timing(ov_pipe* p, int32_t on) {
   if (!p) return OV_EINVAL;
-  p->timing = on != 0;
+  if (on < 0) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_timing: negative stride");
+  p->timing = on;
   return OV_OK;
 }
 
@@ -210,14 +218,16 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   const ov_step_buffers& b = p->sets[k];
   hipError_t e = hipSuccess;
   const double* ps = poses;
-  const bool timed = p->timing && p->ntimed < (int)p->tb.size();
+  const bool timed = p->timing > 0 && t % p->timing == 0 && p->ntimed < (int)p->tb.size();
   for (int g = 0; g < n && e == hipSuccess; ++g) {
     hipStream_t s = p->st[g];
     // after the previous group of this step, or (first group) after the
     // last group of the step that used this buffer set before
     if (n > 1) {
-      if (g > 0) e = hipStreamWaitEvent(s, p->done[g - 1][k], 0);
-      else if (t >= n) e = hipStreamWaitEvent(s, p->done[n - 1][k], 0);
+      if (g > 0)
+        e = hipStreamWaitValue64(s, p->seq + g - 1, (uint64_t)(t + 1), hipStreamWaitValueGte, ~0ull);
+      else if (t >= n)
+        e = hipStreamWaitValue64(s, p->seq + n - 1, (uint64_t)(t + 1 - n), hipStreamWaitValueGte, ~0ull);
     }
     if (e == hipSuccess && g == 0 && p->graphs) {
       double* slot = p->poses_slot + 12 * ctx->grids.size() * k;
@@ -237,7 +247,7 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
         if (e == hipSuccess && timed && stage == 0) e = hipEventRecord(p->te[p->ntimed], s);
       }
     }
-    if (e == hipSuccess && n > 1) e = hipEventRecord(p->done[g][k], s);
+    if (e == hipSuccess && n > 1) e = hipStreamWriteValue64(s, p->seq + g, (uint64_t)(t + 1), 0);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "ov_pipe_submit");
   if (timed) ++p->ntimed;
@@ -284,11 +294,9 @@ int ov_pipe_destroy(ov_pipe* p) {
   for (int g = 0; g < p->nsets; ++g)
     if (p->st[g]) (void)hipStreamSynchronize(p->st[g]);
   destroy_graphs(p);
-  for (int g = 0; g < 3; ++g) {
-    for (int k = 0; k < 3; ++k)
-      if (p->done[g][k]) (void)hipEventDestroy(p->done[g][k]);
+  for (int g = 0; g < 3; ++g)
     if (p->join[g]) (void)hipEventDestroy(p->join[g]);
-  }
+  if (p->seq) (void)hipFree(p->seq);
   for (auto ev : p->tb)
     if (ev) (void)hipEventDestroy(ev);
   for (auto ev : p->te)
