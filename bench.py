@@ -22,6 +22,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fringe points assembled+interpolated/s per step; mixed-batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32
+# Algorithmic flops of the one-kernel back half per unit of work, counted from
+# its code (adds, multiplies and divides; an FMA counts 2):
+#  per walked cell: trilinear map coefficients from the 8 corners (60) plus
+#    the residual, Jacobian and determinant at convergence (114; mixed: + the
+#    condition estimate, 50);
+#  per Newton iteration: residual and Jacobian (100) and the Cramer solve (54);
+#  per fallback-scan candidate: the hull rejection test (290) and the map (60);
+#  per query: transform (15), body frame and bin (30), weights and the
+#    4-field gather (85).
+FLOPS_PER_CELL = {"fp64": 174, "mixed": 224}
+FLOPS_PER_NEWTON_ITER = 154
+FLOPS_PER_SCAN_CANDIDATE = 350
+FLOPS_PER_QUERY = 130
+KERNEL_SOURCES = ["paper_1910_09315_amd/csrc/ov_search.hip", "paper_1910_09315_amd/csrc/ov_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash(files) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(key: str):
+    """HBM bytes per launch measured with rocprofv3 counters for `key`, or
+    None if none were recorded or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            e = json.load(fh).get(key)
+    except (OSError, ValueError):
+        return None
+    if not e or e.get("source_sha256") != source_hash(e.get("sources", KERNEL_SOURCES)):
+        return None
+    return e.get("bytes_per_launch")
 
 
 def log(*a):
@@ -69,7 +108,11 @@ def main():
     ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
     ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
-    ap.add_argument("--stages", type=int, default=1, choices=(1, 2, 3), help="native executor streams")
+    ap.add_argument("--stages", type=int, default=None, choices=(1, 2, 3),
+                    help="native executor streams (default: the tuned choice, else 3)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the executor for this workload first when no tuned entry is cached")
+    ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
     ap.add_argument("--per-step-submit", action="store_true",
                     help="native pipeline: one host call per step instead of one call for all timed steps")
     ap.add_argument("--native-graphs", action="store_true",
@@ -79,8 +122,10 @@ def main():
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
     ap.add_argument("--time-every", type=int, default=10,
-                    help="native executor: time the hole cut of every N-th timed step with events (each costs "
-                         "device time)")
+                    help="native executor: time the roofline kernel of every N-th timed step with events (each "
+                         "costs device time)")
+    ap.add_argument("--roofline", choices=("back", "holecut"), default="back",
+                    help="kernel for the roofline object: the one-kernel back half (native executor) or the hole cut")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -130,6 +175,27 @@ def main():
     cap = 2 * n0 + 4096
     a.allocate(cap)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).to(dev)
+    tuned = None
+    if not (args.graph or args.sequential or args.eager or args.graphs or args.no_tuned):
+        from paper_1910_09315_amd import autotune as AT
+        sig = AT.signature(w, precision)
+        tuned = AT.load(sig)
+        if tuned is None and args.autotune:
+            t1 = time.perf_counter()
+            tuned = AT.tune(a, cap, poses, steps=min(30, w.steps - 3), log=log)
+            tuned["workload"] = w.name
+            AT.store(sig, tuned)
+            log(f"[bench] tuned in {time.perf_counter() - t1:.1f}s: {tuned}")
+        if tuned is not None:
+            params = dict(tuned["params"])
+            if args.npl:
+                params["holecut_npl"] = args.npl
+            AT.apply(a, params)
+            if args.stages is None:
+                args.stages = params["stages"]
+            log(f"[bench] tuned parameters {params}")
+    if args.stages is None:
+        args.stages = 3
     mode = ("graph" if args.graph else "sequential" if args.sequential else "pipelined-py" if args.eager else
             "pipelined-graph" if args.graphs else "pipelined")
     log(f"[bench] set-up done, {n0} queries at t=0, capacity {cap}, mode {mode}")
@@ -185,9 +251,11 @@ def main():
     t_wall = time.perf_counter()
     start.record()
     t_host0 = time.perf_counter()
-    if pipe is not None and pipe.native is not None:
-        pipe.native.holecut_times(0)  # restart the timing record
-        pipe.native.set_timing(args.time_every)
+    native = pipe is not None and pipe.native is not None
+    roof_back = args.roofline == "back" and native and not args.unfused_back
+    if native:
+        pipe.native.stage_times(0)  # restart the timing record
+        pipe.native.set_timing(args.time_every, 2 if roof_back else 0)
     if pipe is not None:
         pipe.wait_current()
     if many:
@@ -212,17 +280,38 @@ def main():
         f"{total_ms / args.steps * 1e3:.1f} us/step, status {status}")
 
     roofline = None
-    roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
-    if pipe is not None and pipe.native is not None:
+    if native:
         pipe.native.set_timing(0)
-        hc_ms = np.array(pipe.native.holecut_times(args.steps))
-        roof_note = (f"hip events around the hole cut of every {args.time_every}-th timed step, recorded by the "
-                     f"native executor on the stream it runs on")
+        ms = np.array(pipe.native.stage_times(args.steps))
+        roof_note = (f"hip events around the {'back half' if roof_back else 'hole cut'} of every "
+                     f"{args.time_every}-th timed step, recorded by the native executor on the stream it runs on")
     elif hc:
-        hc_ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
+        ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
+        roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
     else:
-        hc_ms = None
-    if hc_ms is not None and len(hc_ms):
+        ms = None
+    if ms is not None and len(ms) and roof_back:
+        launches = max(1, stat[5])
+        cells, iters, cands = stat[2] / launches, stat[3] / launches, stat[4] / launches
+        qpl = queries / args.steps
+        flops = (FLOPS_PER_CELL[precision] * cells + FLOPS_PER_NEWTON_ITER * iters
+                 + FLOPS_PER_SCAN_CANDIDATE * cands + FLOPS_PER_QUERY * qpl)
+        avg_s = ms.mean() / 1e3
+        peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+        achieved = flops / avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": "k_back (transform + donor search + interpolation)",
+                    "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 6),
+                    "traffic": recorded_traffic(f"k_back|{w.name}|{precision}"),
+                    "avg_us": round(ms.mean() * 1e3, 2), "algorithmic_flops_per_launch": round(flops),
+                    "per_unit": f"{FLOPS_PER_CELL[precision]} x {cells:.0f} walked cells + {FLOPS_PER_NEWTON_ITER} "
+                                f"x {iters:.0f} Newton iterations + {FLOPS_PER_SCAN_CANDIDATE} x {cands:.0f} "
+                                f"fallback-scan candidates + {FLOPS_PER_QUERY} x {qpl:.0f} queries per launch "
+                                f"(counted by the kernel)",
+                    "peak_note": "vector FP64 peak" if precision == "fp64" else
+                                 "vector FP32 peak (the walk and weights run in FP32; FP64 corrections included)",
+                    "timing": roof_note}
+    elif ms is not None and len(ms):
         nodes = w.total_nodes
         per_node = 25 if precision == "fp64" else 13   # coordinates (3 x 8 or 3 x 4 B) + 1 flag byte
         bytes_launch = per_node * nodes
@@ -237,12 +326,12 @@ def main():
             bytes_launch = int(nodes + base_nodes + coord_b * stat[0] / max(1, stat[1]) + 32 * nsub)
             per_node = f"1 B flag written x {nodes} nodes + 1 B base flag read x {base_nodes} nodes + {coord_b} B " \
                        f"coordinates x {stat[0] / max(1, stat[1]):.0f} nodes read + 32 B x {nsub} sub-tile spheres"
-        avg_s = hc_ms.mean() / 1e3
+        avg_s = ms.mean() / 1e3
         achieved = bytes_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": "hole cut (k_fill_masks + k_holecut_cand)" if not args.no_cull
+        roofline = {"bound": "hbm", "kernel": "hole cut (k_flag_fill + k_holecut_sub)" if not args.no_cull
                     else "k_holecut", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "avg_us": round(hc_ms.mean() * 1e3, 2),
+                    "avg_us": round(ms.mean() * 1e3, 2),
                     "algorithmic_bytes_per_launch": bytes_launch,
                     "per_unit": per_node if isinstance(per_node, str) else f"{per_node} B per node x {nodes} nodes",
                     "timing": roof_note}
@@ -260,7 +349,8 @@ def main():
                                    + (", per-stream graphs" if args.native_graphs else "")
                                    + (", unfused back half" if args.unfused_back else ", fused back half")
                                    + ("" if args.per_step_submit else ", one submit call for all timed steps")
-                                   if mode == "pipelined" else "")},
+                                   if mode == "pipelined" else ""),
+                   "tuned": tuned["params"] if tuned else None},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -112,7 +112,9 @@ enum ov_option {
     OV_OPT_BACK_FUSED = 10, /* step executors (ov_pipe_*): 1 (default) runs transform, donor search and
                                interpolation of a step as one kernel; 0 as the separate kernels of the three
                                calls. Same results. */
-    OV_OPT_BACK_BLOCKS = 11 /* 256-thread workgroups per CU of that one kernel (1..32, default 8) */
+    OV_OPT_BACK_BLOCKS = 11,/* workgroups per CU of that one kernel (1..32, default 8) */
+    OV_OPT_BACK_BLOCK = 12  /* its threads per workgroup: 64, 128 or 256 (default; also the width of the
+                               cooperative fallback scan) */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.
@@ -155,6 +157,11 @@ int ov_node_offsets(const ov_ctx *ctx, int64_t *out);
 /* Work counters accumulated by the step calls since the last fetch. */
 #define OV_STAT_HOLECUT_NODES_READ 0  /* nodes whose coordinates the hole cut read */
 #define OV_STAT_HOLECUT_CALLS 1       /* overset_holecut calls */
+/* Donor-search work of the executors' one-kernel back half (counted there only): */
+#define OV_STAT_SEARCH_CELLS 2         /* cells the stencil walks visited */
+#define OV_STAT_NEWTON_ITERS 3         /* Newton iterations, walks and fallback scans */
+#define OV_STAT_SCAN_CANDIDATES 4      /* control-cell list entries the fallback scans tested */
+#define OV_STAT_BACK_CALLS 5           /* launches of that kernel */
 #define OV_STAT_COUNT 8
 
 /* Copy the OV_STAT_COUNT counters into host_out [host] and zero them.
@@ -283,7 +290,7 @@ int ov_pipe_create1(ov_ctx *ctx, int32_t nf, const ov_step_buffers *set, const v
  * cannot wait on memory values.
  *  sets        2 buffer sets [host array; the device buffers stay caller-owned]
  *  fields      4*total_nodes field values, or NULL for no interpolation
- *  max_timed   number of steps whose hole cut may be timed (events, see below)
+ *  max_timed   number of steps whose stage may be timed (events, see below)
  * The context must not be used by other calls while the pipeline has work
  * in flight. Streams must differ and stay alive until ov_pipe_destroy. */
 int ov_pipe_create(ov_ctx *ctx, int32_t nf, const ov_step_buffers *sets, const void *fields,
@@ -323,15 +330,17 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
 /* Make `stream` wait for all work submitted so far. */
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 
-/* Time the hole cut of every on-th following submitted step (on = 1: every
- * step; 0: stop timing) with events on the stream it runs on (front / stage
- * A), up to max_timed steps. Each timed step adds two event records to the
- * stream, which cost device time of their own. */
-int ov_pipe_set_timing(ov_pipe *pipe, int32_t on);
+/* Time stage `stage` (0 = A hole cut, 1 = B fringe + compaction, 2 = C back
+ * half) of every `every`-th following submitted step (counting all steps
+ * submitted to this executor; every = 0 stops timing) with events on the
+ * stream it runs on, up to max_timed steps. With graphs the events bracket
+ * the whole graph of that stage's stream. Each timed step adds two event
+ * records to the stream, which cost device time of their own. */
+int ov_pipe_set_timing(ov_pipe *pipe, int32_t every, int32_t stage);
 
-/* Elapsed milliseconds of the timed hole cuts so far (waits for them) into
+/* Elapsed milliseconds of the timed stages so far (waits for them) into
  * ms_out[0..*n_out) [host], then restarts the record. */
-int ov_pipe_holecut_times(ov_pipe *pipe, float *ms_out, int32_t max, int32_t *n_out);
+int ov_pipe_stage_times(ov_pipe *pipe, float *ms_out, int32_t max, int32_t *n_out);
 
 /* Wait for the pipeline's streams and free its events. */
 int ov_pipe_destroy(ov_pipe *pipe);

@@ -1,0 +1,161 @@
+"""Autotuner for the step executor and its kernels.
+
+The tuned parameters and what they choose:
+  stages        streams of the native executor (1, 2 or 3): host time per
+                step against overlap of the stages on the device;
+  holecut_npl   candidate hole cut, nodes per lane: 4 (one 256-thread block
+                per 16x8x8 sub-tile) or 16 (one wavefront per sub-tile);
+  persist       workgroups per CU of the persistent front-half kernels
+                (candidate hole cut, compaction);
+  back_block    threads per workgroup of the one-kernel back half (64, 128,
+                256; also the width of its cooperative fallback scan);
+  back_blocks   its workgroups per CU.
+Every parameter leaves the results unchanged (the parity tests run the
+variants); only the time per step differs.
+
+Search: coordinate descent from the library defaults, two passes over the
+parameters, each candidate timed over the same steps of the workload (from a
+reset warm-start history, after a short warm-up) with events around one
+multi-step submit. Results are cached in a JSON file keyed by device name,
+precision, grid dimensions and buffer width.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+SPACE = {
+    "stages": (1, 2, 3),
+    "holecut_npl": (4, 16),
+    "persist": (4, 8, 16),
+    "back_block": (64, 128, 256),
+    "back_blocks": (4, 8, 16),
+}
+DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8}
+CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks")
+
+
+def signature(w, precision: str) -> str:
+    import torch
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    dims = ";".join("x".join(str(d) for d in g.dims) for g in w.grids)
+    return f"{dev}|{precision}|nf{w.nf}|{dims}"
+
+
+def load(sig: str, path: str = CACHE):
+    try:
+        with open(path) as fh:
+            return json.load(fh).get(sig)
+    except (OSError, ValueError):
+        return None
+
+
+def store(sig: str, entry: dict, path: str = CACHE):
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        d = {}
+    d[sig] = entry
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+
+
+def time_config(asm, capacity: int, poses, params: dict, steps: int, warmup: int) -> float:
+    """Microseconds per step of the native executor with `params`, over
+    poses[warmup : warmup + steps] after warm-up steps poses[:warmup], from a
+    reset warm-start history."""
+    import torch
+    from .assembly import Pipeline
+    for k in CTX_OPTIONS:
+        asm.ctx.set_option(k, params[k])
+    asm.ctx.reset_history()
+    pipe = Pipeline(asm, capacity, native=True, stages=params["stages"])
+    pipe.submit_many(0, poses[:warmup])
+    pipe.join()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    pipe.wait_current()
+    pipe.submit_many(warmup, poses[warmup:warmup + steps])
+    pipe.join()
+    t1.record()
+    torch.cuda.synchronize()
+    us = t0.elapsed_time(t1) * 1e3 / steps
+    pipe.native.close()
+    return us
+
+
+def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: int = 2, log=print) -> dict:
+    """Coordinate descent over SPACE; returns the best parameters with their
+    time per step and the number of configurations timed."""
+    best = dict(DEFAULTS)
+    seen = {}
+
+    def cost(p):
+        key = tuple(sorted(p.items()))
+        if key not in seen:
+            seen[key] = time_config(asm, capacity, poses, p, steps, warmup)
+            log(f"[autotune] {p} -> {seen[key]:.1f} us/step")
+        return seen[key]
+
+    best_us = cost(best)
+    for _ in range(passes):
+        changed = False
+        for name, values in SPACE.items():
+            for v in values:
+                if v == best[name]:
+                    continue
+                cand = dict(best, **{name: v})
+                us = cost(cand)
+                if us < best_us * 0.99:  # a clear gain only
+                    best, best_us, changed = cand, us, True
+        if not changed:
+            break
+    for k in CTX_OPTIONS:
+        asm.ctx.set_option(k, best[k])
+    asm.ctx.reset_history()
+    return {"params": best, "us_per_step": round(best_us, 2), "configs_timed": len(seen),
+            "steps": steps, "warmup": warmup, "when": time.strftime("%Y-%m-%d")}
+
+
+def apply(asm, params: dict):
+    for k in CTX_OPTIONS:
+        if k in params:
+            asm.ctx.set_option(k, params[k])
+
+
+def main():
+    import argparse
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import workloads as W
+    from .assembly import Assembly
+    ap = argparse.ArgumentParser(description="tune the step executor for a workload and cache the result")
+    ap.add_argument("--config", default="C1")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    w = W.build(args.config)
+    precision = args.precision or w.precision
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision)
+    cap = 2 * a.count_queries(w.poses[0]) + 4096
+    a.allocate(cap)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    steps = min(args.steps, w.steps - 3)
+    res = tune(a, cap, poses, steps=steps)
+    sig = signature(w, precision)
+    res["workload"] = w.name
+    store(sig, res, args.out)
+    print(json.dumps({"signature": sig, **res}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

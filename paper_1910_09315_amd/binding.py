@@ -23,7 +23,7 @@ OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE = 1, 2, 4
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
        "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
-       "back_fused": 10, "back_blocks": 11}
+       "back_fused": 10, "back_blocks": 11, "back_block": 12}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
@@ -31,7 +31,7 @@ EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "o
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
            "overset_interp", "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
            "ov_pipe_submit",
-           "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_holecut_times", "ov_pipe_destroy"]
+           "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_stage_times", "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -83,8 +83,8 @@ def load(path: str = LIB_PATH):
         "ov_pipe_submit": (ctypes.c_int, [_P, _P, _P]),
         "ov_pipe_submit_many": (ctypes.c_int, [_P, _P, _I64, _I64, _P]),
         "ov_pipe_join": (ctypes.c_int, [_P, _P]),
-        "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32]),
-        "ov_pipe_holecut_times": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
+        "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32, _I32]),
+        "ov_pipe_stage_times": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
         "ov_pipe_destroy": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
@@ -252,15 +252,16 @@ class NativePipe:
     def join(self, stream=None):
         self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")
 
-    def set_timing(self, every: int):
-        """Time the hole cut of every `every`-th following step (0: stop)."""
-        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(every)), "ov_pipe_set_timing")
+    def set_timing(self, every: int, stage: int = 0):
+        """Time stage `stage` (0 hole cut, 1 fringe + compaction, 2 back half)
+        of every `every`-th following step (0: stop)."""
+        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(every), int(stage)), "ov_pipe_set_timing")
 
-    def holecut_times(self, max_n: int):
+    def stage_times(self, max_n: int):
         out = (ctypes.c_float * max(1, max_n))()
         n = _I32()
-        self.ctx.check(self.ctx.lib.ov_pipe_holecut_times(self.h, out, int(max_n), ctypes.byref(n)),
-                       "ov_pipe_holecut_times")
+        self.ctx.check(self.ctx.lib.ov_pipe_stage_times(self.h, out, int(max_n), ctypes.byref(n)),
+                       "ov_pipe_stage_times")
         return [out[i] for i in range(n.value)]
 
     def close(self):

@@ -134,6 +134,7 @@ struct ov_ctx {
   int holecut_npl = 16;  // candidate nodes per lane in the culled hole cut: 16 (wavefront per sub-tile) or 4 (block)
   int back_fused = 1;    // step executors: transform, search and interpolation in one kernel
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
+  int back_block = 256;        // its threads per block (64, 128 or 256)
   std::string err;
 };
 

@@ -49,10 +49,11 @@ struct ov_pipe {
   double* poses_slot = nullptr;  // nsets x ngrids x 12
   hipGraphExec_t gx[3][3] = {};  // [set][group]
   hipGraph_t g[3][3] = {};
-  // hole-cut timing (optional)
+  // stage timing (optional)
   std::vector<hipEvent_t> tb, te;
   int ntimed = 0;
-  int timing = 0;  // time the hole cut of every timing-th submitted step (0: none)
+  int timing = 0;       // time stage timed_stage of every timing-th submitted step (0: none)
+  int timed_stage = 0;  // 0 = A (hole cut), 1 = B, 2 = C
 };
 
 using namespace ov;
@@ -202,10 +203,11 @@ int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
   return OV_OK;
 }
 
-int ov_pipe_set_timing(ov_pipe* p, int32_t on) {
+int ov_pipe_set_timing(ov_pipe* p, int32_t every, int32_t stage) {
   if (!p) return OV_EINVAL;
-  if (on < 0) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_timing: negative stride");
-  p->timing = on;
+  if (every < 0 || stage < 0 || stage > 2) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_timing: bad argument");
+  p->timing = every;
+  p->timed_stage = stage;
   return OV_OK;
 }
 
@@ -235,16 +237,18 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
       ps = slot;
     }
     if (p->graphs) {
-      // (timing covers the whole first graph)
-      if (e == hipSuccess && timed && g == 0) e = hipEventRecord(p->tb[p->ntimed], s);
+      // (timing covers the whole graph of the timed stage's stream)
+      const bool tg = timed && p->timed_stage >= first_stage(p, g) && p->timed_stage < first_stage(p, g + 1);
+      if (e == hipSuccess && tg) e = hipEventRecord(p->tb[p->ntimed], s);
       if (e == hipSuccess) e = hipGraphLaunch(p->gx[k][g], s);
-      if (e == hipSuccess && timed && g == 0) e = hipEventRecord(p->te[p->ntimed], s);
+      if (e == hipSuccess && tg) e = hipEventRecord(p->te[p->ntimed], s);
       if (e == hipSuccess && g == n - 1 && count_out) e = launch_copy_count((long long*)count_out, b.d_count, s);
     } else {
       for (int stage = first_stage(p, g); stage < first_stage(p, g + 1) && e == hipSuccess; ++stage) {
-        if (timed && stage == 0) e = hipEventRecord(p->tb[p->ntimed], s);
+        const bool ts = timed && stage == p->timed_stage;
+        if (ts) e = hipEventRecord(p->tb[p->ntimed], s);
         if (e == hipSuccess) e = stage_launch(p, k, stage, ps, s, stage == 2 ? (long long*)count_out : nullptr);
-        if (e == hipSuccess && timed && stage == 0) e = hipEventRecord(p->te[p->ntimed], s);
+        if (e == hipSuccess && ts) e = hipEventRecord(p->te[p->ntimed], s);
       }
     }
     if (e == hipSuccess && n > 1) e = hipStreamWriteValue64(s, p->seq + g, (uint64_t)(t + 1), 0);
@@ -276,13 +280,13 @@ int ov_pipe_join(ov_pipe* p, void* stream) {
   return e == hipSuccess ? OV_OK : hip_fail(p->ctx, e, "ov_pipe_join");
 }
 
-int ov_pipe_holecut_times(ov_pipe* p, float* ms_out, int32_t max, int32_t* n_out) {
+int ov_pipe_stage_times(ov_pipe* p, float* ms_out, int32_t max, int32_t* n_out) {
   if (!p || !n_out || (max > 0 && !ms_out)) return OV_EINVAL;
   int n = p->ntimed < max ? p->ntimed : max;
   for (int i = 0; i < n; ++i) {
     hipError_t e = hipEventSynchronize(p->te[i]);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms_out[i], p->tb[i], p->te[i]);
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "ov_pipe_holecut_times");
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "ov_pipe_stage_times");
   }
   *n_out = n;
   p->ntimed = 0;

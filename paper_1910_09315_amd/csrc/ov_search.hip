@@ -101,12 +101,14 @@ __device__ __forceinline__ T det3(const T J[3][3]) {
 // *cond receives ||J||_F ||J^-1||_F at the result (an upper bound of the
 // 2-norm condition number).
 // *inv_norm receives ||J^-1||_F at the result.
+// *iters (if given) is increased by the iterations taken.
 template <typename T>
-__device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullptr) {
+__device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullptr, int* iters = nullptr) {
   const T tol = sizeof(T) == 8 ? (T)kNewtonTol : (T)kNewtonTolF;
   const int maxit = sizeof(T) == 8 ? kNewtonMaxIt : kNewtonMaxItF;
   s[0] = s[1] = s[2] = (T)0.5;
   for (int it = 0; it < maxit; ++it) {
+    if (iters) ++*iters;
     T r[3], J[3][3];
     map_and_jacobian(m, s, r, J);
     // Cramer's rule with the columns of J
@@ -189,7 +191,7 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
 // perr bounds the error of each component of xi (FP32 only; 0 when exact).
 template <typename T>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
-                    int max_walk, bool& limit, int& visited) {
+                    int max_walk, bool& limit, int& visited, int* iters = nullptr) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   int hist[4] = {-1, -1, -1, -1};  // the last cells visited: a revisit ends the walk
@@ -198,7 +200,8 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     CellMap<T> m;
     load_cell<T>(G, ci, cj, ck, xi, m);
     T cond = 0, inv_norm = 0;
-    bool conv = newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr, sizeof(T) == 4 ? &inv_norm : (T*)nullptr);
+    bool conv =
+        newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr, sizeof(T) == 4 ? &inv_norm : (T*)nullptr, iters);
     const int here = (int)(ci + (long long)G.nci * (cj + (long long)G.ncj * ck));
     if (sizeof(T) == 4) {
       // FP32 decides only clear cases: inside with margin >= 1e-4 in a
@@ -415,13 +418,13 @@ __device__ __forceinline__ long long bin_of(const GridDev& G, const double xi[3]
 template <typename T>
 __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp, const Query& Q, int B,
                                          const uint8_t* fl, const double xi[3], int& cell, T s[3], int max_walk,
-                                         bool& limit, int& how, int& visited) {
+                                         bool& limit, int& how, int& visited, int* iters = nullptr) {
   const GridDev& G = grids[B];
-  int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
+  int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, iters);
   if (sizeof(T) == 4 && r == kDoubt) {
     double s64[3], xe[3];
     exact_body(grids, sp, Q, B, xi, xe);
-    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited);
+    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, iters);
     s[0] = (T)s64[0];
     s[1] = (T)s64[1];
     s[2] = (T)s64[2];
@@ -577,8 +580,10 @@ struct ScanLds {
   double s[4][3];
 };
 
+// *cands / *iters (if given) are increased by this thread's tested list
+// entries and Newton iterations.
 __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3],
-                                       ScanLds& S) {
+                                       ScanLds& S, int* cands = nullptr, int* iters = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long b = bin_of(G, xi);
   const long long e0 = gp(G.bstart)[b], e1 = gp(G.bstart)[b + 1];
@@ -590,6 +595,7 @@ __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, cons
     bool hit = false;
     double s[3] = {0.0, 0.0, 0.0};
     if (e < e1) {
+      if (cands) ++*cands;
       int ci, cj, ck;
       cell_ijk(G, cell, ci, cj, ck);
       double P[8][3];
@@ -600,7 +606,7 @@ __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, cons
       if (!hull_excludes(P, xi)) {
         CellMap<double> m;
         map_from_corners<double>(P, xi, m);
-        hit = newton<double>(m, s, nullptr) && inside<double>(s, kSTol) && cell_valid(G, fl, ci, cj, ck);
+        hit = newton<double>(m, s, nullptr, nullptr, iters) && inside<double>(s, kSTol) && cell_valid(G, fl, ci, cj, ck);
       }
     }
     const unsigned long long hits = __ballot(hit);
@@ -720,29 +726,37 @@ __global__ void __launch_bounds__(256)
 
 // The whole back half of a step in one kernel (the step executors' form of
 // the transform, the three search passes and the interpolation). Each block
-// takes 256 queries at a time, one per thread: the transform; the walk over
+// takes BS (64, 128 or 256) queries at a time, one per thread: the transform; the walk over
 // the candidate grids, with the FP64 correction of an undecided FP32 walk
 // done at once by its lane; then the block's deferred queries one at a time
 // with all its threads, as in the scan pass; then each thread writes its
 // result and interpolates its fields. Every rule that orders candidates,
 // seeds and deferrals is the one of the separate passes, so the results are
 // the same bit for bit.
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS)
     k_back(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid, const int32_t* __restrict__ q_node,
            T* __restrict__ qx, const long long* __restrict__ d_count, long long cap,
            int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
            int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
            int use_warm, int max_walk, int32_t* __restrict__ dev_status, const T* __restrict__ fields,
-           long long total_nodes, T* __restrict__ out, long long* __restrict__ count_out) {
+           long long total_nodes, T* __restrict__ out, long long* __restrict__ count_out,
+           unsigned long long* __restrict__ stats) {
   __shared__ double sp[kMaxGrids * 12];
-  __shared__ int list_q[256], list_st[256];
+  __shared__ int list_q[BS], list_st[BS];
   __shared__ int nlist;
   __shared__ ScanLds S;
+  __shared__ unsigned long long work[3];  // cells walked, Newton iterations, scan candidates
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  if (threadIdx.x < 3) work[threadIdx.x] = 0;
   const long long n = min(*d_count, cap);
-  if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = *d_count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (count_out) *count_out = *d_count;
+    atomicAdd(&stats[OV_STAT_BACK_CALLS], 1ULL);
+  }
+  int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
+  unsigned long long my_cells = 0;
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
     if (threadIdx.x == 0) nlist = 0;
     __syncthreads();  // (also orders the pose staging before the first use)
@@ -784,10 +798,10 @@ __global__ void __launch_bounds__(256)
           int cell = seed >= 0 ? seed : rep;
           T s[3];
           const uint8_t* fl = flags + G.node_off;
-          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
+          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
           if (r == kToScan && seed >= 0 && rep >= 0 && rep != seed) {
             cell = rep;
-            r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited);
+            r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
           }
           int how = OV_Q_FOUND;
           if (sizeof(T) == 4 && r == kDoubt) {
@@ -796,7 +810,7 @@ __global__ void __launch_bounds__(256)
             const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
             double xe[3], s64[3];
             body_frame(sp + 12 * B, QE.x, xe);
-            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited);
+            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters);
             s[0] = (T)s64[0];
             s[1] = (T)s64[1];
             s[2] = (T)s64[2];
@@ -839,6 +853,7 @@ __global__ void __launch_bounds__(256)
       int g_grid = -1, g_cell = -1, g_status = OV_Q_ORPHAN;
       T gs[3] = {(T)NAN, (T)NAN, (T)NAN};
       bool dlimit = false;
+      int walk_iters = 0;  // (the same in every thread: counted once, by the owner)
       for (int t = t0; t < ngrids; ++t) {
         const int B = candidate_at(t, Q.A, Q.first);
         if (B < 0) continue;
@@ -855,11 +870,12 @@ __global__ void __launch_bounds__(256)
           if (seed < 0) continue;
           cell = seed;
           how = OV_Q_FOUND;
-          walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited) == kFound;
+          walked =
+              walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited, &walk_iters) == kFound;
         }
         if (!walked) {
           double s64[3];
-          cell = scan_control_cell_block(G, fl, xi, s64, S);
+          cell = scan_control_cell_block(G, fl, xi, s64, S, &my_cands, &my_iters);
           s[0] = (T)s64[0];
           s[1] = (T)s64[1];
           s[2] = (T)s64[2];
@@ -884,9 +900,11 @@ __global__ void __launch_bounds__(256)
         rs[2] = gs[2];
         visited = dvisited;
         limit |= dlimit;
+        my_iters += walk_iters;
       }
     }
     if (mine) {
+      my_cells += visited;
       if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
       write_result<T>(q, cap, key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
                       donor_cell, s_out, status, warm_cell, warm_grid);
@@ -899,6 +917,13 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();  // nlist and the list are rebuilt for the next range
   }
+  // the block's work, one device atomic per counter
+  if (my_cells) atomicAdd(&work[0], my_cells);
+  if (my_iters) atomicAdd(&work[1], (unsigned long long)my_iters);
+  if (my_cands) atomicAdd(&work[2], (unsigned long long)my_cands);
+  __syncthreads();
+  if (threadIdx.x < 3 && work[threadIdx.x])
+    atomicAdd(&stats[OV_STAT_SEARCH_CELLS + threadIdx.x], work[threadIdx.x]);
 }
 
 template <typename T>
@@ -929,12 +954,17 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
                           const int32_t* q_node, T* qx, const long long* d_count, long long capacity,
                           int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, const T* fields,
                           T* out, long long* count_out, hipStream_t st) {
+  const int bs = ctx->back_block;
   const long long grid =
-      std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + 255) / 256));
-  hipLaunchKernelGGL(k_back<T>, dim3((unsigned)grid), dim3(256), 0, st, ctx->d_grids, (int)ctx->grids.size(), poses,
-                     flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status,
-                     ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, fields,
-                     ctx->node_off.back(), out, count_out);
+      std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + bs - 1) / bs));
+#define OV_BACK_ARGS                                                                                             \
+  ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
+      s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, fields,               \
+      ctx->node_off.back(), out, count_out, ctx->d_stats
+  if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), 0, st, OV_BACK_ARGS);
+  else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), 0, st, OV_BACK_ARGS);
+  else hipLaunchKernelGGL((k_back<T, 256>), dim3((unsigned)grid), dim3(256), 0, st, OV_BACK_ARGS);
+#undef OV_BACK_ARGS
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

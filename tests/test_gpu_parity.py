@@ -214,10 +214,22 @@ def test_pipeline_matches_sequential(native, stages, graphs, fused, precision):
     executor or from Python, with the back half as one kernel or as the
     separate kernels, equal the single-stream five-call steps bitwise,
     including each step's query count."""
+    _check_pipeline(native, stages, graphs, precision, {"back_fused": int(fused)})
+
+
+@pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
+                                     {"persist": 4, "holecut_npl": 4}, {"persist": 16}])
+def test_tuned_variants_match_sequential(options):
+    """Every value the autotuner may pick leaves the results unchanged."""
+    _check_pipeline(True, 1, False, "fp64", options)
+    _check_pipeline(True, 3, False, "mixed", options)
+
+
+def _check_pipeline(native, stages, graphs, precision, options):
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
     a = _assembly(w, precision)
-    b = _assembly(w, precision, capacity=a.capacity, options={"back_fused": int(fused)})
+    b = _assembly(w, precision, capacity=a.capacity, options=options)
     pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     counts = torch.full((7,), -1, dtype=torch.int64, device="cuda")
