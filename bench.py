@@ -99,7 +99,8 @@ def cpu_baseline(w, budget_s: float) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: every step of the workload after the warm-up)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C1")
     ap.add_argument("--precision", default=None, help="fp64 or mixed (default: the config's)")
@@ -121,7 +122,7 @@ def main():
                     help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
-    ap.add_argument("--time-every", type=int, default=10,
+    ap.add_argument("--time-every", type=int, default=16,
                     help="native executor: time the roofline kernel of every N-th timed step with events (each "
                          "costs device time)")
     ap.add_argument("--roofline", choices=("back", "holecut"), default="back",
@@ -161,6 +162,11 @@ def main():
 
     t0 = time.perf_counter()
     w = W.build(args.config)
+    if args.steps is None:
+        args.steps = w.steps - args.warmup
+    if args.warmup + args.steps > w.steps:
+        log(f"[bench] note: steps {args.warmup}..{args.warmup + args.steps - 1} run past the workload's {w.steps} "
+            f"poses and wrap around to pose 0 (a jump the warm start does not follow)")
     precision = args.precision or w.precision
     log(f"[bench] workload {w.name} built in {time.perf_counter() - t0:.1f}s: {w.total_nodes} nodes, "
         f"{w.ngrids} grids, {w.steps} poses, precision {precision}")
@@ -303,7 +309,8 @@ def main():
                     "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 6),
                     "traffic": recorded_traffic(f"k_back|{w.name}|{precision}"),
-                    "avg_us": round(ms.mean() * 1e3, 2), "algorithmic_flops_per_launch": round(flops),
+                    "avg_us": round(ms.mean() * 1e3, 2), "samples_us": [round(x * 1e3, 1) for x in ms],
+                    "algorithmic_flops_per_launch": round(flops),
                     "per_unit": f"{FLOPS_PER_CELL[precision]} x {cells:.0f} walked cells + {FLOPS_PER_NEWTON_ITER} "
                                 f"x {iters:.0f} Newton iterations + {FLOPS_PER_SCAN_CANDIDATE} x {cands:.0f} "
                                 f"fallback-scan candidates + {FLOPS_PER_QUERY} x {qpl:.0f} queries per launch "

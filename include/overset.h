@@ -334,8 +334,12 @@ int ov_pipe_join(ov_pipe *pipe, void *stream);
  * half) of every `every`-th following submitted step (counting all steps
  * submitted to this executor; every = 0 stops timing) with events on the
  * stream it runs on, up to max_timed steps. With graphs the events bracket
- * the whole graph of that stage's stream. Each timed step adds two event
- * records to the stream, which cost device time of their own. */
+ * the whole graph of that stage's stream. With several streams a timed stage
+ * runs alone (it waits for the other streams' earlier work, and the next
+ * step waits for it), so its events time its own kernels, not the queueing
+ * behind other streams; this costs some overlap on the timed steps. Each
+ * timed step also adds two event records to the stream, which cost device
+ * time of their own. */
 int ov_pipe_set_timing(ov_pipe *pipe, int32_t every, int32_t stage);
 
 /* Elapsed milliseconds of the timed stages so far (waits for them) into

@@ -16,8 +16,9 @@ variants); only the time per step differs.
 Search: coordinate descent from the library defaults, two passes over the
 parameters, each candidate timed over the same steps of the workload (from a
 reset warm-start history, after a short warm-up) with events around one
-multi-step submit. Results are cached in a JSON file keyed by device name,
-precision, grid dimensions and buffer width.
+multi-step submit. Results are cached in a JSON file keyed by the device's
+architecture and compute-unit count, the precision, the grid dimensions and
+the buffer width.
 """
 from __future__ import annotations
 
@@ -41,7 +42,11 @@ CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks")
 
 def signature(w, precision: str) -> str:
     import torch
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    if torch.cuda.is_available():
+        pr = torch.cuda.get_device_properties(0)
+        dev = f"{pr.gcnArchName.split(':')[0]}x{pr.multi_processor_count}"
+    else:
+        dev = "cpu"
     dims = ";".join("x".join(str(d) for d in g.dims) for g in w.grids)
     return f"{dev}|{precision}|nf{w.nf}|{dims}"
 

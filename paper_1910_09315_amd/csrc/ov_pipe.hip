@@ -54,6 +54,9 @@ struct ov_pipe {
   int ntimed = 0;
   int timing = 0;       // time stage timed_stage of every timing-th submitted step (0: none)
   int timed_stage = 0;  // 0 = A (hole cut), 1 = B, 2 = C
+  // the timed group runs alone: the next step's first group waits for it
+  int after_group = -1;
+  long long after_value = 0;
 };
 
 using namespace ov;
@@ -225,11 +228,24 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
     hipStream_t s = p->st[g];
     // after the previous group of this step, or (first group) after the
     // last group of the step that used this buffer set before
+    const bool tg = timed && p->timed_stage >= first_stage(p, g) && p->timed_stage < first_stage(p, g + 1);
     if (n > 1) {
       if (g > 0)
         e = hipStreamWaitValue64(s, p->seq + g - 1, (uint64_t)(t + 1), hipStreamWaitValueGte, ~0ull);
       else if (t >= n)
         e = hipStreamWaitValue64(s, p->seq + n - 1, (uint64_t)(t + 1 - n), hipStreamWaitValueGte, ~0ull);
+      if (g == 0 && p->after_group >= 0 && e == hipSuccess) {
+        e = hipStreamWaitValue64(s, p->seq + p->after_group, (uint64_t)p->after_value, hipStreamWaitValueGte, ~0ull);
+        p->after_group = -1;
+      }
+      // a timed group also waits for the previous step's later groups, so
+      // that its events time it alone
+      for (int g2 = g + 1; tg && g2 < n && t >= 1 && e == hipSuccess; ++g2)
+        e = hipStreamWaitValue64(s, p->seq + g2, (uint64_t)t, hipStreamWaitValueGte, ~0ull);
+      if (tg) {
+        p->after_group = g;
+        p->after_value = t + 1;
+      }
     }
     if (e == hipSuccess && g == 0 && p->graphs) {
       double* slot = p->poses_slot + 12 * ctx->grids.size() * k;
@@ -238,7 +254,6 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
     }
     if (p->graphs) {
       // (timing covers the whole graph of the timed stage's stream)
-      const bool tg = timed && p->timed_stage >= first_stage(p, g) && p->timed_stage < first_stage(p, g + 1);
       if (e == hipSuccess && tg) e = hipEventRecord(p->tb[p->ntimed], s);
       if (e == hipSuccess) e = hipGraphLaunch(p->gx[k][g], s);
       if (e == hipSuccess && tg) e = hipEventRecord(p->te[p->ntimed], s);
