@@ -118,6 +118,9 @@ def main():
                     help="native pipeline: one host call per step instead of one call for all timed steps")
     ap.add_argument("--native-graphs", action="store_true",
                     help="the native executor replays per-stream HIP graphs instead of launching kernels directly")
+    ap.add_argument("--fields", choices=("interleaved", "blocks"), default="interleaved",
+                    help="field layout in HBM: u, v, w, p interleaved per node, or four blocks")
+    ap.add_argument("--max-walk", type=int, default=0, help="walk steps before the fallback scan (0: library default)")
     ap.add_argument("--unfused-back", action="store_true",
                     help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
@@ -176,6 +179,9 @@ def main():
         opts["holecut_npl"] = args.npl
     if args.unfused_back:
         opts["back_fused"] = 0
+    if args.max_walk:
+        opts["max_walk"] = args.max_walk
+    opts["field_layout"] = 1 if args.fields == "interleaved" else 0
     a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=opts)
     n0 = a.count_queries(w.poses[0])
     cap = 2 * n0 + 4096
@@ -352,6 +358,8 @@ def main():
                                f"curvilinear background + {w.ngrids - 1} overset shell(s), rigid motion, "
                                f"{precision}, {mode}",
                    "nodes": w.total_nodes, "queries_per_step_mean": round(queries / args.steps, 1),
+                   "fields": "u, v, w, p interleaved per node" if args.fields == "interleaved" else
+                             "u, v, w, p as four blocks",
                    "mode": mode + (f", native executor on {args.stages} stream(s)"
                                    + (", per-stream graphs" if args.native_graphs else "")
                                    + (", unfused back half" if args.unfused_back else ", fused back half")

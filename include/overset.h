@@ -98,7 +98,7 @@ enum ov_blank_kind {
 /* Options (ov_set_option). */
 enum ov_option {
     OV_OPT_WARM = 1,        /* 1 (default): seed the walk from the previous step's donor; 0: cold */
-    OV_OPT_MAX_WALK = 2,    /* walk steps before the brute-force fallback (default 64, >= 1) */
+    OV_OPT_MAX_WALK = 2,    /* walk steps before the brute-force fallback (default 16, >= 1) */
     OV_OPT_SEARCH_BLOCK = 3,/* threads per block of the donor search walk (64..256, multiple of 64) */
     OV_OPT_INTERP_BLOCK = 4,/* threads per block of the interpolation (64..1024, multiple of 64) */
     OV_OPT_HOLECUT_BLOCK = 5,/* threads per block of the hole cut (64..1024, multiple of 64) */
@@ -113,8 +113,11 @@ enum ov_option {
                                interpolation of a step as one kernel; 0 as the separate kernels of the three
                                calls. Same results. */
     OV_OPT_BACK_BLOCKS = 11,/* workgroups per CU of that one kernel (1..32, default 8) */
-    OV_OPT_BACK_BLOCK = 12  /* its threads per workgroup: 64, 128 or 256 (default; also the width of the
+    OV_OPT_BACK_BLOCK = 12, /* its threads per workgroup: 64, 128 or 256 (default; also the width of the
                                cooperative fallback scan) */
+    OV_OPT_FIELD_LAYOUT = 13 /* layout of the fields given to overset_interp and the executors: 0 (default)
+                               four blocks of total_nodes values (u block, v, w, p); 1 interleaved per node
+                               (u, v, w, p of node 0, then node 1, ...): one load per donor corner */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.
@@ -242,7 +245,8 @@ int overset_donor_search(ov_ctx *ctx, const double *poses, const uint8_t *flags,
 /* Trilinear interpolation (Sec. 2.2.6): out[f][i] = sum_{c=0..7} w_c F_f[corner c]
  * with w_c = prod_d (c_d ? s_d : 1 - s_d), for the 4 fields u, v, w, p and every
  * query i < *d_count with a donor; orphans are not written.
- *  fields   4*total_nodes values (u block, v, w, p; grids packed by node offset)
+ *  fields   4*total_nodes values, grids packed by node offset: four blocks (u block, v, w,
+ *           p) or, with OV_OPT_FIELD_LAYOUT = 1, interleaved (u, v, w, p per node)
  *  out      4*capacity values
  * Both double (OV_FP64) or float (OV_MIXED). */
 int overset_interp(ov_ctx *ctx, const int32_t *donor_grid, const int32_t *donor_cell, const void *s,

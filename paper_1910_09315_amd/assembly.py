@@ -58,8 +58,11 @@ class Assembly:
             self.coords.append((X, Y, Z))
             self.ctx.grid_add(g.dims, g.periodic, X, Y, Z, g.blank_kind, tuple(g.blank_prm), tuple(g.outer))
         self.ctx.finalize()
+        self.field_layout = 0
         for k, v in (options or {}).items():
             self.ctx.set_option(k, v)
+            if k == "field_layout":
+                self.field_layout = int(v)
         self.ngrids = len(grids)
         self.total = self.ctx.total_nodes()
         self.node_off = np.array(self.ctx.node_offsets(), dtype=np.int64)
@@ -74,8 +77,11 @@ class Assembly:
 
     # ------------------------------------------------------------ buffers
     def set_fields(self, fields):
+        """fields: [4, total_nodes] (u, v, w, p). Stored as four blocks, or
+        interleaved per node when the context's field layout is 1."""
         npdt = np.float32 if self.dtype == torch.float32 else np.float64
-        f = np.ascontiguousarray(np.asarray(fields).reshape(4, self.total), dtype=npdt)
+        f = np.asarray(fields).reshape(4, self.total)
+        f = np.ascontiguousarray(f.T if self.field_layout == 1 else f, dtype=npdt)
         self.fields = torch.as_tensor(f).to(self.dev).reshape(-1).contiguous()
 
     def allocate(self, capacity: int):

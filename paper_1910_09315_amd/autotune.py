@@ -9,9 +9,15 @@ The tuned parameters and what they choose:
                 (candidate hole cut, compaction);
   back_block    threads per workgroup of the one-kernel back half (64, 128,
                 256; also the width of its cooperative fallback scan);
-  back_blocks   its workgroups per CU.
-Every parameter leaves the results unchanged (the parity tests run the
-variants); only the time per step differs.
+  back_blocks   its workgroups per CU;
+  max_walk      stencil-walk steps before a query goes to the workgroup's
+                cooperative brute-force scan (a long walk is one lane's serial
+                chain, which the whole kernel waits for).
+The first five leave the results unchanged (the parity tests run them);
+max_walk can change the reported cell only for a point that lies within the
+containment tolerance of a face shared by two valid cells (the walk keeps
+the first it meets, the scan the lowest index), never for a point with a
+margin to every face.
 
 Search: coordinate descent from the library defaults, two passes over the
 parameters, each candidate timed over the same steps of the workload (from a
@@ -35,9 +41,10 @@ SPACE = {
     "persist": (4, 8, 16),
     "back_block": (64, 128, 256),
     "back_blocks": (4, 8, 16),
+    "max_walk": (8, 16, 32),
 }
-DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8}
-CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks")
+DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16}
+CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk")
 
 
 def signature(w, precision: str) -> str:
@@ -147,10 +154,12 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--fields", choices=("interleaved", "blocks"), default="interleaved")
     args = ap.parse_args()
     w = W.build(args.config)
     precision = args.precision or w.precision
-    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision)
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision,
+                 options={"field_layout": 1 if args.fields == "interleaved" else 0})
     cap = 2 * a.count_queries(w.poses[0]) + 4096
     a.allocate(cap)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()

@@ -23,7 +23,7 @@ OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE = 1, 2, 4
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
        "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
-       "back_fused": 10, "back_blocks": 11, "back_block": 12}
+       "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",

@@ -673,6 +673,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       if (v != 64 && v != 128 && v != 256) break;
       ctx->back_block = (int)v;
       return OV_OK;
+    case OV_OPT_FIELD_LAYOUT:
+      if (v != 0 && v != 1) break;
+      ctx->field_layout = (int)v;
+      return OV_OK;
     case OV_OPT_PERSIST:
       if (v < 0 || v > 32) break;
       ctx->persist = (int)v;

@@ -124,7 +124,7 @@ struct ov_ctx {
   long long nchunks = 0, nsuper = 0;
   // options
   int warm = 1;
-  int max_walk = 64;
+  int max_walk = 16;
   int search_block = 64;
   int interp_block = 256;
   int holecut_block = 512;
@@ -135,6 +135,7 @@ struct ov_ctx {
   int back_fused = 1;    // step executors: transform, search and interpolation in one kernel
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   int back_block = 256;        // its threads per block (64, 128 or 256)
+  int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
   std::string err;
 };
 
@@ -187,6 +188,7 @@ __device__ __forceinline__ gmem<T>* gp(const T* p) {
 }
 
 typedef double ov_dv2 __attribute__((ext_vector_type(2)));
+typedef float ov_fv4 __attribute__((ext_vector_type(4)));
 
 // (x, y, z) of node n from a grid's gather layout: two 16-byte loads.
 __device__ __forceinline__ void load_xyz(const GridDev& G, long long n, double& x, double& y, double& z) {
@@ -266,12 +268,15 @@ __device__ __forceinline__ void transform_node(const GridDev& G, const double* p
   }
 }
 
-// Trilinear interpolation of the 4 fields (field f at fields + f * total) in
-// cell `cell` of grid B at natural coordinates s: weights
-// w_c = prod_d (c_d ? s_d : 1 - s_d) over the 8 corners (periodic wrap).
+// Trilinear interpolation of the 4 fields in cell `cell` of grid B at
+// natural coordinates s: weights w_c = prod_d (c_d ? s_d : 1 - s_d) over the
+// 8 corners (periodic wrap). Fields: four blocks (field f of node n at
+// fields[f * total + n]) or, interleaved, fields[4 n + f] (one 16- or
+// 32-byte load per corner).
 template <typename T>
 __device__ __forceinline__ void interp_point(const GridDev& G, int cell, T s0, T s1, T s2,
-                                             const T* __restrict__ fields, long long total, T v[4]) {
+                                             const T* __restrict__ fields, long long total, bool interleaved,
+                                             T v[4]) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   T w[8];
@@ -283,6 +288,34 @@ __device__ __forceinline__ void interp_point(const GridDev& G, int cell, T s0, T
     T d = (c & 4) ? s2 : (T)1 - s2;
     w[c] = a * b * d;
     nd[c] = G.node_off + corner_node(G, ci, cj, ck, c);
+  }
+  if (interleaved) {
+    T acc[4] = {0, 0, 0, 0};
+    T q[8][4];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (sizeof(T) == 4) {
+        const ov_fv4 x = ((gmem<ov_fv4>*)gp(fields))[nd[c]];
+        q[c][0] = (T)x.x;
+        q[c][1] = (T)x.y;
+        q[c][2] = (T)x.z;
+        q[c][3] = (T)x.w;
+      } else {
+        gmem<ov_dv2>* p = (gmem<ov_dv2>*)gp(fields) + 2 * nd[c];
+        const ov_dv2 a = p[0], b = p[1];
+        q[c][0] = (T)a.x;
+        q[c][1] = (T)a.y;
+        q[c][2] = (T)b.x;
+        q[c][3] = (T)b.y;
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[f] += w[c] * q[c][f];
+      v[f] = acc[f];
+    }
+    return;
   }
 #pragma unroll
   for (int f = 0; f < 4; ++f) {

@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(BS)
            int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
            int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
            int use_warm, int max_walk, int32_t* __restrict__ dev_status, const T* __restrict__ fields,
-           long long total_nodes, T* __restrict__ out, long long* __restrict__ count_out,
+           long long total_nodes, int interleaved, T* __restrict__ out, long long* __restrict__ count_out,
            unsigned long long* __restrict__ stats) {
   __shared__ double sp[kMaxGrids * 12];
   __shared__ int list_q[BS], list_st[BS];
@@ -910,7 +910,7 @@ __global__ void __launch_bounds__(BS)
                       donor_cell, s_out, status, warm_cell, warm_grid);
       if (fields && res_grid >= 0) {
         T v[4];
-        interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, v);
+        interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, interleaved != 0, v);
 #pragma unroll
         for (int f = 0; f < 4; ++f) out[(long long)f * cap + q] = v[f];
       }
@@ -960,7 +960,7 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, fields,               \
-      ctx->node_off.back(), out, count_out, ctx->d_stats
+      ctx->node_off.back(), ctx->field_layout, out, count_out, ctx->d_stats
   if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), 0, st, OV_BACK_ARGS);
   else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), 0, st, OV_BACK_ARGS);
   else hipLaunchKernelGGL((k_back<T, 256>), dim3((unsigned)grid), dim3(256), 0, st, OV_BACK_ARGS);

@@ -1234,13 +1234,14 @@ template <typename T>
 __global__ void k_interp(const GridDev* __restrict__ grids, const int32_t* __restrict__ donor_grid,
                          const int32_t* __restrict__ donor_cell, const T* __restrict__ s,
                          const long long* __restrict__ d_count, long long capacity, const T* __restrict__ fields,
-                         long long total_nodes, T* __restrict__ out) {
+                         long long total_nodes, int interleaved, T* __restrict__ out) {
   long long n = min(*d_count, capacity);
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
     int B = donor_grid[q];
     if (B < 0) continue;
     T v[4];
-    interp_point<T>(grids[B], donor_cell[q], s[q], s[capacity + q], s[2 * capacity + q], fields, total_nodes, v);
+    interp_point<T>(grids[B], donor_cell[q], s[q], s[capacity + q], s[2 * capacity + q], fields, total_nodes,
+                    interleaved != 0, v);
 #pragma unroll
     for (int f = 0; f < 4; ++f) out[(long long)f * capacity + q] = v[f];
   }
@@ -1253,10 +1254,12 @@ hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* 
   long long total = ctx->node_off.back();
   if (ctx->precision == OV_MIXED)
     hipLaunchKernelGGL(k_interp<float>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, donor_grid,
-                       donor_cell, (const float*)s, d_count, capacity, (const float*)fields, total, (float*)out);
+                       donor_cell, (const float*)s, d_count, capacity, (const float*)fields, total,
+                       ctx->field_layout, (float*)out);
   else
     hipLaunchKernelGGL(k_interp<double>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, donor_grid,
-                       donor_cell, (const double*)s, d_count, capacity, (const double*)fields, total, (double*)out);
+                       donor_cell, (const double*)s, d_count, capacity, (const double*)fields, total,
+                       ctx->field_layout, (double*)out);
   return hipGetLastError();
 }
 

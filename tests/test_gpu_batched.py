@@ -2,8 +2,8 @@
 shells over a stretched background (overlapping overset grids exchange
 fringe points) and many spherical shells with three fringe layers. Small
 variants are checked at every step in both precisions; the full-size cases
-run through the two-stream native executor, as the benchmark does, and are
-checked at sampled steps. Needs an MI355X."""
+run through the three-stream native executor with interleaved fields, as the
+benchmark does, and are checked at sampled steps. Needs an MI355X."""
 import numpy as np
 import pytest
 import torch
@@ -44,10 +44,10 @@ def _run_steps(w, steps, precision, options=None):
     return out
 
 
-def _run_pipeline(w, steps, precision, stages=3):
+def _run_pipeline(w, steps, precision, stages=3, options=None):
     from paper_1910_09315_amd.assembly import Assembly, Pipeline
     o = oracle.Oracle(w.grids, w.nf)
-    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision)
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=options)
     cap = 2 * a.count_queries(w.poses[0]) + 4096
     a.allocate(cap)
     pipe = Pipeline(a, cap, native=True, stages=stages)
@@ -89,7 +89,7 @@ def test_school_small_block_candidate_holecut():
 @pytest.mark.timeout(300)
 def test_school_full_size_pipelined_sampled_steps():
     w = W.c3(steps=200)
-    stats = _run_pipeline(w, [0, 1, 100, 199], "mixed")
+    stats = _run_pipeline(w, [0, 1, 100, 199], "mixed", options={"field_layout": 1})
     assert all(s["orphans"] == 0 for s in stats)
     assert sum(s["overset_to_overset"] for s in stats) > 0
 
@@ -97,5 +97,5 @@ def test_school_full_size_pipelined_sampled_steps():
 @pytest.mark.timeout(300)
 def test_shells_full_size_pipelined_sampled_steps():
     w = W.c4(steps=500)
-    stats = _run_pipeline(w, [0, 499], "mixed")
+    stats = _run_pipeline(w, [0, 499], "mixed", options={"field_layout": 1, "max_walk": 8})
     assert all(s["orphans"] == 0 for s in stats)

@@ -64,6 +64,13 @@ def test_c1_small_block_candidate_holecut_matches_oracle():
     _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_npl": 4})
 
 
+def test_c1_small_interleaved_fields_match_oracle():
+    """Fields interleaved per node (u, v, w, p) instead of four blocks."""
+    w = W.c1_small(steps=3)
+    _run_and_compare(w, [0, 2], options={"field_layout": 1})
+    _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"field_layout": 1})
+
+
 def test_c1_small_mixed_matches_oracle():
     w = W.c1_small(steps=6)
     stats = _run_and_compare(w, list(range(6)), precision="mixed", value_rtol=1e-5, s_tol=1e-4)
@@ -218,7 +225,7 @@ def test_pipeline_matches_sequential(native, stages, graphs, fused, precision):
 
 
 @pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
-                                     {"persist": 4, "holecut_npl": 4}, {"persist": 16}])
+                                     {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1}])
 def test_tuned_variants_match_sequential(options):
     """Every value the autotuner may pick leaves the results unchanged."""
     _check_pipeline(True, 1, False, "fp64", options)
