@@ -156,6 +156,37 @@ __global__ void k_bin_rep(GridDev g, const long long* __restrict__ start, const 
   }
 }
 
+// Sub-bin lists of the split control cells: one block per split bin, one
+// thread per entry of its list; each cell goes on every sub-bin its padded
+// box overlaps (the test that put it on the bin's list). PASS 0 counts,
+// PASS 1 writes.
+template <int PASS>
+__global__ void k_subbins(GridDev g, const int* __restrict__ split, long long nsplit,
+                          unsigned long long* __restrict__ cnt, const long long* __restrict__ sstart,
+                          int* __restrict__ scells) {
+  for (long long h = blockIdx.x; h < nsplit; h += gridDim.x) {
+    const long long b = split[h];
+    const int base = g.bsub[b];
+    const int bx = (int)(b % g.nb[0]), by = (int)((b / g.nb[0]) % g.nb[1]),
+              bz = (int)(b / ((long long)g.nb[0] * g.nb[1]));
+    for (long long e = g.bstart[b] + threadIdx.x; e < g.bstart[b + 1]; e += blockDim.x) {
+      const int c = g.bcells[e];
+      double lo[3], hi[3];
+      cell_box(g, c, lo, hi);
+      const int x0 = sub_axis(g, 0, lo[0], bx), x1 = sub_axis(g, 0, hi[0], bx);
+      const int y0 = sub_axis(g, 1, lo[1], by), y1 = sub_axis(g, 1, hi[1], by);
+      const int z0 = sub_axis(g, 2, lo[2], bz), z1 = sub_axis(g, 2, hi[2], bz);
+      for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+          for (int x = x0; x <= x1; ++x) {
+            const long long k = base + x + kSubBins * (y + kSubBins * z);
+            const unsigned long long p = atomicAdd(&cnt[k], 1ULL);
+            if (PASS == 1) scells[sstart[k] + (long long)p] = c;
+          }
+    }
+  }
+}
+
 // Bounding sphere (body frame) of each sub-tile (kSubI x kTileJ x kTileK
 // nodes, kTileI / kSubI of them per tile along i, sub-tile sb of tile t at
 // index t * kSubPerTile + sb): centre of its coordinate box, radius = half
@@ -313,6 +344,69 @@ int build_control_cells(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   g.bstart = gh.bstart;
   g.bcells = gh.bcells;
   g.brep = gh.brep;
+  g.bsub = nullptr;
+  g.sstart = nullptr;
+  g.scells = nullptr;
+  return build_subbins(ctx, gh, cnt, s);
+}
+
+// Second level of the control cells: bins listing more than kSplitList
+// cells (where cells are much smaller than a bin, e.g. the wedge cells of a
+// shell around its polar axis) get kSubBins^3 sub-bins, so that the
+// brute-force scan of a point reads one sub-bin's list.
+int build_subbins(ov_ctx* ctx, GridHost& gh, const std::vector<unsigned long long>& cnt, hipStream_t s) {
+  GridDev& g = gh.d;
+  const long long nbins = (long long)cnt.size();
+  std::vector<int> split, bsub(nbins, -1);
+  constexpr long long per = (long long)kSubBins * kSubBins * kSubBins;
+  for (long long b = 0; b < nbins; ++b)
+    if ((long long)cnt[b] > kSplitList) {
+      bsub[b] = (int)(per * (long long)split.size());
+      split.push_back((int)b);
+    }
+  if (split.empty()) return OV_OK;
+  const long long nsplit = (long long)split.size(), nsub = per * nsplit;
+  if (nsub >= (1LL << 31)) return fail(ctx, OV_EDIMS, "too many split control cells");
+  int* d_split = nullptr;
+  unsigned long long* d_cnt = nullptr;
+  HIPCHK(hipMalloc(&gh.bsub, sizeof(int) * nbins), "hipMalloc sub-bin index");
+  HIPCHK(hipMalloc(&d_split, sizeof(int) * nsplit), "hipMalloc split bins");
+  HIPCHK(hipMalloc(&d_cnt, sizeof(unsigned long long) * (nsub + 1)), "hipMalloc sub-bin counts");
+  HIPCHK(hipMemcpyAsync(gh.bsub, bsub.data(), sizeof(int) * nbins, hipMemcpyHostToDevice, s), "sub-bin index copy");
+  HIPCHK(hipMemcpyAsync(d_split, split.data(), sizeof(int) * nsplit, hipMemcpyHostToDevice, s), "split bins copy");
+  g.bsub = gh.bsub;
+  const unsigned nblk = (unsigned)std::min<long long>(nsplit, 65536);
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nsub + 1)), dim3(256), 0, s, d_cnt, nsub + 1);
+  hipLaunchKernelGGL(k_subbins<0>, dim3(nblk), dim3(256), 0, s, g, (const int*)d_split, nsplit, d_cnt,
+                     (const long long*)nullptr, (int*)nullptr);
+  std::vector<unsigned long long> scnt(nsub);
+  HIPCHK(hipMemcpyAsync(scnt.data(), d_cnt, sizeof(unsigned long long) * nsub, hipMemcpyDeviceToHost, s),
+         "sub-bin count copy");
+  HIPCHK(hipStreamSynchronize(s), "sub-bin count sync");
+  std::vector<long long> start(nsub + 1);
+  start[0] = 0;
+  for (long long k = 0; k < nsub; ++k) start[k + 1] = start[k] + (long long)scnt[k];
+  const long long entries = start[nsub];
+  if (entries >= (1LL << 31)) {
+    (void)hipFree(d_cnt);
+    (void)hipFree(d_split);
+    return fail(ctx, OV_EDIMS, "sub-bin lists too large (%lld entries)", entries);
+  }
+  HIPCHK(hipMalloc(&gh.sstart, sizeof(long long) * (nsub + 1)), "hipMalloc sub-bin start");
+  HIPCHK(hipMalloc(&gh.scells, sizeof(int) * std::max(1LL, entries)), "hipMalloc sub-bin cells");
+  HIPCHK(hipMemcpyAsync(gh.sstart, start.data(), sizeof(long long) * (nsub + 1), hipMemcpyHostToDevice, s),
+         "sub-bin start copy");
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nsub + 1)), dim3(256), 0, s, d_cnt, nsub + 1);
+  hipLaunchKernelGGL(k_subbins<1>, dim3(nblk), dim3(256), 0, s, g, (const int*)d_split, nsplit, d_cnt,
+                     (const long long*)gh.sstart, gh.scells);
+  hipLaunchKernelGGL(k_bin_sort, dim3(blocks_for(nsub)), dim3(256), 0, s, (const long long*)gh.sstart, gh.scells,
+                     nsub);
+  HIPCHK(hipGetLastError(), "sub-bin kernels");
+  HIPCHK(hipStreamSynchronize(s), "sub-bin sync");
+  (void)hipFree(d_cnt);
+  (void)hipFree(d_split);
+  g.sstart = gh.sstart;
+  g.scells = gh.scells;
   return OV_OK;
 }
 
@@ -407,6 +501,9 @@ int ov_ctx_destroy(ov_ctx* ctx) {
     (void)hipFree(g.bstart);
     (void)hipFree(g.bcells);
     (void)hipFree(g.brep);
+    (void)hipFree(g.bsub);
+    (void)hipFree(g.sstart);
+    (void)hipFree(g.scells);
   }
   (void)hipFree(ctx->d_grids);
   (void)hipFree(ctx->d_status);

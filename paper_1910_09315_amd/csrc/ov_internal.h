@@ -62,8 +62,13 @@ struct GridDev {
   int nb[3];
   int pad_;
   const long long* bstart;  // [nbins + 1]
-  const int* bcells;        // candidate donor cells, bin after bin
-  const int* brep;          // lowest cell of each bin, -1 if empty
+  const int* bcells;        // candidate donor cells, bin after bin (ascending in each bin)
+  const int* brep;          // walk seed of each bin (listed cell nearest its centre), -1 if empty
+  // second level: a bin listing more than kSplitList cells is split into
+  // kSubBins^3 sub-bins with (ascending) lists of their own
+  const int* bsub;          // per bin: its first sub-bin, or -1 (null: no bin is split)
+  const long long* sstart;  // [nsub + 1]
+  const int* scells;
 };
 
 struct GridHost {
@@ -76,6 +81,9 @@ struct GridHost {
   long long* bstart = nullptr;
   int* bcells = nullptr;
   int* brep = nullptr;
+  int* bsub = nullptr;
+  long long* sstart = nullptr;
+  int* scells = nullptr;
 };
 
 }  // namespace ov
@@ -173,6 +181,7 @@ hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, c
 hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st);
 // setup (control cells, shadows)
 int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);
+int build_subbins(ov_ctx* ctx, GridHost& g, const std::vector<unsigned long long>& cnt, hipStream_t s);
 int build_shadows(ov_ctx* ctx, GridHost& g, hipStream_t s);
 int build_gather_layout(ov_ctx* ctx, GridHost& g, hipStream_t s);
 
@@ -332,6 +341,38 @@ __device__ __forceinline__ int bin_axis(const GridDev& g, int d, double v) {
   if (!(t >= 0.0)) return 0;  // also NaN
   if (t >= (double)g.nb[d]) return g.nb[d] - 1;
   return (int)t;
+}
+
+// Sub-bins of a split control cell: kSubBins per axis.
+constexpr int kSubBins = 4;
+constexpr long long kSplitList = 128;
+
+// Sub-bin coordinate along axis d of v inside bin `bin` of that axis. The
+// same product as bin_axis, scaled by kSubBins (exact), so a point inside a
+// cell's box falls in a sub-bin the cell was listed in.
+__device__ __forceinline__ int sub_axis(const GridDev& g, int d, double v, int bin) {
+  const double t = floor((v - g.blo[d]) * g.binv[d] * (double)kSubBins) - (double)kSubBins * bin;
+  if (!(t >= 0.0)) return 0;  // also NaN
+  return t >= (double)(kSubBins - 1) ? kSubBins - 1 : (int)t;
+}
+
+// The candidate donor cells of the control cell (or sub-bin) holding xi:
+// entries [e0, e1) of the returned array, ascending.
+__device__ __forceinline__ const int* control_list(const GridDev& G, const double xi[3], long long& e0,
+                                                   long long& e1) {
+  const int bx = bin_axis(G, 0, xi[0]), by = bin_axis(G, 1, xi[1]), bz = bin_axis(G, 2, xi[2]);
+  const long long b = bx + (long long)G.nb[0] * (by + (long long)G.nb[1] * bz);
+  const int sb = G.bsub ? gp(G.bsub)[b] : -1;
+  if (sb < 0) {
+    e0 = gp(G.bstart)[b];
+    e1 = gp(G.bstart)[b + 1];
+    return G.bcells;
+  }
+  const long long k = sb + sub_axis(G, 0, xi[0], bx) +
+                      kSubBins * (sub_axis(G, 1, xi[1], by) + kSubBins * sub_axis(G, 2, xi[2], bz));
+  e0 = gp(G.sstart)[k];
+  e1 = gp(G.sstart)[k + 1];
+  return G.scells;
 }
 
 }  // namespace ov

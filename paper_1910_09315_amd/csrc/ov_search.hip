@@ -568,10 +568,12 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Block-cooperative brute-force scan of the control cell holding xi: its
-// sorted list is taken blockDim.x candidates per round, one per thread; the
-// first round holding a valid containing cell ends the scan with its lowest
-// such cell (lists ascend, so that is the lowest list position that hits).
+// Block-cooperative brute-force scan of the control cell (or sub-bin)
+// holding xi: its sorted list is taken blockDim.x candidates per round, one
+// per thread; the first round holding a valid containing cell ends the scan
+// with its lowest such cell (lists ascend, so that is the lowest list
+// position that hits). Every cell containing xi is on that list, so this is
+// the lowest valid containing cell of the grid.
 // The next round's cell ids are loaded while the current round is tested.
 // Every thread of the block calls it with the same G and xi.
 struct ScanLds {
@@ -585,13 +587,13 @@ struct ScanLds {
 __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3],
                                        ScanLds& S, int* cands = nullptr, int* iters = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long long b = bin_of(G, xi);
-  const long long e0 = gp(G.bstart)[b], e1 = gp(G.bstart)[b + 1];
-  int next = e0 + tid < e1 ? gp(G.bcells)[e0 + tid] : -1;
+  long long e0, e1;
+  gmem<int>* list = gp(control_list(G, xi, e0, e1));
+  int next = e0 + tid < e1 ? list[e0 + tid] : -1;
   for (long long base = e0; base < e1; base += blockDim.x) {
     const long long e = base + tid;
     const int cell = next;
-    next = e + blockDim.x < e1 ? gp(G.bcells)[e + blockDim.x] : -1;
+    next = e + blockDim.x < e1 ? list[e + blockDim.x] : -1;
     bool hit = false;
     double s[3] = {0.0, 0.0, 0.0};
     if (e < e1) {

@@ -91,6 +91,13 @@ def test_c2_mixed_matches_oracle_sampled_steps(c1):
     print("C2 value errors", [s["value_err"] for s in stats])
 
 
+def test_c1_every_query_by_fallback_scan_matches_oracle(c1):
+    """max_walk = 1 without warm start sends (nearly) every C1 query to the
+    block-cooperative scan of its control cell, through the sub-bin lists of
+    the shell's crowded polar control cells."""
+    _run_and_compare(c1, [0, 1], options={"max_walk": 1, "warm": 0})
+
+
 def test_warm_equals_cold_and_runs_are_deterministic():
     w = W.c1_small(steps=4)
     a = _assembly(w)
