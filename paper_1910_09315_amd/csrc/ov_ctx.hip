@@ -510,6 +510,7 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_stats);
   (void)hipFree(ctx->d_warm_cell);
   (void)hipFree(ctx->d_warm_grid);
+  (void)hipFree(ctx->d_warm_tag);
   (void)hipFree(ctx->d_tile_sphere);
   (void)hipFree(ctx->d_tile_info);
   (void)hipFree(ctx->d_base_flags);
@@ -625,6 +626,8 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
   HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
   hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
+  HIPCHK(hipMalloc(&ctx->d_warm_tag, total), "hipMalloc warm tags");
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_tag, total, (uint8_t)0);
   HIPCHK(hipMalloc(&ctx->d_tile_sphere, sizeof(double4) * kSubPerTile * std::max(1LL, ctx->total_tiles)),
          "hipMalloc sub-tile spheres");
   for (auto& g : ctx->grids) {

@@ -101,6 +101,7 @@ struct ov_ctx {
   unsigned long long* d_stats = nullptr;  // OV_STAT_* counters (accumulate until ov_stats_fetch)
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
+  uint8_t* d_warm_tag = nullptr;  // per node: low byte of the stamp of the step that wrote its warm entry
   double4* d_tile_sphere = nullptr;  // per sub-tile: body-frame bounding sphere (centre, radius; -inf if empty)
   int4* d_tile_info = nullptr;       // per node tile: (grid, ti, tj, tk)
   // The flags every step starts from (field everywhere, fringe on the fixed
@@ -166,18 +167,19 @@ hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_g
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                                const int32_t* q_node, const void* qx, const long long* d_count,
                                long long capacity, int32_t* donor_grid, int32_t* donor_cell, void* s,
-                               int32_t* status, hipStream_t st);
+                               int32_t* status, hipStream_t st, int slot = 0);
 hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* donor_cell, const void* s,
                          const long long* d_count, long long capacity, const void* fields, void* out,
                          hipStream_t st);
 // The back half of a step (transform, donor search, interpolation when
 // fields is non-null) for the step executors: one kernel when back_fused is
 // set, else the three launchers above. count_out (nullable) receives the
-// step's query count.
+// step's query count; slot is the step's front-half scratch slot (its stamp
+// dates the warm-start entries).
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
-                       void* out, long long* count_out, hipStream_t st);
+                       void* out, long long* count_out, hipStream_t st, int slot = 0);
 hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st);
 // setup (control cells, shadows)
 int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);

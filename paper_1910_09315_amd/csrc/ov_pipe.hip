@@ -85,7 +85,7 @@ static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses
   }
   return launch_back(ctx, poses, b.flags, b.q_grid, b.q_node, b.qx, (const long long*)b.d_count, b.capacity,
                      b.donor_grid, b.donor_cell, b.s, b.status, p->fields, p->fields ? b.out : nullptr, count_out,
-                     s);
+                     s, slot);
 }
 
 static void destroy_graphs(ov_pipe* p) {

@@ -433,18 +433,39 @@ __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp,
   return r;
 }
 
+// Warm-start history: per node, the donor (grid, cell) of its last query
+// and the low byte of the stamp of the step that wrote it. A node that was
+// not a query in the last steps (one that just entered the buffer layer, say)
+// would start its walk from a donor long out of date; its entry is then
+// ignored and the walk starts from the control cell's seed.
+struct Warm {
+  int32_t* cell;
+  uint8_t* grid;
+  uint8_t* tag;
+  const unsigned int* stamp;  // the running step's stamp
+  int use;
+};
+constexpr int kWarmMaxAge = 2;  // steps
+
+__device__ __forceinline__ int warm_grid_of(const Warm& w, long long key, uint8_t now) {
+  if (!w.use) return 255;
+  const uint8_t age = (uint8_t)(now - w.tag[key]);
+  return age <= kWarmMaxAge ? (int)w.grid[key] : 255;
+}
+
 template <typename T>
 __device__ __forceinline__ void write_result(long long q, long long cap, long long key, int grid, int cell, int st,
                                              const T s[3], int32_t* donor_grid, int32_t* donor_cell, T* s_out,
-                                             int32_t* status, int32_t* warm_cell, uint8_t* warm_grid) {
+                                             int32_t* status, const Warm& warm, uint8_t now) {
   donor_grid[q] = grid;
   donor_cell[q] = cell;
   status[q] = st;  // bits 8-15: cells the walk visited (diagnostic)
   s_out[q] = s[0];
   s_out[cap + q] = s[1];
   s_out[2 * cap + q] = s[2];
-  warm_grid[key] = grid < 0 ? (uint8_t)255 : (uint8_t)grid;
-  warm_cell[key] = cell;
+  warm.grid[key] = grid < 0 ? (uint8_t)255 : (uint8_t)grid;
+  warm.cell[key] = cell;
+  warm.tag[key] = now;
 }
 
 // Markers left in donor_grid between the passes of one search call; status
@@ -465,10 +486,11 @@ __global__ void __launch_bounds__(256)
                  const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
                  const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
                  long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
-                 T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
-                 uint8_t* __restrict__ warm_grid, int use_warm, int max_walk, int32_t* __restrict__ dev_status) {
+                 T* __restrict__ s_out, int32_t* __restrict__ status, Warm warm, int max_walk,
+                 int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const uint8_t now = (uint8_t)*warm.stamp;
   __syncthreads();
   const long long n = min(*d_count, cap);
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
@@ -480,7 +502,7 @@ __global__ void __launch_bounds__(256)
     if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
-      const int wg = use_warm ? (int)warm_grid[Q.key] : 255;
+      const int wg = warm_grid_of(warm, Q.key, now);
       for (int t = -2; t < ngrids; ++t) {
         const int B = candidate_at(t, Q.A, Q.first);
         if (B < 0) continue;
@@ -491,7 +513,7 @@ __global__ void __launch_bounds__(256)
         const int rep = gp(G.brep)[bin_of(G, xi)];
         int seed = -1;
         if (wg == B) {
-          int wc = warm_cell[Q.key];
+          int wc = warm.cell[Q.key];
           if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
         }
         if (seed < 0 && rep < 0) continue;  // no cell reaches this control cell
@@ -524,7 +546,7 @@ __global__ void __launch_bounds__(256)
       status[q] = defer_status(defer_t, visited);
     } else {
       write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
-                      donor_cell, s_out, status, warm_cell, warm_grid);
+                      donor_cell, s_out, status, warm, now);
     }
   }
 }
@@ -537,10 +559,11 @@ __global__ void __launch_bounds__(256)
                 const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
                 const int32_t* __restrict__ q_node, const float* __restrict__ qx, const long long* __restrict__ d_count,
                 long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
-                float* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
-                uint8_t* __restrict__ warm_grid, int max_walk, int32_t* __restrict__ dev_status) {
+                float* __restrict__ s_out, int32_t* __restrict__ status, Warm warm, int max_walk,
+                int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const uint8_t now = (uint8_t)*warm.stamp;
   __syncthreads();
   const long long n = min(*d_count, cap);
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
@@ -560,7 +583,7 @@ __global__ void __launch_bounds__(256)
     if (r == kFound) {
       const float sf[3] = {(float)s64[0], (float)s64[1], (float)s64[2]};
       write_result<float>(q, cap, Q.key, B, cell, OV_Q_FOUND | OV_Q_FP64_FIXED | (min(visited, 255) << 8), sf,
-                          donor_grid, donor_cell, s_out, status, warm_cell, warm_grid);
+                          donor_grid, donor_cell, s_out, status, warm, now);
     } else {
       donor_grid[q] = kDeferScan;
       status[q] = defer_status(t, visited);
@@ -652,13 +675,14 @@ __global__ void __launch_bounds__(256)
                  const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
                  const int32_t* __restrict__ q_node, const T* __restrict__ qx, const long long* __restrict__ d_count,
                  long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
-                 T* __restrict__ s_out, int32_t* __restrict__ status, int32_t* __restrict__ warm_cell,
-                 uint8_t* __restrict__ warm_grid, int max_walk, int32_t* __restrict__ dev_status) {
+                 T* __restrict__ s_out, int32_t* __restrict__ status, Warm warm, int max_walk,
+                 int32_t* __restrict__ dev_status) {
   __shared__ double sp[kMaxGrids * 12];
   __shared__ int list_q[256], list_st[256];
   __shared__ int nlist;
   __shared__ ScanLds S;
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const uint8_t now = (uint8_t)*warm.stamp;
   const long long n = min(*d_count, cap);
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
     if (threadIdx.x == 0) nlist = 0;
@@ -719,7 +743,7 @@ __global__ void __launch_bounds__(256)
       if (threadIdx.x == 0) {
         if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
         write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
-                        donor_cell, s_out, status, warm_cell, warm_grid);
+                        donor_cell, s_out, status, warm, now);
       }
     }
     __syncthreads();  // the list is rebuilt for the next range
@@ -737,12 +761,12 @@ __global__ void __launch_bounds__(256)
 // the same bit for bit.
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS)
-    k_back(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+    k_back(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid, const int32_t* __restrict__ q_node,
            T* __restrict__ qx, const long long* __restrict__ d_count, long long cap,
            int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
-           int32_t* __restrict__ status, int32_t* __restrict__ warm_cell, uint8_t* __restrict__ warm_grid,
-           int use_warm, int max_walk, int32_t* __restrict__ dev_status, const T* __restrict__ fields,
+           int32_t* __restrict__ status, Warm warm, int max_walk, int32_t* __restrict__ dev_status,
+           const T* __restrict__ fields,
            long long total_nodes, int interleaved, T* __restrict__ out, long long* __restrict__ count_out,
            unsigned long long* __restrict__ stats) {
   __shared__ double sp[kMaxGrids * 12];
@@ -750,7 +774,15 @@ __global__ void __launch_bounds__(BS)
   __shared__ int nlist;
   __shared__ ScanLds S;
   __shared__ unsigned long long work[3];  // cells walked, Newton iterations, scan candidates
+  // the grid table, staged in LDS (dynamic: ngrids records): its fields are
+  // read at every candidate grid and walk
+  extern __shared__ unsigned long long grid_lds[];
+  static_assert(sizeof(GridDev) % 8 == 0, "grid records are staged in 8-byte words");
+  for (int i = threadIdx.x; i < ngrids * (int)(sizeof(GridDev) / 8); i += blockDim.x)
+    grid_lds[i] = ((const unsigned long long*)grids_g)[i];
+  const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const uint8_t now = (uint8_t)*warm.stamp;
   if (threadIdx.x < 3) work[threadIdx.x] = 0;
   const long long n = min(*d_count, cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -783,7 +815,7 @@ __global__ void __launch_bounds__(BS)
       if (!Q.finite) {
         atomicOr(dev_status, OV_DEV_NONFINITE);
       } else {
-        const int wg = use_warm ? (int)warm_grid[Q.key] : 255;
+        const int wg = warm_grid_of(warm, Q.key, now);
         for (int t = -2; t < ngrids; ++t) {
           const int B = candidate_at(t, Q.A, Q.first);
           if (B < 0) continue;
@@ -793,7 +825,7 @@ __global__ void __launch_bounds__(BS)
           const int rep = gp(G.brep)[bin_of(G, xi)];
           int seed = -1;
           if (wg == B) {
-            int wc = warm_cell[Q.key];
+            int wc = warm.cell[Q.key];
             if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
           }
           if (seed < 0 && rep < 0) continue;
@@ -909,7 +941,7 @@ __global__ void __launch_bounds__(BS)
       my_cells += visited;
       if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
       write_result<T>(q, cap, key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
-                      donor_cell, s_out, status, warm_cell, warm_grid);
+                      donor_cell, s_out, status, warm, now);
       if (fields && res_grid >= 0) {
         T v[4];
         interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, interleaved != 0, v);
@@ -928,26 +960,32 @@ __global__ void __launch_bounds__(BS)
     atomicAdd(&stats[OV_STAT_SEARCH_CELLS + threadIdx.x], work[threadIdx.x]);
 }
 
+static Warm warm_of(ov_ctx* ctx, int slot) {
+  return Warm{ctx->d_warm_cell, ctx->d_warm_grid, ctx->d_warm_tag, ctx->d_stamp + 1 + slot, ctx->warm};
+}
+
 template <typename T>
 static void launch_search_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                             const int32_t* q_node, const T* qx, const long long* d_count, long long capacity,
-                            int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, hipStream_t st) {
+                            int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, hipStream_t st,
+                            int slot) {
+  const Warm warm = warm_of(ctx, slot);
   const int ng = (int)ctx->grids.size();
   const int block = ctx->search_block;
   long long grid = grid_size_for(ctx, capacity, block);
   hipLaunchKernelGGL(k_donor_walk<T>, dim3((unsigned)grid), dim3(block), 0, st, ctx->d_grids, ng, poses, flags,
-                     q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, ctx->d_warm_cell,
-                     ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status);
+                     q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s, status, warm, ctx->max_walk,
+                     ctx->d_status);
   // the sweeps: one lane (FP64 correction) or one block per 256 queries (scan)
   const long long sweep_cap = (long long)ctx->num_cus * 8;
   if (sizeof(T) == 4)
     hipLaunchKernelGGL(k_donor_fix, dim3((unsigned)std::max(1LL, std::min(sweep_cap, (capacity + 255) / 256))),
                        dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid, q_node, (const float*)qx, d_count,
-                       capacity, donor_grid, donor_cell, (float*)s, status, ctx->d_warm_cell, ctx->d_warm_grid,
+                       capacity, donor_grid, donor_cell, (float*)s, status, warm,
                        ctx->max_walk, ctx->d_status);
   hipLaunchKernelGGL(k_donor_scan<T>, dim3((unsigned)std::max(1LL, std::min(sweep_cap, (capacity + 255) / 256))),
                      dim3(256), 0, st, ctx->d_grids, ng, poses, flags, q_grid, q_node, qx, d_count, capacity,
-                     donor_grid, donor_cell, s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->max_walk,
+                     donor_grid, donor_cell, s, status, warm, ctx->max_walk,
                      ctx->d_status);
 }
 
@@ -955,29 +993,32 @@ template <typename T>
 static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                           const int32_t* q_node, T* qx, const long long* d_count, long long capacity,
                           int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, const T* fields,
-                          T* out, long long* count_out, hipStream_t st) {
+                          T* out, long long* count_out, hipStream_t st, int slot) {
+  const Warm warm = warm_of(ctx, slot);
   const int bs = ctx->back_block;
   const long long grid =
       std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + bs - 1) / bs));
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
-      s, status, ctx->d_warm_cell, ctx->d_warm_grid, ctx->warm, ctx->max_walk, ctx->d_status, fields,               \
+      s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
       ctx->node_off.back(), ctx->field_layout, out, count_out, ctx->d_stats
-  if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), 0, st, OV_BACK_ARGS);
-  else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), 0, st, OV_BACK_ARGS);
-  else hipLaunchKernelGGL((k_back<T, 256>), dim3((unsigned)grid), dim3(256), 0, st, OV_BACK_ARGS);
+  const size_t lds = sizeof(GridDev) * ctx->grids.size();
+  if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), lds, st, OV_BACK_ARGS);
+  else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), lds, st, OV_BACK_ARGS);
+  else hipLaunchKernelGGL((k_back<T, 256>), dim3((unsigned)grid), dim3(256), lds, st, OV_BACK_ARGS);
 #undef OV_BACK_ARGS
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                                const int32_t* q_node, const void* qx, const long long* d_count, long long capacity,
-                               int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, hipStream_t st) {
+                               int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, hipStream_t st,
+                               int slot) {
   if (ctx->precision == OV_MIXED)
     launch_search_t<float>(ctx, poses, flags, q_grid, q_node, (const float*)qx, d_count, capacity, donor_grid,
-                           donor_cell, (float*)s, status, st);
+                           donor_cell, (float*)s, status, st, slot);
   else
     launch_search_t<double>(ctx, poses, flags, q_grid, q_node, (const double*)qx, d_count, capacity, donor_grid,
-                            donor_cell, (double*)s, status, st);
+                            donor_cell, (double*)s, status, st, slot);
   return hipGetLastError();
 }
 
@@ -991,14 +1032,15 @@ hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st)
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
-                       void* out, long long* count_out, hipStream_t st) {
+                       void* out, long long* count_out, hipStream_t st, int slot) {
   if (capacity > 0 && ctx->back_fused) {
     if (ctx->precision == OV_MIXED)
       launch_back_t<float>(ctx, poses, flags, q_grid, q_node, (float*)qx, d_count, capacity, donor_grid, donor_cell,
-                           (float*)s, status, (const float*)fields, (float*)out, count_out, st);
+                           (float*)s, status, (const float*)fields, (float*)out, count_out, st, slot);
     else
       launch_back_t<double>(ctx, poses, flags, q_grid, q_node, (double*)qx, d_count, capacity, donor_grid,
-                            donor_cell, (double*)s, status, (const double*)fields, (double*)out, count_out, st);
+                            donor_cell, (double*)s, status, (const double*)fields, (double*)out, count_out, st,
+                            slot);
     return hipGetLastError();
   }
   hipError_t e = hipSuccess;
@@ -1006,7 +1048,7 @@ hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, c
     e = launch_transform(ctx, poses, q_grid, q_node, d_count, capacity, qx, st);
     if (e == hipSuccess)
       e = launch_donor_search(ctx, poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, s,
-                              status, st);
+                              status, st, slot);
     if (e == hipSuccess && fields)
       e = launch_interp(ctx, donor_grid, donor_cell, s, d_count, capacity, fields, out, st);
   }
@@ -1029,6 +1071,6 @@ extern "C" int overset_donor_search(ov_ctx* ctx, const double* poses, const uint
   if (!poses || !flags || !q_grid || !q_node || !qx || !d_count || !donor_grid || !donor_cell || !s || !status)
     return fail(ctx, OV_EINVAL, "overset_donor_search: null pointer");
   hipError_t e = launch_donor_search(ctx, poses, flags, q_grid, q_node, qx, (const long long*)d_count, capacity,
-                                     donor_grid, donor_cell, s, status, (hipStream_t)stream);
+                                     donor_grid, donor_cell, s, status, (hipStream_t)stream, 0);
   return e == hipSuccess ? OV_OK : hip_fail(ctx, e, "overset_donor_search");
 }
