@@ -38,6 +38,7 @@ constexpr int kSuperChunk = 64;
 // one slot; up to kSlots steps can be between the two at once.
 constexpr int kSlots = 3;
 constexpr int kSuperSlots = 8;  // count slots per superchunk (spreads the atomics)
+constexpr long long kFusedScanMax = 4096;  // superchunks whose offsets one block forms in LDS
 
 // One grid as the kernels see it.
 struct GridDev {
@@ -128,7 +129,7 @@ struct ov_ctx {
   int32_t* d_chunk_list_count = nullptr;      // per slot: length of this step's part
   long long n_static_chunks = 0;
   unsigned long long* d_chunk_counts = nullptr;  // per chunk: stamp << 32 | query count (listed chunks)
-  int32_t* d_super_counts = nullptr;             // per 64 chunks, kSuperSlots partial counts (zeroed by the scan)
+  int32_t* d_super_counts = nullptr;             // per slot, per 64 chunks, kSuperSlots partial counts
   long long* d_super_offsets = nullptr;          // per 64 chunks: first query position; last entry the total
   long long nchunks = 0, nsuper = 0;
   // options
@@ -160,8 +161,11 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0);
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0);
 int build_static_chunks(ov_ctx* ctx, hipStream_t s);
+// fused: the write kernel forms the superchunk offsets itself (no scan
+// kernel); only for callers whose next hole cut on this slot precedes the
+// next compaction (the step executors).
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
-                          long long capacity, long long* d_count, hipStream_t s, int slot = 0);
+                          long long capacity, long long* d_count, hipStream_t s, int slot = 0, bool fused = false);
 hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_grid, const int32_t* q_node,
                             const long long* d_count, long long capacity, void* qx, hipStream_t s);
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

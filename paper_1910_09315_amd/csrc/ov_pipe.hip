@@ -80,7 +80,7 @@ static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses
   if (stage == 1) {
     hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot);
     if (e == hipSuccess)
-      e = launch_compact(ctx, b.flags, b.q_grid, b.q_node, b.capacity, (long long*)b.d_count, s, slot);
+      e = launch_compact(ctx, b.flags, b.q_grid, b.q_node, b.capacity, (long long*)b.d_count, s, slot, true);
     return e;
   }
   return launch_back(ctx, poses, b.flags, b.q_grid, b.q_node, b.qx, (const long long*)b.d_count, b.capacity,

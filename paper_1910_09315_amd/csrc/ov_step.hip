@@ -346,8 +346,12 @@ __device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigne
 }
 
 __global__ void k_begin_step(unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
-                             int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count) {
-  k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+                             int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count,
+                             int32_t* __restrict__ super_counts, long long n_super_counts) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
+       i += (long long)gridDim.x * blockDim.x)
+    super_counts[i] = 0;
 }
 
 // Tile index along one axis holding the node `which` positions from tile t:
@@ -494,8 +498,14 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, 
                                                   long long fill_words, unsigned int* __restrict__ counter,
                                                   unsigned int* __restrict__ d_stamp,
                                                   int32_t* __restrict__ near_count,
-                                                  int32_t* __restrict__ chunk_list_count) {
+                                                  int32_t* __restrict__ chunk_list_count,
+                                                  int32_t* __restrict__ super_counts, long long n_super_counts) {
   if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+  // the slot's superchunk counts start from zero (the last reader of this
+  // slot's counts, the previous compaction using it, is done)
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
+       i += (long long)gridDim.x * blockDim.x)
+    super_counts[i] = 0;
   flag_fill_body(flags, base, fill_ranges, nranges, fill_words, blockIdx.x, gridDim.x);
 }
 
@@ -755,11 +765,13 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   int32_t* nl = ctx->d_near_list + slot * std::max(1LL, nt);
   int32_t* nc = ctx->d_near_count + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
+  const long long nsc = kSuperSlots * ctx->nsuper;
+  int32_t* sc = ctx->d_super_counts + (long long)slot * nsc;
   if (ctx->cull) {
     const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
                                                 (long long)ctx->num_cus * 32));
     hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
-                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc);
+                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc);
     const long long nsub = nt * kSubPerTile;
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
@@ -777,7 +789,8 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
 #undef OV_SUB_ARGS
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, counter, st, nc, clc);
+  hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
+                     counter, st, nc, clc, sc, nsc);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st);
   else launch_holecut_t<double>(ctx, poses, flags, s, st);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
@@ -832,59 +845,62 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
     const TileGeo G = TG[info.x];
     const long long noff = noffs[info.x];
     const int i0 = info.y * kTileI, j0 = info.z * kTileJ, k0 = info.w * kTileK;
-    // chunks holding this tile's nodes: one tile row (j, k) per thread
-    if (threadIdx.x < kTileJ * kTileK) {
-      const int j = j0 + (threadIdx.x & 7), k = k0 + (threadIdx.x >> 3);
-      if (j < G.nj && k < G.nk) {
-        const long long r = noff + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-        const long long c0 = (r + i0) / kCompactChunk, c1 = (r + min(G.ni, i0 + kTileI) - 1) / kCompactChunk;
-        for (long long ch = c0; ch <= c1; ++ch)
-          if (!chunk_static[ch] && atomicExch(&chunk_stamp[ch], stamp) != stamp)
-            chunk_list[n_static + atomicAdd(chunk_list_count, 1)] = (int32_t)ch;
+    // chunks holding this tile's nodes (one tile row (j, k) per thread of
+    // the first wavefront); issued after the staging loads below, so that
+    // the atomics' round trips overlap the loads'
+    auto mark_chunks = [&]() {
+      if (threadIdx.x < kTileJ * kTileK) {
+        const int j = j0 + (threadIdx.x & 7), k = k0 + (threadIdx.x >> 3);
+        if (j < G.nj && k < G.nk) {
+          const long long r = noff + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+          const long long c0 = (r + i0) / kCompactChunk, c1 = (r + min(G.ni, i0 + kTileI) - 1) / kCompactChunk;
+          for (long long ch = c0; ch <= c1; ++ch)
+            if (!chunk_static[ch] && atomicExch(&chunk_stamp[ch], stamp) != stamp)
+              chunk_list[n_static + atomicAdd(chunk_list_count, 1)] = (int32_t)ch;
+        }
       }
+    };
+    if (NF == 0) {
+      mark_chunks();
+      continue;
     }
-    if (NF == 0) continue;
     uint8_t* fl = flags + noff;
-    bool any_hole = false;
     // stage hole causes with halo: 16 threads per row load the 64 interior
-    // bytes as words where the row is aligned and in range, the halo bytewise;
-    // fixed trip counts so that all loads are issued before the LDS stores
+    // bytes as words where the row is aligned and in range, the halo bytewise
+    // (out-of-range bytes read as 0, a field node). Fixed trip counts: all
+    // loads are issued first, then the chunk marking, then the conversions
+    // and LDS stores.
+    constexpr int NIT = (NROW + 255) / 256, NHIT = (NHALO + 255) / 256;
+    uint32_t raw[NIT];
+    uint8_t hraw[NHIT];
 #pragma unroll
-    for (int it = 0; it < (NROW + 255) / 256; ++it) {
+    for (int it = 0; it < NIT; ++it) {
+      raw[it] = 0u;
       const int e = threadIdx.x + it * 256;
       if (e >= NROW) continue;  // only the last round is partial
       const int row = e >> 4, part = e & 15;
       const int y = row % EJ, z = row / EJ;
       const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
       const int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
-      uint8_t v[4] = {255, 255, 255, 255};
       if (j >= 0 && k >= 0) {
         const uint8_t* rowp = fl + (long long)G.ni * ((long long)j + (long long)G.nj * k);
         const int i = i0 + part * 4;
         if (i + 4 <= G.ni && (((uintptr_t)(rowp + i)) & 3) == 0) {
-          uint32_t w4 = *reinterpret_cast<const uint32_t*>(rowp + i);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            uint8_t f = (uint8_t)(w4 >> (8 * q));
-            v[q] = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
-          }
+          raw[it] = *reinterpret_cast<const uint32_t*>(rowp + i);
         } else {
+          uint32_t w = 0u;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             int ii = wrap_or_out(i + q, G.ni, G.per & 1);
-            if (ii >= 0) {
-              uint8_t f = rowp[ii];
-              if ((f & 3) == kHole) v[q] = f >> 2;
-            }
+            if (ii >= 0) w |= (uint32_t)rowp[ii] << (8 * q);
           }
+          raw[it] = w;
         }
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[z][y][NF + part * 4 + q] = v[q];
-      any_hole |= (v[0] & v[1] & v[2] & v[3]) != 255;
     }
 #pragma unroll
-    for (int it = 0; it < (NHALO + 255) / 256; ++it) {
+    for (int it = 0; it < NHIT; ++it) {
+      hraw[it] = 0;
       const int e = threadIdx.x + it * 256;
       if (e >= NHALO) continue;  // only the last round is partial
       const int h = e % (2 * H), row = e / (2 * H);  // (H = NF here: NF = 0 never gets this far)
@@ -893,11 +909,35 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
       const int i = wrap_or_out(i0 - NF + x, G.ni, G.per & 1);
       const int j = wrap_or_out(j0 - NF + y, G.nj, G.per & 2);
       const int k = wrap_or_out(k0 - NF + z, G.nk, G.per & 4);
-      uint8_t v = 255;
-      if (i >= 0 && j >= 0 && k >= 0) {
-        uint8_t f = fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)];
-        if ((f & 3) == kHole) v = f >> 2;
+      if (i >= 0 && j >= 0 && k >= 0)
+        hraw[it] = fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)];
+    }
+    mark_chunks();
+    bool any_hole = false;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= NROW) continue;
+      const int row = e >> 4, part = e & 15;
+      const int y = row % EJ, z = row / EJ;
+      uint8_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint8_t f = (uint8_t)(raw[it] >> (8 * q));
+        v[q] = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
+        a[z][y][NF + part * 4 + q] = v[q];
       }
+      any_hole |= (v[0] & v[1] & v[2] & v[3]) != 255;
+    }
+#pragma unroll
+    for (int it = 0; it < NHIT; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= NHALO) continue;
+      const int h = e % (2 * H), row = e / (2 * H);
+      const int y = row % EJ, z = row / EJ;
+      const int x = h < NF ? h : kTileI + h;
+      const uint8_t f = hraw[it];
+      const uint8_t v = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
       a[z][y][x] = v;
       any_hole |= v != 255;
     }
@@ -942,7 +982,8 @@ hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int
   const unsigned int* st = ctx->d_stamp + 1 + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
   // persistent blocks over the near list (its length is on the device)
-  long long g = std::max(1LL, std::min<long long>(ctx->total_tiles, (long long)ctx->num_cus * 4));
+  long long g = std::max(1LL, std::min<long long>(ctx->total_tiles,
+                                                    (long long)ctx->num_cus * (ctx->persist > 0 ? ctx->persist : 4)));
 #define OV_FRINGE_ARGS                                                                                            \
   ctx->d_grids, ng, flags, ctx->d_tile_info, nl, nc, st, ctx->d_chunk_static, ctx->d_chunk_stamp, ctx->d_chunk_list, \
       clc, ctx->n_static_chunks
@@ -1067,11 +1108,49 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int32_t* __restrict__ sup
   super_scan(super_counts, nsuper, offsets, d_count, capacity, status);
 }
 
+// The superchunk offsets computed by one block into LDS: exclusive prefix
+// sums of the superchunk counts (each thread a contiguous run of
+// superchunks), soff[nsuper] = the total. The counts are left as they are.
+__device__ __forceinline__ void block_super_prefix(const int32_t* __restrict__ super_counts, long long nsuper,
+                                                   long long* soff) {
+  __shared__ long long wt[kCompactThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long per = (nsuper + blockDim.x - 1) / blockDim.x;
+  const long long b0 = min(nsuper, (long long)threadIdx.x * per), b1 = min(nsuper, b0 + per);
+  gmem<int32_t>* sc = gp(super_counts);
+  long long sum = 0;
+  for (long long i = b0; i < b1; ++i)
+    for (int q = 0; q < kSuperSlots; ++q) sum += sc[i * kSuperSlots + q];
+  long long inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wt[wave] = inc;
+  __syncthreads();
+  long long run = inc - sum;
+  for (int w = 0; w < wave; ++w) run += wt[w];
+  for (long long i = b0; i < b1; ++i) {
+    soff[i] = run;
+    for (int q = 0; q < kSuperSlots; ++q) run += sc[i * kSuperSlots + q];
+  }
+  if (threadIdx.x == blockDim.x - 1) soff[nsuper] = run;
+}
+
+// Pass (3). FUSED (the step executors): each block first forms the
+// superchunk offsets itself (block_super_prefix, in LDS), block 0 stores the
+// query count, and no scan kernel runs; the counts are zeroed by the next
+// hole cut of the same scratch slot. Otherwise the offsets come from the
+// scan kernel.
+template <bool FUSED>
 __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev* __restrict__ grids, int ngrids,
                                                                    const uint8_t* __restrict__ flags, long long total,
                                                                    const unsigned long long* __restrict__ counts,
                                                                    long long nchunks,
                                                                    const long long* __restrict__ super_offsets,
+                                                                   const int32_t* __restrict__ super_counts,
+                                                                   long long nsuper, long long* __restrict__ d_count,
+                                                                   int32_t* __restrict__ status,
                                                                    const int32_t* __restrict__ chunk_list,
                                                                    const int32_t* __restrict__ chunk_list_count,
                                                                    long long n_static,
@@ -1080,8 +1159,17 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
                                                                    int32_t* __restrict__ q_node, long long capacity) {
   __shared__ int wsum[kCompactThreads / 64];
   __shared__ long long off[kMaxGrids + 1];
+  extern __shared__ long long soff[];  // FUSED: nsuper + 1 superchunk offsets
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) off[g] = grids[g].node_off;
   if (threadIdx.x == 0) off[ngrids] = total;
+  if (FUSED) {
+    block_super_prefix(super_counts, nsuper, soff);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *d_count = soff[nsuper];
+      if (soff[nsuper] > capacity) atomicOr(status, OV_DEV_CAPACITY);
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long nl = n_static + *chunk_list_count;
@@ -1094,7 +1182,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
     const unsigned long long v = (c < ch && c < nchunks) ? counts[c] : 0ull;
     long long below = (unsigned int)(v >> 32) == stamp ? (long long)(unsigned int)v : 0;
     for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
-    const long long base = super_offsets[ch / kSuperChunk] + below;
+    const long long base = (FUSED ? soff[ch / kSuperChunk] : super_offsets[ch / kSuperChunk]) + below;
     const unsigned long long own = counts[ch];
     if ((unsigned int)own == 0u || base >= capacity) continue;  // nothing to write (same in every thread)
     long long n0 = ch * kCompactChunk + threadIdx.x * 16;
@@ -1127,20 +1215,29 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
 }
 
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node, long long capacity,
-                          long long* d_count, hipStream_t s, int slot) {
+                          long long* d_count, hipStream_t s, int slot, bool fused) {
   const long long total = ctx->node_off.back();
   const unsigned int* st = ctx->d_stamp + 1 + slot;
   const int32_t* clc = ctx->d_chunk_list_count + slot;
+  int32_t* sc = ctx->d_super_counts + (long long)slot * kSuperSlots * ctx->nsuper;
   // persistent blocks over the chunk list (its length is on the device)
   long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, ctx->d_super_counts, ctx->d_chunk_list, clc, ctx->n_static_chunks, st);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, ctx->d_super_counts, ctx->nsuper,
-                     ctx->d_super_offsets, d_count, capacity, ctx->d_status);
-  hipLaunchKernelGGL(k_compact_write, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, ctx->d_grids,
-                     (int)ctx->grids.size(), flags, total, ctx->d_chunk_counts, ctx->nchunks, ctx->d_super_offsets,
-                     ctx->d_chunk_list, clc, ctx->n_static_chunks, st, q_grid, q_node, capacity);
+                     ctx->d_chunk_counts, sc, ctx->d_chunk_list, clc, ctx->n_static_chunks, st);
+  fused = fused && ctx->nsuper <= kFusedScanMax;
+  if (!fused)
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, sc, ctx->nsuper, ctx->d_super_offsets, d_count,
+                       capacity, ctx->d_status);
+#define OV_WRITE_ARGS                                                                                                \
+  ctx->d_grids, (int)ctx->grids.size(), flags, total, ctx->d_chunk_counts, ctx->nchunks, ctx->d_super_offsets, sc,   \
+      ctx->nsuper, d_count, ctx->d_status, ctx->d_chunk_list, clc, ctx->n_static_chunks, st, q_grid, q_node, capacity
+  if (fused)
+    hipLaunchKernelGGL(k_compact_write<true>, dim3((unsigned)grid), dim3(kCompactThreads),
+                       sizeof(long long) * (ctx->nsuper + 1), s, OV_WRITE_ARGS);
+  else
+    hipLaunchKernelGGL(k_compact_write<false>, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, OV_WRITE_ARGS);
+#undef OV_WRITE_ARGS
   return hipGetLastError();
 }
 
