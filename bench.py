@@ -6,7 +6,10 @@ search and interpolation of u, v, w, p. Inputs (grids, fields, the pose
 table of every step) are resident in HBM before timing starts.
 
 Prints one JSON line. `value` = fringe points assembled and interpolated per
-second = sum of per-step query counts / wall time of the timed steps.
+second = sum of per-step query counts / wall time of the timed steps, for the
+bench workload (default C1, plain FP64). `forms` adds the same metric for the
+mixed-precision batched form (default C4, `--compare`), measured the same way
+in the same run.
 """
 from __future__ import annotations
 
@@ -96,66 +99,8 @@ def cpu_baseline(w, budget_s: float) -> dict:
                       f"control cells built beforehand; host CPU {cpu_model()}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: every step of the workload after the warm-up)")
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C1")
-    ap.add_argument("--precision", default=None, help="fp64 or mixed (default: the config's)")
-    ap.add_argument("--graph", action="store_true", help="single stream, each step replayed from a HIP graph")
-    ap.add_argument("--sequential", action="store_true", help="single stream, eager launches")
-    ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
-    ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
-    ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
-    ap.add_argument("--stages", type=int, default=None, choices=(1, 2, 3),
-                    help="native executor streams (default: the tuned choice, else 3)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="tune the executor for this workload first when no tuned entry is cached")
-    ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
-    ap.add_argument("--per-step-submit", action="store_true",
-                    help="native pipeline: one host call per step instead of one call for all timed steps")
-    ap.add_argument("--native-graphs", action="store_true",
-                    help="the native executor replays per-stream HIP graphs instead of launching kernels directly")
-    ap.add_argument("--fields", choices=("interleaved", "blocks"), default="interleaved",
-                    help="field layout in HBM: u, v, w, p interleaved per node, or four blocks")
-    ap.add_argument("--max-walk", type=int, default=0, help="walk steps before the fallback scan (0: library default)")
-    ap.add_argument("--unfused-back", action="store_true",
-                    help="native executor: transform, search and interpolation as separate kernels")
-    ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
-                    help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
-    ap.add_argument("--time-every", type=int, default=16,
-                    help="native executor: time the roofline kernel of every N-th timed step with events (each "
-                         "costs device time)")
-    ap.add_argument("--roofline", choices=("back", "holecut"), default="back",
-                    help="kernel for the roofline object: the one-kernel back half (native executor) or the hole cut")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device-to-device copy of MIB MiB 5 times (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        n = args.copy_calibration * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / 5
-        print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": n * 8, "bytes_written": n * 8,
-                          "avg_ms": round(ms, 4), "gbs_read_plus_write": round(2 * n * 8 / ms / 1e6, 1)}), flush=True)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this path has no multi-GPU form.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def measure(args):
+    """Times args.steps steps of workload args.config; returns (the JSON fields, the workload)."""
     import numpy as np
     import torch
 
@@ -265,7 +210,8 @@ def main():
     t_host0 = time.perf_counter()
     native = pipe is not None and pipe.native is not None
     roof_back = args.roofline == "back" and native and not args.unfused_back
-    if native:
+    timing = native and args.roofline != "none"
+    if timing:
         pipe.native.stage_times(0)  # restart the timing record
         pipe.native.set_timing(args.time_every, 2 if roof_back else 0)
     if pipe is not None:
@@ -292,12 +238,12 @@ def main():
         f"{total_ms / args.steps * 1e3:.1f} us/step, status {status}")
 
     roofline = None
-    if native:
+    if timing:
         pipe.native.set_timing(0)
         ms = np.array(pipe.native.stage_times(args.steps))
         roof_note = (f"hip events around the {'back half' if roof_back else 'hole cut'} of every "
                      f"{args.time_every}-th timed step, recorded by the native executor on the stream it runs on")
-    elif hc:
+    elif hc and args.roofline != "none":
         ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
         roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
     else:
@@ -368,6 +314,92 @@ def main():
                    "tuned": tuned["params"] if tuned else None},
         "roofline": roofline,
     }
+    return out, w
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: every step of the workload after the warm-up)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C1")
+    ap.add_argument("--precision", default=None, help="fp64 or mixed (default: the config's)")
+    ap.add_argument("--graph", action="store_true", help="single stream, each step replayed from a HIP graph")
+    ap.add_argument("--sequential", action="store_true", help="single stream, eager launches")
+    ap.add_argument("--eager", action="store_true", help="two-stream pipeline driven from Python, eager launches")
+    ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
+    ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
+    ap.add_argument("--stages", type=int, default=None, choices=(1, 2, 3),
+                    help="native executor streams (default: the tuned choice, else 3)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the executor for this workload first when no tuned entry is cached")
+    ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
+    ap.add_argument("--per-step-submit", action="store_true",
+                    help="native pipeline: one host call per step instead of one call for all timed steps")
+    ap.add_argument("--native-graphs", action="store_true",
+                    help="the native executor replays per-stream HIP graphs instead of launching kernels directly")
+    ap.add_argument("--fields", choices=("interleaved", "blocks"), default="interleaved",
+                    help="field layout in HBM: u, v, w, p interleaved per node, or four blocks")
+    ap.add_argument("--max-walk", type=int, default=0, help="walk steps before the fallback scan (0: library default)")
+    ap.add_argument("--unfused-back", action="store_true",
+                    help="native executor: transform, search and interpolation as separate kernels")
+    ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
+                    help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
+    ap.add_argument("--time-every", type=int, default=16,
+                    help="native executor: time the roofline kernel of every N-th timed step with events (each "
+                         "costs device time)")
+    ap.add_argument("--compare", default="C4",
+                    help="also time this workload (the mixed-precision batched form) and report both ('' to skip)")
+    ap.add_argument("--roofline", choices=("back", "holecut", "none"), default="back",
+                    help="kernel for the roofline object: the one-kernel back half (native executor) or the hole cut")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB 5 times (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 5
+        print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": n * 8, "bytes_written": n * 8,
+                          "avg_ms": round(ms, 4), "gbs_read_plus_write": round(2 * n * 8 / ms / 1e6, 1)}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this path has no multi-GPU form.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    out, w = measure(args)
+    if args.compare and args.compare != args.config:
+        import copy
+        import gc
+        import torch
+        gc.collect()
+        torch.cuda.empty_cache()
+        a2 = copy.copy(args)
+        a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, None, None, None, 0
+        a2.roofline = "none"
+        o2, w2 = measure(a2)
+        out["forms"] = {
+            "note": "the same metric for the plain FP64 form (value above) and the mixed-precision batched form",
+            "plain_fp64": {"workload": out["config"]["workload"], "value": out["value"],
+                           "ms_per_step": out["ms_per_step"]},
+            "mixed_batched": {"workload": o2["config"]["workload"], "value": o2["value"],
+                              "ms_per_step": o2["ms_per_step"], "steps": o2["steps"],
+                              "queries_per_step_mean": o2["config"]["queries_per_step_mean"],
+                              "tuned": o2["config"]["tuned"]},
+            "mixed_batched_over_plain_fp64": round(o2["value"] / out["value"], 3)}
+        del w2
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
