@@ -9,7 +9,9 @@ FP64, ``-ffp-contract=off``); this module only marshals numpy arrays.
 Each stage follows a passage of Hedayat & Borazjani, arXiv:1910.09315:
 transform (Sec. 2.1), hole cutting (Sec. 2.2.2), query points (Sec. 2.2.3,
 Alg. 1), donor search by control cells and brute force (Sec. 2.2.5, Alg. 3),
-donor priority (Sec. 2.4 item 1), trilinear interpolation (Sec. 2.2.6).
+donor priority (Sec. 2.4 item 1), trilinear interpolation (Sec. 2.2.6),
+velocities in the receiver's frame (Sec. 2.3), the interpolation matrix and
+its application (Sec. 2.2.6 second option, Alg. 4).
 """
 from __future__ import annotations
 
@@ -71,6 +73,12 @@ def lib():
         L.orc_weights.restype = None
         L.orc_weights.argtypes = [_P, _P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_frame_velocity.restype = None
+        L.orc_frame_velocity.argtypes = [_P, ctypes.c_int64, _P, _P, _P]
+        L.orc_interp_matrix.restype = None
+        L.orc_interp_matrix.argtypes = [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]
+        L.orc_matrix_apply.restype = None
+        L.orc_matrix_apply.argtypes = [ctypes.c_int64, _P, _P, ctypes.c_int, ctypes.c_int64, _P, _P]
         _lib = L
     return _lib
 
@@ -198,6 +206,42 @@ class Oracle:
         vals = self.interp(fields, d["donor_grid"], d["donor_cell"], d["s"])
         return {"holecut_flags": holes, "flags": flags, "min_gap": gap, "q_grid": qg, "q_node": qn,
                 **d, "values": vals}
+
+
+def frame_velocity(poses, q_grid, donor_grid, values):
+    """Velocity components (fields 0..2 of `values`, [nfields, nq]) turned
+    from each donor's frame into its receiver's frame (Sec. 2.3); returns a
+    new array."""
+    out = np.ascontiguousarray(values, dtype=np.float64).copy()
+    nq = out.shape[1]
+    lib().orc_frame_velocity(_ptr(np.ascontiguousarray(poses, dtype=np.float64).reshape(-1)), nq,
+                             _ptr(np.ascontiguousarray(q_grid, dtype=np.int32)),
+                             _ptr(np.ascontiguousarray(donor_grid, dtype=np.int32)), _ptr(out))
+    return out
+
+
+def interp_matrix(o, donor_grid, donor_cell, s):
+    """The interpolation matrix of Alg. 4 for Oracle `o`: (cols [nq, 8] int64
+    global node indices, -1 for no donor; vals [nq, 8] weights)."""
+    nq = len(donor_grid)
+    cols = np.empty((max(nq, 1), 8), dtype=np.int64)
+    vals = np.empty((max(nq, 1), 8))
+    lib().orc_interp_matrix(_ptr(o.dims), _ptr(o.node_off), nq,
+                            _ptr(np.ascontiguousarray(donor_grid, dtype=np.int32)),
+                            _ptr(np.ascontiguousarray(donor_cell, dtype=np.int32)),
+                            _ptr(np.ascontiguousarray(s, dtype=np.float64)), _ptr(cols), _ptr(vals))
+    return cols[:nq], vals[:nq]
+
+
+def matrix_apply(cols, vals, x):
+    """y = M x for the rows of (cols, vals) and x [nrhs, total_nodes]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nrhs, total = x.shape
+    nq = cols.shape[0]
+    y = np.empty((nrhs, max(nq, 1)))
+    lib().orc_matrix_apply(nq, _ptr(np.ascontiguousarray(cols, dtype=np.int64)),
+                           _ptr(np.ascontiguousarray(vals, dtype=np.float64)), nrhs, total, _ptr(x), _ptr(y))
+    return y[:, :nq]
 
 
 def weights(s):

@@ -24,6 +24,12 @@
  *                      trilinear natural coordinates found by Newton's method;
  *                      donor priority of Sec. 2.4 item 1; blanked donors invalid
  *   orc_interp         trilinear interpolation (Sec. 2.2.6)
+ *   orc_frame_velocity interpolated velocity given in the receiver's frame
+ *                      (Sec. 2.3, the non-inertial velocity relation)
+ *   orc_interp_matrix  the interpolation matrix: per query the global indices
+ *                      of its donor's corners and their weights (Sec. 2.2.6,
+ *                      second option; Alg. 4)
+ *   orc_matrix_apply   that matrix times field vectors
  *
  * The walk of Alg. 3 is an accelerator that must reach the same cell; the
  * oracle therefore omits it and searches every candidate cell.
@@ -659,4 +665,65 @@ void orc_weights(const double *s, double *w) {
         for (int d = 0; d < 3; ++d) f[d] = ((c >> d) & 1) ? s[d] : 1.0 - s[d];
         w[c] = (f[0] * f[1]) * f[2];
     }
+}
+
+/* Velocity in the receiver's frame (Sec. 2.3): the fields interpolated from
+ * donor grid B are components in B's non-inertial frame; the receiver, a
+ * node of grid A, needs them in A's frame. With poses x = R X + c (R = Q^T of
+ * the paper), the inertial velocity is R_B u_B and A's components are
+ * u_A = R_A^T (R_B u_B). Fields 0, 1, 2 of values (nfields blocks of nq) are
+ * rewritten in place; queries without a donor are left alone. */
+void orc_frame_velocity(const double *poses, int64_t nq, const int32_t *q_grid, const int32_t *donor_grid,
+                        double *values) {
+    for (int64_t q = 0; q < nq; ++q) {
+        int B = donor_grid[q];
+        if (B < 0) continue;
+        const double *rb = poses + 12 * B, *ra = poses + 12 * q_grid[q];
+        double u[3] = {values[q], values[nq + q], values[2 * nq + q]}, w[3];
+        for (int i = 0; i < 3; ++i) w[i] = (rb[3 * i] * u[0] + rb[3 * i + 1] * u[1]) + rb[3 * i + 2] * u[2];
+        for (int i = 0; i < 3; ++i) values[i * nq + q] = (ra[i] * w[0] + ra[3 + i] * w[1]) + ra[6 + i] * w[2];
+    }
+}
+
+/* The interpolation matrix (Sec. 2.2.6, second option; Alg. 4): row q
+ * holds, for its 8 corners c, the global index of the corner node (grids
+ * packed by node offset, the paper's global index with one process) and
+ * the trilinear weight w_c = prod_d (c_d ? s_d : 1 - s_d). A query without a
+ * donor has an empty row: index -1, weight 0. */
+void orc_interp_matrix(const int32_t *dims, const int64_t *node_off, int64_t nq, const int32_t *donor_grid,
+                       const int32_t *donor_cell, const double *s, int64_t *cols, double *vals) {
+    for (int64_t q = 0; q < nq; ++q) {
+        int B = donor_grid[q];
+        if (B < 0) {
+            for (int c = 0; c < 8; ++c) {
+                cols[8 * q + c] = -1;
+                vals[8 * q + c] = 0.0;
+            }
+            continue;
+        }
+        gdim g = make_dim(dims + 4 * B);
+        int64_t nd[8];
+        cell_corners(&g, donor_cell[q], nd);
+        for (int c = 0; c < 8; ++c) {
+            double f[3];
+            for (int d = 0; d < 3; ++d) f[d] = ((c >> d) & 1) ? s[3 * q + d] : 1.0 - s[3 * q + d];
+            cols[8 * q + c] = node_off[B] + nd[c];
+            vals[8 * q + c] = (f[0] * f[1]) * f[2];
+        }
+    }
+}
+
+/* y_r = M x_r for nrhs vectors x_r (blocks of total_nodes), y as nrhs
+ * blocks of nq. Empty entries (index -1) contribute nothing. */
+void orc_matrix_apply(int64_t nq, const int64_t *cols, const double *vals, int nrhs, int64_t total_nodes,
+                      const double *x, double *y) {
+    for (int r = 0; r < nrhs; ++r)
+        for (int64_t q = 0; q < nq; ++q) {
+            double acc = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                int64_t j = cols[8 * q + c];
+                if (j >= 0) acc = acc + vals[8 * q + c] * x[(int64_t)r * total_nodes + j];
+            }
+            y[(int64_t)r * nq + q] = acc;
+        }
 }
