@@ -99,6 +99,69 @@ def cpu_baseline(w, budget_s: float) -> dict:
                       f"control cells built beforehand; host CPU {cpu_model()}"}
 
 
+def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
+    """Times the calls that follow a step on its buffer set `b`: the
+    interpolation matrix (ELL-8), its application to nrhs vectors, and the
+    velocity-frame rotation, each over `reps` launches with events on the
+    stream they are launched on. Algorithmic bytes per launch: what each
+    call must read and write once (for the application, each distinct
+    column's x values once per vector)."""
+    import torch
+    from paper_1910_09315_amd import binding as B
+    dev = a.dev
+    torch.cuda.synchronize(dev)
+    n = min(int(b.d_count.item()), b.capacity)
+    es = 4 if a.dtype == torch.float32 else 8
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    x = torch.randn((nrhs, a.total), generator=gen, dtype=torch.float64, device=dev).to(a.dtype).contiguous()
+    y = torch.empty((nrhs, b.capacity), dtype=a.dtype, device=dev)
+    cols, vals = a.interp_matrix(b)
+    a.interp_apply(cols, vals, x, b, y)
+    torch.cuda.synchronize(dev)
+    live = cols[:n]
+    distinct = int(torch.unique(live[live >= 0]).numel())
+    poses = torch.zeros(a.ngrids * 12, dtype=torch.float64, device=dev)
+    poses[0::12] = 1.0
+    poses[4::12] = 1.0
+    poses[8::12] = 1.0
+    out = b.out.clone()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    us_apply = timed(lambda: a.interp_apply(cols, vals, x, b, y))
+    us_matrix = timed(lambda: a.interp_matrix(b))
+    # identity poses: the rotation leaves the values as they are, so repeated launches see the same data
+    us_frame = timed(lambda: B.overset_frame_velocity(a.ctx, poses, b.q_grid, b.donor_grid, b.d_count, b.capacity,
+                                                      out))
+    bytes_apply = n * 8 * (4 + es) + n * nrhs * es + distinct * nrhs * es
+    bytes_matrix = n * (4 + 4 + 3 * es) + n * 8 * (4 + es)
+    bytes_frame = n * (4 + 4) + 2 * n * 3 * es
+
+    def row(us, nbytes, per_unit):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        return {"avg_us": round(us, 2), "algorithmic_bytes_per_launch": nbytes, "achieved_gbs": round(gbs, 1),
+                "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "rows_per_s": round(n / (us * 1e-6), 1),
+                "per_unit": per_unit}
+
+    return {"rows": n, "reps": reps, "timing": "hip events around the launches on the stream they run on",
+            "interp_apply": dict(row(us_apply, bytes_apply,
+                                     f"per row 8 x ({4 + es} B index+weight) + {nrhs} x {es} B y; plus "
+                                     f"{distinct} distinct columns x {nrhs} x {es} B x"), nrhs=nrhs),
+            "interp_matrix": row(us_matrix, bytes_matrix,
+                                 f"per row 8 B donor grid+cell + {3 * es} B s read, 8 x ({4 + es} B) written"),
+            "frame_velocity": row(us_frame, bytes_frame,
+                                  f"per row 8 B grids read + 3 x {es} B read and written")}
+
+
 def measure(args):
     """Times args.steps steps of workload args.config; returns (the JSON fields, the workload)."""
     import numpy as np
@@ -314,6 +377,11 @@ def measure(args):
                    "tuned": tuned["params"] if tuned else None},
         "roofline": roofline,
     }
+    if args.next_rows:
+        last = args.warmup + args.steps - 1
+        b = pipe.bufs[last % pipe.nsets] if pipe is not None else a.buf
+        out["next_rows"] = measure_next_rows(a, b, args.apply_nrhs, reps=50)
+        log(f"[bench] next rows: {out['next_rows']}")
     return out, w
 
 
@@ -353,6 +421,9 @@ def main():
                     help="also time this workload (the mixed-precision batched form) and report both ('' to skip)")
     ap.add_argument("--roofline", choices=("back", "holecut", "none"), default="back",
                     help="kernel for the roofline object: the one-kernel back half (native executor) or the hole cut")
+    ap.add_argument("--no-next-rows", dest="next_rows", action="store_false",
+                    help="skip timing the interpolation matrix, its application and the frame rotation")
+    ap.add_argument("--apply-nrhs", type=int, default=4, help="vectors per application of the interpolation matrix")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -397,7 +468,7 @@ def main():
             "mixed_batched": {"workload": o2["config"]["workload"], "value": o2["value"],
                               "ms_per_step": o2["ms_per_step"], "steps": o2["steps"],
                               "queries_per_step_mean": o2["config"]["queries_per_step_mean"],
-                              "tuned": o2["config"]["tuned"]},
+                              "tuned": o2["config"]["tuned"], "next_rows": o2.get("next_rows")},
             "mixed_batched_over_plain_fp64": round(o2["value"] / out["value"], 3)}
         del w2
     if not args.no_cpu_baseline:

@@ -115,9 +115,12 @@ enum ov_option {
     OV_OPT_BACK_BLOCKS = 11,/* workgroups per CU of that one kernel (1..32, default 8) */
     OV_OPT_BACK_BLOCK = 12, /* its threads per workgroup: 64, 128 or 256 (default; also the width of the
                                cooperative fallback scan) */
-    OV_OPT_FIELD_LAYOUT = 13 /* layout of the fields given to overset_interp and the executors: 0 (default)
+    OV_OPT_FIELD_LAYOUT = 13,/* layout of the fields given to overset_interp and the executors: 0 (default)
                                four blocks of total_nodes values (u block, v, w, p); 1 interleaved per node
                                (u, v, w, p of node 0, then node 1, ...): one load per donor corner */
+    OV_OPT_FRAME_VELOCITY = 14 /* step executors: 1 gives the interpolated u, v, w in the receiver's frame
+                               (as overset_frame_velocity does after overset_interp); 0 (default) leaves them
+                               in the donor's frame */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.
@@ -251,6 +254,41 @@ int overset_donor_search(ov_ctx *ctx, const double *poses, const uint8_t *flags,
  * Both double (OV_FP64) or float (OV_MIXED). */
 int overset_interp(ov_ctx *ctx, const int32_t *donor_grid, const int32_t *donor_cell, const void *s,
                    const int64_t *d_count, int64_t capacity, const void *fields, void *out, void *stream);
+
+/* Velocities in the receiver's frame (Sec. 2.3): each grid's flow is solved
+ * in its own non-inertial frame, so the u, v, w that overset_interp gathers
+ * from donor grid B are components in B's frame. For every query i <
+ * *d_count with a donor this rewrites fields 0, 1, 2 of out in place as the
+ * components in the frame of the query's grid A: u_A = R_A^T R_B u_B, with R
+ * the rotation of each pose (x = R X + c; R is the transpose of the paper's
+ * Q). The pressure (field 3) is a scalar and stays as it is.
+ *  poses      ngrids*12 doubles of this step (device)
+ *  q_grid, donor_grid, d_count, capacity: as from the compaction and search
+ *  out        4*capacity values, context precision (in/out)
+ * In the step executors, OV_OPT_FRAME_VELOCITY = 1 does the same inside the
+ * back half. */
+int overset_frame_velocity(ov_ctx *ctx, const double *poses, const int32_t *q_grid, const int32_t *donor_grid,
+                           const int64_t *d_count, int64_t capacity, void *out, void *stream);
+
+/* The interpolation matrix (Sec. 2.2.6, second option; Alg. 4), one row per
+ * query i < *d_count in ELL form of 8 entries, row-major: cols[8 i + c] is
+ * the global index (node offset of the donor grid + node: the paper's
+ * global index on one GPU) of corner c (= c0 + 2 c1 + 4 c2, periodic wrap)
+ * of the donor cell, vals[8 i + c] its trilinear weight; a query without a
+ * donor has cols -1 and vals 0. Rows from *d_count on are not written.
+ *  cols   8*capacity int32 (device); needs total_nodes < 2^31 (OV_EDIMS otherwise)
+ *  vals   8*capacity values, context precision */
+int overset_interp_matrix(ov_ctx *ctx, const int32_t *donor_grid, const int32_t *donor_cell, const void *s,
+                          const int64_t *d_count, int64_t capacity, int32_t *cols, void *vals, void *stream);
+
+/* The matrix applied to nrhs field vectors (the product Alg. 4 repeats at
+ * every Newton-Krylov iteration): y[r*capacity + i] = sum over the row's
+ * entries with cols >= 0 of vals[8 i + c] * x[r*total_nodes + cols[8 i + c]],
+ * for every row i < *d_count and vector r < nrhs.
+ *  x   nrhs*total_nodes values (vectors packed by node offset), context precision
+ *  y   nrhs*capacity values, context precision */
+int overset_interp_apply(ov_ctx *ctx, const int32_t *cols, const void *vals, const int64_t *d_count,
+                         int64_t capacity, const void *x, int32_t nrhs, void *y, void *stream);
 
 /* ---------------------------------------------------------------- pipelined steps */
 

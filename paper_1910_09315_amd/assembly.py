@@ -59,10 +59,9 @@ class Assembly:
             self.ctx.grid_add(g.dims, g.periodic, X, Y, Z, g.blank_kind, tuple(g.blank_prm), tuple(g.outer))
         self.ctx.finalize()
         self.field_layout = 0
+        self.frame_velocity = 0
         for k, v in (options or {}).items():
-            self.ctx.set_option(k, v)
-            if k == "field_layout":
-                self.field_layout = int(v)
+            self.set_option(k, v)
         self.ngrids = len(grids)
         self.total = self.ctx.total_nodes()
         self.node_off = np.array(self.ctx.node_offsets(), dtype=np.int64)
@@ -74,6 +73,13 @@ class Assembly:
             self.allocate(capacity)
         self.graph = None
         self.pose_slot = None
+
+    def set_option(self, name: str, value: int):
+        self.ctx.set_option(name, value)
+        if name == "field_layout":
+            self.field_layout = int(value)
+        elif name == "frame_velocity":
+            self.frame_velocity = int(value)
 
     # ------------------------------------------------------------ buffers
     def set_fields(self, fields):
@@ -125,6 +131,29 @@ class Assembly:
                                b.donor_cell, b.s, b.status, stream)
         if self.fields is not None:
             B.overset_interp(self.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count, cap, self.fields, b.out, stream)
+            if self.frame_velocity:
+                B.overset_frame_velocity(self.ctx, p, b.q_grid, b.donor_grid, b.d_count, cap, b.out, stream)
+
+    # ------------------------------------------------------------ interpolation matrix
+    def interp_matrix(self, b: StepBuffers | None = None, stream=None):
+        """The step's interpolation matrix in ELL-8 form: (cols [capacity, 8]
+        int32 global node indices, vals [capacity, 8] weights)."""
+        b = self.buf if b is None else b
+        cols = torch.empty((b.capacity, 8), dtype=torch.int32, device=self.dev)
+        vals = torch.empty((b.capacity, 8), dtype=self.dtype, device=self.dev)
+        B.overset_interp_matrix(self.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count, b.capacity, cols, vals,
+                                stream)
+        return cols, vals
+
+    def interp_apply(self, cols, vals, x, b: StepBuffers | None = None, y=None, stream=None):
+        """y = M x for x of shape [nrhs, total_nodes] (context precision);
+        returns y of shape [nrhs, capacity]."""
+        b = self.buf if b is None else b
+        nrhs = x.shape[0]
+        if y is None:
+            y = torch.empty((nrhs, b.capacity), dtype=self.dtype, device=self.dev)
+        B.overset_interp_apply(self.ctx, cols, vals, b.d_count, b.capacity, x, nrhs, y, stream)
+        return y
 
     def step(self, poses, stream=None):
         """One time step on one stream; nothing synchronises."""

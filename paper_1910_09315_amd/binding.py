@@ -23,13 +23,15 @@ OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE = 1, 2, 4
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
        "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
-       "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13}
+       "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13,
+       "frame_velocity": 14}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
-           "overset_interp", "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
+           "overset_interp", "overset_frame_velocity", "overset_interp_matrix", "overset_interp_apply",
+           "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
            "ov_pipe_submit",
            "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_stage_times", "ov_pipe_destroy"]
 
@@ -76,6 +78,9 @@ def load(path: str = LIB_PATH):
         "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
         "overset_donor_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P]),
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
+        "overset_frame_velocity": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
+        "overset_interp_matrix": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
+        "overset_interp_apply": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _I32, _P, _P]),
         "ov_pipe_create": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_create3": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_create1": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
@@ -205,6 +210,22 @@ def overset_donor_search(ctx: Context, poses, flags, q_grid, q_node, qx, d_count
 def overset_interp(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, fields, out, stream=None):
     ctx.check(ctx.lib.overset_interp(ctx.h, _ptr(donor_grid), _ptr(donor_cell), _ptr(s), _ptr(d_count),
                                      int(capacity), _ptr(fields), _ptr(out), _stream(stream)), "overset_interp")
+
+
+def overset_frame_velocity(ctx: Context, poses, q_grid, donor_grid, d_count, capacity, out, stream=None):
+    ctx.check(ctx.lib.overset_frame_velocity(ctx.h, _ptr(poses), _ptr(q_grid), _ptr(donor_grid), _ptr(d_count),
+                                             int(capacity), _ptr(out), _stream(stream)), "overset_frame_velocity")
+
+
+def overset_interp_matrix(ctx: Context, donor_grid, donor_cell, s, d_count, capacity, cols, vals, stream=None):
+    ctx.check(ctx.lib.overset_interp_matrix(ctx.h, _ptr(donor_grid), _ptr(donor_cell), _ptr(s), _ptr(d_count),
+                                            int(capacity), _ptr(cols), _ptr(vals), _stream(stream)),
+              "overset_interp_matrix")
+
+
+def overset_interp_apply(ctx: Context, cols, vals, d_count, capacity, x, nrhs, y, stream=None):
+    ctx.check(ctx.lib.overset_interp_apply(ctx.h, _ptr(cols), _ptr(vals), _ptr(d_count), int(capacity), _ptr(x),
+                                           int(nrhs), _ptr(y), _stream(stream)), "overset_interp_apply")
 
 
 class NativePipe:

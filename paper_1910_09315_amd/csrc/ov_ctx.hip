@@ -778,6 +778,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       if (v != 0 && v != 1) break;
       ctx->field_layout = (int)v;
       return OV_OK;
+    case OV_OPT_FRAME_VELOCITY:
+      if (v != 0 && v != 1) break;
+      ctx->frame_velocity = (int)v;
+      return OV_OK;
     case OV_OPT_PERSIST:
       if (v < 0 || v > 32) break;
       ctx->persist = (int)v;

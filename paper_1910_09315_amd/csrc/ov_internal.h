@@ -146,6 +146,7 @@ struct ov_ctx {
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   int back_block = 256;        // its threads per block (64, 128 or 256)
   int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
+  int frame_velocity = 0;      // executors: interpolated velocities in the receiver's frame
   std::string err;
 };
 
@@ -185,6 +186,9 @@ hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, c
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
                        void* out, long long* count_out, hipStream_t st, int slot = 0);
 hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st);
+hipError_t launch_frame_velocity(ov_ctx* ctx, const double* poses, const int32_t* q_grid,
+                                 const int32_t* donor_grid, const long long* d_count, long long capacity, void* out,
+                                 hipStream_t st);
 // setup (control cells, shadows)
 int build_control_cells(ov_ctx* ctx, GridHost& g, hipStream_t s);
 int build_subbins(ov_ctx* ctx, GridHost& g, const std::vector<unsigned long long>& cnt, hipStream_t s);
@@ -340,6 +344,19 @@ __device__ __forceinline__ void interp_point(const GridDev& G, int cell, T s0, T
     for (int c = 0; c < 8; ++c) acc += w[c] * F[nd[c]];
     v[f] = acc;
   }
+}
+
+// A velocity's components turned from donor frame B into receiver frame A:
+// v <- R_A^T (R_B v), with R the rotation of each pose (row-major, the pose's
+// first 9 values); formed in FP64.
+template <typename T>
+__device__ __forceinline__ void frame_rotate(const double* pa, const double* pb, T v[3]) {
+  const double u0 = (double)v[0], u1 = (double)v[1], u2 = (double)v[2];
+  double w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = pb[3 * i] * u0 + pb[3 * i + 1] * u1 + pb[3 * i + 2] * u2;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = (T)(pa[i] * w[0] + pa[3 + i] * w[1] + pa[6 + i] * w[2]);
 }
 
 __device__ __forceinline__ int bin_axis(const GridDev& g, int d, double v) {

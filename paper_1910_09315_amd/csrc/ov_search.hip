@@ -767,8 +767,8 @@ __global__ void __launch_bounds__(BS)
            int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
            int32_t* __restrict__ status, Warm warm, int max_walk, int32_t* __restrict__ dev_status,
            const T* __restrict__ fields,
-           long long total_nodes, int interleaved, T* __restrict__ out, long long* __restrict__ count_out,
-           unsigned long long* __restrict__ stats) {
+           long long total_nodes, int interleaved, int frame_velocity, T* __restrict__ out,
+           long long* __restrict__ count_out, unsigned long long* __restrict__ stats) {
   __shared__ double sp[kMaxGrids * 12];
   __shared__ int list_q[BS], list_st[BS];
   __shared__ int nlist;
@@ -801,8 +801,10 @@ __global__ void __launch_bounds__(BS)
     int visited = 0;
     bool limit = false;
     long long key = 0;
+    int my_grid = 0;
     if (mine) {
       const int A = q_grid[q];
+      my_grid = A;
       T o[3];
       transform_node<T>(grids[A], sp + 12 * A, q_node[q], o);
       qx[q] = o[0];
@@ -945,6 +947,7 @@ __global__ void __launch_bounds__(BS)
       if (fields && res_grid >= 0) {
         T v[4];
         interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, interleaved != 0, v);
+        if (frame_velocity) frame_rotate<T>(sp + 12 * my_grid, sp + 12 * res_grid, v);
 #pragma unroll
         for (int f = 0; f < 4; ++f) out[(long long)f * cap + q] = v[f];
       }
@@ -1001,7 +1004,7 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
-      ctx->node_off.back(), ctx->field_layout, out, count_out, ctx->d_stats
+      ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, count_out, ctx->d_stats
   const size_t lds = sizeof(GridDev) * ctx->grids.size();
   if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), lds, st, OV_BACK_ARGS);
   else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), lds, st, OV_BACK_ARGS);
@@ -1051,6 +1054,8 @@ hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, c
                               status, st, slot);
     if (e == hipSuccess && fields)
       e = launch_interp(ctx, donor_grid, donor_cell, s, d_count, capacity, fields, out, st);
+    if (e == hipSuccess && fields && ctx->frame_velocity)
+      e = launch_frame_velocity(ctx, poses, q_grid, donor_grid, d_count, capacity, out, st);
   }
   if (e == hipSuccess && count_out) e = launch_copy_count(count_out, (const int64_t*)d_count, st);
   return e;

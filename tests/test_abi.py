@@ -33,6 +33,12 @@ def test_header_declares_the_five_step_calls():
         assert n in names
 
 
+def test_header_declares_the_matrix_and_frame_calls():
+    names = declared()
+    for n in ("overset_frame_velocity", "overset_interp_matrix", "overset_interp_apply"):
+        assert n in names
+
+
 def test_library_exports_every_declared_symbol(lib):
     for n in declared():
         assert hasattr(lib, n), n
