@@ -101,11 +101,12 @@ def cpu_baseline(w, budget_s: float) -> dict:
 
 def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
     """Times the calls that follow a step on its buffer set `b`: the
-    interpolation matrix (ELL-8), its application to nrhs vectors, and the
-    velocity-frame rotation, each over `reps` launches with events on the
-    stream they are launched on. Algorithmic bytes per launch: what each
-    call must read and write once (for the application, each distinct
-    column's x values once per vector)."""
+    interpolation matrix (ELL-8), its application to nrhs vectors
+    interleaved per node, and the velocity-frame rotation. Each call is
+    captured `reps` times into a HIP graph whose replay is timed with events
+    on the replaying stream (no host gaps between the launches). Algorithmic
+    bytes per launch: what each call must read and write once (for the
+    application, each distinct column's x values once)."""
     import torch
     from paper_1910_09315_amd import binding as B
     dev = a.dev
@@ -114,10 +115,11 @@ def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
     es = 4 if a.dtype == torch.float32 else 8
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
-    x = torch.randn((nrhs, a.total), generator=gen, dtype=torch.float64, device=dev).to(a.dtype).contiguous()
-    y = torch.empty((nrhs, b.capacity), dtype=a.dtype, device=dev)
-    cols, vals = a.interp_matrix(b)
-    a.interp_apply(cols, vals, x, b, y)
+    x = torch.randn((a.total, nrhs), generator=gen, dtype=torch.float64, device=dev).to(a.dtype).contiguous()
+    y = torch.empty((b.capacity, nrhs), dtype=a.dtype, device=dev)
+    cols = torch.empty((b.capacity, 8), dtype=torch.int32, device=dev)
+    vals = torch.empty((b.capacity, 8), dtype=a.dtype, device=dev)
+    B.overset_interp_matrix(a.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count, b.capacity, cols, vals)
     torch.cuda.synchronize(dev)
     live = cols[:n]
     distinct = int(torch.unique(live[live >= 0]).numel())
@@ -126,40 +128,51 @@ def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
     poses[4::12] = 1.0
     poses[8::12] = 1.0
     out = b.out.clone()
+    calls = {
+        "interp_apply": lambda: B.overset_interp_apply(a.ctx, cols, vals, b.d_count, b.capacity, x, nrhs, y,
+                                                       layout=1),
+        "interp_matrix": lambda: B.overset_interp_matrix(a.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count,
+                                                         b.capacity, cols, vals),
+        # identity poses: the rotation leaves the values as they are, so every launch sees the same data
+        "frame_velocity": lambda: B.overset_frame_velocity(a.ctx, poses, b.q_grid, b.donor_grid, b.d_count,
+                                                           b.capacity, out),
+    }
 
     def timed(fn):
-        fn()
+        s = torch.cuda.Stream(dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream(dev).wait_stream(s)
+        torch.cuda.synchronize(dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(reps):
-            fn()
+        g.replay()
         e1.record()
         torch.cuda.synchronize(dev)
         return e0.elapsed_time(e1) * 1e3 / reps
 
-    us_apply = timed(lambda: a.interp_apply(cols, vals, x, b, y))
-    us_matrix = timed(lambda: a.interp_matrix(b))
-    # identity poses: the rotation leaves the values as they are, so repeated launches see the same data
-    us_frame = timed(lambda: B.overset_frame_velocity(a.ctx, poses, b.q_grid, b.donor_grid, b.d_count, b.capacity,
-                                                      out))
-    bytes_apply = n * 8 * (4 + es) + n * nrhs * es + distinct * nrhs * es
-    bytes_matrix = n * (4 + 4 + 3 * es) + n * 8 * (4 + es)
-    bytes_frame = n * (4 + 4) + 2 * n * 3 * es
-
-    def row(us, nbytes, per_unit):
-        gbs = nbytes / (us * 1e-6) / 1e9
-        return {"avg_us": round(us, 2), "algorithmic_bytes_per_launch": nbytes, "achieved_gbs": round(gbs, 1),
-                "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "rows_per_s": round(n / (us * 1e-6), 1),
-                "per_unit": per_unit}
-
-    return {"rows": n, "reps": reps, "timing": "hip events around the launches on the stream they run on",
-            "interp_apply": dict(row(us_apply, bytes_apply,
-                                     f"per row 8 x ({4 + es} B index+weight) + {nrhs} x {es} B y; plus "
-                                     f"{distinct} distinct columns x {nrhs} x {es} B x"), nrhs=nrhs),
-            "interp_matrix": row(us_matrix, bytes_matrix,
-                                 f"per row 8 B donor grid+cell + {3 * es} B s read, 8 x ({4 + es} B) written"),
-            "frame_velocity": row(us_frame, bytes_frame,
-                                  f"per row 8 B grids read + 3 x {es} B read and written")}
+    us = {k: timed(f) for k, f in calls.items()}
+    nbytes = {"interp_apply": n * 8 * (4 + es) + n * nrhs * es + distinct * nrhs * es,
+              "interp_matrix": n * (4 + 4 + 3 * es) + n * 8 * (4 + es),
+              "frame_velocity": n * (4 + 4) + 2 * n * 3 * es}
+    per_unit = {"interp_apply": f"per row 8 x ({4 + es} B index+weight) + {nrhs} x {es} B y; plus {distinct} "
+                                f"distinct columns x {nrhs} x {es} B x (vectors interleaved per node)",
+                "interp_matrix": f"per row 8 B donor grid+cell + {3 * es} B s read, 8 x ({4 + es} B) written",
+                "frame_velocity": f"per row 8 B grids read + 3 x {es} B read and written"}
+    res = {"rows": n, "reps": reps, "nrhs": nrhs,
+           "timing": "hip events around a graph replay of reps launches, on the replaying stream"}
+    for k in calls:
+        gbs = nbytes[k] / (us[k] * 1e-6) / 1e9
+        res[k] = {"avg_us": round(us[k], 2), "algorithmic_bytes_per_launch": nbytes[k], "achieved_gbs": round(gbs, 1),
+                  "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "rows_per_s": round(n / (us[k] * 1e-6), 1),
+                  "per_unit": per_unit[k]}
+    return res
 
 
 def measure(args):

@@ -282,13 +282,18 @@ int overset_interp_matrix(ov_ctx *ctx, const int32_t *donor_grid, const int32_t 
                           const int64_t *d_count, int64_t capacity, int32_t *cols, void *vals, void *stream);
 
 /* The matrix applied to nrhs field vectors (the product Alg. 4 repeats at
- * every Newton-Krylov iteration): y[r*capacity + i] = sum over the row's
- * entries with cols >= 0 of vals[8 i + c] * x[r*total_nodes + cols[8 i + c]],
- * for every row i < *d_count and vector r < nrhs.
- *  x   nrhs*total_nodes values (vectors packed by node offset), context precision
- *  y   nrhs*capacity values, context precision */
+ * every Newton-Krylov iteration): for every row i < *d_count and vector
+ * r < nrhs, y_r[i] = sum over the row's entries with cols >= 0, in corner
+ * order, of vals[8 i + c] * x_r[cols[8 i + c]].
+ *  layout 0: vectors as blocks, x[r*total_nodes + node], y[r*capacity + i];
+ *  layout 1: interleaved per node, x[node*nrhs + r], y[i*nrhs + r] (with
+ *            nrhs = 4, one load per corner and one store per row).
+ *  x   nrhs*total_nodes values, context precision
+ *  y   nrhs*capacity values, context precision; rows from *d_count on are not written
+ * cols and vals must be 16-byte aligned; x and y aligned to one value, or to
+ * 4 values with layout 1 and nrhs = 4 (OV_EINVAL otherwise). */
 int overset_interp_apply(ov_ctx *ctx, const int32_t *cols, const void *vals, const int64_t *d_count,
-                         int64_t capacity, const void *x, int32_t nrhs, void *y, void *stream);
+                         int64_t capacity, const void *x, int32_t nrhs, int32_t layout, void *y, void *stream);
 
 /* ---------------------------------------------------------------- pipelined steps */
 

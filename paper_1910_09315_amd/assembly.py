@@ -145,14 +145,15 @@ class Assembly:
                                 stream)
         return cols, vals
 
-    def interp_apply(self, cols, vals, x, b: StepBuffers | None = None, y=None, stream=None):
-        """y = M x for x of shape [nrhs, total_nodes] (context precision);
-        returns y of shape [nrhs, capacity]."""
+    def interp_apply(self, cols, vals, x, b: StepBuffers | None = None, y=None, layout: int = 0, stream=None):
+        """y = M x. layout 0: x [nrhs, total_nodes], y [nrhs, capacity];
+        layout 1 (interleaved per node): x [total_nodes, nrhs], y [capacity, nrhs]."""
         b = self.buf if b is None else b
-        nrhs = x.shape[0]
+        nrhs = x.shape[0] if layout == 0 else x.shape[1]
         if y is None:
-            y = torch.empty((nrhs, b.capacity), dtype=self.dtype, device=self.dev)
-        B.overset_interp_apply(self.ctx, cols, vals, b.d_count, b.capacity, x, nrhs, y, stream)
+            shape = (nrhs, b.capacity) if layout == 0 else (b.capacity, nrhs)
+            y = torch.empty(shape, dtype=self.dtype, device=self.dev)
+        B.overset_interp_apply(self.ctx, cols, vals, b.d_count, b.capacity, x, nrhs, y, layout, stream)
         return y
 
     def step(self, poses, stream=None):

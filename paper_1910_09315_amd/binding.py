@@ -80,7 +80,7 @@ def load(path: str = LIB_PATH):
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "overset_frame_velocity": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
         "overset_interp_matrix": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
-        "overset_interp_apply": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _I32, _P, _P]),
+        "overset_interp_apply": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _I32, _I32, _P, _P]),
         "ov_pipe_create": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_create3": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
         "ov_pipe_create1": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
@@ -223,9 +223,9 @@ def overset_interp_matrix(ctx: Context, donor_grid, donor_cell, s, d_count, capa
               "overset_interp_matrix")
 
 
-def overset_interp_apply(ctx: Context, cols, vals, d_count, capacity, x, nrhs, y, stream=None):
+def overset_interp_apply(ctx: Context, cols, vals, d_count, capacity, x, nrhs, y, layout=0, stream=None):
     ctx.check(ctx.lib.overset_interp_apply(ctx.h, _ptr(cols), _ptr(vals), _ptr(d_count), int(capacity), _ptr(x),
-                                           int(nrhs), _ptr(y), _stream(stream)), "overset_interp_apply")
+                                           int(nrhs), int(layout), _ptr(y), _stream(stream)), "overset_interp_apply")
 
 
 class NativePipe:

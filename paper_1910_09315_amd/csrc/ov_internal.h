@@ -208,6 +208,7 @@ __device__ __forceinline__ gmem<T>* gp(const T* p) {
 
 typedef double ov_dv2 __attribute__((ext_vector_type(2)));
 typedef float ov_fv4 __attribute__((ext_vector_type(4)));
+typedef int ov_iv4 __attribute__((ext_vector_type(4)));
 
 // (x, y, z) of node n from a grid's gather layout: two 16-byte loads.
 __device__ __forceinline__ void load_xyz(const GridDev& G, long long n, double& x, double& y, double& z) {

@@ -147,6 +147,27 @@ def test_interp_apply_matches_oracle(name, precision, nrhs):
     assert np.all(np.abs(yf[:, live] - g["values"][:, live]) <= (1e-13 if precision == "fp64" else 1e-5) * scale)
 
 
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 4), ("mixed", 4), ("fp64", 3), ("mixed", 1)])
+def test_interp_apply_interleaved_equals_blocks(precision, nrhs):
+    """Vectors interleaved per node (one gather per corner with 4 vectors)
+    give the blocks layout's results bitwise."""
+    w = W.c3_small(steps=2)
+    a = _assembly(w, precision)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    for k in range(w.steps):
+        a.step(poses[k])
+    cols, vals = a.interp_matrix()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(99)
+    x = torch.randn((nrhs, a.total), generator=gen, dtype=torch.float64, device="cuda").to(a.dtype).contiguous()
+    yb = a.interp_apply(cols, vals, x)
+    yi = a.interp_apply(cols, vals, x.t().contiguous(), layout=1)
+    torch.cuda.synchronize()
+    n = int(a.d_count.item())
+    assert n > 10000
+    assert torch.equal(yi[:n].t(), yb[:, :n])
+
+
 def test_matrix_calls_with_no_rows_and_bad_arguments():
     """Zero rows leave the outputs untouched; bad arguments are errors
     before any launch."""
@@ -164,6 +185,10 @@ def test_matrix_calls_with_no_rows_and_bad_arguments():
     assert bool((cols == 77).all()) and bool((vals == 5.0).all()) and bool((y == 3.0).all())
     with pytest.raises(B.OversetError):
         B.overset_interp_apply(a.ctx, cols, vals, a.d_count, a.capacity, x, -1, y)
+    with pytest.raises(B.OversetError):
+        B.overset_interp_apply(a.ctx, cols, vals, a.d_count, a.capacity, x, 2, y, layout=2)
+    with pytest.raises(B.OversetError):  # interleaved 4-vector gathers need 32-byte aligned fp64 values
+        B.overset_interp_apply(a.ctx, cols, vals, a.d_count, a.capacity, x.reshape(-1)[1:], 4, y, layout=1)
     with pytest.raises(B.OversetError):
         B.overset_interp_matrix(a.ctx, a.donor_grid, a.donor_cell, None, a.d_count, a.capacity, cols, vals)
     with pytest.raises(B.OversetError):
