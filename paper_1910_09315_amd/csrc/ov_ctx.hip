@@ -480,8 +480,8 @@ int ov_ctx_create(ov_ctx** out, int device, int precision) {
     ctx->num_cus = prop.multiProcessorCount;
   if (hipMalloc(&ctx->d_status, sizeof(int32_t)) != hipSuccess ||
       hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&ctx->d_stats, sizeof(unsigned long long) * OV_STAT_COUNT) != hipSuccess ||
-      hipMemset(ctx->d_stats, 0, sizeof(unsigned long long) * OV_STAT_COUNT) != hipSuccess) {
+      hipMalloc(&ctx->d_stats, sizeof(unsigned long long) * kStatSlots * kStatStride) != hipSuccess ||
+      hipMemset(ctx->d_stats, 0, sizeof(unsigned long long) * kStatSlots * kStatStride) != hipSuccess) {
     delete ctx;
     return OV_EHIP;
   }
@@ -818,13 +818,18 @@ int ov_status_fetch(ov_ctx* ctx, int32_t* host_status, void* stream) {
 int ov_stats_fetch(ov_ctx* ctx, int64_t* host_out, void* stream) {
   if (!ctx || !host_out) return OV_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  unsigned long long v[OV_STAT_COUNT];
+  static_assert(OV_STAT_COUNT <= kStatStride, "counters fit one slot");
+  unsigned long long v[kStatSlots * kStatStride];
   hipError_t e = hipMemcpyAsync(v, ctx->d_stats, sizeof v, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->d_stats, 0, sizeof v, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(ctx, e, "stats fetch");
-  for (int i = 0; i < OV_STAT_COUNT; ++i) host_out[i] = (int64_t)v[i];
+  for (int i = 0; i < OV_STAT_COUNT; ++i) {
+    unsigned long long sum = 0;
+    for (int k = 0; k < kStatSlots; ++k) sum += v[k * kStatStride + i];
+    host_out[i] = (int64_t)sum;
+  }
   return OV_OK;
 }
 

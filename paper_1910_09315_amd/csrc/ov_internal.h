@@ -99,7 +99,11 @@ struct ov_ctx {
   long long total_tiles = 0;
   ov::GridDev* d_grids = nullptr;
   int32_t* d_status = nullptr;
-  unsigned long long* d_stats = nullptr;  // OV_STAT_* counters (accumulate until ov_stats_fetch)
+  // OV_STAT_* counters (accumulate until ov_stats_fetch), spread over
+  // kStatSlots slots of kStatStride words: a workgroup adds to the slot of
+  // its index, so that the per-workgroup additions of one launch do not all
+  // queue on one address
+  unsigned long long* d_stats = nullptr;
   int32_t* d_warm_cell = nullptr;
   uint8_t* d_warm_grid = nullptr;
   uint8_t* d_warm_tag = nullptr;  // per node: low byte of the stamp of the step that wrote its warm entry
@@ -207,6 +211,13 @@ __device__ __forceinline__ gmem<T>* gp(const T* p) {
 }
 
 typedef double ov_dv2 __attribute__((ext_vector_type(2)));
+constexpr int kStatSlots = 64;
+constexpr int kStatStride = 16;  // 128 bytes: one slot per cache line
+// This workgroup's slot of the statistics counters.
+__device__ __forceinline__ unsigned long long* stat_slot(unsigned long long* stats) {
+  return stats + (blockIdx.x & (kStatSlots - 1)) * kStatStride;
+}
+
 typedef float ov_fv4 __attribute__((ext_vector_type(4)));
 typedef int ov_iv4 __attribute__((ext_vector_type(4)));
 

@@ -168,6 +168,15 @@ __device__ __forceinline__ bool cell_valid(const GridDev& G, const uint8_t* fl, 
   return ok;
 }
 
+// The same test on flags already loaded (the walk fetches a cell's corner
+// flags together with its corner coordinates: one memory round trip).
+__device__ __forceinline__ bool corners_valid(const uint8_t cf[8]) {
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ok &= (cf[c] & 3) != kHole;
+  return ok;
+}
+
 __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, bool& clamped) {
   int w = v + dv;
   if (periodic) {
@@ -198,6 +207,9 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
   for (int stepn = 0; stepn < max_walk; ++stepn) {
     ++visited;
     CellMap<T> m;
+    uint8_t cf[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) cf[c] = fl[corner_node(G, ci, cj, ck, c)];
     load_cell<T>(G, ci, cj, ck, xi, m);
     T cond = 0, inv_norm = 0;
     bool conv =
@@ -217,7 +229,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
       const T es = (T)(2.0 * 1.7320508075688772 * perr) * inv_norm;
       if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
-        return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
+        return corners_valid(cf) ? kFound : kToScan;
       }
       if (mg > -((sure ? (T)kMixedMargin : (T)kClearlyOutside) + es)) {
         cell = here;
@@ -226,7 +238,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     } else {
       if (conv && inside<T>(s, (T)kSTol)) {
         cell = here;
-        return cell_valid(G, fl, ci, cj, ck) ? kFound : kToScan;
+        return corners_valid(cf) ? kFound : kToScan;
       }
     }
     if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
@@ -773,7 +785,6 @@ __global__ void __launch_bounds__(BS)
   __shared__ int list_q[BS], list_st[BS];
   __shared__ int nlist;
   __shared__ ScanLds S;
-  __shared__ unsigned long long work[3];  // cells walked, Newton iterations, scan candidates
   // the grid table, staged in LDS (dynamic: ngrids records): its fields are
   // read at every candidate grid and walk
   extern __shared__ unsigned long long grid_lds[];
@@ -782,15 +793,23 @@ __global__ void __launch_bounds__(BS)
     grid_lds[i] = ((const unsigned long long*)grids_g)[i];
   const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  // this thread's first query, read before the count is known (entries up
+  // to the capacity are allocated): one memory round trip less on every
+  // query's path
+  const long long q_first = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int first_A = 0, first_m = 0;
+  if (q_first < cap) {
+    first_A = q_grid[q_first];
+    first_m = q_node[q_first];
+  }
   const uint8_t now = (uint8_t)*warm.stamp;
-  if (threadIdx.x < 3) work[threadIdx.x] = 0;
   const long long n = min(*d_count, cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (count_out) *count_out = *d_count;
-    atomicAdd(&stats[OV_STAT_BACK_CALLS], 1ULL);
+    atomicAdd(&stat_slot(stats)[OV_STAT_BACK_CALLS], 1ULL);
   }
   int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
-  unsigned long long my_cells = 0;
+  unsigned int my_cells = 0;
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
     if (threadIdx.x == 0) nlist = 0;
     __syncthreads();  // (also orders the pose staging before the first use)
@@ -803,15 +822,19 @@ __global__ void __launch_bounds__(BS)
     long long key = 0;
     int my_grid = 0;
     if (mine) {
-      const int A = q_grid[q];
+      const bool first = base == (long long)blockIdx.x * blockDim.x;
+      const int A = first ? first_A : q_grid[q];
+      const int qm = first ? first_m : q_node[q];
       my_grid = A;
+      // the warm-start entry, read beside the node's coordinates
+      const long long wkey = grids[A].node_off + qm;
+      const int wcell = warm.use ? warm.cell[wkey] : -1;
       T o[3];
-      transform_node<T>(grids[A], sp + 12 * A, q_node[q], o);
+      transform_node<T>(grids[A], sp + 12 * A, qm, o);
       qx[q] = o[0];
       qx[cap + q] = o[1];
       qx[2 * cap + q] = o[2];
-      const Query Q =
-          make_query<T>(grids, ngrids, sp, flags, A, q_node[q], (double)o[0], (double)o[1], (double)o[2], false);
+      const Query Q = make_query<T>(grids, ngrids, sp, flags, A, qm, (double)o[0], (double)o[1], (double)o[2], false);
       key = Q.key;
       int defer = 0, defer_t = 0;
       if (!Q.finite) {
@@ -824,20 +847,25 @@ __global__ void __launch_bounds__(BS)
           const GridDev& G = grids[B];
           double xi[3];
           if (!to_body(G, sp + 12 * B, Q, xi)) continue;
-          const int rep = gp(G.brep)[bin_of(G, xi)];
           int seed = -1;
-          if (wg == B) {
-            int wc = warm.cell[Q.key];
-            if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
+          if (wg == B && wcell >= 0 && (long long)wcell < G.ncells) seed = wcell;
+          // the control cell's seed only when there is no warm seed, or
+          // for the second walk after a failed warm one
+          int rep = -1;
+          if (seed < 0) {
+            rep = gp(G.brep)[bin_of(G, xi)];
+            if (rep < 0) continue;
           }
-          if (seed < 0 && rep < 0) continue;
           int cell = seed >= 0 ? seed : rep;
           T s[3];
           const uint8_t* fl = flags + G.node_off;
           int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
-          if (r == kToScan && seed >= 0 && rep >= 0 && rep != seed) {
-            cell = rep;
-            r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
+          if (r == kToScan && seed >= 0) {
+            rep = gp(G.brep)[bin_of(G, xi)];
+            if (rep >= 0 && rep != seed) {
+              cell = rep;
+              r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
+            }
           }
           int how = OV_Q_FOUND;
           if (sizeof(T) == 4 && r == kDoubt) {
@@ -954,13 +982,22 @@ __global__ void __launch_bounds__(BS)
     }
     __syncthreads();  // nlist and the list are rebuilt for the next range
   }
-  // the block's work, one device atomic per counter
-  if (my_cells) atomicAdd(&work[0], my_cells);
-  if (my_iters) atomicAdd(&work[1], (unsigned long long)my_iters);
-  if (my_cands) atomicAdd(&work[2], (unsigned long long)my_cands);
-  __syncthreads();
-  if (threadIdx.x < 3 && work[threadIdx.x])
-    atomicAdd(&stats[OV_STAT_SEARCH_CELLS + threadIdx.x], work[threadIdx.x]);
+  // the wavefront's work, summed across its lanes with shuffles (an atomic
+  // on a value that differs per lane compiles to a serial loop over the
+  // lanes), then one device atomic per counter from its first lane
+  unsigned int w0 = (unsigned int)my_cells, w1 = (unsigned int)my_iters, w2 = (unsigned int)my_cands;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    w0 += __shfl_xor(w0, o, 64);
+    w1 += __shfl_xor(w1, o, 64);
+    w2 += __shfl_xor(w2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* slot = stat_slot(stats);
+    if (w0) atomicAdd(&slot[OV_STAT_SEARCH_CELLS], (unsigned long long)w0);
+    if (w1) atomicAdd(&slot[OV_STAT_NEWTON_ITERS], (unsigned long long)w1);
+    if (w2) atomicAdd(&slot[OV_STAT_SCAN_CANDIDATES], (unsigned long long)w2);
+  }
 }
 
 static Warm warm_of(ov_ctx* ctx, int slot) {

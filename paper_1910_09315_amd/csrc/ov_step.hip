@@ -274,8 +274,8 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
     }
     coff[ngrids] = c;
     if (blockIdx.x == 0) {
-      atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)L.off[ngrids]);
-      atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+      atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)L.off[ngrids]);
+      atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_CALLS], 1ULL);
     }
   }
   __syncthreads();
@@ -572,7 +572,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   }
   int nr = n;
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
-  if ((t & 63) == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+  if ((t & 63) == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
   if (__syncthreads_or(hole) && t < 125)
     mark_near(t, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
               near_list, near_count);
@@ -652,7 +652,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
   }
   int nr = n;
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
-  if (lane == 0) atomicAdd(&stats[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
+  if (lane == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
   if (__any(hole))
     for (int e = lane; e < 125; e += 64)
       mark_near(e, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
   stage_tile_geo(TG, grids, ngrids);
   holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
   const unsigned int stamp = *d_stamp;
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[OV_STAT_HOLECUT_CALLS], 1ULL);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_CALLS], 1ULL);
   const long long nb = gridDim.x;
   for (long long r0 = 0; r0 < nsub; r0 += 256 * nb) {
     if (threadIdx.x == 0) c_n = 0;
