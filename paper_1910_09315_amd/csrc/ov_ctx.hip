@@ -686,7 +686,7 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (1 + kSlots)), "hipMalloc stamps");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * nt), "hipMalloc tile holes");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
-  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int32_t) * kSlots * nt), "hipMalloc near lists");
+  HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int4) * kSlots * nt), "hipMalloc near lists");
   HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t) * kSlots), "hipMalloc near counts");
   HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (1 + kSlots), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * nt, s), "tile hole init");

@@ -125,7 +125,7 @@ struct ov_ctx {
   unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`
   unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
-  int32_t* d_near_list = nullptr;             // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
+  int4* d_near_list = nullptr;                // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;            // per slot
   uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
   unsigned int* d_chunk_stamp = nullptr;      // per chunk: stamp if on this step's chunk list

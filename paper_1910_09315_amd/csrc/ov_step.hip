@@ -372,17 +372,17 @@ __device__ __forceinline__ int reach_tile(int t, int which, int n, int size, boo
   return v / size;
 }
 
-// Puts combination e (< 125) of the reach tiles of tile (ti, tj, tk) on the
-// near list, once per stamp.
-__device__ __forceinline__ void mark_near(int e, int ti, int tj, int tk, int ni, int nj, int nk, int per, int tiles_i,
+// Puts combination e (< 125) of the reach tiles of tile (ti, tj, tk) of
+// grid g on the near list, once per stamp, as its (grid, tile i, j, k).
+__device__ __forceinline__ void mark_near(int e, int g, int ti, int tj, int tk, int ni, int nj, int nk, int per, int tiles_i,
                                           int tiles_j, long long tile_off, unsigned int stamp,
-                                          unsigned int* __restrict__ tile_near, int32_t* __restrict__ near_list,
+                                          unsigned int* __restrict__ tile_near, int4* __restrict__ near_list,
                                           int32_t* __restrict__ near_count) {
   const int x = reach_tile(ti, e % 5, ni, kTileI, per & 1);
   const int y = reach_tile(tj, (e / 5) % 5, nj, kTileJ, per & 2);
   const int z = reach_tile(tk, e / 25, nk, kTileK, per & 4);
   const long long n = tile_off + x + (long long)tiles_i * (y + (long long)tiles_j * z);
-  if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = (int32_t)n;
+  if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = make_int4(g, x, y, z);
 }
 
 // Which blank regions may reach sub-tile `sub` (bit B set: grid B's region
@@ -521,7 +521,7 @@ template <typename CT>
 __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
                                            uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                            unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
-                                           int32_t* __restrict__ near_list, int32_t* __restrict__ near_count,
+                                           int4* __restrict__ near_list, int32_t* __restrict__ near_count,
                                            unsigned long long* __restrict__ stats) {
   const int4 ti = tile_info[sub / kSubPerTile];
   const int A = uniform_i32(ti.x);
@@ -574,7 +574,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
   if ((t & 63) == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
   if (__syncthreads_or(hole) && t < 125)
-    mark_near(t, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+    mark_near(t, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
               near_list, near_count);
 }
 
@@ -587,7 +587,7 @@ template <typename CT>
 __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
                                           uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                           unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
-                                          int32_t* __restrict__ near_list, int32_t* __restrict__ near_count,
+                                          int4* __restrict__ near_list, int32_t* __restrict__ near_count,
                                           unsigned long long* __restrict__ stats) {
   const int lane = threadIdx.x & 63;
   const int4 ti = tile_info[sub / kSubPerTile];
@@ -655,7 +655,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
   if (lane == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
   if (__any(hole))
     for (int e = lane; e < 125; e += 64)
-      mark_near(e, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+      mark_near(e, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
                 near_list, near_count);
 }
 
@@ -674,7 +674,7 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
                                                     const int4* __restrict__ tile_info, long long nsub,
                                                     const unsigned int* __restrict__ d_stamp,
                                                     unsigned int* __restrict__ tile_near,
-                                                    int32_t* __restrict__ near_list,
+                                                    int4* __restrict__ near_list,
                                                     int32_t* __restrict__ near_count,
                                                     unsigned long long* __restrict__ stats) {
   __shared__ HoleLds L;
@@ -721,7 +721,7 @@ __global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restri
                                                         const int4* __restrict__ tile_info, long long total_tiles,
                                                         const unsigned int* __restrict__ d_stamp,
                                                         unsigned int* __restrict__ tile_near,
-                                                        int32_t* __restrict__ near_list,
+                                                        int4* __restrict__ near_list,
                                                         int32_t* __restrict__ near_count) {
   const unsigned int stamp = *d_stamp;
   for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile < total_tiles;
@@ -731,7 +731,7 @@ __global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restri
     const GeomR G(grids[info.x]);
     const int ti = info.y, tj = info.z, tk = info.w;
     for (int e = 0; e < 125; ++e)
-      mark_near(e, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near, near_list,
+      mark_near(e, info.x, ti, tj, tk, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near, near_list,
                 near_count);
   }
 }
@@ -762,7 +762,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   const long long nt = ctx->total_tiles;
   unsigned int* counter = ctx->d_stamp;
   unsigned int* st = ctx->d_stamp + 1 + slot;
-  int32_t* nl = ctx->d_near_list + slot * std::max(1LL, nt);
+  int4* nl = ctx->d_near_list + slot * std::max(1LL, nt);
   int32_t* nc = ctx->d_near_count + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
   const long long nsc = kSuperSlots * ctx->nsuper;
@@ -817,10 +817,24 @@ __device__ __forceinline__ int wrap_or_out(int v, int n, bool periodic) {
   return v < 0 ? v + n : v;
 }
 
+// Byte-wise minimum of four 7-bit values per word: bit 7 of each byte of
+// (a | 0x80..) - b is set exactly where a >= b (no borrow crosses a byte,
+// every byte of a | 0x80.. exceeding every byte of b), which selects b there.
+__device__ __forceinline__ uint32_t bytemin7(uint32_t a, uint32_t b) {
+  const uint32_t ge = (((a | 0x80808080u) - b) & 0x80808080u) >> 7;
+  const uint32_t m = ge * 0xFFu;
+  return (b & m) | (a & ~m);
+}
+
+// Bytes d .. d+3 of the little-endian pair (lo, hi), 0 <= d <= 4.
+__device__ __forceinline__ uint32_t window4(uint32_t lo, uint32_t hi, int d) {
+  return d == 0 ? lo : d == 4 ? hi : __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)d);
+}
+
 template <int NF>
 __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict__ grids, int ngrids,
-                                                     uint8_t* __restrict__ flags, const int4* __restrict__ tile_info,
-                                                     const int32_t* __restrict__ near_list,
+                                                     uint8_t* __restrict__ flags,
+                                                     const int4* __restrict__ near_list,
                                                      const int32_t* __restrict__ near_count,
                                                      const unsigned int* __restrict__ d_stamp,
                                                      const uint8_t* __restrict__ chunk_static,
@@ -828,20 +842,30 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
                                                      int32_t* __restrict__ chunk_list,
                                                      int32_t* __restrict__ chunk_list_count, long long n_static) {
   constexpr int H = NF > 0 ? NF : 1;  // LDS sizes (unused when NF = 0)
-  constexpr int EI = kTileI + 2 * H, EJ = kTileJ + 2 * H, EK = kTileK + 2 * H;
+  constexpr int EJ = kTileJ + 2 * H, EK = kTileK + 2 * H;
   constexpr int NROW = EJ * EK * 16, NHALO = EJ * EK * 2 * H;
-  __shared__ uint8_t a[EK][EJ][EI];
-  __shared__ uint8_t b[EK][EJ][kTileI];
-  __shared__ uint8_t c[EK][kTileJ][kTileI];
+  // staged rows: NF halo bytes, the 64 tile bytes, NF halo bytes, padded to
+  // whole words; values are hole causes (< 63) or 0x7F for "no hole", so
+  // that the min filter runs on 4 bytes per word (bytemin7)
+  constexpr int EIW = (kTileI + 2 * H + 3) / 4;  // words per staged row
+  static_assert(kTileI == 64, "16 words per tile row");
+  __shared__ uint32_t a32[EK * EJ * EIW];
+  __shared__ uint32_t b32[EK * EJ * 16];
+  __shared__ uint32_t c32[EK * kTileJ * 16];
+  uint8_t* const a8 = reinterpret_cast<uint8_t*>(a32);
   __shared__ TileGeo TG[kMaxGrids];
   __shared__ long long noffs[kMaxGrids];
+  // the count, the stamp and this block's first entry are read together
+  // with the grid staging (the list is allocated for every tile, and the
+  // grid never has more blocks than tiles)
+  const int ntl = *near_count;
+  const unsigned int stamp = *d_stamp;
+  const int4 first_info = near_list[blockIdx.x];
   stage_tile_geo(TG, grids, ngrids);
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) noffs[g] = grids[g].node_off;
   __syncthreads();
-  const int ntl = *near_count;
-  const unsigned int stamp = *d_stamp;
   for (int idx = blockIdx.x; idx < ntl; idx += gridDim.x) {
-    const int4 info = tile_info[near_list[idx]];
+    const int4 info = idx == (int)blockIdx.x ? first_info : near_list[idx];
     const TileGeo G = TG[info.x];
     const long long noff = noffs[info.x];
     const int i0 = info.y * kTileI, j0 = info.z * kTileJ, k0 = info.w * kTileK;
@@ -924,10 +948,10 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint8_t f = (uint8_t)(raw[it] >> (8 * q));
-        v[q] = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
-        a[z][y][NF + part * 4 + q] = v[q];
+        v[q] = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)0x7F;
+        a8[(z * EJ + y) * 4 * EIW + NF + part * 4 + q] = v[q];
       }
-      any_hole |= (v[0] & v[1] & v[2] & v[3]) != 255;
+      any_hole |= (v[0] & v[1] & v[2] & v[3]) != 0x7F;
     }
 #pragma unroll
     for (int it = 0; it < NHIT; ++it) {
@@ -937,39 +961,59 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
       const int y = row % EJ, z = row / EJ;
       const int x = h < NF ? h : kTileI + h;
       const uint8_t f = hraw[it];
-      const uint8_t v = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)255;
-      a[z][y][x] = v;
-      any_hole |= v != 255;
+      const uint8_t v = ((f & 3) == kHole) ? (uint8_t)(f >> 2) : (uint8_t)0x7F;
+      a8[(z * EJ + y) * 4 * EIW + x] = v;
+      any_hole |= v != 0x7F;
     }
     // no hole within nf of the tile: nothing to mark (same in every thread)
     if (!__syncthreads_or(any_hole)) continue;
-    for (int e = threadIdx.x; e < kTileI * EJ * EK; e += blockDim.x) {
-      int x = e & 63, y = (e >> 6) % EJ, z = (e >> 6) / EJ;
-      uint8_t m = 255;
+    // separable min filter over the (2 nf + 1)^3 box, 4 nodes per word, with
+    // fixed trip counts so that each pass's LDS reads are issued together:
+    // along i (windows of the staged row), along j, along k
+    constexpr int N1 = EK * EJ * 16, N2 = EK * kTileJ * 16, N3 = kTileK * kTileJ * 16;
 #pragma unroll
-      for (int d = 0; d <= 2 * NF; ++d) m = min(m, a[z][y][x + d]);
-      b[z][y][x] = m;
+    for (int it = 0; it < (N1 + 255) / 256; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= N1) break;
+      const int row = e >> 4, w = e & 15;
+      const uint32_t* r = a32 + row * EIW + w;
+      const uint32_t w0 = r[0], w1 = r[1], w2 = (2 * NF > 4) ? r[2] : 0u;
+      uint32_t m = w0;
+#pragma unroll
+      for (int d = 1; d <= 2 * NF; ++d) m = bytemin7(m, d <= 4 ? window4(w0, w1, d) : window4(w1, w2, d - 4));
+      b32[e] = m;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTileI * kTileJ * EK; e += blockDim.x) {
-      int x = e & 63, y = (e >> 6) & 7, z = e >> 9;
-      uint8_t m = 255;
 #pragma unroll
-      for (int d = 0; d <= 2 * NF; ++d) m = min(m, b[z][y + d][x]);
-      c[z][y][x] = m;
+    for (int it = 0; it < (N2 + 255) / 256; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e >= N2) break;
+      const int w = e & 15, y = (e >> 4) & 7, z = e >> 7;
+      uint32_t m = b32[(z * EJ + y) * 16 + w];
+#pragma unroll
+      for (int d = 1; d <= 2 * NF; ++d) m = bytemin7(m, b32[(z * EJ + y + d) * 16 + w]);
+      c32[e] = m;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTileI * kTileJ * kTileK; e += blockDim.x) {
-      int x = e & 63, y = (e >> 6) & 7, z = e >> 9;
-      int i = i0 + x, j = j0 + y, k = k0 + z;
-      if (i >= G.ni || j >= G.nj || k >= G.nk) continue;
-      if (a[z + NF][y + NF][x + NF] != 255) continue;  // a hole (staged above)
-      uint8_t cause = 255;
 #pragma unroll
-      for (int d = 0; d <= 2 * NF; ++d) cause = min(cause, c[z + d][y][x]);
-      if (cause == 255) continue;
-      // buffer causes are grid ids < 63, so they win over an outer-boundary cause
-      fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)] = (uint8_t)(kFringe | (cause << 2));
+    for (int it = 0; it < N3 / 256; ++it) {
+      const int e = threadIdx.x + it * 256;
+      const int w = e & 15, y = (e >> 4) & 7, z = e >> 7;
+      uint32_t cause = c32[(z * kTileJ + y) * 16 + w];
+#pragma unroll
+      for (int d = 1; d <= 2 * NF; ++d) cause = bytemin7(cause, c32[((z + d) * kTileJ + y) * 16 + w]);
+      if (cause == 0x7F7F7F7Fu) continue;  // no hole within reach of these 4 nodes
+      const int j = j0 + y, k = k0 + z;
+      if (j >= G.nj || k >= G.nk) continue;
+      const uint8_t* ctr = a8 + ((z + NF) * EJ + (y + NF)) * 4 * EIW + NF + 4 * w;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * w + q;
+        const uint32_t cq = (cause >> (8 * q)) & 0xFFu;
+        if (i >= G.ni || cq == 0x7F || ctr[q] != 0x7F) continue;  // out of range, none in reach, or a hole
+        // buffer causes are grid ids < 63, so they win over an outer-boundary cause
+        fl[(long long)i + (long long)G.ni * ((long long)j + (long long)G.nj * k)] = (uint8_t)(kFringe | (cq << 2));
+      }
     }
     __syncthreads();
   }
@@ -977,7 +1021,7 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot) {
   const int ng = (int)ctx->grids.size();
-  const int32_t* nl = ctx->d_near_list + slot * std::max(1LL, ctx->total_tiles);
+  const int4* nl = ctx->d_near_list + slot * std::max(1LL, ctx->total_tiles);
   const int32_t* nc = ctx->d_near_count + slot;
   const unsigned int* st = ctx->d_stamp + 1 + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
@@ -985,7 +1029,7 @@ hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int
   long long g = std::max(1LL, std::min<long long>(ctx->total_tiles,
                                                     (long long)ctx->num_cus * (ctx->persist > 0 ? ctx->persist : 4)));
 #define OV_FRINGE_ARGS                                                                                            \
-  ctx->d_grids, ng, flags, ctx->d_tile_info, nl, nc, st, ctx->d_chunk_static, ctx->d_chunk_stamp, ctx->d_chunk_list, \
+  ctx->d_grids, ng, flags, nl, nc, st, ctx->d_chunk_static, ctx->d_chunk_stamp, ctx->d_chunk_list, \
       clc, ctx->n_static_chunks
   switch (nf) {
     case 0:
