@@ -1126,10 +1126,13 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
                                                                    long long n_static,
                                                                    const unsigned int* __restrict__ d_stamp) {
   __shared__ int red[kCompactThreads / 64];
+  // the list length, the stamp and this block's first entry in one round
+  // trip (the list has room for every chunk; the grid has no more blocks)
   const long long nl = n_static + *chunk_list_count;
   const unsigned int stamp = *d_stamp;
+  const int32_t first = chunk_list[blockIdx.x];
   for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
-    const long long ch = chunk_list[e];
+    const long long ch = e == (long long)blockIdx.x ? first : chunk_list[e];
     uint32_t mask;
     int cnt = count_fringe16(flags, ch * kCompactChunk + threadIdx.x * 16, total, mask);
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
@@ -1204,6 +1207,12 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
   __shared__ int wsum[kCompactThreads / 64];
   __shared__ long long off[kMaxGrids + 1];
   extern __shared__ long long soff[];  // FUSED: nsuper + 1 superchunk offsets
+  // read up front, beside the superchunk counts: the list length, the stamp
+  // and this block's first entry (the list has room for every chunk; the
+  // grid has no more blocks)
+  const long long nl = n_static + *chunk_list_count;
+  const unsigned int stamp = *d_stamp;
+  const int32_t first = chunk_list[blockIdx.x];
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) off[g] = grids[g].node_off;
   if (threadIdx.x == 0) off[ngrids] = total;
   if (FUSED) {
@@ -1216,10 +1225,13 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long nl = n_static + *chunk_list_count;
-  const unsigned int stamp = *d_stamp;
   for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
-    const long long ch = chunk_list[e];
+    const long long ch = e == (long long)blockIdx.x ? first : chunk_list[e];
+    // the chunk's flags, read with its counts (before the test for an empty
+    // chunk, so that both loads are in flight together)
+    const long long n0 = ch * kCompactChunk + threadIdx.x * 16;
+    uint32_t mask;
+    const int cnt = count_fringe16(flags, n0, total, mask);
     // this step's counts of the chunks of ch's superchunk below ch (every
     // wavefront forms the same sum)
     const long long c = ch - ch % kSuperChunk + lane;
@@ -1229,9 +1241,6 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
     const long long base = (FUSED ? soff[ch / kSuperChunk] : super_offsets[ch / kSuperChunk]) + below;
     const unsigned long long own = counts[ch];
     if ((unsigned int)own == 0u || base >= capacity) continue;  // nothing to write (same in every thread)
-    long long n0 = ch * kCompactChunk + threadIdx.x * 16;
-    uint32_t mask;
-    int cnt = count_fringe16(flags, n0, total, mask);
     // inclusive wave scan
     int inc = cnt;
     for (int o = 1; o < 64; o <<= 1) {
