@@ -427,9 +427,9 @@ def main():
                     help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
-    ap.add_argument("--time-every", type=int, default=16,
-                    help="native executor: time the roofline kernel of every N-th timed step with events (each "
-                         "costs device time)")
+    ap.add_argument("--time-every", type=int, default=48,
+                    help="native executor: time the roofline kernel of every N-th step with events, run alone (the "
+                         "executor drains the other streams around it: each sample costs about 1.5 steps)")
     ap.add_argument("--compare", default="C4",
                     help="also time this workload (the mixed-precision batched form) and report both ('' to skip)")
     ap.add_argument("--roofline", choices=("back", "holecut", "none"), default="back",

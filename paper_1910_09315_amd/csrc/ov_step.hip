@@ -861,6 +861,7 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
   const int ntl = *near_count;
   const unsigned int stamp = *d_stamp;
   const int4 first_info = near_list[blockIdx.x];
+  if ((int)blockIdx.x >= ntl) return;  // no tile for this block (same in every thread)
   stage_tile_geo(TG, grids, ngrids);
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) noffs[g] = grids[g].node_off;
   __syncthreads();
@@ -1215,7 +1216,8 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
   const int32_t first = chunk_list[blockIdx.x];
   for (int g = threadIdx.x; g < ngrids; g += blockDim.x) off[g] = grids[g].node_off;
   if (threadIdx.x == 0) off[ngrids] = total;
-  if (FUSED) {
+  // (a block without a listed chunk skips the prefix; block 0 stores the count)
+  if (FUSED && ((long long)blockIdx.x < nl || blockIdx.x == 0)) {
     block_super_prefix(super_counts, nsuper, soff);
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
