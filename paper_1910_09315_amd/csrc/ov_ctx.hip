@@ -250,9 +250,9 @@ __global__ void k_fill_u8(uint8_t* p, long long n, uint8_t v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
 }
-__global__ void k_fill_u64(unsigned long long* p, long long n) {
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v = 0ULL) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = 0ULL;
+    p[i] = v;
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
@@ -508,9 +508,7 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_grids);
   (void)hipFree(ctx->d_status);
   (void)hipFree(ctx->d_stats);
-  (void)hipFree(ctx->d_warm_cell);
-  (void)hipFree(ctx->d_warm_grid);
-  (void)hipFree(ctx->d_warm_tag);
+  (void)hipFree(ctx->d_warm);
   (void)hipFree(ctx->d_tile_sphere);
   (void)hipFree(ctx->d_tile_info);
   (void)hipFree(ctx->d_base_flags);
@@ -623,11 +621,8 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   HIPCHK(hipMalloc(&ctx->d_grids, sizeof(GridDev) * table.size()), "hipMalloc grid table");
   HIPCHK(hipMemcpy(ctx->d_grids, table.data(), sizeof(GridDev) * table.size(), hipMemcpyHostToDevice),
          "grid table copy");
-  HIPCHK(hipMalloc(&ctx->d_warm_cell, sizeof(int32_t) * total), "hipMalloc warm cells");
-  HIPCHK(hipMalloc(&ctx->d_warm_grid, total), "hipMalloc warm grids");
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_grid, total, (uint8_t)255);
-  HIPCHK(hipMalloc(&ctx->d_warm_tag, total), "hipMalloc warm tags");
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm_tag, total, (uint8_t)0);
+  HIPCHK(hipMalloc(&ctx->d_warm, sizeof(unsigned long long) * total), "hipMalloc warm-start records");
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(total)), dim3(256), 0, s, ctx->d_warm, total, kWarmEmpty);
   HIPCHK(hipMalloc(&ctx->d_tile_sphere, sizeof(double4) * kSubPerTile * std::max(1LL, ctx->total_tiles)),
          "hipMalloc sub-tile spheres");
   for (auto& g : ctx->grids) {
@@ -796,8 +791,8 @@ int ov_reset_history(ov_ctx* ctx, void* stream) {
   if (!ctx) return OV_EINVAL;
   if (!ctx->finalized) return fail(ctx, OV_ESTATE, "ov_reset_history before ov_finalize");
   long long total = ctx->node_off.back();
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream, ctx->d_warm_grid,
-                     total, (uint8_t)255);
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream, ctx->d_warm, total,
+                     kWarmEmpty);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? OV_OK : hip_fail(ctx, e, "reset history");
 }

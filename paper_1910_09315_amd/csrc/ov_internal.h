@@ -104,9 +104,11 @@ struct ov_ctx {
   // its index, so that the per-workgroup additions of one launch do not all
   // queue on one address
   unsigned long long* d_stats = nullptr;
-  int32_t* d_warm_cell = nullptr;
-  uint8_t* d_warm_grid = nullptr;
-  uint8_t* d_warm_tag = nullptr;  // per node: low byte of the stamp of the step that wrote its warm entry
+  // per node, one 8-byte warm-start record: bits 0-31 the donor cell of its
+  // last query, bits 32-39 the donor grid (255: none), bits 40-47 the low
+  // byte of the stamp of the step that wrote it (one load and one store per
+  // query instead of three of each)
+  unsigned long long* d_warm = nullptr;
   double4* d_tile_sphere = nullptr;  // per sub-tile: body-frame bounding sphere (centre, radius; -inf if empty)
   int4* d_tile_info = nullptr;       // per node tile: (grid, ti, tj, tk)
   // The flags every step starts from (field everywhere, fringe on the fixed
@@ -211,6 +213,8 @@ __device__ __forceinline__ gmem<T>* gp(const T* p) {
 }
 
 typedef double ov_dv2 __attribute__((ext_vector_type(2)));
+// The warm-start record of a node with no history.
+constexpr unsigned long long kWarmEmpty = 0x000000FFFFFFFFFFULL;  // cell -1, grid 255, stamp 0
 constexpr int kStatSlots = 64;
 constexpr int kStatStride = 16;  // 128 bytes: one slot per cache line
 // This workgroup's slot of the statistics counters.
@@ -283,19 +287,22 @@ __device__ __forceinline__ void cell_box(const GridDev& g, long long cell, doubl
 
 // Offset of node m of grid G from the grid's frame centre in inertial axes,
 // o = R X (pose p: R row-major, then the centre): FP64 from the FP64
-// coordinates, or FP32 from the FP32 shadows and the rounded pose.
+// coordinates, or FP32 from their FP32 roundings (the values of the FP32
+// shadows) and the rounded pose. The coordinates come from the packed
+// gather layout: one 32-byte record instead of three arrays.
 template <typename T>
 __device__ __forceinline__ void transform_node(const GridDev& G, const double* p, long long m, T o[3]) {
+  double X, Y, Z;
+  load_xyz(G, m, X, Y, Z);
   if (sizeof(T) == 8) {
-    const double X = gp(G.X)[m], Y = gp(G.Y)[m], Z = gp(G.Z)[m];
     o[0] = (T)(p[0] * X + p[1] * Y + p[2] * Z);
     o[1] = (T)(p[3] * X + p[4] * Y + p[5] * Z);
     o[2] = (T)(p[6] * X + p[7] * Y + p[8] * Z);
   } else {
-    const float X = gp(G.Xf)[m], Y = gp(G.Yf)[m], Z = gp(G.Zf)[m];
-    o[0] = (T)((float)p[0] * X + (float)p[1] * Y + (float)p[2] * Z);
-    o[1] = (T)((float)p[3] * X + (float)p[4] * Y + (float)p[5] * Z);
-    o[2] = (T)((float)p[6] * X + (float)p[7] * Y + (float)p[8] * Z);
+    const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
+    o[0] = (T)((float)p[0] * Xf + (float)p[1] * Yf + (float)p[2] * Zf);
+    o[1] = (T)((float)p[3] * Xf + (float)p[4] * Yf + (float)p[5] * Zf);
+    o[2] = (T)((float)p[6] * Xf + (float)p[7] * Yf + (float)p[8] * Zf);
   }
 }
 

@@ -446,23 +446,28 @@ __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp,
 }
 
 // Warm-start history: per node, the donor (grid, cell) of its last query
-// and the low byte of the stamp of the step that wrote it. A node that was
-// not a query in the last steps (one that just entered the buffer layer, say)
-// would start its walk from a donor long out of date; its entry is then
-// ignored and the walk starts from the control cell's seed.
+// and the low byte of the stamp of the step that wrote it, in one 8-byte
+// record. A node that was not a query in the last steps (one that just
+// entered the buffer layer, say) would start its walk from a donor long out
+// of date; its entry is then ignored and the walk starts from the control
+// cell's seed.
 struct Warm {
-  int32_t* cell;
-  uint8_t* grid;
-  uint8_t* tag;
+  unsigned long long* rec;
   const unsigned int* stamp;  // the running step's stamp
   int use;
 };
 constexpr int kWarmMaxAge = 2;  // steps
 
-__device__ __forceinline__ int warm_grid_of(const Warm& w, long long key, uint8_t now) {
-  if (!w.use) return 255;
-  const uint8_t age = (uint8_t)(now - w.tag[key]);
-  return age <= kWarmMaxAge ? (int)w.grid[key] : 255;
+// The node's warm seed: grid (255: none) and cell.
+__device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t now, int& grid, int& cell) {
+  grid = 255;
+  cell = -1;
+  if (!w.use) return;
+  const unsigned long long r = gp(w.rec)[key];
+  const uint8_t age = (uint8_t)(now - (uint8_t)(r >> 40));
+  if (age > kWarmMaxAge) return;
+  grid = (int)((r >> 32) & 0xFF);
+  cell = (int)(uint32_t)r;
 }
 
 template <typename T>
@@ -475,9 +480,8 @@ __device__ __forceinline__ void write_result(long long q, long long cap, long lo
   s_out[q] = s[0];
   s_out[cap + q] = s[1];
   s_out[2 * cap + q] = s[2];
-  warm.grid[key] = grid < 0 ? (uint8_t)255 : (uint8_t)grid;
-  warm.cell[key] = cell;
-  warm.tag[key] = now;
+  warm.rec[key] = (unsigned long long)(uint32_t)cell | ((unsigned long long)(grid < 0 ? 255u : (unsigned)grid) << 32) |
+                  ((unsigned long long)now << 40);
 }
 
 // Markers left in donor_grid between the passes of one search call; status
@@ -514,7 +518,8 @@ __global__ void __launch_bounds__(256)
     if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
-      const int wg = warm_grid_of(warm, Q.key, now);
+      int wg, wc;
+      warm_read(warm, Q.key, now, wg, wc);
       for (int t = -2; t < ngrids; ++t) {
         const int B = candidate_at(t, Q.A, Q.first);
         if (B < 0) continue;
@@ -524,10 +529,7 @@ __global__ void __launch_bounds__(256)
         // seeds: last step's donor cell, then the control cell's lowest cell
         const int rep = gp(G.brep)[bin_of(G, xi)];
         int seed = -1;
-        if (wg == B) {
-          int wc = warm.cell[Q.key];
-          if (wc >= 0 && (long long)wc < G.ncells) seed = wc;
-        }
+        if (wg == B && wc >= 0 && (long long)wc < G.ncells) seed = wc;
         if (seed < 0 && rep < 0) continue;  // no cell reaches this control cell
         int cell = seed >= 0 ? seed : rep;
         T s[3];
@@ -827,8 +829,8 @@ __global__ void __launch_bounds__(BS)
       const int qm = first ? first_m : q_node[q];
       my_grid = A;
       // the warm-start entry, read beside the node's coordinates
-      const long long wkey = grids[A].node_off + qm;
-      const int wcell = warm.use ? warm.cell[wkey] : -1;
+      int wg, wcell;
+      warm_read(warm, grids[A].node_off + qm, now, wg, wcell);
       T o[3];
       transform_node<T>(grids[A], sp + 12 * A, qm, o);
       qx[q] = o[0];
@@ -840,7 +842,6 @@ __global__ void __launch_bounds__(BS)
       if (!Q.finite) {
         atomicOr(dev_status, OV_DEV_NONFINITE);
       } else {
-        const int wg = warm_grid_of(warm, Q.key, now);
         for (int t = -2; t < ngrids; ++t) {
           const int B = candidate_at(t, Q.A, Q.first);
           if (B < 0) continue;
@@ -1001,7 +1002,7 @@ __global__ void __launch_bounds__(BS)
 }
 
 static Warm warm_of(ov_ctx* ctx, int slot) {
-  return Warm{ctx->d_warm_cell, ctx->d_warm_grid, ctx->d_warm_tag, ctx->d_stamp + 1 + slot, ctx->warm};
+  return Warm{ctx->d_warm, ctx->d_stamp + 1 + slot, ctx->warm};
 }
 
 template <typename T>

@@ -1275,9 +1275,11 @@ hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, in
   const unsigned int* st = ctx->d_stamp + 1 + slot;
   const int32_t* clc = ctx->d_chunk_list_count + slot;
   int32_t* sc = ctx->d_super_counts + (long long)slot * kSuperSlots * ctx->nsuper;
-  // persistent blocks over the chunk list (its length is on the device)
-  long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
-  if (ctx->persist > 0) grid = std::min<long long>(grid, (long long)ctx->num_cus * ctx->persist);
+  // persistent blocks over the chunk list (its length is on the device):
+  // as many as the chip holds at once (8 of 256 threads per CU), since each
+  // block takes its chunks one after another and every chunk is a chain of
+  // dependent memory round trips
+  const long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
                      ctx->d_chunk_counts, sc, ctx->d_chunk_list, clc, ctx->n_static_chunks, st);
   fused = fused && ctx->nsuper <= kFusedScanMax;
