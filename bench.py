@@ -332,11 +332,15 @@ def measure(args):
                  + FLOPS_PER_SCAN_CANDIDATE * cands + FLOPS_PER_QUERY * qpl)
         avg_s = ms.mean() / 1e3
         peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+        # HBM bytes per launch from the counter runs (null once the kernel changed)
+        traffic = recorded_traffic(f"k_back|{w.name}|{precision}")
         achieved = flops / avg_s / 1e12
         roofline = {"bound": "alu", "kernel": "k_back (transform + donor search + interpolation)",
                     "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 6),
-                    "traffic": recorded_traffic(f"k_back|{w.name}|{precision}"),
+                    "traffic": traffic,
+                    "traffic_gbs": round(traffic / avg_s / 1e9, 1) if traffic else None,
+                    "traffic_frac_hbm": round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                     "avg_us": round(ms.mean() * 1e3, 2), "samples_us": [round(x * 1e3, 1) for x in ms],
                     "algorithmic_flops_per_launch": round(flops),
                     "per_unit": f"{FLOPS_PER_CELL[precision]} x {cells:.0f} walked cells + {FLOPS_PER_NEWTON_ITER} "

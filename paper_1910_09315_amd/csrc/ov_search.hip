@@ -207,9 +207,14 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
   for (int stepn = 0; stepn < max_walk; ++stepn) {
     ++visited;
     CellMap<T> m;
+    // FP64 (latency-bound sizes): the corner flags ride with the corner
+    // coordinates; FP32 (the large batched sizes, bound by the gathers'
+    // lines): only the accepted cell's flags are read
     uint8_t cf[8];
+    if (sizeof(T) == 8) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) cf[c] = fl[corner_node(G, ci, cj, ck, c)];
+      for (int c = 0; c < 8; ++c) cf[c] = fl[corner_node(G, ci, cj, ck, c)];
+    }
     load_cell<T>(G, ci, cj, ck, xi, m);
     T cond = 0, inv_norm = 0;
     bool conv =
@@ -229,7 +234,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
       const T es = (T)(2.0 * 1.7320508075688772 * perr) * inv_norm;
       if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
-        return corners_valid(cf) ? kFound : kToScan;
+        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid(G, fl, ci, cj, ck)) ? kFound : kToScan;
       }
       if (mg > -((sure ? (T)kMixedMargin : (T)kClearlyOutside) + es)) {
         cell = here;
@@ -238,7 +243,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     } else {
       if (conv && inside<T>(s, (T)kSTol)) {
         cell = here;
-        return corners_valid(cf) ? kFound : kToScan;
+        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid(G, fl, ci, cj, ck)) ? kFound : kToScan;
       }
     }
     if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
