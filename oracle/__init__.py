@@ -49,7 +49,9 @@ def lib():
             build()
         L = ctypes.CDLL(LIB_PATH)
         L.orc_holecut.restype = ctypes.c_double
-        L.orc_holecut.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_holecut.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_mesh_inside.restype = ctypes.c_double
+        L.orc_mesh_inside.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]
         L.orc_fringe.restype = None
         L.orc_fringe.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int, _P, _P]
         L.orc_compact.restype = ctypes.c_int64
@@ -111,6 +113,11 @@ class Oracle:
         self.Yp = np.array([a.ctypes.data for a in self._Y], dtype=np.uint64)
         self.Zp = np.array([a.ctypes.data for a in self._Z], dtype=np.uint64)
         self._bins = [None] * self.ng
+        # triangulated blank surfaces (ray-parity hole cut), per grid
+        self._mesh = [np.ascontiguousarray(getattr(g, "blank_mesh", None), dtype=np.float64).reshape(-1)
+                      if getattr(g, "blank_mesh", None) is not None else None for g in grids]
+        self.mesh_ptr = np.array([m.ctypes.data if m is not None else 0 for m in self._mesh], dtype=np.uint64)
+        self.mesh_ntri = np.array([m.size // 9 if m is not None else 0 for m in self._mesh], dtype=np.int64)
 
     @property
     def total_nodes(self) -> int:
@@ -144,7 +151,7 @@ class Oracle:
         flags = np.empty(self.total_nodes, dtype=np.uint8)
         gap = lib().orc_holecut(self.ng, _ptr(self.dims), _ptr(self.Xp), _ptr(self.Yp), _ptr(self.Zp),
                                 _ptr(self.blank_kind), _ptr(self.blank_prm), _ptr(poses),
-                                _ptr(self.node_off), _ptr(flags))
+                                _ptr(self.node_off), _ptr(flags), _ptr(self.mesh_ptr), _ptr(self.mesh_ntri))
         return flags, gap
 
     def fringe(self, flags, nf=None):
@@ -206,6 +213,17 @@ class Oracle:
         vals = self.interp(fields, d["donor_grid"], d["donor_cell"], d["s"])
         return {"holecut_flags": holes, "flags": flags, "min_gap": gap, "q_grid": qg, "q_node": qn,
                 **d, "values": vals}
+
+
+def mesh_inside(tri, points):
+    """Ray-parity inside test of points [n, 3] against the closed
+    triangulated surface tri [ntri, 3, 3] (body frame). Returns (inside
+    bool [n], smallest crossing gap)."""
+    t = np.ascontiguousarray(tri, dtype=np.float64).reshape(-1)
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(len(p), dtype=np.uint8)
+    gap = lib().orc_mesh_inside(_ptr(t), t.size // 9, len(p), _ptr(p), _ptr(out))
+    return out.astype(bool), gap
 
 
 def frame_velocity(poses, q_grid, donor_grid, values):

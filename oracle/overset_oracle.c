@@ -12,7 +12,9 @@
  *
  *   orc_transform      rigid frame map x = R X + c            (Sec. 2.1, frame of Fig. "non-inertial")
  *   orc_holecut        explicit hole cutting against closed blank surfaces
- *                      given as input                          (Sec. 2.2.2)
+ *                      given as input: implicit shapes, or a closed surface
+ *                      triangulation tested by ray parity      (Sec. 2.2.2)
+ *   orc_mesh_inside    that ray-parity test for given points
  *   orc_fringe         potential query points: overset boundary faces and the
  *                      buffer layer around blanked nodes      (Sec. 2.2.3, item 1)
  *   orc_compact        the ordered query list and its count NQ (Sec. 2.2.3, Alg. 1)
@@ -38,7 +40,9 @@
  * design notes):
  *  - flag byte: state in bits 0-1 (0 field, 1 hole, 2 fringe), cause grid in
  *    bits 2-7 (63 = overset outer boundary); hole > fringe > field.
- *  - hole test is the sign of an implicit closed surface, strict inside.
+ *  - hole test is the sign of an implicit closed surface, strict inside; a
+ *    triangulated closed surface is tested by ray parity along +x with the
+ *    edge rule of mesh_inside.
  *  - buffer layer = the non-hole nodes within Chebyshev index distance nf of a
  *    hole (outside the hole, 26-connected); cause = min over the causes met.
  *  - donor = the lowest linear cell index among valid containing cells of the
@@ -64,6 +68,7 @@
 #define BLANK_CYL 1
 #define BLANK_SPHERE 2
 #define BLANK_ELLIPSOID 3
+#define BLANK_MESH 4
 
 #define NEWTON_MAXIT 50
 #define NEWTON_TOL 1e-12   /* stop when the last Newton step is this small */
@@ -144,14 +149,114 @@ static int blank_inside(int kind, const double *prm, const double xi[3], double 
     return 0;
 }
 
+/* Inside test of a closed triangulated surface by ray parity (the hole cut
+ * against the body's surface triangulation of Sec. 2.2.2): the ray from xi
+ * along +x crosses the surface an odd number of times.
+ *  - A triangle is crossed when xi's projection (y, z) lies in the
+ *    triangle's projection and the crossing lies beyond xi in x.
+ *  - The projection is taken counter-clockwise (b and c swapped when its
+ *    signed area is negative; an edge-on triangle, area 0, is skipped).
+ *  - Edge function of edge u->v at p: (v_y - u_y)(p_z - u_z) - (v_z - u_z)(p_y - u_y),
+ *    computed from the endpoint with the smaller (y, z) (negated when that
+ *    is v), so that it is exactly antisymmetric in u and v.
+ *    p is in the projection when every edge function is > 0, or = 0 on an
+ *    edge that is included: v_z > u_z, or v_z = u_z and v_y > u_y. An edge
+ *    shared by two triangles on opposite sides is included by exactly one
+ *    of them, so a crossing through a projected edge or vertex counts once.
+ *  - The crossing is beyond xi when w0 a_x + w1 b_x + w2 c_x > x (w0 + w1 + w2),
+ *    with the edge functions w opposite a, b, c (barycentric weights times
+ *    the area, which is positive).
+ * Outside the surface's axis-aligned box the point is outside. *gap
+ * receives the smallest |crossing x - xi_x| met (diagnostic). */
+static int edge_included(const double *u, const double *v) {
+    double dz = v[2] - u[2], dy = v[1] - u[1];
+    return dz > 0.0 || (dz == 0.0 && dy > 0.0);
+}
+
+static double edge_fn_raw(const double *u, const double *v, const double *p) {
+    double t0 = (v[1] - u[1]) * (p[2] - u[2]);
+    double t1 = (v[2] - u[2]) * (p[1] - u[1]);
+    return t0 - t1;
+}
+
+/* Evaluated with the endpoints in a fixed order (ascending (y, z)) and
+ * negated for the other direction, so that the two triangles sharing an
+ * edge get exactly opposite values: rounding cannot put a point inside both
+ * or neither. */
+static double edge_fn(const double *u, const double *v, const double *p) {
+    if (u[1] < v[1] || (u[1] == v[1] && u[2] < v[2])) return edge_fn_raw(u, v, p);
+    return -edge_fn_raw(v, u, p);
+}
+
+static void mesh_box(const double *tri, int64_t ntri, double box[6]) {
+    for (int d = 0; d < 3; ++d) {
+        box[d] = INFINITY;
+        box[3 + d] = -INFINITY;
+    }
+    for (int64_t k = 0; k < 3 * ntri; ++k)
+        for (int d = 0; d < 3; ++d) {
+            double v = tri[3 * k + d];
+            if (v < box[d]) box[d] = v;
+            if (v > box[3 + d]) box[3 + d] = v;
+        }
+}
+
+static int mesh_inside(const double *tri, int64_t ntri, const double box[6], const double xi[3], double *gap) {
+    *gap = INFINITY;
+    for (int d = 0; d < 3; ++d)
+        if (xi[d] < box[d] || xi[d] > box[3 + d]) return 0;
+    int odd = 0;
+    for (int64_t k = 0; k < ntri; ++k) {
+        const double *a = tri + 9 * k, *b = a + 3, *c = a + 6;
+        double area = edge_fn(a, b, c);
+        if (area == 0.0) continue;
+        if (area < 0.0) {
+            const double *t = b;
+            b = c;
+            c = t;
+        }
+        double w0 = edge_fn(b, c, xi), w1 = edge_fn(c, a, xi), w2 = edge_fn(a, b, xi);
+        if (!(w0 > 0.0 || (w0 == 0.0 && edge_included(b, c)))) continue;
+        if (!(w1 > 0.0 || (w1 == 0.0 && edge_included(c, a)))) continue;
+        if (!(w2 > 0.0 || (w2 == 0.0 && edge_included(a, b)))) continue;
+        double den = (w0 + w1) + w2;
+        double num = (w0 * a[0] + w1 * b[0]) + w2 * c[0];
+        double rhs = xi[0] * den;
+        double g = fabs(num - rhs) / den;
+        if (g < *gap) *gap = g;
+        if (num > rhs) odd ^= 1;
+    }
+    return odd;
+}
+
+/* The ray-parity test for n points xi[3n] against one surface; out[n] = 0/1.
+ * Returns the smallest crossing gap met. */
+double orc_mesh_inside(const double *tri, int64_t ntri, int64_t n, const double *xi, uint8_t *out) {
+    double box[6], gmin = INFINITY;
+    mesh_box(tri, ntri, box);
+    for (int64_t q = 0; q < n; ++q) {
+        double g;
+        out[q] = (uint8_t)mesh_inside(tri, ntri, box, xi + 3 * q, &g);
+        if (g < gmin) gmin = g;
+    }
+    return gmin;
+}
+
 /* dims: [ngrids*4] = ni, nj, nk, periodic ; coords: arrays of ngrids pointers ;
- * blank_prm: [ngrids*8] ; poses: [ngrids*12] ; node_off: [ngrids+1].
- * flags (total nodes) receives hole/field states. Returns the smallest
- * surface gap met (diagnostic: a tiny gap means the decision is fragile). */
+ * blank_prm: [ngrids*8] ; poses: [ngrids*12] ; node_off: [ngrids+1] ;
+ * mesh_tri / mesh_ntri: per grid the triangles (9 doubles each, body frame)
+ * of a BLANK_MESH region (NULL / 0 otherwise; both arrays may be NULL when
+ * no grid has one). flags (total nodes) receives hole/field states. Returns
+ * the smallest surface gap met (diagnostic: a tiny gap means the decision
+ * is fragile). */
 double orc_holecut(int ngrids, const int32_t *dims, const double *const *X, const double *const *Y,
                    const double *const *Z, const int32_t *blank_kind, const double *blank_prm,
-                   const double *poses, const int64_t *node_off, uint8_t *flags) {
+                   const double *poses, const int64_t *node_off, uint8_t *flags, const double *const *mesh_tri,
+                   const int64_t *mesh_ntri) {
     double min_gap = INFINITY;
+    double *mbox = (double *)malloc(sizeof(double) * 6 * (size_t)ngrids);
+    for (int B = 0; B < ngrids; ++B)
+        if (blank_kind[B] == BLANK_MESH) mesh_box(mesh_tri[B], mesh_ntri[B], mbox + 6 * B);
     for (int A = 0; A < ngrids; ++A) {
         int64_t n = (int64_t)dims[4 * A] * dims[4 * A + 1] * dims[4 * A + 2];
         const double *pa = poses + 12 * A;
@@ -165,7 +270,9 @@ double orc_holecut(int ngrids, const int32_t *dims, const double *const *X, cons
                 if (B == A || blank_kind[B] == BLANK_NONE) continue;
                 double xi[3], gap;
                 apply_pose_inv(poses + 12 * B, w, xi);
-                int in = blank_inside(blank_kind[B], blank_prm + 8 * B, xi, &gap);
+                int in = blank_kind[B] == BLANK_MESH
+                             ? mesh_inside(mesh_tri[B], mesh_ntri[B], mbox + 6 * B, xi, &gap)
+                             : blank_inside(blank_kind[B], blank_prm + 8 * B, xi, &gap);
                 if (gap < gmin) gmin = gap;
                 if (in) {
                     f = (uint8_t)(ST_HOLE | (B << 2));
@@ -176,6 +283,7 @@ double orc_holecut(int ngrids, const int32_t *dims, const double *const *X, cons
         }
         if (gmin < min_gap) min_gap = gmin;
     }
+    free(mbox);
     return min_gap;
 }
 

@@ -33,7 +33,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BLANK_NONE, BLANK_CYL, BLANK_SPHERE, BLANK_ELLIPSOID = 0, 1, 2, 3
+BLANK_NONE, BLANK_CYL, BLANK_SPHERE, BLANK_ELLIPSOID, BLANK_MESH = 0, 1, 2, 3, 4
 PERIODIC_I, PERIODIC_J, PERIODIC_K = 1, 2, 4
 
 
@@ -49,6 +49,8 @@ class Grid:
     Z: np.ndarray
     blank_kind: int = BLANK_NONE
     blank_prm: tuple = ()
+    # BLANK_MESH: closed surface triangulation [ntri, 3, 3] in the body frame
+    blank_mesh: np.ndarray = None
     # fringe layers on the faces (i-, i+, j-, j+, k-, k+)
     outer: tuple = (0, 0, 0, 0, 0, 0)
 
@@ -401,8 +403,45 @@ FISH_OUTER = (0.95, 0.45, 0.38)
 DIAMOND = ((0.0, 0.0), (-1.2, 0.45), (-1.2, -0.45), (-2.4, 0.0))
 
 
+def triangulated_ellipsoid(semi, n_theta: int, n_phi: int, seed: int) -> np.ndarray:
+    """A closed triangulation [ntri, 3, 3] of the ellipsoid with semi-axes
+    `semi`: a latitude-longitude net of the unit sphere (n_theta - 1 rings of
+    n_phi vertices plus two poles), turned by a random rotation drawn from
+    default_rng(seed) so that no vertex or edge sits on a special plane, then
+    scaled per axis. Every vertex lies on the ellipsoid; shared vertices are
+    the same numbers in every triangle that uses them."""
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                  [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                  [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+    verts = [(0.0, 0.0, 1.0)]
+    for i in range(1, n_theta):
+        th = math.pi * i / n_theta
+        for j in range(n_phi):
+            ph = 2 * math.pi * j / n_phi
+            verts.append((math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)))
+    verts.append((0.0, 0.0, -1.0))
+    V = (np.array(verts) @ R.T) * np.asarray(semi, dtype=np.float64)
+    ring = lambda i, j: 1 + (i - 1) * n_phi + (j % n_phi)
+    last = len(verts) - 1
+    tris = []
+    for j in range(n_phi):
+        tris.append((0, ring(1, j), ring(1, j + 1)))
+        tris.append((last, ring(n_theta - 1, j + 1), ring(n_theta - 1, j)))
+    for i in range(1, n_theta - 1):
+        for j in range(n_phi):
+            a, b, c, d = ring(i, j), ring(i, j + 1), ring(i + 1, j), ring(i + 1, j + 1)
+            tris.append((a, c, d))
+            tris.append((a, d, b))
+    return np.ascontiguousarray(V[np.array(tris)])
+
+
 def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixed",
-                extent=(1.5, 1.0, 1.0), diamonds=((0.95, 0.5, 0.3), (0.95, 0.5, 0.7)), dt=1.0 / 240.0) -> Workload:
+                extent=(1.5, 1.0, 1.0), diamonds=((0.95, 0.5, 0.3), (0.95, 0.5, 0.7)), dt=1.0 / 240.0,
+                mesh=None) -> Workload:
     """Stretched background on [0,1.5]x[0,1]^2 and two diamonds of four
     fish-like ellipsoidal shells (polar axis along the swimming direction x).
     shell_dims: (N_r, N_phi, N_theta) of the four positions of a diamond.
@@ -410,7 +449,9 @@ def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixe
     0.1 L sin(2 pi t + a_g) along y, yaw 0.2 sin(2 pi t + b_g) about z,
     translation U_g t along x with U_g in [0.1, 0.3] L per unit time.
     Draw order from default_rng(seed): for each fish a_g, b_g, U_g; then the
-    Fourier modes of u, v, w, p."""
+    Fourier modes of u, v, w, p. mesh = (n_theta, n_phi): each fish's blank
+    region is the triangulated ellipsoid of the same semi-axes (ray-parity
+    hole cut), its rotation drawn from default_rng(seed + 1000 + g)."""
     rng = np.random.default_rng(seed)
     bg = stretched_background(bg_dims, extent=extent)
     grids = [bg]
@@ -421,6 +462,9 @@ def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixe
                                   name=f"fish{len(grids)}")
             g.blank_kind = BLANK_ELLIPSOID
             g.blank_prm = tuple(L * a for a in FISH_BLANK)
+            if mesh is not None:
+                g.blank_kind = BLANK_MESH
+                g.blank_mesh = triangulated_ellipsoid(g.blank_prm, mesh[0], mesh[1], seed + 1000 + len(grids))
             g.outer = (0, nf, 0, 0, 0, 0)
             grids.append(g)
             centres.append((dc[0] + dx * L, dc[1] + dy * L, dc[2]))
@@ -453,6 +497,21 @@ def c3_small(steps=4, precision="fp64") -> Workload:
     of 12-24 layers, faster motion (dt = 1/24)."""
     return school_case("C3-small", (128, 96, 96), ((24, 24, 20), (20, 20, 16), (16, 20, 16), (12, 16, 12)),
                        0.25, steps, seed=33, precision=precision, dt=1.0 / 24.0)
+
+
+def c3_mesh(steps=200) -> Workload:
+    """C3 with each fish's blank region given as a closed surface
+    triangulation (48 x 96 latitude-longitude net, 9,024 triangles) instead
+    of the implicit ellipsoid: the hole cut by ray parity."""
+    return school_case("C3M", (384, 256, 256), ((160, 96, 96), (128, 96, 64), (96, 64, 64), (64, 64, 64)),
+                       0.25, steps, seed=3, mesh=(48, 96))
+
+
+def c3_mesh_small(steps=4, precision="fp64") -> Workload:
+    """The small school with triangulated blank surfaces (12 x 24 net, 528
+    triangles per fish) for parity tests."""
+    return school_case("C3M-small", (128, 96, 96), ((24, 24, 20), (20, 20, 16), (16, 20, 16), (12, 16, 12)),
+                       0.25, steps, seed=33, precision=precision, dt=1.0 / 24.0, mesh=(12, 24))
 
 
 # ---------------------------------------------------------------- many random shells
@@ -530,7 +589,7 @@ def c4_small(steps=4, precision="fp64") -> Workload:
 
 
 CONFIGS = {"C0": c0, "C1": c1, "C2": c2, "C1-small": c1_small, "C3": c3, "C3-small": c3_small,
-           "C4": c4, "C4-small": c4_small}
+           "C3M": c3_mesh, "C3M-small": c3_mesh_small, "C4": c4, "C4-small": c4_small}
 
 
 def build(name: str, **kw) -> Workload:
