@@ -72,7 +72,8 @@ enum ov_blank_kind {
     OV_BLANK_NONE = 0,
     OV_BLANK_CYL = 1,       /* prm: r, z0, z1 — x^2 + y^2 < r^2 and z0 <= z <= z1 (body frame) */
     OV_BLANK_SPHERE = 2,    /* prm: r         — x^2 + y^2 + z^2 < r^2 */
-    OV_BLANK_ELLIPSOID = 3  /* prm: a, b, c   — (x/a)^2 + (y/b)^2 + (z/c)^2 < 1 */
+    OV_BLANK_ELLIPSOID = 3, /* prm: a, b, c   — (x/a)^2 + (y/b)^2 + (z/c)^2 < 1 */
+    OV_BLANK_MESH = 4       /* a closed surface triangulation, set with ov_grid_set_blank_mesh */
 };
 
 /* Flag byte fields. */
@@ -132,6 +133,27 @@ int ov_ctx_destroy(ov_ctx *ctx);
 
 /* Last error message of `ctx` (static string owned by the context). */
 const char *ov_last_error(const ov_ctx *ctx);
+
+/* The blank region of grid `grid` as a closed surface triangulation (the
+ * body's surface triangles of Sec. 2.2.2), replacing its implicit shape: a
+ * node of another grid is a hole when the ray from it along +x (in this
+ * grid's body frame) crosses the surface an odd number of times. Counting
+ * rule, exactly that of the FP64 decision on every node:
+ *  - a triangle is crossed when the node's (y, z) lies in the triangle's
+ *    (y, z) projection, oriented counter-clockwise (edge-on triangles never
+ *    count), and the crossing lies beyond the node in x;
+ *  - on a projected edge u->v the node counts when v_z > u_z, or v_z = u_z
+ *    and v_y > u_y, with the edge function evaluated from the endpoint of
+ *    smaller (y, z), so that a crossing through a shared edge or vertex
+ *    counts once;
+ *  - outside the surface's axis-aligned box a node is outside.
+ * The surface must be closed (every edge shared by two triangles, shared
+ * vertices bit-identical); the test is decided in FP64 in both precisions.
+ *  tri   ntri x 9 doubles (vertices a, b, c) in the grid's body frame [host, copied]
+ *  ntri  >= 4
+ * Must follow ov_grid_add of that grid and precede ov_finalize. OV_EINVAL
+ * for a bad grid id, fewer than 4 triangles or a non-finite coordinate. */
+int ov_grid_set_blank_mesh(ov_ctx *ctx, int32_t grid, const double *tri, int64_t ntri);
 
 /* Register a structured grid (Sec. 2.2: a block of the overset system).
  *  ni, nj, nk     nodes per direction, each >= 2; total nodes of all grids < 2^31

@@ -56,7 +56,11 @@ class Assembly:
             Y = torch.as_tensor(np.ascontiguousarray(g.Y, dtype=np.float64)).to(self.dev)
             Z = torch.as_tensor(np.ascontiguousarray(g.Z, dtype=np.float64)).to(self.dev)
             self.coords.append((X, Y, Z))
-            self.ctx.grid_add(g.dims, g.periodic, X, Y, Z, g.blank_kind, tuple(g.blank_prm), tuple(g.outer))
+            mesh = getattr(g, "blank_mesh", None)
+            gid = self.ctx.grid_add(g.dims, g.periodic, X, Y, Z, B.OV_BLANK_NONE if mesh is not None else g.blank_kind,
+                                    tuple(g.blank_prm), tuple(g.outer))
+            if mesh is not None:
+                self.ctx.set_blank_mesh(gid, mesh)
         self.ctx.finalize()
         self.field_layout = 0
         self.frame_velocity = 0

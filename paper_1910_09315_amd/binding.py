@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboverset.so")
 
 OV_FP64, OV_MIXED = 0, 1
 OV_BLANK_NONE, OV_BLANK_CYL, OV_BLANK_SPHERE, OV_BLANK_ELLIPSOID = 0, 1, 2, 3
+OV_BLANK_NONE, OV_BLANK_CYL, OV_BLANK_SPHERE, OV_BLANK_ELLIPSOID, OV_BLANK_MESH = 0, 1, 2, 3, 4
 OV_STATE_FIELD, OV_STATE_HOLE, OV_STATE_FRINGE = 0, 1, 2
 OV_CAUSE_BOUNDARY = 63
 OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
@@ -26,7 +27,8 @@ OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_
        "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13,
        "frame_velocity": 14}
 
-EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_finalize", "ov_num_grids",
+EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_grid_set_blank_mesh",
+           "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
@@ -65,6 +67,7 @@ def load(path: str = LIB_PATH):
         "ov_ctx_destroy": (ctypes.c_int, [_P]),
         "ov_last_error": (ctypes.c_char_p, [_P]),
         "ov_grid_add": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _I32, _P, _P, _P]),
+        "ov_grid_set_blank_mesh": (ctypes.c_int, [_P, _I32, _P, _I64]),
         "ov_finalize": (ctypes.c_int, [_P, _P]),
         "ov_num_grids": (_I32, [_P]),
         "ov_total_nodes": (_I64, [_P]),
@@ -150,6 +153,13 @@ class Context:
                                         _ptr(X), _ptr(Y), _ptr(Z), int(blank_kind), prm, out,
                                         ctypes.byref(gid)), "ov_grid_add")
         return gid.value
+
+    def set_blank_mesh(self, grid: int, tri):
+        """tri: [ntri, 3, 3] FP64 triangles of a closed surface (body frame); copied."""
+        import numpy as np
+        t = np.ascontiguousarray(tri, dtype=np.float64).reshape(-1)
+        self.check(self.lib.ov_grid_set_blank_mesh(self.h, int(grid), t.ctypes.data_as(ctypes.c_void_p), t.size // 9),
+                   "ov_grid_set_blank_mesh")
 
     def finalize(self, stream=None):
         self.check(self.lib.ov_finalize(self.h, _stream(stream)), "ov_finalize")

@@ -504,6 +504,9 @@ int ov_ctx_destroy(ov_ctx* ctx) {
     (void)hipFree(g.bsub);
     (void)hipFree(g.sstart);
     (void)hipFree(g.scells);
+    (void)hipFree(g.mtri);
+    (void)hipFree(g.mstart);
+    (void)hipFree(g.mvox);
   }
   (void)hipFree(ctx->d_grids);
   (void)hipFree(ctx->d_status);
@@ -599,6 +602,152 @@ int ov_grid_add(ov_ctx* ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t period
   return OV_OK;
 }
 
+int ov_grid_set_blank_mesh(ov_ctx* ctx, int32_t grid, const double* tri, int64_t ntri) {
+  if (!ctx) return OV_EINVAL;
+  if (ctx->finalized) return fail(ctx, OV_ESTATE, "ov_grid_set_blank_mesh after ov_finalize");
+  if (grid < 0 || grid >= (int)ctx->grids.size()) return fail(ctx, OV_EINVAL, "no grid %d", grid);
+  if (!tri || ntri < 4) return fail(ctx, OV_EINVAL, "a closed surface needs at least 4 triangles");
+  if (ntri > (1LL << 28)) return fail(ctx, OV_EINVAL, "too many triangles");
+  GridHost& g = ctx->grids[grid];
+  double r2 = 0.0;
+  for (long long k = 0; k < 9 * ntri; ++k)
+    if (!std::isfinite(tri[k])) return fail(ctx, OV_EINVAL, "non-finite triangle coordinate");
+  for (long long k = 0; k < 3 * ntri; ++k) {
+    const double* v = tri + 3 * k;
+    r2 = std::max(r2, v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  }
+  g.mesh.assign(tri, tri + 9 * ntri);
+  g.d.blank_kind = OV_BLANK_MESH;
+  for (int p = 0; p < 8; ++p) g.d.blank_prm[p] = 0.0;
+  // the surface lies in the ball through its farthest vertex; inflated as
+  // for the implicit shapes
+  g.d.cull_r2 = r2 * (1.0 + 1e-9) + 1e-300;
+  return OV_OK;
+}
+
+// The (y, z) bins of a surface triangulation: about one triangle per bin
+// on average, at most 256 per axis.
+static int build_mesh_bins(ov_ctx* ctx, GridHost& g) {
+  const long long ntri = (long long)g.mesh.size() / 9;
+  const double* t = g.mesh.data();
+  double* box = g.d.mbox;
+  for (int d = 0; d < 3; ++d) {
+    box[d] = INFINITY;
+    box[3 + d] = -INFINITY;
+  }
+  for (long long k = 0; k < 3 * ntri; ++k)
+    for (int d = 0; d < 3; ++d) {
+      box[d] = std::min(box[d], t[3 * k + d]);
+      box[3 + d] = std::max(box[3 + d], t[3 * k + d]);
+    }
+  const int n = (int)std::max(1.0, std::min(256.0, std::floor(std::sqrt((double)ntri))));
+  for (int a = 0; a < 2; ++a) {
+    const double ext = box[4 + a] - box[1 + a];
+    g.d.mn[a] = ext > 0.0 ? n : 1;
+    g.d.minv[a] = ext > 0.0 ? n / ext : 0.0;
+  }
+  const int ny = g.d.mn[0], nz = g.d.mn[1];
+  std::vector<int> start((size_t)ny * nz + 1, 0);
+  auto range = [&](long long k, int& y0, int& y1, int& z0, int& z1) {
+    const double* a = t + 9 * k;
+    const double ylo = std::min(a[1], std::min(a[4], a[7])), yhi = std::max(a[1], std::max(a[4], a[7]));
+    const double zlo = std::min(a[2], std::min(a[5], a[8])), zhi = std::max(a[2], std::max(a[5], a[8]));
+    y0 = mesh_bin(ylo, box[1], g.d.minv[0], ny);
+    y1 = mesh_bin(yhi, box[1], g.d.minv[0], ny);
+    z0 = mesh_bin(zlo, box[2], g.d.minv[1], nz);
+    z1 = mesh_bin(zhi, box[2], g.d.minv[1], nz);
+  };
+  for (long long k = 0; k < ntri; ++k) {
+    int y0, y1, z0, z1;
+    range(k, y0, y1, z0, z1);
+    for (int z = z0; z <= z1; ++z)
+      for (int y = y0; y <= y1; ++y) ++start[(size_t)z * ny + y + 1];
+  }
+  for (size_t b = 0; b < (size_t)ny * nz; ++b) start[b + 1] += start[b];
+  // each bin's triangles stored contiguously, oriented counter-clockwise in
+  // (y, z) by the same edge function the test uses; edge-on ones dropped
+  std::vector<double> binned((size_t)start.back() * 9);
+  std::vector<int> fill(start.begin(), start.end() - 1);
+  for (long long k = 0; k < ntri; ++k) {
+    const double* a = t + 9 * k;
+    const double* b = a + 3;
+    const double* c = a + 6;
+    const double area = mesh_edge(a, b, c[1], c[2]);
+    if (area == 0.0) continue;
+    if (area < 0.0) std::swap(b, c);
+    int y0, y1, z0, z1;
+    range(k, y0, y1, z0, z1);
+    for (int z = z0; z <= z1; ++z)
+      for (int y = y0; y <= y1; ++y) {
+        double* dst = binned.data() + 9 * (size_t)fill[(size_t)z * ny + y]++;
+        for (int d = 0; d < 3; ++d) {
+          dst[d] = a[d];
+          dst[3 + d] = b[d];
+          dst[6 + d] = c[d];
+        }
+      }
+  }
+  // (bins end where their fill stopped: edge-on triangles leave gaps at the
+  // end of a bin, closed here)
+  std::vector<int> st2(start.size(), 0);
+  std::vector<double> packed;
+  packed.reserve(binned.size());
+  for (size_t bin = 0; bin + 1 < start.size(); ++bin) {
+    st2[bin] = (int)(packed.size() / 9);
+    packed.insert(packed.end(), binned.begin() + 9 * (size_t)start[bin], binned.begin() + 9 * (size_t)fill[bin]);
+  }
+  st2.back() = (int)(packed.size() / 9);
+  if (packed.empty()) packed.assign(9, 0.0);
+  HIPCHK(hipMalloc(&g.mtri, sizeof(double) * packed.size()), "hipMalloc surface triangles");
+  HIPCHK(hipMemcpy(g.mtri, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice),
+         "surface triangles copy");
+  HIPCHK(hipMalloc(&g.mstart, sizeof(int) * st2.size()), "hipMalloc surface bins");
+  HIPCHK(hipMemcpy(g.mstart, st2.data(), sizeof(int) * st2.size(), hipMemcpyHostToDevice), "surface bins copy");
+  g.d.mtri = g.mtri;
+  g.d.mstart = g.mstart;
+  // voxels: about 128 along the box's longest side; a voxel met by a
+  // triangle's box padded by 1e-4 of that side is "the surface may pass";
+  // every other voxel takes the ray-parity status of its centre, which
+  // holds for every point within the padding of the voxel (no surface
+  // there): also for a node whose FP32 body-frame position lies in it (its
+  // FP32 error is far below the padding)
+  const double ext = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
+  const double h = ext / 128.0, pad = 1e-4 * ext;
+  for (int d = 0; d < 3; ++d) {
+    const double e = box[3 + d] - box[d];
+    g.d.mvn[d] = e > 0.0 ? (int)std::min(256.0, std::max(1.0, std::ceil(e / h))) : 1;
+    g.d.mvinv[d] = e > 0.0 ? g.d.mvn[d] / e : 0.0;
+  }
+  const int vx = g.d.mvn[0], vy = g.d.mvn[1], vz = g.d.mvn[2];
+  std::vector<uint8_t> vox((size_t)vx * vy * vz, 0);
+  for (long long k = 0; k < ntri; ++k) {
+    const double* a = t + 9 * k;
+    int r[3][2];
+    for (int d = 0; d < 3; ++d) {
+      const double lo = std::min(a[d], std::min(a[3 + d], a[6 + d])) - pad;
+      const double hi = std::max(a[d], std::max(a[3 + d], a[6 + d])) + pad;
+      r[d][0] = mesh_bin(lo, box[d], g.d.mvinv[d], g.d.mvn[d]);
+      r[d][1] = mesh_bin(hi, box[d], g.d.mvinv[d], g.d.mvn[d]);
+    }
+    for (int z = r[2][0]; z <= r[2][1]; ++z)
+      for (int y = r[1][0]; y <= r[1][1]; ++y)
+        for (int x = r[0][0]; x <= r[0][1]; ++x) vox[((size_t)z * vy + y) * vx + x] = 2;
+  }
+  for (int z = 0; z < vz; ++z)
+    for (int y = 0; y < vy; ++y)
+      for (int x = 0; x < vx; ++x) {
+        uint8_t& v = vox[((size_t)z * vy + y) * vx + x];
+        if (v == 2) continue;
+        const double cx = box[0] + (x + 0.5) / g.d.mvinv[0], cy = box[1] + (y + 0.5) / g.d.mvinv[1],
+                     cz = box[2] + (z + 0.5) / g.d.mvinv[2];
+        v = mesh_parity(packed.data(), st2.data(), box, g.d.minv, g.d.mn, cx, cy, cz) ? 1 : 0;
+      }
+  HIPCHK(hipMalloc(&g.mvox, vox.size()), "hipMalloc surface voxels");
+  HIPCHK(hipMemcpy(g.mvox, vox.data(), vox.size(), hipMemcpyHostToDevice), "surface voxels copy");
+  g.d.mvox = g.mvox;
+  return OV_OK;
+}
+
 int ov_finalize(ov_ctx* ctx, void* stream) {
   if (!ctx) return OV_EINVAL;
   if (ctx->finalized) return fail(ctx, OV_ESTATE, "already finalized");
@@ -614,6 +763,10 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     }
     rc = build_gather_layout(ctx, g, s);
     if (rc != OV_OK) return rc;
+    if (g.d.blank_kind == OV_BLANK_MESH) {
+      rc = build_mesh_bins(ctx, g);
+      if (rc != OV_OK) return rc;
+    }
   }
   long long total = ctx->node_off.back();
   std::vector<GridDev> table;

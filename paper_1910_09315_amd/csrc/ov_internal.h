@@ -70,6 +70,21 @@ struct GridDev {
   const int* bsub;          // per bin: its first sub-bin, or -1 (null: no bin is split)
   const long long* sstart;  // [nsub + 1]
   const int* scells;
+  // OV_BLANK_MESH: the closed surface triangulation (9 doubles per triangle,
+  // body frame), its triangles binned by their (y, z) box over a uniform
+  // 2-D grid of the surface's (y, z) box (a ray along +x meets only the
+  // triangles of its bin)
+  const double* mtri;  // per bin its triangles, contiguous, oriented (see mesh_parity)
+  const int* mstart;   // [mn[0] * mn[1] + 1], in triangles
+  double mbox[6];     // axis-aligned box of the surface: lo x, y, z, hi x, y, z
+  double minv[2];     // bins per unit length along y and z
+  int mn[2];          // bins along y and z
+  // voxels over the box: 0 outside, 1 inside (no triangle's padded box
+  // meets the voxel; the status of its centre), 2 the surface may pass
+  const uint8_t* mvox;
+  double mvinv[3];  // voxels per unit length along x, y, z
+  int mvn[3];       // voxels along x, y, z
+  int mpad_;
 };
 
 struct GridHost {
@@ -85,6 +100,10 @@ struct GridHost {
   int* bsub = nullptr;
   long long* sstart = nullptr;
   int* scells = nullptr;
+  std::vector<double> mesh;  // OV_BLANK_MESH triangles (host copy until finalize)
+  double* mtri = nullptr;
+  int* mstart = nullptr;
+  uint8_t* mvox = nullptr;
 };
 
 }  // namespace ov
@@ -213,6 +232,72 @@ __device__ __forceinline__ gmem<T>* gp(const T* p) {
 }
 
 typedef double ov_dv2 __attribute__((ext_vector_type(2)));
+// Bin of a coordinate along one axis of a surface triangulation's (y, z)
+// grid: the same formula on the host (binning triangle boxes) and on the
+// device (binning a node), so that a triangle whose box holds the node is
+// listed in the node's bin (the map is monotone in v).
+__host__ __device__ __forceinline__ int mesh_bin(double v, double lo, double inv, int n) {
+#pragma clang fp contract(off)
+  const double t = floor((v - lo) * inv);
+  return t < 0.0 ? 0 : (t >= (double)n ? n - 1 : (int)t);
+}
+
+// Ray-parity inside test of a closed surface triangulation (the body's
+// surface triangles, Sec. 2.2.2): the ray from (x, y, z) along +x crosses
+// the surface an odd number of times. Only the triangles of the node's
+// (y, z) bin can be crossed. A triangle counts when the node's (y, z) lies
+// in its counter-clockwise projection (edge functions > 0, or = 0 on an
+// included edge) and the crossing lies beyond x. The edge function of a
+// projected edge is evaluated from its endpoint of smaller (y, z) and
+// negated for the other direction, so the two triangles of a shared edge
+// get exactly opposite values, and an edge is included when it runs toward
+// larger z (or, level, toward larger y): a crossing through a shared edge
+// or vertex counts once. No contraction into fused multiply-adds: the
+// decision is the same, bit for bit, as the reference evaluation order.
+__host__ __device__ __forceinline__ double mesh_edge_raw(const double* u, const double* v, double py, double pz) {
+#pragma clang fp contract(off)
+  const double t0 = (v[1] - u[1]) * (pz - u[2]);
+  const double t1 = (v[2] - u[2]) * (py - u[1]);
+  return t0 - t1;
+}
+
+__host__ __device__ __forceinline__ double mesh_edge(const double* u, const double* v, double py, double pz) {
+  if (u[1] < v[1] || (u[1] == v[1] && u[2] < v[2])) return mesh_edge_raw(u, v, py, pz);
+  return -mesh_edge_raw(v, u, py, pz);
+}
+
+__host__ __device__ __forceinline__ bool mesh_edge_included(const double* u, const double* v) {
+#pragma clang fp contract(off)
+  const double dz = v[2] - u[2], dy = v[1] - u[1];
+  return dz > 0.0 || (dz == 0.0 && dy > 0.0);
+}
+
+// tri: the triangles of each (y, z) bin stored contiguously (9 doubles
+// each), already in counter-clockwise projected order, edge-on ones left
+// out (both fixed at set-up with the same edge function).
+__host__ __device__ inline bool mesh_parity(const double* tri, const int* start, const double* bx, const double* inv,
+                                            const int* n, double x, double y, double z) {
+#pragma clang fp contract(off)
+  if (x < bx[0] || x > bx[3] || y < bx[1] || y > bx[4] || z < bx[2] || z > bx[5]) return false;
+  const int bin = mesh_bin(z, bx[2], inv[1], n[1]) * n[0] + mesh_bin(y, bx[1], inv[0], n[0]);
+  const int e1 = start[bin + 1];
+  bool odd = false;
+#pragma unroll 4
+  for (int e = start[bin]; e < e1; ++e) {
+    const double* a = tri + 9LL * e;
+    const double* b = a + 3;
+    const double* c = a + 6;
+    const double w0 = mesh_edge(b, c, y, z), w1 = mesh_edge(c, a, y, z), w2 = mesh_edge(a, b, y, z);
+    if (!(w0 > 0.0 || (w0 == 0.0 && mesh_edge_included(b, c)))) continue;
+    if (!(w1 > 0.0 || (w1 == 0.0 && mesh_edge_included(c, a)))) continue;
+    if (!(w2 > 0.0 || (w2 == 0.0 && mesh_edge_included(a, b)))) continue;
+    const double den = (w0 + w1) + w2;
+    const double num = (w0 * a[0] + w1 * b[0]) + w2 * c[0];
+    if (num > x * den) odd = !odd;
+  }
+  return odd;
+}
+
 // The warm-start record of a node with no history.
 constexpr unsigned long long kWarmEmpty = 0x000000FFFFFFFFFFULL;  // cell -1, grid 255, stamp 0
 constexpr int kStatSlots = 64;

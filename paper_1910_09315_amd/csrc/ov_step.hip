@@ -57,7 +57,16 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
       L.prmf[g][0] = (float)(1.0 / q[0]);
       L.prmf[g][1] = (float)(1.0 / q[1]);
       L.prmf[g][2] = (float)(1.0 / q[2]);
-    } else if (G.blank_kind != OV_BLANK_NONE) {
+    } else if (G.blank_kind == OV_BLANK_MESH) {
+      // the surface's box padded far beyond FP32 rounding of a body-frame
+      // position: outside it a node is decided in FP32, inside it in FP64
+      const double* b = G.mbox;
+      const double pad = 1e-3 * fmax(b[3] - b[0], fmax(b[4] - b[1], b[5] - b[2])) + 1e-5;
+      for (int d = 0; d < 3; ++d) {
+        L.prmf[g][d] = (float)(b[d] - pad);
+        L.prmf[g][3 + d] = (float)(b[3 + d] + pad);
+      }
+    } else if (G.blank_kind == OV_BLANK_SPHERE || G.blank_kind == OV_BLANK_CYL) {
       L.prmf[g][0] = (float)(1.0 / (q[0] * q[0]));
       L.prmf[g][3] = (float)(1.0 / q[0]);
       L.prmf[g][4] = (float)q[1];
@@ -87,6 +96,11 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
       for (int d = 0; d < 3; ++d) {
         lo[d] = -q[d];
         hi[d] = q[d];
+      }
+    } else if (G.blank_kind == OV_BLANK_MESH) {
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = G.mbox[d];
+        hi[d] = G.mbox[3 + d];
       }
     }
     for (int d = 0; d < 3; ++d) {
@@ -119,6 +133,7 @@ __device__ __forceinline__ float blank_measure_f32(int kind, const float* c, flo
 }
 
 __device__ __forceinline__ bool blank_inside_fp64(int kind, const double* prm, double x, double y, double z) {
+#pragma clang fp contract(off)
   if (kind == OV_BLANK_CYL) {
     double r = prm[0];
     return (x * x + y * y) < r * r && z >= prm[1] && z <= prm[2];
@@ -128,9 +143,33 @@ __device__ __forceinline__ bool blank_inside_fp64(int kind, const double* prm, d
   return (u * u + v * v + w * w) < 1.0;
 }
 
+// The ray-parity test of a triangulated blank surface: a node in a voxel
+// that no triangle's (padded) box meets takes the voxel's precomputed
+// status (the surface does not pass between it and the voxel's centre, where
+// the same test was evaluated at set-up); a node in a voxel the surface may
+// pass through runs the test on the triangles of its (y, z) bin.
+// Voxel status of a body-frame point (clamped into the voxel grid).
+__device__ __forceinline__ int mesh_voxel(const GridDev& G, double x, double y, double z) {
+  const double* bx = G.mbox;
+  return G.mvox[(mesh_bin(z, bx[2], G.mvinv[2], G.mvn[2]) * G.mvn[1] + mesh_bin(y, bx[1], G.mvinv[1], G.mvn[1])) *
+                    G.mvn[0] +
+                mesh_bin(x, bx[0], G.mvinv[0], G.mvn[0])];
+}
+
+__device__ __noinline__ bool mesh_inside(const GridDev& G, double x, double y, double z) {
+  const double* bx = G.mbox;
+  if (x < bx[0] || x > bx[3] || y < bx[1] || y > bx[4] || z < bx[2] || z > bx[5]) return false;
+  const int v = mesh_voxel(G, x, y, z);
+  if (v != 2) return v == 1;
+  return mesh_parity(G.mtri, G.mstart, bx, G.minv, G.mn, x, y, z);
+}
+
 // FP64 decision for one node of grid A at world position w: first blanking
-// grid (ascending grid id, among the bits of mask) or -1.
-__device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const double w[3], unsigned long long mask) {
+// grid (ascending grid id, among the bits of mask) or -1. The body-frame
+// position is formed without fused multiply-adds, in the reference order.
+__device__ __forceinline__ int holecut_fp64(const HoleLds& L, const GridDev* __restrict__ grids, int A,
+                                            const double w[3], unsigned long long mask) {
+#pragma clang fp contract(off)
   mask &= ~(1ull << A);
   while (mask) {
     const int B = __ffsll((long long)mask) - 1;
@@ -138,12 +177,21 @@ __device__ __forceinline__ int holecut_fp64(const HoleLds& L, int A, const doubl
     const double* p = L.pose[B];
     double d0 = w[0] - p[9], d1 = w[1] - p[10], d2 = w[2] - p[11];
     if (d0 * d0 + d1 * d1 + d2 * d2 >= L.cull[B]) continue;
-    double x = p[0] * d0 + p[3] * d1 + p[6] * d2;
-    double y = p[1] * d0 + p[4] * d1 + p[7] * d2;
-    double z = p[2] * d0 + p[5] * d1 + p[8] * d2;
-    if (blank_inside_fp64(L.kind[B], L.prm[B], x, y, z)) return B;
+    double x = (p[0] * d0 + p[3] * d1) + p[6] * d2;
+    double y = (p[1] * d0 + p[4] * d1) + p[7] * d2;
+    double z = (p[2] * d0 + p[5] * d1) + p[8] * d2;
+    const bool in = L.kind[B] == OV_BLANK_MESH ? mesh_inside(grids[B], x, y, z)
+                                                : blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
+    if (in) return B;
   }
   return -1;
+}
+
+// World position of a node, ((R_i0 X + R_i1 Y) + R_i2 Z) + c_i, without
+// fused multiply-adds (the reference order).
+__device__ __forceinline__ void world_exact(const double* pa, double X, double Y, double Z, double w[3]) {
+#pragma clang fp contract(off)
+  for (int i = 0; i < 3; ++i) w[i] = ((pa[3 * i] * X + pa[3 * i + 1] * Y) + pa[3 * i + 2] * Z) + pa[9 + i];
 }
 
 // FP32 guard band: nodes whose FP32 inside measure is within this of the
@@ -160,10 +208,8 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
   const double* pa = L.pose[A];
   if (sizeof(CT) == 8) {
     double w[3];
-    w[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
-    w[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
-    w[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
-    return holecut_fp64(L, A, w, mask);
+    world_exact(pa, (double)X, (double)Y, (double)Z, w);
+    return holecut_fp64(L, grids, A, w, mask);
   }
   const float* pf = L.posef[A];
   const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
@@ -180,7 +226,24 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     float x = p[0] * d0 + p[3] * d1 + p[6] * d2;
     float y = p[1] * d0 + p[4] * d1 + p[7] * d2;
     float z = p[2] * d0 + p[5] * d1 + p[8] * d2;
-    float f = blank_measure_f32(L.kind[B], L.prmf[B], x, y, z);
+    // a triangulated surface: outside its padded box, or in a voxel the
+    // surface does not reach, decided in FP32 (the voxel's status holds within
+    // a padding far above FP32 error); otherwise in FP64
+    const float* c = L.prmf[B];
+    float f;
+    if (L.kind[B] != OV_BLANK_MESH) {
+      f = blank_measure_f32(L.kind[B], c, x, y, z);
+    } else if (x < c[0] || x > c[3] || y < c[1] || y > c[4] || z < c[2] || z > c[5]) {
+      f = 1.f;
+    } else {
+      // (only strictly inside the surface's box: near its faces the FP64
+      // test decides)
+      const double* bx = L.box[B];
+      const double xd = x, yd = y, zd = z;
+      const bool in_box = xd > bx[0] && xd < bx[3] && yd > bx[1] && yd < bx[4] && zd > bx[2] && zd < bx[5];
+      const int v = in_box ? mesh_voxel(grids[B], xd, yd, zd) : 2;
+      f = v == 0 ? 1.f : v == 1 ? -1.f : 0.f;
+    }
     if (fabsf(f) < kHoleGuard) {
       unsure = true;
       break;
@@ -194,10 +257,8 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     const GridDev& G = grids[A];
     double Xd = gp(G.X)[m], Yd = gp(G.Y)[m], Zd = gp(G.Z)[m];
     double w[3];
-    w[0] = pa[0] * Xd + pa[1] * Yd + pa[2] * Zd + pa[9];
-    w[1] = pa[3] * Xd + pa[4] * Yd + pa[5] * Zd + pa[10];
-    w[2] = pa[6] * Xd + pa[7] * Yd + pa[8] * Zd + pa[11];
-    cause = holecut_fp64(L, A, w, mask);
+    world_exact(pa, Xd, Yd, Zd, w);
+    cause = holecut_fp64(L, grids, A, w, mask);
   }
   return cause;
 }

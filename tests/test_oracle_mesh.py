@@ -18,15 +18,6 @@ def _built():
     oracle.build(force=False)
 
 
-def _rotation(seed):
-    q = np.random.default_rng(seed).standard_normal(4)
-    q /= np.linalg.norm(q)
-    w, x, y, z = q
-    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
-                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
-                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
-
-
 def _hull_case(seed, npts=40):
     rng = np.random.default_rng(seed)
     pts = rng.standard_normal((npts, 3)) @ np.diag([1.0, 0.6, 0.8])
@@ -99,11 +90,11 @@ def _implicit_measure(w, t, B):
 
 
 def test_triangulated_ellipsoids_agree_with_the_implicit_ones_away_from_the_surface():
-    """C3M-small (528 triangles per fish) against the same school with the
+    """C3M-small (320 triangles per fish) against the same school with the
     implicit ellipsoids: a node outside every implicit ellipsoid is no
-    mesh hole (the net is inscribed in a convex body), and a node deeper than
-    the chord error (measure < -0.12; the 12 x 24 net stays within -0.09 of
-    the surface) is a mesh hole."""
+    mesh hole (the triangulation is inscribed in a convex body), and a node
+    deeper than the chord error (measure < -0.12; the faces stay within
+    -0.04 of the surface) is a mesh hole."""
     wm = W.c3_mesh_small(steps=2)
     t = 1
     o = oracle.Oracle(wm.grids, wm.nf)

@@ -403,10 +403,11 @@ FISH_OUTER = (0.95, 0.45, 0.38)
 DIAMOND = ((0.0, 0.0), (-1.2, 0.45), (-1.2, -0.45), (-2.4, 0.0))
 
 
-def triangulated_ellipsoid(semi, n_theta: int, n_phi: int, seed: int) -> np.ndarray:
+def triangulated_ellipsoid(semi, level: int, seed: int) -> np.ndarray:
     """A closed triangulation [ntri, 3, 3] of the ellipsoid with semi-axes
-    `semi`: a latitude-longitude net of the unit sphere (n_theta - 1 rings of
-    n_phi vertices plus two poles), turned by a random rotation drawn from
+    `semi`: an icosahedron subdivided `level` times (each triangle into four,
+    new vertices pushed onto the unit sphere; 20 * 4^level triangles, no
+    vertex joined to more than six), turned by a random rotation drawn from
     default_rng(seed) so that no vertex or edge sits on a special plane, then
     scaled per axis. Every vertex lies on the ellipsoid; shared vertices are
     the same numbers in every triangle that uses them."""
@@ -417,26 +418,32 @@ def triangulated_ellipsoid(semi, n_theta: int, n_phi: int, seed: int) -> np.ndar
     R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
                   [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
                   [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
-    verts = [(0.0, 0.0, 1.0)]
-    for i in range(1, n_theta):
-        th = math.pi * i / n_theta
-        for j in range(n_phi):
-            ph = 2 * math.pi * j / n_phi
-            verts.append((math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)))
-    verts.append((0.0, 0.0, -1.0))
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    verts = [np.array(v, dtype=np.float64) for v in
+             ((-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+              (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1))]
+    verts = [v / np.linalg.norm(v) for v in verts]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+             (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                m = verts[i] + verts[j]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
     V = (np.array(verts) @ R.T) * np.asarray(semi, dtype=np.float64)
-    ring = lambda i, j: 1 + (i - 1) * n_phi + (j % n_phi)
-    last = len(verts) - 1
-    tris = []
-    for j in range(n_phi):
-        tris.append((0, ring(1, j), ring(1, j + 1)))
-        tris.append((last, ring(n_theta - 1, j + 1), ring(n_theta - 1, j)))
-    for i in range(1, n_theta - 1):
-        for j in range(n_phi):
-            a, b, c, d = ring(i, j), ring(i, j + 1), ring(i + 1, j), ring(i + 1, j + 1)
-            tris.append((a, c, d))
-            tris.append((a, d, b))
-    return np.ascontiguousarray(V[np.array(tris)])
+    return np.ascontiguousarray(V[np.array(faces)])
 
 
 def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixed",
@@ -449,9 +456,9 @@ def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixe
     0.1 L sin(2 pi t + a_g) along y, yaw 0.2 sin(2 pi t + b_g) about z,
     translation U_g t along x with U_g in [0.1, 0.3] L per unit time.
     Draw order from default_rng(seed): for each fish a_g, b_g, U_g; then the
-    Fourier modes of u, v, w, p. mesh = (n_theta, n_phi): each fish's blank
-    region is the triangulated ellipsoid of the same semi-axes (ray-parity
-    hole cut), its rotation drawn from default_rng(seed + 1000 + g)."""
+    Fourier modes of u, v, w, p. mesh = a subdivision level: each fish's
+    blank region is the triangulated ellipsoid of the same semi-axes
+    (ray-parity hole cut), its rotation drawn from default_rng(seed + 1000 + g)."""
     rng = np.random.default_rng(seed)
     bg = stretched_background(bg_dims, extent=extent)
     grids = [bg]
@@ -464,7 +471,7 @@ def school_case(name, bg_dims, shell_dims, L, steps, seed, nf=2, precision="mixe
             g.blank_prm = tuple(L * a for a in FISH_BLANK)
             if mesh is not None:
                 g.blank_kind = BLANK_MESH
-                g.blank_mesh = triangulated_ellipsoid(g.blank_prm, mesh[0], mesh[1], seed + 1000 + len(grids))
+                g.blank_mesh = triangulated_ellipsoid(g.blank_prm, mesh, seed + 1000 + len(grids))
             g.outer = (0, nf, 0, 0, 0, 0)
             grids.append(g)
             centres.append((dc[0] + dx * L, dc[1] + dy * L, dc[2]))
@@ -501,17 +508,17 @@ def c3_small(steps=4, precision="fp64") -> Workload:
 
 def c3_mesh(steps=200) -> Workload:
     """C3 with each fish's blank region given as a closed surface
-    triangulation (48 x 96 latitude-longitude net, 9,024 triangles) instead
+    triangulation (icosahedron subdivided 4 times, 5,120 triangles) instead
     of the implicit ellipsoid: the hole cut by ray parity."""
     return school_case("C3M", (384, 256, 256), ((160, 96, 96), (128, 96, 64), (96, 64, 64), (64, 64, 64)),
-                       0.25, steps, seed=3, mesh=(48, 96))
+                       0.25, steps, seed=3, mesh=4)
 
 
 def c3_mesh_small(steps=4, precision="fp64") -> Workload:
-    """The small school with triangulated blank surfaces (12 x 24 net, 528
-    triangles per fish) for parity tests."""
+    """The small school with triangulated blank surfaces (icosahedron
+    subdivided twice, 320 triangles per fish) for parity tests."""
     return school_case("C3M-small", (128, 96, 96), ((24, 24, 20), (20, 20, 16), (16, 20, 16), (12, 16, 12)),
-                       0.25, steps, seed=33, precision=precision, dt=1.0 / 24.0, mesh=(12, 24))
+                       0.25, steps, seed=33, precision=precision, dt=1.0 / 24.0, mesh=2)
 
 
 # ---------------------------------------------------------------- many random shells
