@@ -766,6 +766,7 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     if (g.d.blank_kind == OV_BLANK_MESH) {
       rc = build_mesh_bins(ctx, g);
       if (rc != OV_OK) return rc;
+      ctx->has_mesh = true;
     }
   }
   long long total = ctx->node_off.back();

@@ -172,6 +172,7 @@ struct ov_ctx {
   int back_block = 256;        // its threads per block (64, 128 or 256)
   int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
   int frame_velocity = 0;      // executors: interpolated velocities in the receiver's frame
+  bool has_mesh = false;       // some grid's blank region is a triangulation
   std::string err;
 };
 
@@ -272,9 +273,27 @@ __host__ __device__ __forceinline__ bool mesh_edge_included(const double* u, con
   return dz > 0.0 || (dz == 0.0 && dy > 0.0);
 }
 
+// Whether the ray from (x, y, z) along +x crosses triangle t (9 doubles:
+// a, b, c, already counter-clockwise in the (y, z) projection).
+__host__ __device__ __forceinline__ bool mesh_crossed(const double* t, double x, double y, double z) {
+#pragma clang fp contract(off)
+  const double* a = t;
+  const double* b = t + 3;
+  const double* c = t + 6;
+  const double w0 = mesh_edge(b, c, y, z), w1 = mesh_edge(c, a, y, z), w2 = mesh_edge(a, b, y, z);
+  if (!(w0 > 0.0 || (w0 == 0.0 && mesh_edge_included(b, c)))) return false;
+  if (!(w1 > 0.0 || (w1 == 0.0 && mesh_edge_included(c, a)))) return false;
+  if (!(w2 > 0.0 || (w2 == 0.0 && mesh_edge_included(a, b)))) return false;
+  const double den = (w0 + w1) + w2;
+  const double num = (w0 * a[0] + w1 * b[0]) + w2 * c[0];
+  return num > x * den;
+}
+
 // tri: the triangles of each (y, z) bin stored contiguously (9 doubles
 // each), already in counter-clockwise projected order, edge-on ones left
-// out (both fixed at set-up with the same edge function).
+// out (both fixed at set-up with the same edge function). Two triangles are
+// loaded per round, so that their loads are in flight together (four held
+// more registers than they saved).
 __host__ __device__ inline bool mesh_parity(const double* tri, const int* start, const double* bx, const double* inv,
                                             const int* n, double x, double y, double z) {
 #pragma clang fp contract(off)
@@ -282,19 +301,14 @@ __host__ __device__ inline bool mesh_parity(const double* tri, const int* start,
   const int bin = mesh_bin(z, bx[2], inv[1], n[1]) * n[0] + mesh_bin(y, bx[1], inv[0], n[0]);
   const int e1 = start[bin + 1];
   bool odd = false;
-#pragma unroll 4
-  for (int e = start[bin]; e < e1; ++e) {
-    const double* a = tri + 9LL * e;
-    const double* b = a + 3;
-    const double* c = a + 6;
-    const double w0 = mesh_edge(b, c, y, z), w1 = mesh_edge(c, a, y, z), w2 = mesh_edge(a, b, y, z);
-    if (!(w0 > 0.0 || (w0 == 0.0 && mesh_edge_included(b, c)))) continue;
-    if (!(w1 > 0.0 || (w1 == 0.0 && mesh_edge_included(c, a)))) continue;
-    if (!(w2 > 0.0 || (w2 == 0.0 && mesh_edge_included(a, b)))) continue;
-    const double den = (w0 + w1) + w2;
-    const double num = (w0 * a[0] + w1 * b[0]) + w2 * c[0];
-    if (num > x * den) odd = !odd;
+  int e = start[bin];
+  for (; e + 1 < e1; e += 2) {
+    double t[2][9];
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 9; ++k) t[j][k] = tri[9LL * (e + j) + k];
+    for (int j = 0; j < 2; ++j) odd ^= mesh_crossed(t[j], x, y, z);
   }
+  if (e < e1) odd ^= mesh_crossed(tri + 9LL * e, x, y, z);
   return odd;
 }
 

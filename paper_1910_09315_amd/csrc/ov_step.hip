@@ -167,6 +167,7 @@ __device__ __noinline__ bool mesh_inside(const GridDev& G, double x, double y, d
 // FP64 decision for one node of grid A at world position w: first blanking
 // grid (ascending grid id, among the bits of mask) or -1. The body-frame
 // position is formed without fused multiply-adds, in the reference order.
+template <bool MESH>
 __device__ __forceinline__ int holecut_fp64(const HoleLds& L, const GridDev* __restrict__ grids, int A,
                                             const double w[3], unsigned long long mask) {
 #pragma clang fp contract(off)
@@ -180,8 +181,12 @@ __device__ __forceinline__ int holecut_fp64(const HoleLds& L, const GridDev* __r
     double x = (p[0] * d0 + p[3] * d1) + p[6] * d2;
     double y = (p[1] * d0 + p[4] * d1) + p[7] * d2;
     double z = (p[2] * d0 + p[5] * d1) + p[8] * d2;
-    const bool in = L.kind[B] == OV_BLANK_MESH ? mesh_inside(grids[B], x, y, z)
-                                                : blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
+    bool in;
+    if constexpr (MESH)
+      in = L.kind[B] == OV_BLANK_MESH ? mesh_inside(grids[B], x, y, z)
+                                      : blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
+    else
+      in = blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
     if (in) return B;
   }
   return -1;
@@ -202,14 +207,16 @@ constexpr float kHoleGuard = 1e-3f;
 // mask (a superset of those that can contain it) are tested in ascending
 // grid id; the first that contains the node is its cause. In FP32, a node
 // within the guard band of a surface is decided again in FP64.
-template <typename CT>
+// MESH: some grid's blank region is a triangulation (a variant of its own,
+// so that the other kernels keep their registers).
+template <typename CT, bool MESH>
 __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __restrict__ grids, int A, long long m,
                                             CT X, CT Y, CT Z, unsigned long long mask) {
   const double* pa = L.pose[A];
   if (sizeof(CT) == 8) {
     double w[3];
     world_exact(pa, (double)X, (double)Y, (double)Z, w);
-    return holecut_fp64(L, grids, A, w, mask);
+    return holecut_fp64<MESH>(L, grids, A, w, mask);
   }
   const float* pf = L.posef[A];
   const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
@@ -231,7 +238,7 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     // a padding far above FP32 error); otherwise in FP64
     const float* c = L.prmf[B];
     float f;
-    if (L.kind[B] != OV_BLANK_MESH) {
+    if (!MESH || L.kind[B] != OV_BLANK_MESH) {
       f = blank_measure_f32(L.kind[B], c, x, y, z);
     } else if (x < c[0] || x > c[3] || y < c[1] || y > c[4] || z < c[2] || z > c[5]) {
       f = 1.f;
@@ -258,7 +265,7 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     double Xd = gp(G.X)[m], Yd = gp(G.Y)[m], Zd = gp(G.Z)[m];
     double w[3];
     world_exact(pa, Xd, Yd, Zd, w);
-    cause = holecut_fp64(L, grids, A, w, mask);
+    cause = holecut_fp64<MESH>(L, grids, A, w, mask);
   }
   return cause;
 }
@@ -381,7 +388,7 @@ __global__ void __launch_bounds__(1024) k_holecut(const GridDev* __restrict__ gr
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         if (m + w >= nn) continue;
-        int cause = holecut_node<CT>(L, grids, A, m + w, X[r][w], Y[r][w], Z[r][w], L.allmask);
+        int cause = holecut_node<CT, true>(L, grids, A, m + w, X[r][w], Y[r][w], Z[r][w], L.allmask);
         fa[m + w] = (cause < 0 && !outerA) ? (uint8_t)OV_STATE_FIELD : node_flag(GR, m + w, cause, tile_hole, stamp);
       }
     }
@@ -578,7 +585,7 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, 
 // their 4 flags.
 static_assert(kSubI == 16 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a sub-tile with 4 nodes each");
 
-template <typename CT>
+template <typename CT, bool MESH>
 __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
                                            uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                            unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
@@ -615,7 +622,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (r >= n) continue;
-      const int cause = holecut_node<CT>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
+      const int cause = holecut_node<CT, MESH>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
       uint32_t f = OV_STATE_FIELD;
       if (cause >= 0) {
         f = kHole | (cause << 2);
@@ -644,7 +651,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
 // i0 .. i0 + 15 of row (j0 + l % 8, k0 + l / 8), loads their coordinates in
 // batches of 4, tests them against the blank regions of the sub-tile's mask
 // only and writes their 16 flags.
-template <typename CT>
+template <typename CT, bool MESH>
 __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
                                           uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                           unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
@@ -687,7 +694,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
       for (int r = 0; r < 4; ++r) {
         const int e = b0 + r;
         if (e >= n) continue;
-        const int cause = holecut_node<CT>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
+        const int cause = holecut_node<CT, MESH>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
         uint32_t f = OV_STATE_FIELD;
         if (cause >= 0) {
           f = kHole | (cause << 2);
@@ -728,7 +735,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
 // nodes, one candidate per block (cand_block) or per wavefront (cand_wave)
 // at a time. No list leaves the block, so nothing needs resetting between
 // steps.
-template <typename CT, bool WAVE>
+template <typename CT, bool WAVE, bool MESH>
 __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__ grids, int ngrids,
                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
                                                     const double4* __restrict__ spheres,
@@ -764,11 +771,11 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
     const int n = c_n;
     if (WAVE) {
       for (int c = threadIdx.x >> 6; c < n; c += 4)
-        cand_wave<CT>(L, TG, grids, flags, tile_info, uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
+        cand_wave<CT, MESH>(L, TG, grids, flags, tile_info, uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
                       tile_near, near_list, near_count, stats);
     } else {
       for (int c = 0; c < n; ++c)
-        cand_block<CT>(L, TG, grids, flags, tile_info, c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
+        cand_block<CT, MESH>(L, TG, grids, flags, tile_info, c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
                        near_list, near_count, stats);
     }
     __syncthreads();  // the list is rebuilt by the next round
@@ -840,13 +847,20 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, st, ctx->d_tile_near, \
       nl, nc, ctx->d_stats
     const bool mixed = ctx->precision == OV_MIXED;
+    const dim3 g((unsigned)cb), b(256);
+#define OV_SUB(CT, W)                                                                                  \
+  do {                                                                                                 \
+    if (ctx->has_mesh) hipLaunchKernelGGL((k_holecut_sub<CT, W, true>), g, b, 0, s, OV_SUB_ARGS);     \
+    else hipLaunchKernelGGL((k_holecut_sub<CT, W, false>), g, b, 0, s, OV_SUB_ARGS);                  \
+  } while (0)
     if (ctx->holecut_npl == 4) {
-      if (mixed) hipLaunchKernelGGL((k_holecut_sub<float, false>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
-      else hipLaunchKernelGGL((k_holecut_sub<double, false>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
+      if (mixed) OV_SUB(float, false);
+      else OV_SUB(double, false);
     } else {
-      if (mixed) hipLaunchKernelGGL((k_holecut_sub<float, true>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
-      else hipLaunchKernelGGL((k_holecut_sub<double, true>), dim3((unsigned)cb), dim3(256), 0, s, OV_SUB_ARGS);
+      if (mixed) OV_SUB(float, true);
+      else OV_SUB(double, true);
     }
+#undef OV_SUB
 #undef OV_SUB_ARGS
     return hipGetLastError();
   }
