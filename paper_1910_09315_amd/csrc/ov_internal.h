@@ -185,8 +185,14 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 // launchers (kernel files)
 // slot: which front-half scratch slot (0..kSlots-1) the step uses (the hole
 // cut and the fringe/compaction of one step must use the same slot)
-hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0);
-hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0);
+// gen: which of the slot's two near lists the step writes (and the fringe
+// pass reads); reset: instead of writing every flag, return only the tiles
+// on the slot's other near list (the previous step of this slot and flags
+// buffer) to their base flags, for callers whose flags buffer holds exactly
+// that step's result (the step executors).
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0,
+                          bool reset = false);
+hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0);
 int build_static_chunks(ov_ctx* ctx, hipStream_t s);
 // fused: the write kernel forms the superchunk offsets itself (no scan
 // kernel); only for callers whose next hole cut on this slot precedes the

@@ -57,6 +57,9 @@ struct ov_pipe {
   // the timed group runs alone: the next step's first group waits for it
   int after_group = -1;
   long long after_value = 0;
+  // per buffer set: steps started on it, and the near list its current step uses
+  long long uses[3] = {0, 0, 0};
+  int gen[3] = {0, 0, 0};
 };
 
 using namespace ov;
@@ -76,9 +79,16 @@ static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses
   ov_ctx* ctx = p->ctx;
   const ov_step_buffers& b = p->sets[k];
   const int slot = k;
-  if (stage == 0) return launch_holecut(ctx, poses, b.flags, s, slot);
+  if (stage == 0) {
+    // alternate the slot's two near lists; from the set's second step on,
+    // reset only the previous step's tiles (not under graphs, whose
+    // captured launches cannot alternate)
+    const int use = p->uses[k]++;
+    p->gen[k] = p->graphs ? 0 : (use & 1);
+    return launch_holecut(ctx, poses, b.flags, s, slot, p->gen[k], !p->graphs && use > 0);
+  }
   if (stage == 1) {
-    hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot);
+    hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot, p->gen[k]);
     if (e == hipSuccess)
       e = launch_compact(ctx, b.flags, b.q_grid, b.q_node, b.capacity, (long long*)b.d_count, s, slot, true);
     return e;
@@ -176,7 +186,9 @@ int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
   if (!p) return OV_EINVAL;
   if (p->t != 0) return pipe_fail(p, OV_ESTATE, "ov_pipe_use_graphs after the first submit");
   destroy_graphs(p);
+  for (int k = 0; k < 3; ++k) p->uses[k] = 0;  // the next direct step starts from a full fill
   if (!on) return OV_OK;
+  p->graphs = true;  // (captured steps write every flag and use near list 0)
   ov_ctx* ctx = p->ctx;
   const size_t per_set = 12 * ctx->grids.size();
   hipStream_t cap = nullptr;

@@ -561,6 +561,40 @@ __device__ __forceinline__ void flag_fill_body(uint8_t* __restrict__ flags, cons
 }
 
 // Block 0 also starts the step (new stamp, empty lists).
+// The step executors' start of a step on a flags buffer that holds the
+// previous step of its slot: every byte that step changed from the base
+// flags (holes, buffer layers) lies in a tile of its near list (a hole's own
+// tile is on it, and buffer layers are only written in listed tiles), so
+// only those tiles are returned to their base flags (a copy, or field for a
+// grid without outer layers): one workgroup per tile, a quarter row of 16
+// bytes per thread. Also starts the step as k_flag_fill does.
+__global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ grids, uint8_t* __restrict__ flags,
+                                                   const uint8_t* __restrict__ base,
+                                                   const int4* __restrict__ old_list,
+                                                   const int32_t* __restrict__ old_count,
+                                                   unsigned int* __restrict__ counter,
+                                                   unsigned int* __restrict__ d_stamp,
+                                                   int32_t* __restrict__ near_count,
+                                                   int32_t* __restrict__ chunk_list_count,
+                                                   int32_t* __restrict__ super_counts, long long n_super_counts) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
+       i += (long long)gridDim.x * blockDim.x)
+    super_counts[i] = 0;
+  const int n = *old_count;
+  static_assert(kTileI == 64 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a tile, 16 bytes a thread");
+  for (int idx = blockIdx.x; idx < n; idx += gridDim.x) {
+    const int4 info = old_list[idx];
+    const GridDev& G = grids[info.x];
+    const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int j = info.z * kTileJ + (row & 7), k = info.w * kTileK + (row >> 3);
+    if (j >= G.nj || k >= G.nk) continue;
+    const int i0 = info.y * kTileI + 16 * q, i1 = min(G.ni, i0 + 16);
+    const long long r = G.node_off + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+    for (int i = i0; i < i1; ++i) flags[r + i] = G.has_outer ? base[r + i] : (uint8_t)OV_STATE_FIELD;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, const uint8_t* __restrict__ base,
                                                   const long long* __restrict__ fill_ranges, int nranges,
                                                   long long fill_words, unsigned int* __restrict__ counter,
@@ -825,21 +859,30 @@ static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, h
                        chunks, ctx->d_tile_hole, st, ctx->d_stats);
 }
 
-hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot) {
+hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot, int gen,
+                          bool reset) {
   const int ng = (int)ctx->grids.size();
   const long long nt = ctx->total_tiles;
   unsigned int* counter = ctx->d_stamp;
   unsigned int* st = ctx->d_stamp + 1 + slot;
-  int4* nl = ctx->d_near_list + slot * std::max(1LL, nt);
-  int32_t* nc = ctx->d_near_count + slot;
+  int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, nt);
+  int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
   const long long nsc = kSuperSlots * ctx->nsuper;
   int32_t* sc = ctx->d_super_counts + (long long)slot * nsc;
   if (ctx->cull) {
     const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
                                                 (long long)ctx->num_cus * 32));
-    hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
-                       ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc);
+    if (reset) {
+      const int og = 1 - gen;
+      const long long rb = std::max(1LL, std::min(nt, (long long)ctx->num_cus * 8));
+      hipLaunchKernelGGL(k_flag_reset, dim3((unsigned)rb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
+                         ctx->d_near_list + (og * kSlots + slot) * std::max(1LL, nt),
+                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc);
+    } else {
+      hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
+                         ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc);
+    }
     const long long nsub = nt * kSubPerTile;
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
@@ -1095,10 +1138,10 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
   }
 }
 
-hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot) {
+hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot, int gen) {
   const int ng = (int)ctx->grids.size();
-  const int4* nl = ctx->d_near_list + slot * std::max(1LL, ctx->total_tiles);
-  const int32_t* nc = ctx->d_near_count + slot;
+  const int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, ctx->total_tiles);
+  const int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
   const unsigned int* st = ctx->d_stamp + 1 + slot;
   int32_t* clc = ctx->d_chunk_list_count + slot;
   // persistent blocks over the near list (its length is on the device)
