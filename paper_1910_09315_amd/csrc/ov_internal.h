@@ -144,7 +144,7 @@ struct ov_ctx {
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
   unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`
-  unsigned int* d_tile_hole = nullptr;        // per tile: stamp if it holds a hole (streaming hole cut)
+  unsigned int* d_tile_hole = nullptr;        // per slot and tile: the stamp of the slot's step if the tile holds a hole
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
   int4* d_near_list = nullptr;                // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;            // per slot

@@ -168,6 +168,28 @@ __device__ __forceinline__ bool cell_valid(const GridDev& G, const uint8_t* fl, 
   return ok;
 }
 
+// The same test that first looks the corners' tiles up in the step's map of
+// tiles holding a hole (a few bytes that stay in cache): a cell none of whose
+// tiles holds a hole is valid without reading its 8 flag bytes (each on its
+// own line). th: the map of the step's slot (null: read the flags).
+__device__ __forceinline__ bool cell_valid_map(const GridDev& G, const uint8_t* fl, int ci, int cj, int ck,
+                                               const unsigned int* th, unsigned int stamp) {
+  if (th) {
+    bool hole_tile = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      int i = ci + (c & 1), j = cj + ((c >> 1) & 1), k = ck + ((c >> 2) & 1);
+      i = (i == G.ni) ? 0 : i;
+      j = (j == G.nj) ? 0 : j;
+      k = (k == G.nk) ? 0 : k;
+      hole_tile |= gp(th)[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] ==
+                   stamp;
+    }
+    if (!hole_tile) return true;
+  }
+  return cell_valid(G, fl, ci, cj, ck);
+}
+
 // The same test on flags already loaded (the walk fetches a cell's corner
 // flags together with its corner coordinates: one memory round trip).
 __device__ __forceinline__ bool corners_valid(const uint8_t cf[8]) {
@@ -200,7 +222,8 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
 // perr bounds the error of each component of xi (FP32 only; 0 when exact).
 template <typename T>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
-                    int max_walk, bool& limit, int& visited, int* iters = nullptr) {
+                    int max_walk, bool& limit, int& visited, int* iters = nullptr, const unsigned int* th = nullptr,
+                    unsigned int stamp = 0) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   int hist[4] = {-1, -1, -1, -1};  // the last cells visited: a revisit ends the walk
@@ -234,7 +257,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
       const T es = (T)(2.0 * 1.7320508075688772 * perr) * inv_norm;
       if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
-        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid(G, fl, ci, cj, ck)) ? kFound : kToScan;
+        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid_map(G, fl, ci, cj, ck, th, stamp)) ? kFound : kToScan;
       }
       if (mg > -((sure ? (T)kMixedMargin : (T)kClearlyOutside) + es)) {
         cell = here;
@@ -243,7 +266,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     } else {
       if (conv && inside<T>(s, (T)kSTol)) {
         cell = here;
-        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid(G, fl, ci, cj, ck)) ? kFound : kToScan;
+        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid_map(G, fl, ci, cj, ck, th, stamp)) ? kFound : kToScan;
       }
     }
     if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
@@ -787,7 +810,8 @@ __global__ void __launch_bounds__(BS)
            int32_t* __restrict__ status, Warm warm, int max_walk, int32_t* __restrict__ dev_status,
            const T* __restrict__ fields,
            long long total_nodes, int interleaved, int frame_velocity, T* __restrict__ out,
-           long long* __restrict__ count_out, unsigned long long* __restrict__ stats) {
+           long long* __restrict__ count_out, unsigned long long* __restrict__ stats,
+           const unsigned int* __restrict__ tile_hole) {
   __shared__ double sp[kMaxGrids * 12];
   __shared__ int list_q[BS], list_st[BS];
   __shared__ int nlist;
@@ -809,7 +833,8 @@ __global__ void __launch_bounds__(BS)
     first_A = q_grid[q_first];
     first_m = q_node[q_first];
   }
-  const uint8_t now = (uint8_t)*warm.stamp;
+  const unsigned int stamp = *warm.stamp;
+  const uint8_t now = (uint8_t)stamp;
   const long long n = min(*d_count, cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (count_out) *count_out = *d_count;
@@ -865,12 +890,12 @@ __global__ void __launch_bounds__(BS)
           int cell = seed >= 0 ? seed : rep;
           T s[3];
           const uint8_t* fl = flags + G.node_off;
-          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
+          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp);
           if (r == kToScan && seed >= 0) {
             rep = gp(G.brep)[bin_of(G, xi)];
             if (rep >= 0 && rep != seed) {
               cell = rep;
-              r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters);
+              r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp);
             }
           }
           int how = OV_Q_FOUND;
@@ -1047,7 +1072,8 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
-      ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, count_out, ctx->d_stats
+      ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, count_out, ctx->d_stats,                  \
+      ctx->d_tile_hole + slot * std::max(1LL, ctx->total_tiles)
   const size_t lds = sizeof(GridDev) * ctx->grids.size();
   if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), lds, st, OV_BACK_ARGS);
   else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), lds, st, OV_BACK_ARGS);

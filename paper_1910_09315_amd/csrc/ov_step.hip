@@ -624,7 +624,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
                                            uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                            unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
                                            int4* __restrict__ near_list, int32_t* __restrict__ near_count,
-                                           unsigned long long* __restrict__ stats) {
+                                           unsigned int* __restrict__ tile_hole, unsigned long long* __restrict__ stats) {
   const int4 ti = tile_info[sub / kSubPerTile];
   const int A = uniform_i32(ti.x);
   const TileGeo& G = TG[A];
@@ -675,9 +675,13 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   int nr = n;
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
   if ((t & 63) == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
-  if (__syncthreads_or(hole) && t < 125)
-    mark_near(t, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-              near_list, near_count);
+  if (__syncthreads_or(hole)) {
+    if (t < 125)
+      mark_near(t, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                near_list, near_count);
+    else if (t == 128)
+      tile_hole[sub / kSubPerTile] = stamp;  // this step has a hole in the tile
+  }
 }
 
 // Candidate sub-tiles, one wavefront each at a time (the variant for many
@@ -690,7 +694,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
                                           uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
                                           unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
                                           int4* __restrict__ near_list, int32_t* __restrict__ near_count,
-                                          unsigned long long* __restrict__ stats) {
+                                          unsigned int* __restrict__ tile_hole, unsigned long long* __restrict__ stats) {
   const int lane = threadIdx.x & 63;
   const int4 ti = tile_info[sub / kSubPerTile];
   const int A = uniform_i32(ti.x);
@@ -755,10 +759,12 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
   int nr = n;
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
   if (lane == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
-  if (__any(hole))
+  if (__any(hole)) {
     for (int e = lane; e < 125; e += 64)
       mark_near(e, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
                 near_list, near_count);
+    if (lane == 0) tile_hole[sub / kSubPerTile] = stamp;  // this step has a hole in the tile
+  }
 }
 
 // The culled hole cut after the fill: each block takes an interleaved share
@@ -778,6 +784,7 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
                                                     unsigned int* __restrict__ tile_near,
                                                     int4* __restrict__ near_list,
                                                     int32_t* __restrict__ near_count,
+                                                    unsigned int* __restrict__ tile_hole,
                                                     unsigned long long* __restrict__ stats) {
   __shared__ HoleLds L;
   __shared__ TileGeo TG[kMaxGrids];
@@ -806,11 +813,11 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
     if (WAVE) {
       for (int c = threadIdx.x >> 6; c < n; c += 4)
         cand_wave<CT, MESH>(L, TG, grids, flags, tile_info, uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
-                      tile_near, near_list, near_count, stats);
+                            tile_near, near_list, near_count, tile_hole, stats);
     } else {
       for (int c = 0; c < n; ++c)
         cand_block<CT, MESH>(L, TG, grids, flags, tile_info, c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
-                       near_list, near_count, stats);
+                             near_list, near_count, tile_hole, stats);
     }
     __syncthreads();  // the list is rebuilt by the next round
   }
@@ -839,7 +846,8 @@ __global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restri
 }
 
 template <typename CT>
-static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, unsigned int* st) {
+static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, unsigned int* st,
+                             unsigned int* tile_hole) {
   int block = ctx->holecut_block;
   int R = ctx->holecut_npt;  // 16-byte vectors per lane per chunk
   long long span = (long long)block * Vec16<CT>::W * R;
@@ -850,13 +858,13 @@ static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, h
   int ng = (int)ctx->grids.size();
   if (R == 4)
     hipLaunchKernelGGL((k_holecut<CT, 4>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
+                       chunks, tile_hole, st, ctx->d_stats);
   else if (R == 2)
     hipLaunchKernelGGL((k_holecut<CT, 2>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
+                       chunks, tile_hole, st, ctx->d_stats);
   else
     hipLaunchKernelGGL((k_holecut<CT, 1>), dim3((unsigned)grid), dim3(block), 0, s, ctx->d_grids, ng, poses, flags,
-                       chunks, ctx->d_tile_hole, st, ctx->d_stats);
+                       chunks, tile_hole, st, ctx->d_stats);
 }
 
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot, int gen,
@@ -867,6 +875,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   unsigned int* st = ctx->d_stamp + 1 + slot;
   int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, nt);
   int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
+  unsigned int* th = ctx->d_tile_hole + slot * std::max(1LL, nt);
   int32_t* clc = ctx->d_chunk_list_count + slot;
   const long long nsc = kSuperSlots * ctx->nsuper;
   int32_t* sc = ctx->d_super_counts + (long long)slot * nsc;
@@ -888,7 +897,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
 #define OV_SUB_ARGS                                                                                             \
   ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, st, ctx->d_tile_near, \
-      nl, nc, ctx->d_stats
+      nl, nc, th, ctx->d_stats
     const bool mixed = ctx->precision == OV_MIXED;
     const dim3 g((unsigned)cb), b(256);
 #define OV_SUB(CT, W)                                                                                  \
@@ -909,10 +918,10 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   }
   hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
                      counter, st, nc, clc, sc, nsc);
-  if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st);
-  else launch_holecut_t<double>(ctx, poses, flags, s, st);
+  if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st, th);
+  else launch_holecut_t<double>(ctx, poses, flags, s, st, th);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
-  hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, ctx->d_tile_hole,
+  hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, th,
                      ctx->d_tile_info, nt, st, ctx->d_tile_near, nl, nc);
   return hipGetLastError();
 }
