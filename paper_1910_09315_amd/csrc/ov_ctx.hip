@@ -625,8 +625,9 @@ int ov_grid_set_blank_mesh(ov_ctx* ctx, int32_t grid, const double* tri, int64_t
   return OV_OK;
 }
 
-// The (y, z) bins of a surface triangulation: about one triangle per bin
-// on average, at most 256 per axis.
+// The (y, z) bins of a surface triangulation: 2 sqrt(n_tri) per axis (at
+// most 512), so that a node meets few more triangles than the surface
+// layers above it.
 static int build_mesh_bins(ov_ctx* ctx, GridHost& g) {
   const long long ntri = (long long)g.mesh.size() / 9;
   const double* t = g.mesh.data();
@@ -640,7 +641,7 @@ static int build_mesh_bins(ov_ctx* ctx, GridHost& g) {
       box[d] = std::min(box[d], t[3 * k + d]);
       box[3 + d] = std::max(box[3 + d], t[3 * k + d]);
     }
-  const int n = (int)std::max(1.0, std::min(256.0, std::floor(std::sqrt((double)ntri))));
+  const int n = (int)std::max(1.0, std::min(512.0, std::floor(2.0 * std::sqrt((double)ntri))));
   for (int a = 0; a < 2; ++a) {
     const double ext = box[4 + a] - box[1 + a];
     g.d.mn[a] = ext > 0.0 ? n : 1;
