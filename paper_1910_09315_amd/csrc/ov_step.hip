@@ -167,7 +167,12 @@ __device__ __noinline__ bool mesh_inside(const GridDev& G, double x, double y, d
 // FP64 decision for one node of grid A at world position w: first blanking
 // grid (ascending grid id, among the bits of mask) or -1. The body-frame
 // position is formed without fused multiply-adds, in the reference order.
-template <bool MESH>
+// CHEAP: a triangulated region whose voxel the surface may cross is not
+// tested here; the node's decision is deferred (kDeferNode) to a balanced
+// pass of the whole workgroup.
+constexpr int kDeferNode = -2;
+
+template <bool MESH, bool CHEAP = false>
 __device__ __forceinline__ int holecut_fp64(const HoleLds& L, const GridDev* __restrict__ grids, int A,
                                             const double w[3], unsigned long long mask) {
 #pragma clang fp contract(off)
@@ -182,11 +187,21 @@ __device__ __forceinline__ int holecut_fp64(const HoleLds& L, const GridDev* __r
     double y = (p[1] * d0 + p[4] * d1) + p[7] * d2;
     double z = (p[2] * d0 + p[5] * d1) + p[8] * d2;
     bool in;
-    if constexpr (MESH)
-      in = L.kind[B] == OV_BLANK_MESH ? mesh_inside(grids[B], x, y, z)
-                                      : blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
-    else
+    if constexpr (MESH) {
+      if (L.kind[B] != OV_BLANK_MESH) {
+        in = blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
+      } else if (CHEAP) {
+        const double* bx = L.box[B];
+        const bool in_box = !(x < bx[0] || x > bx[3] || y < bx[1] || y > bx[4] || z < bx[2] || z > bx[5]);
+        const int v = in_box ? mesh_voxel(grids[B], x, y, z) : 0;
+        if (v == 2) return kDeferNode;
+        in = v == 1;
+      } else {
+        in = mesh_inside(grids[B], x, y, z);
+      }
+    } else {
       in = blank_inside_fp64(L.kind[B], L.prm[B], x, y, z);
+    }
     if (in) return B;
   }
   return -1;
@@ -209,14 +224,16 @@ constexpr float kHoleGuard = 1e-3f;
 // within the guard band of a surface is decided again in FP64.
 // MESH: some grid's blank region is a triangulation (a variant of its own,
 // so that the other kernels keep their registers).
-template <typename CT, bool MESH>
+// DEFER: return kDeferNode instead of running a triangulation's parity
+// test (the caller decides those nodes in a balanced pass).
+template <typename CT, bool MESH, bool DEFER = false>
 __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __restrict__ grids, int A, long long m,
                                             CT X, CT Y, CT Z, unsigned long long mask) {
   const double* pa = L.pose[A];
   if (sizeof(CT) == 8) {
     double w[3];
     world_exact(pa, (double)X, (double)Y, (double)Z, w);
-    return holecut_fp64<MESH>(L, grids, A, w, mask);
+    return holecut_fp64<MESH, DEFER>(L, grids, A, w, mask);
   }
   const float* pf = L.posef[A];
   const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
@@ -265,9 +282,19 @@ __device__ __forceinline__ int holecut_node(const HoleLds& L, const GridDev* __r
     double Xd = gp(G.X)[m], Yd = gp(G.Y)[m], Zd = gp(G.Z)[m];
     double w[3];
     world_exact(pa, Xd, Yd, Zd, w);
-    cause = holecut_fp64<MESH>(L, grids, A, w, mask);
+    cause = holecut_fp64<MESH, DEFER>(L, grids, A, w, mask);
   }
   return cause;
+}
+
+// The full FP64 decision of node m of grid A from its FP64 coordinates.
+template <bool MESH>
+__device__ __forceinline__ int holecut_node_exact(const HoleLds& L, const GridDev* __restrict__ grids, int A,
+                                                  long long m, unsigned long long mask) {
+  const GridDev& G = grids[A];
+  double w[3];
+  world_exact(L.pose[A], gp(G.X)[m], gp(G.Y)[m], gp(G.Z)[m], w);
+  return holecut_fp64<MESH>(L, grids, A, w, mask);
 }
 
 // Flag byte of a node given its hole cause (-1: none). Holes mark their
@@ -638,38 +665,104 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   const bool outer = L.outer[A] != 0;
   const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
   bool hole = false;
-  if (ok) {
-    const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
-    uint8_t* dst = flags + L.off[A] + m0;
-    gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
-    gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
-    gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
-    CT X[4], Y[4], Z[4];
+  if constexpr (!MESH) {
+    if (ok) {
+      const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+      uint8_t* dst = flags + L.off[A] + m0;
+      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+      CT X[4], Y[4], Z[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (r < n) {
-        X[r] = Xa[r];
-        Y[r] = Ya[r];
-        Z[r] = Za[r];
-      }
-    uint32_t word = 0u;
+      for (int r = 0; r < 4; ++r)
+        if (r < n) {
+          X[r] = Xa[r];
+          Y[r] = Ya[r];
+          Z[r] = Za[r];
+        }
+      uint32_t word = 0u;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (r >= n) continue;
-      const int cause = holecut_node<CT, MESH>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
-      uint32_t f = OV_STATE_FIELD;
-      if (cause >= 0) {
-        f = kHole | (cause << 2);
-        hole = true;
-      } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
-        f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+      for (int r = 0; r < 4; ++r) {
+        if (r >= n) continue;
+        const int cause = holecut_node<CT, false>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
+        uint32_t f = OV_STATE_FIELD;
+        if (cause >= 0) {
+          f = kHole | (cause << 2);
+          hole = true;
+        } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
+          f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+        }
+        word |= f << (8 * r);
       }
-      word |= f << (8 * r);
+      if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(dst) = word;
+      } else {
+        for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
+      }
     }
-    if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
-      *reinterpret_cast<uint32_t*>(dst) = word;
-    } else {
-      for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
+  } else {
+    const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
+    int cz[4] = {-1, -1, -1, -1};
+    if (ok) {
+      gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
+      gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
+      gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
+      CT X[4], Y[4], Z[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < n) {
+          X[r] = Xa[r];
+          Y[r] = Ya[r];
+          Z[r] = Za[r];
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < n) cz[r] = holecut_node<CT, MESH, MESH>(L, grids, A, m0 + r, X[r], Y[r], Z[r], mask);
+    }
+    if constexpr (MESH) {
+      // nodes near a triangulated surface cluster in a few lanes: their parity
+      // tests are shared out over the whole workgroup, one node per thread
+      __shared__ int dq_node[1024];
+      __shared__ int dq_res[1024];
+      __shared__ int dq_n;
+      if (t == 0) dq_n = 0;
+      __syncthreads();
+      int slot[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (cz[r] == kDeferNode) {
+          slot[r] = atomicAdd(&dq_n, 1);
+          dq_node[slot[r]] = m0 + r;
+        }
+      __syncthreads();
+      const int qn = dq_n;
+      for (int q = t; q < qn; q += blockDim.x) dq_res[q] = holecut_node_exact<MESH>(L, grids, A, dq_node[q], mask);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (cz[r] == kDeferNode) cz[r] = dq_res[slot[r]];
+    }
+    if (ok) {
+      uint8_t* dst = flags + L.off[A] + m0;
+      uint32_t word = 0u;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r >= n) continue;
+        const int cause = cz[r];
+        uint32_t f = OV_STATE_FIELD;
+        if (cause >= 0) {
+          f = kHole | (cause << 2);
+          hole = true;
+        } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
+          f = kFringe | (OV_CAUSE_BOUNDARY << 2);
+        }
+        word |= f << (8 * r);
+      }
+      if (n == 4 && (((uintptr_t)dst) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(dst) = word;
+      } else {
+        for (int e = 0; e < n; ++e) dst[e] = (uint8_t)(word >> (8 * e));
+      }
     }
   }
   int nr = n;
