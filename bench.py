@@ -80,9 +80,11 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(w, budget_s: float) -> dict:
+def cpu_baseline(w, budget_s: float, check=None) -> tuple[dict, dict | None]:
     """The CPU oracle, untuned, on a bounded sample of the same workload:
-    whole steps (all five stages) from step 0 on, until `budget_s` of work."""
+    whole steps (all five stages) from step 0 on, until `budget_s` of work.
+    check = (t, GPU result of step t): afterwards (untimed) the oracle's step
+    t is compared with it; the second return value holds the error norms."""
     import oracle
     o = oracle.Oracle(w.grids, w.nf)
     for g in range(w.ngrids):
@@ -94,9 +96,35 @@ def cpu_baseline(w, budget_s: float) -> dict:
         el += time.perf_counter() - t0
         pts += len(r["q_grid"])
         steps += 1
-    return {"value": pts / el, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+    base = {"value": pts / el, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{w.name} steps 0..{steps - 1} ({steps} full steps, {pts} queries, {el:.1f} s), "
                       f"control cells built beforehand; host CPU {cpu_model()}"}
+    return base, (error_norms(o.step(w.poses[check[0]], w.fields), check[1], check[0]) if check else None)
+
+
+def error_norms(ref: dict, gpu: dict, t: int) -> dict:
+    """How step t of the timed executor compares with the oracle's: identical
+    flags and query lists, the share of identical donors, and the value
+    errors over queries with the same donor, relative to each field's
+    largest magnitude."""
+    import numpy as np
+    n = len(ref["q_grid"])
+    same_q = gpu["count"] == n and np.array_equal(gpu["q_grid"], ref["q_grid"]) and \
+        np.array_equal(gpu["q_node"], ref["q_node"])
+    out = {"step": t, "queries": n, "flags_identical": bool(np.array_equal(gpu["flags"], ref["flags"])),
+           "queries_identical": bool(same_q)}
+    if same_q and n:
+        found = ref["donor_grid"] >= 0
+        same = found & (gpu["donor_grid"] == ref["donor_grid"]) & (gpu["donor_cell"] == ref["donor_cell"])
+        out["orphans_identical"] = bool(np.array_equal(gpu["donor_grid"] < 0, ~found))
+        out["donors_identical_frac"] = round(float(same.sum() / max(1, found.sum())), 6)
+        if same.any() and "values" in gpu:
+            rv, gv = ref["values"][:, same], gpu["values"][:, same]
+            scale = np.maximum(np.abs(rv).max(axis=1, keepdims=True), 1e-300)
+            e = np.abs(gv - rv) / scale
+            out["value_err_max_rel"] = float(f"{e.max():.3e}")
+            out["value_err_rms_rel"] = float(f"{np.sqrt(np.mean(e * e)):.3e}")
+    return out
 
 
 def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
@@ -399,7 +427,53 @@ def measure(args):
         b = pipe.bufs[last % pipe.nsets] if pipe is not None else a.buf
         out["next_rows"] = measure_next_rows(a, b, args.apply_nrhs, reps=50)
         log(f"[bench] next rows: {out['next_rows']}")
+    if native and args.step_report:
+        out["step_report"], last_result = step_report(pipe, poses, w, args.warmup + args.steps,
+                                                      min(48, args.steps), dev)
+        log(f"[bench] step report: {out['step_report']}")
+        out["_last_result"] = last_result
     return out, w
+
+
+def step_report(pipe, poses, w, t0: int, n: int, dev):
+    """Untimed, after the measured steps: 3 x n more steps through the same
+    executor, with hip events (recorded by the executor on the stream each
+    stage runs on) around one stage of every step in turn, for the median
+    and p90 of each stage's duration under the overlap the timed run has;
+    then the outcome mix of the last step (walk, fallback scan, FP64
+    correction, orphan)."""
+    import numpy as np
+    import torch
+    rep = {"steps_per_stage": n, "timing": "hip events around one stage of every step, on its stream, "
+                                         "with the other stages of neighbouring steps running beside it"}
+    names = ("hole_cut", "fringe_compact", "back_half")
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    t = t0
+    for st, name in enumerate(names):
+        idx = torch.arange(t, t + n, device=dev) % w.steps
+        pp = poses[idx].contiguous()
+        torch.cuda.synchronize(dev)
+        pipe.native.stage_times(0)
+        pipe.native.set_timing(1, st)
+        pipe.submit_many(t, pp, counts)
+        pipe.join()
+        torch.cuda.synchronize(dev)
+        pipe.native.set_timing(0)
+        us = np.array(pipe.native.stage_times(n)) * 1e3
+        rep[name] = {"median_us": round(float(np.median(us)), 2), "p90_us": round(float(np.percentile(us, 90)), 2)}
+        t += n
+    last = t - 1
+    r = pipe.results(last)
+    st = r["status"]
+    kind = st & 3
+    m = max(1, len(st))
+    rep["outcomes_last_step"] = {
+        "step": last % w.steps, "queries": int(len(st)),
+        "walk_frac": round(float(np.sum(kind == 1)) / m, 6),
+        "fallback_scan_frac": round(float(np.sum(kind == 2)) / m, 6),
+        "orphan_frac": round(float(np.sum(kind == 0)) / m, 6),
+        "fp64_fixed_frac": round(float(np.sum((st & 4) != 0)) / m, 6)}
+    return rep, (last % w.steps, r)
 
 
 def main():
@@ -443,6 +517,8 @@ def main():
     ap.add_argument("--apply-nrhs", type=int, default=4, help="vectors per application of the interpolation matrix")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-step-report", dest="step_report", action="store_false",
+                    help="skip the per-stage durations and outcome mix measured after the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB 5 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -478,6 +554,7 @@ def main():
         a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, None, None, None, 0
         a2.roofline = "none"
         o2, w2 = measure(a2)
+        o2.pop("_last_result", None)
         out["forms"] = {
             "note": "the same metric for the plain FP64 form (value above) and the mixed-precision batched form",
             "plain_fp64": {"workload": out["config"]["workload"], "value": out["value"],
@@ -485,12 +562,16 @@ def main():
             "mixed_batched": {"workload": o2["config"]["workload"], "value": o2["value"],
                               "ms_per_step": o2["ms_per_step"], "steps": o2["steps"],
                               "queries_per_step_mean": o2["config"]["queries_per_step_mean"],
-                              "tuned": o2["config"]["tuned"], "next_rows": o2.get("next_rows")},
+                              "tuned": o2["config"]["tuned"], "next_rows": o2.get("next_rows"),
+                              "step_report": o2.get("step_report")},
             "mixed_batched_over_plain_fp64": round(o2["value"] / out["value"], 3)}
         del w2
+    last_result = out.pop("_last_result", None)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        out["cpu_baseline"], err = cpu_baseline(w, args.cpu_budget, check=last_result)
+        if err is not None:
+            out["step_report"]["vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 
