@@ -1427,6 +1427,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
                                                                    int32_t* __restrict__ q_node, long long capacity) {
   __shared__ int wsum[kCompactThreads / 64];
   __shared__ long long off[kMaxGrids + 1];
+  __shared__ uint16_t qofs[kCompactChunk];  // the chunk's fringe nodes (offsets in the chunk), in order
   extern __shared__ long long soff[];  // FUSED: nsuper + 1 superchunk offsets
   // read up front, beside the superchunk counts: the list length, the stamp
   // and this block's first entry (the list has room for every chunk; the
@@ -1471,19 +1472,27 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
     }
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    long long pos = base + before + (inc - cnt);
+    int before = 0, tot = 0;
+    for (int w = 0; w < kCompactThreads / 64; ++w) {
+      if (w < wave) before += wsum[w];
+      tot += wsum[w];
+    }
+    // the nodes go to LDS in order, then out with consecutive threads on
+    // consecutive queries (coalesced stores)
+    int p = before + (inc - cnt);
     while (mask) {
-      int q = __ffs(mask) - 1;
+      const int q = __ffs(mask) - 1;
       mask &= mask - 1;
-      if (pos < capacity) {
-        long long n = n0 + q;
-        int A = grid_of_node(off, ngrids, n);
-        q_grid[pos] = A;
-        q_node[pos] = (int32_t)(n - off[A]);
-      }
-      ++pos;
+      qofs[p++] = (uint16_t)(threadIdx.x * 16 + q);
+    }
+    __syncthreads();
+    const int lim = (int)min((long long)tot, capacity - base);
+    const long long c0 = ch * kCompactChunk;
+    for (int x = threadIdx.x; x < lim; x += kCompactThreads) {
+      const long long n = c0 + qofs[x];
+      const int A = grid_of_node(off, ngrids, n);
+      q_grid[base + x] = A;
+      q_node[base + x] = (int32_t)(n - off[A]);
     }
     __syncthreads();
   }
