@@ -439,13 +439,13 @@ def step_report(pipe, poses, w, t0: int, n: int, dev):
     """Untimed, after the measured steps: 3 x n more steps through the same
     executor, with hip events (recorded by the executor on the stream each
     stage runs on) around one stage of every step in turn, for the median
-    and p90 of each stage's duration under the overlap the timed run has;
-    then the outcome mix of the last step (walk, fallback scan, FP64
-    correction, orphan)."""
+    and p90 of each stage's duration on its own; then the outcome mix of
+    the last step (walk, fallback scan, FP64 correction, orphan)."""
     import numpy as np
     import torch
-    rep = {"steps_per_stage": n, "timing": "hip events around one stage of every step, on its stream, "
-                                         "with the other stages of neighbouring steps running beside it"}
+    rep = {"steps_per_stage": n, "timing": "hip events around one stage of every step, on its stream; while a "
+                                         "stage is timed the executor holds the other stages back, so each "
+                                         "duration is that stage alone"}
     names = ("hole_cut", "fringe_compact", "back_half")
     counts = torch.zeros(n, dtype=torch.int64, device=dev)
     t = t0

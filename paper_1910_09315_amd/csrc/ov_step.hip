@@ -618,7 +618,15 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
     if (j >= G.nj || k >= G.nk) continue;
     const int i0 = info.y * kTileI + 16 * q, i1 = min(G.ni, i0 + 16);
     const long long r = G.node_off + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-    for (int i = i0; i < i1; ++i) flags[r + i] = G.has_outer ? base[r + i] : (uint8_t)OV_STATE_FIELD;
+    uint8_t* dst = flags + r + i0;
+    if (i1 - i0 == 16 && ((((uintptr_t)dst) | ((uintptr_t)(base + r + i0))) & 15) == 0) {
+      // a whole aligned 16-byte run: one vector store (base flags share the layout)
+      constexpr uint32_t fw = 0x01010101u * (uint32_t)OV_STATE_FIELD;
+      *reinterpret_cast<uint4*>(dst) =
+          G.has_outer ? *reinterpret_cast<const uint4*>(base + r + i0) : make_uint4(fw, fw, fw, fw);
+    } else {
+      for (int i = i0; i < i1; ++i) flags[r + i] = G.has_outer ? base[r + i] : (uint8_t)OV_STATE_FIELD;
+    }
   }
 }
 
