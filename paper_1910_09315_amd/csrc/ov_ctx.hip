@@ -706,14 +706,17 @@ static int build_mesh_bins(ov_ctx* ctx, GridHost& g) {
   HIPCHK(hipMemcpy(g.mstart, st2.data(), sizeof(int) * st2.size(), hipMemcpyHostToDevice), "surface bins copy");
   g.d.mtri = g.mtri;
   g.d.mstart = g.mstart;
-  // voxels: about 128 along the box's longest side; a voxel met by a
-  // triangle's box padded by 1e-4 of that side is "the surface may pass";
-  // every other voxel takes the ray-parity status of its centre, which
-  // holds for every point within the padding of the voxel (no surface
-  // there): also for a node whose FP32 body-frame position lies in it (its
-  // FP32 error is far below the padding)
+  // voxels: about 256 along the box's longest side. A voxel grown by 1e-4
+  // of that side on every face is "the surface may pass" (status 2) when
+  // some triangle can meet it: the voxel lies in the triangle's box and the
+  // triangle's plane crosses it (two of the separating axes of a triangle
+  // and a box; no voxel a triangle meets fails either). Every other voxel
+  // takes the ray-parity status of its centre, which holds for every point
+  // of the grown voxel (no surface there): also for a node whose FP32
+  // body-frame position lies in the voxel (its FP32 error is far below the
+  // growth)
   const double ext = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
-  const double h = ext / 128.0, pad = 1e-4 * ext;
+  const double h = ext / 256.0, pad = 1e-4 * ext;
   for (int d = 0; d < 3; ++d) {
     const double e = box[3 + d] - box[d];
     g.d.mvn[d] = e > 0.0 ? (int)std::min(256.0, std::max(1.0, std::ceil(e / h))) : 1;
@@ -730,9 +733,29 @@ static int build_mesh_bins(ov_ctx* ctx, GridHost& g) {
       r[d][0] = mesh_bin(lo, box[d], g.d.mvinv[d], g.d.mvn[d]);
       r[d][1] = mesh_bin(hi, box[d], g.d.mvinv[d], g.d.mvn[d]);
     }
+    // the plane: unit normal; a voxel (half sizes e_d, grown by pad) meets
+    // it iff |n . (centre - a)| <= sum_d |n_d| (e_d + pad)
+    double nv[3] = {(a[4] - a[1]) * (a[8] - a[2]) - (a[5] - a[2]) * (a[7] - a[1]),
+                    (a[5] - a[2]) * (a[6] - a[0]) - (a[3] - a[0]) * (a[8] - a[2]),
+                    (a[3] - a[0]) * (a[7] - a[1]) - (a[4] - a[1]) * (a[6] - a[0])};
+    const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    const bool plane = nl > 0.0 && std::isfinite(nl);
+    double rad = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      nv[d] = plane ? nv[d] / nl : 0.0;
+      rad += std::fabs(nv[d]) * (0.5 / g.d.mvinv[d] + pad);
+    }
+    rad *= 1.0 + 1e-9;  // (rounding of the test itself)
     for (int z = r[2][0]; z <= r[2][1]; ++z)
       for (int y = r[1][0]; y <= r[1][1]; ++y)
-        for (int x = r[0][0]; x <= r[0][1]; ++x) vox[((size_t)z * vy + y) * vx + x] = 2;
+        for (int x = r[0][0]; x <= r[0][1]; ++x) {
+          if (plane) {
+            const double cx = box[0] + (x + 0.5) / g.d.mvinv[0], cy = box[1] + (y + 0.5) / g.d.mvinv[1],
+                         cz = box[2] + (z + 0.5) / g.d.mvinv[2];
+            if (std::fabs(nv[0] * (cx - a[0]) + nv[1] * (cy - a[1]) + nv[2] * (cz - a[2])) > rad) continue;
+          }
+          vox[((size_t)z * vy + y) * vx + x] = 2;
+        }
   }
   for (int z = 0; z < vz; ++z)
     for (int y = 0; y < vy; ++y)
