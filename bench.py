@@ -96,9 +96,29 @@ def cpu_baseline(w, budget_s: float, check=None) -> tuple[dict, dict | None]:
         el += time.perf_counter() - t0
         pts += len(r["q_grid"])
         steps += 1
-    base = {"value": pts / el, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    base = {"value": pts / el, "unit": "points/s", "cores": cores, "kind": "oracle",
             "sample": f"{w.name} steps 0..{steps - 1} ({steps} full steps, {pts} queries, {el:.1f} s), "
-                      f"control cells built beforehand; host CPU {cpu_model()}"}
+                      f"control cells built beforehand; host CPU {cpu_model()}, os.cpu_count() "
+                      f"{os.cpu_count()}, affinity mask {affinity} CPUs"}
+    # the same steps on one thread, while they fit in half the budget
+    one = None
+    if cores > 1 and el / steps * cores <= budget_s / 2:
+        oracle.set_threads(1)
+        p1, e1, s1 = 0, 0.0, 0
+        while (s1 == 0 or e1 < budget_s / 2) and s1 < steps:
+            t0 = time.perf_counter()
+            r = o.step(w.poses[s1], w.fields)
+            e1 += time.perf_counter() - t0
+            p1 += len(r["q_grid"])
+            s1 += 1
+        oracle.set_threads(cores)
+        one = {"value": round(p1 / e1, 1), "sample": f"steps 0..{s1 - 1} ({s1} steps, {e1:.1f} s)"}
+    base["one_thread"] = one
     return base, (error_norms(o.step(w.poses[check[0]], w.fields), check[1], check[0]) if check else None)
 
 

@@ -75,6 +75,8 @@ def lib():
         L.orc_weights.restype = None
         L.orc_weights.argtypes = [_P, _P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_frame_velocity.restype = None
         L.orc_frame_velocity.argtypes = [_P, ctypes.c_int64, _P, _P, _P]
         L.orc_interp_matrix.restype = None
@@ -91,6 +93,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (for timing)."""
+    lib().orc_set_threads(int(n))
 
 
 class Oracle:

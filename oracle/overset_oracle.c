@@ -83,6 +83,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* The thread count of the following parallel regions (n >= 1; timing only). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------ transform */
 /* x_i = ((R_i0 X + R_i1 Y) + R_i2 Z) + c_i ; pose = R row-major (9) then c (3). */
 static void apply_pose(const double *p, double X, double Y, double Z, double out[3]) {
