@@ -733,22 +733,27 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
       __shared__ int dq_node[1024];
       __shared__ int dq_res[1024];
       __shared__ int dq_n;
+      bool deferred = false;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) deferred |= cz[r] == kDeferNode;
       if (t == 0) dq_n = 0;
-      __syncthreads();
-      int slot[4];
+      if (__syncthreads_or(deferred)) {  // (most candidate sub-tiles have none)
+        int slot[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (cz[r] == kDeferNode) {
-          slot[r] = atomicAdd(&dq_n, 1);
-          dq_node[slot[r]] = m0 + r;
-        }
-      __syncthreads();
-      const int qn = dq_n;
-      for (int q = t; q < qn; q += blockDim.x) dq_res[q] = holecut_node_exact<MESH>(L, grids, A, dq_node[q], mask);
-      __syncthreads();
+        for (int r = 0; r < 4; ++r)
+          if (cz[r] == kDeferNode) {
+            slot[r] = atomicAdd(&dq_n, 1);
+            dq_node[slot[r]] = m0 + r;
+          }
+        __syncthreads();
+        const int qn = dq_n;
+        for (int q = t; q < qn; q += blockDim.x)
+          dq_res[q] = holecut_node_exact<MESH>(L, grids, A, dq_node[q], mask);
+        __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (cz[r] == kDeferNode) cz[r] = dq_res[slot[r]];
+        for (int r = 0; r < 4; ++r)
+          if (cz[r] == kDeferNode) cz[r] = dq_res[slot[r]];
+      }
     }
     if (ok) {
       uint8_t* dst = flags + L.off[A] + m0;
@@ -1346,7 +1351,9 @@ __device__ __forceinline__ void super_scan(int32_t* __restrict__ super_counts, l
   }
 }
 
-// Pass (1): the counts.
+// Pass (1): the counts. One wavefront per listed chunk (64 lanes x 4 x 16
+// bytes), so that a block holds four chunks in flight and no block barrier
+// sits on a chunk's path.
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
                                                                    unsigned long long* __restrict__ counts,
                                                                    int32_t* __restrict__ super_counts,
@@ -1354,26 +1361,25 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
                                                                    const int32_t* __restrict__ chunk_list_count,
                                                                    long long n_static,
                                                                    const unsigned int* __restrict__ d_stamp) {
-  __shared__ int red[kCompactThreads / 64];
-  // the list length, the stamp and this block's first entry in one round
-  // trip (the list has room for every chunk; the grid has no more blocks)
+  static_assert(kCompactChunk == 64 * 4 * 16, "a wavefront covers a chunk in four 16-byte rounds");
+  constexpr int kWaves = kCompactThreads / 64;
   const long long nl = n_static + *chunk_list_count;
   const unsigned int stamp = *d_stamp;
-  const int32_t first = chunk_list[blockIdx.x];
-  for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
-    const long long ch = e == (long long)blockIdx.x ? first : chunk_list[e];
-    uint32_t mask;
-    int cnt = count_fringe16(flags, ch * kCompactChunk + threadIdx.x * 16, total, mask);
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int sum = 0;
-      for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[w];
-      counts[ch] = ((unsigned long long)stamp << 32) | (unsigned int)sum;
-      if (sum) atomicAdd(&super_counts[(ch / kSuperChunk) * kSuperSlots + ch % kSuperSlots], sum);
+  const int lane = threadIdx.x & 63;
+  const long long w0 = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6), nw = (long long)gridDim.x * kWaves;
+  for (long long e = w0; e < nl; e += nw) {
+    const long long ch = chunk_list[e];
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t mask;
+      cnt += count_fringe16(flags, ch * kCompactChunk + (r * 64 + lane) * 16, total, mask);
     }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) {
+      counts[ch] = ((unsigned long long)stamp << 32) | (unsigned int)cnt;
+      if (cnt) atomicAdd(&super_counts[(ch / kSuperChunk) * kSuperSlots + ch % kSuperSlots], cnt);
+    }
   }
 }
 
