@@ -1351,9 +1351,7 @@ __device__ __forceinline__ void super_scan(int32_t* __restrict__ super_counts, l
   }
 }
 
-// Pass (1): the counts. One wavefront per listed chunk (64 lanes x 4 x 16
-// bytes), so that a block holds four chunks in flight and no block barrier
-// sits on a chunk's path.
+// Pass (1): the counts.
 __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t* __restrict__ flags, long long total,
                                                                    unsigned long long* __restrict__ counts,
                                                                    int32_t* __restrict__ super_counts,
@@ -1361,25 +1359,26 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_count(const uint8_t
                                                                    const int32_t* __restrict__ chunk_list_count,
                                                                    long long n_static,
                                                                    const unsigned int* __restrict__ d_stamp) {
-  static_assert(kCompactChunk == 64 * 4 * 16, "a wavefront covers a chunk in four 16-byte rounds");
-  constexpr int kWaves = kCompactThreads / 64;
+  __shared__ int red[kCompactThreads / 64];
+  // the list length, the stamp and this block's first entry in one round
+  // trip (the list has room for every chunk; the grid has no more blocks)
   const long long nl = n_static + *chunk_list_count;
   const unsigned int stamp = *d_stamp;
-  const int lane = threadIdx.x & 63;
-  const long long w0 = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6), nw = (long long)gridDim.x * kWaves;
-  for (long long e = w0; e < nl; e += nw) {
-    const long long ch = chunk_list[e];
-    int cnt = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      uint32_t mask;
-      cnt += count_fringe16(flags, ch * kCompactChunk + (r * 64 + lane) * 16, total, mask);
+  const int32_t first = chunk_list[blockIdx.x];
+  for (long long e = blockIdx.x; e < nl; e += gridDim.x) {
+    const long long ch = e == (long long)blockIdx.x ? first : chunk_list[e];
+    uint32_t mask;
+    int cnt = count_fringe16(flags, ch * kCompactChunk + threadIdx.x * 16, total, mask);
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int sum = 0;
+      for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[w];
+      counts[ch] = ((unsigned long long)stamp << 32) | (unsigned int)sum;
+      if (sum) atomicAdd(&super_counts[(ch / kSuperChunk) * kSuperSlots + ch % kSuperSlots], sum);
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if (lane == 0) {
-      counts[ch] = ((unsigned long long)stamp << 32) | (unsigned int)cnt;
-      if (cnt) atomicAdd(&super_counts[(ch / kSuperChunk) * kSuperSlots + ch % kSuperSlots], cnt);
-    }
+    __syncthreads();
   }
 }
 
