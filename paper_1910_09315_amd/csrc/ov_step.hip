@@ -1111,7 +1111,11 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
         const int j = j0 + (threadIdx.x & 7), k = k0 + (threadIdx.x >> 3);
         if (j < G.nj && k < G.nk) {
           const long long r = noff + (long long)G.ni * ((long long)j + (long long)G.nj * k);
-          const long long c0 = (r + i0) / kCompactChunk, c1 = (r + min(G.ni, i0 + kTileI) - 1) / kCompactChunk;
+          const long long last = min(G.ni, i0 + kTileI) - 1;
+          long long c0 = (r + i0) / kCompactChunk;
+          const long long c1 = (r + last) / kCompactChunk;
+          // a chunk the tile's previous row (j - 1) ends in is that row's to mark
+          if ((threadIdx.x & 7) > 0 && (r - G.ni + last) / kCompactChunk == c0) ++c0;
           for (long long ch = c0; ch <= c1; ++ch)
             if (!chunk_static[ch] && atomicExch(&chunk_stamp[ch], stamp) != stamp)
               chunk_list[n_static + atomicAdd(chunk_list_count, 1)] = (int32_t)ch;
