@@ -459,8 +459,9 @@ def step_report(pipe, poses, w, t0: int, n: int, dev):
     """Untimed, after the measured steps: 3 x n more steps through the same
     executor, with hip events (recorded by the executor on the stream each
     stage runs on) around one stage of every step in turn, for the median
-    and p90 of each stage's duration on its own; then the outcome mix of
-    the last step (walk, fallback scan, FP64 correction, orphan)."""
+    and p90 of each stage's duration on its own; n more steps for the
+    median and p90 of the step interval; then the outcome mix of the last
+    step (walk, fallback scan, FP64 correction, orphan)."""
     import numpy as np
     import torch
     rep = {"steps_per_stage": n, "timing": "hip events around one stage of every step, on its stream; while a "
@@ -482,6 +483,21 @@ def step_report(pipe, poses, w, t0: int, n: int, dev):
         us = np.array(pipe.native.stage_times(n)) * 1e3
         rep[name] = {"median_us": round(float(np.median(us)), 2), "p90_us": round(float(np.percentile(us, 90)), 2)}
         t += n
+    # the step interval: an event on the last stream after each step's back
+    # half; consecutive events are one step apart in the steady state
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    torch.cuda.synchronize(dev)
+    for i in range(n):
+        pipe.submit(t + i, poses[(t + i) % w.steps])
+        evs[i].record(pipe.streams[-1])
+    pipe.join()
+    torch.cuda.synchronize(dev)
+    gaps = np.array([evs[i - 1].elapsed_time(evs[i]) for i in range(2, n)]) * 1e3
+    rep["step_interval"] = {"median_us": round(float(np.median(gaps)), 2),
+                            "p90_us": round(float(np.percentile(gaps, 90)), 2),
+                            "timing": "hip events after each step's back half on its stream, steps submitted one "
+                                      "call each (the timed run submits all its steps in one call)"}
+    t += n
     last = t - 1
     r = pipe.results(last)
     st = r["status"]
