@@ -32,14 +32,15 @@ _lib = None
 _P = ctypes.c_void_p
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
+def build(force: bool = True, src: str = _SRC, out: str = LIB_PATH) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP); `src` and
+    `out` default to this package's source and library."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.run(["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-                        "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+                        "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
@@ -47,44 +48,49 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        L.orc_holecut.restype = ctypes.c_double
-        L.orc_holecut.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
-        L.orc_mesh_inside.restype = ctypes.c_double
-        L.orc_mesh_inside.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]
-        L.orc_fringe.restype = None
-        L.orc_fringe.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int, _P, _P]
-        L.orc_compact.restype = ctypes.c_int64
-        L.orc_compact.argtypes = [ctypes.c_int, _P, _P, _P, _P, ctypes.c_int64]
-        L.orc_bins_build.restype = _P
-        L.orc_bins_build.argtypes = [_P, _P, _P, _P]
-        L.orc_bins_free.restype = None
-        L.orc_bins_free.argtypes = [_P]
-        L.orc_bins_entries.restype = ctypes.c_int64
-        L.orc_bins_entries.argtypes = [_P]
-        L.orc_donor_search.restype = None
-        L.orc_donor_search.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int,
-                                       ctypes.c_int64, _P, _P, _P, _P, _P, _P]
-        L.orc_cell_coords.restype = ctypes.c_int
-        L.orc_cell_coords.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, _P]
-        L.orc_interp.restype = None
-        L.orc_interp.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.c_int64,
-                                 _P, _P, _P, _P]
-        L.orc_transform.restype = None
-        L.orc_transform.argtypes = [_P, _P, _P, _P, _P, ctypes.c_int64, _P, _P, _P]
-        L.orc_weights.restype = None
-        L.orc_weights.argtypes = [_P, _P]
-        L.orc_num_threads.restype = ctypes.c_int
-        L.orc_set_threads.restype = None
-        L.orc_set_threads.argtypes = [ctypes.c_int]
-        L.orc_frame_velocity.restype = None
-        L.orc_frame_velocity.argtypes = [_P, ctypes.c_int64, _P, _P, _P]
-        L.orc_interp_matrix.restype = None
-        L.orc_interp_matrix.argtypes = [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]
-        L.orc_matrix_apply.restype = None
-        L.orc_matrix_apply.argtypes = [ctypes.c_int64, _P, _P, ctypes.c_int, ctypes.c_int64, _P, _P]
-        _lib = L
+        _lib = bind(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def bind(L):
+    """Declare the argument and result types of the oracle's entry points on
+    the loaded library `L` (also used by tests that load a variant build)."""
+    L.orc_holecut.restype = ctypes.c_double
+    L.orc_holecut.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_mesh_inside.restype = ctypes.c_double
+    L.orc_mesh_inside.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]
+    L.orc_fringe.restype = None
+    L.orc_fringe.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int, _P, _P]
+    L.orc_compact.restype = ctypes.c_int64
+    L.orc_compact.argtypes = [ctypes.c_int, _P, _P, _P, _P, ctypes.c_int64]
+    L.orc_bins_build.restype = _P
+    L.orc_bins_build.argtypes = [_P, _P, _P, _P]
+    L.orc_bins_free.restype = None
+    L.orc_bins_free.argtypes = [_P]
+    L.orc_bins_entries.restype = ctypes.c_int64
+    L.orc_bins_entries.argtypes = [_P]
+    L.orc_donor_search.restype = None
+    L.orc_donor_search.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int,
+                                   ctypes.c_int64, _P, _P, _P, _P, _P, _P]
+    L.orc_cell_coords.restype = ctypes.c_int
+    L.orc_cell_coords.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, _P]
+    L.orc_interp.restype = None
+    L.orc_interp.argtypes = [ctypes.c_int, _P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.c_int64,
+                             _P, _P, _P, _P]
+    L.orc_transform.restype = None
+    L.orc_transform.argtypes = [_P, _P, _P, _P, _P, ctypes.c_int64, _P, _P, _P]
+    L.orc_weights.restype = None
+    L.orc_weights.argtypes = [_P, _P]
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_threads.restype = None
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_frame_velocity.restype = None
+    L.orc_frame_velocity.argtypes = [_P, ctypes.c_int64, _P, _P, _P]
+    L.orc_interp_matrix.restype = None
+    L.orc_interp_matrix.argtypes = [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]
+    L.orc_matrix_apply.restype = None
+    L.orc_matrix_apply.argtypes = [ctypes.c_int64, _P, _P, ctypes.c_int, ctypes.c_int64, _P, _P]
+    return L
 
 
 def _ptr(a: np.ndarray):
