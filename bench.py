@@ -8,8 +8,9 @@ table of every step) are resident in HBM before timing starts.
 Prints one JSON line. `value` = fringe points assembled and interpolated per
 second = sum of per-step query counts / wall time of the timed steps, for the
 bench workload (default C1, plain FP64). `forms` adds the same metric for the
-mixed-precision batched form (default C4, `--compare`), measured the same way
-in the same run.
+largest workload (default C4, `--compare`) in mixed precision (the batched
+form) and in plain FP64, measured the same way in the same run, so that the
+two precisions are compared on the same grids.
 """
 from __future__ import annotations
 
@@ -42,6 +43,40 @@ FLOPS_PER_SCAN_CANDIDATE = 350
 FLOPS_PER_QUERY = 130
 KERNEL_SOURCES = ["paper_1910_09315_amd/csrc/ov_search.hip", "paper_1910_09315_amd/csrc/ov_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# work counters (binding.STAT), by index
+ST_HC_NODES, ST_HC_CALLS, ST_CELLS, ST_ITERS, ST_CANDS, ST_BACK, ST_FLAG_W, ST_BASE_R, ST_STARTS = range(9)
+# Algorithmic HBM bytes of the one-kernel back half (transform + donor search +
+# interpolation), per unit, from the per-unit figures of the path's work:
+#  per query: its grid and node ids (8) and FP64 node coordinates (24) read;
+#    offsets, natural coordinates (3 values each), donor grid + cell (8),
+#    status (4) and the 4 interpolated values written;
+#  per walked cell: 8 corners x 24 B coordinates;
+#  per fallback-scan candidate: its id (4) + 8 corners x 24 B;
+#  per distinct donor-corner node: its 4 field values (read once).
+BACK_BYTES_PER_CELL = 8 * 24
+BACK_BYTES_PER_CAND = 4 + 8 * 24
+
+
+def back_bytes_per_query(es: int) -> int:
+    return 8 + 24 + 3 * es + 3 * es + 8 + 4 + 4 * es
+
+
+def profiler_counting() -> bool:
+    """True inside a rocprofv3 counter-collection run (--pmc or counter
+    groups), which serialises kernel dispatches."""
+    v = os.environ.get("ROCPROF_COUNTER_COLLECTION", "")
+    return v.strip().lower() not in ("", "0", "false", "no", "off")
+
+
+_WORKLOADS = {}
+
+
+def load_workload(name: str):
+    """The seeded workload `name`, built once per process."""
+    import workloads as W
+    if name not in _WORKLOADS:
+        _WORKLOADS[name] = W.build(name)
+    return _WORKLOADS[name]
 
 
 def source_hash(files) -> str:
@@ -223,24 +258,83 @@ def measure_next_rows(a, b, nrhs: int, reps: int, seed: int = 7) -> dict:
     return res
 
 
-def measure(args):
-    """Times args.steps steps of workload args.config; returns (the JSON fields, the workload)."""
+def back_roofline(stat, queries_per_launch: float, avg_s: float, precision: str, es: int, distinct_nodes,
+                  traffic) -> dict:
+    """The one-kernel back half against the chip: algorithmic flops per
+    launch against the vector peak of its precision, and algorithmic bytes per
+    launch against HBM; `bound` is the resource of the larger fraction.
+    stat: work counters summed over the launches timed."""
+    launches = max(1, stat[ST_BACK])
+    cells, iters, cands = stat[ST_CELLS] / launches, stat[ST_ITERS] / launches, stat[ST_CANDS] / launches
+    flops = (FLOPS_PER_CELL[precision] * cells + FLOPS_PER_NEWTON_ITER * iters
+             + FLOPS_PER_SCAN_CANDIDATE * cands + FLOPS_PER_QUERY * queries_per_launch)
+    peak_fl = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+    tflops = flops / avg_s / 1e12
+    nbytes = (back_bytes_per_query(es) * queries_per_launch + BACK_BYTES_PER_CELL * cells
+              + BACK_BYTES_PER_CAND * cands + 4 * es * (distinct_nodes or 0))
+    gbs = nbytes / avg_s / 1e9
+    alu = {"achieved": round(tflops, 4), "peak": peak_fl, "unit": "TFLOP/s", "frac": round(tflops / peak_fl, 6),
+           "algorithmic_flops_per_launch": round(flops),
+           "per_unit": f"{FLOPS_PER_CELL[precision]} x {cells:.0f} walked cells + {FLOPS_PER_NEWTON_ITER} x "
+                       f"{iters:.0f} Newton iterations + {FLOPS_PER_SCAN_CANDIDATE} x {cands:.0f} fallback-scan "
+                       f"candidates + {FLOPS_PER_QUERY} x {queries_per_launch:.0f} queries per launch (counted by "
+                       f"the kernel)",
+           "peak_note": "vector FP64 peak" if precision == "fp64" else
+                        "vector FP32 peak (the walk and weights run in FP32; FP64 corrections included)"}
+    hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "algorithmic_bytes_per_launch": round(nbytes),
+           "per_unit": f"{back_bytes_per_query(es)} B x {queries_per_launch:.0f} queries + {BACK_BYTES_PER_CELL} B "
+                       f"x {cells:.0f} walked cells + {BACK_BYTES_PER_CAND} B x {cands:.0f} scan candidates + "
+                       f"{4 * es} B x {distinct_nodes} distinct donor-corner nodes per launch"}
+    top = hbm if hbm["frac"] >= alu["frac"] else alu
+    r = {"bound": "hbm" if top is hbm else "alu", "kernel": "k_back (transform + donor search + interpolation)",
+         "achieved": top["achieved"], "peak": top["peak"], "unit": top["unit"], "frac": top["frac"],
+         "traffic": traffic,
+         "traffic_gbs": round(traffic / avg_s / 1e9, 1) if traffic else None,
+         "traffic_frac_hbm": round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+         "avg_us": round(avg_s * 1e6, 2), "hbm_view": hbm, "alu_view": alu}
+    return r
+
+
+def holecut_roofline(stat, avg_s: float, precision: str, nsub: int, note: str) -> dict:
+    """The hole-cut stage (start of the step's flags + the culled hole cut)
+    against HBM, in the bytes it must move: the flag bytes the step's start
+    wrote (the previous step's near tiles in the executors, every node in a
+    full fill) and the base flags it read, the coordinates and flag of every
+    candidate node tested, and the sub-tile spheres."""
+    calls = max(1, stat[ST_HC_CALLS])
+    coord_b = 24 if precision == "fp64" else 12
+    written, base, cand = stat[ST_FLAG_W] / calls, stat[ST_BASE_R] / calls, stat[ST_HC_NODES] / calls
+    nbytes = written + base + (coord_b + 1) * cand + 32 * nsub
+    gbs = nbytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": "hole-cut stage (k_flag_reset + k_holecut_sub in the executors)",
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(nbytes),
+            "per_unit": f"1 B x {written:.0f} flag bytes written + 1 B x {base:.0f} base flags read at the step's "
+                        f"start ({stat[ST_STARTS] / calls:.2f} starts per call) + {coord_b + 1} B x {cand:.0f} "
+                        f"candidate nodes tested + 32 B x {nsub} sub-tile spheres per launch (counted by the kernels)",
+            "timing": note}
+
+
+def measure(args, w=None):
+    """Times args.steps steps of workload args.config; returns (the JSON
+    fields, the workload)."""
     import numpy as np
     import torch
 
-    import workloads as W
     from paper_1910_09315_amd import binding as B
     from paper_1910_09315_amd.assembly import Assembly, Pipeline
 
     t0 = time.perf_counter()
-    w = W.build(args.config)
+    if w is None:
+        w = load_workload(args.config)
     if args.steps is None:
         args.steps = w.steps - args.warmup
     if args.warmup + args.steps > w.steps:
         log(f"[bench] note: steps {args.warmup}..{args.warmup + args.steps - 1} run past the workload's {w.steps} "
             f"poses and wrap around to pose 0 (a jump the warm start does not follow)")
     precision = args.precision or w.precision
-    log(f"[bench] workload {w.name} built in {time.perf_counter() - t0:.1f}s: {w.total_nodes} nodes, "
+    log(f"[bench] workload {w.name} ready in {time.perf_counter() - t0:.1f}s: {w.total_nodes} nodes, "
         f"{w.ngrids} grids, {w.steps} poses, precision {precision}")
     dev = torch.device("cuda", 0)
     opts = {"holecut_cull": 0 if args.no_cull else 1}
@@ -277,12 +371,19 @@ def measure(args):
             log(f"[bench] tuned parameters {params}")
     if args.stages is None:
         args.stages = 3
+    if args.stages > 1 and profiler_counting():
+        # counter collection serialises dispatches: a stream waiting on
+        # another stream's counter could wait for work that cannot start
+        log(f"[bench] rocprofv3 counter collection detected: the executor runs on one stream "
+            f"(asked for {args.stages})")
+        args.stages = 1
     mode = ("graph" if args.graph else "sequential" if args.sequential else "pipelined-py" if args.eager else
             "pipelined-graph" if args.graphs else "pipelined")
     log(f"[bench] set-up done, {n0} queries at t=0, capacity {cap}, mode {mode}")
     pipe = None
+    max_timed = max(args.steps, 64)
     if mode.startswith("pipelined"):
-        pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=args.steps,
+        pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=max_timed,
                         stages=args.stages if mode == "pipelined" else 2,
                         graphs=(mode == "pipelined" and args.native_graphs))
     elif mode == "graph":
@@ -315,7 +416,8 @@ def measure(args):
 
     # the native executor takes the timed steps in one call: their poses as one
     # contiguous device table, prepared before the timed region
-    many = pipe is not None and pipe.native is not None and not args.per_step_submit
+    native = pipe is not None and pipe.native is not None
+    many = native and not args.per_step_submit
     if many:
         idx = torch.arange(args.warmup, args.warmup + args.steps, device=dev) % w.steps
         timed_poses = poses[idx].contiguous()
@@ -327,17 +429,17 @@ def measure(args):
     a.ctx.stats()  # zero the work counters: count the timed steps only
     log("[bench] warm-up done")
 
+    # the back half of every time_every-th timed step (from the first) is
+    # timed with events on its stream, in place in the pipeline
+    roof_back = args.roofline == "back" and native and not args.unfused_back and args.time_every > 0
+    if roof_back:
+        pipe.native.stage_times(0)  # restart the timing record
+        pipe.native.set_timing(args.time_every, 2, alone=False)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     start.record()
     t_host0 = time.perf_counter()
-    native = pipe is not None and pipe.native is not None
-    roof_back = args.roofline == "back" and native and not args.unfused_back
-    timing = native and args.roofline != "none"
-    if timing:
-        pipe.native.stage_times(0)  # restart the timing record
-        pipe.native.set_timing(args.time_every, 2 if roof_back else 0)
     if pipe is not None:
         pipe.wait_current()
     if many:
@@ -355,73 +457,48 @@ def measure(args):
     status = a.ctx.status()
     stat = a.ctx.stats()
     ntiles = sum(-(-g.dims[0] // 64) * -(-g.dims[1] // 8) * -(-g.dims[2] // 8) for g in w.grids)
+    nsub = 4 * ntiles
     queries = int(counts[args.warmup:].sum().item())
     value = queries / (total_ms / 1e3)
     log(f"[bench] {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms, host submit {host_ms:.1f} ms), "
-        f"{queries} queries, "
-        f"{total_ms / args.steps * 1e3:.1f} us/step, status {status}")
+        f"{queries} queries, {total_ms / args.steps * 1e3:.1f} us/step, status {status}")
+    es = 4 if precision == "mixed" else 8
+    last_t = args.warmup + args.steps - 1
+    # the last timed step's results, for the oracle comparison (its pose is
+    # the next after the previous step's: the warm start followed the motion)
+    last_result = (last_t % w.steps, pipe.results(last_t) if pipe is not None else a.results())
+
+    def distinct_corner_nodes(b):
+        """Distinct donor-corner nodes of a step's donors (the interpolation
+        matrix's columns), counted on the device."""
+        cols = torch.empty((b.capacity, 8), dtype=torch.int32, device=dev)
+        vals = torch.empty((b.capacity, 8), dtype=a.dtype, device=dev)
+        B.overset_interp_matrix(a.ctx, b.donor_grid, b.donor_cell, b.s, b.d_count, b.capacity, cols, vals)
+        n = min(int(b.d_count.item()), b.capacity)
+        live = cols[:n]
+        return int(torch.unique(live[live >= 0]).numel())
+
+    last_buf = pipe.bufs[last_t % pipe.nsets] if pipe is not None else a.buf
+    distinct = distinct_corner_nodes(last_buf)
 
     roofline = None
-    if timing:
+    if roof_back:
         pipe.native.set_timing(0)
-        ms = np.array(pipe.native.stage_times(args.steps))
-        roof_note = (f"hip events around the {'back half' if roof_back else 'hole cut'} of every "
-                     f"{args.time_every}-th timed step, recorded by the native executor on the stream it runs on")
-    elif hc and args.roofline != "none":
+        ms = np.array(pipe.native.stage_times(max_timed))
+        if len(ms):
+            traffic = recorded_traffic(f"k_back|{w.name}|{precision}")
+            roofline = back_roofline(stat, queries / args.steps, ms.mean() / 1e3, precision, es, distinct, traffic)
+            roofline["samples_us"] = [round(x * 1e3, 1) for x in ms]
+            roofline["timing"] = (f"hip events on the back half's stream around k_back of every "
+                                  f"{args.time_every}-th timed step from the first ({len(ms)} samples), in place in "
+                                  f"the pipeline (no extra waits), recorded by the native executor; work counters "
+                                  f"summed over the timed steps; distinct corner nodes of the last timed step")
+        else:
+            log("[bench] warning: no back-half timing samples")
+    elif hc and args.roofline != "none" and mode != "graph":
         ms = np.array([e[0].elapsed_time(e[1]) for e in hc])
-        roof_note = "hip events around every hole cut of the timed steps (on the stream it runs on)"
-    else:
-        ms = None
-    if ms is not None and len(ms) and roof_back:
-        launches = max(1, stat[5])
-        cells, iters, cands = stat[2] / launches, stat[3] / launches, stat[4] / launches
-        qpl = queries / args.steps
-        flops = (FLOPS_PER_CELL[precision] * cells + FLOPS_PER_NEWTON_ITER * iters
-                 + FLOPS_PER_SCAN_CANDIDATE * cands + FLOPS_PER_QUERY * qpl)
-        avg_s = ms.mean() / 1e3
-        peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
-        # HBM bytes per launch from the counter runs (null once the kernel changed)
-        traffic = recorded_traffic(f"k_back|{w.name}|{precision}")
-        achieved = flops / avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": "k_back (transform + donor search + interpolation)",
-                    "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 6),
-                    "traffic": traffic,
-                    "traffic_gbs": round(traffic / avg_s / 1e9, 1) if traffic else None,
-                    "traffic_frac_hbm": round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
-                    "avg_us": round(ms.mean() * 1e3, 2), "samples_us": [round(x * 1e3, 1) for x in ms],
-                    "algorithmic_flops_per_launch": round(flops),
-                    "per_unit": f"{FLOPS_PER_CELL[precision]} x {cells:.0f} walked cells + {FLOPS_PER_NEWTON_ITER} "
-                                f"x {iters:.0f} Newton iterations + {FLOPS_PER_SCAN_CANDIDATE} x {cands:.0f} "
-                                f"fallback-scan candidates + {FLOPS_PER_QUERY} x {qpl:.0f} queries per launch "
-                                f"(counted by the kernel)",
-                    "peak_note": "vector FP64 peak" if precision == "fp64" else
-                                 "vector FP32 peak (the walk and weights run in FP32; FP64 corrections included)",
-                    "timing": roof_note}
-    elif ms is not None and len(ms):
-        nodes = w.total_nodes
-        per_node = 25 if precision == "fp64" else 13   # coordinates (3 x 8 or 3 x 4 B) + 1 flag byte
-        bytes_launch = per_node * nodes
-        if not args.no_cull:
-            # culled sub-tiles move only their flag byte (grids with outer
-            # fringe layers also read it from the precomputed base flags):
-            # count the coordinates the kernel actually read, per launch, from
-            # the library's counters, and the sub-tile spheres
-            coord_b = 24 if precision == "fp64" else 12
-            nsub = 4 * ntiles
-            base_nodes = sum(g.nodes for g in w.grids if any(g.outer))
-            bytes_launch = int(nodes + base_nodes + coord_b * stat[0] / max(1, stat[1]) + 32 * nsub)
-            per_node = f"1 B flag written x {nodes} nodes + 1 B base flag read x {base_nodes} nodes + {coord_b} B " \
-                       f"coordinates x {stat[0] / max(1, stat[1]):.0f} nodes read + 32 B x {nsub} sub-tile spheres"
-        avg_s = ms.mean() / 1e3
-        achieved = bytes_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": "hole cut (k_flag_fill + k_holecut_sub)" if not args.no_cull
-                    else "k_holecut", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "avg_us": round(ms.mean() * 1e3, 2),
-                    "algorithmic_bytes_per_launch": bytes_launch,
-                    "per_unit": per_node if isinstance(per_node, str) else f"{per_node} B per node x {nodes} nodes",
-                    "timing": roof_note}
+        roofline = holecut_roofline(stat, ms.mean() / 1e3, precision, nsub,
+                                    "hip events around every hole cut of the timed steps (on the stream it runs on)")
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -443,25 +520,33 @@ def measure(args):
         "roofline": roofline,
     }
     if args.next_rows:
-        last = args.warmup + args.steps - 1
-        b = pipe.bufs[last % pipe.nsets] if pipe is not None else a.buf
-        out["next_rows"] = measure_next_rows(a, b, args.apply_nrhs, reps=50)
+        out["next_rows"] = measure_next_rows(a, last_buf, args.apply_nrhs, reps=50)
         log(f"[bench] next rows: {out['next_rows']}")
     if native and args.step_report:
-        out["step_report"], last_result = step_report(pipe, poses, w, args.warmup + args.steps,
-                                                      min(48, args.steps), dev)
+        out["step_report"] = step_report(pipe, a, poses, w, args.warmup + args.steps, min(48, args.steps), dev,
+                                         precision, es, nsub, distinct)
+        rh = out["step_report"].pop("_holecut_roofline", None)
+        if rh is not None:
+            out["roofline_holecut"] = rh
         log(f"[bench] step report: {out['step_report']}")
-        out["_last_result"] = last_result
+    out["_last_result"] = last_result
+    if pipe is not None:
+        pipe.close()
+    a.close()
+    del pipe, a
+    torch.cuda.synchronize(dev)
+    torch.cuda.empty_cache()
     return out, w
 
 
-def step_report(pipe, poses, w, t0: int, n: int, dev):
+def step_report(pipe, a, poses, w, t0: int, n: int, dev, precision: str, es: int, nsub: int, distinct) -> dict:
     """Untimed, after the measured steps: 3 x n more steps through the same
     executor, with hip events (recorded by the executor on the stream each
     stage runs on) around one stage of every step in turn, for the median
-    and p90 of each stage's duration on its own; n more steps for the
-    median and p90 of the step interval; then the outcome mix of the last
-    step (walk, fallback scan, FP64 correction, orphan)."""
+    and p90 of each stage's duration on its own and the work counters of
+    those steps; n more steps for the median and p90 of the step interval;
+    then the outcome mix of the last step (walk, fallback scan, FP64
+    correction, orphan)."""
     import numpy as np
     import torch
     rep = {"steps_per_stage": n, "timing": "hip events around one stage of every step, on its stream; while a "
@@ -475,13 +560,26 @@ def step_report(pipe, poses, w, t0: int, n: int, dev):
         pp = poses[idx].contiguous()
         torch.cuda.synchronize(dev)
         pipe.native.stage_times(0)
-        pipe.native.set_timing(1, st)
+        a.ctx.stats()
+        pipe.native.set_timing(1, st, alone=True)
         pipe.submit_many(t, pp, counts)
         pipe.join()
         torch.cuda.synchronize(dev)
         pipe.native.set_timing(0)
-        us = np.array(pipe.native.stage_times(n)) * 1e3
+        stat = a.ctx.stats()
+        ms = np.array(pipe.native.stage_times(n))
+        us = ms * 1e3
         rep[name] = {"median_us": round(float(np.median(us)), 2), "p90_us": round(float(np.percentile(us, 90)), 2)}
+        if st == 0:
+            rep["_holecut_roofline"] = holecut_roofline(
+                stat, ms.mean() / 1e3, precision, nsub,
+                f"hip events around the hole-cut stage of each of {n} steps after the timed region, run alone "
+                f"(recorded by the native executor on its stream); work counters of those steps")
+        if st == 2:
+            q = float(counts.sum().item()) / n
+            r = back_roofline(stat, q, ms.mean() / 1e3, precision, es, distinct, None)
+            rep[name]["alone_frac"] = {"hbm": r["hbm_view"]["frac"], "alu": r["alu_view"]["frac"],
+                                       "avg_us": r["avg_us"]}
         t += n
     # the step interval: an event on the last stream after each step's back
     # half; consecutive events are one step apart in the steady state
@@ -509,10 +607,27 @@ def step_report(pipe, poses, w, t0: int, n: int, dev):
         "fallback_scan_frac": round(float(np.sum(kind == 2)) / m, 6),
         "orphan_frac": round(float(np.sum(kind == 0)) / m, 6),
         "fp64_fixed_frac": round(float(np.sum((st & 4) != 0)) / m, 6)}
-    return rep, (last % w.steps, r)
+    return rep
 
 
-def main():
+def oracle_check(w, check, budget_note: str = "") -> dict:
+    """The oracle's step check[0] compared with the GPU's (check[1])."""
+    import oracle
+    t1 = time.perf_counter()
+    o = oracle.Oracle(w.grids, w.nf)
+    ref = o.step(w.poses[check[0]], w.fields)
+    e = error_norms(ref, check[1], check[0])
+    e["oracle_s"] = round(time.perf_counter() - t1, 1)
+    return e
+
+
+def sampled_steps(steps: int, every: int) -> list:
+    """Indices of the timed steps whose back half the executor times (the
+    first timed step, then every `every`-th)."""
+    return list(range(0, steps, every)) if every > 0 else []
+
+
+def make_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
@@ -526,7 +641,7 @@ def main():
     ap.add_argument("--graphs", action="store_true", help="two-stream pipeline driven from Python, per-half graphs")
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
     ap.add_argument("--stages", type=int, default=None, choices=(1, 2, 3),
-                    help="native executor streams (default: the tuned choice, else 3)")
+                    help="native executor streams (default: the tuned choice, else 3; 1 under rocprofv3 counters)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the executor for this workload first when no tuned entry is cached")
     ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
@@ -541,11 +656,13 @@ def main():
                     help="native executor: transform, search and interpolation as separate kernels")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
-    ap.add_argument("--time-every", type=int, default=48,
-                    help="native executor: time the roofline kernel of every N-th step with events, run alone (the "
-                         "executor drains the other streams around it: each sample costs about 1.5 steps)")
+    ap.add_argument("--time-every", type=int, default=4,
+                    help="native executor: time k_back of every N-th timed step from the first with events, in "
+                         "place in the pipeline (0: no timing in the timed region)")
     ap.add_argument("--compare", default="C4",
-                    help="also time this workload (the mixed-precision batched form) and report both ('' to skip)")
+                    help="also time this workload in mixed precision (the batched form) and in FP64 ('' to skip)")
+    ap.add_argument("--compare-precisions", default="mixed,fp64",
+                    help="precisions of the compared workload, comma-separated")
     ap.add_argument("--roofline", choices=("back", "holecut", "none"), default="back",
                     help="kernel for the roofline object: the one-kernel back half (native executor) or the hole cut")
     ap.add_argument("--no-next-rows", dest="next_rows", action="store_false",
@@ -553,11 +670,17 @@ def main():
     ap.add_argument("--apply-nrhs", type=int, default=4, help="vectors per application of the interpolation matrix")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip comparing the last timed step of each workload with the oracle's")
     ap.add_argument("--no-step-report", dest="step_report", action="store_false",
                     help="skip the per-stage durations and outcome mix measured after the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB 5 times (reference for HBM counters)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 8
@@ -580,34 +703,50 @@ def main():
         sys.exit(2)
 
     out, w = measure(args)
+    last_result = out.pop("_last_result", None)
+    if not args.no_oracle_check and last_result is not None:
+        log("[bench] comparing the last timed step with the oracle")
+        out["vs_oracle"] = oracle_check(w, last_result)
+        log(f"[bench] vs oracle: {out['vs_oracle']}")
     if args.compare and args.compare != args.config:
         import copy
-        import gc
-        import torch
-        gc.collect()
-        torch.cuda.empty_cache()
-        a2 = copy.copy(args)
-        a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, None, None, None, 0
-        a2.roofline = "none"
-        o2, w2 = measure(a2)
-        o2.pop("_last_result", None)
-        out["forms"] = {
-            "note": "the same metric for the plain FP64 form (value above) and the mixed-precision batched form",
-            "plain_fp64": {"workload": out["config"]["workload"], "value": out["value"],
-                           "ms_per_step": out["ms_per_step"]},
-            "mixed_batched": {"workload": o2["config"]["workload"], "value": o2["value"],
-                              "ms_per_step": o2["ms_per_step"], "steps": o2["steps"],
-                              "queries_per_step_mean": o2["config"]["queries_per_step_mean"],
-                              "tuned": o2["config"]["tuned"], "next_rows": o2.get("next_rows"),
-                              "step_report": o2.get("step_report")},
-            "mixed_batched_over_plain_fp64": round(o2["value"] / out["value"], 3)}
+        forms = {"note": "the same metric, the value above being the plain FP64 form on its workload; "
+                         "`same_workload` times the compared workload in each precision in this run"}
+        w2, res = None, {}
+        for prec in [p for p in args.compare_precisions.split(",") if p]:
+            a2 = copy.copy(args)
+            a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, prec, None, None, 0
+            a2.roofline = "back"
+            a2.next_rows = args.next_rows and prec == "mixed"
+            o2, w2 = measure(a2, w2)
+            lr = o2.pop("_last_result", None)
+            if not args.no_oracle_check and lr is not None:
+                log(f"[bench] comparing the last timed step of {args.compare} ({prec}) with the oracle")
+                o2["vs_oracle"] = oracle_check(w2, lr)
+                log(f"[bench] vs oracle: {o2['vs_oracle']}")
+            res[prec] = {"workload": o2["config"]["workload"], "value": o2["value"],
+                         "ms_per_step": o2["ms_per_step"], "steps": o2["steps"],
+                         "queries_per_step_mean": o2["config"]["queries_per_step_mean"],
+                         "tuned": o2["config"]["tuned"], "roofline": o2.get("roofline"),
+                         "roofline_holecut": o2.get("roofline_holecut"), "vs_oracle": o2.get("vs_oracle"),
+                         "next_rows": o2.get("next_rows"), "step_report": o2.get("step_report")}
+            del lr
+        forms["plain_fp64"] = {"workload": out["config"]["workload"], "value": out["value"],
+                               "ms_per_step": out["ms_per_step"]}
+        if "mixed" in res:
+            forms["mixed_batched"] = res["mixed"]
+        forms["same_workload"] = {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                      "roofline": r["roofline"], "vs_oracle": r["vs_oracle"]}
+                                  for p, r in res.items() if p != "mixed"}
+        if "mixed" in res and "fp64" in res:
+            forms["same_workload"]["workload"] = args.compare
+            forms["same_workload"]["mixed_over_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+        out["forms"] = forms
         del w2
-    last_result = out.pop("_last_result", None)
+        _WORKLOADS.pop(args.compare, None)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
-        out["cpu_baseline"], err = cpu_baseline(w, args.cpu_budget, check=last_result)
-        if err is not None:
-            out["step_report"]["vs_oracle"] = err
+        out["cpu_baseline"], _ = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

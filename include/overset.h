@@ -190,7 +190,13 @@ int ov_node_offsets(const ov_ctx *ctx, int64_t *out);
 #define OV_STAT_NEWTON_ITERS 3         /* Newton iterations, walks and fallback scans */
 #define OV_STAT_SCAN_CANDIDATES 4      /* control-cell list entries the fallback scans tested */
 #define OV_STAT_BACK_CALLS 5           /* launches of that kernel */
-#define OV_STAT_COUNT 8
+/* Flag bytes a step's start wrote: every node (the full fill) or only the
+ * previous step's near tiles (the executors' incremental reset), and the
+ * base-flag bytes it read for grids with outer layers: */
+#define OV_STAT_FLAG_BYTES_WRITTEN 6
+#define OV_STAT_BASE_BYTES_READ 7
+#define OV_STAT_FLAG_STARTS 8          /* fills + resets */
+#define OV_STAT_COUNT 9
 
 /* Copy the OV_STAT_COUNT counters into host_out [host] and zero them.
  * Synchronises `stream`. */
@@ -206,6 +212,14 @@ int ov_reset_history(ov_ctx *ctx, void *stream);
 /* Copy the device status word into *host_status [host] and clear it.
  * Synchronises `stream`. */
 int ov_status_fetch(ov_ctx *ctx, int32_t *host_status, void *stream);
+
+/* The same two calls under the names of the step calls' family:
+ * overset_status_fetch is ov_status_fetch (the device conditions of the step
+ * calls: capacity overflow, walk limit, non-finite input), and
+ * overset_last_error is ov_last_error (the message of the last negative
+ * status a call on `ctx` returned). */
+int overset_status_fetch(ov_ctx *ctx, int32_t *host_status, void *stream);
+const char *overset_last_error(const ov_ctx *ctx);
 
 /* ---------------------------------------------------------------- step */
 
@@ -231,9 +245,12 @@ int overset_holecut(ov_ctx *ctx, const double *poses, uint8_t *flags, void *stre
  * int64). Entries beyond `capacity` are not written; the device status bit
  * OV_DEV_CAPACITY is set instead.
  *  nf         buffer width, 0..3
- *  flags      the output of overset_holecut on this context, unmodified
- *             (the call uses the hole-tile record that hole cut left);
- *             updated in place; 16-byte aligned */
+ *  flags      hole-cut flags: holes (any cause) and outer-layer FRINGE
+ *             nodes as overset_holecut writes them, FIELD elsewhere; updated
+ *             in place; 16-byte aligned. The call finds the tiles that hold
+ *             a hole from these flags themselves (one read of every flag
+ *             byte), so any such buffer may be passed, whichever hole cut
+ *             wrote it. */
 int overset_fringe_compact(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
                            int64_t capacity, int64_t *d_count, void *stream);
 
@@ -400,16 +417,21 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 
 /* Time stage `stage` (0 = A hole cut, 1 = B fringe + compaction, 2 = C back
- * half) of every `every`-th following submitted step (counting all steps
- * submitted to this executor; every = 0 stops timing) with events on the
- * stream it runs on, up to max_timed steps. With graphs the events bracket
- * the whole graph of that stage's stream. With several streams a timed stage
- * runs alone (it waits for the other streams' earlier work, and the next
- * step waits for it), so its events time its own kernels, not the queueing
- * behind other streams; this costs some overlap on the timed steps. Each
- * timed step also adds two event records to the stream, which cost device
- * time of their own. */
+ * half) of the next submitted step and of every `every`-th step after it
+ * (every = 0 stops timing) with events on the stream it runs on, up to
+ * max_timed steps. With graphs the events bracket the whole graph of that
+ * stage's stream. With several streams a timed stage runs alone (it waits
+ * for the other streams' earlier work, and the next step waits for it), so
+ * its events time its own kernels, not the queueing behind other streams;
+ * this costs some overlap on the timed steps. Each timed step also adds two
+ * event records to the stream, which cost device time of their own. */
 int ov_pipe_set_timing(ov_pipe *pipe, int32_t every, int32_t stage);
+
+/* As ov_pipe_set_timing, with alone = 0: the timed stage keeps its place in
+ * the pipeline (no extra waits), so its events include any slowdown from the
+ * other streams' kernels running beside it: the duration it has in the
+ * steady state. alone = 1 is ov_pipe_set_timing. */
+int ov_pipe_set_timing_mode(ov_pipe *pipe, int32_t every, int32_t stage, int32_t alone);
 
 /* Elapsed milliseconds of the timed stages so far (waits for them) into
  * ms_out[0..*n_out) [host], then restarts the record. */

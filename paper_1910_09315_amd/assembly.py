@@ -78,6 +78,13 @@ class Assembly:
         self.graph = None
         self.pose_slot = None
 
+    def close(self):
+        """Free the library context now (it holds device memory) instead of
+        at interpreter exit."""
+        self.graph = None
+        if getattr(self, "ctx", None) is not None:
+            self.ctx.close()
+
     def set_option(self, name: str, value: int):
         self.ctx.set_option(name, value)
         if name == "field_layout":
@@ -340,3 +347,10 @@ class Pipeline:
     def results(self, t: int) -> dict:
         self.join()
         return self.a.results(self.bufs[t % self.nsets])
+
+    def close(self):
+        """Wait for the executor's streams and free it."""
+        if self.native is not None:
+            self.native.close()
+            self.native = None
+        self.graphs = None

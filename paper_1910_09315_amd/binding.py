@@ -22,6 +22,10 @@ OV_STATE_FIELD, OV_STATE_HOLE, OV_STATE_FRINGE = 0, 1, 2
 OV_CAUSE_BOUNDARY = 63
 OV_Q_ORPHAN, OV_Q_FOUND, OV_Q_FALLBACK, OV_Q_FP64_FIXED = 0, 1, 2, 4
 OV_DEV_CAPACITY, OV_DEV_WALK_LIMIT, OV_DEV_NONFINITE = 1, 2, 4
+# work counters (OV_STAT_*)
+STAT = {"holecut_nodes_read": 0, "holecut_calls": 1, "search_cells": 2, "newton_iters": 3, "scan_candidates": 4,
+        "back_calls": 5, "flag_bytes_written": 6, "base_bytes_read": 7, "flag_starts": 8}
+OV_STAT_COUNT = 9
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
        "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
        "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13,
@@ -30,12 +34,13 @@ OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_grid_set_blank_mesh",
            "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
-           "ov_stats_fetch",
+           "ov_stats_fetch", "overset_status_fetch", "overset_last_error",
            "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
            "overset_interp", "overset_frame_velocity", "overset_interp_matrix", "overset_interp_apply",
            "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
            "ov_pipe_submit",
-           "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_stage_times", "ov_pipe_destroy"]
+           "ov_pipe_submit_many", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_set_timing_mode", "ov_pipe_stage_times",
+           "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -76,6 +81,8 @@ def load(path: str = LIB_PATH):
         "ov_reset_history": (ctypes.c_int, [_P, _P]),
         "ov_status_fetch": (ctypes.c_int, [_P, _P, _P]),
         "ov_stats_fetch": (ctypes.c_int, [_P, _P, _P]),
+        "overset_status_fetch": (ctypes.c_int, [_P, _P, _P]),
+        "overset_last_error": (ctypes.c_char_p, [_P]),
         "overset_holecut": (ctypes.c_int, [_P, _P, _P, _P]),
         "overset_fringe_compact": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _P, _P]),
         "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
@@ -92,6 +99,7 @@ def load(path: str = LIB_PATH):
         "ov_pipe_submit_many": (ctypes.c_int, [_P, _P, _I64, _I64, _P]),
         "ov_pipe_join": (ctypes.c_int, [_P, _P]),
         "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32, _I32]),
+        "ov_pipe_set_timing_mode": (ctypes.c_int, [_P, _I32, _I32, _I32]),
         "ov_pipe_stage_times": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
         "ov_pipe_destroy": (ctypes.c_int, [_P]),
     }
@@ -130,7 +138,7 @@ class Context:
 
     def check(self, rc: int, what: str):
         if rc != 0:
-            msg = self.lib.ov_last_error(self.h)
+            msg = self.lib.overset_last_error(self.h)
             raise OversetError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
 
     def close(self):
@@ -172,12 +180,12 @@ class Context:
 
     def status(self, stream=None) -> int:
         v = ctypes.c_int32()
-        self.check(self.lib.ov_status_fetch(self.h, ctypes.byref(v), _stream(stream)), "ov_status_fetch")
+        self.check(self.lib.overset_status_fetch(self.h, ctypes.byref(v), _stream(stream)), "overset_status_fetch")
         return v.value
 
     def stats(self, stream=None) -> list:
-        """Work counters since the last fetch (OV_STAT_*), then zeroed."""
-        arr = (ctypes.c_int64 * 8)()
+        """Work counters since the last fetch (OV_STAT_*, indices in STAT), then zeroed."""
+        arr = (ctypes.c_int64 * OV_STAT_COUNT)()
         self.check(self.lib.ov_stats_fetch(self.h, arr, _stream(stream)), "ov_stats_fetch")
         return list(arr)
 
@@ -283,10 +291,12 @@ class NativePipe:
     def join(self, stream=None):
         self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")
 
-    def set_timing(self, every: int, stage: int = 0):
+    def set_timing(self, every: int, stage: int = 0, alone: bool = True):
         """Time stage `stage` (0 hole cut, 1 fringe + compaction, 2 back half)
-        of every `every`-th following step (0: stop)."""
-        self.ctx.check(self.ctx.lib.ov_pipe_set_timing(self.h, int(every), int(stage)), "ov_pipe_set_timing")
+        of the next step and every `every`-th step after it (0: stop); alone:
+        the timed stage runs alone (else it keeps its place in the pipeline)."""
+        self.ctx.check(self.ctx.lib.ov_pipe_set_timing_mode(self.h, int(every), int(stage), int(bool(alone))),
+                       "ov_pipe_set_timing_mode")
 
     def stage_times(self, max_n: int):
         out = (ctypes.c_float * max(1, max_n))()

@@ -989,6 +989,12 @@ int ov_status_fetch(ov_ctx* ctx, int32_t* host_status, void* stream) {
   return OV_OK;
 }
 
+int overset_status_fetch(ov_ctx* ctx, int32_t* host_status, void* stream) {
+  return ov_status_fetch(ctx, host_status, stream);
+}
+
+const char* overset_last_error(const ov_ctx* ctx) { return ov_last_error(ctx); }
+
 int ov_stats_fetch(ov_ctx* ctx, int64_t* host_out, void* stream) {
   if (!ctx || !host_out) return OV_EINVAL;
   hipStream_t s = (hipStream_t)stream;

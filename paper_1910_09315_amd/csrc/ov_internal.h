@@ -193,6 +193,9 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0,
                           bool reset = false);
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0);
+// A new stamp on slot 0 and its near list built from the flags themselves
+// (tiles holding a hole), for a fringe pass whose flags came from any hole cut.
+hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t s);
 int build_static_chunks(ov_ctx* ctx, hipStream_t s);
 // fused: the write kernel forms the superchunk offsets itself (no scan
 // kernel); only for callers whose next hole cut on this slot precedes the

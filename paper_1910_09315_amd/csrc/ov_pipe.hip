@@ -53,7 +53,9 @@ struct ov_pipe {
   std::vector<hipEvent_t> tb, te;
   int ntimed = 0;
   int timing = 0;       // time stage timed_stage of every timing-th submitted step (0: none)
+  long long timing_t0 = 0;  // the first step timed: the next step submitted after the timing call
   int timed_stage = 0;  // 0 = A (hole cut), 1 = B, 2 = C
+  bool timed_alone = true;  // a timed stage runs alone (extra waits) or keeps its place in the pipeline
   // the timed group runs alone: the next step's first group waits for it
   int after_group = -1;
   long long after_value = 0;
@@ -98,7 +100,14 @@ static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses
                      s, slot);
 }
 
+// Also forgets the buffer sets' history, so that the next direct step of
+// each set starts from a full flag fill (captured launches, or a capture
+// that failed half way, leave that history undefined).
 static void destroy_graphs(ov_pipe* p) {
+  for (int k = 0; k < 3; ++k) {
+    p->uses[k] = 0;
+    p->gen[k] = 0;
+  }
   for (int k = 0; k < 3; ++k)
     for (int g = 0; g < 3; ++g) {
       if (p->gx[k][g]) (void)hipGraphExecDestroy(p->gx[k][g]);
@@ -185,8 +194,7 @@ int ov_pipe_create3(ov_ctx* ctx, int32_t nf, const ov_step_buffers* sets, const 
 int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
   if (!p) return OV_EINVAL;
   if (p->t != 0) return pipe_fail(p, OV_ESTATE, "ov_pipe_use_graphs after the first submit");
-  destroy_graphs(p);
-  for (int k = 0; k < 3; ++k) p->uses[k] = 0;  // the next direct step starts from a full fill
+  destroy_graphs(p);  // (the next direct step of every set starts from a full fill)
   if (!on) return OV_OK;
   p->graphs = true;  // (captured steps write every flag and use near list 0)
   ov_ctx* ctx = p->ctx;
@@ -218,13 +226,18 @@ int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
   return OV_OK;
 }
 
-int ov_pipe_set_timing(ov_pipe* p, int32_t every, int32_t stage) {
+int ov_pipe_set_timing_mode(ov_pipe* p, int32_t every, int32_t stage, int32_t alone) {
   if (!p) return OV_EINVAL;
-  if (every < 0 || stage < 0 || stage > 2) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_timing: bad argument");
+  if (every < 0 || stage < 0 || stage > 2 || alone < 0 || alone > 1)
+    return pipe_fail(p, OV_EINVAL, "ov_pipe_set_timing: bad argument");
   p->timing = every;
+  p->timing_t0 = p->t;
   p->timed_stage = stage;
+  p->timed_alone = alone != 0;
   return OV_OK;
 }
+
+int ov_pipe_set_timing(ov_pipe* p, int32_t every, int32_t stage) { return ov_pipe_set_timing_mode(p, every, stage, 1); }
 
 int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   if (!p || !poses) return pipe_fail(p, OV_EINVAL, "ov_pipe_submit: null argument");
@@ -235,12 +248,14 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   const ov_step_buffers& b = p->sets[k];
   hipError_t e = hipSuccess;
   const double* ps = poses;
-  const bool timed = p->timing > 0 && t % p->timing == 0 && p->ntimed < (int)p->tb.size();
+  const bool timed = p->timing > 0 && (t - p->timing_t0) % p->timing == 0 && p->ntimed < (int)p->tb.size();
+  const bool alone = timed && p->timed_alone;
   for (int g = 0; g < n && e == hipSuccess; ++g) {
     hipStream_t s = p->st[g];
     // after the previous group of this step, or (first group) after the
     // last group of the step that used this buffer set before
     const bool tg = timed && p->timed_stage >= first_stage(p, g) && p->timed_stage < first_stage(p, g + 1);
+    const bool tg_alone = tg && alone;
     if (n > 1) {
       if (g > 0)
         e = hipStreamWaitValue64(s, p->seq + g - 1, (uint64_t)(t + 1), hipStreamWaitValueGte, ~0ull);
@@ -252,9 +267,9 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
       }
       // a timed group also waits for the previous step's later groups, so
       // that its events time it alone
-      for (int g2 = g + 1; tg && g2 < n && t >= 1 && e == hipSuccess; ++g2)
+      for (int g2 = g + 1; tg_alone && g2 < n && t >= 1 && e == hipSuccess; ++g2)
         e = hipStreamWaitValue64(s, p->seq + g2, (uint64_t)t, hipStreamWaitValueGte, ~0ull);
-      if (tg) {
+      if (tg_alone) {
         p->after_group = g;
         p->after_value = t + 1;
       }

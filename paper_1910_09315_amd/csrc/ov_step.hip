@@ -603,12 +603,17 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
                                                    unsigned int* __restrict__ d_stamp,
                                                    int32_t* __restrict__ near_count,
                                                    int32_t* __restrict__ chunk_list_count,
-                                                   int32_t* __restrict__ super_counts, long long n_super_counts) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+                                                   int32_t* __restrict__ super_counts, long long n_super_counts,
+                                                   unsigned long long* __restrict__ stats) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+    atomicAdd(&stat_slot(stats)[OV_STAT_FLAG_STARTS], 1ULL);
+  }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
        i += (long long)gridDim.x * blockDim.x)
     super_counts[i] = 0;
   const int n = *old_count;
+  unsigned int written = 0, base_read = 0;  // this thread's bytes (work counters)
   static_assert(kTileI == 64 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a tile, 16 bytes a thread");
   for (int idx = blockIdx.x; idx < n; idx += gridDim.x) {
     const int4 info = old_list[idx];
@@ -619,6 +624,10 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
     const int i0 = info.y * kTileI + 16 * q, i1 = min(G.ni, i0 + 16);
     const long long r = G.node_off + (long long)G.ni * ((long long)j + (long long)G.nj * k);
     uint8_t* dst = flags + r + i0;
+    if (i1 > i0) {
+      written += (unsigned int)(i1 - i0);
+      if (G.has_outer) base_read += (unsigned int)(i1 - i0);
+    }
     if (i1 - i0 == 16 && ((((uintptr_t)dst) | ((uintptr_t)(base + r + i0))) & 15) == 0) {
       // a whole aligned 16-byte run: one vector store (base flags share the layout)
       constexpr uint32_t fw = 0x01010101u * (uint32_t)OV_STATE_FIELD;
@@ -628,6 +637,17 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
       for (int i = i0; i < i1; ++i) flags[r + i] = G.has_outer ? base[r + i] : (uint8_t)OV_STATE_FIELD;
     }
   }
+  // the wavefront's bytes, summed with shuffles, one atomic per counter
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    written += __shfl_xor(written, o, 64);
+    base_read += __shfl_xor(base_read, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && written) {
+    unsigned long long* slot = stat_slot(stats);
+    atomicAdd(&slot[OV_STAT_FLAG_BYTES_WRITTEN], (unsigned long long)written);
+    if (base_read) atomicAdd(&slot[OV_STAT_BASE_BYTES_READ], (unsigned long long)base_read);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, const uint8_t* __restrict__ base,
@@ -636,8 +656,16 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, 
                                                   unsigned int* __restrict__ d_stamp,
                                                   int32_t* __restrict__ near_count,
                                                   int32_t* __restrict__ chunk_list_count,
-                                                  int32_t* __restrict__ super_counts, long long n_super_counts) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+                                                  int32_t* __restrict__ super_counts, long long n_super_counts,
+                                                  unsigned long long* __restrict__ stats, long long nodes,
+                                                  long long base_nodes) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+    unsigned long long* slot = stat_slot(stats);
+    atomicAdd(&slot[OV_STAT_FLAG_STARTS], 1ULL);
+    atomicAdd(&slot[OV_STAT_FLAG_BYTES_WRITTEN], (unsigned long long)nodes);
+    atomicAdd(&slot[OV_STAT_BASE_BYTES_READ], (unsigned long long)base_nodes);
+  }
   // the slot's superchunk counts start from zero (the last reader of this
   // slot's counts, the previous compaction using it, is done)
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
@@ -951,6 +979,62 @@ __global__ void __launch_bounds__(256) k_near_from_holes(const GridDev* __restri
   }
 }
 
+// Near list from a flags buffer alone (the fringe call of the C ABI, which
+// may be given flags from any hole cut): one block per tile at a time, a
+// quarter row of 16 flag bytes per thread; a tile holding a hole lists its
+// 125 reach combinations, one per thread.
+__global__ void __launch_bounds__(256) k_near_from_flags(const GridDev* __restrict__ grids,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const int4* __restrict__ tile_info, long long total_tiles,
+                                                        const unsigned int* __restrict__ d_stamp,
+                                                        unsigned int* __restrict__ tile_near,
+                                                        int4* __restrict__ near_list,
+                                                        int32_t* __restrict__ near_count) {
+  static_assert(kTileI == 64 && kTileJ * kTileK * 4 == 256, "a 256-thread block covers a tile, 16 bytes a thread");
+  const unsigned int stamp = *d_stamp;
+  for (long long tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    const int4 info = tile_info[tile];
+    const GridDev& G = grids[info.x];
+    const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int j = info.z * kTileJ + (row & 7), k = info.w * kTileK + (row >> 3);
+    bool hole = false;
+    if (j < G.nj && k < G.nk) {
+      const int i0 = info.y * kTileI + 16 * q, i1 = min(G.ni, i0 + 16);
+      const uint8_t* p = flags + G.node_off + (long long)G.ni * ((long long)j + (long long)G.nj * k);
+      if (i1 - i0 == 16 && (((uintptr_t)(p + i0)) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p + i0);
+        // state bits 0-1 of each byte equal to 1 (HOLE): bit 0 set, bit 1 clear
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hole |= ((w[e] & ~(w[e] >> 1)) & 0x01010101u) != 0u;
+      } else {
+        for (int i = i0; i < i1; ++i) hole |= (p[i] & 3) == kHole;
+      }
+    }
+    hole = __syncthreads_or(hole);
+    if (hole && threadIdx.x < 125)
+      mark_near((int)threadIdx.x, info.x, info.y, info.z, info.w, G.ni, G.nj, G.nk, G.per, G.tiles_i, G.tiles_j,
+                G.tile_off, stamp, tile_near, near_list, near_count);
+  }
+}
+
+hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t s) {
+  const long long nt = ctx->total_tiles;
+  const int slot = 0, gen = 0;
+  unsigned int* st = ctx->d_stamp + 1 + slot;
+  int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, nt);
+  int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
+  const long long nsc = kSuperSlots * ctx->nsuper;
+  int32_t* sc = ctx->d_super_counts + (long long)slot * nsc;
+  // a new stamp (empty near and chunk lists, zero superchunk counts)
+  hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
+                     ctx->d_stamp, st, nc, ctx->d_chunk_list_count + slot, sc, nsc);
+  const long long nb = std::max(1LL, std::min(nt, (long long)ctx->num_cus * 8));
+  hipLaunchKernelGGL(k_near_from_flags, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_tile_info,
+                     nt, st, ctx->d_tile_near, nl, nc);
+  return hipGetLastError();
+}
+
 template <typename CT>
 static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, unsigned int* st,
                              unsigned int* tile_hole) {
@@ -993,10 +1077,14 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
       const long long rb = std::max(1LL, std::min(nt, (long long)ctx->num_cus * 8));
       hipLaunchKernelGGL(k_flag_reset, dim3((unsigned)rb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
                          ctx->d_near_list + (og * kSlots + slot) * std::max(1LL, nt),
-                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc);
+                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc, ctx->d_stats);
     } else {
+      long long base_nodes = 0;
+      for (const auto& g : ctx->grids)
+        if (g.d.has_outer) base_nodes += g.d.nnodes;
       hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
-                         ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc);
+                         ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc,
+                         ctx->d_stats, ctx->node_off.back(), base_nodes);
     }
     const long long nsub = nt * kSubPerTile;
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
@@ -1697,7 +1785,8 @@ int overset_fringe_compact(ov_ctx* ctx, int32_t nf, uint8_t* flags, int32_t* q_g
   if (nf < 0 || nf > kMaxNf) return fail(ctx, OV_EINVAL, "overset_fringe_compact: nf must be in 0..%d", kMaxNf);
   if (capacity < 0) return fail(ctx, OV_EINVAL, "overset_fringe_compact: negative capacity");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_fringe(ctx, nf, flags, s);
+  hipError_t e = launch_near_from_flags(ctx, flags, s);
+  if (e == hipSuccess) e = launch_fringe(ctx, nf, flags, s);
   if (e == hipSuccess) e = launch_compact(ctx, flags, q_grid, q_node, capacity, (long long*)d_count, s);
   return launched(ctx, e, "overset_fringe_compact");
 }

@@ -73,3 +73,45 @@ def test_recorded_traffic_only_for_the_sources_it_was_measured_on(tmp_path, monk
     assert bench.recorded_traffic("k_back|C9|mixed") is None
     src.write_text("// version 2\n")
     assert bench.recorded_traffic("k_back|C9|fp64") is None
+
+
+def test_driver_argument_set_times_the_back_half():
+    """The driver runs `--gpus 1 --steps 20 --warmup 5`: the executor must
+    time k_back on several of those steps (counted from the first timed
+    step, not from the executor's first step)."""
+    args = bench.make_parser().parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert args.roofline == "back" and args.time_every > 0
+    got = bench.sampled_steps(args.steps, args.time_every)
+    assert got[0] == 0 and len(got) >= 3 and max(got) < args.steps
+
+
+def test_counter_runs_are_detected(monkeypatch):
+    monkeypatch.delenv("ROCPROF_COUNTER_COLLECTION", raising=False)
+    assert not bench.profiler_counting()
+    for v in ("1", "True", "true"):
+        monkeypatch.setenv("ROCPROF_COUNTER_COLLECTION", v)
+        assert bench.profiler_counting()
+    monkeypatch.setenv("ROCPROF_COUNTER_COLLECTION", "0")
+    assert not bench.profiler_counting()
+
+
+def test_roofline_objects_from_work_counters():
+    """Per-launch algorithmic work from summed counters, and the bound set by
+    the larger fraction."""
+    stat = [0] * 9
+    stat[bench.ST_BACK] = 2
+    stat[bench.ST_CELLS] = 2 * 1000
+    stat[bench.ST_ITERS] = 2 * 3000
+    r = bench.back_roofline(stat, 500.0, 10e-6, "fp64", 8, 800, None)
+    hb = r["hbm_view"]["algorithmic_bytes_per_launch"]
+    assert hb == bench.back_bytes_per_query(8) * 500 + bench.BACK_BYTES_PER_CELL * 1000 + 32 * 800
+    fl = r["alu_view"]["algorithmic_flops_per_launch"]
+    assert fl == bench.FLOPS_PER_CELL["fp64"] * 1000 + bench.FLOPS_PER_NEWTON_ITER * 3000 + bench.FLOPS_PER_QUERY * 500
+    assert r["bound"] == ("hbm" if r["hbm_view"]["frac"] >= r["alu_view"]["frac"] else "alu")
+    stat = [0] * 9
+    stat[bench.ST_HC_CALLS] = 4
+    stat[bench.ST_FLAG_W] = 4 * 4096
+    stat[bench.ST_BASE_R] = 4 * 1024
+    stat[bench.ST_HC_NODES] = 4 * 100
+    h = bench.holecut_roofline(stat, 5e-6, "mixed", 10, "t")
+    assert h["algorithmic_bytes_per_launch"] == 4096 + 1024 + 13 * 100 + 32 * 10

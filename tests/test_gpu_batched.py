@@ -99,3 +99,19 @@ def test_shells_full_size_pipelined_sampled_steps():
     w = W.c4(steps=500)
     stats = _run_pipeline(w, [0, 499], "mixed", options={"field_layout": 1, "max_walk": 8})
     assert all(s["orphans"] == 0 for s in stats)
+
+
+@pytest.mark.timeout(300)
+def test_shells_full_size_tuned_parameters():
+    """The full-size shells workload through the executor with the tuned
+    parameters the benchmark applies (streams, hole-cut width, persistence,
+    back-half block and workgroups, walk limit), checked against the oracle."""
+    from paper_1910_09315_amd import autotune as AT
+    w = W.c4(steps=500)
+    tuned = AT.load(AT.signature(w, "mixed"))
+    assert tuned is not None, "no tuned entry for this workload"
+    p = dict(tuned["params"])
+    opts = {k: p[k] for k in AT.CTX_OPTIONS if k in p}
+    opts["field_layout"] = 1
+    stats = _run_pipeline(w, [0, 3, 250], "mixed", stages=p["stages"], options=opts)
+    assert all(s["orphans"] == 0 for s in stats)

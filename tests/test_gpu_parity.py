@@ -321,3 +321,56 @@ def test_buffer_wraps_two_tiles_across_a_thin_periodic_seam():
     assert ((f[:, 118, :4] & 3) == oracle.ST_FRINGE).sum() == 0
     _run_and_compare(w, [0])
     _run_and_compare(w, [0], options={"holecut_cull": 0})
+
+
+def test_fringe_compact_on_flags_of_another_hole_cut():
+    """overset_fringe_compact finds the hole tiles from the flags it is given:
+    two hole cuts (steps 0 and 2) into two buffers, then the fringe
+    compaction of the first buffer, run after the second hole cut, still
+    gives step 0's flags and query list, and the rest of that step matches
+    the oracle."""
+    from paper_1910_09315_amd import binding as B
+    from paper_1910_09315_amd.assembly import StepBuffers
+    w = W.c1_small(steps=3)
+    o = oracle.Oracle(w.grids, w.nf)
+    for precision, tol in (("fp64", dict(value_rtol=1e-12, s_tol=1e-12, qx_tol=1e-14)),
+                           ("mixed", dict(value_rtol=1e-5, s_tol=1e-4, qx_tol=1e-6))):
+        a = _assembly(w, precision)
+        other = StepBuffers(a.dev, a.total, a.capacity, a.dtype)
+        p0, p2 = a.as_poses(w.poses[0]), a.as_poses(w.poses[2])
+        B.overset_holecut(a.ctx, p0, a.flags)
+        B.overset_holecut(a.ctx, p2, other.flags)
+        B.overset_fringe_compact(a.ctx, a.nf, a.flags, a.q_grid, a.q_node, a.capacity, a.d_count)
+        a.back(p0, a.buf)
+        g = a.results()
+        r = o.step(w.poses[0], w.fields)
+        st = compare(o, w.poses[0], r, g, **tol)
+        print("fringe on step-0 flags after the step-2 hole cut", precision, st, flush=True)
+        # and the other buffer's own fringe pass gives step 2
+        B.overset_fringe_compact(a.ctx, a.nf, other.flags, other.q_grid, other.q_node, a.capacity, other.d_count)
+        a.back(p2, other)
+        compare(o, w.poses[2], o.step(w.poses[2], w.fields), a.results(other), **tol)
+        assert (a.ctx.status() & ~2) == 0
+
+
+@pytest.mark.parametrize("alone", [True, False])
+def test_executor_stage_timing_counts_from_the_next_step(alone):
+    """ov_pipe_set_timing times the next submitted step and every `every`-th
+    one after it, whatever the executor's step count when it is called."""
+    from paper_1910_09315_amd.assembly import Pipeline
+    w = W.c1_small(steps=12)
+    a = _assembly(w, "fp64")
+    pipe = Pipeline(a, a.capacity, native=True, stages=3, max_timed=16)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    for t in range(5):
+        pipe.submit(t, poses[t])
+    pipe.native.stage_times(0)
+    pipe.native.set_timing(3, 2, alone=alone)
+    for t in range(5, 12):
+        pipe.submit(t, poses[t])
+    pipe.join()
+    torch.cuda.synchronize()
+    pipe.native.set_timing(0)
+    ms = pipe.native.stage_times(16)
+    assert len(ms) == 3 and all(x > 0 for x in ms)  # steps 5, 8 and 11
+    pipe.close()
