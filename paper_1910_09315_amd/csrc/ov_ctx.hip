@@ -856,13 +856,13 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
     HIPCHK(hipMemcpy(ctx->d_fill_ranges, ranges.data(), sizeof(long long) * ranges.size(), hipMemcpyHostToDevice),
            "fill ranges copy");
   }
-  HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (1 + kSlots)), "hipMalloc stamps");
+  HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (2 + kSlots)), "hipMalloc stamps");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * kSlots * nt), "hipMalloc tile holes");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
   // two near lists per slot (alternate steps of a slot write one each)
   HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int4) * 2 * kSlots * nt), "hipMalloc near lists");
   HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t) * 2 * kSlots), "hipMalloc near counts");
-  HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (1 + kSlots), s), "stamp init");
+  HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (2 + kSlots), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * kSlots * nt, s), "tile hole init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
   HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t) * 2 * kSlots, s), "near count init");

@@ -143,7 +143,8 @@ struct ov_ctx {
   // the fringe pass and the compaction. Each hole cut starts a new stamp; a
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
-  unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`
+  unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`,
+                                              // [1 + kSlots] counter of the C-ABI fringe call's own lists
   unsigned int* d_tile_hole = nullptr;        // per slot and tile: the stamp of the slot's step if the tile holds a hole
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
   int4* d_near_list = nullptr;                // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
@@ -192,16 +193,41 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 // that step's result (the step executors).
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0,
                           bool reset = false);
+// The scratch of one fringe pass and compaction: the near-tile list, the
+// chunk list and the compaction's per-chunk and per-superchunk counts. It
+// lives in the context's slots, or (the no-allocation fringe call) in the
+// library's static device array.
+struct FrontScratch {
+  unsigned int* counter;             // step counter: a new stamp is its next value
+  unsigned int* stamp;               // this pass's stamp
+  int4* near_list;                   // [total_tiles]
+  int32_t* near_count;
+  unsigned int* tile_near;           // [total_tiles]: stamp if on the near list
+  unsigned int* chunk_stamp;         // [nchunks]: stamp if on the chunk list
+  int32_t* chunk_list;               // [nchunks]: the static chunks, then this pass's
+  int32_t* chunk_list_count;         // length of this pass's part
+  unsigned long long* chunk_counts;  // [nchunks]: stamp << 32 | query count
+  int32_t* super_counts;             // [kSuperSlots * nsuper]
+  long long* super_offsets;          // [nsuper + 1]
+};
+// The context's scratch of slot `slot` and near list `gen`.
+FrontScratch ctx_scratch(ov_ctx* ctx, int slot, int gen);
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0);
+hipError_t launch_fringe_in(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, const FrontScratch& fs);
 // A new stamp on slot 0 and its near list built from the flags themselves
 // (tiles holding a hole), for a fringe pass whose flags came from any hole cut.
 hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t s);
+// The near list of fs from the flags, under fs's current stamp.
+hipError_t launch_near_list_in(ov_ctx* ctx, const uint8_t* flags, hipStream_t s, const FrontScratch& fs);
 int build_static_chunks(ov_ctx* ctx, hipStream_t s);
 // fused: the write kernel forms the superchunk offsets itself (no scan
 // kernel); only for callers whose next hole cut on this slot precedes the
 // next compaction (the step executors).
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
                           long long capacity, long long* d_count, hipStream_t s, int slot = 0, bool fused = false);
+hipError_t launch_compact_in(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
+                             long long capacity, long long* d_count, hipStream_t s, const FrontScratch& fs,
+                             bool fused);
 hipError_t launch_transform(ov_ctx* ctx, const double* poses, const int32_t* q_grid, const int32_t* q_node,
                             const long long* d_count, long long capacity, void* qx, hipStream_t s);
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,

@@ -430,20 +430,25 @@ static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI *
 // `counter` numbers the steps of the context; `d_stamp` is the stamp of the
 // scratch slot this step uses (separate slots let the hole cut of one step
 // overlap the fringe pass of the previous one).
+// `high` (0 or kStampHigh) keeps the stamps of two counters apart: the hole
+// cut's starts count on one, the fringe call of the C ABI (which starts its
+// own lists from the flags it is given) on another, so that the hole cut's
+// counter advances once per step (the warm start dates its records by it).
+constexpr unsigned int kStampHigh = 0x80000000u;
 __device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigned int* d_stamp, int32_t* near_count,
-                                                  int32_t* chunk_list_count) {
-  unsigned int v = *counter + 1u;
+                                                  int32_t* chunk_list_count, unsigned int high = 0u) {
+  unsigned int v = (*counter + 1u) & ~kStampHigh;
   v = v == 0u ? 1u : v;  // 0 marks "never listed"
   *counter = v;
-  *d_stamp = v;
+  *d_stamp = v | high;
   *near_count = 0;
   *chunk_list_count = 0;
 }
 
 __global__ void k_begin_step(unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
                              int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count,
-                             int32_t* __restrict__ super_counts, long long n_super_counts) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+                             int32_t* __restrict__ super_counts, long long n_super_counts, unsigned int high) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, high);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
        i += (long long)gridDim.x * blockDim.x)
     super_counts[i] = 0;
@@ -1018,21 +1023,39 @@ __global__ void __launch_bounds__(256) k_near_from_flags(const GridDev* __restri
   }
 }
 
-hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t s) {
+FrontScratch ctx_scratch(ov_ctx* ctx, int slot, int gen) {
+  const long long nt = std::max(1LL, ctx->total_tiles);
+  FrontScratch f;
+  f.counter = ctx->d_stamp;
+  f.stamp = ctx->d_stamp + 1 + slot;
+  f.near_list = ctx->d_near_list + (gen * kSlots + slot) * nt;
+  f.near_count = ctx->d_near_count + gen * kSlots + slot;
+  f.tile_near = ctx->d_tile_near;
+  f.chunk_stamp = ctx->d_chunk_stamp;
+  f.chunk_list = ctx->d_chunk_list;
+  f.chunk_list_count = ctx->d_chunk_list_count + slot;
+  f.chunk_counts = ctx->d_chunk_counts;
+  f.super_counts = ctx->d_super_counts + (long long)slot * kSuperSlots * ctx->nsuper;
+  f.super_offsets = ctx->d_super_offsets;
+  return f;
+}
+
+hipError_t launch_near_list_in(ov_ctx* ctx, const uint8_t* flags, hipStream_t s, const FrontScratch& fs) {
   const long long nt = ctx->total_tiles;
-  const int slot = 0, gen = 0;
-  unsigned int* st = ctx->d_stamp + 1 + slot;
-  int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, nt);
-  int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
-  const long long nsc = kSuperSlots * ctx->nsuper;
-  int32_t* sc = ctx->d_super_counts + (long long)slot * nsc;
-  // a new stamp (empty near and chunk lists, zero superchunk counts)
-  hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
-                     ctx->d_stamp, st, nc, ctx->d_chunk_list_count + slot, sc, nsc);
   const long long nb = std::max(1LL, std::min(nt, (long long)ctx->num_cus * 8));
   hipLaunchKernelGGL(k_near_from_flags, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_tile_info,
-                     nt, st, ctx->d_tile_near, nl, nc);
+                     nt, fs.stamp, fs.tile_near, fs.near_list, fs.near_count);
   return hipGetLastError();
+}
+
+hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t s) {
+  FrontScratch fs = ctx_scratch(ctx, 0, 0);
+  fs.counter = ctx->d_stamp + 1 + kSlots;  // the fringe call's own counter
+  const long long nsc = kSuperSlots * ctx->nsuper;
+  // a new stamp (empty near and chunk lists, zero superchunk counts)
+  hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
+                     fs.counter, fs.stamp, fs.near_count, fs.chunk_list_count, fs.super_counts, nsc, kStampHigh);
+  return launch_near_list_in(ctx, flags, s, fs);
 }
 
 template <typename CT>
@@ -1111,7 +1134,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
-                     counter, st, nc, clc, sc, nsc);
+                     counter, st, nc, clc, sc, nsc, 0u);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st, th);
   else launch_holecut_t<double>(ctx, poses, flags, s, st, th);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
@@ -1346,17 +1369,21 @@ __global__ void __launch_bounds__(256) k_fringe_tiles(const GridDev* __restrict_
 }
 
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot, int gen) {
+  return launch_fringe_in(ctx, nf, flags, s, ctx_scratch(ctx, slot, gen));
+}
+
+hipError_t launch_fringe_in(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, const FrontScratch& fs) {
   const int ng = (int)ctx->grids.size();
-  const int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, ctx->total_tiles);
-  const int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
-  const unsigned int* st = ctx->d_stamp + 1 + slot;
-  int32_t* clc = ctx->d_chunk_list_count + slot;
+  const int4* nl = fs.near_list;
+  const int32_t* nc = fs.near_count;
+  const unsigned int* st = fs.stamp;
+  int32_t* clc = fs.chunk_list_count;
   // persistent blocks over the near list (its length is on the device)
   long long g = std::max(1LL, std::min<long long>(ctx->total_tiles,
                                                     (long long)ctx->num_cus * (ctx->persist > 0 ? ctx->persist : 4)));
 #define OV_FRINGE_ARGS                                                                                            \
-  ctx->d_grids, ng, flags, nl, nc, st, ctx->d_chunk_static, ctx->d_chunk_stamp, ctx->d_chunk_list, \
-      clc, ctx->n_static_chunks
+  ctx->d_grids, ng, flags, nl, nc, st, ctx->d_chunk_static, fs.chunk_stamp, fs.chunk_list, clc, \
+      ctx->n_static_chunks
   switch (nf) {
     case 0:
       hipLaunchKernelGGL(k_fringe_tiles<0>, dim3((unsigned)g), dim3(256), 0, s, OV_FRINGE_ARGS);
@@ -1605,24 +1632,30 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact_write(const GridDev
 
 hipError_t launch_compact(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node, long long capacity,
                           long long* d_count, hipStream_t s, int slot, bool fused) {
+  return launch_compact_in(ctx, flags, q_grid, q_node, capacity, d_count, s, ctx_scratch(ctx, slot, 0), fused);
+}
+
+hipError_t launch_compact_in(ov_ctx* ctx, const uint8_t* flags, int32_t* q_grid, int32_t* q_node,
+                             long long capacity, long long* d_count, hipStream_t s, const FrontScratch& fs,
+                             bool fused) {
   const long long total = ctx->node_off.back();
-  const unsigned int* st = ctx->d_stamp + 1 + slot;
-  const int32_t* clc = ctx->d_chunk_list_count + slot;
-  int32_t* sc = ctx->d_super_counts + (long long)slot * kSuperSlots * ctx->nsuper;
+  const unsigned int* st = fs.stamp;
+  const int32_t* clc = fs.chunk_list_count;
+  int32_t* sc = fs.super_counts;
   // persistent blocks over the chunk list (its length is on the device):
   // as many as the chip holds at once (8 of 256 threads per CU), since each
   // block takes its chunks one after another and every chunk is a chain of
   // dependent memory round trips
   const long long grid = std::max(1LL, std::min<long long>(ctx->nchunks, (long long)ctx->num_cus * 8));
   hipLaunchKernelGGL(k_compact_count, dim3((unsigned)grid), dim3(kCompactThreads), 0, s, flags, total,
-                     ctx->d_chunk_counts, sc, ctx->d_chunk_list, clc, ctx->n_static_chunks, st);
+                     fs.chunk_counts, sc, fs.chunk_list, clc, ctx->n_static_chunks, st);
   fused = fused && ctx->nsuper <= kFusedScanMax;
   if (!fused)
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, sc, ctx->nsuper, ctx->d_super_offsets, d_count,
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, sc, ctx->nsuper, fs.super_offsets, d_count,
                        capacity, ctx->d_status);
 #define OV_WRITE_ARGS                                                                                                \
-  ctx->d_grids, (int)ctx->grids.size(), flags, total, ctx->d_chunk_counts, ctx->nchunks, ctx->d_super_offsets, sc,   \
-      ctx->nsuper, d_count, ctx->d_status, ctx->d_chunk_list, clc, ctx->n_static_chunks, st, q_grid, q_node, capacity
+  ctx->d_grids, (int)ctx->grids.size(), flags, total, fs.chunk_counts, ctx->nchunks, fs.super_offsets, sc,           \
+      ctx->nsuper, d_count, ctx->d_status, fs.chunk_list, clc, ctx->n_static_chunks, st, q_grid, q_node, capacity
   if (fused)
     hipLaunchKernelGGL(k_compact_write<true>, dim3((unsigned)grid), dim3(kCompactThreads),
                        sizeof(long long) * (ctx->nsuper + 1), s, OV_WRITE_ARGS);
