@@ -254,6 +254,21 @@ int overset_holecut(ov_ctx *ctx, const double *poses, uint8_t *flags, void *stre
 int overset_fringe_compact(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
                            int64_t capacity, int64_t *d_count, void *stream);
 
+/* overset_fringe_compact for callers that cannot allocate device memory
+ * (work under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation). Same arguments, results and errors as overset_fringe_compact;
+ * the call's scratch (near-tile list, chunk list, per-chunk and
+ * per-superchunk counts) lives in a static device array of the library
+ * (6 MiB per device, held until the process ends) instead of the context's
+ * memory, and the call allocates nothing. A context whose grids need more
+ * scratch than the array holds (about 20 bytes per 64x8x8 node tile plus
+ * 17 bytes per 4096 nodes) is refused with OV_ECAPACITY before any launch.
+ * All calls on one device share its array, and each starts by clearing it:
+ * calls on one device must be ordered (one stream, or streams ordered
+ * against each other), or they race. */
+int overset_fringe_compact_noalloc(ov_ctx *ctx, int32_t nf, uint8_t *flags, int32_t *q_grid, int32_t *q_node,
+                                   int64_t capacity, int64_t *d_count, void *stream);
+
 /* Inertial-frame positions of the compacted queries (the coordinate packets
  * of Sec. 2.2.3 item 6), stored as the offset from the query grid's frame
  * centre: qx = x - c_g = R_g X_g[node], for i < *d_count. The consumer adds

@@ -35,7 +35,7 @@ EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "o
            "ov_finalize", "ov_num_grids",
            "ov_total_nodes", "ov_node_offsets", "ov_set_option", "ov_reset_history", "ov_status_fetch",
            "ov_stats_fetch", "overset_status_fetch", "overset_last_error",
-           "overset_holecut", "overset_fringe_compact", "overset_transform", "overset_donor_search",
+           "overset_holecut", "overset_fringe_compact", "overset_fringe_compact_noalloc", "overset_transform", "overset_donor_search",
            "overset_interp", "overset_frame_velocity", "overset_interp_matrix", "overset_interp_apply",
            "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
            "ov_pipe_submit",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "overset_last_error": (ctypes.c_char_p, [_P]),
         "overset_holecut": (ctypes.c_int, [_P, _P, _P, _P]),
         "overset_fringe_compact": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _P, _P]),
+        "overset_fringe_compact_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _P, _P]),
         "overset_transform": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P]),
         "overset_donor_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P]),
         "overset_interp": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P]),
@@ -211,6 +212,12 @@ def overset_fringe_compact(ctx: Context, nf, flags, q_grid, q_node, capacity, d_
     ctx.check(ctx.lib.overset_fringe_compact(ctx.h, int(nf), _ptr(flags), _ptr(q_grid), _ptr(q_node),
                                              int(capacity), _ptr(d_count), _stream(stream)),
               "overset_fringe_compact")
+
+
+def overset_fringe_compact_noalloc(ctx: Context, nf, flags, q_grid, q_node, capacity, d_count, stream=None):
+    ctx.check(ctx.lib.overset_fringe_compact_noalloc(ctx.h, int(nf), _ptr(flags), _ptr(q_grid), _ptr(q_node),
+                                                     int(capacity), _ptr(d_count), _stream(stream)),
+              "overset_fringe_compact_noalloc")
 
 
 def overset_transform(ctx: Context, poses, q_grid, q_node, d_count, capacity, qx, stream=None):

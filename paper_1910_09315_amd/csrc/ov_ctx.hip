@@ -485,6 +485,10 @@ int ov_ctx_create(ov_ctx** out, int device, int precision) {
     delete ctx;
     return OV_EHIP;
   }
+  // the no-allocation fringe call's static array on this device (without
+  // it that one call refuses to run; nothing else depends on it)
+  void* sp = nullptr;
+  if (static_scratch_address(device, &sp) == hipSuccess) ctx->static_scratch = sp;
   *out = ctx;
   return OV_OK;
 }

@@ -174,6 +174,7 @@ struct ov_ctx {
   int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
   int frame_velocity = 0;      // executors: interpolated velocities in the receiver's frame
   bool has_mesh = false;       // some grid's blank region is a triangulation
+  void* static_scratch = nullptr;  // this device's copy of the no-allocation call's static array
   std::string err;
 };
 
@@ -210,6 +211,9 @@ struct FrontScratch {
   int32_t* super_counts;             // [kSuperSlots * nsuper]
   long long* super_offsets;          // [nsuper + 1]
 };
+// Device address of this device's copy of the static scratch array of the
+// no-allocation fringe call (looked up once per device; `device` current).
+hipError_t static_scratch_address(int device, void** out);
 // The context's scratch of slot `slot` and near list `gen`.
 FrontScratch ctx_scratch(ov_ctx* ctx, int slot, int gen);
 hipError_t launch_fringe(ov_ctx* ctx, int nf, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0);
