@@ -369,6 +369,10 @@ def measure(args, w=None):
             if args.stages is None:
                 args.stages = params["stages"]
             log(f"[bench] tuned parameters {params}")
+    for kv in args.opt:
+        k, v = kv.split("=", 1)
+        a.set_option(k, int(v))
+        log(f"[bench] option {k} = {v}")
     if args.stages is None:
         args.stages = 3
     if args.stages > 1 and profiler_counting():
@@ -601,12 +605,20 @@ def step_report(pipe, a, poses, w, t0: int, n: int, dev, precision: str, es: int
     st = r["status"]
     kind = st & 3
     m = max(1, len(st))
+    # cells each query's walk visited (status bits 8-15), and the largest of
+    # each run of 64 consecutive queries (a wavefront walks as long as its
+    # longest walk)
+    vis = ((st >> 8) & 255).astype(np.float64)
+    nw = len(vis) // 64
     rep["outcomes_last_step"] = {
         "step": last % w.steps, "queries": int(len(st)),
         "walk_frac": round(float(np.sum(kind == 1)) / m, 6),
         "fallback_scan_frac": round(float(np.sum(kind == 2)) / m, 6),
         "orphan_frac": round(float(np.sum(kind == 0)) / m, 6),
-        "fp64_fixed_frac": round(float(np.sum((st & 4) != 0)) / m, 6)}
+        "fp64_fixed_frac": round(float(np.sum((st & 4) != 0)) / m, 6),
+        "walk_cells_mean": round(float(vis.mean()), 3) if len(vis) else 0.0,
+        "walk_cells_max_per_64_mean": round(float(vis[:nw * 64].reshape(nw, 64).max(axis=1).mean()), 3)
+        if nw else 0.0}
     return rep
 
 
@@ -654,6 +666,8 @@ def make_parser():
     ap.add_argument("--max-walk", type=int, default=0, help="walk steps before the fallback scan (0: library default)")
     ap.add_argument("--unfused-back", action="store_true",
                     help="native executor: transform, search and interpolation as separate kernels")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                    help="a context option (binding.OPT name) set after the tuned parameters; repeatable")
     ap.add_argument("--npl", type=int, default=0, choices=(0, 4, 16),
                     help="candidate hole-cut nodes per lane (0: the tuned or default choice)")
     ap.add_argument("--time-every", type=int, default=4,
@@ -716,6 +730,7 @@ def main():
         for prec in [p for p in args.compare_precisions.split(",") if p]:
             a2 = copy.copy(args)
             a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, prec, None, None, 0
+            a2.opt = []
             a2.roofline = "back"
             a2.next_rows = args.next_rows and prec == "mixed"
             o2, w2 = measure(a2, w2)

@@ -111,8 +111,10 @@ enum ov_option {
     OV_OPT_HOLECUT_NPL = 9, /* culled hole cut, candidate nodes per lane: 16 (default, one wavefront per
                                sub-tile) or 4 (one block per sub-tile: shorter latency when candidates are few) */
     OV_OPT_BACK_FUSED = 10, /* step executors (ov_pipe_*): 1 (default) runs transform, donor search and
-                               interpolation of a step as one kernel; 0 as the separate kernels of the three
-                               calls. Same results. */
+                               interpolation of a step as one kernel; 2 as two kernels, the second taking the
+                               queries the first could not decide (FP64 corrections, brute-force scans) from a
+                               queue the executor owns, so that the first holds only the walk's registers;
+                               0 as the separate kernels of the three calls. Same results. */
     OV_OPT_BACK_BLOCKS = 11,/* workgroups per CU of that one kernel (1..32, default 8) */
     OV_OPT_BACK_BLOCK = 12, /* its threads per workgroup: 64, 128 or 256 (default; also the width of the
                                cooperative fallback scan) */

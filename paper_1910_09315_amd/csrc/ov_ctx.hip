@@ -446,15 +446,41 @@ __global__ void k_pack_xyz(const double* __restrict__ X, const double* __restric
     P[m] = make_double4(X[m], Y[m], Z[m], 0.0);
 }
 
+__global__ void k_pack_xyz_f32(const double* __restrict__ X, const double* __restrict__ Y,
+                               const double* __restrict__ Z, long long n, double ax, double ay, double az,
+                               float4* __restrict__ P) {
+  for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (long long)gridDim.x * blockDim.x)
+    P[m] = make_float4((float)(X[m] - ax), (float)(Y[m] - ay), (float)(Z[m] - az), 0.0f);
+}
+
 // (x, y, z, 0) per node, 32 bytes: a cell's corners i and i+1 share a
 // 64-byte span, so one cell is 4 row pairs instead of 12 separate lines of
 // the three coordinate arrays. Built once: body-frame coordinates are fixed.
+// Mixed precision adds the FP32 walk's copy, 16 bytes per node: offsets
+// from the centre of the nodes' box, rounded to FP32. |offset| is at most
+// the box's half extent h, so each component's rounding is at most 2^-24 h
+// (round to nearest; the FP64 difference before it is exact to 2^-53).
 int build_gather_layout(ov_ctx* ctx, GridHost& g, hipStream_t s) {
   HIPCHK(hipMalloc(&g.p, sizeof(double4) * g.d.nnodes), "hipMalloc gather layout");
   hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.d.nnodes)), dim3(256), 0, s, g.d.X, g.d.Y, g.d.Z, g.d.nnodes,
                      g.p);
   HIPCHK(hipGetLastError(), "gather layout");
   g.d.P = g.p;
+  g.d.PF = nullptr;
+  g.d.pf_err = 0.0;
+  if (ctx->precision == OV_MIXED) {
+    double half = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      g.d.anchor[d] = 0.5 * (g.d.blo[d] + g.d.bhi[d]);
+      half = std::max(half, 0.5 * (g.d.bhi[d] - g.d.blo[d]));
+    }
+    g.d.pf_err = std::ldexp(half, -24) * (1.0 + 1e-6);
+    HIPCHK(hipMalloc(&g.pf, sizeof(float4) * g.d.nnodes), "hipMalloc FP32 gather layout");
+    hipLaunchKernelGGL(k_pack_xyz_f32, dim3(blocks_for(g.d.nnodes)), dim3(256), 0, s, g.d.X, g.d.Y, g.d.Z,
+                       g.d.nnodes, g.d.anchor[0], g.d.anchor[1], g.d.anchor[2], g.pf);
+    HIPCHK(hipGetLastError(), "FP32 gather layout");
+    g.d.PF = g.pf;
+  }
   return OV_OK;
 }
 
@@ -502,6 +528,7 @@ int ov_ctx_destroy(ov_ctx* ctx) {
     (void)hipFree(g.yf);
     (void)hipFree(g.zf);
     (void)hipFree(g.p);
+    (void)hipFree(g.pf);
     (void)hipFree(g.bstart);
     (void)hipFree(g.bcells);
     (void)hipFree(g.brep);
@@ -565,6 +592,8 @@ int ov_grid_add(ov_ctx* ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t period
   g.nck = (periodic & 4) ? nk : nk - 1;
   g.nnodes = n;
   g.ncells = (long long)g.nci * g.ncj * g.nck;
+  g.inv_nci = 1.0 / (double)g.nci;
+  g.inv_plane = 1.0 / ((double)g.nci * (double)g.ncj);
   if (g.ncells >= (1LL << 31)) return fail(ctx, OV_EDIMS, "too many cells");
   g.node_off = ctx->node_off.back();
   g.X = X;
@@ -941,7 +970,7 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       ctx->holecut_npl = (int)v;
       return OV_OK;
     case OV_OPT_BACK_FUSED:
-      if (v != 0 && v != 1) break;
+      if (v < 0 || v > 2) break;
       ctx->back_fused = (int)v;
       return OV_OK;
     case OV_OPT_BACK_BLOCKS:

@@ -45,6 +45,7 @@ struct GridDev {
   int ni, nj, nk, per;
   int nci, ncj, nck, blank_kind;
   long long node_off, nnodes, ncells;
+  double inv_nci, inv_plane;  // 1 / nci and 1 / (nci ncj), rounded: cell decomposition without division
   const double* X;
   const double* Y;
   const double* Z;
@@ -52,6 +53,12 @@ struct GridDev {
   const float* Yf;
   const float* Zf;
   const double4* P;  // (x, y, z, 0) per node: the donor search's gather layout
+  // mixed precision: (x, y, z, 0) per node in FP32 as offsets from `anchor`
+  // (the centre of the box of the grid's nodes), the FP32 walk's corners;
+  // every component's rounding is at most pf_err
+  const float4* PF;
+  double anchor[3];
+  double pf_err;
   double blank_prm[8];
   double cull_r2;  // body-frame sphere about the origin enclosing the blank region, squared
   int outer[6];
@@ -94,6 +101,7 @@ struct GridHost {
   float* yf = nullptr;
   float* zf = nullptr;
   double4* p = nullptr;
+  float4* pf = nullptr;
   long long* bstart = nullptr;
   int* bcells = nullptr;
   int* brep = nullptr;
@@ -246,10 +254,15 @@ hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* 
 // set, else the three launchers above. count_out (nullable) receives the
 // step's query count; slot is the step's front-half scratch slot (its stamp
 // dates the warm-start entries).
+// back_fused = 2 with a deferral queue (defer_items: capacity entries,
+// defer_count: two counters, zero before the first step; caller-owned, for
+// the back halves of one stream) runs it as two kernels: the walk, and the
+// FP64 corrections and brute-force scans of the queries the walk left.
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
-                       void* out, long long* count_out, hipStream_t st, int slot = 0);
+                       void* out, long long* count_out, hipStream_t st, int slot = 0, int32_t* defer_items = nullptr,
+                       unsigned int* defer_count = nullptr);
 hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st);
 hipError_t launch_frame_velocity(ov_ctx* ctx, const double* poses, const int32_t* q_grid,
                                  const int32_t* donor_grid, const long long* d_count, long long capacity, void* out,
@@ -382,21 +395,34 @@ __device__ __forceinline__ int grid_of_node(const long long* off, int ngrids, lo
   return lo;
 }
 
+// (ci, cj, ck) of a linear cell index without an integer division: a grid
+// has fewer than 2^31 cells, so the FP64 product with the rounded reciprocal
+// is within 2^-21 of the exact quotient, and its floor is the quotient or
+// one off it (only next to an exact multiple), which one comparison fixes.
+__device__ __forceinline__ int div_by(int c, int d, double inv) {
+  int q = (int)((double)c * inv);
+  if ((long long)q * d > c) --q;
+  else if ((long long)(q + 1) * d <= c) ++q;
+  return q;
+}
+
 __device__ __forceinline__ void cell_ijk(const GridDev& g, long long cell, int& ci, int& cj, int& ck) {
-  long long plane = (long long)g.nci * g.ncj;
-  ck = (int)(cell / plane);
-  long long r = cell - (long long)ck * plane;
-  cj = (int)(r / g.nci);
-  ci = (int)(r - (long long)cj * g.nci);
+  const int c = (int)cell;
+  const int plane = g.nci * g.ncj;
+  ck = div_by(c, plane, g.inv_plane);
+  const int r = c - ck * plane;
+  cj = div_by(r, g.nci, g.inv_nci);
+  ci = r - cj * g.nci;
 }
 
 // Node of corner c (c0 + 2 c1 + 4 c2) of cell (ci, cj, ck); periodic wrap.
+// 32-bit arithmetic: a grid has fewer than 2^31 nodes.
 __device__ __forceinline__ long long corner_node(const GridDev& g, int ci, int cj, int ck, int c) {
   int i = ci + (c & 1), j = cj + ((c >> 1) & 1), k = ck + ((c >> 2) & 1);
   i = (i == g.ni) ? 0 : i;
   j = (j == g.nj) ? 0 : j;
   k = (k == g.nk) ? 0 : k;
-  return (long long)i + (long long)g.ni * ((long long)j + (long long)g.nj * k);
+  return (long long)((unsigned)i + (unsigned)g.ni * ((unsigned)j + (unsigned)g.nj * (unsigned)k));
 }
 
 // Padded corner box of a cell (FP64), the same test the fallback scan applies.

@@ -30,6 +30,7 @@
 // launch per stream and the counter operations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "ov_internal.h"
@@ -62,6 +63,10 @@ struct ov_pipe {
   // per buffer set: steps started on it, and the near list its current step uses
   long long uses[3] = {0, 0, 0};
   int gen[3] = {0, 0, 0};
+  // deferral queue of the two-kernel back half (OV_OPT_BACK_FUSED = 2):
+  // entries for the largest capacity, two step counters (zeroed here)
+  int32_t* defer_items = nullptr;
+  unsigned int* defer_count = nullptr;
 };
 
 using namespace ov;
@@ -97,7 +102,7 @@ static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses
   }
   return launch_back(ctx, poses, b.flags, b.q_grid, b.q_node, b.qx, (const long long*)b.d_count, b.capacity,
                      b.donor_grid, b.donor_cell, b.s, b.status, p->fields, p->fields ? b.out : nullptr, count_out,
-                     s, slot);
+                     s, slot, p->defer_items, p->defer_count);
 }
 
 // Also forgets the buffer sets' history, so that the next direct step of
@@ -157,6 +162,11 @@ static int pipe_create(ov_ctx* ctx, int32_t nf, int nsets, const ov_step_buffers
     ok = ok && hipMalloc(&p->seq, sizeof(unsigned long long) * 3) == hipSuccess;
     ok = ok && hipMemset(p->seq, 0, sizeof(unsigned long long) * 3) == hipSuccess;
   }
+  long long max_cap = 1;
+  for (int k = 0; k < nsets; ++k) max_cap = std::max(max_cap, (long long)sets[k].capacity);
+  ok = ok && hipMalloc(&p->defer_items, sizeof(int32_t) * max_cap) == hipSuccess;
+  ok = ok && hipMalloc(&p->defer_count, sizeof(unsigned int) * 2) == hipSuccess;
+  ok = ok && hipMemset(p->defer_count, 0, sizeof(unsigned int) * 2) == hipSuccess;
   p->tb.assign(max_timed, nullptr);
   p->te.assign(max_timed, nullptr);
   for (int i = 0; i < max_timed && ok; ++i) {
@@ -343,6 +353,8 @@ int ov_pipe_destroy(ov_pipe* p) {
   for (int g = 0; g < 3; ++g)
     if (p->join[g]) (void)hipEventDestroy(p->join[g]);
   if (p->seq) (void)hipFree(p->seq);
+  if (p->defer_items) (void)hipFree(p->defer_items);
+  if (p->defer_count) (void)hipFree(p->defer_count);
   for (auto ev : p->tb)
     if (ev) (void)hipEventDestroy(ev);
   for (auto ev : p->te)

@@ -69,6 +69,35 @@ __device__ __forceinline__ void map_from_corners(const double P[8][3], const dou
 template <typename T>
 __device__ __forceinline__ void load_cell(const GridDev& G, int ci, int cj, int ck, const double xi[3],
                                           CellMap<T>& m) {
+  if (sizeof(T) == 4 && G.PF) {
+    // the FP32 walk: corners from the FP32 layout (16 bytes each, offsets
+    // from the grid's anchor); the query's offset from corner 0 formed in
+    // FP64 and then rounded. The corners' rounding (pf_err per component)
+    // enters the walk's acceptance test.
+    float P[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const ov_fv4 v = ((gmem<ov_fv4>*)gp((const float*)G.PF))[corner_node(G, ci, cj, ck, c)];
+      P[c][0] = v.x;
+      P[c][1] = v.y;
+      P[c][2] = v.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float p0 = P[0][d];
+      const float q1 = P[1][d] - p0, q2 = P[2][d] - p0, q3 = P[3][d] - p0, q4 = P[4][d] - p0;
+      const float q5 = P[5][d] - p0, q6 = P[6][d] - p0, q7 = P[7][d] - p0;
+      m.e[d] = (T)((xi[d] - G.anchor[d]) - (double)p0);
+      m.a[1][d] = (T)q1;
+      m.a[2][d] = (T)q2;
+      m.a[3][d] = (T)q4;
+      m.a[4][d] = (T)(q3 - q1 - q2);
+      m.a[5][d] = (T)(q5 - q1 - q4);
+      m.a[6][d] = (T)(q6 - q2 - q4);
+      m.a[7][d] = (T)(q7 - q3 - q5 - q6 + q1 + q2 + q4);
+    }
+    return;
+  }
   double P[8][3];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -199,11 +228,13 @@ __device__ __forceinline__ bool corners_valid(const uint8_t cf[8]) {
   return ok;
 }
 
+// One axis of a walk step. A periodic step is at most max(2, nc / 4)
+// cells from a cell in [0, nc) (nc >= 2), so one wrap brings it back.
 __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, bool& clamped) {
   int w = v + dv;
   if (periodic) {
-    w %= nc;
     if (w < 0) w += nc;
+    else if (w >= nc) w -= nc;
     return w;
   }
   if (w < 0) {
@@ -242,7 +273,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     T cond = 0, inv_norm = 0;
     bool conv =
         newton<T>(m, s, sizeof(T) == 4 ? &cond : (T*)nullptr, sizeof(T) == 4 ? &inv_norm : (T*)nullptr, iters);
-    const int here = (int)(ci + (long long)G.nci * (cj + (long long)G.ncj * ck));
+    const int here = (int)((unsigned)ci + (unsigned)G.nci * ((unsigned)cj + (unsigned)G.ncj * (unsigned)ck));
     if (sizeof(T) == 4) {
       // FP32 decides only clear cases: inside with margin >= 1e-4 in a
       // well-conditioned cell, or outside by more than the FP32 error can
@@ -253,8 +284,12 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
         return kDoubt;
       }
       const bool sure = conv && cond <= (T)kMixedCond;
-      // the position error in natural coordinates: |ds|_inf <= ||J^-1||_2 |e|_2
-      const T es = (T)(2.0 * 1.7320508075688772 * perr) * inv_norm;
+      // the position error in natural coordinates, |ds|_inf <= ||J^-1||_2 |e|_2,
+      // with e the query position's error (perr per component, twice over)
+      // plus the corners' FP32 rounding (the map moves by at most pf_err
+      // per component inside the cell, where the weights are a partition
+      // of unity)
+      const T es = (T)(1.7320508075688772 * (2.0 * perr + G.pf_err)) * inv_norm;
       if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
         return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid_map(G, fl, ci, cj, ck, th, stamp)) ? kFound : kToScan;
@@ -287,7 +322,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     int ni = step_axis(ci, di, G.nci, G.per & 1, clamped);
     int nj = step_axis(cj, dj, G.ncj, G.per & 2, clamped);
     int nk = step_axis(ck, dk, G.nck, G.per & 4, clamped);
-    const int next = (int)(ni + (long long)G.nci * (nj + (long long)G.ncj * nk));
+    const int next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
     hist[stepn & 3] = here;
     if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
     ci = ni;
@@ -792,17 +827,166 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Queue of the two-kernel back half: the queries the first kernel could not
+// decide (an FP32 walk left in doubt, or a walk that must hand over to the
+// brute-force scan), as indices into the step's query list. Their state is
+// kept in the step's outputs meanwhile, as between the passes of the search
+// call: donor_grid a marker, donor_cell the cell to go on from, status the
+// candidate position and the cells visited. Two counters serve alternate
+// steps (the parity of the step's stamp): a step's first kernel appends to
+// its own and clears the other, which the previous step's second kernel has
+// finished reading (the back halves of consecutive steps run in stream
+// order).
+struct DeferQueue {
+  int32_t* items;        // [capacity]
+  unsigned int* count;   // [2]
+};
+
+// The cooperative scans of a block's deferred queries, one query at a time
+// with all the block's threads (Alg. 3's fallback): the scan of the grid whose
+// walk failed, then the remaining candidate grids (walk, and scan where it
+// fails), all on the exact query position. Entry d of the LDS list is query
+// list_q[d] of thread list_owner[d] with deferral status list_st[d]; the
+// owner thread receives the result. The same rules as the scan pass of the
+// search call.
+template <typename T>
+__device__ __forceinline__ void block_deferred_scans(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ q_grid,
+                                                     const int32_t* __restrict__ q_node, int nd,
+                                                     const int* list_owner, const long long* list_q,
+                                                     const int* list_st, ScanLds& S, int max_walk, int& res_grid,
+                                                     int& res_cell, int& res_status, T rs[3], int& visited,
+                                                     bool& limit, int& my_iters, int& my_cands) {
+  for (int d = 0; d < nd; ++d) {
+    // every thread takes the deferred query (same values in all lanes)
+    const int owner = list_owner[d];
+    const long long qd = list_q[d];
+    const int st = list_st[d];
+    const int t0 = (st & 255) - 2;
+    int dvisited = (st >> 8) & 255;
+    const int A = q_grid[qd];
+    T o[3] = {0, 0, 0};
+    if (sizeof(T) == 8) transform_node<T>(grids[A], sp + 12 * A, q_node[qd], o);  // (FP32: the exact position)
+    const Query Q =
+        make_query<T>(grids, ngrids, sp, flags, A, q_node[qd], (double)o[0], (double)o[1], (double)o[2], true);
+    int g_grid = -1, g_cell = -1, g_status = OV_Q_ORPHAN;
+    T gs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    bool dlimit = false;
+    int walk_iters = 0;  // (the same in every thread: counted once, by the owner)
+    for (int t = t0; t < ngrids; ++t) {
+      const int B = candidate_at(t, Q.A, Q.first);
+      if (B < 0) continue;
+      const GridDev& G = grids[B];
+      double xi[3];
+      if (t == t0) body_frame(sp + 12 * B, Q.x, xi);
+      else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+      const uint8_t* fl = flags + G.node_off;
+      int cell = -1, how = OV_Q_FALLBACK;
+      T s[3];
+      bool walked = false;
+      if (t != t0) {
+        int seed = gp(G.brep)[bin_of(G, xi)];
+        if (seed < 0) continue;
+        cell = seed;
+        how = OV_Q_FOUND;
+        walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited, &walk_iters) == kFound;
+      }
+      if (!walked) {
+        double s64[3];
+        cell = scan_control_cell_block(G, fl, xi, s64, S, &my_cands, &my_iters);
+        s[0] = (T)s64[0];
+        s[1] = (T)s64[1];
+        s[2] = (T)s64[2];
+        how = OV_Q_FALLBACK;
+      }
+      if (cell >= 0) {
+        g_grid = B;
+        g_cell = cell;
+        g_status = how;
+        gs[0] = s[0];
+        gs[1] = s[1];
+        gs[2] = s[2];
+        break;
+      }
+    }
+    if ((int)threadIdx.x == owner) {
+      res_grid = g_grid;
+      res_cell = g_cell;
+      res_status = g_status;
+      rs[0] = gs[0];
+      rs[1] = gs[1];
+      rs[2] = gs[2];
+      visited = dvisited;
+      limit |= dlimit;
+      my_iters += walk_iters;
+    }
+  }
+}
+
+// A query's result written out (donor, natural coordinates, status, warm-start
+// record) and its four fields interpolated (turned into the receiver's frame
+// when asked).
+template <typename T>
+__device__ __forceinline__ void finish_query(const GridDev* __restrict__ grids, const double* sp, long long q,
+                                             long long cap, long long key, int my_grid, int res_grid, int res_cell,
+                                             int res_status, int visited, const T rs[3],
+                                             int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                                             T* __restrict__ s_out, int32_t* __restrict__ status, const Warm& warm,
+                                             uint8_t now, const T* __restrict__ fields, long long total_nodes,
+                                             int interleaved, int frame_velocity, T* __restrict__ out) {
+  write_result<T>(q, cap, key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid, donor_cell,
+                  s_out, status, warm, now);
+  if (fields && res_grid >= 0) {
+    T v[4];
+    interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, interleaved != 0, v);
+    if (frame_velocity) frame_rotate<T>(sp + 12 * my_grid, sp + 12 * res_grid, v);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) out[(long long)f * cap + q] = v[f];
+  }
+}
+
+// The wavefront's work counters, summed across its lanes with shuffles (an
+// atomic on a value that differs per lane compiles to a serial loop over the
+// lanes), then one device atomic per counter from its first lane.
+__device__ __forceinline__ void add_work_counters(unsigned long long* stats, unsigned int cells, unsigned int iters,
+                                                  unsigned int cands) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cells += __shfl_xor(cells, o, 64);
+    iters += __shfl_xor(iters, o, 64);
+    cands += __shfl_xor(cands, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* slot = stat_slot(stats);
+    if (cells) atomicAdd(&slot[OV_STAT_SEARCH_CELLS], (unsigned long long)cells);
+    if (iters) atomicAdd(&slot[OV_STAT_NEWTON_ITERS], (unsigned long long)iters);
+    if (cands) atomicAdd(&slot[OV_STAT_SCAN_CANDIDATES], (unsigned long long)cands);
+  }
+}
+
+// Occupancy asked of the back kernels: with the cold paths in a second
+// kernel, the FP32 walk fits three wavefronts per SIMD (168 VGPRs).
+template <typename T, bool SPLIT>
+struct BackWaves {
+  static constexpr int value = (SPLIT && sizeof(T) == 4) ? 3 : 1;
+};
+
 // The whole back half of a step in one kernel (the step executors' form of
 // the transform, the three search passes and the interpolation). Each block
-// takes BS (64, 128 or 256) queries at a time, one per thread: the transform; the walk over
-// the candidate grids, with the FP64 correction of an undecided FP32 walk
-// done at once by its lane; then the block's deferred queries one at a time
-// with all its threads, as in the scan pass; then each thread writes its
-// result and interpolates its fields. Every rule that orders candidates,
-// seeds and deferrals is the one of the separate passes, so the results are
-// the same bit for bit.
-template <typename T, int BS>
-__global__ void __launch_bounds__(BS)
+// takes BS (64, 128 or 256) queries at a time, one per thread: the transform;
+// the walk over the candidate grids, with the FP64 correction of an
+// undecided FP32 walk done at once by its lane; then the block's deferred
+// queries one at a time with all its threads, as in the scan pass; then each
+// thread writes its result and interpolates its fields. Every rule that
+// orders candidates, seeds and deferrals is the one of the separate passes,
+// so the results are the same bit for bit.
+// SPLIT: the first of two kernels. A query FP32 cannot decide, or whose walk
+// fails, goes to the deferral queue (its state in its outputs) for
+// k_back_defer instead of being corrected or scanned here: this kernel then
+// holds only the walk's registers.
+template <typename T, int BS, bool SPLIT>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWaves<T, SPLIT>::value)))
     k_back(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid, const int32_t* __restrict__ q_node,
            T* __restrict__ qx, const long long* __restrict__ d_count, long long cap,
@@ -811,9 +995,10 @@ __global__ void __launch_bounds__(BS)
            const T* __restrict__ fields,
            long long total_nodes, int interleaved, int frame_velocity, T* __restrict__ out,
            long long* __restrict__ count_out, unsigned long long* __restrict__ stats,
-           const unsigned int* __restrict__ tile_hole) {
+           const unsigned int* __restrict__ tile_hole, DeferQueue dq) {
   __shared__ double sp[kMaxGrids * 12];
-  __shared__ int list_q[BS], list_st[BS];
+  __shared__ int list_owner[SPLIT ? 1 : BS], list_st[SPLIT ? 1 : BS];
+  __shared__ long long list_q[SPLIT ? 1 : BS];
   __shared__ int nlist;
   __shared__ ScanLds S;
   // the grid table, staged in LDS (dynamic: ngrids records): its fields are
@@ -839,11 +1024,15 @@ __global__ void __launch_bounds__(BS)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (count_out) *count_out = *d_count;
     atomicAdd(&stat_slot(stats)[OV_STAT_BACK_CALLS], 1ULL);
+    if (SPLIT) dq.count[(stamp & 1u) ^ 1u] = 0u;  // the other step's counter (its reader is done)
   }
+  unsigned int* const dq_count = dq.count + (stamp & 1u);
   int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
-    if (threadIdx.x == 0) nlist = 0;
+    if (!SPLIT) {
+      if (threadIdx.x == 0) nlist = 0;
+    }
     __syncthreads();  // (also orders the pose staging before the first use)
     const long long q = base + threadIdx.x;
     const bool mine = q < n;
@@ -853,6 +1042,8 @@ __global__ void __launch_bounds__(BS)
     bool limit = false;
     long long key = 0;
     int my_grid = 0;
+    int defer = 0;  // SPLIT: kDeferFix or kDeferScan
+    int defer_t = 0, defer_cell = -1;
     if (mine) {
       const bool first = base == (long long)blockIdx.x * blockDim.x;
       const int A = first ? first_A : q_grid[q];
@@ -868,7 +1059,6 @@ __global__ void __launch_bounds__(BS)
       qx[2 * cap + q] = o[2];
       const Query Q = make_query<T>(grids, ngrids, sp, flags, A, qm, (double)o[0], (double)o[1], (double)o[2], false);
       key = Q.key;
-      int defer = 0, defer_t = 0;
       if (!Q.finite) {
         atomicOr(dev_status, OV_DEV_NONFINITE);
       } else {
@@ -900,6 +1090,12 @@ __global__ void __launch_bounds__(BS)
           }
           int how = OV_Q_FOUND;
           if (sizeof(T) == 4 && r == kDoubt) {
+            if (SPLIT) {
+              defer = kDeferFix;
+              defer_t = t;
+              defer_cell = cell;
+              break;
+            }
             // the FP64 correction: the walk goes on from this cell in FP64
             // on the exact position
             const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
@@ -919,116 +1115,145 @@ __global__ void __launch_bounds__(BS)
             rs[1] = s[1];
             rs[2] = s[2];
           } else {
-            defer = 1;
+            defer = kDeferScan;
             defer_t = t;
+            defer_cell = cell;
           }
           break;
         }
       }
-      if (defer) {
+      if (!SPLIT && defer) {
         const int slot = atomicAdd(&nlist, 1);
-        list_q[slot] = (int)threadIdx.x;
+        list_owner[slot] = (int)threadIdx.x;
+        list_q[slot] = q;
         list_st[slot] = defer_status(defer_t, visited);
       }
     }
-    __syncthreads();
-    const int nd = nlist;
-    for (int d = 0; d < nd; ++d) {
-      // every thread takes the deferred query (same values in all lanes)
-      const int owner = list_q[d];
-      const long long qd = base + owner;
-      const int st = list_st[d];
-      const int t0 = (st & 255) - 2;
-      int dvisited = (st >> 8) & 255;
-      const int A = q_grid[qd];
-      T o[3] = {0, 0, 0};
-      if (sizeof(T) == 8) transform_node<T>(grids[A], sp + 12 * A, q_node[qd], o);  // (FP32: the exact position)
-      const Query Q =
-          make_query<T>(grids, ngrids, sp, flags, A, q_node[qd], (double)o[0], (double)o[1], (double)o[2], true);
-      int g_grid = -1, g_cell = -1, g_status = OV_Q_ORPHAN;
-      T gs[3] = {(T)NAN, (T)NAN, (T)NAN};
-      bool dlimit = false;
-      int walk_iters = 0;  // (the same in every thread: counted once, by the owner)
-      for (int t = t0; t < ngrids; ++t) {
-        const int B = candidate_at(t, Q.A, Q.first);
-        if (B < 0) continue;
-        const GridDev& G = grids[B];
-        double xi[3];
-        if (t == t0) body_frame(sp + 12 * B, Q.x, xi);
-        else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
-        const uint8_t* fl = flags + G.node_off;
-        int cell = -1, how = OV_Q_FALLBACK;
-        T s[3];
-        bool walked = false;
-        if (t != t0) {
-          int seed = gp(G.brep)[bin_of(G, xi)];
-          if (seed < 0) continue;
-          cell = seed;
-          how = OV_Q_FOUND;
-          walked =
-              walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited, &walk_iters) == kFound;
-        }
-        if (!walked) {
-          double s64[3];
-          cell = scan_control_cell_block(G, fl, xi, s64, S, &my_cands, &my_iters);
-          s[0] = (T)s64[0];
-          s[1] = (T)s64[1];
-          s[2] = (T)s64[2];
-          how = OV_Q_FALLBACK;
-        }
-        if (cell >= 0) {
-          g_grid = B;
-          g_cell = cell;
-          g_status = how;
-          gs[0] = s[0];
-          gs[1] = s[1];
-          gs[2] = s[2];
-          break;
+    if (SPLIT) {
+      // the wavefront's deferred queries go to the queue with one atomic
+      const unsigned long long dm = __ballot(mine && defer != 0);
+      if (dm) {
+        unsigned int base_slot = 0;
+        const int leader = __ffsll((long long)dm) - 1;
+        if ((int)(threadIdx.x & 63) == leader) base_slot = atomicAdd(dq_count, (unsigned int)__popcll(dm));
+        base_slot = __shfl(base_slot, leader, 64);
+        if (mine && defer) {
+          const unsigned int rank = __popcll(dm & ((1ull << (threadIdx.x & 63)) - 1ull));
+          if ((long long)(base_slot + rank) < cap) dq.items[base_slot + rank] = (int32_t)q;
+          donor_grid[q] = defer;
+          donor_cell[q] = defer_cell;
+          status[q] = defer_status(defer_t, visited);
         }
       }
-      if ((int)threadIdx.x == owner) {
-        res_grid = g_grid;
-        res_cell = g_cell;
-        res_status = g_status;
-        rs[0] = gs[0];
-        rs[1] = gs[1];
-        rs[2] = gs[2];
-        visited = dvisited;
-        limit |= dlimit;
-        my_iters += walk_iters;
-      }
+    } else {
+      __syncthreads();
+      block_deferred_scans<T>(grids, ngrids, sp, flags, q_grid, q_node, nlist, list_owner, list_q, list_st, S,
+                              max_walk, res_grid, res_cell, res_status, rs, visited, limit, my_iters, my_cands);
     }
     if (mine) {
       my_cells += visited;
       if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-      write_result<T>(q, cap, key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
-                      donor_cell, s_out, status, warm, now);
-      if (fields && res_grid >= 0) {
-        T v[4];
-        interp_point<T>(grids[res_grid], res_cell, rs[0], rs[1], rs[2], fields, total_nodes, interleaved != 0, v);
-        if (frame_velocity) frame_rotate<T>(sp + 12 * my_grid, sp + 12 * res_grid, v);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) out[(long long)f * cap + q] = v[f];
+      if (!(SPLIT && defer))
+        finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
+                        donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
+    }
+    if (!SPLIT) __syncthreads();  // nlist and the list are rebuilt for the next range
+  }
+  add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
+}
+
+// The second kernel of the two-kernel back half: the queued queries of this
+// step (stamp parity), BS per block at a time, one per thread: the FP64
+// correction of an undecided FP32 walk (the walk goes on in FP64 from its
+// cell, on the exact position); then the block's queries still without a
+// donor one at a time with all its threads (the cooperative scans); then
+// each thread writes its result and interpolates. The work counters add the
+// cells, iterations and candidates of this kernel only.
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS)
+    k_back_defer(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
+                 const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                 const int32_t* __restrict__ q_node, long long cap, int32_t* __restrict__ donor_grid,
+                 int32_t* __restrict__ donor_cell, T* __restrict__ s_out, int32_t* __restrict__ status, Warm warm,
+                 int max_walk, int32_t* __restrict__ dev_status, const T* __restrict__ fields, long long total_nodes,
+                 int interleaved, int frame_velocity, T* __restrict__ out, unsigned long long* __restrict__ stats,
+                 DeferQueue dq) {
+  __shared__ double sp[kMaxGrids * 12];
+  __shared__ int list_owner[BS], list_st[BS];
+  __shared__ long long list_q[BS];
+  __shared__ int nlist;
+  __shared__ ScanLds S;
+  extern __shared__ unsigned long long grid_lds[];
+  const unsigned int stamp = *warm.stamp;
+  const uint8_t now = (uint8_t)stamp;
+  const long long n = min((long long)dq.count[stamp & 1u], cap);
+  // entry i goes to block i mod gridDim.x: the usual few queued queries
+  // (each a chain of FP64 Newton solves, or a block-wide scan) spread over
+  // the blocks instead of queueing in one
+  if ((long long)blockIdx.x >= n) return;  // nothing for this block (same in every thread)
+  for (int i = threadIdx.x; i < ngrids * (int)(sizeof(GridDev) / 8); i += blockDim.x)
+    grid_lds[i] = ((const unsigned long long*)grids_g)[i];
+  const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  int my_iters = 0, my_cands = 0;
+  unsigned int my_cells = 0;
+  for (long long base = 0; base + blockIdx.x < n; base += (long long)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    const long long idx = base + (long long)threadIdx.x * gridDim.x + blockIdx.x;
+    const bool mine = idx < n;
+    long long q = 0, key = 0;
+    int my_grid = 0, visited = 0, visited0 = 0;
+    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    bool limit = false;
+    if (mine) {
+      q = dq.items[idx];
+      const int marker = donor_grid[q];
+      int cell = donor_cell[q];
+      const int st = status[q];
+      const int t0 = (st & 255) - 2;
+      visited = visited0 = (st >> 8) & 255;
+      const int A = q_grid[q];
+      my_grid = A;
+      const Query QE = make_query<T>(grids, ngrids, sp, flags, A, q_node[q], 0.0, 0.0, 0.0, true);
+      key = QE.key;
+      bool scan = true;
+      if (sizeof(T) == 4 && marker == kDeferFix) {
+        const int B = candidate_at(t0, A, QE.first);
+        const GridDev& G = grids[B];
+        double xe[3], s64[3];
+        body_frame(sp + 12 * B, QE.x, xe);
+        const int r = walk<double>(G, flags + G.node_off, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters);
+        if (r == kFound) {
+          res_grid = B;
+          res_cell = cell;
+          res_status = OV_Q_FOUND | OV_Q_FP64_FIXED;
+          rs[0] = (T)s64[0];
+          rs[1] = (T)s64[1];
+          rs[2] = (T)s64[2];
+          scan = false;
+        }
       }
+      if (scan) {
+        const int slot = atomicAdd(&nlist, 1);
+        list_owner[slot] = (int)threadIdx.x;
+        list_q[slot] = q;
+        list_st[slot] = defer_status(t0, visited);
+      }
+    }
+    __syncthreads();
+    block_deferred_scans<T>(grids, ngrids, sp, flags, q_grid, q_node, nlist, list_owner, list_q, list_st, S, max_walk,
+                            res_grid, res_cell, res_status, rs, visited, limit, my_iters, my_cands);
+    if (mine) {
+      my_cells += (unsigned int)max(0, visited - visited0);
+      if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+      finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
+                      donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
     }
     __syncthreads();  // nlist and the list are rebuilt for the next range
   }
-  // the wavefront's work, summed across its lanes with shuffles (an atomic
-  // on a value that differs per lane compiles to a serial loop over the
-  // lanes), then one device atomic per counter from its first lane
-  unsigned int w0 = (unsigned int)my_cells, w1 = (unsigned int)my_iters, w2 = (unsigned int)my_cands;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    w0 += __shfl_xor(w0, o, 64);
-    w1 += __shfl_xor(w1, o, 64);
-    w2 += __shfl_xor(w2, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    unsigned long long* slot = stat_slot(stats);
-    if (w0) atomicAdd(&slot[OV_STAT_SEARCH_CELLS], (unsigned long long)w0);
-    if (w1) atomicAdd(&slot[OV_STAT_NEWTON_ITERS], (unsigned long long)w1);
-    if (w2) atomicAdd(&slot[OV_STAT_SCAN_CANDIDATES], (unsigned long long)w2);
-  }
+  add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
 }
 
 static Warm warm_of(ov_ctx* ctx, int slot) {
@@ -1064,21 +1289,44 @@ template <typename T>
 static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                           const int32_t* q_node, T* qx, const long long* d_count, long long capacity,
                           int32_t* donor_grid, int32_t* donor_cell, T* s, int32_t* status, const T* fields,
-                          T* out, long long* count_out, hipStream_t st, int slot) {
+                          T* out, long long* count_out, hipStream_t st, int slot, const DeferQueue* dq) {
   const Warm warm = warm_of(ctx, slot);
   const int bs = ctx->back_block;
   const long long grid =
       std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + bs - 1) / bs));
+  const bool split = dq != nullptr;
+  const DeferQueue q = split ? *dq : DeferQueue{nullptr, nullptr};
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
       ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, count_out, ctx->d_stats,                  \
-      ctx->d_tile_hole + slot * std::max(1LL, ctx->total_tiles)
+      ctx->d_tile_hole + slot * std::max(1LL, ctx->total_tiles), q
+#define OV_DEFER_ARGS                                                                                            \
+  ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, capacity, donor_grid, donor_cell, s, status, \
+      warm, ctx->max_walk, ctx->d_status, fields, ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, \
+      ctx->d_stats, q
   const size_t lds = sizeof(GridDev) * ctx->grids.size();
-  if (bs == 64) hipLaunchKernelGGL((k_back<T, 64>), dim3((unsigned)grid), dim3(64), lds, st, OV_BACK_ARGS);
-  else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128>), dim3((unsigned)grid), dim3(128), lds, st, OV_BACK_ARGS);
-  else hipLaunchKernelGGL((k_back<T, 256>), dim3((unsigned)grid), dim3(256), lds, st, OV_BACK_ARGS);
+  const dim3 g((unsigned)grid);
+  if (!split) {
+    if (bs == 64) hipLaunchKernelGGL((k_back<T, 64, false>), g, dim3(64), lds, st, OV_BACK_ARGS);
+    else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128, false>), g, dim3(128), lds, st, OV_BACK_ARGS);
+    else hipLaunchKernelGGL((k_back<T, 256, false>), g, dim3(256), lds, st, OV_BACK_ARGS);
+  } else {
+    // the second kernel: usually a few queries; as many blocks as CUs
+    const dim3 gd((unsigned)std::max(1LL, std::min((long long)ctx->num_cus, (capacity + bs - 1) / bs)));
+    if (bs == 64) {
+      hipLaunchKernelGGL((k_back<T, 64, true>), g, dim3(64), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_defer<T, 64>), gd, dim3(64), lds, st, OV_DEFER_ARGS);
+    } else if (bs == 128) {
+      hipLaunchKernelGGL((k_back<T, 128, true>), g, dim3(128), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_defer<T, 128>), gd, dim3(128), lds, st, OV_DEFER_ARGS);
+    } else {
+      hipLaunchKernelGGL((k_back<T, 256, true>), g, dim3(256), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_defer<T, 256>), gd, dim3(256), lds, st, OV_DEFER_ARGS);
+    }
+  }
 #undef OV_BACK_ARGS
+#undef OV_DEFER_ARGS
 }
 
 hipError_t launch_donor_search(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
@@ -1104,15 +1352,18 @@ hipError_t launch_copy_count(long long* dst, const int64_t* src, hipStream_t st)
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
-                       void* out, long long* count_out, hipStream_t st, int slot) {
+                       void* out, long long* count_out, hipStream_t st, int slot, int32_t* defer_items,
+                       unsigned int* defer_count) {
   if (capacity > 0 && ctx->back_fused) {
+    DeferQueue dq{defer_items, defer_count};
+    const DeferQueue* q = (ctx->back_fused == 2 && defer_items && defer_count) ? &dq : nullptr;
     if (ctx->precision == OV_MIXED)
       launch_back_t<float>(ctx, poses, flags, q_grid, q_node, (float*)qx, d_count, capacity, donor_grid, donor_cell,
-                           (float*)s, status, (const float*)fields, (float*)out, count_out, st, slot);
+                           (float*)s, status, (const float*)fields, (float*)out, count_out, st, slot, q);
     else
       launch_back_t<double>(ctx, poses, flags, q_grid, q_node, (double*)qx, d_count, capacity, donor_grid,
                             donor_cell, (double*)s, status, (const double*)fields, (double*)out, count_out, st,
-                            slot);
+                            slot, q);
     return hipGetLastError();
   }
   hipError_t e = hipSuccess;

@@ -438,7 +438,10 @@ constexpr unsigned int kStampHigh = 0x80000000u;
 __device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigned int* d_stamp, int32_t* near_count,
                                                   int32_t* chunk_list_count, unsigned int high = 0u) {
   unsigned int v = (*counter + 1u) & ~kStampHigh;
-  v = v == 0u ? 1u : v;  // 0 marks "never listed"
+  // 0 marks "never listed"; the wrap goes on to 2, so that the parity of
+  // consecutive stamps alternates (the two-kernel back half picks its queue
+  // counter by it)
+  v = v == 0u ? 2u : v;
   *counter = v;
   *d_stamp = v | high;
   *near_count = 0;

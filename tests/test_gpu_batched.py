@@ -115,3 +115,12 @@ def test_shells_full_size_tuned_parameters():
     opts["field_layout"] = 1
     stats = _run_pipeline(w, [0, 3, 250], "mixed", stages=p["stages"], options=opts)
     assert all(s["orphans"] == 0 for s in stats)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_shells_full_size_split_back_half(precision):
+    """The full-size shells workload with the two-kernel back half."""
+    w = W.c4(steps=500)
+    stats = _run_pipeline(w, [0, 2, 499], precision, options={"field_layout": 1, "back_fused": 2})
+    assert all(s["orphans"] == 0 for s in stats)

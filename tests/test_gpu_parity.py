@@ -220,7 +220,8 @@ def test_bad_arguments_rejected_before_launch():
     (True, 1, False, True, "fp64"), (True, 1, False, True, "mixed"), (True, 1, True, True, "fp64"),
     (True, 2, False, True, "fp64"), (True, 2, False, False, "fp64"), (False, 2, False, True, "fp64"),
     (True, 3, False, True, "mixed"), (True, 3, False, False, "mixed"), (True, 2, True, True, "mixed"),
-    (True, 3, True, True, "fp64")])
+    (True, 3, True, True, "fp64"), (True, 1, False, 2, "fp64"), (True, 3, False, 2, "mixed"),
+    (True, 3, False, 2, "fp64"), (True, 2, True, 2, "mixed"), (True, 1, False, 2, "mixed")])
 def test_pipeline_matches_sequential(native, stages, graphs, fused, precision):
     """Steps run by the executors (one stream; two streams: front half of
     step t+1 beside the back half of step t; three streams: hole cut of t+1,
@@ -231,18 +232,41 @@ def test_pipeline_matches_sequential(native, stages, graphs, fused, precision):
     _check_pipeline(native, stages, graphs, precision, {"back_fused": int(fused)})
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_back_half_with_every_query_deferred(precision):
+    """The two-kernel back half with the walk limited to one cell and no warm
+    start: most queries go through the deferral queue to the cooperative
+    scans of the second kernel; the executor's steps equal the five calls'
+    bitwise and match the oracle."""
+    _check_pipeline(True, 3, False, precision, {"back_fused": 2, "max_walk": 1, "warm": 0},
+                    seq_options={"max_walk": 1, "warm": 0})
+    w = W.c1_small(steps=3)
+    o = oracle.Oracle(w.grids, w.nf)
+    from paper_1910_09315_amd.assembly import Pipeline
+    a = _assembly(w, precision, options={"back_fused": 2, "max_walk": 1, "warm": 0})
+    pipe = Pipeline(a, a.capacity, native=True, stages=1)
+    tol = dict(value_rtol=1e-12) if precision == "fp64" else dict(value_rtol=1e-5, s_tol=1e-4, qx_tol=1e-6)
+    for t in range(3):
+        pipe.submit(t, torch.as_tensor(w.poses[t].reshape(-1)).cuda())
+        st = compare(o, w.poses[t], o.step(w.poses[t], w.fields), pipe.results(t), **tol)
+        print("split, max_walk 1", precision, st, flush=True)
+    pipe.close()
+
+
 @pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
-                                     {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1}])
+                                     {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1},
+                                     {"back_fused": 2, "back_block": 64, "back_blocks": 4},
+                                     {"back_fused": 2, "back_block": 256, "back_blocks": 8}])
 def test_tuned_variants_match_sequential(options):
     """Every value the autotuner may pick leaves the results unchanged."""
     _check_pipeline(True, 1, False, "fp64", options)
     _check_pipeline(True, 3, False, "mixed", options)
 
 
-def _check_pipeline(native, stages, graphs, precision, options):
+def _check_pipeline(native, stages, graphs, precision, options, seq_options=None):
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
-    a = _assembly(w, precision)
+    a = _assembly(w, precision, options=seq_options)
     b = _assembly(w, precision, capacity=a.capacity, options=options)
     pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
