@@ -675,6 +675,8 @@ def make_parser():
                          "place in the pipeline (0: no timing in the timed region)")
     ap.add_argument("--compare", default="C4",
                     help="also time this workload in mixed precision (the batched form) and in FP64 ('' to skip)")
+    ap.add_argument("--no-graph-form", dest="graph_form", action="store_false",
+                    help="skip timing the main workload with the executor replaying per-stream HIP graphs")
     ap.add_argument("--compare-precisions", default="mixed,fp64",
                     help="precisions of the compared workload, comma-separated")
     ap.add_argument("--roofline", choices=("back", "holecut", "none"), default="back",
@@ -722,8 +724,21 @@ def main():
         log("[bench] comparing the last timed step with the oracle")
         out["vs_oracle"] = oracle_check(w, last_result)
         log(f"[bench] vs oracle: {out['vs_oracle']}")
+    import copy
+    if args.graph_form and not (args.graph or args.sequential or args.eager or args.graphs or args.native_graphs):
+        # the same executor with each stream's stages replayed from HIP graphs
+        # captured once per buffer set: host cost per step against direct launches
+        a3 = copy.copy(args)
+        a3.native_graphs, a3.step_report, a3.next_rows, a3.roofline = True, False, False, "none"
+        a3.steps = out["steps"]
+        o3, _ = measure(a3, w)
+        o3.pop("_last_result", None)
+        out.setdefault("forms", {})["native_graphs"] = {
+            "workload": o3["config"]["workload"], "value": o3["value"], "ms_per_step": o3["ms_per_step"],
+            "over_direct_launches": round(o3["value"] / out["value"], 3),
+            "note": "the native executor replaying one HIP graph per stream and step (captured per buffer set; "
+                    "each step then starts from a full flag fill, as captured launches cannot alternate near lists)"}
     if args.compare and args.compare != args.config:
-        import copy
         forms = {"note": "the same metric, the value above being the plain FP64 form on its workload; "
                          "`same_workload` times the compared workload in each precision in this run"}
         w2, res = None, {}
@@ -756,7 +771,7 @@ def main():
         if "mixed" in res and "fp64" in res:
             forms["same_workload"]["workload"] = args.compare
             forms["same_workload"]["mixed_over_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
-        out["forms"] = forms
+        out.setdefault("forms", {}).update(forms)
         del w2
         _WORKLOADS.pop(args.compare, None)
     if not args.no_cpu_baseline:

@@ -121,9 +121,12 @@ enum ov_option {
     OV_OPT_FIELD_LAYOUT = 13,/* layout of the fields given to overset_interp and the executors: 0 (default)
                                four blocks of total_nodes values (u block, v, w, p); 1 interleaved per node
                                (u, v, w, p of node 0, then node 1, ...): one load per donor corner */
-    OV_OPT_FRAME_VELOCITY = 14 /* step executors: 1 gives the interpolated u, v, w in the receiver's frame
+    OV_OPT_FRAME_VELOCITY = 14,/* step executors: 1 gives the interpolated u, v, w in the receiver's frame
                                (as overset_frame_velocity does after overset_interp); 0 (default) leaves them
                                in the donor's frame */
+    OV_OPT_BACK_QUEUE = 15  /* step executors: 1 lets the back half's workgroups take their chunks of queries
+                               from an atomic work queue (each its own first chunk, then the next free one)
+                               instead of a fixed stride; 0 (default) the fixed stride. Same results. */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.

@@ -12,8 +12,12 @@ The tuned parameters and what they choose:
   back_blocks   its workgroups per CU;
   max_walk      stencil-walk steps before a query goes to the workgroup's
                 cooperative brute-force scan (a long walk is one lane's serial
-                chain, which the whole kernel waits for).
-The first five leave the results unchanged (the parity tests run them);
+                chain, which the whole kernel waits for);
+  back_fused    the back half as one kernel (1) or two (2: the walk, then
+                the FP64 corrections and scans of the queries it left);
+  back_queue    the back half's workgroups take their query chunks from an
+                atomic work queue (1) or by a fixed stride (0).
+All but max_walk leave the results unchanged (the parity tests run them);
 max_walk can change the reported cell only for a point that lies within the
 containment tolerance of a face shared by two valid cells (the walk keeps
 the first it meets, the scan the lowest index), never for a point with a
@@ -42,9 +46,12 @@ SPACE = {
     "back_block": (64, 128, 256),
     "back_blocks": (4, 8, 16),
     "max_walk": (8, 16, 32),
+    "back_fused": (1, 2),
+    "back_queue": (0, 1),
 }
-DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16}
-CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk")
+DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16,
+            "back_fused": 1, "back_queue": 0}
+CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk", "back_fused", "back_queue")
 
 
 def signature(w, precision: str) -> str:

@@ -977,6 +977,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       if (v < 1 || v > 32) break;
       ctx->back_blocks_per_cu = (int)v;
       return OV_OK;
+    case OV_OPT_BACK_QUEUE:
+      if (v != 0 && v != 1) break;
+      ctx->back_queue = (int)v;
+      return OV_OK;
     case OV_OPT_BACK_BLOCK:
       if (v != 64 && v != 128 && v != 256) break;
       ctx->back_block = (int)v;

@@ -179,6 +179,7 @@ struct ov_ctx {
   int back_fused = 1;    // step executors: transform, search and interpolation in one kernel
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   int back_block = 256;        // its threads per block (64, 128 or 256)
+  int back_queue = 0;          // its blocks take query chunks from an atomic head (executors)
   int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
   int frame_velocity = 0;      // executors: interpolated velocities in the receiver's frame
   bool has_mesh = false;       // some grid's blank region is a triangulation
@@ -255,9 +256,11 @@ hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* 
 // step's query count; slot is the step's front-half scratch slot (its stamp
 // dates the warm-start entries).
 // back_fused = 2 with a deferral queue (defer_items: capacity entries,
-// defer_count: two counters, zero before the first step; caller-owned, for
+// defer_count: four counters, zero before the first step; caller-owned, for
 // the back halves of one stream) runs it as two kernels: the walk, and the
-// FP64 corrections and brute-force scans of the queries the walk left.
+// FP64 corrections and brute-force scans of the queries the walk left;
+// back_queue takes the one or first kernel's chunks from a work queue whose
+// heads are defer_count[2, 4).
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,

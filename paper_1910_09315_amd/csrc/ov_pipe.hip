@@ -64,7 +64,8 @@ struct ov_pipe {
   long long uses[3] = {0, 0, 0};
   int gen[3] = {0, 0, 0};
   // deferral queue of the two-kernel back half (OV_OPT_BACK_FUSED = 2):
-  // entries for the largest capacity, two step counters (zeroed here)
+  // entries for the largest capacity, two step counters, then the two heads
+  // of the back half's work queue (OV_OPT_BACK_QUEUE), all zeroed here
   int32_t* defer_items = nullptr;
   unsigned int* defer_count = nullptr;
 };
@@ -165,8 +166,8 @@ static int pipe_create(ov_ctx* ctx, int32_t nf, int nsets, const ov_step_buffers
   long long max_cap = 1;
   for (int k = 0; k < nsets; ++k) max_cap = std::max(max_cap, (long long)sets[k].capacity);
   ok = ok && hipMalloc(&p->defer_items, sizeof(int32_t) * max_cap) == hipSuccess;
-  ok = ok && hipMalloc(&p->defer_count, sizeof(unsigned int) * 2) == hipSuccess;
-  ok = ok && hipMemset(p->defer_count, 0, sizeof(unsigned int) * 2) == hipSuccess;
+  ok = ok && hipMalloc(&p->defer_count, sizeof(unsigned int) * 4) == hipSuccess;
+  ok = ok && hipMemset(p->defer_count, 0, sizeof(unsigned int) * 4) == hipSuccess;
   p->tb.assign(max_timed, nullptr);
   p->te.assign(max_timed, nullptr);
   for (int i = 0; i < max_timed && ok; ++i) {

@@ -837,9 +837,15 @@ __global__ void __launch_bounds__(256)
 // its own and clears the other, which the previous step's second kernel has
 // finished reading (the back halves of consecutive steps run in stream
 // order).
+// `chunk` (optional, [2], the same parity rule): the work queue's heads.
+// With it, a block takes its first BS-query chunk by its index and each
+// further one from an atomic head (the grid's chunks after its own
+// first), asked for at the start of the chunk before, so that blocks that
+// meet cheap queries take more chunks.
 struct DeferQueue {
   int32_t* items;        // [capacity]
   unsigned int* count;   // [2]
+  unsigned int* chunk;   // [2] or null: static chunks (block b takes b, b + grid, ...)
 };
 
 // The cooperative scans of a block's deferred queries, one query at a time
@@ -1025,14 +1031,19 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
     if (count_out) *count_out = *d_count;
     atomicAdd(&stat_slot(stats)[OV_STAT_BACK_CALLS], 1ULL);
     if (SPLIT) dq.count[(stamp & 1u) ^ 1u] = 0u;  // the other step's counter (its reader is done)
+    if (dq.chunk) dq.chunk[(stamp & 1u) ^ 1u] = 0u;
   }
-  unsigned int* const dq_count = dq.count + (stamp & 1u);
+  unsigned int* const dq_count = SPLIT ? dq.count + (stamp & 1u) : nullptr;
+  unsigned int* const chunk_head = dq.chunk ? dq.chunk + (stamp & 1u) : nullptr;
+  __shared__ long long next_base;
   int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += (long long)gridDim.x * blockDim.x) {
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n;) {
     if (!SPLIT) {
       if (threadIdx.x == 0) nlist = 0;
     }
+    unsigned int ticket = 0;  // the block's next chunk (work queue), in flight during this one
+    if (chunk_head && threadIdx.x == 0) ticket = atomicAdd(chunk_head, 1u);
     __syncthreads();  // (also orders the pose staging before the first use)
     const long long q = base + threadIdx.x;
     const bool mine = q < n;
@@ -1157,7 +1168,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
         finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
                         donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
     }
-    if (!SPLIT) __syncthreads();  // nlist and the list are rebuilt for the next range
+    if (chunk_head) {
+      if (threadIdx.x == 0) next_base = ((long long)gridDim.x + ticket) * blockDim.x;
+      __syncthreads();  // (also: nlist and the list are rebuilt for the next range)
+      base = next_base;
+    } else {
+      base += (long long)gridDim.x * blockDim.x;
+      if (!SPLIT) __syncthreads();  // nlist and the list are rebuilt for the next range
+    }
   }
   add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
 }
@@ -1294,8 +1312,8 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
   const int bs = ctx->back_block;
   const long long grid =
       std::max(1LL, std::min((long long)ctx->num_cus * ctx->back_blocks_per_cu, (capacity + bs - 1) / bs));
-  const bool split = dq != nullptr;
-  const DeferQueue q = split ? *dq : DeferQueue{nullptr, nullptr};
+  const bool split = dq != nullptr && dq->items != nullptr;
+  const DeferQueue q = dq ? *dq : DeferQueue{nullptr, nullptr, nullptr};
 #define OV_BACK_ARGS                                                                                             \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
@@ -1355,8 +1373,11 @@ hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, c
                        void* out, long long* count_out, hipStream_t st, int slot, int32_t* defer_items,
                        unsigned int* defer_count) {
   if (capacity > 0 && ctx->back_fused) {
-    DeferQueue dq{defer_items, defer_count};
-    const DeferQueue* q = (ctx->back_fused == 2 && defer_items && defer_count) ? &dq : nullptr;
+    // defer_count: [0, 2) the deferral queue's counters, [2, 4) the work queue's heads
+    const bool split = ctx->back_fused == 2 && defer_items && defer_count;
+    const bool queue = ctx->back_queue && defer_count;
+    DeferQueue dq{split ? defer_items : nullptr, split ? defer_count : nullptr, queue ? defer_count + 2 : nullptr};
+    const DeferQueue* q = (split || queue) ? &dq : nullptr;
     if (ctx->precision == OV_MIXED)
       launch_back_t<float>(ctx, poses, flags, q_grid, q_node, (float*)qx, d_count, capacity, donor_grid, donor_cell,
                            (float*)s, status, (const float*)fields, (float*)out, count_out, st, slot, q);

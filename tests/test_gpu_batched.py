@@ -124,3 +124,11 @@ def test_shells_full_size_split_back_half(precision):
     w = W.c4(steps=500)
     stats = _run_pipeline(w, [0, 2, 499], precision, options={"field_layout": 1, "back_fused": 2})
     assert all(s["orphans"] == 0 for s in stats)
+
+
+@pytest.mark.timeout(300)
+def test_shells_full_size_work_queue():
+    """The full-size shells workload with the back half's work queue."""
+    w = W.c4(steps=500)
+    stats = _run_pipeline(w, [0, 1, 250], "mixed", options={"field_layout": 1, "back_queue": 1, "back_blocks": 2})
+    assert all(s["orphans"] == 0 for s in stats)

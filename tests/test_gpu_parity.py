@@ -256,7 +256,9 @@ def test_split_back_half_with_every_query_deferred(precision):
 @pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
                                      {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1},
                                      {"back_fused": 2, "back_block": 64, "back_blocks": 4},
-                                     {"back_fused": 2, "back_block": 256, "back_blocks": 8}])
+                                     {"back_fused": 2, "back_block": 256, "back_blocks": 8},
+                                     {"back_queue": 1, "back_block": 64, "back_blocks": 2},
+                                     {"back_queue": 1, "back_fused": 2, "back_block": 128, "back_blocks": 4}])
 def test_tuned_variants_match_sequential(options):
     """Every value the autotuner may pick leaves the results unchanged."""
     _check_pipeline(True, 1, False, "fp64", options)
