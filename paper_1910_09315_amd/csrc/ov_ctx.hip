@@ -844,6 +844,25 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   // front-half scratch (stamps start at 0: "never listed")
   const long long nt = std::max(1LL, ctx->total_tiles);
   {
+    // the hole cut visits sub-tile (idx * sub_perm) mod nsub at position idx:
+    // a prime near nsub / golden ratio that does not divide nsub is prime to
+    // it, and keeps neighbouring sub-tiles far apart in the visiting order
+    const long long nsub = nt * kSubPerTile;
+    auto is_prime = [](long long v) {
+      if (v < 2) return false;
+      for (long long d = 2; d * d <= v; ++d)
+        if (v % d == 0) return false;
+      return true;
+    };
+    ctx->sub_perm = 1;
+    if (nsub > 2 && nsub < (1LL << 31))
+      for (long long p = (long long)(0.6180339887 * (double)nsub); p > 1; --p)
+        if (is_prime(p) && nsub % p != 0) {
+          ctx->sub_perm = p;
+          break;
+        }
+  }
+  {
     std::vector<int4> info((size_t)nt, make_int4(0, 0, 0, 0));
     for (size_t gi = 0; gi < ctx->grids.size(); ++gi) {
       const GridDev& g = ctx->grids[gi].d;

@@ -124,6 +124,7 @@ struct ov_ctx {
   std::vector<ov::GridHost> grids;
   std::vector<long long> node_off{0};
   long long total_tiles = 0;
+  long long sub_perm = 1;  // multiplier prime to the sub-tile count: the hole cut's visiting order
   ov::GridDev* d_grids = nullptr;
   int32_t* d_status = nullptr;
   // OV_STAT_* counters (accumulate until ov_stats_fetch), spread over

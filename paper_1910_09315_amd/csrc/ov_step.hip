@@ -922,6 +922,7 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
                                                     const double4* __restrict__ spheres,
                                                     const int4* __restrict__ tile_info, long long nsub,
+                                                    long long perm,
                                                     const unsigned int* __restrict__ d_stamp,
                                                     unsigned int* __restrict__ tile_near,
                                                     int4* __restrict__ near_list,
@@ -941,7 +942,13 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
   for (long long r0 = 0; r0 < nsub; r0 += 256 * nb) {
     if (threadIdx.x == 0) c_n = 0;
     __syncthreads();
-    const long long sub = r0 + (long long)threadIdx.x * nb + blockIdx.x;
+    // position idx of the round visits sub-tile idx * perm mod nsub (perm is
+    // prime to nsub: a bijection), which scatters the sub-tiles of one body's
+    // neighbourhood over the blocks; a plain stride would fold a grid's
+    // planes of sub-tiles onto the same blocks whenever the plane length is a
+    // multiple of the block count
+    const long long idx = r0 + (long long)threadIdx.x * nb + blockIdx.x;
+    const long long sub = idx < nsub ? (idx * perm) % nsub : nsub;
     if (sub < nsub) {
       const unsigned long long m = sub_mask(L, tile_info[sub / kSubPerTile].x, spheres[sub]);
       if (m) {
@@ -1116,8 +1123,8 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
 #define OV_SUB_ARGS                                                                                             \
-  ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, st, ctx->d_tile_near, \
-      nl, nc, th, ctx->d_stats
+  ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, ctx->sub_perm, st,     \
+      ctx->d_tile_near, nl, nc, th, ctx->d_stats
     const bool mixed = ctx->precision == OV_MIXED;
     const dim3 g((unsigned)cb), b(256);
 #define OV_SUB(CT, W)                                                                                  \
