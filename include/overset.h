@@ -124,9 +124,15 @@ enum ov_option {
     OV_OPT_FRAME_VELOCITY = 14,/* step executors: 1 gives the interpolated u, v, w in the receiver's frame
                                (as overset_frame_velocity does after overset_interp); 0 (default) leaves them
                                in the donor's frame */
-    OV_OPT_BACK_QUEUE = 15  /* step executors: 1 lets the back half's workgroups take their chunks of queries
+    OV_OPT_BACK_QUEUE = 15, /* step executors: 1 lets the back half's workgroups take their chunks of queries
                                from an atomic work queue (each its own first chunk, then the next free one)
                                instead of a fixed stride; 0 (default) the fixed stride. Same results. */
+    OV_OPT_BACK_XCD = 16    /* step executors: k in 1..64 puts runs of k consecutive chunks of queries on the
+                               workgroups of one XCD (the runs going to the XCDs in turn) where the back half's
+                               workgroups take their chunks by index (every round of the fixed stride, the
+                               first chunk with the work queue), so that neighbouring queries, whose donor
+                               cells share lines, run under one L2; 0 (default), or a grid that 8 k does not
+                               divide: launch order. Same results. */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.

@@ -209,6 +209,27 @@ class Assembly:
         return r
 
 
+_EXECUTOR_STREAMS = {}
+
+
+def executor_streams(dev, n: int):
+    """The first n of the three streams that every Pipeline on device `dev`
+    runs on, created together at the first call and kept for the process.
+    The runtime multiplexes a process's streams onto a few hardware queues;
+    streams that share one run their work one after another. torch's stream
+    pool hands out a different set at every request, so the pipelines of one
+    process would land on different queue mappings (some with two stages on
+    one queue, which loses their overlap); shared streams give every pipeline
+    the mapping of the first. Pipelines alive at the same time then order
+    their stages among each other as well, which is still correct: every wait
+    of the executor is for work submitted before it."""
+    d = torch.device(dev)
+    key = d.index if d.index is not None else torch.cuda.current_device()
+    if key not in _EXECUTOR_STREAMS:
+        _EXECUTOR_STREAMS[key] = [torch.cuda.Stream(d) for _ in range(3)]
+    return _EXECUTOR_STREAMS[key][:n]
+
+
 class Pipeline:
     """Pipelined execution of consecutive steps of an Assembly.
     stages=1: one stream and one buffer set (native only); stages=2: two
@@ -227,7 +248,7 @@ class Pipeline:
         dev = asm.dev
         self.nsets = stages
         self.bufs = [StepBuffers(dev, asm.total, capacity, asm.dtype) for _ in range(stages)]
-        self.streams = [torch.cuda.Stream(dev) for _ in range(stages)]
+        self.streams = executor_streams(dev, stages)
         self.s_front = self.streams[0]
         self.s_back = self.streams[-1]
         self.native = None

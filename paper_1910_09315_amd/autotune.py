@@ -16,7 +16,10 @@ The tuned parameters and what they choose:
   back_fused    the back half as one kernel (1) or two (2: the walk, then
                 the FP64 corrections and scans of the queries it left);
   back_queue    the back half's workgroups take their query chunks from an
-                atomic work queue (1) or by a fixed stride (0).
+                atomic work queue (1) or by a fixed stride (0);
+  back_xcd      runs of this many consecutive chunks taken by index go to the
+                workgroups of one XCD (neighbouring chunks share its L2; 0:
+                launch order).
 All but max_walk leave the results unchanged (the parity tests run them);
 max_walk can change the reported cell only for a point that lies within the
 containment tolerance of a face shared by two valid cells (the walk keeps
@@ -48,10 +51,12 @@ SPACE = {
     "max_walk": (8, 16, 32),
     "back_fused": (1, 2),
     "back_queue": (0, 1),
+    "back_xcd": (0, 8),
 }
 DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16,
-            "back_fused": 1, "back_queue": 0}
-CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk", "back_fused", "back_queue")
+            "back_fused": 1, "back_queue": 0, "back_xcd": 0}
+CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk", "back_fused", "back_queue",
+               "back_xcd")
 
 
 def signature(w, precision: str) -> str:

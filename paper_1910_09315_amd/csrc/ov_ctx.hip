@@ -1000,6 +1000,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
       if (v != 0 && v != 1) break;
       ctx->back_queue = (int)v;
       return OV_OK;
+    case OV_OPT_BACK_XCD:
+      if (v < 0 || v > 64) break;
+      ctx->back_xcd = (int)v;
+      return OV_OK;
     case OV_OPT_BACK_BLOCK:
       if (v != 64 && v != 128 && v != 256) break;
       ctx->back_block = (int)v;

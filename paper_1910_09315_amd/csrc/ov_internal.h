@@ -181,6 +181,7 @@ struct ov_ctx {
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   int back_block = 256;        // its threads per block (64, 128 or 256)
   int back_queue = 0;          // its blocks take query chunks from an atomic head (executors)
+  int back_xcd = 0;            // runs of this many consecutive chunks go to one XCD (0: launch order)
   int field_layout = 0;        // 0: four blocks u, v, w, p; 1: interleaved per node
   int frame_velocity = 0;      // executors: interpolated velocities in the receiver's frame
   bool has_mesh = false;       // some grid's blank region is a triangulation
@@ -261,7 +262,8 @@ hipError_t launch_interp(ov_ctx* ctx, const int32_t* donor_grid, const int32_t* 
 // the back halves of one stream) runs it as two kernels: the walk, and the
 // FP64 corrections and brute-force scans of the queries the walk left;
 // back_queue takes the one or first kernel's chunks from a work queue whose
-// heads are defer_count[2, 4).
+// heads are defer_count[2, 4); back_xcd puts runs of that many consecutive
+// chunks of the first (or, without the queue, every) round on one XCD.
 hipError_t launch_back(ov_ctx* ctx, const double* poses, const uint8_t* flags, const int32_t* q_grid,
                        const int32_t* q_node, void* qx, const long long* d_count, long long capacity,
                        int32_t* donor_grid, int32_t* donor_cell, void* s, int32_t* status, const void* fields,
@@ -375,6 +377,20 @@ constexpr int kStatStride = 16;  // 128 bytes: one slot per cache line
 // This workgroup's slot of the statistics counters.
 __device__ __forceinline__ unsigned long long* stat_slot(unsigned long long* stats) {
   return stats + (blockIdx.x & (kStatSlots - 1)) * kStatStride;
+}
+
+// The dispatcher hands a launch's workgroups to the chip's XCDs in turn
+// (workgroup b to XCD b mod kXcds), and each XCD has its own L2. xcd_rank
+// renumbers them so that runs of k consecutive ranks fall on one XCD and the
+// runs go to the XCDs in turn: work items taken in rank order then meet their
+// k - 1 neighbours in one L2, and every XCD still gets an even mix of the
+// whole range. A bijection of [0, nb) when kXcds * k divides nb; otherwise
+// (and for k = 0) the launch order is kept.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long long xcd_rank(long long b, long long nb, int k) {
+  if (k <= 0 || nb % ((long long)kXcds * k) != 0) return b;
+  const long long x = b % kXcds, l = b / kXcds;
+  return ((l / k) * kXcds + x) * k + l % k;
 }
 
 typedef float ov_fv4 __attribute__((ext_vector_type(4)));

@@ -1001,7 +1001,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
            const T* __restrict__ fields,
            long long total_nodes, int interleaved, int frame_velocity, T* __restrict__ out,
            long long* __restrict__ count_out, unsigned long long* __restrict__ stats,
-           const unsigned int* __restrict__ tile_hole, DeferQueue dq) {
+           const unsigned int* __restrict__ tile_hole, DeferQueue dq, int xcd_run) {
   __shared__ double sp[kMaxGrids * 12];
   __shared__ int list_owner[SPLIT ? 1 : BS], list_st[SPLIT ? 1 : BS];
   __shared__ long long list_q[SPLIT ? 1 : BS];
@@ -1018,7 +1018,11 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
   // this thread's first query, read before the count is known (entries up
   // to the capacity are allocated): one memory round trip less on every
   // query's path
-  const long long q_first = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // the block's position in each round of chunks: with xcd_run > 0 the
+  // blocks of one XCD take runs of consecutive chunks, whose queries are
+  // neighbours on the grids and share donor-cell lines in that XCD's L2
+  const long long brank = xcd_rank(blockIdx.x, gridDim.x, xcd_run);
+  const long long q_first = brank * blockDim.x + threadIdx.x;
   int first_A = 0, first_m = 0;
   if (q_first < cap) {
     first_A = q_grid[q_first];
@@ -1038,7 +1042,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
   __shared__ long long next_base;
   int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < n;) {
+  for (long long base = brank * blockDim.x; base < n;) {
     if (!SPLIT) {
       if (threadIdx.x == 0) nlist = 0;
     }
@@ -1056,7 +1060,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
     int defer = 0;  // SPLIT: kDeferFix or kDeferScan
     int defer_t = 0, defer_cell = -1;
     if (mine) {
-      const bool first = base == (long long)blockIdx.x * blockDim.x;
+      const bool first = base == brank * blockDim.x;
       const int A = first ? first_A : q_grid[q];
       const int qm = first ? first_m : q_node[q];
       my_grid = A;
@@ -1318,7 +1322,7 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, qx, d_count, capacity, donor_grid, donor_cell, \
       s, status, warm, ctx->max_walk, ctx->d_status, fields,                                                       \
       ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, count_out, ctx->d_stats,                  \
-      ctx->d_tile_hole + slot * std::max(1LL, ctx->total_tiles), q
+      ctx->d_tile_hole + slot * std::max(1LL, ctx->total_tiles), q, ctx->back_xcd
 #define OV_DEFER_ARGS                                                                                            \
   ctx->d_grids, (int)ctx->grids.size(), poses, flags, q_grid, q_node, capacity, donor_grid, donor_cell, s, status, \
       warm, ctx->max_walk, ctx->d_status, fields, ctx->node_off.back(), ctx->field_layout, ctx->frame_velocity, out, \

@@ -258,7 +258,10 @@ def test_split_back_half_with_every_query_deferred(precision):
                                      {"back_fused": 2, "back_block": 64, "back_blocks": 4},
                                      {"back_fused": 2, "back_block": 256, "back_blocks": 8},
                                      {"back_queue": 1, "back_block": 64, "back_blocks": 2},
-                                     {"back_queue": 1, "back_fused": 2, "back_block": 128, "back_blocks": 4}])
+                                     {"back_queue": 1, "back_fused": 2, "back_block": 128, "back_blocks": 4},
+                                     {"back_xcd": 2, "back_block": 128, "back_blocks": 4},
+                                     {"back_xcd": 4, "back_queue": 1, "back_block": 64, "back_blocks": 2},
+                                     {"back_xcd": 64, "back_block": 64, "back_blocks": 2}])
 def test_tuned_variants_match_sequential(options):
     """Every value the autotuner may pick leaves the results unchanged."""
     _check_pipeline(True, 1, False, "fp64", options)
