@@ -9,6 +9,8 @@
 // packets Sec. 2.2.3 item 6; interpolation Sec. 2.2.6.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "ov_internal.h"
 
 namespace ov {
@@ -488,6 +490,68 @@ __device__ __forceinline__ void mark_near(int e, int g, int ti, int tj, int tk, 
   if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = make_int4(g, x, y, z);
 }
 
+// The tiles along one axis that hold a position within kMaxNf of the range
+// [lo, hi] (which lies inside one tile), as a run of `count` consecutive
+// tiles from `first` (modulo the tile count on a periodic axis). Where the
+// padded range could come round to its first tile again (an axis hardly
+// longer than it), every tile of the axis.
+__device__ __forceinline__ void reach_run(int lo, int hi, int n, int size, bool per, int& first, int& count) {
+  const int nt = (n + size - 1) / size;
+  if (per) {
+    if (hi - lo + 1 + 2 * kMaxNf + size > n) {
+      first = 0;
+      count = nt;
+      return;
+    }
+    const int a = lo - kMaxNf < 0 ? lo - kMaxNf + n : lo - kMaxNf;
+    const int b = hi + kMaxNf >= n ? hi + kMaxNf - n : hi + kMaxNf;
+    first = a / size;
+    count = (b / size - first + nt) % nt + 1;
+  } else {
+    first = max(lo - kMaxNf, 0) / size;
+    count = min(hi + kMaxNf, n - 1) / size - first + 1;
+  }
+}
+
+// The holes of a sub-tile as a box of node indices (lo/hi per axis; lo >
+// hi when there are none), and the near-list entries it gives: every tile
+// holding a node within kMaxNf of the box, which holds every buffer node
+// the sub-tile's holes can make.
+struct HoleBox {
+  int lo[3], hi[3];
+};
+
+__device__ __forceinline__ void hole_box_wave(HoleBox& b) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = min(b.lo[d], __shfl_xor(b.lo[d], o, 64));
+      b.hi[d] = max(b.hi[d], __shfl_xor(b.hi[d], o, 64));
+    }
+}
+
+// Lanes `lane` of `width` put entry e = lane, lane + width, ... of the box's
+// runs along i, j and k on the near list (once per stamp).
+__device__ __forceinline__ void mark_near_box(const HoleBox& b, int lane, int width, int g, int ni, int nj, int nk,
+                                              int per, int tiles_i, int tiles_j, long long tile_off,
+                                              unsigned int stamp, unsigned int* __restrict__ tile_near,
+                                              int4* __restrict__ near_list, int32_t* __restrict__ near_count) {
+  int fi, ci, fj, cj, fk, ck;
+  reach_run(b.lo[0], b.hi[0], ni, kTileI, per & 1, fi, ci);
+  reach_run(b.lo[1], b.hi[1], nj, kTileJ, per & 2, fj, cj);
+  reach_run(b.lo[2], b.hi[2], nk, kTileK, per & 4, fk, ck);
+  const int tiles_k = (nk + kTileK - 1) / kTileK;
+  for (int e = lane; e < ci * cj * ck; e += width) {
+    int x = fi + e % ci, y = fj + (e / ci) % cj, z = fk + e / (ci * cj);
+    x = x >= tiles_i ? x - tiles_i : x;
+    y = y >= tiles_j ? y - tiles_j : y;
+    z = z >= tiles_k ? z - tiles_k : z;
+    const long long n = tile_off + x + (long long)tiles_i * (y + (long long)tiles_j * z);
+    if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = make_int4(g, x, y, z);
+  }
+}
+
 // Which blank regions may reach sub-tile `sub` (bit B set: grid B's region
 // may contain a node of it). The sub-tile's bounding sphere, placed at its
 // grid's pose, is tested against the sphere about grid B's origin that
@@ -709,6 +773,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   const bool outer = L.outer[A] != 0;
   const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
   bool hole = false;
+  unsigned int hm = 0u;  // bit r: node i + r is a hole
   if constexpr (!MESH) {
     if (ok) {
       const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
@@ -733,6 +798,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
         if (cause >= 0) {
           f = kHole | (cause << 2);
           hole = true;
+          hm |= 1u << r;
         } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
           f = kFringe | (OV_CAUSE_BOUNDARY << 2);
         }
@@ -802,6 +868,7 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
         if (cause >= 0) {
           f = kHole | (cause << 2);
           hole = true;
+          hm |= 1u << r;
         } else if (outer && (row_outer || i + r < o0 || i + r >= ni - o1)) {
           f = kFringe | (OV_CAUSE_BOUNDARY << 2);
         }
@@ -817,12 +884,35 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
   int nr = n;
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
   if ((t & 63) == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
-  if (__syncthreads_or(hole)) {
-    if (t < 125)
-      mark_near(t, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-                near_list, near_count);
-    else if (t == 128)
-      tile_hole[sub / kSubPerTile] = stamp;  // this step has a hole in the tile
+  // the box of the sub-tile's holes: per wavefront, then over the block
+  __shared__ int wbox[4][6];
+  HoleBox hb;
+  hb.lo[0] = hm ? i + __builtin_ctz(hm) : INT_MAX;
+  hb.hi[0] = hm ? i + 31 - __builtin_clz(hm) : INT_MIN;
+  hb.lo[1] = hm ? j : INT_MAX;
+  hb.hi[1] = hm ? j : INT_MIN;
+  hb.lo[2] = hm ? k : INT_MAX;
+  hb.hi[2] = hm ? k : INT_MIN;
+  if (__any(hm != 0u)) hole_box_wave(hb);
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wbox[t >> 6][d] = hb.lo[d];
+      wbox[t >> 6][3 + d] = hb.hi[d];
+    }
+  }
+  if (__syncthreads_or(hole)) {  // (the same in every thread)
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        hb.lo[d] = min(hb.lo[d], wbox[w][d]);
+        hb.hi[d] = max(hb.hi[d], wbox[w][3 + d]);
+      }
+    __syncthreads();  // every thread has read the boxes before the next candidate writes them
+    mark_near_box(hb, t, 256, ti.x, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near, near_list,
+                  near_count);
+    if (t == 0) tile_hole[sub / kSubPerTile] = stamp;  // this step has a hole in the tile
   }
 }
 
@@ -850,6 +940,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
   const bool outer = L.outer[A] != 0;
   const bool row_outer = outer && (j < o2 || j >= nj - o3 || k < o4 || k >= nk - o5);
   bool hole = false;
+  unsigned int hm = 0u;  // bit e: node i + e is a hole
   if (ok) {
     const int m0 = i + ni * (j + nj * k);  // node index in grid A (< 2^31)
     uint8_t* dst = flags + L.off[A] + m0;
@@ -879,6 +970,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
         if (cause >= 0) {
           f = kHole | (cause << 2);
           hole = true;
+          hm |= 1u << e;
         } else if (outer && (row_outer || i + e < o0 || i + e >= ni - o1)) {
           f = kFringe | (OV_CAUSE_BOUNDARY << 2);
         }
@@ -902,9 +994,16 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
   for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, 64);
   if (lane == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_NODES_READ], (unsigned long long)nr);
   if (__any(hole)) {
-    for (int e = lane; e < 125; e += 64)
-      mark_near(e, ti.x, ti.y, ti.z, ti.w, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
-                near_list, near_count);
+    HoleBox hb;
+    hb.lo[0] = hm ? i + __builtin_ctz(hm) : INT_MAX;
+    hb.hi[0] = hm ? i + 31 - __builtin_clz(hm) : INT_MIN;
+    hb.lo[1] = hm ? j : INT_MAX;
+    hb.hi[1] = hm ? j : INT_MIN;
+    hb.lo[2] = hm ? k : INT_MAX;
+    hb.hi[2] = hm ? k : INT_MIN;
+    hole_box_wave(hb);
+    mark_near_box(hb, lane, 64, ti.x, ni, nj, nk, G.per, G.tiles_i, G.tiles_j, G.tile_off, stamp, tile_near,
+                  near_list, near_count);
     if (lane == 0) tile_hole[sub / kSubPerTile] = stamp;  // this step has a hole in the tile
   }
 }
