@@ -127,12 +127,17 @@ enum ov_option {
     OV_OPT_BACK_QUEUE = 15, /* step executors: 1 lets the back half's workgroups take their chunks of queries
                                from an atomic work queue (each its own first chunk, then the next free one)
                                instead of a fixed stride; 0 (default) the fixed stride. Same results. */
-    OV_OPT_BACK_XCD = 16    /* step executors: k in 1..64 puts runs of k consecutive chunks of queries on the
+    OV_OPT_BACK_XCD = 16,   /* step executors: k in 1..64 puts runs of k consecutive chunks of queries on the
                                workgroups of one XCD (the runs going to the XCDs in turn) where the back half's
                                workgroups take their chunks by index (every round of the fixed stride, the
                                first chunk with the work queue), so that neighbouring queries, whose donor
                                cells share lines, run under one L2; 0 (default), or a grid that 8 k does not
                                divide: launch order. Same results. */
+    OV_OPT_HOLECUT_LIST = 17/* culled hole cut: 1 computes which blank regions may reach each sub-tile in the
+                               kernel that starts the step (flag fill or reset) and hands the candidate
+                               sub-tiles out in rank order, one per workgroup of the hole cut (no workgroup
+                               waits on a second candidate while others idle); 0 (default) each workgroup culls
+                               and tests its own share of the sub-tiles. Same flags. */
 };
 
 /* Create a context on HIP device `device` with precision `precision`.

@@ -19,7 +19,11 @@ The tuned parameters and what they choose:
                 atomic work queue (1) or by a fixed stride (0);
   back_xcd      runs of this many consecutive chunks taken by index go to the
                 workgroups of one XCD (neighbouring chunks share its L2; 0:
-                launch order).
+                launch order);
+  holecut_list  the sub-tile cull in the kernel that starts the step and the
+                candidates handed out one per hole-cut workgroup by rank (1),
+                or each hole-cut workgroup culling and testing its own share
+                of the sub-tiles (0).
 All but max_walk leave the results unchanged (the parity tests run them);
 max_walk can change the reported cell only for a point that lies within the
 containment tolerance of a face shared by two valid cells (the walk keeps
@@ -52,11 +56,12 @@ SPACE = {
     "back_fused": (1, 2),
     "back_queue": (0, 1),
     "back_xcd": (0, 8),
+    "holecut_list": (0, 1),
 }
 DEFAULTS = {"stages": 3, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16,
-            "back_fused": 1, "back_queue": 0, "back_xcd": 0}
+            "back_fused": 1, "back_queue": 0, "back_xcd": 0, "holecut_list": 0}
 CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk", "back_fused", "back_queue",
-               "back_xcd")
+               "back_xcd", "holecut_list")
 
 
 def signature(w, precision: str) -> str:
@@ -115,10 +120,14 @@ def time_config(asm, capacity: int, poses, params: dict, steps: int, warmup: int
     return us
 
 
-def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: int = 2, log=print) -> dict:
-    """Coordinate descent over SPACE; returns the best parameters with their
-    time per step and the number of configurations timed."""
+def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: int = 2, log=print,
+         start: dict | None = None) -> dict:
+    """Coordinate descent over SPACE from `start` (default: the library
+    defaults); returns the best parameters with their time per step and the
+    number of configurations timed."""
     best = dict(DEFAULTS)
+    if start:
+        best.update({k: v for k, v in start.items() if k in SPACE})
     seen = {}
 
     def cost(p):
@@ -167,6 +176,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--out", default=CACHE)
     ap.add_argument("--fields", choices=("interleaved", "blocks"), default="interleaved")
+    ap.add_argument("--from-cache", action="store_true", help="start the search from the cached entry, if any")
     args = ap.parse_args()
     w = W.build(args.config)
     precision = args.precision or w.precision
@@ -176,8 +186,9 @@ def main():
     a.allocate(cap)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     steps = min(args.steps, w.steps - 3)
-    res = tune(a, cap, poses, steps=steps)
     sig = signature(w, precision)
+    cached = load(sig, args.out) if args.from_cache else None
+    res = tune(a, cap, poses, steps=steps, start=cached["params"] if cached else None)
     res["workload"] = w.name
     store(sig, res, args.out)
     print(json.dumps({"signature": sig, **res}), flush=True)

@@ -29,7 +29,7 @@ OV_STAT_COUNT = 9
 OPT = {"warm": 1, "max_walk": 2, "search_block": 3, "interp_block": 4, "holecut_block": 5,
        "holecut_npt": 6, "persist": 7, "holecut_cull": 8, "holecut_npl": 9,
        "back_fused": 10, "back_blocks": 11, "back_block": 12, "field_layout": 13,
-       "frame_velocity": 14, "back_queue": 15, "back_xcd": 16}
+       "frame_velocity": 14, "back_queue": 15, "back_xcd": 16, "holecut_list": 17}
 
 EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "ov_grid_set_blank_mesh",
            "ov_finalize", "ov_num_grids",

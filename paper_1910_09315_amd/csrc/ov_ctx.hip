@@ -549,6 +549,8 @@ int ov_ctx_destroy(ov_ctx* ctx) {
   (void)hipFree(ctx->d_fill_ranges);
   (void)hipFree(ctx->d_stamp);
   (void)hipFree(ctx->d_tile_hole);
+  (void)hipFree(ctx->d_sub_mask);
+  (void)hipFree(ctx->d_mask_counts);
   (void)hipFree(ctx->d_tile_near);
   (void)hipFree(ctx->d_near_list);
   (void)hipFree(ctx->d_near_count);
@@ -910,6 +912,9 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   }
   HIPCHK(hipMalloc(&ctx->d_stamp, sizeof(unsigned int) * (2 + kSlots)), "hipMalloc stamps");
   HIPCHK(hipMalloc(&ctx->d_tile_hole, sizeof(unsigned int) * kSlots * nt), "hipMalloc tile holes");
+  ctx->nmask_chunks = (nt * kSubPerTile + kMaskChunk - 1) / kMaskChunk;
+  HIPCHK(hipMalloc(&ctx->d_sub_mask, sizeof(unsigned long long) * kSlots * kSubPerTile * nt), "hipMalloc sub-tile masks");
+  HIPCHK(hipMalloc(&ctx->d_mask_counts, sizeof(int32_t) * kSlots * ctx->nmask_chunks), "hipMalloc mask counts");
   HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
   // two near lists per slot (alternate steps of a slot write one each)
   HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int4) * 2 * kSlots * nt), "hipMalloc near lists");
@@ -987,6 +992,10 @@ int ov_set_option(ov_ctx* ctx, int32_t key, int64_t v) {
     case OV_OPT_HOLECUT_NPL:
       if (v != 4 && v != 16) break;
       ctx->holecut_npl = (int)v;
+      return OV_OK;
+    case OV_OPT_HOLECUT_LIST:
+      if (v != 0 && v != 1) break;
+      ctx->holecut_list = (int)v;
       return OV_OK;
     case OV_OPT_BACK_FUSED:
       if (v < 0 || v > 2) break;

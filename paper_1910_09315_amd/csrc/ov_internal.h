@@ -29,6 +29,8 @@ constexpr double kDetMin = 1e-300;
 // The hole cut culls per sub-tile (kSubI nodes along i).
 constexpr int kTileI = 64, kTileJ = 8, kTileK = 8;
 constexpr int kSubI = 16, kSubPerTile = kTileI / kSubI;
+// sub-tiles per mask chunk (one per thread of a 256-thread block)
+constexpr int kMaskChunk = 256;
 constexpr int kMaxNf = 3;
 // Compaction chunk: 256 threads x 16 flag bytes; 64 chunks form a superchunk.
 constexpr int kCompactThreads = 256;
@@ -155,6 +157,12 @@ struct ov_ctx {
   unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`,
                                               // [1 + kSlots] counter of the C-ABI fringe call's own lists
   unsigned int* d_tile_hole = nullptr;        // per slot and tile: the stamp of the slot's step if the tile holds a hole
+  // the culled hole cut's candidate lookup (OV_OPT_HOLECUT_LIST): per slot,
+  // the blank regions that may reach each sub-tile, computed by the step's
+  // start kernel, and the number of sub-tiles with any in each mask chunk
+  unsigned long long* d_sub_mask = nullptr;   // [kSlots * nsub]
+  int32_t* d_mask_counts = nullptr;           // [kSlots * nmask_chunks]
+  long long nmask_chunks = 0;
   unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
   int4* d_near_list = nullptr;                // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;            // per slot
@@ -177,6 +185,7 @@ struct ov_ctx {
   int persist = 0;
   int cull = 1;  // hole cut: skip coordinate reads of tiles no blank region can reach
   int holecut_npl = 16;  // candidate nodes per lane in the culled hole cut: 16 (wavefront per sub-tile) or 4 (block)
+  int holecut_list = 0;  // culled hole cut: candidates ranked from the start kernel's masks, one per block
   int back_fused = 1;    // step executors: transform, search and interpolation in one kernel
   int back_blocks_per_cu = 8;  // persistent blocks of that kernel per compute unit
   int back_block = 256;        // its threads per block (64, 128 or 256)

@@ -36,6 +36,35 @@ struct HoleLds {
   double rad[kMaxGrids];       // radius of the sphere about the origin enclosing it
 };
 
+// Body-frame box of grid G's blank region (lo xyz, hi xyz; zeros if none).
+__device__ __forceinline__ void region_box(const GridDev& G, double* box) {
+  const double* q = G.blank_prm;
+  double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+  if (G.blank_kind == OV_BLANK_CYL) {
+    lo[0] = lo[1] = -q[0];
+    hi[0] = hi[1] = q[0];
+    lo[2] = q[1];
+    hi[2] = q[2];
+  } else if (G.blank_kind == OV_BLANK_SPHERE) {
+    lo[0] = lo[1] = lo[2] = -q[0];
+    hi[0] = hi[1] = hi[2] = q[0];
+  } else if (G.blank_kind == OV_BLANK_ELLIPSOID) {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = -q[d];
+      hi[d] = q[d];
+    }
+  } else if (G.blank_kind == OV_BLANK_MESH) {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = G.mbox[d];
+      hi[d] = G.mbox[3 + d];
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    box[d] = lo[d];
+    box[3 + d] = hi[d];
+  }
+}
+
 template <typename CT>
 __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restrict__ grids, int ngrids,
                                               const double* __restrict__ poses) {
@@ -85,30 +114,7 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
     }
     if (g == ngrids - 1) L.off[ngrids] = G.node_off + G.nnodes;
     L.rad[g] = sqrt(G.cull_r2);
-    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
-    if (G.blank_kind == OV_BLANK_CYL) {
-      lo[0] = lo[1] = -q[0];
-      hi[0] = hi[1] = q[0];
-      lo[2] = q[1];
-      hi[2] = q[2];
-    } else if (G.blank_kind == OV_BLANK_SPHERE) {
-      lo[0] = lo[1] = lo[2] = -q[0];
-      hi[0] = hi[1] = hi[2] = q[0];
-    } else if (G.blank_kind == OV_BLANK_ELLIPSOID) {
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = -q[d];
-        hi[d] = q[d];
-      }
-    } else if (G.blank_kind == OV_BLANK_MESH) {
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = G.mbox[d];
-        hi[d] = G.mbox[3 + d];
-      }
-    }
-    for (int d = 0; d < 3; ++d) {
-      L.box[g][d] = lo[d];
-      L.box[g][3 + d] = hi[d];
-    }
+    region_box(G, L.box[g]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -116,6 +122,33 @@ __device__ __forceinline__ void holecut_stage(HoleLds& L, const GridDev* __restr
     for (int g = 0; g < ngrids; ++g)
       if (L.kind[g] != OV_BLANK_NONE) m |= 1ull << g;
     L.allmask = m;
+  }
+  __syncthreads();
+}
+
+// What the sub-tile cull needs of every grid, staged in LDS: pose, the blank
+// region's body-frame box and enclosing radius, and the grids that have one.
+struct MaskLds {
+  double pose[kMaxGrids][12];
+  double box[kMaxGrids][6];
+  double rad[kMaxGrids];
+  unsigned long long allmask;
+};
+
+__device__ __forceinline__ void mask_stage(MaskLds& L, const GridDev* __restrict__ grids, int ngrids,
+                                           const double* __restrict__ poses) {
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) L.pose[i / 12][i % 12] = poses[i];
+  if (threadIdx.x < 64) {
+    const int g = threadIdx.x;
+    bool has = false;
+    if (g < ngrids) {
+      const GridDev& G = grids[g];
+      L.rad[g] = sqrt(G.cull_r2);
+      region_box(G, L.box[g]);
+      has = G.blank_kind != OV_BLANK_NONE;
+    }
+    const unsigned long long m = __ballot(has);
+    if (g == 0) L.allmask = m;
   }
   __syncthreads();
 }
@@ -532,7 +565,9 @@ __device__ __forceinline__ void hole_box_wave(HoleBox& b) {
 }
 
 // Lanes `lane` of `width` put entry e = lane, lane + width, ... of the box's
-// runs along i, j and k on the near list (once per stamp).
+// runs along i, j and k on the near list (once per stamp). Every lane of a
+// wavefront calls it with the same box; the entries a wavefront claims are
+// appended with one atomic on the list's count.
 __device__ __forceinline__ void mark_near_box(const HoleBox& b, int lane, int width, int g, int ni, int nj, int nk,
                                               int per, int tiles_i, int tiles_j, long long tile_off,
                                               unsigned int stamp, unsigned int* __restrict__ tile_near,
@@ -542,24 +577,47 @@ __device__ __forceinline__ void mark_near_box(const HoleBox& b, int lane, int wi
   reach_run(b.lo[1], b.hi[1], nj, kTileJ, per & 2, fj, cj);
   reach_run(b.lo[2], b.hi[2], nk, kTileK, per & 4, fk, ck);
   const int tiles_k = (nk + kTileK - 1) / kTileK;
-  for (int e = lane; e < ci * cj * ck; e += width) {
-    int x = fi + e % ci, y = fj + (e / ci) % cj, z = fk + e / (ci * cj);
-    x = x >= tiles_i ? x - tiles_i : x;
-    y = y >= tiles_j ? y - tiles_j : y;
-    z = z >= tiles_k ? z - tiles_k : z;
-    const long long n = tile_off + x + (long long)tiles_i * (y + (long long)tiles_j * z);
-    if (atomicExch(&tile_near[n], stamp) != stamp) near_list[atomicAdd(near_count, 1)] = make_int4(g, x, y, z);
+  const int total = ci * cj * ck;
+  const int wl = (int)(threadIdx.x & 63);
+  for (int e0 = 0; e0 < total; e0 += width) {
+    const int e = e0 + lane;
+    int x = 0, y = 0, z = 0;
+    bool fresh = false;
+    if (e < total) {
+      x = fi + e % ci;
+      y = fj + (e / ci) % cj;
+      z = fk + e / (ci * cj);
+      x = x >= tiles_i ? x - tiles_i : x;
+      y = y >= tiles_j ? y - tiles_j : y;
+      z = z >= tiles_k ? z - tiles_k : z;
+      const long long n = tile_off + x + (long long)tiles_i * (y + (long long)tiles_j * z);
+      fresh = atomicExch(&tile_near[n], stamp) != stamp;
+    }
+    const unsigned long long fm = __ballot(fresh);
+    if (fm) {
+      const int leader = __ffsll((long long)fm) - 1;
+      int base = 0;
+      if (wl == leader) base = atomicAdd(near_count, (int)__popcll(fm));
+      base = __shfl(base, leader, 64);
+      if (fresh) near_list[base + (int)__popcll(fm & ((1ull << wl) - 1ull))] = make_int4(g, x, y, z);
+    }
   }
 }
 
 // Which blank regions may reach sub-tile `sub` (bit B set: grid B's region
-// may contain a node of it). The sub-tile's bounding sphere, placed at its
-// grid's pose, is tested against the sphere about grid B's origin that
-// encloses B's region, then against the region's box in B's body frame
-// (distance from the sphere's centre to the box at most the radius). The
-// radius is padded far beyond FP64 rounding, so no node the exact test
-// would blank is ever culled.
-__device__ __forceinline__ unsigned long long sub_mask(const HoleLds& L, int A, double4 sp) {
+// may contain a node of it). The sub-tile's bounding sphere (radius w),
+// placed at its grid's pose, is tested against the sphere about grid B's
+// origin that encloses B's region (radius R), then against the region's box
+// in B's body frame. Both tests are padded by a relative 1e-9 of the lengths
+// involved plus 1e-12, far beyond FP64 rounding, so no node the exact test
+// would blank is ever culled. The sphere test compares squared distances:
+// with centre distance d, B is kept while d <= K = (R + w)(1 + 3e-9) + 2e-12,
+// which exceeds ((R + w)(1 + 1e-9) + 1e-12) / (1 - 1e-9), the bound of the
+// test d <= R + w + 1e-9 (w + d + R) + 1e-12; the box test then uses the
+// padded radius w + 1e-9 (w + K + R) + 1e-12, at least the one the distance
+// itself would give.
+template <class LDS>
+__device__ __forceinline__ unsigned long long sub_mask(const LDS& L, int A, double4 sp) {
   const double* pa = L.pose[A];
   const double w0 = pa[0] * sp.x + pa[1] * sp.y + pa[2] * sp.z + pa[9];
   const double w1 = pa[3] * sp.x + pa[4] * sp.y + pa[5] * sp.z + pa[10];
@@ -569,9 +627,9 @@ __device__ __forceinline__ unsigned long long sub_mask(const HoleLds& L, int A, 
     const int B = __ffsll((long long)mm) - 1;
     const double* p = L.pose[B];
     const double d0 = w0 - p[9], d1 = w1 - p[10], d2 = w2 - p[11];
-    const double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    const double r = sp.w + 1e-9 * (sp.w + dd + L.rad[B]) + 1e-12;
-    if (dd > L.rad[B] + r) continue;
+    const double K = (L.rad[B] + sp.w) * (1.0 + 3e-9) + 2e-12;
+    if (d0 * d0 + d1 * d1 + d2 * d2 > K * K) continue;
+    const double r = sp.w + 1e-9 * (sp.w + K + L.rad[B]) + 1e-12;
     const double x = p[0] * d0 + p[3] * d1 + p[6] * d2;
     const double y = p[1] * d0 + p[4] * d1 + p[7] * d2;
     const double z = p[2] * d0 + p[5] * d1 + p[8] * d2;
@@ -581,6 +639,32 @@ __device__ __forceinline__ unsigned long long sub_mask(const HoleLds& L, int A, 
     if (ex * ex + ey * ey + ez * ez <= r * r) mask |= 1ull << B;
   }
   return mask;
+}
+
+// The start kernel's share of the cull (OV_OPT_HOLECUT_LIST): mask chunk c
+// (kMaskChunk consecutive sub-tiles, one per thread of a 256-thread block)
+// for c = bid, bid + nblocks, ...: every sub-tile's mask, and the chunk's
+// number of candidates (sub-tiles with a non-zero mask).
+__device__ __forceinline__ void mask_chunks(const MaskLds& L, const double4* __restrict__ spheres,
+                                            const int4* __restrict__ tile_info, long long nsub,
+                                            unsigned long long* __restrict__ sub_mask_out,
+                                            int32_t* __restrict__ mask_counts, long long nmc, long long bid,
+                                            long long nblocks) {
+  static_assert(kMaskChunk == 256, "one sub-tile per thread of a 256-thread block");
+  __shared__ int wcount[4];
+  for (long long c = bid; c < nmc; c += nblocks) {
+    const long long sub = c * kMaskChunk + threadIdx.x;
+    unsigned long long m = 0;
+    if (sub < nsub) {
+      m = sub_mask(L, tile_info[sub / kSubPerTile].x, spheres[sub]);
+      sub_mask_out[sub] = m;
+    }
+    const int wc = (int)__popcll(__ballot(m != 0ull));
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = wc;
+    __syncthreads();
+    if (threadIdx.x == 0) mask_counts[c] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();  // wcount is rewritten by the next chunk
+  }
 }
 
 // Geometry of every grid for the tile kernels, staged in LDS.
@@ -611,6 +695,28 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
   unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
   unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
   return ((unsigned long long)hi << 32) | lo;
+}
+
+// The cull of the step's sub-tiles, done by the kernel that starts the step
+// (OV_OPT_HOLECUT_LIST); nmc = 0: none.
+struct MaskJob {
+  const double* poses;
+  const double4* spheres;
+  const int4* tile_info;
+  unsigned long long* sub_mask;
+  int32_t* mask_counts;
+  long long nsub, nmc;
+  int ngrids;
+};
+
+// The mask chunks go to the blocks from the last one down, so that where the
+// start kernel has fewer tiles to reset than blocks, different blocks take
+// the two jobs.
+__device__ __forceinline__ void mask_job(const MaskJob& mj, const GridDev* __restrict__ grids) {
+  __shared__ MaskLds ML;
+  mask_stage(ML, grids, mj.ngrids, mj.poses);
+  mask_chunks(ML, mj.spheres, mj.tile_info, mj.nsub, mj.sub_mask, mj.mask_counts, mj.nmc,
+              (long long)gridDim.x - 1 - blockIdx.x, gridDim.x);
 }
 
 // The culled hole cut runs in two kernels, in stream order:
@@ -676,11 +782,12 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
                                                    int32_t* __restrict__ near_count,
                                                    int32_t* __restrict__ chunk_list_count,
                                                    int32_t* __restrict__ super_counts, long long n_super_counts,
-                                                   unsigned long long* __restrict__ stats) {
+                                                   unsigned long long* __restrict__ stats, MaskJob mj) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
     atomicAdd(&stat_slot(stats)[OV_STAT_FLAG_STARTS], 1ULL);
   }
+  if (mj.nmc > 0) mask_job(mj, grids);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
        i += (long long)gridDim.x * blockDim.x)
     super_counts[i] = 0;
@@ -722,7 +829,8 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, const uint8_t* __restrict__ base,
+__global__ void __launch_bounds__(256) k_flag_fill(const GridDev* __restrict__ grids, uint8_t* __restrict__ flags,
+                                                  const uint8_t* __restrict__ base,
                                                   const long long* __restrict__ fill_ranges, int nranges,
                                                   long long fill_words, unsigned int* __restrict__ counter,
                                                   unsigned int* __restrict__ d_stamp,
@@ -730,7 +838,8 @@ __global__ void __launch_bounds__(256) k_flag_fill(uint8_t* __restrict__ flags, 
                                                   int32_t* __restrict__ chunk_list_count,
                                                   int32_t* __restrict__ super_counts, long long n_super_counts,
                                                   unsigned long long* __restrict__ stats, long long nodes,
-                                                  long long base_nodes) {
+                                                  long long base_nodes, MaskJob mj) {
+  if (mj.nmc > 0) mask_job(mj, grids);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
     unsigned long long* slot = stat_slot(stats);
@@ -756,11 +865,10 @@ static_assert(kSubI == 16 && kTileJ * kTileK * 4 == 256, "a 256-thread block cov
 
 template <typename CT, bool MESH>
 __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
-                                           uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
+                                           uint8_t* __restrict__ flags, const int4 ti, int sub,
                                            unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
                                            int4* __restrict__ near_list, int32_t* __restrict__ near_count,
                                            unsigned int* __restrict__ tile_hole, unsigned long long* __restrict__ stats) {
-  const int4 ti = tile_info[sub / kSubPerTile];
   const int A = uniform_i32(ti.x);
   const TileGeo& G = TG[A];
   const int ni = G.ni, nj = G.nj, nk = G.nk;
@@ -917,18 +1025,19 @@ __device__ __forceinline__ void cand_block(const HoleLds& L, const TileGeo* TG, 
 }
 
 // Candidate sub-tiles, one wavefront each at a time (the variant for many
-// candidates: no block barrier per sub-tile): lane l takes the 16 nodes
-// i0 .. i0 + 15 of row (j0 + l % 8, k0 + l / 8), loads their coordinates in
-// batches of 4, tests them against the blank regions of the sub-tile's mask
-// only and writes their 16 flags.
+// candidates: no block barrier per sub-tile, the block's wavefronts on
+// different candidates at once): lane l takes the 16 nodes i0 .. i0 + 15 of
+// row (j0 + l % 8, k0 + l / 8), loads all their coordinates (FP32; FP64 in
+// two halves) before testing any, tests them against the blank regions of
+// the sub-tile's mask only and writes their 16 flags in one store.
 template <typename CT, bool MESH>
 __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, const GridDev* __restrict__ grids,
-                                          uint8_t* __restrict__ flags, const int4* __restrict__ tile_info, int sub,
+                                          uint8_t* __restrict__ flags, const int4 ti, int sub,
                                           unsigned long long mask, unsigned int stamp, unsigned int* __restrict__ tile_near,
                                           int4* __restrict__ near_list, int32_t* __restrict__ near_count,
                                           unsigned int* __restrict__ tile_hole, unsigned long long* __restrict__ stats) {
+  constexpr int kBatch = sizeof(CT) == 4 ? kSubI : kSubI / 2;  // nodes whose coordinates are loaded together
   const int lane = threadIdx.x & 63;
-  const int4 ti = tile_info[sub / kSubPerTile];
   const int A = uniform_i32(ti.x);
   const TileGeo& G = TG[A];
   const int ni = G.ni, nj = G.nj, nk = G.nk;
@@ -947,22 +1056,21 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
     gmem<CT>* Xa = gp((const CT*)L.X[A]) + m0;
     gmem<CT>* Ya = gp((const CT*)L.Y[A]) + m0;
     gmem<CT>* Za = gp((const CT*)L.Z[A]) + m0;
-    uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;  // the 16 flag bytes
-    // 16 nodes in batches of 4: a batch's coordinates are loaded before
-    // any of its nodes is tested
-#pragma unroll 1
-    for (int b0 = 0; b0 < kSubI; b0 += 4) {
-      uint32_t word = 0u;
-      CT X[4], Y[4], Z[4];
+    uint32_t w[4] = {0u, 0u, 0u, 0u};  // the 16 flag bytes
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (b0 + r < n) {
-          X[r] = Xa[b0 + r];
-          Y[r] = Ya[b0 + r];
-          Z[r] = Za[b0 + r];
-        }
+    for (int b0 = 0; b0 < kSubI; b0 += kBatch) {
+      CT X[kBatch], Y[kBatch], Z[kBatch];
+      // every load of the batch issued before the first test (a node past
+      // the row's end re-reads its last node and is not tested)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kBatch; ++r) {
+        const int e = min(b0 + r, n - 1);
+        X[r] = Xa[e];
+        Y[r] = Ya[e];
+        Z[r] = Za[e];
+      }
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
         const int e = b0 + r;
         if (e >= n) continue;
         const int cause = holecut_node<CT, MESH>(L, grids, A, m0 + e, X[r], Y[r], Z[r], mask);
@@ -974,18 +1082,14 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
         } else if (outer && (row_outer || i + e < o0 || i + e >= ni - o1)) {
           f = kFringe | (OV_CAUSE_BOUNDARY << 2);
         }
-        word |= f << (8 * r);
+        w[e >> 2] |= f << (8 * (e & 3));
       }
-      w0 = b0 == 0 ? word : w0;
-      w1 = b0 == 4 ? word : w1;
-      w2 = b0 == 8 ? word : w2;
-      w3 = b0 == 12 ? word : w3;
     }
     if (n == 16 && (((uintptr_t)dst) & 15) == 0) {
-      *reinterpret_cast<uint4*>(dst) = make_uint4(w0, w1, w2, w3);
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
     } else {
       for (int e = 0; e < n; ++e) {
-        const uint32_t wd = e < 4 ? w0 : e < 8 ? w1 : e < 12 ? w2 : w3;
+        const uint32_t wd = e < 4 ? w[0] : e < 8 ? w[1] : e < 12 ? w[2] : w[3];
         dst[e] = (uint8_t)(wd >> (8 * (e & 3)));
       }
     }
@@ -1017,7 +1121,7 @@ __device__ __forceinline__ void cand_wave(const HoleLds& L, const TileGeo* TG, c
 // at a time. No list leaves the block, so nothing needs resetting between
 // steps.
 template <typename CT, bool WAVE, bool MESH>
-__global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__ grids, int ngrids,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MESH ? 1 : (sizeof(CT) == 4 ? 4 : 3)))) k_holecut_sub(const GridDev* __restrict__ grids, int ngrids,
                                                     const double* __restrict__ poses, uint8_t* __restrict__ flags,
                                                     const double4* __restrict__ spheres,
                                                     const int4* __restrict__ tile_info, long long nsub,
@@ -1032,6 +1136,7 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
   __shared__ TileGeo TG[kMaxGrids];
   __shared__ int c_sub[256];
   __shared__ unsigned long long c_mask[256];
+  __shared__ int4 c_info[256];
   __shared__ int c_n;
   stage_tile_geo(TG, grids, ngrids);
   holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
@@ -1049,25 +1154,125 @@ __global__ void __launch_bounds__(256) k_holecut_sub(const GridDev* __restrict__
     const long long idx = r0 + (long long)threadIdx.x * nb + blockIdx.x;
     const long long sub = idx < nsub ? (idx * perm) % nsub : nsub;
     if (sub < nsub) {
-      const unsigned long long m = sub_mask(L, tile_info[sub / kSubPerTile].x, spheres[sub]);
+      const int4 info = tile_info[sub / kSubPerTile];
+      const unsigned long long m = sub_mask(L, info.x, spheres[sub]);
       if (m) {
         const int slot = atomicAdd(&c_n, 1);
         c_sub[slot] = (int)sub;
         c_mask[slot] = m;
+        c_info[slot] = info;
       }
     }
     __syncthreads();
     const int n = c_n;
     if (WAVE) {
       for (int c = threadIdx.x >> 6; c < n; c += 4)
-        cand_wave<CT, MESH>(L, TG, grids, flags, tile_info, uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
+        cand_wave<CT, MESH>(L, TG, grids, flags, c_info[c], uniform_i32(c_sub[c]), uniform_u64(c_mask[c]), stamp,
                             tile_near, near_list, near_count, tile_hole, stats);
     } else {
       for (int c = 0; c < n; ++c)
-        cand_block<CT, MESH>(L, TG, grids, flags, tile_info, c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
+        cand_block<CT, MESH>(L, TG, grids, flags, c_info[c], c_sub[c], uniform_u64(c_mask[c]), stamp, tile_near,
                              near_list, near_count, tile_hole, stats);
     }
     __syncthreads();  // the list is rebuilt by the next round
+  }
+}
+
+// The culled hole cut after a start kernel that culled the sub-tiles
+// (OV_OPT_HOLECUT_LIST): the step's candidates, in ascending sub-tile order,
+// are ranked from the start kernel's per-chunk counts, and block b tests
+// candidates b, b + gridDim, ... (one each when there are fewer candidates
+// than blocks). Every block scans the chunk counts itself, 1024 chunks at a
+// time (4 per thread), finds the chunk of each of its ranks by bisection of
+// the scanned counts, and the candidate in the chunk by the rank of its
+// non-zero mask among the chunk's.
+template <typename CT, bool MESH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MESH ? 1 : 4)))
+    k_holecut_list(const GridDev* __restrict__ grids, int ngrids, const double* __restrict__ poses,
+                   uint8_t* __restrict__ flags, const int4* __restrict__ tile_info,
+                   const unsigned long long* __restrict__ sub_masks, const int32_t* __restrict__ mask_counts,
+                   long long nsub, long long nmc, const unsigned int* __restrict__ d_stamp,
+                   unsigned int* __restrict__ tile_near, int4* __restrict__ near_list,
+                   int32_t* __restrict__ near_count, unsigned int* __restrict__ tile_hole,
+                   unsigned long long* __restrict__ stats) {
+  static_assert(kMaskChunk == 256, "one sub-tile of a chunk per thread");
+  constexpr int kBatch = 4 * 256;  // chunks scanned per round
+  __shared__ HoleLds L;
+  __shared__ TileGeo TG[kMaxGrids];
+  __shared__ int pre[kBatch + 1];  // exclusive prefix of the round's chunk counts; [kBatch] their sum
+  __shared__ int wsum[4];
+  __shared__ int c_sub;
+  __shared__ unsigned long long c_mask;
+  __shared__ int4 c_info;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // the first round's counts are loaded before the staging's barriers
+  int v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = 4 * t + e < nmc ? mask_counts[4 * t + e] : 0;
+  stage_tile_geo(TG, grids, ngrids);
+  holecut_stage<CT>(L, grids, ngrids, poses);  // ends with a barrier
+  const unsigned int stamp = *d_stamp;
+  if (blockIdx.x == 0 && t == 0) atomicAdd(&stat_slot(stats)[OV_STAT_HOLECUT_CALLS], 1ULL);
+  long long before = 0;         // candidates in the chunks of the earlier rounds
+  long long r = blockIdx.x;     // this block's next rank
+  for (long long c0 = 0; c0 < nmc; c0 += kBatch) {
+    if (c0 > 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = c0 + 4 * t + e < nmc ? mask_counts[c0 + 4 * t + e] : 0;
+    }
+    // block-wide exclusive scan of the threads' sums
+    const int mine = v[0] + v[1] + v[2] + v[3];
+    int inc = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int ex = inc - mine;
+    for (int w = 0; w < wv; ++w) ex += wsum[w];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    pre[4 * t] = ex;
+    pre[4 * t + 1] = ex + v[0];
+    pre[4 * t + 2] = ex + v[0] + v[1];
+    pre[4 * t + 3] = ex + v[0] + v[1] + v[2];
+    if (t == 0) pre[kBatch] = total;
+    __syncthreads();
+    while (r < before + total) {  // (the same in every thread)
+      const int k = (int)(r - before);
+      // the chunk of rank k: the last e with pre[e] <= k (its count is > 0)
+      int lo = 0, hi = kBatch - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      const int kk = k - pre[lo];
+      const long long sub = (c0 + lo) * kMaskChunk + t;
+      unsigned long long m = 0;
+      int4 info = make_int4(0, 0, 0, 0);
+      if (sub < nsub) {
+        m = sub_masks[sub];
+        info = tile_info[sub / kSubPerTile];
+      }
+      const unsigned long long bm = __ballot(m != 0ull);
+      if (lane == 0) wsum[wv] = (int)__popcll(bm);
+      __syncthreads();
+      int rank = (int)__popcll(bm & ((1ull << lane) - 1ull));
+      for (int w = 0; w < wv; ++w) rank += wsum[w];
+      if (m != 0ull && rank == kk) {
+        c_sub = (int)sub;
+        c_mask = m;
+        c_info = info;
+      }
+      __syncthreads();
+      cand_block<CT, MESH>(L, TG, grids, flags, c_info, c_sub, uniform_u64(c_mask), stamp, tile_near, near_list,
+                           near_count, tile_hole, stats);
+      __syncthreads();  // c_sub, c_mask, c_info and wsum are rewritten next
+      r += gridDim.x;
+    }
+    before += total;
   }
 }
 
@@ -1204,22 +1409,50 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
   if (ctx->cull) {
     const long long fb = std::max(1LL, std::min((ctx->fill_words + 256 * kFillUnroll - 1) / (256 * kFillUnroll),
                                                 (long long)ctx->num_cus * 32));
+    const long long nsub = nt * kSubPerTile;
+    MaskJob mj{};
+    if (ctx->holecut_list) {
+      mj.poses = poses;
+      mj.spheres = (const double4*)ctx->d_tile_sphere;
+      mj.tile_info = ctx->d_tile_info;
+      mj.sub_mask = ctx->d_sub_mask + (long long)slot * nsub;
+      mj.mask_counts = ctx->d_mask_counts + (long long)slot * ctx->nmask_chunks;
+      mj.nsub = nsub;
+      mj.nmc = ctx->nmask_chunks;
+      mj.ngrids = ng;
+    }
     if (reset) {
       const int og = 1 - gen;
-      const long long rb = std::max(1LL, std::min(nt, (long long)ctx->num_cus * 8));
+      const long long rb = std::max(1LL, std::min(std::max(nt, mj.nmc), (long long)ctx->num_cus * 8));
       hipLaunchKernelGGL(k_flag_reset, dim3((unsigned)rb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
                          ctx->d_near_list + (og * kSlots + slot) * std::max(1LL, nt),
-                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc, ctx->d_stats);
+                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc, ctx->d_stats, mj);
     } else {
       long long base_nodes = 0;
       for (const auto& g : ctx->grids)
         if (g.d.has_outer) base_nodes += g.d.nnodes;
-      hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, flags, ctx->d_base_flags,
+      hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
                          ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc,
-                         ctx->d_stats, ctx->node_off.back(), base_nodes);
+                         ctx->d_stats, ctx->node_off.back(), base_nodes, mj);
     }
-    const long long nsub = nt * kSubPerTile;
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
+    if (ctx->holecut_list) {
+      const long long lb = std::max(1LL, std::min(nsub, (long long)ctx->num_cus * per_cu));
+      const dim3 g((unsigned)lb), b(256);
+#define OV_LIST_ARGS                                                                                             \
+  ctx->d_grids, ng, poses, flags, ctx->d_tile_info, (const unsigned long long*)mj.sub_mask,                          \
+      (const int32_t*)mj.mask_counts, nsub, mj.nmc, st, ctx->d_tile_near, nl, nc, th, ctx->d_stats
+      const bool mixed = ctx->precision == OV_MIXED;
+      if (ctx->has_mesh) {
+        if (mixed) hipLaunchKernelGGL((k_holecut_list<float, true>), g, b, 0, s, OV_LIST_ARGS);
+        else hipLaunchKernelGGL((k_holecut_list<double, true>), g, b, 0, s, OV_LIST_ARGS);
+      } else {
+        if (mixed) hipLaunchKernelGGL((k_holecut_list<float, false>), g, b, 0, s, OV_LIST_ARGS);
+        else hipLaunchKernelGGL((k_holecut_list<double, false>), g, b, 0, s, OV_LIST_ARGS);
+      }
+#undef OV_LIST_ARGS
+      return hipGetLastError();
+    }
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
 #define OV_SUB_ARGS                                                                                             \
   ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, ctx->sub_perm, st,     \

@@ -86,6 +86,22 @@ def test_school_small_block_candidate_holecut():
     _run_steps(w, [0, 1, 2], "mixed", options={"holecut_npl": 4})
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_school_small_listed_candidate_holecut(precision):
+    w = W.c3_small(steps=3)
+    _run_steps(w, [0, 1, 2], precision, options={"holecut_list": 1})
+
+
+@pytest.mark.timeout(300)
+def test_shells_full_size_listed_candidate_holecut():
+    """The full-size shells workload with the listed-candidate hole cut through
+    the three-stream executor (flags, query list and donors against the
+    oracle at sampled steps)."""
+    w = W.c4(steps=500)
+    stats = _run_pipeline(w, [0, 1, 250], "mixed", options={"field_layout": 1, "holecut_list": 1, "persist": 4})
+    assert all(s["orphans"] == 0 for s in stats)
+
+
 @pytest.mark.timeout(300)
 def test_school_full_size_pipelined_sampled_steps():
     w = W.c3(steps=200)

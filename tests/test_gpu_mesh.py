@@ -24,7 +24,8 @@ def _assembly(w, precision, options=None, capacity=None):
 
 
 @pytest.mark.parametrize("precision,options", [("fp64", None), ("mixed", None), ("fp64", {"holecut_cull": 0}),
-                                               ("mixed", {"holecut_npl": 4})])
+                                               ("mixed", {"holecut_npl": 4}), ("mixed", {"holecut_list": 1}),
+                                               ("fp64", {"holecut_list": 1})])
 def test_triangulated_school_matches_oracle_every_step(precision, options):
     w = W.c3_mesh_small(steps=4)
     o = oracle.Oracle(w.grids, w.nf)

@@ -64,6 +64,14 @@ def test_c1_small_block_candidate_holecut_matches_oracle():
     _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_npl": 4})
 
 
+def test_c1_small_listed_candidate_holecut_matches_oracle():
+    """The culled hole cut with the sub-tile cull done by the kernel that
+    starts the step and the candidates handed out one per block by rank."""
+    w = W.c1_small(steps=3)
+    _run_and_compare(w, [0, 1, 2], options={"holecut_list": 1})
+    _run_and_compare(w, [0, 2], precision="mixed", value_rtol=1e-5, s_tol=1e-4, options={"holecut_list": 1})
+
+
 def test_c1_small_interleaved_fields_match_oracle():
     """Fields interleaved per node (u, v, w, p) instead of four blocks."""
     w = W.c1_small(steps=3)
@@ -255,6 +263,7 @@ def test_split_back_half_with_every_query_deferred(precision):
 
 @pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
                                      {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1},
+                                     {"holecut_list": 1, "persist": 4}, {"holecut_list": 1, "persist": 16},
                                      {"back_fused": 2, "back_block": 64, "back_blocks": 4},
                                      {"back_fused": 2, "back_block": 256, "back_blocks": 8},
                                      {"back_queue": 1, "back_block": 64, "back_blocks": 2},
