@@ -368,6 +368,8 @@ def measure(args, w=None):
             AT.apply(a, params)
             if args.stages is None:
                 args.stages = params["stages"]
+            if args.threads is None:
+                args.threads = int(params.get("threads", 0))
             log(f"[bench] tuned parameters {params}")
     for kv in args.opt:
         k, v = kv.split("=", 1)
@@ -375,6 +377,8 @@ def measure(args, w=None):
         log(f"[bench] option {k} = {v}")
     if args.stages is None:
         args.stages = 3
+    if args.threads is None:
+        args.threads = 0
     if args.stages > 1 and profiler_counting():
         # counter collection serialises dispatches: a stream waiting on
         # another stream's counter could wait for work that cannot start
@@ -389,7 +393,8 @@ def measure(args, w=None):
     if mode.startswith("pipelined"):
         pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=max_timed,
                         stages=args.stages if mode == "pipelined" else 2,
-                        graphs=(mode == "pipelined" and args.native_graphs))
+                        graphs=(mode == "pipelined" and args.native_graphs),
+                        threads=(mode == "pipelined" and bool(args.threads)))
     elif mode == "graph":
         a.capture()
     if mode == "pipelined-graph":
@@ -517,6 +522,7 @@ def measure(args, w=None):
                              "u, v, w, p as four blocks",
                    "mode": mode + (f", native executor on {args.stages} stream(s)"
                                    + (", per-stream graphs" if args.native_graphs else "")
+                                   + (", one host thread per stream" if args.threads and args.stages > 1 else "")
                                    + (", unfused back half" if args.unfused_back else ", fused back half")
                                    + ("" if args.per_step_submit else ", one submit call for all timed steps")
                                    if mode == "pipelined" else ""),
@@ -654,6 +660,8 @@ def make_parser():
     ap.add_argument("--no-cull", action="store_true", help="hole cut streams every node (no tile culling)")
     ap.add_argument("--stages", type=int, default=None, choices=(1, 2, 3),
                     help="native executor streams (default: the tuned choice, else 3; 1 under rocprofv3 counters)")
+    ap.add_argument("--threads", type=int, default=None, choices=(0, 1),
+                    help="native executor: one host thread per stream in multi-step submits (default: tuned, else 0)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the executor for this workload first when no tuned entry is cached")
     ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
@@ -745,6 +753,7 @@ def main():
         for prec in [p for p in args.compare_precisions.split(",") if p]:
             a2 = copy.copy(args)
             a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, prec, None, None, 0
+            a2.threads = None
             a2.opt = []
             a2.roofline = "back"
             a2.next_rows = args.next_rows and prec == "mixed"

@@ -444,6 +444,17 @@ int ov_pipe_submit(ov_pipe *pipe, const double *poses, int64_t *count_out);
  * as n calls of ov_pipe_submit, without a host round trip per step. */
 int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride, int64_t n, int64_t *counts_out);
 
+/* on = 1: ov_pipe_submit_many of more than one step on two or three streams
+ * issues each stream's work from a host thread of its own (the calling thread
+ * takes the first stream; the others are started for the call and joined
+ * before it returns), so that the host's time per step is that of one
+ * stream's calls rather than of all of them. The order between the streams
+ * is the device-side one in either case, so the results are the same. Not
+ * used with graphs or with a stage timed alone (ov_pipe_set_timing), where
+ * the calls go out from the calling thread. on = 0 (default): one thread.
+ * Returns OV_EINVAL for another value. */
+int ov_pipe_set_threads(ov_pipe *pipe, int32_t on);
+
 /* Make `stream` wait for all work submitted so far. */
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 

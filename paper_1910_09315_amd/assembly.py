@@ -241,7 +241,7 @@ class Pipeline:
     (optionally replaying per-half HIP graphs, see capture())."""
 
     def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024, stages: int = 2,
-                 graphs: bool = False):
+                 graphs: bool = False, threads: bool = False):
         if stages not in (1, 2, 3) or (stages != 2 and not native):
             raise ValueError("stages must be 2, or 1 or 3 with the native executor")
         self.a = asm
@@ -256,6 +256,8 @@ class Pipeline:
             self.native = B.NativePipe(asm.ctx, asm.nf, self.bufs, asm.fields, self.streams, max_timed)
             if graphs:
                 self.native.use_graphs(True)
+            if threads:
+                self.native.set_threads(True)
         self.front_done = [torch.cuda.Event() for _ in range(2)]
         self.back_done = [torch.cuda.Event() for _ in range(2)]
         self.started = [False] * stages

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 #include "ov_internal.h"
@@ -68,6 +69,8 @@ struct ov_pipe {
   // of the back half's work queue (OV_OPT_BACK_QUEUE), all zeroed here
   int32_t* defer_items = nullptr;
   unsigned int* defer_count = nullptr;
+  // submit_many from one host thread per stream (ov_pipe_set_threads)
+  bool threads = false;
 };
 
 using namespace ov;
@@ -82,21 +85,16 @@ static int first_stage(const ov_pipe* p, int g) {
 
 // Launches stage `stage` (0 = A, 1 = B, 2 = C) for buffer set k on stream s,
 // reading poses from `poses`; count_out (nullable) gets the query count.
+// gen: the slot's near list this step writes (A) and reads (B); reset: A
+// starts from the set's previous step (k_flag_reset) instead of a full fill.
 static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses, hipStream_t s,
-                               long long* count_out) {
+                               long long* count_out, int gen, bool reset) {
   ov_ctx* ctx = p->ctx;
   const ov_step_buffers& b = p->sets[k];
   const int slot = k;
-  if (stage == 0) {
-    // alternate the slot's two near lists; from the set's second step on,
-    // reset only the previous step's tiles (not under graphs, whose
-    // captured launches cannot alternate)
-    const int use = p->uses[k]++;
-    p->gen[k] = p->graphs ? 0 : (use & 1);
-    return launch_holecut(ctx, poses, b.flags, s, slot, p->gen[k], !p->graphs && use > 0);
-  }
+  if (stage == 0) return launch_holecut(ctx, poses, b.flags, s, slot, gen, reset);
   if (stage == 1) {
-    hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot, p->gen[k]);
+    hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot, gen);
     if (e == hipSuccess)
       e = launch_compact(ctx, b.flags, b.q_grid, b.q_node, b.capacity, (long long*)b.d_count, s, slot, true);
     return e;
@@ -220,7 +218,7 @@ int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
       hipError_t le = hipSuccess;
       for (int stage = first_stage(p, g); stage < first_stage(p, g + 1) && e == hipSuccess && le == hipSuccess;
            ++stage)
-        le = stage_launch(p, k, stage, poses, cap, nullptr);
+        le = stage_launch(p, k, stage, poses, cap, nullptr, 0, false);  // (captured steps: full fill, list 0)
       hipGraph_t graph = nullptr;
       if (e == hipSuccess) e = hipStreamEndCapture(cap, &graph);
       p->g[k][g] = graph;
@@ -261,6 +259,13 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   const double* ps = poses;
   const bool timed = p->timing > 0 && (t - p->timing_t0) % p->timing == 0 && p->ntimed < (int)p->tb.size();
   const bool alone = timed && p->timed_alone;
+  // alternate the slot's two near lists; from the set's second step on,
+  // reset only the previous step's tiles (not under graphs, whose captured
+  // launches cannot alternate)
+  const long long use = p->uses[k]++;
+  const int gen = p->graphs ? 0 : (int)(use & 1);
+  const bool reset = !p->graphs && use > 0;
+  p->gen[k] = gen;
   for (int g = 0; g < n && e == hipSuccess; ++g) {
     hipStream_t s = p->st[g];
     // after the previous group of this step, or (first group) after the
@@ -300,7 +305,8 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
       for (int stage = first_stage(p, g); stage < first_stage(p, g + 1) && e == hipSuccess; ++stage) {
         const bool ts = timed && stage == p->timed_stage;
         if (ts) e = hipEventRecord(p->tb[p->ntimed], s);
-        if (e == hipSuccess) e = stage_launch(p, k, stage, ps, s, stage == 2 ? (long long*)count_out : nullptr);
+        if (e == hipSuccess)
+          e = stage_launch(p, k, stage, ps, s, stage == 2 ? (long long*)count_out : nullptr, gen, reset);
         if (e == hipSuccess && ts) e = hipEventRecord(p->te[p->ntimed], s);
       }
     }
@@ -312,9 +318,83 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   return OV_OK;
 }
 
+// submit_many with one host thread per stream: every step's bookkeeping
+// (buffer set, near list, start kind, timing slot) is fixed first, in
+// submission order; then thread g issues group g's waits, launches and
+// counter writes for all the steps. The order between the groups is the
+// device-side one of the counters, so the threads need none among
+// themselves; each stream still receives its work in step order.
+static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride, int64_t n, int64_t* counts_out) {
+  struct Plan {
+    long long t;
+    int k, gen, tidx;
+    bool reset;
+    const double* poses;
+    long long* count_out;
+  };
+  ov_ctx* ctx = p->ctx;
+  const int ns = p->nsets;
+  std::vector<Plan> plan((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    Plan& pl = plan[(size_t)i];
+    pl.t = p->t + i;
+    pl.k = (int)(pl.t % ns);
+    const long long use = p->uses[pl.k]++;
+    pl.gen = (int)(use & 1);
+    pl.reset = use > 0;
+    p->gen[pl.k] = pl.gen;
+    const bool timed = p->timing > 0 && (pl.t - p->timing_t0) % p->timing == 0 && p->ntimed < (int)p->tb.size();
+    pl.tidx = timed ? p->ntimed++ : -1;
+    pl.poses = poses + pose_stride * i;
+    pl.count_out = counts_out ? (long long*)(counts_out + i) : nullptr;
+  }
+  const int after_group = p->after_group;
+  const long long after_value = p->after_value;
+  p->after_group = -1;
+  auto run_group = [&](int g) -> hipError_t {
+    hipError_t e = hipSetDevice(ctx->device);
+    hipStream_t s = p->st[g];
+    for (size_t i = 0; i < plan.size() && e == hipSuccess; ++i) {
+      const Plan& pl = plan[i];
+      if (g > 0)
+        e = hipStreamWaitValue64(s, p->seq + g - 1, (uint64_t)(pl.t + 1), hipStreamWaitValueGte, ~0ull);
+      else if (pl.t >= ns)
+        e = hipStreamWaitValue64(s, p->seq + ns - 1, (uint64_t)(pl.t + 1 - ns), hipStreamWaitValueGte, ~0ull);
+      if (g == 0 && i == 0 && after_group >= 0 && e == hipSuccess)
+        e = hipStreamWaitValue64(s, p->seq + after_group, (uint64_t)after_value, hipStreamWaitValueGte, ~0ull);
+      for (int stage = first_stage(p, g); stage < first_stage(p, g + 1) && e == hipSuccess; ++stage) {
+        const bool ts = pl.tidx >= 0 && stage == p->timed_stage;
+        if (ts) e = hipEventRecord(p->tb[pl.tidx], s);
+        if (e == hipSuccess)
+          e = stage_launch(p, pl.k, stage, pl.poses, s, stage == 2 ? pl.count_out : nullptr, pl.gen, pl.reset);
+        if (e == hipSuccess && ts) e = hipEventRecord(p->te[pl.tidx], s);
+      }
+      if (e == hipSuccess) e = hipStreamWriteValue64(s, p->seq + g, (uint64_t)(pl.t + 1), 0);
+    }
+    return e;
+  };
+  std::vector<hipError_t> err((size_t)ns, hipSuccess);
+  std::vector<std::thread> workers;
+  for (int g = 1; g < ns; ++g) workers.emplace_back([&, g] { err[(size_t)g] = run_group(g); });
+  err[0] = run_group(0);
+  for (auto& w : workers) w.join();
+  p->t += n;
+  for (hipError_t e : err)
+    if (e != hipSuccess) return hip_fail(ctx, e, "ov_pipe_submit_many");
+  return OV_OK;
+}
+
+int ov_pipe_set_threads(ov_pipe* p, int32_t on) {
+  if (!p || on < 0 || on > 1) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_threads: bad argument");
+  p->threads = on != 0;
+  return OV_OK;
+}
+
 int ov_pipe_submit_many(ov_pipe* p, const double* poses, int64_t pose_stride, int64_t n, int64_t* counts_out) {
   if (!p || !poses || n < 0 || pose_stride < 12 * (int64_t)p->ctx->grids.size())
     return pipe_fail(p, OV_EINVAL, "ov_pipe_submit_many: bad argument");
+  if (p->threads && p->nsets > 1 && !p->graphs && !(p->timing > 0 && p->timed_alone) && n > 1)
+    return submit_threaded(p, poses, pose_stride, n, counts_out);
   for (int64_t i = 0; i < n; ++i) {
     int rc = ov_pipe_submit(p, poses + pose_stride * i, counts_out ? counts_out + i : nullptr);
     if (rc != OV_OK) return rc;

@@ -125,8 +125,9 @@ __device__ __forceinline__ T det3(const T J[3][3]) {
          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
-// Newton's method from s = (1/2, 1/2, 1/2) for x(s) = query. Returns true when
-// the last step is <= tol (and, in FP64, |det J| >= kDetMin at the result).
+// Newton's method for x(s) = query from the s given (the cell's centre, or a
+// point carried over from a neighbouring cell). Returns true when the last
+// step is <= tol (and, in FP64, |det J| >= kDetMin at the result).
 // *cond receives ||J||_F ||J^-1||_F at the result (an upper bound of the
 // 2-norm condition number).
 // *inv_norm receives ||J^-1||_F at the result.
@@ -135,7 +136,6 @@ template <typename T>
 __device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullptr, int* iters = nullptr) {
   const T tol = sizeof(T) == 8 ? (T)kNewtonTol : (T)kNewtonTolF;
   const int maxit = sizeof(T) == 8 ? kNewtonMaxIt : kNewtonMaxItF;
-  s[0] = s[1] = s[2] = (T)0.5;
   for (int it = 0; it < maxit; ++it) {
     if (iters) ++*iters;
     T r[3], J[3][3];
@@ -184,6 +184,28 @@ __device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullp
   return false;
 }
 
+// Newton's start in the first cell of a walk: a point of [0, 1]^3, or (on =
+// false) the cell's centre. Passed by value, so that it stays in registers.
+struct Start {
+  double v[3];
+  bool on;
+};
+constexpr Start kCentre = {{0.5, 0.5, 0.5}, false};
+
+// A start from a solve's result: each component clamped to [0, 1] (a NaN
+// component, as a failed solve leaves, becomes 1/2).
+template <typename T>
+__device__ __forceinline__ Start start_from(const T s[3]) {
+  Start r;
+  r.on = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double v = (double)s[d];
+    r.v[d] = v == v ? fmin(fmax(v, 0.0), 1.0) : 0.5;
+  }
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ bool inside(const T s[3], T tol) {
   return s[0] >= -tol && s[0] <= (T)1 + tol && s[1] >= -tol && s[1] <= (T)1 + tol && s[2] >= -tol &&
@@ -197,26 +219,25 @@ __device__ __forceinline__ bool cell_valid(const GridDev& G, const uint8_t* fl, 
   return ok;
 }
 
-// The same test that first looks the corners' tiles up in the step's map of
-// tiles holding a hole (a few bytes that stay in cache): a cell none of whose
-// tiles holds a hole is valid without reading its 8 flag bytes (each on its
-// own line). th: the map of the step's slot (null: read the flags).
-__device__ __forceinline__ bool cell_valid_map(const GridDev& G, const uint8_t* fl, int ci, int cj, int ck,
-                                               const unsigned int* th, unsigned int stamp) {
-  if (th) {
-    bool hole_tile = false;
+// Whether a tile holding a corner of the cell holds a hole this step, from
+// the step's map of tiles holding a hole (a few bytes that stay in cache):
+// a cell none of whose tiles does is valid without reading its 8 flag bytes
+// (each on its own line). th: the map of the step's slot (null: true, the
+// flags decide).
+__device__ __forceinline__ bool corner_tiles_hold_hole(const GridDev& G, int ci, int cj, int ck,
+                                                       const unsigned int* th, unsigned int stamp) {
+  if (!th) return true;
+  bool hole_tile = false;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      int i = ci + (c & 1), j = cj + ((c >> 1) & 1), k = ck + ((c >> 2) & 1);
-      i = (i == G.ni) ? 0 : i;
-      j = (j == G.nj) ? 0 : j;
-      k = (k == G.nk) ? 0 : k;
-      hole_tile |= gp(th)[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] ==
-                   stamp;
-    }
-    if (!hole_tile) return true;
+  for (int c = 0; c < 8; ++c) {
+    int i = ci + (c & 1), j = cj + ((c >> 1) & 1), k = ck + ((c >> 2) & 1);
+    i = (i == G.ni) ? 0 : i;
+    j = (j == G.nj) ? 0 : j;
+    k = (k == G.nk) ? 0 : k;
+    hole_tile |= gp(th)[G.tile_off + (i >> 6) + (long long)G.tiles_i * ((j >> 3) + (long long)G.tiles_j * (k >> 3))] ==
+                 stamp;
   }
-  return cell_valid(G, fl, ci, cj, ck);
+  return hole_tile;
 }
 
 // The same test on flags already loaded (the walk fetches a cell's corner
@@ -251,13 +272,21 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
 // Stencil walk in precision T from `cell`. On kFound, cell/s hold the donor.
 // On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
 // perr bounds the error of each component of xi (FP32 only; 0 when exact).
+// s_init: Newton's start in the first cell.
 template <typename T>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
                     int max_walk, bool& limit, int& visited, int* iters = nullptr, const unsigned int* th = nullptr,
-                    unsigned int stamp = 0) {
+                    unsigned int stamp = 0, Start s_init = kCentre) {
   int ci, cj, ck;
   cell_ijk(G, cell, ci, cj, ck);
   int hist[4] = {-1, -1, -1, -1};  // the last cells visited: a revisit ends the walk
+  // Newton starts in the first cell from s_init (or its centre); in each
+  // later cell from the previous cell's s moved by the step taken (natural
+  // coordinates of neighbouring cells continue across their shared face),
+  // kept in [0, 1]
+  s[0] = s_init.on ? (T)s_init.v[0] : (T)0.5;
+  s[1] = s_init.on ? (T)s_init.v[1] : (T)0.5;
+  s[2] = s_init.on ? (T)s_init.v[2] : (T)0.5;
   for (int stepn = 0; stepn < max_walk; ++stepn) {
     ++visited;
     CellMap<T> m;
@@ -265,9 +294,13 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     // coordinates; FP32 (the large batched sizes, bound by the gathers'
     // lines): only the accepted cell's flags are read
     uint8_t cf[8];
+    bool hole_tile = true;
     if (sizeof(T) == 8) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) cf[c] = fl[corner_node(G, ci, cj, ck, c)];
+    } else {
+      // (issued with the corner loads; needed only if the cell is accepted)
+      hole_tile = corner_tiles_hold_hole(G, ci, cj, ck, th, stamp);
     }
     load_cell<T>(G, ci, cj, ck, xi, m);
     T cond = 0, inv_norm = 0;
@@ -292,7 +325,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
       const T es = (T)(1.7320508075688772 * (2.0 * perr + G.pf_err)) * inv_norm;
       if (sure && mg >= (T)kMixedMargin + es) {
         cell = here;
-        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid_map(G, fl, ci, cj, ck, th, stamp)) ? kFound : kToScan;
+        return (!hole_tile || cell_valid(G, fl, ci, cj, ck)) ? kFound : kToScan;
       }
       if (mg > -((sure ? (T)kMixedMargin : (T)kClearlyOutside) + es)) {
         cell = here;
@@ -301,7 +334,7 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     } else {
       if (conv && inside<T>(s, (T)kSTol)) {
         cell = here;
-        return (sizeof(T) == 8 ? corners_valid(cf) : cell_valid_map(G, fl, ci, cj, ck, th, stamp)) ? kFound : kToScan;
+        return (sizeof(T) == 8 ? corners_valid(cf) : (!hole_tile || cell_valid(G, fl, ci, cj, ck))) ? kFound : kToScan;
       }
     }
     if (!(s[0] == s[0] && s[1] == s[1] && s[2] == s[2])) return kToScan;
@@ -325,6 +358,9 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     const int next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
     hist[stepn & 3] = here;
     if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
+    s[0] = fmin(fmax(s[0] - (T)di, (T)0), (T)1);
+    s[1] = fmin(fmax(s[1] - (T)dj, (T)0), (T)1);
+    s[2] = fmin(fmax(s[2] - (T)dk, (T)0), (T)1);
     ci = ni;
     cj = nj;
     ck = nk;
@@ -499,7 +535,7 @@ __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp,
   if (sizeof(T) == 4 && r == kDoubt) {
     double s64[3], xe[3];
     exact_body(grids, sp, Q, B, xi, xe);
-    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, iters);
+    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, iters, nullptr, 0u, start_from<T>(s));
     s[0] = (T)s64[0];
     s[1] = (T)s64[1];
     s[2] = (T)s64[2];
@@ -508,9 +544,10 @@ __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp,
   return r;
 }
 
-// Warm-start history: per node, the donor (grid, cell) of its last query
-// and the low byte of the stamp of the step that wrote it, in one 8-byte
-// record. A node that was not a query in the last steps (one that just
+// Warm-start history: per node, the donor (grid, cell) of its last query,
+// its natural coordinates to 5 bits each (the next step's Newton start in
+// that cell) and the low byte of the stamp of the step that wrote it, in
+// one 8-byte record. A node that was not a query in the last steps (one that just
 // entered the buffer layer, say) would start its walk from a donor long out
 // of date; its entry is then ignored and the walk starts from the control
 // cell's seed.
@@ -521,16 +558,33 @@ struct Warm {
 };
 constexpr int kWarmMaxAge = 2;  // steps
 
-// The node's warm seed: grid (255: none) and cell.
-__device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t now, int& grid, int& cell) {
+// The node's warm seed: grid (255: none), cell and the Newton start there.
+__device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t now, int& grid, int& cell,
+                                          Start& s0) {
   grid = 255;
   cell = -1;
+  s0 = kCentre;
   if (!w.use) return;
   const unsigned long long r = gp(w.rec)[key];
   const uint8_t age = (uint8_t)(now - (uint8_t)(r >> 40));
   if (age > kWarmMaxAge) return;
   grid = (int)((r >> 32) & 0xFF);
   cell = (int)(uint32_t)r;
+  const unsigned int b = (unsigned int)(r >> 48);
+  s0.on = true;
+  s0.v[0] = (double)(b & 31u) * (1.0 / 31.0);
+  s0.v[1] = (double)((b >> 5) & 31u) * (1.0 / 31.0);
+  s0.v[2] = (double)((b >> 10) & 31u) * (1.0 / 31.0);
+}
+
+// s to 5 bits per component (nearest of 0, 1/31, ..., 1; a NaN as 1/2).
+template <typename T>
+__device__ __forceinline__ unsigned long long warm_s_bits(const T s[3]) {
+  const Start v = start_from<T>(s);
+  unsigned long long b = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) b |= (unsigned long long)(unsigned int)rint(v.v[d] * 31.0) << (5 * d);
+  return b << 48;
 }
 
 template <typename T>
@@ -544,7 +598,7 @@ __device__ __forceinline__ void write_result(long long q, long long cap, long lo
   s_out[cap + q] = s[1];
   s_out[2 * cap + q] = s[2];
   warm.rec[key] = (unsigned long long)(uint32_t)cell | ((unsigned long long)(grid < 0 ? 255u : (unsigned)grid) << 32) |
-                  ((unsigned long long)now << 40);
+                  ((unsigned long long)now << 40) | warm_s_bits<T>(s);
 }
 
 // Markers left in donor_grid between the passes of one search call; status
@@ -578,11 +632,13 @@ __global__ void __launch_bounds__(256)
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
     bool limit = false;
     int visited = 0, defer = 0, defer_t = 0;
+    T s[3] = {(T)NAN, (T)NAN, (T)NAN};
     if (!Q.finite) {
       atomicOr(dev_status, OV_DEV_NONFINITE);
     } else {
       int wg, wc;
-      warm_read(warm, Q.key, now, wg, wc);
+      Start ws;
+      warm_read(warm, Q.key, now, wg, wc, ws);
       for (int t = -2; t < ngrids; ++t) {
         const int B = candidate_at(t, Q.A, Q.first);
         if (B < 0) continue;
@@ -595,8 +651,8 @@ __global__ void __launch_bounds__(256)
         if (wg == B && wc >= 0 && (long long)wc < G.ncells) seed = wc;
         if (seed < 0 && rep < 0) continue;  // no cell reaches this control cell
         int cell = seed >= 0 ? seed : rep;
-        T s[3];
-        int r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
+        int r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited, nullptr, nullptr, 0u,
+                        seed >= 0 ? ws : kCentre);
         if (r == kToScan && seed >= 0 && rep >= 0 && rep != seed) {
           cell = rep;  // a second start before the brute-force scan
           r = walk<T>(G, flags + G.node_off, xi, Q.err, cell, s, max_walk, limit, visited);
@@ -621,6 +677,11 @@ __global__ void __launch_bounds__(256)
       donor_grid[q] = defer;
       donor_cell[q] = res_cell;
       status[q] = defer_status(defer_t, visited);
+      if (defer == kDeferFix) {  // the FP32 solve's s: the FP64 correction's start
+        s_out[q] = s[0];
+        s_out[cap + q] = s[1];
+        s_out[2 * cap + q] = s[2];
+      }
     } else {
       write_result<T>(q, cap, Q.key, res_grid, res_cell, res_status | (min(visited, 255) << 8), rs, donor_grid,
                       donor_cell, s_out, status, warm, now);
@@ -655,7 +716,9 @@ __global__ void __launch_bounds__(256)
     body_frame(sp + 12 * B, Q.x, xi);
     int cell = donor_cell[q];
     bool limit = false;
-    const int r = walk<double>(G, flags + G.node_off, xi, 0.0, cell, s64, max_walk, limit, visited);
+    const float sf0[3] = {s_out[q], s_out[cap + q], s_out[2 * cap + q]};
+    const int r = walk<double>(G, flags + G.node_off, xi, 0.0, cell, s64, max_walk, limit, visited, nullptr, nullptr,
+                               0u, start_from<float>(sf0));
     if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
     if (r == kFound) {
       const float sf[3] = {(float)s64[0], (float)s64[1], (float)s64[2]};
@@ -708,6 +771,7 @@ __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, cons
       if (!hull_excludes(P, xi)) {
         CellMap<double> m;
         map_from_corners<double>(P, xi, m);
+        s[0] = s[1] = s[2] = 0.5;
         hit = newton<double>(m, s, nullptr, nullptr, iters) && inside<double>(s, kSTol) && cell_valid(G, fl, ci, cj, ck);
       }
     }
@@ -737,6 +801,49 @@ __device__ int scan_control_cell_block(const GridDev& G, const uint8_t* fl, cons
     }
     __syncthreads();  // S is reused by the next round or call
     if (found >= 0) return found;
+  }
+  return -1;
+}
+
+// The same scan by one wavefront: 64 candidates per round; the first hit in
+// list order (the lowest cell index) is taken from its lane by shuffles, so
+// the wavefront needs no barrier and no shared memory.
+__device__ int scan_control_cell_wave(const GridDev& G, const uint8_t* fl, const double xi[3], double s_best[3],
+                                      int* cands = nullptr, int* iters = nullptr) {
+  const int lane = threadIdx.x & 63;
+  long long e0, e1;
+  gmem<int>* list = gp(control_list(G, xi, e0, e1));
+  int next = e0 + lane < e1 ? list[e0 + lane] : -1;
+  for (long long base = e0; base < e1; base += 64) {
+    const long long e = base + lane;
+    const int cell = next;
+    next = e + 64 < e1 ? list[e + 64] : -1;
+    bool hit = false;
+    double s[3] = {0.0, 0.0, 0.0};
+    if (e < e1) {
+      if (cands) ++*cands;
+      int ci, cj, ck;
+      cell_ijk(G, cell, ci, cj, ck);
+      double P[8][3];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        load_xyz(G, corner_node(G, ci, cj, ck, c), P[c][0], P[c][1], P[c][2]);
+      }
+      if (!hull_excludes(P, xi)) {
+        CellMap<double> m;
+        map_from_corners<double>(P, xi, m);
+        s[0] = s[1] = s[2] = 0.5;
+        hit = newton<double>(m, s, nullptr, nullptr, iters) && inside<double>(s, kSTol) && cell_valid(G, fl, ci, cj, ck);
+      }
+    }
+    const unsigned long long hits = __ballot(hit);
+    if (hits) {  // (the same in every lane)
+      const int first = __ffsll((long long)hits) - 1;
+      s_best[0] = __shfl(s[0], first, 64);
+      s_best[1] = __shfl(s[1], first, 64);
+      s_best[2] = __shfl(s[2], first, 64);
+      return __shfl(cell, first, 64);
+    }
   }
   return -1;
 }
@@ -855,6 +962,66 @@ struct DeferQueue {
 // list_q[d] of thread list_owner[d] with deferral status list_st[d]; the
 // owner thread receives the result. The same rules as the scan pass of the
 // search call.
+// One deferred query (position t0 of its candidate list, `dvisited` cells
+// walked so far), taken by every thread of the group that scans: the exact
+// position in FP64; in the grid of position t0 the brute-force scan of the
+// control cell; in later grids a walk from the control cell's seed, and the
+// scan if the walk fails. The first grid with a valid containing cell is
+// the donor. WAVE: the scans run on one wavefront (else the whole block).
+template <typename T, bool WAVE>
+__device__ __forceinline__ void deferred_scan_one(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                                  const uint8_t* __restrict__ flags, int A, int qm, int st,
+                                                  ScanLds& S, int max_walk, int& g_grid, int& g_cell,
+                                                  int& g_status, T gs[3], int& dvisited, bool& dlimit,
+                                                  int& walk_iters, int& my_iters, int& my_cands) {
+  const int t0 = (st & 255) - 2;
+  dvisited = (st >> 8) & 255;
+  T o[3] = {0, 0, 0};
+  if (sizeof(T) == 8) transform_node<T>(grids[A], sp + 12 * A, qm, o);  // (FP32: the exact position)
+  const Query Q = make_query<T>(grids, ngrids, sp, flags, A, qm, (double)o[0], (double)o[1], (double)o[2], true);
+  g_grid = -1;
+  g_cell = -1;
+  g_status = OV_Q_ORPHAN;
+  gs[0] = gs[1] = gs[2] = (T)NAN;
+  for (int t = t0; t < ngrids; ++t) {
+    const int B = candidate_at(t, Q.A, Q.first);
+    if (B < 0) continue;
+    const GridDev& G = grids[B];
+    double xi[3];
+    if (t == t0) body_frame(sp + 12 * B, Q.x, xi);
+    else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+    const uint8_t* fl = flags + G.node_off;
+    int cell = -1, how = OV_Q_FALLBACK;
+    T s[3];
+    bool walked = false;
+    if (t != t0) {
+      int seed = gp(G.brep)[bin_of(G, xi)];
+      if (seed < 0) continue;
+      cell = seed;
+      how = OV_Q_FOUND;
+      walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited, &walk_iters) == kFound;
+    }
+    if (!walked) {
+      double s64[3];
+      cell = WAVE ? scan_control_cell_wave(G, fl, xi, s64, &my_cands, &my_iters)
+                  : scan_control_cell_block(G, fl, xi, s64, S, &my_cands, &my_iters);
+      s[0] = (T)s64[0];
+      s[1] = (T)s64[1];
+      s[2] = (T)s64[2];
+      how = OV_Q_FALLBACK;
+    }
+    if (cell >= 0) {
+      g_grid = B;
+      g_cell = cell;
+      g_status = how;
+      gs[0] = s[0];
+      gs[1] = s[1];
+      gs[2] = s[2];
+      break;
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void block_deferred_scans(const GridDev* __restrict__ grids, int ngrids, const double* sp,
                                                      const uint8_t* __restrict__ flags,
@@ -868,54 +1035,11 @@ __device__ __forceinline__ void block_deferred_scans(const GridDev* __restrict__
     // every thread takes the deferred query (same values in all lanes)
     const int owner = list_owner[d];
     const long long qd = list_q[d];
-    const int st = list_st[d];
-    const int t0 = (st & 255) - 2;
-    int dvisited = (st >> 8) & 255;
-    const int A = q_grid[qd];
-    T o[3] = {0, 0, 0};
-    if (sizeof(T) == 8) transform_node<T>(grids[A], sp + 12 * A, q_node[qd], o);  // (FP32: the exact position)
-    const Query Q =
-        make_query<T>(grids, ngrids, sp, flags, A, q_node[qd], (double)o[0], (double)o[1], (double)o[2], true);
-    int g_grid = -1, g_cell = -1, g_status = OV_Q_ORPHAN;
-    T gs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    int g_grid, g_cell, g_status, dvisited, walk_iters = 0;  // (walk work counted once, by the owner)
+    T gs[3];
     bool dlimit = false;
-    int walk_iters = 0;  // (the same in every thread: counted once, by the owner)
-    for (int t = t0; t < ngrids; ++t) {
-      const int B = candidate_at(t, Q.A, Q.first);
-      if (B < 0) continue;
-      const GridDev& G = grids[B];
-      double xi[3];
-      if (t == t0) body_frame(sp + 12 * B, Q.x, xi);
-      else if (!to_body(G, sp + 12 * B, Q, xi)) continue;
-      const uint8_t* fl = flags + G.node_off;
-      int cell = -1, how = OV_Q_FALLBACK;
-      T s[3];
-      bool walked = false;
-      if (t != t0) {
-        int seed = gp(G.brep)[bin_of(G, xi)];
-        if (seed < 0) continue;
-        cell = seed;
-        how = OV_Q_FOUND;
-        walked = walk_grid<T>(grids, sp, Q, B, fl, xi, cell, s, max_walk, dlimit, how, dvisited, &walk_iters) == kFound;
-      }
-      if (!walked) {
-        double s64[3];
-        cell = scan_control_cell_block(G, fl, xi, s64, S, &my_cands, &my_iters);
-        s[0] = (T)s64[0];
-        s[1] = (T)s64[1];
-        s[2] = (T)s64[2];
-        how = OV_Q_FALLBACK;
-      }
-      if (cell >= 0) {
-        g_grid = B;
-        g_cell = cell;
-        g_status = how;
-        gs[0] = s[0];
-        gs[1] = s[1];
-        gs[2] = s[2];
-        break;
-      }
-    }
+    deferred_scan_one<T, false>(grids, ngrids, sp, flags, q_grid[qd], q_node[qd], list_st[d], S, max_walk, g_grid,
+                                g_cell, g_status, gs, dvisited, dlimit, walk_iters, my_iters, my_cands);
     if ((int)threadIdx.x == owner) {
       res_grid = g_grid;
       res_cell = g_cell;
@@ -971,29 +1095,23 @@ __device__ __forceinline__ void add_work_counters(unsigned long long* stats, uns
   }
 }
 
-// Occupancy asked of the back kernels: with the cold paths in a second
-// kernel, the FP32 walk fits three wavefronts per SIMD (168 VGPRs).
-template <typename T, bool SPLIT>
-struct BackWaves {
-  static constexpr int value = (SPLIT && sizeof(T) == 4) ? 3 : 1;
+// Occupancy asked of the walk kernel of the two-kernel back half: with the
+// cold paths in the second kernel, the FP32 walk fits three wavefronts per
+// SIMD (168 VGPRs).
+template <typename T>
+struct WalkWaves {
+  static constexpr int value = sizeof(T) == 4 ? 3 : 1;
 };
 
-// The whole back half of a step in one kernel (the step executors' form of
-// the transform, the three search passes and the interpolation). Each block
-// takes BS (64, 128 or 256) queries at a time, one per thread: the transform;
-// the walk over the candidate grids, with the FP64 correction of an
-// undecided FP32 walk done at once by its lane; then the block's deferred
-// queries one at a time with all its threads, as in the scan pass; then each
-// thread writes its result and interpolates its fields. Every rule that
-// orders candidates, seeds and deferrals is the one of the separate passes,
-// so the results are the same bit for bit.
-// SPLIT: the first of two kernels. A query FP32 cannot decide, or whose walk
-// fails, goes to the deferral queue (its state in its outputs) for
-// k_back_defer instead of being corrected or scanned here: this kernel then
-// holds only the walk's registers.
-template <typename T, int BS, bool SPLIT>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWaves<T, SPLIT>::value)))
-    k_back(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
+// The first kernel of the two-kernel back half (OV_OPT_BACK_FUSED = 2). Each
+// block takes BS (64, 128 or 256) queries at a time, one per thread: the
+// transform and the walk over the candidate grids. A query FP32 cannot
+// decide, or whose walk fails, goes to the deferral queue (its state in its
+// outputs) for k_back_defer; every other thread writes its result and
+// interpolates its fields. The kernel holds only the walk's registers.
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWaves<T>::value)))
+    k_back_walk(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
            const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid, const int32_t* __restrict__ q_node,
            T* __restrict__ qx, const long long* __restrict__ d_count, long long cap,
            int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell, T* __restrict__ s_out,
@@ -1003,10 +1121,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
            long long* __restrict__ count_out, unsigned long long* __restrict__ stats,
            const unsigned int* __restrict__ tile_hole, DeferQueue dq, int xcd_run) {
   __shared__ double sp[kMaxGrids * 12];
-  __shared__ int list_owner[SPLIT ? 1 : BS], list_st[SPLIT ? 1 : BS];
-  __shared__ long long list_q[SPLIT ? 1 : BS];
-  __shared__ int nlist;
-  __shared__ ScanLds S;
   // the grid table, staged in LDS (dynamic: ngrids records): its fields are
   // read at every candidate grid and walk
   extern __shared__ unsigned long long grid_lds[];
@@ -1015,18 +1129,18 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
     grid_lds[i] = ((const unsigned long long*)grids_g)[i];
   const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
-  // this thread's first query, read before the count is known (entries up
-  // to the capacity are allocated): one memory round trip less on every
-  // query's path
   // the block's position in each round of chunks: with xcd_run > 0 the
   // blocks of one XCD take runs of consecutive chunks, whose queries are
   // neighbours on the grids and share donor-cell lines in that XCD's L2
   const long long brank = xcd_rank(blockIdx.x, gridDim.x, xcd_run);
+  // the ids of this thread's query in the block's next chunk, loaded one
+  // chunk ahead (the first before the count is known: entries up to the
+  // capacity are allocated), so that a chunk starts with them in registers
   const long long q_first = brank * blockDim.x + threadIdx.x;
-  int first_A = 0, first_m = 0;
+  int cur_A = 0, cur_m = 0;
   if (q_first < cap) {
-    first_A = q_grid[q_first];
-    first_m = q_node[q_first];
+    cur_A = q_grid[q_first];
+    cur_m = q_node[q_first];
   }
   const unsigned int stamp = *warm.stamp;
   const uint8_t now = (uint8_t)stamp;
@@ -1034,39 +1148,44 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (count_out) *count_out = *d_count;
     atomicAdd(&stat_slot(stats)[OV_STAT_BACK_CALLS], 1ULL);
-    if (SPLIT) dq.count[(stamp & 1u) ^ 1u] = 0u;  // the other step's counter (its reader is done)
+    dq.count[(stamp & 1u) ^ 1u] = 0u;  // the other step's counter (its reader is done)
     if (dq.chunk) dq.chunk[(stamp & 1u) ^ 1u] = 0u;
   }
-  unsigned int* const dq_count = SPLIT ? dq.count + (stamp & 1u) : nullptr;
+  unsigned int* const dq_count = dq.count + (stamp & 1u);
   unsigned int* const chunk_head = dq.chunk ? dq.chunk + (stamp & 1u) : nullptr;
   __shared__ long long next_base;
   int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
   for (long long base = brank * blockDim.x; base < n;) {
-    if (!SPLIT) {
-      if (threadIdx.x == 0) nlist = 0;
-    }
     unsigned int ticket = 0;  // the block's next chunk (work queue), in flight during this one
     if (chunk_head && threadIdx.x == 0) ticket = atomicAdd(chunk_head, 1u);
     __syncthreads();  // (also orders the pose staging before the first use)
     const long long q = base + threadIdx.x;
     const bool mine = q < n;
+    // the next chunk's ids (fixed stride: its base is known now; work queue:
+    // once the ticket is shared at the end of the chunk)
+    int nxt_A = 0, nxt_m = 0;
+    long long nbase = base + (long long)gridDim.x * blockDim.x;
+    if (!chunk_head && nbase + threadIdx.x < cap) {
+      nxt_A = q_grid[nbase + threadIdx.x];
+      nxt_m = q_node[nbase + threadIdx.x];
+    }
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
     int visited = 0;
     bool limit = false;
     long long key = 0;
     int my_grid = 0;
-    int defer = 0;  // SPLIT: kDeferFix or kDeferScan
+    int defer = 0;  // kDeferFix or kDeferScan
     int defer_t = 0, defer_cell = -1;
     if (mine) {
-      const bool first = base == brank * blockDim.x;
-      const int A = first ? first_A : q_grid[q];
-      const int qm = first ? first_m : q_node[q];
+      const int A = cur_A;
+      const int qm = cur_m;
       my_grid = A;
       // the warm-start entry, read beside the node's coordinates
       int wg, wcell;
-      warm_read(warm, grids[A].node_off + qm, now, wg, wcell);
+      Start ws;
+      warm_read(warm, grids[A].node_off + qm, now, wg, wcell, ws);
       T o[3];
       transform_node<T>(grids[A], sp + 12 * A, qm, o);
       qx[q] = o[0];
@@ -1095,7 +1214,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
           int cell = seed >= 0 ? seed : rep;
           T s[3];
           const uint8_t* fl = flags + G.node_off;
-          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp);
+          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp,
+                          seed >= 0 ? ws : kCentre);
           if (r == kToScan && seed >= 0) {
             rep = gp(G.brep)[bin_of(G, xi)];
             if (rep >= 0 && rep != seed) {
@@ -1103,29 +1223,19 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
               r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp);
             }
           }
-          int how = OV_Q_FOUND;
           if (sizeof(T) == 4 && r == kDoubt) {
-            if (SPLIT) {
-              defer = kDeferFix;
-              defer_t = t;
-              defer_cell = cell;
-              break;
-            }
-            // the FP64 correction: the walk goes on from this cell in FP64
-            // on the exact position
-            const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
-            double xe[3], s64[3];
-            body_frame(sp + 12 * B, QE.x, xe);
-            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters);
-            s[0] = (T)s64[0];
-            s[1] = (T)s64[1];
-            s[2] = (T)s64[2];
-            how = OV_Q_FOUND | OV_Q_FP64_FIXED;
+            defer = kDeferFix;
+            defer_t = t;
+            defer_cell = cell;
+            rs[0] = s[0];  // the FP32 solve's s: the FP64 correction's start
+            rs[1] = s[1];
+            rs[2] = s[2];
+            break;
           }
           if (r == kFound) {
             res_grid = B;
             res_cell = cell;
-            res_status = how;
+            res_status = OV_Q_FOUND;
             rs[0] = s[0];
             rs[1] = s[1];
             rs[2] = s[2];
@@ -1137,14 +1247,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
           break;
         }
       }
-      if (!SPLIT && defer) {
-        const int slot = atomicAdd(&nlist, 1);
-        list_owner[slot] = (int)threadIdx.x;
-        list_q[slot] = q;
-        list_st[slot] = defer_status(defer_t, visited);
-      }
     }
-    if (SPLIT) {
+    {
       // the wavefront's deferred queries go to the queue with one atomic
       const unsigned long long dm = __ballot(mine && defer != 0);
       if (dm) {
@@ -1158,28 +1262,222 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BackWav
           donor_grid[q] = defer;
           donor_cell[q] = defer_cell;
           status[q] = defer_status(defer_t, visited);
+          if (defer == kDeferFix) {
+            s_out[q] = rs[0];
+            s_out[cap + q] = rs[1];
+            s_out[2 * cap + q] = rs[2];
+          }
         }
       }
-    } else {
-      __syncthreads();
-      block_deferred_scans<T>(grids, ngrids, sp, flags, q_grid, q_node, nlist, list_owner, list_q, list_st, S,
-                              max_walk, res_grid, res_cell, res_status, rs, visited, limit, my_iters, my_cands);
     }
     if (mine) {
       my_cells += visited;
       if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
-      if (!(SPLIT && defer))
+      if (!defer)
         finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
                         donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
     }
     if (chunk_head) {
       if (threadIdx.x == 0) next_base = ((long long)gridDim.x + ticket) * blockDim.x;
-      __syncthreads();  // (also: nlist and the list are rebuilt for the next range)
-      base = next_base;
-    } else {
-      base += (long long)gridDim.x * blockDim.x;
-      if (!SPLIT) __syncthreads();  // nlist and the list are rebuilt for the next range
+      __syncthreads();
+      nbase = next_base;
+      if (nbase + threadIdx.x < cap) {
+        nxt_A = q_grid[nbase + threadIdx.x];
+        nxt_m = q_node[nbase + threadIdx.x];
+      }
     }
+    base = nbase;
+    cur_A = nxt_A;
+    cur_m = nxt_m;
+  }
+  add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
+}
+
+// The whole back half of a step in one kernel, each wavefront on its own: it
+// takes 64 queries at a time, one per lane (by a fixed stride over all the
+// launch's wavefronts, or from the work queue): the transform; the walk over
+// the candidate grids, with the FP64 correction of an undecided FP32 walk
+// done at once by its lane; then the wavefront's deferred queries one at a
+// time with all its lanes (the brute-force scans); then each lane writes its
+// result and interpolates its fields. No barrier: a wavefront never waits
+// for another. Every rule that orders candidates, seeds and deferrals is the
+// one of the separate passes, so the results are the same bit for bit.
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS)
+    k_back_wave(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
+                const uint8_t* __restrict__ flags, const int32_t* __restrict__ q_grid,
+                const int32_t* __restrict__ q_node, T* __restrict__ qx, const long long* __restrict__ d_count,
+                long long cap, int32_t* __restrict__ donor_grid, int32_t* __restrict__ donor_cell,
+                T* __restrict__ s_out, int32_t* __restrict__ status, Warm warm, int max_walk,
+                int32_t* __restrict__ dev_status, const T* __restrict__ fields, long long total_nodes,
+                int interleaved, int frame_velocity, T* __restrict__ out, long long* __restrict__ count_out,
+                unsigned long long* __restrict__ stats, const unsigned int* __restrict__ tile_hole, DeferQueue dq,
+                int xcd_run) {
+  __shared__ double sp[kMaxGrids * 12];
+  __shared__ ScanLds S;  // (unused: the wavefront scans need none)
+  // the grid table, staged in LDS (dynamic: ngrids records): its fields are
+  // read at every candidate grid and walk
+  extern __shared__ unsigned long long grid_lds[];
+  static_assert(sizeof(GridDev) % 8 == 0, "grid records are staged in 8-byte words");
+  for (int i = threadIdx.x; i < ngrids * (int)(sizeof(GridDev) / 8); i += blockDim.x)
+    grid_lds[i] = ((const unsigned long long*)grids_g)[i];
+  const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
+  for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
+  const int lane = threadIdx.x & 63;
+  constexpr int kWaves = BS / 64;
+  // this wavefront's rank among the launch's: with xcd_run > 0 the blocks of
+  // one XCD take runs of consecutive chunks, whose queries are neighbours on
+  // the grids and share donor-cell lines in that XCD's L2
+  const long long wrank = xcd_rank(blockIdx.x, gridDim.x, xcd_run) * kWaves + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * kWaves;
+  // the ids of this lane's query in the wavefront's next chunk, loaded one
+  // chunk ahead (the first before the count is known: entries up to the
+  // capacity are allocated)
+  int cur_A = 0, cur_m = 0;
+  if (wrank * 64 + lane < cap) {
+    cur_A = q_grid[wrank * 64 + lane];
+    cur_m = q_node[wrank * 64 + lane];
+  }
+  const unsigned int stamp = *warm.stamp;
+  const uint8_t now = (uint8_t)stamp;
+  const long long n = min(*d_count, cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (count_out) *count_out = *d_count;
+    atomicAdd(&stat_slot(stats)[OV_STAT_BACK_CALLS], 1ULL);
+    if (dq.chunk) dq.chunk[(stamp & 1u) ^ 1u] = 0u;  // the other step's head (its reader is done)
+  }
+  unsigned int* const chunk_head = dq.chunk ? dq.chunk + (stamp & 1u) : nullptr;
+  __syncthreads();  // the staging is complete
+  int my_iters = 0, my_cands = 0;  // this lane's share of the work (walk cells: `visited` of its queries)
+  unsigned int my_cells = 0;
+  for (long long base = wrank * 64; base < n;) {
+    // the wavefront's next chunk (work queue: its ticket, in flight during
+    // this chunk)
+    unsigned int ticket = 0;
+    if (chunk_head && lane == 0) ticket = atomicAdd(chunk_head, 1u);
+    const long long q = base + lane;
+    const bool mine = q < n;
+    int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
+    T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
+    int visited = 0;
+    bool limit = false;
+    long long key = 0;
+    int my_grid = 0;
+    int defer_st = 0;
+    bool defer = false;
+    if (mine) {
+      const int A = cur_A;
+      const int qm = cur_m;
+      my_grid = A;
+      // the warm-start entry, read beside the node's coordinates
+      int wg, wcell;
+      Start ws;
+      warm_read(warm, grids[A].node_off + qm, now, wg, wcell, ws);
+      T o[3];
+      transform_node<T>(grids[A], sp + 12 * A, qm, o);
+      qx[q] = o[0];
+      qx[cap + q] = o[1];
+      qx[2 * cap + q] = o[2];
+      const Query Q = make_query<T>(grids, ngrids, sp, flags, A, qm, (double)o[0], (double)o[1], (double)o[2], false);
+      key = Q.key;
+      if (!Q.finite) {
+        atomicOr(dev_status, OV_DEV_NONFINITE);
+      } else {
+        for (int t = -2; t < ngrids; ++t) {
+          const int B = candidate_at(t, Q.A, Q.first);
+          if (B < 0) continue;
+          const GridDev& G = grids[B];
+          double xi[3];
+          if (!to_body(G, sp + 12 * B, Q, xi)) continue;
+          int seed = -1;
+          if (wg == B && wcell >= 0 && (long long)wcell < G.ncells) seed = wcell;
+          // the control cell's seed only when there is no warm seed, or
+          // for the second walk after a failed warm one
+          int rep = -1;
+          if (seed < 0) {
+            rep = gp(G.brep)[bin_of(G, xi)];
+            if (rep < 0) continue;
+          }
+          int cell = seed >= 0 ? seed : rep;
+          T s[3];
+          const uint8_t* fl = flags + G.node_off;
+          int r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp,
+                          seed >= 0 ? ws : kCentre);
+          if (r == kToScan && seed >= 0) {
+            rep = gp(G.brep)[bin_of(G, xi)];
+            if (rep >= 0 && rep != seed) {
+              cell = rep;
+              r = walk<T>(G, fl, xi, Q.err, cell, s, max_walk, limit, visited, &my_iters, tile_hole, stamp);
+            }
+          }
+          int how = OV_Q_FOUND;
+          if (sizeof(T) == 4 && r == kDoubt) {
+            // the FP64 correction: the walk goes on from this cell in FP64
+            // on the exact position
+            const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
+            double xe[3], s64[3];
+            body_frame(sp + 12 * B, QE.x, xe);
+            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters, nullptr, 0u,
+                             start_from<T>(s));
+            s[0] = (T)s64[0];
+            s[1] = (T)s64[1];
+            s[2] = (T)s64[2];
+            how = OV_Q_FOUND | OV_Q_FP64_FIXED;
+          }
+          if (r == kFound) {
+            res_grid = B;
+            res_cell = cell;
+            res_status = how;
+            rs[0] = s[0];
+            rs[1] = s[1];
+            rs[2] = s[2];
+          } else {
+            defer = true;
+            defer_st = defer_status(t, visited);
+          }
+          break;
+        }
+      }
+    }
+    // the next chunk's base, and its ids (fixed stride; or the ticket, which
+    // has long arrived)
+    long long nbase = base + nwaves * 64;
+    if (chunk_head) nbase = (nwaves + (long long)__shfl((int)ticket, 0, 64)) * 64;
+    int nxt_A = 0, nxt_m = 0;
+    if (nbase + lane < cap) {
+      nxt_A = q_grid[nbase + lane];
+      nxt_m = q_node[nbase + lane];
+    }
+    // the wavefront's deferred queries, one at a time with all its lanes
+    for (unsigned long long dm = __ballot(defer); dm; dm &= dm - 1) {
+      const int owner = __ffsll((long long)dm) - 1;
+      int g_grid, g_cell, g_status, dvisited, walk_iters = 0;  // (walk work counted once, by the owner)
+      T gs[3];
+      bool dlimit = false;
+      deferred_scan_one<T, true>(grids, ngrids, sp, flags, __shfl(cur_A, owner, 64), __shfl(cur_m, owner, 64),
+                                 __shfl(defer_st, owner, 64), S, max_walk, g_grid, g_cell, g_status, gs, dvisited,
+                                 dlimit, walk_iters, my_iters, my_cands);
+      if (lane == owner) {
+        res_grid = g_grid;
+        res_cell = g_cell;
+        res_status = g_status;
+        rs[0] = gs[0];
+        rs[1] = gs[1];
+        rs[2] = gs[2];
+        visited = dvisited;
+        limit |= dlimit;
+        my_iters += walk_iters;
+      }
+    }
+    if (mine) {
+      my_cells += visited;
+      if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
+      finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
+                      donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
+    }
+    base = nbase;
+    cur_A = nxt_A;
+    cur_m = nxt_m;
   }
   add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
 }
@@ -1246,7 +1544,9 @@ __global__ void __launch_bounds__(BS)
         const GridDev& G = grids[B];
         double xe[3], s64[3];
         body_frame(sp + 12 * B, QE.x, xe);
-        const int r = walk<double>(G, flags + G.node_off, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters);
+        const T sq[3] = {s_out[q], s_out[cap + q], s_out[2 * cap + q]};
+        const int r = walk<double>(G, flags + G.node_off, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters,
+                                   nullptr, 0u, start_from<T>(sq));
         if (r == kFound) {
           res_grid = B;
           res_cell = cell;
@@ -1330,20 +1630,20 @@ static void launch_back_t(ov_ctx* ctx, const double* poses, const uint8_t* flags
   const size_t lds = sizeof(GridDev) * ctx->grids.size();
   const dim3 g((unsigned)grid);
   if (!split) {
-    if (bs == 64) hipLaunchKernelGGL((k_back<T, 64, false>), g, dim3(64), lds, st, OV_BACK_ARGS);
-    else if (bs == 128) hipLaunchKernelGGL((k_back<T, 128, false>), g, dim3(128), lds, st, OV_BACK_ARGS);
-    else hipLaunchKernelGGL((k_back<T, 256, false>), g, dim3(256), lds, st, OV_BACK_ARGS);
+    if (bs == 64) hipLaunchKernelGGL((k_back_wave<T, 64>), g, dim3(64), lds, st, OV_BACK_ARGS);
+    else if (bs == 128) hipLaunchKernelGGL((k_back_wave<T, 128>), g, dim3(128), lds, st, OV_BACK_ARGS);
+    else hipLaunchKernelGGL((k_back_wave<T, 256>), g, dim3(256), lds, st, OV_BACK_ARGS);
   } else {
     // the second kernel: usually a few queries; as many blocks as CUs
     const dim3 gd((unsigned)std::max(1LL, std::min((long long)ctx->num_cus, (capacity + bs - 1) / bs)));
     if (bs == 64) {
-      hipLaunchKernelGGL((k_back<T, 64, true>), g, dim3(64), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_walk<T, 64>), g, dim3(64), lds, st, OV_BACK_ARGS);
       hipLaunchKernelGGL((k_back_defer<T, 64>), gd, dim3(64), lds, st, OV_DEFER_ARGS);
     } else if (bs == 128) {
-      hipLaunchKernelGGL((k_back<T, 128, true>), g, dim3(128), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_walk<T, 128>), g, dim3(128), lds, st, OV_BACK_ARGS);
       hipLaunchKernelGGL((k_back_defer<T, 128>), gd, dim3(128), lds, st, OV_DEFER_ARGS);
     } else {
-      hipLaunchKernelGGL((k_back<T, 256, true>), g, dim3(256), lds, st, OV_BACK_ARGS);
+      hipLaunchKernelGGL((k_back_walk<T, 256>), g, dim3(256), lds, st, OV_BACK_ARGS);
       hipLaunchKernelGGL((k_back_defer<T, 256>), gd, dim3(256), lds, st, OV_DEFER_ARGS);
     }
   }
