@@ -119,6 +119,23 @@ __device__ __forceinline__ void map_and_jacobian(const CellMap<T>& m, const T s[
   }
 }
 
+// 1 / x for Newton's update: the hardware reciprocal (FP32: within 1 ulp),
+// in FP64 refined by two Newton-Raphson steps r <- r + r (1 - x r), each of
+// which squares the relative error. Newton's iteration needs no correctly
+// rounded quotient, and this is a shorter dependent chain than a division.
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+
 template <typename T>
 __device__ __forceinline__ T det3(const T J[3][3]) {
   return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
@@ -145,7 +162,7 @@ __device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullp
                 J[0][1] * J[1][2] - J[1][1] * J[0][2]};
     T det = J[0][0] * c12[0] + J[1][0] * c12[1] + J[2][0] * c12[2];
     if (det == (T)0) return false;
-    T inv = (T)1 / det;
+    const T inv = recip<T>(det);
     T d0 = (r[0] * c12[0] + r[1] * c12[1] + r[2] * c12[2]) * inv;
     // column 1 replaced by r: det[J0, r, J2] = J0 . (r x J2)
     T rx2[3] = {r[1] * J[2][2] - r[2] * J[1][2], r[2] * J[0][2] - r[0] * J[2][2], r[0] * J[1][2] - r[1] * J[0][2]};
@@ -175,8 +192,9 @@ __device__ bool newton(const CellMap<T>& m, T s[3], T* cond, T* inv_norm = nullp
             T cf = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
             na += cf * cf;
           }
-        *cond = sqrt(nj) * sqrt(na) / fabs(dt);
-        if (inv_norm) *inv_norm = sqrt(na) / fabs(dt);
+        const T in = sqrt(na) * recip<T>(fabs(dt));
+        *cond = sqrt(nj) * in;
+        if (inv_norm) *inv_norm = in;
       }
       return true;
     }
