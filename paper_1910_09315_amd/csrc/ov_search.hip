@@ -1122,11 +1122,13 @@ struct WalkWaves {
 };
 
 // The first kernel of the two-kernel back half (OV_OPT_BACK_FUSED = 2). Each
-// block takes BS (64, 128 or 256) queries at a time, one per thread: the
-// transform and the walk over the candidate grids. A query FP32 cannot
-// decide, or whose walk fails, goes to the deferral queue (its state in its
-// outputs) for k_back_defer; every other thread writes its result and
-// interpolates its fields. The kernel holds only the walk's registers.
+// wavefront takes 64 queries at a time, one per lane (by a fixed stride over
+// all the launch's wavefronts, or from the work queue), with no barrier
+// between wavefronts: the transform and the walk over the candidate grids.
+// A query FP32 cannot decide, or whose walk fails, goes to the deferral queue
+// (its state in its outputs) for k_back_defer; every other lane writes its
+// result and interpolates its fields. The kernel holds only the walk's
+// registers, which leaves room for three wavefronts per SIMD in FP32.
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWaves<T>::value)))
     k_back_walk(const GridDev* __restrict__ grids_g, int ngrids, const double* __restrict__ poses,
@@ -1147,18 +1149,20 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWav
     grid_lds[i] = ((const unsigned long long*)grids_g)[i];
   const GridDev* __restrict__ grids = reinterpret_cast<const GridDev*>(grid_lds);
   for (int i = threadIdx.x; i < ngrids * 12; i += blockDim.x) sp[i] = poses[i];
-  // the block's position in each round of chunks: with xcd_run > 0 the
-  // blocks of one XCD take runs of consecutive chunks, whose queries are
-  // neighbours on the grids and share donor-cell lines in that XCD's L2
-  const long long brank = xcd_rank(blockIdx.x, gridDim.x, xcd_run);
-  // the ids of this thread's query in the block's next chunk, loaded one
+  const int lane = threadIdx.x & 63;
+  constexpr int kWaves = BS / 64;
+  // this wavefront's rank among the launch's: with xcd_run > 0 the blocks of
+  // one XCD take runs of consecutive chunks, whose queries are neighbours on
+  // the grids and share donor-cell lines in that XCD's L2
+  const long long wrank = xcd_rank(blockIdx.x, gridDim.x, xcd_run) * kWaves + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * kWaves;
+  // the ids of this lane's query in the wavefront's next chunk, loaded one
   // chunk ahead (the first before the count is known: entries up to the
   // capacity are allocated), so that a chunk starts with them in registers
-  const long long q_first = brank * blockDim.x + threadIdx.x;
   int cur_A = 0, cur_m = 0;
-  if (q_first < cap) {
-    cur_A = q_grid[q_first];
-    cur_m = q_node[q_first];
+  if (wrank * 64 + lane < cap) {
+    cur_A = q_grid[wrank * 64 + lane];
+    cur_m = q_node[wrank * 64 + lane];
   }
   const unsigned int stamp = *warm.stamp;
   const uint8_t now = (uint8_t)stamp;
@@ -1171,23 +1175,16 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWav
   }
   unsigned int* const dq_count = dq.count + (stamp & 1u);
   unsigned int* const chunk_head = dq.chunk ? dq.chunk + (stamp & 1u) : nullptr;
-  __shared__ long long next_base;
-  int my_iters = 0, my_cands = 0;  // this thread's share of the work (walk cells: `visited` of its queries)
+  __syncthreads();  // the staging is complete
+  int my_iters = 0, my_cands = 0;  // this lane's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
-  for (long long base = brank * blockDim.x; base < n;) {
-    unsigned int ticket = 0;  // the block's next chunk (work queue), in flight during this one
-    if (chunk_head && threadIdx.x == 0) ticket = atomicAdd(chunk_head, 1u);
-    __syncthreads();  // (also orders the pose staging before the first use)
-    const long long q = base + threadIdx.x;
+  for (long long base = wrank * 64; base < n;) {
+    // the wavefront's next chunk (work queue: its ticket, in flight during
+    // this chunk)
+    unsigned int ticket = 0;
+    if (chunk_head && lane == 0) ticket = atomicAdd(chunk_head, 1u);
+    const long long q = base + lane;
     const bool mine = q < n;
-    // the next chunk's ids (fixed stride: its base is known now; work queue:
-    // once the ticket is shared at the end of the chunk)
-    int nxt_A = 0, nxt_m = 0;
-    long long nbase = base + (long long)gridDim.x * blockDim.x;
-    if (!chunk_head && nbase + threadIdx.x < cap) {
-      nxt_A = q_grid[nbase + threadIdx.x];
-      nxt_m = q_node[nbase + threadIdx.x];
-    }
     int res_grid = -1, res_cell = -1, res_status = OV_Q_ORPHAN;
     T rs[3] = {(T)NAN, (T)NAN, (T)NAN};
     int visited = 0;
@@ -1266,16 +1263,25 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWav
         }
       }
     }
+    // the next chunk's base, and its ids (fixed stride; or the ticket, which
+    // has long arrived)
+    long long nbase = base + nwaves * 64;
+    if (chunk_head) nbase = (nwaves + (long long)__shfl((int)ticket, 0, 64)) * 64;
+    int nxt_A = 0, nxt_m = 0;
+    if (nbase + lane < cap) {
+      nxt_A = q_grid[nbase + lane];
+      nxt_m = q_node[nbase + lane];
+    }
     {
       // the wavefront's deferred queries go to the queue with one atomic
       const unsigned long long dm = __ballot(mine && defer != 0);
       if (dm) {
         unsigned int base_slot = 0;
         const int leader = __ffsll((long long)dm) - 1;
-        if ((int)(threadIdx.x & 63) == leader) base_slot = atomicAdd(dq_count, (unsigned int)__popcll(dm));
+        if (lane == leader) base_slot = atomicAdd(dq_count, (unsigned int)__popcll(dm));
         base_slot = __shfl(base_slot, leader, 64);
         if (mine && defer) {
-          const unsigned int rank = __popcll(dm & ((1ull << (threadIdx.x & 63)) - 1ull));
+          const unsigned int rank = __popcll(dm & ((1ull << lane) - 1ull));
           if ((long long)(base_slot + rank) < cap) dq.items[base_slot + rank] = (int32_t)q;
           donor_grid[q] = defer;
           donor_cell[q] = defer_cell;
@@ -1294,15 +1300,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WalkWav
       if (!defer)
         finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
                         donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
-    }
-    if (chunk_head) {
-      if (threadIdx.x == 0) next_base = ((long long)gridDim.x + ticket) * blockDim.x;
-      __syncthreads();
-      nbase = next_base;
-      if (nbase + threadIdx.x < cap) {
-        nxt_A = q_grid[nbase + threadIdx.x];
-        nxt_m = q_node[nbase + threadIdx.x];
-      }
     }
     base = nbase;
     cur_A = nxt_A;
