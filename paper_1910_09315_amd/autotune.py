@@ -54,7 +54,7 @@ SPACE = {
     "holecut_npl": (4, 16),
     "persist": (4, 8, 16),
     "back_block": (64, 128, 256),
-    "back_blocks": (4, 8, 16),
+    "back_blocks": (2, 4, 8, 16),
     "max_walk": (8, 16, 32),
     "back_fused": (1, 2),
     "back_queue": (0, 1),

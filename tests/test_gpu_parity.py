@@ -262,6 +262,7 @@ def test_split_back_half_with_every_query_deferred(precision):
 
 
 @pytest.mark.parametrize("options", [{"back_block": 64, "back_blocks": 2}, {"back_block": 128, "back_blocks": 16},
+                                     {"back_block": 256, "back_blocks": 2, "back_xcd": 8},
                                      {"persist": 4, "holecut_npl": 4}, {"persist": 16}, {"field_layout": 1},
                                      {"holecut_list": 1, "persist": 4}, {"holecut_list": 1, "persist": 16},
                                      {"back_fused": 2, "back_block": 64, "back_blocks": 4},
