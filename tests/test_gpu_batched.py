@@ -118,18 +118,21 @@ def test_shells_full_size_pipelined_sampled_steps():
 
 
 @pytest.mark.timeout(300)
-def test_shells_full_size_tuned_parameters():
-    """The full-size shells workload through the executor with the tuned
-    parameters the benchmark applies (streams, hole-cut width, persistence,
-    back-half block and workgroups, walk limit), checked against the oracle."""
+@pytest.mark.parametrize("config,precision,sample", [("C4", "mixed", [0, 3, 250]), ("C4", "fp64", [0, 3]),
+                                                     ("C3", "mixed", [0, 3, 150]), ("C1", "fp64", [0, 3, 60])])
+def test_full_size_tuned_parameters(config, precision, sample):
+    """Each full-size workload the benchmark times, through the executor with
+    the tuned parameters it applies (streams, hole-cut form and width,
+    persistence, back-half form, block and workgroups, walk limit, chunk
+    order), checked against the oracle."""
     from paper_1910_09315_amd import autotune as AT
-    w = W.c4(steps=500)
-    tuned = AT.load(AT.signature(w, "mixed"))
+    w = W.build(config)
+    tuned = AT.load(AT.signature(w, precision))
     assert tuned is not None, "no tuned entry for this workload"
     p = dict(tuned["params"])
     opts = {k: p[k] for k in AT.CTX_OPTIONS if k in p}
     opts["field_layout"] = 1
-    stats = _run_pipeline(w, [0, 3, 250], "mixed", stages=p["stages"], options=opts)
+    stats = _run_pipeline(w, sample, precision, stages=p["stages"], options=opts)
     assert all(s["orphans"] == 0 for s in stats)
 
 
