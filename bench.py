@@ -307,7 +307,8 @@ def holecut_roofline(stat, avg_s: float, precision: str, nsub: int, note: str) -
     written, base, cand = stat[ST_FLAG_W] / calls, stat[ST_BASE_R] / calls, stat[ST_HC_NODES] / calls
     nbytes = written + base + (coord_b + 1) * cand + 32 * nsub
     gbs = nbytes / avg_s / 1e9
-    return {"bound": "hbm", "kernel": "hole-cut stage (k_flag_reset + k_holecut_sub in the executors)",
+    return {"bound": "hbm", "kernel": "hole-cut stage (k_flag_reset, then k_holecut_list or k_holecut_sub, in the "
+                                      "executors)",
             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": None, "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(nbytes),
             "per_unit": f"1 B x {written:.0f} flag bytes written + 1 B x {base:.0f} base flags read at the step's "
