@@ -371,6 +371,8 @@ def measure(args, w=None):
                 args.stages = params["stages"]
             if args.threads is None:
                 args.threads = int(params.get("threads", 0))
+            if args.by_step is None:
+                args.by_step = int(params.get("by_step", 0))
             log(f"[bench] tuned parameters {params}")
     for kv in args.opt:
         k, v = kv.split("=", 1)
@@ -380,6 +382,8 @@ def measure(args, w=None):
         args.stages = 3
     if args.threads is None:
         args.threads = 0
+    if args.by_step is None:
+        args.by_step = 0
     if args.stages > 1 and profiler_counting():
         # counter collection serialises dispatches: a stream waiting on
         # another stream's counter could wait for work that cannot start
@@ -395,7 +399,9 @@ def measure(args, w=None):
         pipe = Pipeline(a, cap, native=(mode == "pipelined"), max_timed=max_timed,
                         stages=args.stages if mode == "pipelined" else 2,
                         graphs=(mode == "pipelined" and args.native_graphs),
-                        threads=(mode == "pipelined" and bool(args.threads)))
+                        threads=(mode == "pipelined" and bool(args.threads)),
+                        by_step=(mode == "pipelined" and bool(args.by_step) and args.stages > 1
+                                 and not args.native_graphs))
     elif mode == "graph":
         a.capture()
     if mode == "pipelined-graph":
@@ -523,7 +529,9 @@ def measure(args, w=None):
                              "u, v, w, p as four blocks",
                    "mode": mode + (f", native executor on {args.stages} stream(s)"
                                    + (", per-stream graphs" if args.native_graphs else "")
-                                   + (", one host thread per stream" if args.threads and args.stages > 1 else "")
+                                   + (", all stages of step t on stream t mod streams"
+                                      if args.by_step and args.stages > 1 and not args.native_graphs else
+                                      ", one host thread per stream" if args.threads and args.stages > 1 else "")
                                    + (", unfused back half" if args.unfused_back else ", fused back half")
                                    + ("" if args.per_step_submit else ", one submit call for all timed steps")
                                    if mode == "pipelined" else ""),
@@ -598,7 +606,7 @@ def step_report(pipe, a, poses, w, t0: int, n: int, dev, precision: str, es: int
     torch.cuda.synchronize(dev)
     for i in range(n):
         pipe.submit(t + i, poses[(t + i) % w.steps])
-        evs[i].record(pipe.streams[-1])
+        evs[i].record(pipe.back_stream(t + i))
     pipe.join()
     torch.cuda.synchronize(dev)
     gaps = np.array([evs[i - 1].elapsed_time(evs[i]) for i in range(2, n)]) * 1e3
@@ -663,6 +671,9 @@ def make_parser():
                     help="native executor streams (default: the tuned choice, else 3; 1 under rocprofv3 counters)")
     ap.add_argument("--threads", type=int, default=None, choices=(0, 1),
                     help="native executor: one host thread per stream in multi-step submits (default: tuned, else 0)")
+    ap.add_argument("--by-step", type=int, default=None, choices=(0, 1),
+                    help="native executor, two or three streams: all stages of step t on stream t mod streams "
+                         "(default: tuned, else 0)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the executor for this workload first when no tuned entry is cached")
     ap.add_argument("--no-tuned", action="store_true", help="ignore the cached tuned parameters")
@@ -755,6 +766,7 @@ def main():
             a2 = copy.copy(args)
             a2.config, a2.precision, a2.steps, a2.stages, a2.max_walk = args.compare, prec, None, None, 0
             a2.threads = None
+            a2.by_step = None
             a2.opt = []
             a2.roofline = "back"
             a2.next_rows = args.next_rows and prec == "mixed"

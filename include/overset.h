@@ -455,6 +455,20 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
  * Returns OV_EINVAL for another value. */
 int ov_pipe_set_threads(ov_pipe *pipe, int32_t on);
 
+/* on = 1 (before the first submit; two or three streams, no graphs): the
+ * by-step order. Step t runs all three stages on stream t mod nsets, one
+ * after another, after the step that used that buffer set before; across
+ * streams its hole cut waits for the previous step's hole cut (the step
+ * counter advances in step order) and its back half for the previous step's
+ * back half (the warm start), so that only two orderings cross streams per
+ * step instead of three, and the front half of a step may run while the back
+ * halves of the two steps before it do. The results are the same. A stage
+ * timed alone waits for the other streams' work so far, and the next step
+ * waits for it. on = 0 (default): stream g runs stage group g of every step.
+ * Returns OV_EINVAL for another value or one stream, OV_ESTATE after the
+ * first submit or with graphs. */
+int ov_pipe_set_by_step(ov_pipe *pipe, int32_t on);
+
 /* Make `stream` wait for all work submitted so far. */
 int ov_pipe_join(ov_pipe *pipe, void *stream);
 

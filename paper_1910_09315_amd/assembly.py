@@ -238,10 +238,12 @@ class Pipeline:
     (hole cut | fringe + compaction | back half) and three buffer sets
     (native only). native=True drives the library's C++ executor (ov_pipe_*:
     one host call per step); native=False issues the five calls from Python
-    (optionally replaying per-half HIP graphs, see capture())."""
+    (optionally replaying per-half HIP graphs, see capture()). by_step (native,
+    two or three streams): step t runs all its stages on stream t mod stages
+    instead of stream g running stage group g of every step."""
 
     def __init__(self, asm: Assembly, capacity: int, native: bool = True, max_timed: int = 1024, stages: int = 2,
-                 graphs: bool = False, threads: bool = False):
+                 graphs: bool = False, threads: bool = False, by_step: bool = False):
         if stages not in (1, 2, 3) or (stages != 2 and not native):
             raise ValueError("stages must be 2, or 1 or 3 with the native executor")
         self.a = asm
@@ -258,6 +260,9 @@ class Pipeline:
                 self.native.use_graphs(True)
             if threads:
                 self.native.set_threads(True)
+            if by_step:
+                self.native.set_by_step(True)
+        self.by_step = bool(native and by_step)
         self.front_done = [torch.cuda.Event() for _ in range(2)]
         self.back_done = [torch.cuda.Event() for _ in range(2)]
         self.started = [False] * stages
@@ -366,6 +371,10 @@ class Pipeline:
             return
         s.wait_stream(self.s_front)
         s.wait_stream(self.s_back)
+
+    def back_stream(self, t: int):
+        """The stream step t's back half runs on."""
+        return self.streams[t % self.nsets] if self.by_step else self.streams[-1]
 
     def results(self, t: int) -> dict:
         self.join()

@@ -5,6 +5,8 @@ The tuned parameters and what they choose:
                 step against overlap of the stages on the device;
   threads       a multi-step submit issues each stream's work from a host
                 thread of its own (1) or all of it from the calling thread (0);
+  by_step       two or three streams: all stages of step t on stream t mod
+                streams (1), or stream g running stage group g (0);
   holecut_npl   candidate hole cut, nodes per lane: 4 (one 256-thread block
                 per 16x8x8 sub-tile) or 16 (one wavefront per sub-tile);
   persist       workgroups per CU of the persistent front-half kernels
@@ -51,6 +53,7 @@ CACHE = os.path.join(HERE, "tuned.json")
 SPACE = {
     "stages": (1, 2, 3),
     "threads": (0, 1),
+    "by_step": (0, 1),
     "holecut_npl": (4, 16),
     "persist": (4, 8, 16),
     "back_block": (64, 128, 256),
@@ -61,7 +64,7 @@ SPACE = {
     "back_xcd": (0, 8),
     "holecut_list": (0, 1),
 }
-DEFAULTS = {"stages": 3, "threads": 0, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16,
+DEFAULTS = {"stages": 3, "threads": 0, "by_step": 0, "holecut_npl": 16, "persist": 8, "back_block": 256, "back_blocks": 8, "max_walk": 16,
             "back_fused": 1, "back_queue": 0, "back_xcd": 0, "holecut_list": 0}
 CTX_OPTIONS = ("holecut_npl", "persist", "back_block", "back_blocks", "max_walk", "back_fused", "back_queue",
                "back_xcd", "holecut_list")
@@ -107,7 +110,8 @@ def time_config(asm, capacity: int, poses, params: dict, steps: int, warmup: int
     for k in CTX_OPTIONS:
         asm.ctx.set_option(k, params[k])
     asm.ctx.reset_history()
-    pipe = Pipeline(asm, capacity, native=True, stages=params["stages"], threads=bool(params.get("threads", 0)))
+    pipe = Pipeline(asm, capacity, native=True, stages=params["stages"], threads=bool(params.get("threads", 0)),
+                    by_step=bool(params.get("by_step", 0)) and params["stages"] > 1)
     pipe.submit_many(0, poses[:warmup])
     pipe.join()
     torch.cuda.synchronize()

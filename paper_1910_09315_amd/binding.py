@@ -39,7 +39,7 @@ EXPORTS = ["ov_ctx_create", "ov_ctx_destroy", "ov_last_error", "ov_grid_add", "o
            "overset_interp", "overset_frame_velocity", "overset_interp_matrix", "overset_interp_apply",
            "ov_pipe_create1", "ov_pipe_create", "ov_pipe_create3", "ov_pipe_use_graphs",
            "ov_pipe_submit",
-           "ov_pipe_submit_many", "ov_pipe_set_threads", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_set_timing_mode", "ov_pipe_stage_times",
+           "ov_pipe_submit_many", "ov_pipe_set_threads", "ov_pipe_set_by_step", "ov_pipe_join", "ov_pipe_set_timing", "ov_pipe_set_timing_mode", "ov_pipe_stage_times",
            "ov_pipe_destroy"]
 
 _P = ctypes.c_void_p
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         "ov_pipe_submit": (ctypes.c_int, [_P, _P, _P]),
         "ov_pipe_submit_many": (ctypes.c_int, [_P, _P, _I64, _I64, _P]),
         "ov_pipe_set_threads": (ctypes.c_int, [_P, _I32]),
+        "ov_pipe_set_by_step": (ctypes.c_int, [_P, _I32]),
         "ov_pipe_join": (ctypes.c_int, [_P, _P]),
         "ov_pipe_set_timing": (ctypes.c_int, [_P, _I32, _I32]),
         "ov_pipe_set_timing_mode": (ctypes.c_int, [_P, _I32, _I32, _I32]),
@@ -299,6 +300,10 @@ class NativePipe:
     def set_threads(self, on: bool = True):
         """Issue each stream's work of a multi-step submit from a host thread of its own."""
         self.ctx.check(self.ctx.lib.ov_pipe_set_threads(self.h, int(bool(on))), "ov_pipe_set_threads")
+
+    def set_by_step(self, on: bool = True):
+        """Run all stages of step t on stream t mod nsets (before the first submit)."""
+        self.ctx.check(self.ctx.lib.ov_pipe_set_by_step(self.h, int(bool(on))), "ov_pipe_set_by_step")
 
     def join(self, stream=None):
         self.ctx.check(self.ctx.lib.ov_pipe_join(self.h, _stream(stream)), "ov_pipe_join")

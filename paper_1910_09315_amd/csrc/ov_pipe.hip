@@ -71,6 +71,11 @@ struct ov_pipe {
   unsigned int* defer_count = nullptr;
   // submit_many from one host thread per stream (ov_pipe_set_threads)
   bool threads = false;
+  // by-step order (ov_pipe_set_by_step): step t runs its three stages on
+  // stream t mod nsets; a stage timed alone hands the next step this event
+  bool by_step = false;
+  hipEvent_t alone_done = nullptr;
+  bool alone_pending = false;
 };
 
 using namespace ov;
@@ -155,6 +160,7 @@ static int pipe_create(ov_ctx* ctx, int32_t nf, int nsets, const ov_step_buffers
   bool ok = true;
   for (int g = 0; g < nsets && ok; ++g)
     ok &= hipEventCreateWithFlags(&p->join[g], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&p->alone_done, hipEventDisableTiming) == hipSuccess;
   if (ok && nsets > 1) {
     int can = 0;
     ok = hipDeviceGetAttribute(&can, hipDeviceAttributeCanUseStreamWaitValue, ctx->device) == hipSuccess && can;
@@ -203,6 +209,7 @@ int ov_pipe_create3(ov_ctx* ctx, int32_t nf, const ov_step_buffers* sets, const 
 int ov_pipe_use_graphs(ov_pipe* p, int32_t on) {
   if (!p) return OV_EINVAL;
   if (p->t != 0) return pipe_fail(p, OV_ESTATE, "ov_pipe_use_graphs after the first submit");
+  if (on && p->by_step) return pipe_fail(p, OV_ESTATE, "ov_pipe_use_graphs: not with the by-step order");
   destroy_graphs(p);  // (the next direct step of every set starts from a full fill)
   if (!on) return OV_OK;
   p->graphs = true;  // (captured steps write every flag and use near list 0)
@@ -248,6 +255,45 @@ int ov_pipe_set_timing_mode(ov_pipe* p, int32_t every, int32_t stage, int32_t al
 
 int ov_pipe_set_timing(ov_pipe* p, int32_t every, int32_t stage) { return ov_pipe_set_timing_mode(p, every, stage, 1); }
 
+// One step in the by-step order: all three stages on stream t mod nsets (in
+// stream order after the step that used this buffer set before). The hole
+// cut starts after the previous step's (the step counter and the stamps
+// advance in step order); the back half after the previous step's (the warm
+// start reads what it wrote, and consecutive back halves alternate their
+// queue counters). Both waits are for work submitted before, from this
+// thread. A stage timed alone first waits for every other stream's work so
+// far, and the next step waits for it.
+static hipError_t submit_by_step(ov_pipe* p, long long t, int k, const double* poses, int64_t* count_out, int gen,
+                                 bool reset, bool timed, bool alone) {
+  hipStream_t s = p->st[k];
+  hipError_t e = hipSuccess;
+  if (t >= 1) e = hipStreamWaitValue64(s, p->seq + 0, (uint64_t)t, hipStreamWaitValueGte, ~0ull);
+  if (e == hipSuccess && p->alone_pending) {
+    e = hipStreamWaitEvent(s, p->alone_done, 0);
+    p->alone_pending = false;
+  }
+  for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+    if (stage == 2 && t >= 1) e = hipStreamWaitValue64(s, p->seq + 2, (uint64_t)t, hipStreamWaitValueGte, ~0ull);
+    const bool ts = timed && stage == p->timed_stage;
+    for (int g = 0; ts && alone && g < p->nsets && e == hipSuccess; ++g) {
+      if (g == k) continue;
+      e = hipEventRecord(p->join[g], p->st[g]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[g], 0);
+    }
+    if (e == hipSuccess && ts) e = hipEventRecord(p->tb[p->ntimed], s);
+    if (e == hipSuccess)
+      e = stage_launch(p, k, stage, poses, s, stage == 2 ? (long long*)count_out : nullptr, gen, reset);
+    if (e == hipSuccess && ts) e = hipEventRecord(p->te[p->ntimed], s);
+    if (e == hipSuccess && ts && alone) {
+      e = hipEventRecord(p->alone_done, s);
+      p->alone_pending = e == hipSuccess;
+    }
+    if (e == hipSuccess && stage != 1)
+      e = hipStreamWriteValue64(s, p->seq + stage, (uint64_t)(t + 1), 0);
+  }
+  return e;
+}
+
 int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   if (!p || !poses) return pipe_fail(p, OV_EINVAL, "ov_pipe_submit: null argument");
   ov_ctx* ctx = p->ctx;
@@ -266,6 +312,13 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
   const int gen = p->graphs ? 0 : (int)(use & 1);
   const bool reset = !p->graphs && use > 0;
   p->gen[k] = gen;
+  if (p->by_step) {
+    e = submit_by_step(p, t, k, poses, count_out, gen, reset, timed, alone);
+    if (e != hipSuccess) return hip_fail(ctx, e, "ov_pipe_submit");
+    if (timed) ++p->ntimed;
+    ++p->t;
+    return OV_OK;
+  }
   for (int g = 0; g < n && e == hipSuccess; ++g) {
     hipStream_t s = p->st[g];
     // after the previous group of this step, or (first group) after the
@@ -384,6 +437,15 @@ static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride,
   return OV_OK;
 }
 
+int ov_pipe_set_by_step(ov_pipe* p, int32_t on) {
+  if (!p || on < 0 || on > 1) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_by_step: bad argument");
+  if (p->t != 0) return pipe_fail(p, OV_ESTATE, "ov_pipe_set_by_step after the first submit");
+  if (on && p->graphs) return pipe_fail(p, OV_ESTATE, "ov_pipe_set_by_step: not with graphs");
+  if (on && p->nsets < 2) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_by_step: needs two or three streams");
+  p->by_step = on != 0;
+  return OV_OK;
+}
+
 int ov_pipe_set_threads(ov_pipe* p, int32_t on) {
   if (!p || on < 0 || on > 1) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_threads: bad argument");
   p->threads = on != 0;
@@ -393,7 +455,7 @@ int ov_pipe_set_threads(ov_pipe* p, int32_t on) {
 int ov_pipe_submit_many(ov_pipe* p, const double* poses, int64_t pose_stride, int64_t n, int64_t* counts_out) {
   if (!p || !poses || n < 0 || pose_stride < 12 * (int64_t)p->ctx->grids.size())
     return pipe_fail(p, OV_EINVAL, "ov_pipe_submit_many: bad argument");
-  if (p->threads && p->nsets > 1 && !p->graphs && !(p->timing > 0 && p->timed_alone) && n > 1)
+  if (p->threads && !p->by_step && p->nsets > 1 && !p->graphs && !(p->timing > 0 && p->timed_alone) && n > 1)
     return submit_threaded(p, poses, pose_stride, n, counts_out);
   for (int64_t i = 0; i < n; ++i) {
     int rc = ov_pipe_submit(p, poses + pose_stride * i, counts_out ? counts_out + i : nullptr);
@@ -433,6 +495,7 @@ int ov_pipe_destroy(ov_pipe* p) {
   destroy_graphs(p);
   for (int g = 0; g < 3; ++g)
     if (p->join[g]) (void)hipEventDestroy(p->join[g]);
+  if (p->alone_done) (void)hipEventDestroy(p->alone_done);
   if (p->seq) (void)hipFree(p->seq);
   if (p->defer_items) (void)hipFree(p->defer_items);
   if (p->defer_count) (void)hipFree(p->defer_count);

@@ -278,12 +278,12 @@ def test_tuned_variants_match_sequential(options):
     _check_pipeline(True, 3, False, "mixed", options)
 
 
-def _check_pipeline(native, stages, graphs, precision, options, seq_options=None):
+def _check_pipeline(native, stages, graphs, precision, options, seq_options=None, by_step=False):
     from paper_1910_09315_amd.assembly import Pipeline
     w = W.c1_small(steps=7)
     a = _assembly(w, precision, options=seq_options)
     b = _assembly(w, precision, capacity=a.capacity, options=options)
-    pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs)
+    pipe = Pipeline(b, a.capacity, native=native, stages=stages, graphs=graphs, by_step=by_step)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     counts = torch.full((7,), -1, dtype=torch.int64, device="cuda")
     seq = []
@@ -330,6 +330,51 @@ def test_threaded_submit_matches_sequential(stages, precision):
     assert counts.cpu().tolist() == [r["count"] for r in seq]
     times = pipe.native.stage_times(16)
     assert len(times) == 5 and all(x > 0 for x in times)
+    pipe.close()
+
+
+@pytest.mark.parametrize("stages,precision,options", [(2, "fp64", {}), (3, "fp64", {}), (3, "mixed", {}),
+                                                       (2, "mixed", {"back_fused": 2}),
+                                                       (3, "mixed", {"holecut_list": 1, "back_xcd": 8})])
+def test_by_step_order_matches_sequential(stages, precision, options):
+    """The executor with all stages of step t on stream t mod streams gives
+    the five calls' results bit for bit, step by step."""
+    _check_pipeline(True, stages, False, precision, options, by_step=True)
+
+
+@pytest.mark.parametrize("stages,precision", [(3, "fp64"), (2, "mixed"), (3, "mixed")])
+def test_by_step_order_submit_many_and_timing(stages, precision):
+    """The by-step order under multi-step submits, a single-step submit
+    between them, the back half timed in place and the fringe stage timed
+    alone: results equal the five calls' bit for bit, every timed stage
+    yields a positive duration."""
+    from paper_1910_09315_amd.assembly import Pipeline
+    w = W.c1_small(steps=12)
+    a = _assembly(w, precision)
+    b = _assembly(w, precision, capacity=a.capacity)
+    pipe = Pipeline(b, a.capacity, native=True, stages=stages, by_step=True, max_timed=16)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    counts = torch.full((12,), -1, dtype=torch.int64, device="cuda")
+    seq = []
+    for t in range(12):
+        a.step(poses[t])
+        seq.append(a.results())
+    for t0, t1, stage, alone in ((0, 5, 2, False), (5, 6, 2, False), (6, 12, 1, True)):
+        pipe.native.set_timing(1, stage, alone=alone)
+        if t1 - t0 == 1:
+            pipe.submit(t0, poses[t0], count_out=counts[t0:t1])
+        else:
+            pipe.submit_many(t0, poses[t0:t1].contiguous(), counts[t0:t1])
+        pipe.join()
+        for t in range(max(t0, t1 - stages), t1):
+            r = pipe.results(t)
+            for k in ("flags", "q_node", "qx", "donor_grid", "donor_cell", "status", "s", "values"):
+                assert np.array_equal(r[k], seq[t][k], equal_nan=True), (t, k)
+        times = pipe.native.stage_times(16)
+        assert len(times) == t1 - t0 and all(x > 0 for x in times), times
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [r["count"] for r in seq]
+    pipe.native.set_timing(0)
     pipe.close()
 
 
