@@ -44,13 +44,13 @@ def _run_steps(w, steps, precision, options=None):
     return out
 
 
-def _run_pipeline(w, steps, precision, stages=3, options=None):
+def _run_pipeline(w, steps, precision, stages=3, options=None, by_step=False):
     from paper_1910_09315_amd.assembly import Assembly, Pipeline
     o = oracle.Oracle(w.grids, w.nf)
     a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options=options)
     cap = 2 * a.count_queries(w.poses[0]) + 4096
     a.allocate(cap)
-    pipe = Pipeline(a, cap, native=True, stages=stages)
+    pipe = Pipeline(a, cap, native=True, stages=stages, by_step=by_step and stages > 1)
     poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
     out = []
     for t in range(max(steps) + 1):
@@ -122,9 +122,9 @@ def test_shells_full_size_pipelined_sampled_steps():
                                                      ("C3", "mixed", [0, 3, 150]), ("C1", "fp64", [0, 3, 60])])
 def test_full_size_tuned_parameters(config, precision, sample):
     """Each full-size workload the benchmark times, through the executor with
-    the tuned parameters it applies (streams, hole-cut form and width,
-    persistence, back-half form, block and workgroups, walk limit, chunk
-    order), checked against the oracle."""
+    the tuned parameters it applies (streams and their order, hole-cut form
+    and width, persistence, back-half form, block and workgroups, walk limit,
+    chunk order), checked against the oracle."""
     from paper_1910_09315_amd import autotune as AT
     w = W.build(config)
     tuned = AT.load(AT.signature(w, precision))
@@ -132,7 +132,7 @@ def test_full_size_tuned_parameters(config, precision, sample):
     p = dict(tuned["params"])
     opts = {k: p[k] for k in AT.CTX_OPTIONS if k in p}
     opts["field_layout"] = 1
-    stats = _run_pipeline(w, sample, precision, stages=p["stages"], options=opts)
+    stats = _run_pipeline(w, sample, precision, stages=p["stages"], options=opts, by_step=bool(p.get("by_step", 0)))
     assert all(s["orphans"] == 0 for s in stats)
 
 
