@@ -926,16 +926,21 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
   ctx->nsuper = (ctx->nchunks + kSuperChunk - 1) / kSuperChunk;
   HIPCHK(hipMalloc(&ctx->d_chunk_static, ctx->nchunks), "hipMalloc static chunk marks");
-  HIPCHK(hipMalloc(&ctx->d_chunk_stamp, sizeof(unsigned int) * ctx->nchunks), "hipMalloc chunk stamps");
-  HIPCHK(hipMalloc(&ctx->d_chunk_list, sizeof(int32_t) * ctx->nchunks), "hipMalloc chunk list");
+  // the fringe pass's and the compaction's chunk records, one set per
+  // scratch slot: the steps of different slots may run them at once
+  HIPCHK(hipMalloc(&ctx->d_chunk_stamp, sizeof(unsigned int) * kSlots * ctx->nchunks), "hipMalloc chunk stamps");
+  HIPCHK(hipMalloc(&ctx->d_chunk_list, sizeof(int32_t) * kSlots * ctx->nchunks), "hipMalloc chunk list");
   HIPCHK(hipMalloc(&ctx->d_chunk_list_count, sizeof(int32_t) * kSlots), "hipMalloc chunk list counts");
-  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(unsigned long long) * ctx->nchunks), "hipMalloc chunk counts");
+  HIPCHK(hipMalloc(&ctx->d_chunk_counts, sizeof(unsigned long long) * kSlots * ctx->nchunks),
+         "hipMalloc chunk counts");
   HIPCHK(hipMalloc(&ctx->d_super_counts, sizeof(int32_t) * kSlots * kSuperSlots * ctx->nsuper),
          "hipMalloc superchunk counts");
-  HIPCHK(hipMalloc(&ctx->d_super_offsets, sizeof(long long) * (ctx->nsuper + 1)), "hipMalloc superchunk offsets");
-  HIPCHK(hipMemsetAsync(ctx->d_chunk_stamp, 0, sizeof(unsigned int) * ctx->nchunks, s), "chunk stamp init");
+  HIPCHK(hipMalloc(&ctx->d_super_offsets, sizeof(long long) * kSlots * (ctx->nsuper + 1)),
+         "hipMalloc superchunk offsets");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_stamp, 0, sizeof(unsigned int) * kSlots * ctx->nchunks, s), "chunk stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_chunk_list_count, 0, sizeof(int32_t) * kSlots, s), "chunk list count init");
-  HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(unsigned long long) * ctx->nchunks, s), "chunk count init");
+  HIPCHK(hipMemsetAsync(ctx->d_chunk_counts, 0, sizeof(unsigned long long) * kSlots * ctx->nchunks, s),
+         "chunk count init");
   HIPCHK(hipMemsetAsync(ctx->d_super_counts, 0, sizeof(int32_t) * kSlots * kSuperSlots * ctx->nsuper, s),
          "superchunk count init");
   HIPCHK(hipGetLastError(), "finalize kernels");

@@ -1345,12 +1345,12 @@ FrontScratch ctx_scratch(ov_ctx* ctx, int slot, int gen) {
   f.near_list = ctx->d_near_list + (gen * kSlots + slot) * nt;
   f.near_count = ctx->d_near_count + gen * kSlots + slot;
   f.tile_near = ctx->d_tile_near;
-  f.chunk_stamp = ctx->d_chunk_stamp;
-  f.chunk_list = ctx->d_chunk_list;
+  f.chunk_stamp = ctx->d_chunk_stamp + (long long)slot * ctx->nchunks;
+  f.chunk_list = ctx->d_chunk_list + (long long)slot * ctx->nchunks;
   f.chunk_list_count = ctx->d_chunk_list_count + slot;
-  f.chunk_counts = ctx->d_chunk_counts;
+  f.chunk_counts = ctx->d_chunk_counts + (long long)slot * ctx->nchunks;
   f.super_counts = ctx->d_super_counts + (long long)slot * kSuperSlots * ctx->nsuper;
-  f.super_offsets = ctx->d_super_offsets;
+  f.super_offsets = ctx->d_super_offsets + (long long)slot * (ctx->nsuper + 1);
   return f;
 }
 
@@ -2050,8 +2050,10 @@ int build_static_chunks(ov_ctx* ctx, hipStream_t s) {
   for (long long c = 0; c < nch; ++c)
     if (marks[(size_t)c]) list.push_back((int32_t)c);
   ctx->n_static_chunks = (long long)list.size();
-  if (!list.empty()) {
-    e = hipMemcpy(ctx->d_chunk_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice);
+  // every slot's chunk list starts with the static list
+  for (int k = 0; k < kSlots && !list.empty(); ++k) {
+    e = hipMemcpy(ctx->d_chunk_list + (long long)k * nch, list.data(), sizeof(int32_t) * list.size(),
+                  hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "static chunk list upload");
   }
   return OV_OK;

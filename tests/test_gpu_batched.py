@@ -137,6 +137,42 @@ def test_full_size_tuned_parameters(config, precision, sample):
 
 
 @pytest.mark.timeout(300)
+@pytest.mark.parametrize("config,precision,nsteps", [("C1", "fp64", 60), ("C3", "mixed", 36)])
+def test_by_step_order_full_size_batches_match_five_calls(config, precision, nsteps):
+    """Full-size workloads through the executor in the by-step order, six
+    steps per multi-step submit (so that the stages of consecutive steps run
+    at once on their streams, the fringe passes and compactions of two steps
+    among them), against the five calls step by step: the last three steps of
+    every batch (the ones whose buffer sets still hold them) bit for bit."""
+    from paper_1910_09315_amd.assembly import Assembly, Pipeline
+    w = W.build(config)
+    a = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options={"field_layout": 1})
+    cap = 2 * a.count_queries(w.poses[0]) + 4096
+    a.allocate(cap)
+    b = Assembly(w.grids, w.nf, fields=w.fields, precision=precision, options={"field_layout": 1})
+    b.allocate(cap)
+    pipe = Pipeline(b, cap, native=True, stages=3, by_step=True)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    seq = {}
+    checked = 0
+    for t0 in range(0, nsteps, 6):
+        for t in range(t0, t0 + 6):
+            a.step(poses[t])
+            if t >= t0 + 3:
+                seq[t] = a.results()
+        pipe.submit_many(t0, poses[t0:t0 + 6].contiguous())
+        pipe.join()
+        for t in range(t0 + 3, t0 + 6):
+            r = pipe.results(t)
+            for k in ("flags", "q_node", "qx", "donor_grid", "donor_cell", "status", "s", "values"):
+                assert np.array_equal(r[k], seq[t][k], equal_nan=True), (t, k)
+            checked += 1
+    torch.cuda.synchronize()
+    assert checked == nsteps // 2
+    pipe.close()
+
+
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_shells_full_size_split_back_half(precision):
     """The full-size shells workload with the two-kernel back half."""
