@@ -455,14 +455,14 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
  * Returns OV_EINVAL for another value. */
 int ov_pipe_set_threads(ov_pipe *pipe, int32_t on);
 
-/* on = 1 (before the first submit; two or three streams, no graphs): the
- * by-step order. Step t runs all three stages on stream t mod nsets, one
+/* on = 1 (before the first submit; two or three streams, no graphs; waits
+ * for the device, as the host then numbers this pipe's steps on from the
+ * context's step counter): the by-step order. Step t runs all three stages on stream t mod nsets, one
  * after another, after the step that used that buffer set before; across
- * streams its hole cut waits for the previous step's hole cut (the step
- * counter advances in step order) and its back half for the previous step's
- * back half (the warm start), so that only two orderings cross streams per
- * step instead of three, and the front half of a step may run while the back
- * halves of the two steps before it do. The results are the same. A stage
+ * streams only its back half waits, for the previous step's back half (the
+ * warm start), so that one ordering crosses streams per step instead of
+ * three, and the front half of a step may run while the back halves of the
+ * steps before it do. The results are the same. A stage
  * timed alone waits for the other streams' work so far, and the next step
  * waits for it. on = 0 (default): stream g runs stage group g of every step.
  * Returns OV_EINVAL for another value or one stream, OV_ESTATE after the

@@ -915,13 +915,13 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   ctx->nmask_chunks = (nt * kSubPerTile + kMaskChunk - 1) / kMaskChunk;
   HIPCHK(hipMalloc(&ctx->d_sub_mask, sizeof(unsigned long long) * kSlots * kSubPerTile * nt), "hipMalloc sub-tile masks");
   HIPCHK(hipMalloc(&ctx->d_mask_counts, sizeof(int32_t) * kSlots * ctx->nmask_chunks), "hipMalloc mask counts");
-  HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * nt), "hipMalloc tile near");
+  HIPCHK(hipMalloc(&ctx->d_tile_near, sizeof(unsigned int) * kSlots * nt), "hipMalloc tile near");
   // two near lists per slot (alternate steps of a slot write one each)
   HIPCHK(hipMalloc(&ctx->d_near_list, sizeof(int4) * 2 * kSlots * nt), "hipMalloc near lists");
   HIPCHK(hipMalloc(&ctx->d_near_count, sizeof(int32_t) * 2 * kSlots), "hipMalloc near counts");
   HIPCHK(hipMemsetAsync(ctx->d_stamp, 0, sizeof(unsigned int) * (2 + kSlots), s), "stamp init");
   HIPCHK(hipMemsetAsync(ctx->d_tile_hole, 0, sizeof(unsigned int) * kSlots * nt, s), "tile hole init");
-  HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * nt, s), "tile near init");
+  HIPCHK(hipMemsetAsync(ctx->d_tile_near, 0, sizeof(unsigned int) * kSlots * nt, s), "tile near init");
   HIPCHK(hipMemsetAsync(ctx->d_near_count, 0, sizeof(int32_t) * 2 * kSlots, s), "near count init");
   ctx->nchunks = (total + kCompactChunk - 1) / kCompactChunk;
   ctx->nsuper = (ctx->nchunks + kSuperChunk - 1) / kSuperChunk;

@@ -154,7 +154,7 @@ struct ov_ctx {
   // the fringe pass and the compaction. Each hole cut starts a new stamp; a
   // tile or chunk is on this step's list when its entry equals the stamp, so
   // nothing needs clearing between steps.
-  unsigned int* d_stamp = nullptr;            // [0] step counter, [1 + slot] stamp of scratch slot `slot`,
+  unsigned int* d_stamp = nullptr;            // [0] (unused), [1 + slot] stamp of scratch slot `slot`,
                                               // [1 + kSlots] counter of the C-ABI fringe call's own lists
   unsigned int* d_tile_hole = nullptr;        // per slot and tile: the stamp of the slot's step if the tile holds a hole
   // the culled hole cut's candidate lookup (OV_OPT_HOLECUT_LIST): per slot,
@@ -163,7 +163,8 @@ struct ov_ctx {
   unsigned long long* d_sub_mask = nullptr;   // [kSlots * nsub]
   int32_t* d_mask_counts = nullptr;           // [kSlots * nmask_chunks]
   long long nmask_chunks = 0;
-  unsigned int* d_tile_near = nullptr;        // per tile: stamp if on the near list
+  unsigned int* d_tile_near = nullptr;        // [slot][tile]: stamp if on the slot's near list
+  unsigned int hole_stamp = 0;                // the last stamp numbered on the host (by-step executors)
   int4* d_near_list = nullptr;                // per slot: tiles that may hold buffer nodes (a hole within kMaxNf)
   int32_t* d_near_count = nullptr;            // per slot
   uint8_t* d_chunk_static = nullptr;          // per chunk: holds outer-boundary query nodes
@@ -211,9 +212,23 @@ long long grid_size_for(const ov_ctx* ctx, long long items, int block);
 // pass reads); reset: instead of writing every flag, return only the tiles
 // on the slot's other near list (the previous step of this slot and flags
 // buffer) to their base flags, for callers whose flags buffer holds exactly
-// that step's result (the step executors).
+// that step's result (the step executors). stamp: 0 numbers the step on the
+// device (the context's step counter, advanced by the step's first kernel;
+// also under graph capture, where every replay takes the next number);
+// otherwise the step's stamp, numbered by the caller in issue order
+// (next_hole_stamp), which raises the device counter to it.
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot = 0, int gen = 0,
-                          bool reset = false);
+                          bool reset = false, unsigned int stamp = 0u);
+
+// Stamps: 0 marks "never listed"; the high bit keeps the C ABI's fringe
+// call's own stamps apart from the hole cut's; the wrap goes on to 2, so that
+// the parity of consecutive stamps alternates (the back half picks its queue
+// counters by it).
+constexpr unsigned int kStampHigh = 0x80000000u;
+__host__ __device__ __forceinline__ unsigned int stamp_after(unsigned int v) {
+  v = (v + 1u) & ~kStampHigh;
+  return v == 0u ? 2u : v;
+}
 // The scratch of one fringe pass and compaction: the near-tile list, the
 // chunk list and the compaction's per-chunk and per-superchunk counts. It
 // lives in the context's slots, or (the no-allocation fringe call) in the

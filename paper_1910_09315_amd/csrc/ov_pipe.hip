@@ -91,13 +91,14 @@ static int first_stage(const ov_pipe* p, int g) {
 // Launches stage `stage` (0 = A, 1 = B, 2 = C) for buffer set k on stream s,
 // reading poses from `poses`; count_out (nullable) gets the query count.
 // gen: the slot's near list this step writes (A) and reads (B); reset: A
-// starts from the set's previous step (k_flag_reset) instead of a full fill.
+// starts from the set's previous step (k_flag_reset) instead of a full fill;
+// stamp: the hole cut's stamp numbered on the host, or 0 (on the device).
 static hipError_t stage_launch(ov_pipe* p, int k, int stage, const double* poses, hipStream_t s,
-                               long long* count_out, int gen, bool reset) {
+                               long long* count_out, int gen, bool reset, unsigned int stamp = 0u) {
   ov_ctx* ctx = p->ctx;
   const ov_step_buffers& b = p->sets[k];
   const int slot = k;
-  if (stage == 0) return launch_holecut(ctx, poses, b.flags, s, slot, gen, reset);
+  if (stage == 0) return launch_holecut(ctx, poses, b.flags, s, slot, gen, reset, stamp);
   if (stage == 1) {
     hipError_t e = launch_fringe(ctx, p->nf, b.flags, s, slot, gen);
     if (e == hipSuccess)
@@ -256,19 +257,22 @@ int ov_pipe_set_timing_mode(ov_pipe* p, int32_t every, int32_t stage, int32_t al
 int ov_pipe_set_timing(ov_pipe* p, int32_t every, int32_t stage) { return ov_pipe_set_timing_mode(p, every, stage, 1); }
 
 // One step in the by-step order: all three stages on stream t mod nsets (in
-// stream order after the step that used this buffer set before). The hole
-// cut starts after the previous step's (the step counter and the stamps
-// advance in step order); the back half after the previous step's (the warm
-// start reads what it wrote, and consecutive back halves alternate their
-// queue counters). Both waits are for work submitted before, from this
-// thread. A stage timed alone first waits for every other stream's work so
-// far, and the next step waits for it.
+// stream order after the step that used this buffer set before). Only the
+// back half waits across streams, for the previous step's (the warm start
+// reads what it wrote, and consecutive back halves alternate their queue
+// counters); that wait is for work submitted before, from this thread. The
+// front half needs no order between steps: its stamps are numbered on the
+// host, in submission order, and its scratch belongs to the buffer set's
+// slot. A stage timed alone
+// first waits for every other stream's work so far, and the next step waits
+// for it.
 static hipError_t submit_by_step(ov_pipe* p, long long t, int k, const double* poses, int64_t* count_out, int gen,
                                  bool reset, bool timed, bool alone) {
   hipStream_t s = p->st[k];
   hipError_t e = hipSuccess;
-  if (t >= 1) e = hipStreamWaitValue64(s, p->seq + 0, (uint64_t)t, hipStreamWaitValueGte, ~0ull);
-  if (e == hipSuccess && p->alone_pending) {
+  p->ctx->hole_stamp = stamp_after(p->ctx->hole_stamp);
+  const unsigned int stamp = p->ctx->hole_stamp;
+  if (p->alone_pending) {
     e = hipStreamWaitEvent(s, p->alone_done, 0);
     p->alone_pending = false;
   }
@@ -282,14 +286,13 @@ static hipError_t submit_by_step(ov_pipe* p, long long t, int k, const double* p
     }
     if (e == hipSuccess && ts) e = hipEventRecord(p->tb[p->ntimed], s);
     if (e == hipSuccess)
-      e = stage_launch(p, k, stage, poses, s, stage == 2 ? (long long*)count_out : nullptr, gen, reset);
+      e = stage_launch(p, k, stage, poses, s, stage == 2 ? (long long*)count_out : nullptr, gen, reset, stamp);
     if (e == hipSuccess && ts) e = hipEventRecord(p->te[p->ntimed], s);
     if (e == hipSuccess && ts && alone) {
       e = hipEventRecord(p->alone_done, s);
       p->alone_pending = e == hipSuccess;
     }
-    if (e == hipSuccess && stage != 1)
-      e = hipStreamWriteValue64(s, p->seq + stage, (uint64_t)(t + 1), 0);
+    if (e == hipSuccess && stage == 2) e = hipStreamWriteValue64(s, p->seq + 2, (uint64_t)(t + 1), 0);
   }
   return e;
 }
@@ -442,6 +445,15 @@ int ov_pipe_set_by_step(ov_pipe* p, int32_t on) {
   if (p->t != 0) return pipe_fail(p, OV_ESTATE, "ov_pipe_set_by_step after the first submit");
   if (on && p->graphs) return pipe_fail(p, OV_ESTATE, "ov_pipe_set_by_step: not with graphs");
   if (on && p->nsets < 2) return pipe_fail(p, OV_EINVAL, "ov_pipe_set_by_step: needs two or three streams");
+  if (on) {
+    // the host numbers this pipe's stamps on from the device's step counter
+    // (the context's earlier steps, whatever issued them, are done first)
+    hipError_t e = hipDeviceSynchronize();
+    unsigned int v = 0;
+    if (e == hipSuccess) e = hipMemcpy(&v, p->ctx->d_stamp, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "ov_pipe_set_by_step");
+    p->ctx->hole_stamp = v;
+  }
   p->by_step = on != 0;
   return OV_OK;
 }

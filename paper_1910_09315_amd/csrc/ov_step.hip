@@ -462,31 +462,36 @@ static_assert(kTileI == 64 && kTileJ == 8 && kTileK == 8 && 256 * 16 == kTileI *
 
 // Starts a step of the front half: a new stamp, empty near and chunk lists.
 // Later kernels of the hole cut read the stamp (stream order).
-// `counter` numbers the steps of the context; `d_stamp` is the stamp of the
-// scratch slot this step uses (separate slots let the hole cut of one step
-// overlap the fringe pass of the previous one).
+// `counter` numbers the steps of the context on the device (stamp = 0: the
+// step takes the next number); a nonzero stamp was numbered by the host in
+// issue order (the by-step executor, whose hole cuts may run in any order)
+// and only raises the counter. `d_stamp` is the stamp of the scratch slot
+// this step uses (separate slots let the stages of one step overlap those of
+// others).
 // `high` (0 or kStampHigh) keeps the stamps of two counters apart: the hole
 // cut's starts count on one, the fringe call of the C ABI (which starts its
 // own lists from the flags it is given) on another, so that the hole cut's
 // counter advances once per step (the warm start dates its records by it).
-constexpr unsigned int kStampHigh = 0x80000000u;
-__device__ __forceinline__ void k_begin_step_body(unsigned int* counter, unsigned int* d_stamp, int32_t* near_count,
-                                                  int32_t* chunk_list_count, unsigned int high = 0u) {
-  unsigned int v = (*counter + 1u) & ~kStampHigh;
-  // 0 marks "never listed"; the wrap goes on to 2, so that the parity of
-  // consecutive stamps alternates (the two-kernel back half picks its queue
-  // counter by it)
-  v = v == 0u ? 2u : v;
-  *counter = v;
+__device__ __forceinline__ void k_begin_step_body(unsigned int stamp, unsigned int* counter, unsigned int* d_stamp,
+                                                  int32_t* near_count, int32_t* chunk_list_count,
+                                                  unsigned int high = 0u) {
+  unsigned int v = stamp;
+  if (v == 0u) {
+    v = stamp_after(*counter);
+    *counter = v;
+  } else {
+    atomicMax(counter, v);
+  }
   *d_stamp = v | high;
   *near_count = 0;
   *chunk_list_count = 0;
 }
 
-__global__ void k_begin_step(unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
+__global__ void k_begin_step(unsigned int stamp, unsigned int* __restrict__ counter, unsigned int* __restrict__ d_stamp,
                              int32_t* __restrict__ near_count, int32_t* __restrict__ chunk_list_count,
                              int32_t* __restrict__ super_counts, long long n_super_counts, unsigned int high) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) k_begin_step_body(counter, d_stamp, near_count, chunk_list_count, high);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    k_begin_step_body(stamp, counter, d_stamp, near_count, chunk_list_count, high);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_super_counts;
        i += (long long)gridDim.x * blockDim.x)
     super_counts[i] = 0;
@@ -776,7 +781,7 @@ __device__ __forceinline__ void flag_fill_body(uint8_t* __restrict__ flags, cons
 __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ grids, uint8_t* __restrict__ flags,
                                                    const uint8_t* __restrict__ base,
                                                    const int4* __restrict__ old_list,
-                                                   const int32_t* __restrict__ old_count,
+                                                   const int32_t* __restrict__ old_count, unsigned int stamp,
                                                    unsigned int* __restrict__ counter,
                                                    unsigned int* __restrict__ d_stamp,
                                                    int32_t* __restrict__ near_count,
@@ -784,7 +789,7 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
                                                    int32_t* __restrict__ super_counts, long long n_super_counts,
                                                    unsigned long long* __restrict__ stats, MaskJob mj) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+    k_begin_step_body(stamp, counter, d_stamp, near_count, chunk_list_count);
     atomicAdd(&stat_slot(stats)[OV_STAT_FLAG_STARTS], 1ULL);
   }
   if (mj.nmc > 0) mask_job(mj, grids);
@@ -832,7 +837,8 @@ __global__ void __launch_bounds__(256) k_flag_reset(const GridDev* __restrict__ 
 __global__ void __launch_bounds__(256) k_flag_fill(const GridDev* __restrict__ grids, uint8_t* __restrict__ flags,
                                                   const uint8_t* __restrict__ base,
                                                   const long long* __restrict__ fill_ranges, int nranges,
-                                                  long long fill_words, unsigned int* __restrict__ counter,
+                                                  long long fill_words, unsigned int stamp,
+                                                  unsigned int* __restrict__ counter,
                                                   unsigned int* __restrict__ d_stamp,
                                                   int32_t* __restrict__ near_count,
                                                   int32_t* __restrict__ chunk_list_count,
@@ -841,7 +847,7 @@ __global__ void __launch_bounds__(256) k_flag_fill(const GridDev* __restrict__ g
                                                   long long base_nodes, MaskJob mj) {
   if (mj.nmc > 0) mask_job(mj, grids);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    k_begin_step_body(counter, d_stamp, near_count, chunk_list_count);
+    k_begin_step_body(stamp, counter, d_stamp, near_count, chunk_list_count);
     unsigned long long* slot = stat_slot(stats);
     atomicAdd(&slot[OV_STAT_FLAG_STARTS], 1ULL);
     atomicAdd(&slot[OV_STAT_FLAG_BYTES_WRITTEN], (unsigned long long)nodes);
@@ -1344,7 +1350,7 @@ FrontScratch ctx_scratch(ov_ctx* ctx, int slot, int gen) {
   f.stamp = ctx->d_stamp + 1 + slot;
   f.near_list = ctx->d_near_list + (gen * kSlots + slot) * nt;
   f.near_count = ctx->d_near_count + gen * kSlots + slot;
-  f.tile_near = ctx->d_tile_near;
+  f.tile_near = ctx->d_tile_near + (long long)slot * nt;
   f.chunk_stamp = ctx->d_chunk_stamp + (long long)slot * ctx->nchunks;
   f.chunk_list = ctx->d_chunk_list + (long long)slot * ctx->nchunks;
   f.chunk_list_count = ctx->d_chunk_list_count + slot;
@@ -1368,7 +1374,7 @@ hipError_t launch_near_from_flags(ov_ctx* ctx, const uint8_t* flags, hipStream_t
   const long long nsc = kSuperSlots * ctx->nsuper;
   // a new stamp (empty near and chunk lists, zero superchunk counts)
   hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
-                     fs.counter, fs.stamp, fs.near_count, fs.chunk_list_count, fs.super_counts, nsc, kStampHigh);
+                     0u, fs.counter, fs.stamp, fs.near_count, fs.chunk_list_count, fs.super_counts, nsc, kStampHigh);
   return launch_near_list_in(ctx, flags, s, fs);
 }
 
@@ -1395,11 +1401,12 @@ static void launch_holecut_t(ov_ctx* ctx, const double* poses, uint8_t* flags, h
 }
 
 hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipStream_t s, int slot, int gen,
-                          bool reset) {
+                          bool reset, unsigned int stamp) {
   const int ng = (int)ctx->grids.size();
   const long long nt = ctx->total_tiles;
   unsigned int* counter = ctx->d_stamp;
   unsigned int* st = ctx->d_stamp + 1 + slot;
+  unsigned int* tn = ctx->d_tile_near + (long long)slot * std::max(1LL, nt);
   int4* nl = ctx->d_near_list + (gen * kSlots + slot) * std::max(1LL, nt);
   int32_t* nc = ctx->d_near_count + gen * kSlots + slot;
   unsigned int* th = ctx->d_tile_hole + slot * std::max(1LL, nt);
@@ -1426,13 +1433,15 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
       const long long rb = std::max(1LL, std::min(std::max(nt, mj.nmc), (long long)ctx->num_cus * 8));
       hipLaunchKernelGGL(k_flag_reset, dim3((unsigned)rb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
                          ctx->d_near_list + (og * kSlots + slot) * std::max(1LL, nt),
-                         ctx->d_near_count + og * kSlots + slot, counter, st, nc, clc, sc, nsc, ctx->d_stats, mj);
+                         ctx->d_near_count + og * kSlots + slot, stamp, counter, st, nc, clc, sc, nsc, ctx->d_stats,
+                         mj);
     } else {
       long long base_nodes = 0;
       for (const auto& g : ctx->grids)
         if (g.d.has_outer) base_nodes += g.d.nnodes;
       hipLaunchKernelGGL(k_flag_fill, dim3((unsigned)fb), dim3(256), 0, s, ctx->d_grids, flags, ctx->d_base_flags,
-                         ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, counter, st, nc, clc, sc, nsc,
+                         ctx->d_fill_ranges, ctx->n_fill_ranges, ctx->fill_words, stamp, counter, st, nc, clc, sc,
+                         nsc,
                          ctx->d_stats, ctx->node_off.back(), base_nodes, mj);
     }
     const int per_cu = ctx->persist > 0 ? ctx->persist : 8;
@@ -1441,7 +1450,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
       const dim3 g((unsigned)lb), b(256);
 #define OV_LIST_ARGS                                                                                             \
   ctx->d_grids, ng, poses, flags, ctx->d_tile_info, (const unsigned long long*)mj.sub_mask,                          \
-      (const int32_t*)mj.mask_counts, nsub, mj.nmc, st, ctx->d_tile_near, nl, nc, th, ctx->d_stats
+      (const int32_t*)mj.mask_counts, nsub, mj.nmc, st, tn, nl, nc, th, ctx->d_stats
       const bool mixed = ctx->precision == OV_MIXED;
       if (ctx->has_mesh) {
         if (mixed) hipLaunchKernelGGL((k_holecut_list<float, true>), g, b, 0, s, OV_LIST_ARGS);
@@ -1456,7 +1465,7 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     const long long cb = std::max(1LL, std::min((nsub + 15) / 16, (long long)ctx->num_cus * per_cu));
 #define OV_SUB_ARGS                                                                                             \
   ctx->d_grids, ng, poses, flags, (const double4*)ctx->d_tile_sphere, ctx->d_tile_info, nsub, ctx->sub_perm, st,     \
-      ctx->d_tile_near, nl, nc, th, ctx->d_stats
+      tn, nl, nc, th, ctx->d_stats
     const bool mixed = ctx->precision == OV_MIXED;
     const dim3 g((unsigned)cb), b(256);
 #define OV_SUB(CT, W)                                                                                  \
@@ -1476,12 +1485,12 @@ hipError_t launch_holecut(ov_ctx* ctx, const double* poses, uint8_t* flags, hipS
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_begin_step, dim3((unsigned)std::max(1LL, std::min(64LL, (nsc + 255) / 256))), dim3(256), 0, s,
-                     counter, st, nc, clc, sc, nsc, 0u);
+                     stamp, counter, st, nc, clc, sc, nsc, 0u);
   if (ctx->precision == OV_MIXED) launch_holecut_t<float>(ctx, poses, flags, s, st, th);
   else launch_holecut_t<double>(ctx, poses, flags, s, st, th);
   long long nb = std::max(1LL, std::min((nt + 255) / 256, (long long)ctx->num_cus * 4));
   hipLaunchKernelGGL(k_near_from_holes, dim3((unsigned)nb), dim3(256), 0, s, ctx->d_grids, th,
-                     ctx->d_tile_info, nt, st, ctx->d_tile_near, nl, nc);
+                     ctx->d_tile_info, nt, st, tn, nl, nc);
   return hipGetLastError();
 }
 
