@@ -127,6 +127,18 @@ def time_config(asm, capacity: int, poses, params: dict, steps: int, warmup: int
     return us
 
 
+def normalized(p: dict) -> dict:
+    """The parameters with those that cannot act at their defaults: no by-step
+    order on one stream, one host thread on one stream or in the by-step
+    order (which issues every step from the calling thread)."""
+    q = dict(p)
+    if q.get("stages", 3) == 1:
+        q["by_step"] = 0
+    if q.get("stages", 3) == 1 or q.get("by_step", 0):
+        q["threads"] = 0
+    return q
+
+
 def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: int = 2, log=print,
          start: dict | None = None) -> dict:
     """Coordinate descent over SPACE from `start` (default: the library
@@ -135,6 +147,7 @@ def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: in
     best = dict(DEFAULTS)
     if start:
         best.update({k: v for k, v in start.items() if k in SPACE})
+    best = normalized(best)
     seen = {}
 
     def cost(p):
@@ -151,7 +164,9 @@ def tune(asm, capacity: int, poses, steps: int = 30, warmup: int = 3, passes: in
             for v in values:
                 if v == best[name]:
                     continue
-                cand = dict(best, **{name: v})
+                cand = normalized(dict(best, **{name: v}))
+                if cand == best:
+                    continue
                 us = cost(cand)
                 if us < best_us * 0.99:  # a clear gain only
                     best, best_us, changed = cand, us, True
