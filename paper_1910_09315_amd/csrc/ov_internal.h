@@ -499,9 +499,7 @@ __device__ __forceinline__ void cell_box(const GridDev& g, long long cell, doubl
 // shadows) and the rounded pose. The coordinates come from the packed
 // gather layout: one 32-byte record instead of three arrays.
 template <typename T>
-__device__ __forceinline__ void transform_node(const GridDev& G, const double* p, long long m, T o[3]) {
-  double X, Y, Z;
-  load_xyz(G, m, X, Y, Z);
+__device__ __forceinline__ void transform_xyz(const double* p, double X, double Y, double Z, T o[3]) {
   if (sizeof(T) == 8) {
     o[0] = (T)(p[0] * X + p[1] * Y + p[2] * Z);
     o[1] = (T)(p[3] * X + p[4] * Y + p[5] * Z);
@@ -512,6 +510,13 @@ __device__ __forceinline__ void transform_node(const GridDev& G, const double* p
     o[1] = (T)((float)p[3] * Xf + (float)p[4] * Yf + (float)p[5] * Zf);
     o[2] = (T)((float)p[6] * Xf + (float)p[7] * Yf + (float)p[8] * Zf);
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void transform_node(const GridDev& G, const double* p, long long m, T o[3]) {
+  double X, Y, Z;
+  load_xyz(G, m, X, Y, Z);
+  transform_xyz<T>(p, X, Y, Z, o);
 }
 
 // Trilinear interpolation of the 4 fields in cell `cell` of grid B at

@@ -450,36 +450,40 @@ struct Query {
   bool finite;
 };
 
-// Inertial position of node m of grid A, in FP64 from its FP64 coordinates.
-__device__ __forceinline__ void exact_world(const GridDev& GA, const double* pa, long long m, double x[3]) {
-  double X, Y, Z;
-  load_xyz(GA, m, X, Y, Z);
+// Inertial position of a node from its FP64 body-frame coordinates.
+__device__ __forceinline__ void world_of(const double* pa, double X, double Y, double Z, double x[3]) {
   x[0] = pa[0] * X + pa[1] * Y + pa[2] * Z + pa[9];
   x[1] = pa[3] * X + pa[4] * Y + pa[5] * Z + pa[10];
   x[2] = pa[6] * X + pa[7] * Y + pa[8] * Z + pa[11];
 }
 
+// Inertial position of node m of grid A, in FP64 from its FP64 coordinates.
+__device__ __forceinline__ void exact_world(const GridDev& GA, const double* pa, long long m, double x[3]) {
+  double X, Y, Z;
+  load_xyz(GA, m, X, Y, Z);
+  world_of(pa, X, Y, Z, x);
+}
+
 // The query of grid A's node m with its offset (o0, o1, o2) from the
-// transform (x - c_A). exact = true (or the background in FP32) takes the
-// position from the FP64 node coordinates instead, where the transform's
-// output is FP32.
+// transform (x - c_A), from the node's flag byte and, where the position is
+// taken in FP64 (exact, or the background in FP32), its coordinates
+// (X, Y, Z).
 template <typename T>
-__device__ __forceinline__ Query make_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
-                                            const uint8_t* __restrict__ flags, int A, long long m, double o0,
-                                            double o1, double o2, bool exact) {
+__device__ __forceinline__ Query query_from(const GridDev* __restrict__ grids, int ngrids, const double* sp, int A,
+                                            long long m, uint8_t flag, double o0, double o1, double o2, bool exact,
+                                            double X, double Y, double Z) {
   Query Q;
   Q.A = A;
   Q.m = m;
-  const GridDev& GA = grids[Q.A];
-  Q.key = GA.node_off + Q.m;
-  Q.cause = flags[Q.key] >> 2;
+  Q.key = grids[Q.A].node_off + Q.m;
+  Q.cause = flag >> 2;
   Q.first = (Q.cause != OV_CAUSE_BOUNDARY && Q.cause != Q.A && Q.cause < ngrids) ? Q.cause : -1;
   const double* pa = sp + 12 * Q.A;
   Q.err = 0.0;
   if (sizeof(T) == 4 && (exact || Q.A == 0)) {
     // the background's offsets are absolute positions (large, so FP32 would
     // lose most of a cell); take them in FP64
-    exact_world(GA, pa, Q.m, Q.x);
+    world_of(pa, X, Y, Z, Q.x);
   } else {
     Q.x[0] = pa[9] + o0;
     Q.x[1] = pa[10] + o1;
@@ -490,6 +494,20 @@ __device__ __forceinline__ Query make_query(const GridDev* __restrict__ grids, i
   }
   Q.finite = isfinite(Q.x[0]) && isfinite(Q.x[1]) && isfinite(Q.x[2]);
   return Q;
+}
+
+// The query of grid A's node m (query_from), its flag and coordinates read
+// here. exact = true (or the background in FP32) takes the position from the
+// FP64 node coordinates instead of the transform's FP32 output.
+template <typename T>
+__device__ __forceinline__ Query make_query(const GridDev* __restrict__ grids, int ngrids, const double* sp,
+                                            const uint8_t* __restrict__ flags, int A, long long m, double o0,
+                                            double o1, double o2, bool exact) {
+  const GridDev& GA = grids[A];
+  const uint8_t flag = flags[GA.node_off + m];
+  double X = 0.0, Y = 0.0, Z = 0.0;
+  if (sizeof(T) == 4 && (exact || A == 0)) load_xyz(GA, m, X, Y, Z);
+  return query_from<T>(grids, ngrids, sp, A, m, flag, o0, o1, o2, exact, X, Y, Z);
 }
 
 // Query q of the list, its offset read from the transform's output qx.
@@ -576,14 +594,14 @@ struct Warm {
 };
 constexpr int kWarmMaxAge = 2;  // steps
 
-// The node's warm seed: grid (255: none), cell and the Newton start there.
-__device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t now, int& grid, int& cell,
-                                          Start& s0) {
+// The node's warm seed from its record r: grid (255: none), cell and the
+// Newton start there.
+__device__ __forceinline__ void warm_decode(const Warm& w, unsigned long long r, uint8_t now, int& grid, int& cell,
+                                            Start& s0) {
   grid = 255;
   cell = -1;
   s0 = kCentre;
   if (!w.use) return;
-  const unsigned long long r = gp(w.rec)[key];
   const uint8_t age = (uint8_t)(now - (uint8_t)(r >> 40));
   if (age > kWarmMaxAge) return;
   grid = (int)((r >> 32) & 0xFF);
@@ -593,6 +611,28 @@ __device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t 
   s0.v[0] = (double)(b & 31u) * (1.0 / 31.0);
   s0.v[1] = (double)((b >> 5) & 31u) * (1.0 / 31.0);
   s0.v[2] = (double)((b >> 10) & 31u) * (1.0 / 31.0);
+}
+
+__device__ __forceinline__ void warm_read(const Warm& w, long long key, uint8_t now, int& grid, int& cell,
+                                          Start& s0) {
+  warm_decode(w, w.use ? gp(w.rec)[key] : 0ull, now, grid, cell, s0);
+}
+
+// What the first round trip of a query brings: its node's FP64 coordinates
+// (the gather layout), its warm-start record and its flag byte. The back
+// kernel loads them a chunk ahead.
+struct NodePre {
+  double x, y, z;
+  unsigned long long rec;
+  uint32_t flag;
+};
+
+__device__ __forceinline__ void node_pre_load(const GridDev& G, const Warm& w, const uint8_t* __restrict__ flags,
+                                              int m, NodePre& p) {
+  load_xyz(G, m, p.x, p.y, p.z);
+  const long long key = G.node_off + m;
+  p.rec = w.use ? gp(w.rec)[key] : 0ull;
+  p.flag = flags[key];
 }
 
 // s to 5 bits per component (nearest of 0, 1/31, ..., 1; a NaN as 1/2).
@@ -1345,13 +1385,20 @@ __global__ void __launch_bounds__(BS)
   // the grids and share donor-cell lines in that XCD's L2
   const long long wrank = xcd_rank(blockIdx.x, gridDim.x, xcd_run) * kWaves + (threadIdx.x >> 6);
   const long long nwaves = (long long)gridDim.x * kWaves;
-  // the ids of this lane's query in the wavefront's next chunk, loaded one
-  // chunk ahead (the first before the count is known: entries up to the
-  // capacity are allocated)
-  int cur_A = 0, cur_m = 0;
-  if (wrank * 64 + lane < cap) {
-    cur_A = q_grid[wrank * 64 + lane];
-    cur_m = q_node[wrank * 64 + lane];
+  // the wavefront's chunks: its first two by rank (fixed stride: rank + i
+  // nwaves; work queue: then 2 nwaves + a ticket, each taken two chunks
+  // ahead). A chunk's ids are loaded two chunks ahead and its queries' node
+  // coordinates, warm records and flags one chunk ahead (the first ones
+  // before the count is known: entries up to the capacity are allocated)
+  long long base = wrank * 64, base1 = (wrank + nwaves) * 64;
+  int cur_A = 0, cur_m = 0, nx_A = 0, nx_m = 0;
+  if (base + lane < cap) {
+    cur_A = q_grid[base + lane];
+    cur_m = q_node[base + lane];
+  }
+  if (base1 + lane < cap) {
+    nx_A = q_grid[base1 + lane];
+    nx_m = q_node[base1 + lane];
   }
   const unsigned int stamp = *warm.stamp;
   const uint8_t now = (uint8_t)stamp;
@@ -1363,11 +1410,13 @@ __global__ void __launch_bounds__(BS)
   }
   unsigned int* const chunk_head = dq.chunk ? dq.chunk + (stamp & 1u) : nullptr;
   __syncthreads();  // the staging is complete
+  NodePre pre;
+  if (base + lane < n) node_pre_load(grids[cur_A], warm, flags, cur_m, pre);
   int my_iters = 0, my_cands = 0;  // this lane's share of the work (walk cells: `visited` of its queries)
   unsigned int my_cells = 0;
-  for (long long base = wrank * 64; base < n;) {
-    // the wavefront's next chunk (work queue: its ticket, in flight during
-    // this chunk)
+  while (base < n) {
+    // the wavefront's chunk after next (work queue: its ticket, in flight
+    // during this chunk)
     unsigned int ticket = 0;
     if (chunk_head && lane == 0) ticket = atomicAdd(chunk_head, 1u);
     const long long q = base + lane;
@@ -1384,16 +1433,18 @@ __global__ void __launch_bounds__(BS)
       const int A = cur_A;
       const int qm = cur_m;
       my_grid = A;
-      // the warm-start entry, read beside the node's coordinates
+      // the warm-start entry, the node's coordinates and flag (loaded a
+      // chunk ahead)
       int wg, wcell;
       Start ws;
-      warm_read(warm, grids[A].node_off + qm, now, wg, wcell, ws);
+      warm_decode(warm, pre.rec, now, wg, wcell, ws);
       T o[3];
-      transform_node<T>(grids[A], sp + 12 * A, qm, o);
+      transform_xyz<T>(sp + 12 * A, pre.x, pre.y, pre.z, o);
       qx[q] = o[0];
       qx[cap + q] = o[1];
       qx[2 * cap + q] = o[2];
-      const Query Q = make_query<T>(grids, ngrids, sp, flags, A, qm, (double)o[0], (double)o[1], (double)o[2], false);
+      const Query Q = query_from<T>(grids, ngrids, sp, A, qm, (uint8_t)pre.flag, (double)o[0], (double)o[1],
+                                    (double)o[2], false, pre.x, pre.y, pre.z);
       key = Q.key;
       if (!Q.finite) {
         atomicOr(dev_status, OV_DEV_NONFINITE);
@@ -1454,15 +1505,18 @@ __global__ void __launch_bounds__(BS)
         }
       }
     }
-    // the next chunk's base, and its ids (fixed stride; or the ticket, which
-    // has long arrived)
-    long long nbase = base + nwaves * 64;
-    if (chunk_head) nbase = (nwaves + (long long)__shfl((int)ticket, 0, 64)) * 64;
+    // the chunk after next, and its ids (fixed stride; or the ticket, which
+    // has long arrived); the next chunk's node data, in flight during the
+    // scans and the finish of this one
+    long long base2 = base1 + nwaves * 64;
+    if (chunk_head) base2 = (2 * nwaves + (long long)__shfl((int)ticket, 0, 64)) * 64;
     int nxt_A = 0, nxt_m = 0;
-    if (nbase + lane < cap) {
-      nxt_A = q_grid[nbase + lane];
-      nxt_m = q_node[nbase + lane];
+    if (base2 + lane < cap) {
+      nxt_A = q_grid[base2 + lane];
+      nxt_m = q_node[base2 + lane];
     }
+    NodePre pre1;
+    if (base1 + lane < n) node_pre_load(grids[nx_A], warm, flags, nx_m, pre1);
     // the wavefront's deferred queries, one at a time with all its lanes
     for (unsigned long long dm = __ballot(defer); dm; dm &= dm - 1) {
       const int owner = __ffsll((long long)dm) - 1;
@@ -1490,9 +1544,13 @@ __global__ void __launch_bounds__(BS)
       finish_query<T>(grids, sp, q, cap, key, my_grid, res_grid, res_cell, res_status, visited, rs, donor_grid,
                       donor_cell, s_out, status, warm, now, fields, total_nodes, interleaved, frame_velocity, out);
     }
-    base = nbase;
-    cur_A = nxt_A;
-    cur_m = nxt_m;
+    base = base1;
+    base1 = base2;
+    cur_A = nx_A;
+    cur_m = nx_m;
+    nx_A = nxt_A;
+    nx_m = nxt_m;
+    pre = pre1;
   }
   add_work_counters(stats, my_cells, (unsigned int)my_iters, (unsigned int)my_cands);
 }
