@@ -449,9 +449,11 @@ int ov_pipe_submit_many(ov_pipe *pipe, const double *poses, int64_t pose_stride,
  * takes the first stream; the others are started for the call and joined
  * before it returns), so that the host's time per step is that of one
  * stream's calls rather than of all of them. The order between the streams
- * is the device-side one in either case, so the results are the same. Not
- * used with graphs or with a stage timed alone (ov_pipe_set_timing), where
- * the calls go out from the calling thread. on = 0 (default): one thread.
+ * is the device-side one in either case, so the results are the same; a
+ * thread issues a wait only after the write it waits for has been issued by
+ * its thread, so every wait is for work submitted before it. Not
+ * used with graphs, in the by-step order or with a stage timed alone
+ * (ov_pipe_set_timing), where the calls go out from the calling thread. on = 0 (default): one thread.
  * Returns OV_EINVAL for another value. */
 int ov_pipe_set_threads(ov_pipe *pipe, int32_t on);
 

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -378,8 +379,11 @@ int ov_pipe_submit(ov_pipe* p, const double* poses, int64_t* count_out) {
 // (buffer set, near list, start kind, timing slot) is fixed first, in
 // submission order; then thread g issues group g's waits, launches and
 // counter writes for all the steps. The order between the groups is the
-// device-side one of the counters, so the threads need none among
-// themselves; each stream still receives its work in step order.
+// device-side one of the counters; on the host a thread issues a wait only
+// after the thread that writes the awaited counter has issued that write, so
+// that, as with one thread, every wait is for work submitted before it (two
+// streams that share a hardware queue could otherwise wait on each other).
+// Each stream still receives its work in step order.
 static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride, int64_t n, int64_t* counts_out) {
   struct Plan {
     long long t;
@@ -407,15 +411,28 @@ static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride,
   const int after_group = p->after_group;
   const long long after_value = p->after_value;
   p->after_group = -1;
+  // issued[g]: the steps of this call whose group-g counter write is issued
+  std::atomic<long long> issued[3];
+  for (auto& v : issued) v.store(0);
+  std::atomic<bool> failed{false};
+  auto issued_at_least = [&](int g, long long steps) {
+    while (issued[g].load(std::memory_order_acquire) < steps && !failed.load(std::memory_order_acquire))
+      std::this_thread::yield();
+    return !failed.load(std::memory_order_acquire);
+  };
   auto run_group = [&](int g) -> hipError_t {
     hipError_t e = hipSetDevice(ctx->device);
     hipStream_t s = p->st[g];
     for (size_t i = 0; i < plan.size() && e == hipSuccess; ++i) {
       const Plan& pl = plan[i];
-      if (g > 0)
+      if (g > 0) {
+        if (!issued_at_least(g - 1, (long long)i + 1)) break;
         e = hipStreamWaitValue64(s, p->seq + g - 1, (uint64_t)(pl.t + 1), hipStreamWaitValueGte, ~0ull);
-      else if (pl.t >= ns)
+      } else if (pl.t >= ns) {
+        // (a step of an earlier call was issued before this call began)
+        if ((long long)i >= ns && !issued_at_least(ns - 1, (long long)i - ns + 1)) break;
         e = hipStreamWaitValue64(s, p->seq + ns - 1, (uint64_t)(pl.t + 1 - ns), hipStreamWaitValueGte, ~0ull);
+      }
       if (g == 0 && i == 0 && after_group >= 0 && e == hipSuccess)
         e = hipStreamWaitValue64(s, p->seq + after_group, (uint64_t)after_value, hipStreamWaitValueGte, ~0ull);
       for (int stage = first_stage(p, g); stage < first_stage(p, g + 1) && e == hipSuccess; ++stage) {
@@ -426,7 +443,9 @@ static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride,
         if (e == hipSuccess && ts) e = hipEventRecord(p->te[pl.tidx], s);
       }
       if (e == hipSuccess) e = hipStreamWriteValue64(s, p->seq + g, (uint64_t)(pl.t + 1), 0);
+      if (e == hipSuccess) issued[g].store((long long)i + 1, std::memory_order_release);
     }
+    if (e != hipSuccess) failed.store(true, std::memory_order_release);
     return e;
   };
   std::vector<hipError_t> err((size_t)ns, hipSuccess);
@@ -437,6 +456,7 @@ static int submit_threaded(ov_pipe* p, const double* poses, int64_t pose_stride,
   p->t += n;
   for (hipError_t e : err)
     if (e != hipSuccess) return hip_fail(ctx, e, "ov_pipe_submit_many");
+  if (failed.load()) return pipe_fail(p, OV_EHIP, "ov_pipe_submit_many: a stream's thread stopped");
   return OV_OK;
 }
 
