@@ -116,9 +116,10 @@ def time_config(asm, capacity: int, poses, params: dict, steps: int, warmup: int
     pipe.join()
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pipe.wait_current()  # (stream order only: the device is idle here)
+    timed = poses[warmup:warmup + steps]
     t0.record()
-    pipe.wait_current()
-    pipe.submit_many(warmup, poses[warmup:warmup + steps])
+    pipe.submit_many(warmup, timed)
     pipe.join()
     t1.record()
     torch.cuda.synchronize()
