@@ -189,7 +189,11 @@ int ov_grid_add(ov_ctx *ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t period
 
 /* Build the per-grid control cells (Sec. 2.2.5: an axis-aligned auxiliary grid
  * over each donor grid whose control cells list the donor cells reaching
- * them), FP32 shadows (mixed precision) and warm-start history. Synchronises
+ * them), FP32 shadows (mixed precision) and warm-start history, and find
+ * each grid's polar ends: in a grid with one periodic axis, an end face of
+ * another axis whose nodes coincide along the periodic axis (to 1e-12 of the
+ * grid's extent) lies on an axis of revolution, and the FP64 walk goes on
+ * across it (a result changes nothing but the walk's path). Synchronises
  * `stream`. After this, no grid can be added. */
 int ov_finalize(ov_ctx *ctx, void *stream);
 

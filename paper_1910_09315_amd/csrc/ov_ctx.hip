@@ -425,6 +425,61 @@ int build_shadows(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
   return OV_OK;
 }
 
+// Whether the face at end `end` (0 low, 1 high) of axis `a` collapses onto
+// lines along the periodic axis `pa`: every node of the face within `tol`
+// (per component) of the face's node at periodic index 0 on the same line.
+// *bad is set where one is not.
+__global__ void k_face_collapsed(GridDev g, int a, int end, int pa, double tol, unsigned int* __restrict__ bad) {
+  const int n[3] = {g.ni, g.nj, g.nk};
+  const int q = 3 - a - pa;  // the face's other axis
+  const long long cnt = (long long)n[pa] * n[q];
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < cnt;
+       t += (long long)gridDim.x * blockDim.x) {
+    int idx[3], ref[3];
+    idx[a] = ref[a] = end ? n[a] - 1 : 0;
+    idx[pa] = (int)(t % n[pa]);
+    ref[pa] = 0;
+    idx[q] = ref[q] = (int)(t / n[pa]);
+    const long long m = idx[0] + (long long)g.ni * (idx[1] + (long long)g.nj * idx[2]);
+    const long long r = ref[0] + (long long)g.ni * (ref[1] + (long long)g.nj * ref[2]);
+    if (!(fabs(g.X[m] - g.X[r]) <= tol && fabs(g.Y[m] - g.Y[r]) <= tol && fabs(g.Z[m] - g.Z[r]) <= tol))
+      atomicOr(bad, 1u);
+  }
+}
+
+// The polar ends of a grid with one periodic axis (GridDev::pole): faces of
+// the other two axes that collapse onto the axis of revolution, to within
+// 1e-12 of the grid's extent.
+static int find_poles(ov_ctx* ctx, GridHost& gh, hipStream_t s) {
+  GridDev& g = gh.d;
+  g.pole = 0;
+  if (g.per != 1 && g.per != 2 && g.per != 4) return OV_OK;
+  const int pa = g.per == 1 ? 0 : (g.per == 2 ? 1 : 2);
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) ext = std::max(ext, g.bhi[d] - g.blo[d]);
+  const double tol = 1e-12 * ext;
+  unsigned int* d_bad = nullptr;
+  HIPCHK(hipMalloc(&d_bad, sizeof(unsigned int) * 6), "hipMalloc pole test");
+  hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(unsigned int) * 6, s);
+  const int n[3] = {g.ni, g.nj, g.nk};
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+    if (a == pa) continue;
+    const long long cnt = (long long)n[pa] * n[3 - a - pa];
+    for (int end = 0; end < 2; ++end)
+      hipLaunchKernelGGL(k_face_collapsed, dim3(blocks_for(cnt)), dim3(256), 0, s, g, a, end, pa, tol,
+                         d_bad + 2 * a + end);
+  }
+  unsigned int bad[6] = {1, 1, 1, 1, 1, 1};
+  if (e == hipSuccess) e = hipMemcpyAsync(bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_bad);
+  if (e != hipSuccess) return hip_fail(ctx, e, "pole test");
+  for (int a = 0; a < 3; ++a)
+    for (int end = 0; end < 2; ++end)
+      if (a != pa && !bad[2 * a + end]) g.pole |= 1 << (2 * a + end);
+  return OV_OK;
+}
+
 // Flags of a grid with outer-boundary layers before any hole cut: fringe
 // (cause 63) on its outer layers, field elsewhere.
 __global__ void k_base_flags(GridDev g, uint8_t* __restrict__ out) {
@@ -589,6 +644,7 @@ int ov_grid_add(ov_ctx* ctx, int32_t ni, int32_t nj, int32_t nk, uint32_t period
   g.nj = nj;
   g.nk = nk;
   g.per = (int)periodic;
+  g.pole = 0;  // (found at ov_finalize)
   g.nci = (periodic & 1) ? ni : ni - 1;
   g.ncj = (periodic & 2) ? nj : nj - 1;
   g.nck = (periodic & 4) ? nk : nk - 1;
@@ -815,6 +871,7 @@ int ov_finalize(ov_ctx* ctx, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   for (auto& g : ctx->grids) {
     int rc = build_control_cells(ctx, g, s);
+    if (rc == OV_OK) rc = find_poles(ctx, g, s);
     if (rc != OV_OK) return rc;
     if (ctx->precision == OV_MIXED) {
       rc = build_shadows(ctx, g, s);

@@ -70,7 +70,10 @@ struct GridDev {
   // control cells: uniform bins over the body-frame box of the grid's nodes
   double blo[3], bhi[3], binv[3];
   int nb[3];
-  int pad_;
+  // polar ends: bit 2a (low end) and bit 2a + 1 (high end) of axis a set
+  // where that face collapses onto lines along the one periodic axis (the
+  // axis of a grid of revolution; the cells there are wedges round it)
+  int pole;
   const long long* bstart;  // [nbins + 1]
   const int* bcells;        // candidate donor cells, bin after bin (ascending in each bin)
   const int* brep;          // walk seed of each bin (listed cell nearest its centre), -1 if empty

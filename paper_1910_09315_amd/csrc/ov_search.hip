@@ -287,11 +287,36 @@ __device__ __forceinline__ int step_axis(int v, int dv, int nc, bool periodic, b
   return w;
 }
 
+// One axis of a walk step that went past a polar end (GridDev::pole; ends:
+// bit 0 low, bit 1 high): the step goes on in the cells across the axis of
+// revolution, as far from that end as it went past it. w = the cell index
+// as stepped, n = the cell after clamping, changed here.
+__device__ __forceinline__ bool pole_axis(int w, int nc, int ends, int& n) {
+  if (w < 0 && (ends & 1)) {
+    n = min(-w - 1, nc - 1);
+    return true;
+  }
+  if (w >= nc && (ends & 2)) {
+    n = max(2 * nc - 1 - w, 0);
+    return true;
+  }
+  return false;
+}
+
+// Cell v in [0, nc) of a periodic axis, half a turn on.
+__device__ __forceinline__ int half_turn(int v, int nc) {
+  const int w = v + nc / 2;
+  return w >= nc ? w - nc : w;
+}
+
 // Stencil walk in precision T from `cell`. On kFound, cell/s hold the donor.
 // On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
 // perr bounds the error of each component of xi (FP32 only; 0 when exact).
-// s_init: Newton's start in the first cell.
-template <typename T>
+// s_init: Newton's start in the first cell. Poles: steps past a polar end
+// go on across the axis of revolution (else they clamp there, and a point
+// across the axis is left to the scan); on in the FP64 kernels, off in the
+// mixed ones, whose registers it would push past two wavefronts per SIMD.
+template <typename T, bool Poles = (sizeof(T) == 8)>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
                     int max_walk, bool& limit, int& visited, int* iters = nullptr, const unsigned int* th = nullptr,
                     unsigned int stamp = 0, Start s_init = kCentre) {
@@ -373,6 +398,20 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     int ni = step_axis(ci, di, G.nci, G.per & 1, clamped);
     int nj = step_axis(cj, dj, G.ncj, G.per & 2, clamped);
     int nk = step_axis(ck, dk, G.nck, G.per & 4, clamped);
+    // past a polar end the walk goes on across the axis of revolution,
+    // Newton from the cell's centre
+    if (Poles && clamped && G.pole) {
+      bool across = pole_axis(ci + di, G.nci, G.pole & 3, ni);
+      across |= pole_axis(cj + dj, G.ncj, (G.pole >> 2) & 3, nj);
+      across |= pole_axis(ck + dk, G.nck, (G.pole >> 4) & 3, nk);
+      if (across) {
+        if (G.per & 1) ni = half_turn(ni, G.nci);
+        else if (G.per & 2) nj = half_turn(nj, G.ncj);
+        else nk = half_turn(nk, G.nck);
+        s[0] = s[1] = s[2] = (T)0.5;
+        di = dj = dk = 0;
+      }
+    }
     const int next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
     hist[stepn & 3] = here;
     if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
@@ -571,7 +610,8 @@ __device__ __forceinline__ int walk_grid(const GridDev* grids, const double* sp,
   if (sizeof(T) == 4 && r == kDoubt) {
     double s64[3], xe[3];
     exact_body(grids, sp, Q, B, xi, xe);
-    r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, iters, nullptr, 0u, start_from<T>(s));
+    r = walk<double, sizeof(T) == 8>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, iters, nullptr, 0u,
+                                     start_from<T>(s));
     s[0] = (T)s64[0];
     s[1] = (T)s64[1];
     s[2] = (T)s64[2];
@@ -775,8 +815,8 @@ __global__ void __launch_bounds__(256)
     int cell = donor_cell[q];
     bool limit = false;
     const float sf0[3] = {s_out[q], s_out[cap + q], s_out[2 * cap + q]};
-    const int r = walk<double>(G, flags + G.node_off, xi, 0.0, cell, s64, max_walk, limit, visited, nullptr, nullptr,
-                               0u, start_from<float>(sf0));
+    const int r = walk<double, false>(G, flags + G.node_off, xi, 0.0, cell, s64, max_walk, limit, visited, nullptr,
+                                      nullptr, 0u, start_from<float>(sf0));
     if (limit) atomicOr(dev_status, OV_DEV_WALK_LIMIT);
     if (r == kFound) {
       const float sf[3] = {(float)s64[0], (float)s64[1], (float)s64[2]};
@@ -1483,8 +1523,8 @@ __global__ void __launch_bounds__(BS)
             const Query QE = make_query<T>(grids, ngrids, sp, flags, A, Q.m, 0.0, 0.0, 0.0, true);
             double xe[3], s64[3];
             body_frame(sp + 12 * B, QE.x, xe);
-            r = walk<double>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters, nullptr, 0u,
-                             start_from<T>(s));
+            r = walk<double, false>(G, fl, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters, nullptr, 0u,
+                                    start_from<T>(s));
             s[0] = (T)s64[0];
             s[1] = (T)s64[1];
             s[2] = (T)s64[2];
@@ -1618,8 +1658,8 @@ __global__ void __launch_bounds__(BS)
         double xe[3], s64[3];
         body_frame(sp + 12 * B, QE.x, xe);
         const T sq[3] = {s_out[q], s_out[cap + q], s_out[2 * cap + q]};
-        const int r = walk<double>(G, flags + G.node_off, xe, 0.0, cell, s64, max_walk, limit, visited, &my_iters,
-                                   nullptr, 0u, start_from<T>(sq));
+        const int r = walk<double, false>(G, flags + G.node_off, xe, 0.0, cell, s64, max_walk, limit, visited,
+                                          &my_iters, nullptr, 0u, start_from<T>(sq));
         if (r == kFound) {
           res_grid = B;
           res_cell = cell;

@@ -438,6 +438,58 @@ def test_buffer_wraps_two_tiles_across_a_thin_periodic_seam():
     _run_and_compare(w, [0], options={"holecut_cull": 0})
 
 
+def polar_turn_case():
+    """A spherical shell (polar angle from its x axis with pole nodes at both
+    ends, azimuth periodic, 16 azimuthal cells) in a Cartesian background,
+    turned half a revolution about its own axis after step 0. The queries
+    whose donors are the wedge cells round the axis then start their walk,
+    from step 0's donor, in the cell across the axis from the one that holds
+    them."""
+    bg = W.cartesian_grid(48)
+    sph = W.spherical_shell(8, 16, 9, 0.08, 0.3)
+    sph.blank_kind = W.BLANK_SPHERE
+    sph.blank_prm = (0.08,)
+    sph.outer = (0, 2, 0, 0, 0, 0)
+    c = (0.5, 0.5, 0.5)
+    poses = np.stack([np.stack([W.IDENTITY_POSE, W.pose12(np.eye(3), c)]),
+                      np.stack([W.IDENTITY_POSE, W.pose12(np.diag([1.0, -1.0, -1.0]), c)])])
+    fields = np.random.default_rng(3).standard_normal((4, bg.nodes + sph.nodes))
+    return W.Workload("polar", [bg, sph], nf=2, steps=2, poses=poses, fields=fields)
+
+
+def test_fp64_walk_crosses_the_polar_axis():
+    """Past a polar end the FP64 walk goes on in the cells across the axis of
+    revolution: after the half turn all 56 queries with donors in the polar
+    wedge cells are found by the walk (status FOUND), none by the
+    brute-force scan of the control cell, which is where a walk that clamps
+    at the pole sends them. Both steps match the oracle, through the five
+    calls and through the native executor (bit for bit with the five
+    calls)."""
+    from paper_1910_09315_amd.assembly import Pipeline
+    w = polar_turn_case()
+    o = oracle.Oracle(w.grids, w.nf)
+    a = _assembly(w)
+    b = _assembly(w, capacity=a.capacity)
+    pipe = Pipeline(b, a.capacity, native=True, stages=1)
+    poses = torch.as_tensor(w.poses.reshape(w.steps, -1)).cuda()
+    for t in range(2):
+        a.step(poses[t])
+        g = a.results()
+        r = o.step(w.poses[t], w.fields)
+        compare(o, w.poses[t], r, g, value_rtol=1e-12, s_tol=1e-12, qx_tol=1e-14)
+        pipe.submit(t, poses[t])
+        p = pipe.results(t)
+        for k in ("flags", "q_node", "donor_grid", "donor_cell", "status", "s", "values"):
+            assert np.array_equal(p[k], g[k], equal_nan=True), (t, k)
+    pipe.join()
+    nci, ncj, nck = 7, 16, 8
+    polar = (r["donor_grid"] == 1) & np.isin(r["donor_cell"] // (nci * ncj), (0, nck - 1))
+    assert polar.sum() == 56
+    code = g["status"] & 3
+    assert (code[polar] == 1).all(), np.bincount(code[polar], minlength=4)
+    assert (a.ctx.status() & ~2) == 0
+
+
 def test_fringe_compact_on_flags_of_another_hole_cut():
     """overset_fringe_compact finds the hole tiles from the flags it is given:
     two hole cuts (steps 0 and 2) into two buffers, then the fringe
