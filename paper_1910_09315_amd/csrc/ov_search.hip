@@ -405,9 +405,11 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
       across |= pole_axis(cj + dj, G.ncj, (G.pole >> 2) & 3, nj);
       across |= pole_axis(ck + dk, G.nck, (G.pole >> 4) & 3, nk);
       if (across) {
-        if (G.per & 1) ni = half_turn(ni, G.nci);
-        else if (G.per & 2) nj = half_turn(nj, G.ncj);
-        else nk = half_turn(nk, G.nck);
+        // (from the cell it stepped from: near the axis the periodic
+        // natural coordinate says little about where the point lies)
+        if (G.per & 1) ni = half_turn(ci, G.nci);
+        else if (G.per & 2) nj = half_turn(cj, G.ncj);
+        else nk = half_turn(ck, G.nck);
         s[0] = s[1] = s[2] = (T)0.5;
         di = dj = dk = 0;
       }
