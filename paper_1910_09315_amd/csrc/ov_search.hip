@@ -312,10 +312,11 @@ __device__ __forceinline__ int half_turn(int v, int nc) {
 // Stencil walk in precision T from `cell`. On kFound, cell/s hold the donor.
 // On kDoubt (T = float only), cell holds the cell where FP32 could not decide.
 // perr bounds the error of each component of xi (FP32 only; 0 when exact).
-// s_init: Newton's start in the first cell. Poles: steps past a polar end
-// go on across the axis of revolution (else they clamp there, and a point
-// across the axis is left to the scan); on in the FP64 kernels, off in the
-// mixed ones, whose registers it would push past two wavefronts per SIMD.
+// s_init: Newton's start in the first cell. Poles: a step clamped at a
+// polar end that would revisit a cell goes on across the axis of
+// revolution instead of ending the walk (else a point across the axis is
+// left to the scan); on in the FP64 kernels, off in the mixed ones, whose
+// registers it would push past two wavefronts per SIMD.
 template <typename T, bool Poles = (sizeof(T) == 8)>
 __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], double perr, int& cell, T s[3],
                     int max_walk, bool& limit, int& visited, int* iters = nullptr, const unsigned int* th = nullptr,
@@ -398,25 +399,27 @@ __device__ int walk(const GridDev& G, const uint8_t* fl, const double xi[3], dou
     int ni = step_axis(ci, di, G.nci, G.per & 1, clamped);
     int nj = step_axis(cj, dj, G.ncj, G.per & 2, clamped);
     int nk = step_axis(ck, dk, G.nck, G.per & 4, clamped);
-    // past a polar end the walk goes on across the axis of revolution,
-    // Newton from the cell's centre
-    if (Poles && clamped && G.pole) {
+    int next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
+    hist[stepn & 3] = here;
+    if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) {
+      // a step clamped at a polar end lands on a cell just visited: the
+      // point lies across the axis of revolution, and the walk goes on
+      // there, Newton from the cell's centre; any other revisit ends it
+      if (!(Poles && G.pole)) return kToScan;
       bool across = pole_axis(ci + di, G.nci, G.pole & 3, ni);
       across |= pole_axis(cj + dj, G.ncj, (G.pole >> 2) & 3, nj);
       across |= pole_axis(ck + dk, G.nck, (G.pole >> 4) & 3, nk);
-      if (across) {
-        // (from the cell it stepped from: near the axis the periodic
-        // natural coordinate says little about where the point lies)
-        if (G.per & 1) ni = half_turn(ci, G.nci);
-        else if (G.per & 2) nj = half_turn(cj, G.ncj);
-        else nk = half_turn(ck, G.nck);
-        s[0] = s[1] = s[2] = (T)0.5;
-        di = dj = dk = 0;
-      }
+      if (!across) return kToScan;
+      // (half a turn from the cell it stepped from: near the axis the
+      // periodic natural coordinate says little about where the point lies)
+      if (G.per & 1) ni = half_turn(ci, G.nci);
+      else if (G.per & 2) nj = half_turn(cj, G.ncj);
+      else nk = half_turn(ck, G.nck);
+      next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
+      if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
+      s[0] = s[1] = s[2] = (T)0.5;
+      di = dj = dk = 0;
     }
-    const int next = (int)((unsigned)ni + (unsigned)G.nci * ((unsigned)nj + (unsigned)G.ncj * (unsigned)nk));
-    hist[stepn & 3] = here;
-    if (next == hist[0] || next == hist[1] || next == hist[2] || next == hist[3]) return kToScan;
     s[0] = fmin(fmax(s[0] - (T)di, (T)0), (T)1);
     s[1] = fmin(fmax(s[1] - (T)dj, (T)0), (T)1);
     s[2] = fmin(fmax(s[2] - (T)dk, (T)0), (T)1);
